@@ -1,0 +1,105 @@
+"""Pins of the FP64 oracle's operator and direct solves (CPU only).
+
+Each check fixes the oracle against something other than itself: the
+Kronecker structure of the tensor-grid operator, the closed-form eigenpairs on
+a uniform grid, second-order convergence to a manufactured solution, and two
+independent direct solves.
+"""
+import numpy as np
+import pytest
+
+from paper_2604_01800_amd import inputs
+from oracle import direct
+
+
+def test_kronecker_identity(orc):
+    g = inputs.make_grid(13, 9, 1.5, 0.7)
+    A = direct.kron_matrix(g)
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        x = rng.standard_normal((g.ny, g.nx))
+        y = orc.apply(g, x)
+        np.testing.assert_allclose(y.reshape(-1), A @ x.reshape(-1), rtol=0, atol=1e-12 * np.abs(y).max())
+
+
+def test_symmetry_and_null_space(orc):
+    g = inputs.make_grid(40, 33, 2.5, 1.0)
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal((g.ny, g.nx))
+    v = rng.standard_normal((g.ny, g.nx))
+    Au, Av = orc.apply(g, u), orc.apply(g, v)
+    normA = np.abs(orc.diag(g)).max() * 2
+    assert abs(np.sum(u * Av) - np.sum(v * Au)) <= 1e-13 * normA * np.linalg.norm(u) * np.linalg.norm(v)
+    one = np.ones((g.ny, g.nx))
+    assert np.abs(orc.apply(g, one)).max() <= 1e-14 * normA
+    assert np.sum(u * Au) > 0
+
+
+def test_uniform_closed_form_eigenpairs(orc):
+    n = 16
+    g = inputs.make_grid(n, n, 0.0)
+    h = 1.0 / n
+    i = np.arange(n) + 0.5
+    for k, l in [(0, 1), (1, 0), (3, 5), (15, 15), (7, 2)]:
+        v = np.outer(np.cos(np.pi * l * i / n), np.cos(np.pi * k * i / n))
+        lam = 4 * np.sin(np.pi * k / (2 * n)) ** 2 * (h / h) + 4 * np.sin(np.pi * l / (2 * n)) ** 2 * (h / h)
+        np.testing.assert_allclose(orc.apply(g, v), lam * v, atol=1e-12)
+
+
+def test_uniform_anisotropic_eigenvalue(orc):
+    nx, ny = 8, 12
+    g = inputs.make_grid(nx, ny, 0.0)
+    hx, hy = 1.0 / nx, 1.0 / ny
+    k, l = 3, 4
+    v = np.outer(np.cos(np.pi * l * (np.arange(ny) + 0.5) / ny), np.cos(np.pi * k * (np.arange(nx) + 0.5) / nx))
+    lam = 4 * np.sin(np.pi * k / (2 * nx)) ** 2 * (hy / hx) + 4 * np.sin(np.pi * l / (2 * ny)) ** 2 * (hx / hy)
+    np.testing.assert_allclose(orc.apply(g, v), lam * v, atol=1e-12)
+
+
+def test_rhs_projection(orc):
+    g = inputs.make_grid(20, 24, 1.2)
+    f = inputs.gaussian_bumps(g, 3)
+    b, m = orc.rhs(g, f)
+    raw = np.outer(g.hy, g.hx) * f.astype(np.float32).astype(np.float64)
+    np.testing.assert_allclose(m, raw.mean(), rtol=1e-14)
+    assert abs(b.sum()) <= 1e-15 * np.abs(raw).sum() * 10
+
+
+def test_dense_vs_separable(orc):
+    g = inputs.make_grid(17, 19, 1.5, 2.2)
+    b, _ = orc.rhs(g, inputs.gaussian_bumps(g, 4))
+    x1 = direct.dense_pinv_solve(g, b)
+    x2 = direct.separable_solve(g, b)
+    assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x1) * 10
+    np.testing.assert_allclose(orc.apply(g, x2), b, atol=1e-11 * np.abs(b).max())
+
+
+def _manufactured_error(orc, n, beta):
+    g = inputs.make_grid(n, n, beta)
+    P = np.outer(np.cos(np.pi * g.yc), np.cos(np.pi * g.xc))
+    f = 2 * np.pi ** 2 * P
+    b = np.outer(g.hy, g.hx) * f
+    b -= b.mean()
+    x = direct.separable_solve(g, b)
+    e = x - P
+    e -= e.mean()
+    return np.abs(e).max()
+
+
+def test_second_order_on_stretched_grids(orc):
+    ns = [32, 64, 128, 256]
+    errs = [_manufactured_error(orc, n, 1.5) for n in ns]
+    orders = [np.log2(errs[k] / errs[k + 1]) for k in range(len(ns) - 1)]
+    assert all(1.9 <= o <= 2.1 for o in orders[1:]), (errs, orders)
+    assert 1.8 <= orders[0] <= 2.2, orders
+
+
+def test_manufactured_operator_consistency(orc):
+    # A applied to the exact field reproduces area * f up to O(h^2) relative.
+    for n, tol in [(64, 2e-2), (256, 2e-3)]:
+        g = inputs.make_grid(n, n, 1.5)
+        P = np.outer(np.cos(np.pi * g.yc), np.cos(np.pi * g.xc))
+        interior = (slice(2, -2), slice(2, -2))
+        lhs = orc.apply(g, P)[interior]
+        rhs = (np.outer(g.hy, g.hx) * 2 * np.pi ** 2 * P)[interior]
+        assert np.abs(lhs - rhs).max() <= tol * np.abs(rhs).max()
