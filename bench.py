@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Benchmark of the pressure Poisson solve on one MI355X.
+
+Workload (seeded, synthetic): a 1024 x 1024 cell-centred grid on the unit
+square, tanh-stretched in x and y with beta = 1.75 (max/min spacing 8.8),
+an elliptical obstacle mask (centre U[0.2, 0.8]^2, semi-axes U[0.05, 0.15],
+angle U[0, pi)), and a Gaussian-random-field source (squared-exponential
+covariance, length 0.05, 512 random Fourier features). Each step solves the
+system from x0 = 0 to relative residual 1e-6 (FP64 true residual) with
+Jacobi-PCG, and, when a network is available (--hybrid), with the hybrid
+PCG + line-search method as well.
+
+Prints one JSON line. `roofline` reports the dominant kernel (PCG phase A)
+with its algorithmic bytes per launch divided by its average launch duration
+(HIP events on the launch stream). `cpu_baseline` times the FP64 oracle on a
+bounded sample (a fixed number of PCG iterations on the same system, scaled to
+the iteration count of a full solve).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "PPE solves/sec to rel-res 1e-6, hybrid vs plain PCG, 1024² grid; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+BYTES_PHASE_A = 20  # per cell: reads r, p_old, x_c; writes p, x_c (FP32)
+BYTES_PHASE_B = 12  # per cell: reads p, r; writes r (FP32)
+
+
+def workload(n=1024, beta=1.75, seed=0):
+    from paper_2604_01800_amd import inputs
+    g = inputs.with_ellipse(inputs.make_grid(n, n, beta), np.random.default_rng(seed))
+    f = inputs.grf(g, seed).astype(np.float32)
+    return g, f
+
+
+def cpu_baseline(g, f, iters_full, sample_iters):
+    """Single-threaded FP64 oracle PCG: time `sample_iters` iterations, scale."""
+    import oracle
+    b, _ = oracle.rhs(g, f)
+    t0 = time.perf_counter()
+    oracle.pcg(g, b, tol=0.0, max_iter=sample_iters)
+    dt = time.perf_counter() - t0
+    per_iter = dt / sample_iters
+    return {
+        "value": 1.0 / (per_iter * iters_full),
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{sample_iters} FP64 Jacobi-PCG iterations of the C oracle on the same {g.nx}x{g.ny} "
+                  f"system ({dt:.1f} s, {per_iter * 1e3:.2f} ms/iteration), scaled to the {iters_full} "
+                  f"iterations of a full solve to 1e-6",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--cpu-iters", type=int, default=600)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-reps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2604_01800_amd import ppe
+
+    ppe.lib()
+    torch.cuda.set_device(0)
+    g, f_np = workload(args.n)
+    prob = ppe.ppe_problem_create(g)
+    f = torch.from_numpy(f_np[None]).cuda()
+    x = torch.zeros((1, g.ny, g.nx), dtype=torch.float64, device="cuda")
+    opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1)
+
+    for _ in range(args.warmup):
+        ppe.ppe_solve_plain(prob, f, x, opts)
+    torch.cuda.synchronize()
+    stats_all = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, stats = ppe.ppe_solve_plain(prob, f, x, opts)
+        stats_all.append(stats[0])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    s0 = stats_all[-1]
+    if st != ppe.PPE_OK:
+        print(f"solve did not converge: {s0}", file=sys.stderr)
+
+    # Dominant kernel: PCG phase A, timed alone with HIP events on the stream.
+    xt = torch.zeros_like(x)
+    ms_a, ms_b = ppe.ppe_profile_pcg(prob, f, xt, opts, reps=args.profile_reps)
+    N = g.nx * g.ny
+    ach_a = BYTES_PHASE_A * N / (ms_a * 1e-3) / 1e9
+    ach_b = BYTES_PHASE_B * N / (ms_b * 1e-3) / 1e9
+    iters = s0["iters_total"]
+    pcg_gbs = 32.0 * N * iters / (ms_per_step * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": 1e3 / ms_per_step,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"plain Jacobi-PCG, {g.nx}x{g.ny} tanh grid beta 1.75, ellipse mask, GRF source "
+                        f"l=0.05, x0=0, rel-res {args.tol:g} on the FP64 true residual",
+            "iters": iters,
+            "reliable_updates": s0["reliable_updates"],
+            "rel_res_true": s0["rel_res_true"],
+            "precision": "FP32 vectors, FP64 reductions and solution accumulator",
+            "effective_pcg_GBps": pcg_gbs,
+            "phase_a_ms": ms_a,
+            "phase_b_ms": ms_b,
+            "phase_b_GBps": ach_b,
+        },
+        "roofline": {
+            "kernel": "k_pcg_a (PCG phase A)",
+            "bound": "hbm",
+            "achieved": ach_a,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": ach_a / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, f_np, iters, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * ppe.h — C-ABI of the MI355X pressure-Poisson library.
+ *
+ * The library solves the pressure Poisson equation of the fractional-step
+ * method (Eq. 7, recast as M dp = S in Eq. 10) on a tensor-product stretched
+ * Cartesian grid, either with (Jacobi-)preconditioned conjugate gradients or in
+ * the hybrid form of Sec. 2.2, where a DeepONet with a grid-spacing-aware U-Net
+ * branch (Sec. 2.4) supplies line-search directions (Eqs. 11-13) between blocks
+ * of CG iterations. The network is trained by the library on fabricated
+ * systems with the residual loss of Eq. 19.
+ *
+ * Discretisation (the reading of M used throughout): cell-centred finite
+ * volumes, each interior face weighted by (face length)/(centre distance),
+ * boundary faces dropped (homogeneous Neumann). For the PDE -lap p = f the
+ * library builds b = (cell area) * f and removes the plain mean of b
+ * (compatibility with the constant null space). The returned x is the
+ * minimum-norm solution (zero plain mean). The time step of Eq. 7 is absorbed
+ * into f.
+ *
+ * Conventions
+ *   - Arrays on a grid are row-major [ny][nx], index j*nx + i, and batches are
+ *     [nb][ny][nx]. "device" pointers are HIP device memory on the current
+ *     device, "host" pointers are ordinary host memory.
+ *   - The caller owns every data pointer. *_create copies the host grid arrays;
+ *     the library never keeps caller pointers beyond a call.
+ *   - Work is enqueued on the given stream (0 = the default stream). Solve and
+ *     train calls return after the stream's work for the call has completed,
+ *     since convergence is polled and statistics are host values.
+ *   - Handles are not thread-safe: use one handle per thread.
+ *   - Every entry point validates its arguments before launching anything and
+ *     returns a status; ppe_last_error() gives a thread-local message.
+ */
+#ifndef PPE_H
+#define PPE_H
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ppe_status;
+enum {
+  PPE_OK = 0,
+  PPE_NOT_CONVERGED = 1,   /* x = best iterate (after a final true-residual update), stats valid */
+  PPE_ERR_INVALID_ARG = -1,
+  PPE_ERR_SHAPE = -2,      /* nx, ny not divisible by 2^(levels-1), or net/grid mismatch */
+  PPE_ERR_UNSUPPORTED = -3,
+  PPE_ERR_HIP = -4,        /* a HIP runtime call failed; see ppe_last_error() */
+  PPE_ERR_NONFINITE = -5   /* NaN/Inf in the source f, or produced by the iteration */
+};
+
+typedef struct ppe_problem ppe_problem; /* opaque: one grid, its coefficients and workspaces */
+typedef struct ppe_net ppe_net;         /* opaque: DeepONet weights, optimiser state, buffers */
+
+enum { PPE_PC_NONE = 0, PPE_PC_JACOBI = 1 };           /* vanilla CG / Jacobi-PCG (Sec. 2.5) */
+enum { PPE_TOL_RELATIVE = 0, PPE_TOL_ABSOLUTE = 1 };   /* ||b-Ax||2 <= tol*||b||2 or <= tol */
+
+/* Error-direction provider of the hybrid solve. NET is the DeepONet; the others
+ * replace it for testing the controller and its fallback. */
+enum {
+  PPE_DIR_NET = 0,
+  PPE_DIR_ZERO = 1,    /* e = 0: every line-search step is rejected */
+  PPE_DIR_JACOBI = 2,  /* e = D^-1 r */
+  PPE_DIR_NAN = 3,     /* e = NaN: every step is rejected */
+  PPE_DIR_ONES = 4     /* e = 1 (null space, e^T A e = 0): rejected */
+};
+
+/* Grid description (Sec. 2.5 / Table 1: a stretched Cartesian grid).
+ * xc, yc: host, [nx], [ny] strictly increasing cell centres.
+ * hx, hy: host, [nx], [ny] cell widths > 0 (face length of the other axis).
+ * mask:   host [ny*nx] or NULL, 1 = solid. The obstacle does not enter M (the
+ *         immersed boundary acts through the source); it is an input channel
+ *         of the network. */
+typedef struct {
+  int32_t nx, ny;
+  const double *xc, *yc;
+  const double *hx, *hy;
+  const uint8_t* mask;
+} ppe_grid_desc;
+
+typedef struct {
+  double tol;              /* default 1e-6 */
+  int32_t tol_kind;        /* PPE_TOL_RELATIVE (default) or PPE_TOL_ABSOLUTE */
+  int32_t precond;         /* PPE_PC_JACOBI (default) or PPE_PC_NONE */
+  int32_t max_iter;        /* iterations (CG + line search) before giving up */
+  int32_t num_cg;          /* hybrid: CG iterations per round (default 3) */
+  int32_t num_dlsm;        /* hybrid: line-search steps per round (default 2) */
+  int32_t direction;       /* hybrid: PPE_DIR_* (default PPE_DIR_NET) */
+  double reliable_delta;   /* true-residual update when ||r|| < delta*||r_true|| (default 0.3) */
+  int32_t rows_per_wave;   /* stencil tile height per wavefront: 0 = tuned default, else 2,4,8,16 */
+  int32_t use_graph;       /* 1 (default) = replay iteration chunks as a HIP graph, 0 = eager launches */
+  int32_t chunk;           /* iterations per polled chunk (0 = default 64) */
+  int32_t zero_x0;         /* 1 = ignore x on entry and start from x0 = 0 */
+} ppe_solve_opts;
+
+typedef struct {
+  int32_t status;          /* per solve: PPE_OK / PPE_NOT_CONVERGED / PPE_ERR_NONFINITE */
+  int32_t iters_total, iters_cg, iters_dlsm, dlsm_rejected, reliable_updates;
+  double rel_res_true;     /* FP64 ||b - A x||2 / ||b||2 at exit */
+  double abs_res_true;     /* FP64 ||b - A x||2 at exit */
+  double bnorm;            /* ||b||2 after projection */
+  double rhs_mean_removed; /* plain mean removed from b = area * f */
+  double ms_total;         /* wall time of the call (host clock), same for all solves of a call */
+} ppe_solve_stats;
+
+/* Network configuration (Sec. 2.4). Defaults (ppe_net_config_default): 4 levels,
+ * 32 base channels doubling per level, inputs (scaled residual, mask), 128-term
+ * DeepONet basis, trunk 2 -> 128 x 4 -> 128 (tanh), per-layer weight network
+ * 4 -> 16 (tanh) -> C_in for the Mesh-Conv local weight (Eq. 17). */
+typedef struct {
+  int32_t levels, base_channels, basis, trunk_width, trunk_hidden, phi_hidden;
+  int32_t use_eta;         /* 1 = Mesh-Conv (Eqs. 17-18), 0 = standard conv ("-Conv" ablation) */
+  int32_t use_spacing;     /* 1 = concatenate the normalised widths (hx, hy) at each level */
+} ppe_net_config;
+
+typedef struct {
+  float lr, beta1, beta2, eps;  /* Adam; defaults 1e-3, 0.9, 0.999, 1e-8 */
+  uint64_t seed;                /* data generator seed (used when R == NULL) */
+  int64_t step;                 /* data generator step counter */
+} ppe_train_opts;
+
+/* ---- problem (Sec. 8 a1: per-grid setup, built once and reused, as the paper
+ *      reuses its matrix and preconditioner across time steps) ---- */
+ppe_status ppe_problem_create(const ppe_grid_desc* grid, ppe_problem** out);
+void ppe_problem_destroy(ppe_problem* p);
+void ppe_solve_opts_default(ppe_solve_opts* o);
+
+/* y = A x, the operator of Eq. 10 (FP32 or FP64 arithmetic).
+ * x, y: device [nb][ny][nx]. */
+ppe_status ppe_apply_f32(const ppe_problem* p, int32_t nb, const float* x, float* y, hipStream_t s);
+ppe_status ppe_apply_f64(const ppe_problem* p, int32_t nb, const double* x, double* y, hipStream_t s);
+
+/* Plain (Jacobi-)PCG solve of nb systems on one grid (Sec. 2.5, JPCG).
+ * f: device FP32 [nb][ny][nx], the source of -lap p = f (pointwise values).
+ * x: device FP64 [nb][ny][nx]; in: initial guess, out: solution with zero mean.
+ * stats: host [nb] or NULL. Vectors are FP32; dot products, the solution
+ * accumulator and the convergence judge (true residual) are FP64.
+ * Returns PPE_OK if every solve converged, PPE_NOT_CONVERGED if any did not,
+ * PPE_ERR_NONFINITE if any source held NaN/Inf. */
+ppe_status ppe_solve_plain(ppe_problem* p, int32_t nb, const float* f, double* x,
+                           const ppe_solve_opts* opts, ppe_solve_stats* stats, hipStream_t s);
+
+/* Hybrid solve (Sec. 2.2): rounds of num_cg PCG iterations and num_dlsm
+ * line-search steps along e = NN(r) (Eqs. 12-13), restarting PCG after each
+ * line-search block; convergence judged on the FP64 true residual. net may be
+ * NULL when opts->direction != PPE_DIR_NET. Same arrays as ppe_solve_plain.
+ * Requires nx, ny divisible by 2^(levels-1) when the network is used. */
+ppe_status ppe_solve_hybrid(ppe_problem* p, ppe_net* net, int32_t nb, const float* f, double* x,
+                            const ppe_solve_opts* opts, ppe_solve_stats* stats, hipStream_t s);
+
+/* ---- network (Sec. 2.4) ---- */
+void ppe_net_config_default(ppe_net_config* c);
+ppe_status ppe_net_create(const ppe_net_config* c, uint64_t seed, ppe_net** out); /* random init */
+void ppe_net_destroy(ppe_net* n);
+/* Number of FP32 parameters and the canonical flat layout (see the package's
+ * Python binding for the tensor order). */
+int64_t ppe_net_num_params(const ppe_net* n);
+/* Copy FP32 master parameters host -> net (also refreshes the BF16 copy and
+ * resets the optimiser state) or net -> host. */
+ppe_status ppe_net_set_params(ppe_net* n, const float* host_params, int64_t count);
+ppe_status ppe_net_get_params(const ppe_net* n, float* host_params, int64_t count);
+ppe_status ppe_net_save(const ppe_net* n, const char* path);
+ppe_status ppe_net_load(ppe_net* n, const char* path);
+
+/* Forward pass on nb residual fields of one grid: y = NN(r * sqrt(N)/||r||).
+ * r: device FP32 [nb][ny][nx]; y: device FP32 [nb][ny][nx]. */
+ppe_status ppe_net_forward(ppe_net* n, ppe_problem* p, int32_t nb, const float* r, float* y,
+                           hipStream_t s);
+
+/* One Adam step on nb fabricated systems with the residual loss of Eq. 19,
+ * Loss = mean over cells of (R - A NN(R))^2, averaged over the batch.
+ * problems: host array of nb grids of one size (each sample has its own grid);
+ * R: device FP32 [nb][ny][nx] (zero-sum residual fields).
+ * loss_out: host, the batch loss before the step. grad_out: host or NULL;
+ * when given, receives the FP32 gradient (ppe_net_num_params values). */
+ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* problems, const float* R,
+                              const ppe_train_opts* opts, float* loss_out, float* grad_out,
+                              hipStream_t s);
+
+/* ---- measurement ---- */
+/* Average duration in ms of one phase-A launch (ms_out[0]) and one phase-B
+ * launch (ms_out[1]) of the fused PCG iteration on nb systems, timed with HIP
+ * events on stream s over `reps` back-to-back launches that repeat one CG
+ * iteration's work after a solve setup on (f, x). x is used as the initial
+ * guess and its content is left unspecified. ms_out: host [2]. */
+ppe_status ppe_profile_pcg(ppe_problem* p, int32_t nb, const float* f, double* x,
+                           const ppe_solve_opts* opts, int32_t reps, double* ms_out, hipStream_t s);
+/* Average ms of a plain device copy of `bytes` bytes (multiple of 16) from src
+ * to dst (device buffers, caller-owned): the bandwidth reference and the
+ * calibration kernel for hardware byte counters. ms_out: host [1]. */
+ppe_status ppe_profile_copy(const void* src, void* dst, int64_t bytes, int32_t reps, double* ms_out,
+                            hipStream_t s);
+
+const char* ppe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPE_H */

@@ -1,0 +1,421 @@
+// C-ABI and host runtime of the MI355X PPE library: problem handles,
+// workspaces, graph-captured PCG iteration chunks and convergence polling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ppe.h"
+#include "api_internal.hpp"
+#include "kernels.hpp"
+
+namespace ppe {
+
+thread_local std::string g_last_error;
+
+ppe_status set_error(ppe_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+void* dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+static void free_ws(SolveWs& w) {
+  if (w.exec) (void)hipGraphExecDestroy(w.exec);
+  w.exec = nullptr;
+  dev_free(w.vec);
+  dev_free(w.part);
+  dev_free(w.st);
+  dev_free(w.flags);
+  dev_free(w.call);
+  if (w.h_flags) (void)hipHostFree(w.h_flags);
+  if (w.h_state) (void)hipHostFree(w.h_state);
+  for (auto& e : w.ev)
+    if (e) (void)hipEventDestroy(e);
+  w = SolveWs{};
+}
+
+// Workspace for nb solves: 4 FP32 vectors per solve (x_c, r, p0, p1), the
+// partial-sum arrays, states and polling flags.
+ppe_status ensure_ws(ppe_problem* p, int nb) {
+  SolveWs& w = p->ws;
+  if (w.nb >= nb && w.vec) return PPE_OK;
+  free_ws(w);
+  const int64_t N = (int64_t)p->nx * p->ny;
+  const dim3 g = stencil_grid(p->coef, 2, 1);  // the smallest tile height has the most workgroups
+  w.Pmax = (int)(g.x * g.y);
+  w.vec = (float*)dev_alloc(sizeof(float) * 4 * N * nb);
+  w.part = (double*)dev_alloc(sizeof(double) * 3 * (size_t)w.Pmax * nb);
+  w.st = (SolveState*)dev_alloc(sizeof(SolveState) * nb);
+  w.flags = (int32_t*)dev_alloc(sizeof(int32_t) * nb);
+  w.call = (CallArgs*)dev_alloc(sizeof(CallArgs));
+  if (!w.vec || !w.part || !w.st || !w.flags || !w.call) {
+    free_ws(w);
+    return set_error(PPE_ERR_HIP, "device allocation of the solve workspace (%d x %lld cells) failed", nb,
+                     (long long)N);
+  }
+  if (hipHostMalloc((void**)&w.h_flags, sizeof(int32_t) * 2 * nb, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&w.h_state, sizeof(SolveState) * nb, hipHostMallocDefault) != hipSuccess) {
+    free_ws(w);
+    return set_error(PPE_ERR_HIP, "pinned host allocation failed");
+  }
+  for (auto& e : w.ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      free_ws(w);
+      return set_error(PPE_ERR_HIP, "hipEventCreate failed");
+    }
+  w.nb = nb;
+  return PPE_OK;
+}
+
+PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int tol_kind, int zero_x0) {
+  SolveWs& w = p->ws;
+  PcgArgs a{};
+  a.c = p->coef;
+  const dim3 g = stencil_grid(p->coef, R, 1);
+  a.P = (int)(g.x * g.y);
+  a.R = R;
+  a.N = (int64_t)p->nx * p->ny;
+  const size_t N = (size_t)a.N * nb;
+  a.xc = w.vec;
+  a.r = w.vec + N;
+  a.p0 = w.vec + 2 * N;
+  a.p1 = w.vec + 3 * N;
+  a.partA = w.part;
+  a.partB = w.part + (size_t)a.P * nb;
+  a.st = w.st;
+  a.flags = w.flags;
+  a.call = w.call;
+  a.tol = tol;
+  a.tol_kind = tol_kind;
+  a.jacobi = jacobi;
+  a.zero_x0 = zero_x0;
+  return a;
+}
+
+int default_rows(const ppe_problem* p, int nb) {
+  // Enough workgroups to cover the 256 CUs several times over.
+  const int64_t cells = (int64_t)p->nx * p->ny * nb;
+  if (cells >= (int64_t)4 << 20) return 16;
+  if (cells >= (int64_t)1 << 20) return 8;
+  if (cells >= (int64_t)1 << 17) return 4;
+  return 2;
+}
+
+int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o) {
+  const int r = o.rows_per_wave;
+  if (r == 2 || r == 4 || r == 8 || r == 16) return r;
+  return default_rows(p, nb);
+}
+
+#define HIPCHK(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return set_error(PPE_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+  } while (0)
+
+// Capture (once per workspace shape) a graph of `chunk` CG iteration pairs
+// with alternating parity.
+static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int chunk) {
+  SolveWs& w = p->ws;
+  const int key[4] = {nb, a.R, a.jacobi, chunk};
+  if (w.exec && std::equal(key, key + 4, w.exec_key)) return PPE_OK;
+  if (w.exec) {
+    (void)hipGraphExecDestroy(w.exec);
+    w.exec = nullptr;
+  }
+  if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < chunk; ++k) launch_pcg_pair(a, nb, k & 1, 0, 0, p->cap_stream);
+  hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+  if (e != hipSuccess) return set_error(PPE_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&w.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    w.exec = nullptr;
+    return set_error(PPE_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+  }
+  std::copy(key, key + 4, w.exec_key);
+  return PPE_OK;
+}
+
+// Replays iteration chunks until every solve of the batch has finished. The
+// next chunk is enqueued before the previous chunk's flags are inspected, so
+// the device never waits for the host.
+ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o,
+                          hipStream_t s) {
+  SolveWs& w = p->ws;
+  int chunk = o.chunk > 0 ? o.chunk : 64;
+  chunk += chunk & 1;
+  if (o.use_graph) {
+    ppe_status st = get_chunk_graph(p, a, nb, chunk);
+    if (st != PPE_OK) return st;
+  }
+  const int64_t max_chunks = (2 * (int64_t)o.max_iter + 4) / chunk + 2;
+  for (int64_t c = 0; c < max_chunks; ++c) {
+    if (o.use_graph) {
+      HIPCHK(hipGraphLaunch(w.exec, s));
+    } else {
+      for (int k = 0; k < chunk; ++k) launch_pcg_pair(a, nb, k & 1, 0, 0, s);
+      HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipMemcpyAsync(w.h_flags + (c & 1) * nb, w.flags, sizeof(int32_t) * nb,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(w.ev[c & 1], s));
+    if (c >= 1) {
+      HIPCHK(hipEventSynchronize(w.ev[(c - 1) & 1]));
+      const int32_t* fl = w.h_flags + ((c - 1) & 1) * nb;
+      bool all = true;
+      for (int i = 0; i < nb; ++i) all = all && fl[i] != DONE_NO;
+      if (all) return PPE_OK;
+    }
+  }
+  return PPE_OK;
+}
+
+static ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s,
+                             bool hybrid) {
+  SolveWs& w = p->ws;
+  HIPCHK(hipMemcpyAsync(w.h_state, w.st, sizeof(SolveState) * nb, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ppe_status worst = PPE_OK;
+  for (int i = 0; i < nb; ++i) {
+    const SolveState& S = w.h_state[i];
+    ppe_status st = S.done == DONE_CONV ? PPE_OK
+                    : S.done == DONE_NONFINITE ? PPE_ERR_NONFINITE
+                                               : PPE_NOT_CONVERGED;
+    if (st == PPE_ERR_NONFINITE) worst = st;
+    else if (st == PPE_NOT_CONVERGED && worst == PPE_OK) worst = st;
+    if (stats) {
+      ppe_solve_stats& o = stats[i];
+      memset(&o, 0, sizeof o);
+      o.status = st;
+      o.iters_total = S.it_final;
+      o.iters_cg = S.itcg_final;
+      o.iters_dlsm = hybrid ? S.n_dlsm : 0;
+      o.dlsm_rejected = hybrid ? S.n_rej : 0;
+      o.reliable_updates = S.nru_final;
+      o.abs_res_true = std::sqrt(S.rr_final);
+      o.bnorm = std::sqrt(S.bnorm2);
+      o.rel_res_true = S.bnorm2 > 0 ? std::sqrt(S.rr_final / S.bnorm2) : o.abs_res_true;
+      o.rhs_mean_removed = S.bmean;
+      o.ms_total = ms;
+    }
+  }
+  if (worst == PPE_ERR_NONFINITE) set_error(worst, "non-finite value in a source field or iteration");
+  return worst;
+}
+
+ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, const void* x,
+                            const ppe_solve_opts* opts) {
+  if (!p) return set_error(PPE_ERR_INVALID_ARG, "problem is NULL");
+  if (nb < 0) return set_error(PPE_ERR_INVALID_ARG, "nb < 0");
+  if (nb > 65535) return set_error(PPE_ERR_INVALID_ARG, "nb > 65535");
+  if (nb > 0 && (!f || !x)) return set_error(PPE_ERR_INVALID_ARG, "f or x is NULL");
+  if (opts) {
+    if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol))
+      return set_error(PPE_ERR_INVALID_ARG, "tol must be finite and >= 0");
+    if (opts->max_iter < 0) return set_error(PPE_ERR_INVALID_ARG, "max_iter < 0");
+    if (opts->precond != PPE_PC_NONE && opts->precond != PPE_PC_JACOBI)
+      return set_error(PPE_ERR_UNSUPPORTED, "preconditioner %d is not built", opts->precond);
+    if (opts->tol_kind != PPE_TOL_RELATIVE && opts->tol_kind != PPE_TOL_ABSOLUTE)
+      return set_error(PPE_ERR_INVALID_ARG, "tol_kind %d", opts->tol_kind);
+    if (!(opts->reliable_delta > 0.0 && opts->reliable_delta < 1.0))
+      return set_error(PPE_ERR_INVALID_ARG, "reliable_delta must lie in (0, 1)");
+  }
+  return PPE_OK;
+}
+
+ppe_status solve_plain_impl(ppe_problem* p, int32_t nb, const float* f, double* x,
+                            const ppe_solve_opts& o, ppe_solve_stats* stats, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  ppe_status st = ensure_ws(p, nb);
+  if (st != PPE_OK) return st;
+  const int R = rows_of(p, nb, o);
+  const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
+  launch_pcg_setup(a, nb, s);
+  HIPCHK(hipGetLastError());
+  st = run_pcg_chunks(p, a, nb, o, s);
+  if (st != PPE_OK) return st;
+  launch_pcg_finish(a, nb, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return fill_stats(p, nb, stats, ms, s, false);
+}
+
+}  // namespace ppe
+
+using namespace ppe;
+
+extern "C" {
+
+const char* ppe_last_error(void) { return g_last_error.c_str(); }
+
+void ppe_solve_opts_default(ppe_solve_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof *o);
+  o->tol = 1e-6;
+  o->tol_kind = PPE_TOL_RELATIVE;
+  o->precond = PPE_PC_JACOBI;
+  o->max_iter = 100000;
+  o->num_cg = 3;
+  o->num_dlsm = 2;
+  o->direction = PPE_DIR_NET;
+  o->reliable_delta = 0.3;
+  o->rows_per_wave = 0;
+  o->use_graph = 1;
+  o->chunk = 0;
+}
+
+ppe_status ppe_problem_create(const ppe_grid_desc* g, ppe_problem** out) {
+  if (!g || !out) return set_error(PPE_ERR_INVALID_ARG, "grid or out is NULL");
+  *out = nullptr;
+  const int nx = g->nx, ny = g->ny;
+  if (nx < 2 || ny < 2) return set_error(PPE_ERR_SHAPE, "nx, ny must be >= 2 (got %d x %d)", nx, ny);
+  if ((int64_t)nx * ny > ((int64_t)1 << 30)) return set_error(PPE_ERR_SHAPE, "grid too large");
+  if (!g->xc || !g->yc || !g->hx || !g->hy) return set_error(PPE_ERR_INVALID_ARG, "NULL coordinate array");
+  for (int i = 0; i < nx; ++i) {
+    if (!std::isfinite(g->xc[i]) || !(g->hx[i] > 0.0) || !std::isfinite(g->hx[i]))
+      return set_error(PPE_ERR_INVALID_ARG, "xc/hx invalid at i=%d", i);
+    if (i > 0 && !(g->xc[i] > g->xc[i - 1])) return set_error(PPE_ERR_INVALID_ARG, "xc not increasing at %d", i);
+  }
+  for (int j = 0; j < ny; ++j) {
+    if (!std::isfinite(g->yc[j]) || !(g->hy[j] > 0.0) || !std::isfinite(g->hy[j]))
+      return set_error(PPE_ERR_INVALID_ARG, "yc/hy invalid at j=%d", j);
+    if (j > 0 && !(g->yc[j] > g->yc[j - 1])) return set_error(PPE_ERR_INVALID_ARG, "yc not increasing at %d", j);
+  }
+  ppe_problem* p = new ppe_problem();
+  p->nx = nx;
+  p->ny = ny;
+  p->xc.assign(g->xc, g->xc + nx);
+  p->yc.assign(g->yc, g->yc + ny);
+  p->hx.assign(g->hx, g->hx + nx);
+  p->hy.assign(g->hy, g->hy + ny);
+  if (g->mask) p->mask.assign(g->mask, g->mask + (size_t)nx * ny);
+  ppe_status st = problem_upload(p);
+  if (st != PPE_OK) {
+    ppe_problem_destroy(p);
+    return st;
+  }
+  *out = p;
+  return PPE_OK;
+}
+
+void ppe_problem_destroy(ppe_problem* p) {
+  if (!p) return;
+  free_ws(p->ws);
+  problem_release(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  delete p;
+}
+
+ppe_status ppe_apply_f32(const ppe_problem* p, int32_t nb, const float* x, float* y, hipStream_t s) {
+  if (!p || nb < 0 || (nb > 0 && (!x || !y))) return set_error(PPE_ERR_INVALID_ARG, "bad arguments");
+  if (nb == 0) return PPE_OK;
+  launch_apply_f32(p->coef, nb, x, y, 4, s);
+  HIPCHK(hipGetLastError());
+  return PPE_OK;
+}
+
+ppe_status ppe_apply_f64(const ppe_problem* p, int32_t nb, const double* x, double* y, hipStream_t s) {
+  if (!p || nb < 0 || (nb > 0 && (!x || !y))) return set_error(PPE_ERR_INVALID_ARG, "bad arguments");
+  if (nb == 0) return PPE_OK;
+  launch_apply_f64(p->coef, nb, x, y, 4, s);
+  HIPCHK(hipGetLastError());
+  return PPE_OK;
+}
+
+ppe_status ppe_solve_plain(ppe_problem* p, int32_t nb, const float* f, double* x,
+                           const ppe_solve_opts* opts, ppe_solve_stats* stats, hipStream_t s) {
+  ppe_solve_opts o;
+  ppe_solve_opts_default(&o);
+  if (opts) o = *opts;
+  ppe_status st = check_solve_args(p, nb, f, x, &o);
+  if (st != PPE_OK) return st;
+  if (nb == 0) return PPE_OK;
+  return solve_plain_impl(p, nb, f, x, o, stats, s);
+}
+
+ppe_status ppe_profile_pcg(ppe_problem* p, int32_t nb, const float* f, double* x,
+                           const ppe_solve_opts* opts, int32_t reps, double* ms_out, hipStream_t s) {
+  ppe_solve_opts o;
+  ppe_solve_opts_default(&o);
+  if (opts) o = *opts;
+  ppe_status st = check_solve_args(p, nb, f, x, &o);
+  if (st != PPE_OK) return st;
+  if (nb < 1 || reps < 1 || !ms_out) return set_error(PPE_ERR_INVALID_ARG, "nb, reps >= 1 and ms_out required");
+  st = ensure_ws(p, nb);
+  if (st != PPE_OK) return st;
+  const int R = rows_of(p, nb, o);
+  const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
+  launch_pcg_setup(a, nb, s);
+  launch_pcg_phase_a(a, nb, 0, s);
+  hipEvent_t e0, e1, e2;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventCreate(&e2));
+  // Repeated phase-A launches of parity 0 all read the setup's state slots and
+  // redo the same CG step; repeated phase-B launches redo one residual update.
+  HIPCHK(hipEventRecord(e0, s));
+  for (int k = 0; k < reps; ++k) launch_pcg_phase_a(a, nb, 0, s);
+  HIPCHK(hipEventRecord(e1, s));
+  for (int k = 0; k < reps; ++k) launch_pcg_phase_b(a, nb, 0, s);
+  HIPCHK(hipEventRecord(e2, s));
+  HIPCHK(hipEventSynchronize(e2));
+  float t1 = 0, t2 = 0;
+  HIPCHK(hipEventElapsedTime(&t1, e0, e1));
+  HIPCHK(hipEventElapsedTime(&t2, e1, e2));
+  ms_out[0] = t1 / reps;
+  ms_out[1] = t2 / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  return PPE_OK;
+}
+
+ppe_status ppe_profile_copy(const void* src, void* dst, int64_t bytes, int32_t reps, double* ms_out,
+                            hipStream_t s) {
+  if (!src || !dst || bytes <= 0 || bytes % 16 || reps < 1 || !ms_out)
+    return set_error(PPE_ERR_INVALID_ARG, "copy needs buffers, bytes > 0 divisible by 16, reps >= 1");
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int k = 0; k < reps; ++k) launch_copy16(src, dst, bytes / 16, s);
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float t = 0;
+  HIPCHK(hipEventElapsedTime(&t, e0, e1));
+  ms_out[0] = t / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return PPE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// Host-side internals shared by the C-ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ppe.h"
+#include "kernels.hpp"
+
+namespace ppe {
+
+// Solver workspace of one problem (grown on demand to the largest batch).
+struct SolveWs {
+  int nb = 0;
+  int Pmax = 0;
+  float* vec = nullptr;      // x_c, r, p0, p1: [4][nb][N]
+  double* part = nullptr;    // partial sums: [3][nb][Pmax]
+  SolveState* st = nullptr;  // [nb]
+  int32_t* flags = nullptr;  // [nb]
+  CallArgs* call = nullptr;
+  int32_t* h_flags = nullptr;     // pinned [2][nb]
+  SolveState* h_state = nullptr;  // pinned [nb]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraphExec_t exec = nullptr;
+  int exec_key[4] = {0, 0, 0, 0};
+};
+
+struct NetCache;  // per (problem, net) constants of the network (defined with the net)
+
+}  // namespace ppe
+
+struct ppe_problem {
+  int nx = 0, ny = 0;
+  std::vector<double> xc, yc, hx, hy;
+  std::vector<uint8_t> mask;  // empty = no obstacle
+  // device copies of the 1D coefficients
+  void* dev_coef = nullptr;
+  uint8_t* d_mask = nullptr;
+  ppe::Coef coef{};
+  ppe::SolveWs ws;
+  hipStream_t cap_stream = nullptr;
+  ppe::NetCache* net_cache = nullptr;
+};
+
+namespace ppe {
+extern thread_local std::string g_last_error;
+ppe_status set_error(ppe_status st, const char* fmt, ...);
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+ppe_status problem_upload(ppe_problem* p);
+void problem_release(ppe_problem* p);
+ppe_status ensure_ws(ppe_problem* p, int nb);
+PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int tol_kind, int zero_x0);
+int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o);
+ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s);
+ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, const void* x,
+                            const ppe_solve_opts* opts);
+}  // namespace ppe

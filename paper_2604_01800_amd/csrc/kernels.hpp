@@ -1,0 +1,35 @@
+// Host-side declarations of the kernel launchers.
+#pragma once
+#include "common.hpp"
+
+namespace ppe {
+
+// Arguments of the PCG kernels (passed by value; pointers are device memory).
+struct PcgArgs {
+  Coef c;
+  int P;             // workgroups per solve
+  int R;             // rows per wavefront
+  int64_t N;         // cells per solve
+  float *xc, *r, *p0, *p1;  // [nb][N] each
+  double *partA, *partB;    // [nb][P], [nb][2][P]
+  SolveState* st;           // [nb]
+  int32_t* flags;           // [nb] done codes
+  const CallArgs* call;
+  double tol;
+  int tol_kind;
+  int jacobi;
+  int zero_x0;  // the setup zeroes x before the first residual
+};
+
+dim3 stencil_grid(const Coef& c, int R, int nb);
+void launch_apply_f32(const Coef& c, int nb, const float* x, float* y, int R, hipStream_t s);
+void launch_apply_f64(const Coef& c, int nb, const double* x, double* y, int R, hipStream_t s);
+void launch_set_call(CallArgs* c, const float* f, double* x, int max_iter, double delta2, hipStream_t s);
+void launch_pcg_setup(const PcgArgs& a, int nb, hipStream_t s);
+void launch_pcg_pair(const PcgArgs& a, int nb, int par, int force, int force_restart, hipStream_t s);
+void launch_pcg_phase_a(const PcgArgs& a, int nb, int par, hipStream_t s);
+void launch_pcg_phase_b(const PcgArgs& a, int nb, int par, hipStream_t s);
+void launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
+void launch_pcg_finish(const PcgArgs& a, int nb, hipStream_t s);
+
+}  // namespace ppe

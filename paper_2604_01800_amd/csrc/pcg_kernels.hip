@@ -1,0 +1,721 @@
+// Stencil and fused Jacobi-PCG kernels (HIP, gfx950).
+//
+// Operator: the finite-volume form of the pressure Poisson matrix of Eq. 10,
+// matrix-free from 1D coefficient arrays (see Coef). PCG: the textbook
+// preconditioned CG (Saad, Alg. 9.1) with D = diag(A), reorganised into two
+// fused passes per iteration, each ending in a fixed-order FP64 grid reduction:
+//
+//   phase A: x_c += alpha_{k-1} p_{k-1}          (deferred solution update)
+//            p_k  = D^-1 r_k + beta_k p_{k-1}    (p recomputed on the halo)
+//            q    = A p_k, partial sums of p.q   -> writes p_k, x_c   (20 B/cell)
+//   phase B: alpha_k = rho_k / p.q
+//            r   -= alpha_k A p_k (q recomputed), partial sums of r.r, r.z
+//                                                -> writes r          (12 B/cell)
+//
+// Vectors are FP32; products of FP32 values are exact in FP64 and every sum is
+// FP64. The solution is accumulated in FP64 by reliable updates (residual
+// replacement, Sleijpen & van der Vorst 1996): when the recursive residual has
+// fallen by delta against the last true residual (or claims convergence, or
+// the iteration limit is hit), phase A flushes x_c into the FP64 solution and
+// phase B recomputes r = b - A x in FP64. Convergence is declared only on that
+// FP64 true residual, with the L2 stopping rule of Sec. 2.2.
+//
+// Layout: one wavefront owns a 64-column strip and walks R rows down, keeping
+// the rows above/below in registers; east/west neighbours come from lane
+// shuffles, and lanes 0 and 63 load the halo columns. Workgroup = 4 waves =
+// 64 x 4R cells. Each workgroup of the consuming kernel re-reduces the
+// producer's per-workgroup partials in the same order, so all workgroups see
+// bit-identical scalars and take identical decisions without atomics.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ppe {
+
+template <typename T>
+struct ColCtx {
+  int i, ih;
+  bool ok, hok;
+  T hx, gw, ge;    // own column
+  T hxh, gwh, geh; // halo column (lanes 0 and 63)
+};
+
+template <typename T>
+__device__ __forceinline__ ColCtx<T> col_ctx(int nx, const T* hx, const T* gx, int i0) {
+  ColCtx<T> c;
+  const int lane = threadIdx.x & (kWave - 1);
+  c.i = i0 + lane;
+  c.ok = c.i < nx;
+  c.ih = (lane == 0) ? c.i - 1 : c.i + 1;
+  c.hok = (lane == 0 || lane == kWave - 1) && c.ih >= 0 && c.ih < nx;
+  c.hx = c.ok ? hx[c.i] : T(0);
+  c.gw = c.ok ? gx[c.i] : T(0);
+  c.ge = c.ok ? gx[c.i + 1] : T(0);
+  c.hxh = c.hok ? hx[c.ih] : T(0);
+  c.gwh = c.hok ? gx[c.ih] : T(0);
+  c.geh = c.hok ? gx[c.ih + 1] : T(0);
+  return c;
+}
+
+template <typename T>
+__device__ __forceinline__ T stencil5(T vc, T ve, T vw, T vn, T vs, T hyj, T gs, T gn, T hx, T gw,
+                                      T ge) {
+  return hyj * (ge * (vc - ve) + gw * (vc - vw)) + hx * (gn * (vc - vn) + gs * (vc - vs));
+}
+
+// East/west neighbours of every lane's value: lane i receives lanes i+1 and
+// i-1 of the wavefront; lanes 63 and 0 take the halo value instead.
+// FP32 uses DPP wave shifts (wave_shl:1 reads lane i+1, wave_shr:1 lane i-1);
+// FP64 uses lane shuffles.
+__device__ __forceinline__ void east_west(float vcur, float vh, float& ve, float& vw) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int bits = __float_as_int(vcur);
+  const float e = __int_as_float(__builtin_amdgcn_update_dpp(0, bits, 0x130, 0xf, 0xf, false));
+  const float w = __int_as_float(__builtin_amdgcn_update_dpp(0, bits, 0x138, 0xf, 0xf, false));
+  ve = (lane == kWave - 1) ? vh : e;
+  vw = (lane == 0) ? vh : w;
+}
+
+__device__ __forceinline__ void east_west(double vcur, double vh, double& ve, double& vw) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const double e = __shfl_down(vcur, 1, kWave);
+  const double w = __shfl_up(vcur, 1, kWave);
+  ve = (lane == kWave - 1) ? vh : e;
+  vw = (lane == 0) ? vh : w;
+}
+
+__device__ __forceinline__ int wave_row0(int R) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  return (blockIdx.y * kWaves + w) * R;
+}
+
+__device__ __forceinline__ int block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
+// ---------------------------------------------------------------------------
+// y = A x for a batch (parity checks and the line-search step).
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void k_apply(Coef c, const T* __restrict__ x, T* __restrict__ y) {
+  const int nx = c.nx, ny = c.ny;
+  const size_t off = (size_t)blockIdx.z * nx * ny;
+  x += off;
+  y += off;
+  const T* hx = sizeof(T) == 8 ? (const T*)c.hx64 : (const T*)c.hx;
+  const T* hy = sizeof(T) == 8 ? (const T*)c.hy64 : (const T*)c.hy;
+  const T* gx = sizeof(T) == 8 ? (const T*)c.gx64 : (const T*)c.gx;
+  const T* gy = sizeof(T) == 8 ? (const T*)c.gy64 : (const T*)c.gy;
+  const ColCtx<T> cc = col_ctx<T>(nx, hx, gx, blockIdx.x * kWave);
+  const int j0 = wave_row0(R);
+  if (j0 >= ny) return;
+  T vprev = (j0 > 0 && cc.ok) ? x[(size_t)(j0 - 1) * nx + cc.i] : T(0);
+  T vcur = cc.ok ? x[(size_t)j0 * nx + cc.i] : T(0);
+  for (int q = 0; q < R; ++q) {
+    const int j = j0 + q;
+    if (j >= ny) break;
+    const T vnext = (j + 1 < ny && cc.ok) ? x[(size_t)(j + 1) * nx + cc.i] : T(0);
+    const T vh = cc.hok ? x[(size_t)j * nx + cc.ih] : T(0);
+    T ve, vw;
+    east_west(vcur, vh, ve, vw);
+    const T v = stencil5(vcur, ve, vw, vnext, vprev, hy[j], gy[j], gy[j + 1], cc.hx, cc.gw, cc.ge);
+    if (cc.ok) y[(size_t)j * nx + cc.i] = v;
+    vprev = vcur;
+    vcur = vnext;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Right-hand side: b = (cell area) f - mean. Pass 1: partial sums of area*f
+// and a count of non-finite source values.
+__global__ __launch_bounds__(kBlock) void k_rhs_sum(PcgArgs a) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  const float* f = a.call->f + (size_t)s * a.N;
+  const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+  const int j0 = wave_row0(a.R);
+  double sum = 0.0, bad = 0.0;
+  if (i < nx) {
+    const double hxi = a.c.hx64[i];
+    for (int q = 0; q < a.R; ++q) {
+      const int j = j0 + q;
+      if (j >= ny) break;
+      const float v = f[(size_t)j * nx + i];
+      if (!isfinite(v)) bad += 1.0;
+      else sum += hxi * a.c.hy64[j] * (double)v;
+    }
+  }
+  sum = block_sum(sum, lds);
+  bad = block_sum(bad, lds);
+  if (threadIdx.x == 0) {
+    double* pb = a.partB + (size_t)s * 2 * a.P;
+    pb[block_linear()] = sum;
+    pb[a.P + block_linear()] = bad;
+  }
+}
+
+// Pass 2: the mean, then partial sums of |b|^2.
+__global__ __launch_bounds__(kBlock) void k_rhs_norm(PcgArgs a) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  const double* pb = a.partB + (size_t)s * 2 * a.P;
+  const double sum = reduce_partials(pb, a.P, lds);
+  const double bad = reduce_partials(pb + a.P, a.P, lds);
+  const double mean = sum / (double)a.N;
+  SolveState* st = a.st + s;
+  if (is_first_block()) {
+    st->bmean = mean;
+    st->nonfinite = bad > 0.0;
+  }
+  const float* f = a.call->f + (size_t)s * a.N;
+  const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+  const int j0 = wave_row0(a.R);
+  double bb = 0.0;
+  if (i < nx && bad == 0.0) {
+    const double hxi = a.c.hx64[i];
+    for (int q = 0; q < a.R; ++q) {
+      const int j = j0 + q;
+      if (j >= ny) break;
+      const double b = hxi * a.c.hy64[j] * (double)f[(size_t)j * nx + i] - mean;
+      bb += b * b;
+    }
+  }
+  if (a.zero_x0 && i < nx) {
+    double* x = a.call->x + (size_t)s * a.N;
+    for (int q = 0; q < a.R; ++q) {
+      const int j = j0 + q;
+      if (j >= ny) break;
+      x[(size_t)j * nx + i] = 0.0;
+    }
+  }
+  bb = block_sum(bb, lds);
+  if (threadIdx.x == 0) a.partA[(size_t)s * a.P + block_linear()] = bb;
+}
+
+// Register tile of one wavefront: rows j0-1 .. j0+R of its own column and
+// rows j0 .. j0+R-1 of its halo column (lanes 0 and 63). All loads of a tile
+// are issued together, before any dependent arithmetic.
+template <typename T, int R>
+struct Tile {
+  T own[R + 2];
+  T halo[R];
+};
+
+struct ColIdx {
+  int i, ih;
+  bool ok, hok;
+};
+
+__device__ __forceinline__ ColIdx col_idx(int nx) {
+  ColIdx c;
+  const int lane = threadIdx.x & (kWave - 1);
+  c.i = blockIdx.x * kWave + lane;
+  c.ok = c.i < nx;
+  c.ih = (lane == 0) ? c.i - 1 : c.i + 1;
+  c.hok = (lane == 0 || lane == kWave - 1) && c.ih >= 0 && c.ih < nx;
+  return c;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void load_tile(const T* __restrict__ v, int nx, int ny, int j0, const ColIdx& c,
+                                          Tile<T, R>& t) {
+#pragma unroll
+  for (int q = 0; q < R + 2; ++q) {
+    const int j = j0 - 1 + q;
+    t.own[q] = (c.ok && j >= 0 && j < ny) ? v[(size_t)j * nx + c.i] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int j = j0 + q;
+    t.halo[q] = (c.hok && j < ny) ? v[(size_t)j * nx + c.ih] : T(0);
+  }
+}
+
+// Wave-uniform row coefficients for rows j0-1 .. j0+R: hy (R+2 values) and the
+// south faces gy[j0-1 .. j0+R+1] (R+3 values); 0 outside the grid.
+template <typename T, int R>
+struct RowCoef {
+  T hy[R + 2];
+  T gy[R + 3];
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void load_rows(const T* __restrict__ hy, const T* __restrict__ gy, int ny, int j0,
+                                          RowCoef<T, R>& rc) {
+#pragma unroll
+  for (int q = 0; q < R + 2; ++q) {
+    const int j = j0 - 1 + q;
+    rc.hy[q] = (j >= 0 && j < ny) ? hy[j] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < R + 3; ++q) {
+    const int k = j0 - 1 + q;
+    rc.gy[q] = (k >= 0 && k <= ny) ? gy[k] : T(0);
+  }
+}
+
+// Column coefficients of the own column and the halo column.
+template <typename T>
+struct ColCoef {
+  T hx, gw, ge, hxh, gwh, geh;
+};
+
+template <typename T>
+__device__ __forceinline__ ColCoef<T> load_cols(const T* __restrict__ hx, const T* __restrict__ gx,
+                                                const ColIdx& c) {
+  ColCoef<T> k;
+  k.hx = c.ok ? hx[c.i] : T(0);
+  k.gw = c.ok ? gx[c.i] : T(0);
+  k.ge = c.ok ? gx[c.i + 1] : T(0);
+  k.hxh = c.hok ? hx[c.ih] : T(0);
+  k.gwh = c.hok ? gx[c.ih] : T(0);
+  k.geh = c.hok ? gx[c.ih + 1] : T(0);
+  return k;
+}
+
+// y = A v on the R rows of the tile; own[q + 1] is the centre of output row q.
+template <typename T, int R>
+__device__ __forceinline__ void stencil_rows(const Tile<T, R>& v, const RowCoef<T, R>& rc, const ColCoef<T>& k,
+                                             T (&out)[R]) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const T vc = v.own[q + 1];
+    T ve, vw;
+    east_west(vc, v.halo[q], ve, vw);
+    out[q] = stencil5(vc, ve, vw, v.own[q + 2], v.own[q], rc.hy[q + 1], rc.gy[q + 1], rc.gy[q + 2], k.hx,
+                      k.gw, k.ge);
+  }
+}
+
+// True residual r = b - A x in FP64 over this wave's rows; stores r in FP32
+// and accumulates |r|^2 (FP64 value) and r.D^-1 r (FP32 value, exact products).
+// It runs a handful of times per solve, so it walks the rows with a small
+// register footprint instead of holding a full FP64 tile.
+template <int R, bool JAC>
+__device__ __forceinline__ void true_residual_rows(const PcgArgs& a, int s, double& acc_rr, double& acc_rz) {
+  const int nx = a.c.nx, ny = a.c.ny;
+  const size_t off = (size_t)s * a.N;
+  const double* __restrict__ x = a.call->x + off;
+  const float* __restrict__ f = a.call->f + off;
+  float* __restrict__ r = a.r + off;
+  const ColIdx ci = col_idx(nx);
+  const int j0 = wave_row0(R);
+  if (j0 >= ny) return;
+  const ColCoef<double> k = load_cols<double>(a.c.hx64, a.c.gx64, ci);
+  const ColCoef<float> kf = load_cols<float>(a.c.hx, a.c.gx, ci);
+  const double bmean = a.st[s].bmean;
+  double vprev = (ci.ok && j0 > 0) ? x[(size_t)(j0 - 1) * nx + ci.i] : 0.0;
+  double vcur = ci.ok ? x[(size_t)j0 * nx + ci.i] : 0.0;
+#pragma unroll 1
+  for (int q = 0; q < R; ++q) {
+    const int j = j0 + q;
+    if (j >= ny) break;
+    const double vnext = (ci.ok && j + 1 < ny) ? x[(size_t)(j + 1) * nx + ci.i] : 0.0;
+    const double vh = ci.hok ? x[(size_t)j * nx + ci.ih] : 0.0;
+    const float fv = ci.ok ? f[(size_t)j * nx + ci.i] : 0.f;
+    double ve, vw;
+    east_west(vcur, vh, ve, vw);
+    const double hyj = a.c.hy64[j];
+    const double Ax = stencil5(vcur, ve, vw, vnext, vprev, hyj, a.c.gy64[j], a.c.gy64[j + 1], k.hx, k.gw, k.ge);
+    if (ci.ok) {
+      const double rv = (k.hx * hyj * (double)fv - bmean) - Ax;
+      const float rr = (float)rv;
+      r[(size_t)j * nx + ci.i] = rr;
+      acc_rr += rv * rv;
+      float z = rr;
+      if (JAC) z = rr / (a.c.hy[j] * (kf.gw + kf.ge) + kf.hx * (a.c.gy[j] + a.c.gy[j + 1]));
+      acc_rz += (double)rr * (double)z;
+    }
+    vprev = vcur;
+    vcur = vnext;
+  }
+}
+
+template <int R, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs a) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  SolveState* st = a.st + s;
+  const double bb = reduce_partials(a.partA + (size_t)s * a.P, a.P, lds);
+  const bool bad = st->nonfinite;
+  if (is_first_block()) {
+    st->bnorm2 = bb;
+    st->thr2 = a.tol_kind == 1 ? a.tol * a.tol : a.tol * a.tol * bb;
+    st->mode[1] = MODE_TRUE;
+    st->restart[1] = 1;
+    st->it[1] = 0;
+    st->it_cg[1] = 0;
+    st->n_ru[1] = 0;
+    st->alpha[1] = 0.0;
+    st->rho[1] = 0.0;
+    st->rr_ru[1] = 0.0;
+    st->rr_last[1] = 0.0;
+    st->brk[1] = 0;
+    st->n_dlsm = 0;
+    st->n_rej = 0;
+    st->done = bad ? DONE_NONFINITE : DONE_NO;
+    st->it_final = 0;
+    st->nru_final = 0;
+    st->itcg_final = 0;
+    st->rr_final = 0.0;
+    a.flags[s] = bad ? DONE_NONFINITE : DONE_NO;
+  }
+  double rr = 0.0, rz = 0.0;
+  if (!bad) {
+    const size_t off = (size_t)s * a.N;
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j0 = wave_row0(R);
+    if (i < nx) {
+      for (int q = 0; q < R; ++q) {
+        const int j = j0 + q;
+        if (j >= ny) break;
+        const size_t k = off + (size_t)j * nx + i;
+        a.xc[k] = 0.f;
+        a.p0[k] = 0.f;
+        a.p1[k] = 0.f;
+      }
+    }
+    true_residual_rows<R, JAC>(a, s, rr, rz);
+  }
+  rr = block_sum(rr, lds);
+  rz = block_sum(rz, lds);
+  if (threadIdx.x == 0) {
+    double* pb = a.partB + (size_t)s * 2 * a.P;
+    pb[block_linear()] = rr;
+    pb[a.P + block_linear()] = rz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phase A. par selects the p buffer written (p[par]) and the state slots.
+// force != 0 makes this pass a reliable update (used after line-search
+// blocks); force_restart then also restarts CG (beta = 0) afterwards.
+template <int R, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force, int force_restart) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  SolveState* st = a.st + s;
+  if (block_done(st)) return;
+  const int P = a.P, pm = par ^ 1;
+  const size_t off = (size_t)s * a.N;
+  const float* __restrict__ r = a.r + off;
+  float* __restrict__ xc = a.xc + off;
+  const float* __restrict__ pold = (par ? a.p0 : a.p1) + off;
+  float* __restrict__ pnew = (par ? a.p1 : a.p0) + off;
+  const ColIdx ci = col_idx(nx);
+  const int j0 = wave_row0(R);
+
+  // Tile loads first: they do not depend on the scalars reduced below.
+  Tile<float, R> tr, tp;
+  float xcv[R];
+  load_tile<float, R>(r, nx, ny, j0, ci, tr);
+  load_tile<float, R>(pold, nx, ny, j0, ci, tp);
+#pragma unroll
+  for (int q = 0; q < R; ++q) xcv[q] = (ci.ok && j0 + q < ny) ? xc[(size_t)(j0 + q) * nx + ci.i] : 0.f;
+  RowCoef<float, R> rc;
+  load_rows<float, R>(a.c.hy, a.c.gy, ny, j0, rc);
+  const ColCoef<float> k = load_cols<float>(a.c.hx, a.c.gx, ci);
+
+  const double* pb = a.partB + (size_t)s * 2 * P;
+  const double rr = reduce_partials(pb, P, lds);
+  const double rz = reduce_partials(pb + P, P, lds);
+  const int max_iter = a.call->max_iter;
+  const int prev_mode = st->mode[pm];
+  const int it = st->it[pm], nru = st->n_ru[pm], itcg = st->it_cg[pm];
+  const int restart = st->restart[pm], brk = st->brk[pm];
+  double rr_ru = st->rr_ru[pm];
+  int done = DONE_NO;
+  bool flush = false;
+  if (prev_mode == MODE_TRUE) {
+    rr_ru = rr;
+    if (!isfinite(rr)) done = DONE_NONFINITE;
+    else if (rr <= st->thr2) done = DONE_CONV;
+    else if (it >= max_iter) done = DONE_MAXIT;
+  } else {
+    flush = force || brk || !isfinite(rr) || rr <= st->thr2 || rr <= a.call->delta2 * rr_ru ||
+            it >= max_iter;
+  }
+  const bool leader = is_first_block();
+  if (done) {
+    if (leader) {
+      st->rr_final = rr;
+      st->it_final = it;
+      st->nru_final = nru;
+      st->itcg_final = itcg;
+      st->done = done;
+      a.flags[s] = done;
+    }
+    return;
+  }
+
+  if (flush) {
+    // Reliable update, part 1: x += x_c + alpha p_old in FP64; x_c = 0; p carried over.
+    double* __restrict__ x = a.call->x + off;
+    const double al = st->alpha[pm];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int j = j0 + q;
+      if (ci.ok && j < ny) {
+        const size_t kk = (size_t)j * nx + ci.i;
+        const float po = tp.own[q + 1];
+        x[kk] = x[kk] + ((double)xcv[q] + al * (double)po);
+        xc[kk] = 0.f;
+        pnew[kk] = po;
+      }
+    }
+    if (leader) {
+      st->mode[par] = MODE_TRUE;
+      st->it[par] = it;
+      st->it_cg[par] = itcg;
+      st->n_ru[par] = nru + 1;
+      st->rho[par] = st->rho[pm];
+      st->rr_ru[par] = rr_ru;
+      st->rr_last[par] = rr;
+      st->restart[par] = (force && force_restart) || brk;
+      st->brk[par] = 0;
+    }
+    return;
+  }
+
+  double beta_d = (prev_mode == MODE_TRUE && restart) ? 0.0 : rz / st->rho[pm];
+  if (!isfinite(beta_d)) beta_d = 0.0;
+  const float beta = (float)beta_d;
+  const float alpha_prev = (float)st->alpha[pm];
+  // p = D^-1 r + beta p_old on the own rows (j0-1 .. j0+R) and the halo rows.
+  Tile<float, R> pn;
+#pragma unroll
+  for (int q = 0; q < R + 2; ++q) {
+    const int j = j0 - 1 + q;
+    const bool ok = ci.ok && j >= 0 && j < ny;
+    float z = tr.own[q];
+    if (JAC && ok) z = z / (rc.hy[q] * (k.gw + k.ge) + k.hx * (rc.gy[q] + rc.gy[q + 1]));
+    pn.own[q] = ok ? z + beta * tp.own[q] : 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int j = j0 + q;
+    const bool ok = ci.hok && j < ny;
+    float z = tr.halo[q];
+    if (JAC && ok) z = z / (rc.hy[q + 1] * (k.gwh + k.geh) + k.hxh * (rc.gy[q + 1] + rc.gy[q + 2]));
+    pn.halo[q] = ok ? z + beta * tp.halo[q] : 0.f;
+  }
+  float Ap[R];
+  stencil_rows<float, R>(pn, rc, k, Ap);
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int j = j0 + q;
+    if (ci.ok && j < ny) {
+      const size_t kk = (size_t)j * nx + ci.i;
+      const float pv = pn.own[q + 1];
+      pnew[kk] = pv;
+      xc[kk] = xcv[q] + alpha_prev * tp.own[q + 1];
+      acc += (double)pv * (double)Ap[q];
+    }
+  }
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) a.partA[(size_t)s * P + block_linear()] = acc;
+  if (leader) {
+    st->mode[par] = MODE_CG;
+    st->it[par] = it + 1;
+    st->it_cg[par] = itcg + 1;
+    st->n_ru[par] = nru;
+    st->rho[par] = rz;
+    st->rr_ru[par] = rr_ru;
+    st->rr_last[par] = rr;
+    st->restart[par] = 0;
+    st->brk[par] = 0;
+  }
+}
+
+// Phase B: CG residual update, or the FP64 true residual after a flush.
+template <int R, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int par) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  SolveState* st = a.st + s;
+  if (block_done(st)) return;
+  const int P = a.P;
+  const bool leader = is_first_block();
+  double acc_rr = 0.0, acc_rz = 0.0;
+  if (st->mode[par] == MODE_TRUE) {
+    true_residual_rows<R, JAC>(a, s, acc_rr, acc_rz);
+    if (leader) {
+      st->alpha[par] = 0.0;
+      st->brk[par] = 0;
+    }
+  } else {
+    const size_t off = (size_t)s * a.N;
+    float* __restrict__ r = a.r + off;
+    const float* __restrict__ p = (par ? a.p1 : a.p0) + off;
+    const ColIdx ci = col_idx(nx);
+    const int j0 = wave_row0(R);
+    Tile<float, R> tp;
+    float rv[R];
+    load_tile<float, R>(p, nx, ny, j0, ci, tp);
+#pragma unroll
+    for (int q = 0; q < R; ++q) rv[q] = (ci.ok && j0 + q < ny) ? r[(size_t)(j0 + q) * nx + ci.i] : 0.f;
+    RowCoef<float, R> rc;
+    load_rows<float, R>(a.c.hy, a.c.gy, ny, j0, rc);
+    const ColCoef<float> k = load_cols<float>(a.c.hx, a.c.gx, ci);
+    const double pq = reduce_partials(a.partA + (size_t)s * P, P, lds);
+    double al = st->rho[par] / pq;
+    const bool brk = !(pq > 0.0) || !isfinite(al);
+    if (brk) al = 0.0;
+    const float alf = (float)al;
+    float Ap[R];
+    stencil_rows<float, R>(tp, rc, k, Ap);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int j = j0 + q;
+      if (ci.ok && j < ny) {
+        const float rn = rv[q] - alf * Ap[q];
+        r[(size_t)j * nx + ci.i] = rn;
+        acc_rr += (double)rn * (double)rn;
+        float z = rn;
+        if (JAC) z = rn / (rc.hy[q + 1] * (k.gw + k.ge) + k.hx * (rc.gy[q + 1] + rc.gy[q + 2]));
+        acc_rz += (double)rn * (double)z;
+      }
+    }
+    if (leader) {
+      st->alpha[par] = al;
+      st->brk[par] = brk;
+    }
+  }
+  acc_rr = block_sum(acc_rr, lds);
+  acc_rz = block_sum(acc_rz, lds);
+  if (threadIdx.x == 0) {
+    double* pb = a.partB + (size_t)s * 2 * P;
+    pb[block_linear()] = acc_rr;
+    pb[P + block_linear()] = acc_rz;
+  }
+}
+
+// Minimum-norm output: subtract the plain mean of x.
+__global__ __launch_bounds__(kBlock) void k_x_sum(PcgArgs a) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  const double* x = a.call->x + (size_t)s * a.N;
+  const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+  const int j0 = wave_row0(a.R);
+  double sum = 0.0;
+  if (i < nx)
+    for (int q = 0; q < a.R; ++q) {
+      const int j = j0 + q;
+      if (j >= ny) break;
+      sum += x[(size_t)j * nx + i];
+    }
+  sum = block_sum(sum, lds);
+  if (threadIdx.x == 0) a.partA[(size_t)s * a.P + block_linear()] = sum;
+}
+
+__global__ __launch_bounds__(kBlock) void k_x_shift(PcgArgs a) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  const double mean = reduce_partials(a.partA + (size_t)s * a.P, a.P, lds) / (double)a.N;
+  if (is_first_block()) a.st[s].xmean = mean;
+  double* x = a.call->x + (size_t)s * a.N;
+  const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+  const int j0 = wave_row0(a.R);
+  if (i < nx)
+    for (int q = 0; q < a.R; ++q) {
+      const int j = j0 + q;
+      if (j >= ny) break;
+      x[(size_t)j * nx + i] -= mean;
+    }
+}
+
+// Plain 16-byte-per-lane copy: the bandwidth reference and the byte-counter
+// calibration kernel.
+__global__ __launch_bounds__(kBlock) void k_copy16(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                   int64_t n16) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n16) dst[k] = src[k];
+}
+
+void launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s) {
+  const int64_t blocks = (n16 + kBlock - 1) / kBlock;
+  k_copy16<<<(unsigned)blocks, kBlock, 0, s>>>((const float4*)src, (float4*)dst, n16);
+}
+
+__global__ void k_set_call(CallArgs* c, const float* f, double* x, int max_iter, double delta2) {
+  c->f = f;
+  c->x = x;
+  c->max_iter = max_iter;
+  c->delta2 = delta2;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (template dispatch on the rows-per-wave tile height).
+template <int R>
+static dim3 grid_of(const Coef& c, int nb) {
+  return dim3((c.nx + kWave - 1) / kWave, (c.ny + kWaves * R - 1) / (kWaves * R), nb);
+}
+
+dim3 stencil_grid(const Coef& c, int R, int nb) {
+  return dim3((c.nx + kWave - 1) / kWave, (c.ny + kWaves * R - 1) / (kWaves * R), nb);
+}
+
+#define PPE_DISPATCH_R(R, ...)                     \
+  switch (R) {                                     \
+    case 2: { constexpr int RR = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int RR = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int RR = 8; __VA_ARGS__; } break;   \
+    default: { constexpr int RR = 16; __VA_ARGS__; } break; \
+  }
+
+void launch_apply_f32(const Coef& c, int nb, const float* x, float* y, int R, hipStream_t s) {
+  PPE_DISPATCH_R(R, k_apply<float, RR><<<grid_of<RR>(c, nb), kBlock, 0, s>>>(c, x, y));
+}
+void launch_apply_f64(const Coef& c, int nb, const double* x, double* y, int R, hipStream_t s) {
+  PPE_DISPATCH_R(R, k_apply<double, RR><<<grid_of<RR>(c, nb), kBlock, 0, s>>>(c, x, y));
+}
+
+void launch_set_call(CallArgs* c, const float* f, double* x, int max_iter, double delta2,
+                     hipStream_t s) {
+  k_set_call<<<1, 1, 0, s>>>(c, f, x, max_iter, delta2);
+}
+
+void launch_pcg_setup(const PcgArgs& a, int nb, hipStream_t s) {
+  const dim3 g = stencil_grid(a.c, a.R, nb);
+  k_rhs_sum<<<g, kBlock, 0, s>>>(a);
+  k_rhs_norm<<<g, kBlock, 0, s>>>(a);
+  if (a.jacobi) {
+    PPE_DISPATCH_R(a.R, k_pcg_init<RR, true><<<g, kBlock, 0, s>>>(a));
+  } else {
+    PPE_DISPATCH_R(a.R, k_pcg_init<RR, false><<<g, kBlock, 0, s>>>(a));
+  }
+}
+
+void launch_pcg_pair(const PcgArgs& a, int nb, int par, int force, int force_restart, hipStream_t s) {
+  const dim3 g = stencil_grid(a.c, a.R, nb);
+  if (a.jacobi) {
+    PPE_DISPATCH_R(a.R, k_pcg_a<RR, true><<<g, kBlock, 0, s>>>(a, par, force, force_restart);
+                   k_pcg_b<RR, true><<<g, kBlock, 0, s>>>(a, par));
+  } else {
+    PPE_DISPATCH_R(a.R, k_pcg_a<RR, false><<<g, kBlock, 0, s>>>(a, par, force, force_restart);
+                   k_pcg_b<RR, false><<<g, kBlock, 0, s>>>(a, par));
+  }
+}
+
+void launch_pcg_phase_a(const PcgArgs& a, int nb, int par, hipStream_t s) {
+  const dim3 g = stencil_grid(a.c, a.R, nb);
+  if (a.jacobi) {
+    PPE_DISPATCH_R(a.R, k_pcg_a<RR, true><<<g, kBlock, 0, s>>>(a, par, 0, 0));
+  } else {
+    PPE_DISPATCH_R(a.R, k_pcg_a<RR, false><<<g, kBlock, 0, s>>>(a, par, 0, 0));
+  }
+}
+
+void launch_pcg_phase_b(const PcgArgs& a, int nb, int par, hipStream_t s) {
+  const dim3 g = stencil_grid(a.c, a.R, nb);
+  if (a.jacobi) {
+    PPE_DISPATCH_R(a.R, k_pcg_b<RR, true><<<g, kBlock, 0, s>>>(a, par));
+  } else {
+    PPE_DISPATCH_R(a.R, k_pcg_b<RR, false><<<g, kBlock, 0, s>>>(a, par));
+  }
+}
+
+void launch_pcg_finish(const PcgArgs& a, int nb, hipStream_t s) {
+  const dim3 g = stencil_grid(a.c, a.R, nb);
+  k_x_sum<<<g, kBlock, 0, s>>>(a);
+  k_x_shift<<<g, kBlock, 0, s>>>(a);
+}
+
+}  // namespace ppe

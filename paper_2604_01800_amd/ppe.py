@@ -1,0 +1,235 @@
+"""Python binding of the C-ABI in include/ppe.h (argument marshalling only).
+
+Every function has the name of the C entry point it calls. Device arrays are
+torch tensors on the current HIP device (torch supplies memory and streams
+only; all arithmetic runs in the library's HIP kernels). The library must be
+built (``python -m paper_2604_01800_amd.build``); loading fails loudly if it
+is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libppe_hip.so")
+
+PPE_OK, PPE_NOT_CONVERGED = 0, 1
+PPE_ERR_INVALID_ARG, PPE_ERR_SHAPE, PPE_ERR_UNSUPPORTED, PPE_ERR_HIP, PPE_ERR_NONFINITE = -1, -2, -3, -4, -5
+PPE_PC_NONE, PPE_PC_JACOBI = 0, 1
+PPE_TOL_RELATIVE, PPE_TOL_ABSOLUTE = 0, 1
+PPE_DIR_NET, PPE_DIR_ZERO, PPE_DIR_JACOBI, PPE_DIR_NAN, PPE_DIR_ONES = 0, 1, 2, 3, 4
+
+
+class PPEError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ppe status {status}: {msg}")
+        self.status = status
+
+
+class ppe_grid_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("xc", ctypes.c_void_p), ("yc", ctypes.c_void_p),
+                ("hx", ctypes.c_void_p), ("hy", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p)]
+
+
+class ppe_solve_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("tol_kind", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("num_cg", ctypes.c_int32), ("num_dlsm", ctypes.c_int32),
+                ("direction", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
+                ("rows_per_wave", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("zero_x0", ctypes.c_int32)]
+
+
+class ppe_solve_stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters_total", ctypes.c_int32), ("iters_cg", ctypes.c_int32),
+                ("iters_dlsm", ctypes.c_int32), ("dlsm_rejected", ctypes.c_int32),
+                ("reliable_updates", ctypes.c_int32), ("rel_res_true", ctypes.c_double),
+                ("abs_res_true", ctypes.c_double), ("bnorm", ctypes.c_double),
+                ("rhs_mean_removed", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ppe_net_config(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("base_channels", ctypes.c_int32), ("basis", ctypes.c_int32),
+                ("trunk_width", ctypes.c_int32), ("trunk_hidden", ctypes.c_int32),
+                ("phi_hidden", ctypes.c_int32), ("use_eta", ctypes.c_int32), ("use_spacing", ctypes.c_int32)]
+
+
+class ppe_train_opts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("seed", ctypes.c_uint64), ("step", ctypes.c_int64)]
+
+
+# name -> (restype, argtypes); every symbol declared in include/ppe.h
+_vp, _i32, _i64, _u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+_P = ctypes.POINTER
+SIGNATURES = {
+    "ppe_problem_create": (_i32, [_P(ppe_grid_desc), _P(_vp)]),
+    "ppe_problem_destroy": (None, [_vp]),
+    "ppe_solve_opts_default": (None, [_P(ppe_solve_opts)]),
+    "ppe_apply_f32": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "ppe_apply_f64": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "ppe_solve_plain": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_solve_opts), _vp, _vp]),
+    "ppe_solve_hybrid": (_i32, [_vp, _vp, _i32, _vp, _vp, _P(ppe_solve_opts), _vp, _vp]),
+    "ppe_net_config_default": (None, [_P(ppe_net_config)]),
+    "ppe_net_create": (_i32, [_P(ppe_net_config), _u64, _P(_vp)]),
+    "ppe_net_destroy": (None, [_vp]),
+    "ppe_net_num_params": (_i64, [_vp]),
+    "ppe_net_set_params": (_i32, [_vp, _vp, _i64]),
+    "ppe_net_get_params": (_i32, [_vp, _vp, _i64]),
+    "ppe_net_save": (_i32, [_vp, ctypes.c_char_p]),
+    "ppe_net_load": (_i32, [_vp, ctypes.c_char_p]),
+    "ppe_net_forward": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
+    "ppe_net_train_step": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_train_opts), _vp, _vp, _vp]),
+    "ppe_profile_pcg": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_solve_opts), _i32, _vp, _vp]),
+    "ppe_profile_copy": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),
+    "ppe_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load the built HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_01800_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    L = lib()
+    return {n for n in SIGNATURES if hasattr(L, n)}
+
+
+def _check(st, allow=(PPE_OK,)):
+    if st not in allow:
+        raise PPEError(st, lib().ppe_last_error().decode())
+    return st
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """Owns a ppe_problem handle (one grid)."""
+
+    def __init__(self, grid):
+        self.nx, self.ny = int(grid.nx), int(grid.ny)
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (grid.xc, grid.yc, grid.hx, grid.hy)]
+        mask = None if getattr(grid, "mask", None) is None else np.ascontiguousarray(grid.mask, dtype=np.uint8)
+        d = ppe_grid_desc(self.nx, self.ny, *[a.ctypes.data for a in arrs],
+                          mask.ctypes.data if mask is not None else None)
+        h = ctypes.c_void_p()
+        _check(lib().ppe_problem_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.ppe_problem_destroy(h)
+            self.handle = None
+
+
+def ppe_problem_create(grid) -> Problem:
+    return Problem(grid)
+
+
+def ppe_solve_opts_default(**kw) -> ppe_solve_opts:
+    o = ppe_solve_opts()
+    lib().ppe_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _nb(t, prob):
+    if t.dim() == 2:
+        nb = 1
+        shape = tuple(t.shape)
+    else:
+        nb = t.shape[0]
+        shape = tuple(t.shape[1:])
+    if shape != (prob.ny, prob.nx):
+        raise ValueError(f"field shape {shape} != ({prob.ny}, {prob.nx})")
+    return nb
+
+
+def ppe_apply_f32(prob: Problem, x, y, stream=None):
+    import torch
+    nb = _nb(x, prob)
+    _check(lib().ppe_apply_f32(prob.handle, nb, _dev(x, torch.float32, "x"), _dev(y, torch.float32, "y"),
+                               _stream(stream)))
+
+
+def ppe_apply_f64(prob: Problem, x, y, stream=None):
+    import torch
+    nb = _nb(x, prob)
+    _check(lib().ppe_apply_f64(prob.handle, nb, _dev(x, torch.float64, "x"), _dev(y, torch.float64, "y"),
+                               _stream(stream)))
+
+
+def ppe_solve_plain(prob: Problem, f, x, opts=None, stream=None):
+    """Returns (status, [stats dict per solve])."""
+    import torch
+    nb = _nb(f, prob)
+    if _nb(x, prob) != nb:
+        raise ValueError("f and x batch sizes differ")
+    opts = opts or ppe_solve_opts_default()
+    stats = (ppe_solve_stats * max(nb, 1))()
+    st = lib().ppe_solve_plain(prob.handle, nb, _dev(f, torch.float32, "f"), _dev(x, torch.float64, "x"),
+                               ctypes.byref(opts), ctypes.cast(stats, ctypes.c_void_p), _stream(stream))
+    _check(st, (PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))
+    return st, [stats[i].as_dict() for i in range(nb)]
+
+
+def ppe_profile_pcg(prob: Problem, f, x, opts=None, reps=50, stream=None):
+    """Average ms of one phase-A and one phase-B launch (HIP events)."""
+    import torch
+    nb = _nb(f, prob)
+    opts = opts or ppe_solve_opts_default()
+    out = (ctypes.c_double * 2)()
+    _check(lib().ppe_profile_pcg(prob.handle, nb, _dev(f, torch.float32, "f"), _dev(x, torch.float64, "x"),
+                                 ctypes.byref(opts), reps, ctypes.cast(out, ctypes.c_void_p), _stream(stream)))
+    return out[0], out[1]
+
+
+def ppe_profile_copy(src, dst, reps=20, stream=None):
+    """Average ms of a device copy of src.nbytes bytes into dst."""
+    if src.nbytes != dst.nbytes:
+        raise ValueError("src and dst sizes differ")
+    out = (ctypes.c_double * 1)()
+    _check(lib().ppe_profile_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                  src.nbytes, reps, ctypes.cast(out, ctypes.c_void_p), _stream(stream)))
+    return out[0]
