@@ -1,0 +1,172 @@
+"""Pins of the FP64 DeepONet / Mesh-Conv oracle (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2604_01800_amd import inputs
+from oracle import net as onet
+
+
+def small_cfg(**kw):
+    c = onet.NetConfig(levels=3, base_channels=4, basis=6, trunk_width=8, trunk_hidden=2, phi_hidden=3)
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_param_count_default():
+    cfg = onet.NetConfig()
+    n = onet.num_params(cfg)
+    # conv weights ~1.8 M for 32/64/128/256 channels, trunk ~66 K
+    assert 1.7e6 < n < 2.1e6, n
+
+
+def test_mconv_matches_explicit_loops():
+    rng = np.random.default_rng(0)
+    cin, cout, H, W, Hd = 3, 2, 5, 6, 3
+    p = {"m.W": torch.from_numpy(rng.standard_normal((cout, cin, 3, 3))),
+         "m.b": torch.from_numpy(rng.standard_normal(cout)),
+         "m.phi.W1": torch.from_numpy(rng.standard_normal((Hd, 4))),
+         "m.phi.b1": torch.from_numpy(rng.standard_normal(Hd)),
+         "m.phi.W2": torch.from_numpy(rng.standard_normal((cin, Hd))),
+         "m.phi.b2": torch.from_numpy(rng.standard_normal(cin))}
+    X = rng.standard_normal((1, cin, H, W))
+    delta = rng.uniform(0.2, 2.0, size=(4, H, W))
+    Y = onet.mconv(p, "m", torch.from_numpy(X), torch.from_numpy(delta), 1).numpy()
+    W1, b1, W2, b2 = (p[k].numpy() for k in ("m.phi.W1", "m.phi.b1", "m.phi.W2", "m.phi.b2"))
+    Wc, bc = p["m.W"].numpy(), p["m.b"].numpy()
+    ref = np.zeros((1, cout, H, W))
+    for y in range(H):
+        for x in range(W):
+            for co in range(cout):
+                acc = bc[co]
+                for ky in range(3):
+                    for kx in range(3):
+                        yy, xx = y + ky - 1, x + kx - 1
+                        if not (0 <= yy < H and 0 <= xx < W):
+                            continue
+                        h = [math.tanh(sum(W1[a, k] * delta[k, yy, xx] for k in range(4)) + b1[a]) for a in range(Hd)]
+                        for ci in range(cin):
+                            phi = sum(W2[ci, a] * h[a] for a in range(Hd)) + b2[ci]
+                            acc += Wc[co, ci, ky, kx] * math.exp(-phi * phi) * X[0, ci, yy, xx]
+                ref[0, co, y, x] = acc
+    np.testing.assert_allclose(Y, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_uniform_grid_eta_is_constant():
+    cfg = small_cfg()
+    g = inputs.make_grid(16, 24, 0.0)
+    feats = onet.grid_features(g, cfg)
+    rng = np.random.default_rng(1)
+    p = onet.init_params(cfg, rng)
+    for l, (delta, widths) in enumerate(feats):
+        eta = onet.eta_map(p, f"enc{l}.b", delta, 1)
+        assert torch.allclose(eta, eta[:, :1, :1].expand_as(eta), atol=1e-12)
+        # unit spacing everywhere after normalisation by the mean spacing
+        assert torch.allclose(delta, torch.ones_like(delta), atol=1e-12)
+        assert torch.allclose(widths, torch.ones_like(widths), atol=1e-12)
+
+
+def test_level_coordinates_closed_form():
+    n, beta, L = 64, 2.0, 4
+    faces = inputs.tanh_faces(n, beta)
+    g = inputs.make_grid(n, n, beta)
+    cs, hs = onet.level_coords(g.xc, g.hx, L)
+    for l in range(L):
+        k = 2 ** l
+        np.testing.assert_allclose(hs[l], faces[k::k] - faces[:-k:k][: n // k], rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(cs[l], np.mean(g.xc.reshape(-1, k), axis=1), rtol=1e-13)
+
+
+def test_boundary_padding_nearest_neighbour():
+    g = inputs.make_grid(32, 16, 1.5, 2.5)
+    cfg = small_cfg()
+    feats = onet.grid_features(g, cfg)
+    for delta, _ in feats:
+        d = delta.numpy()
+        assert np.allclose(d[0, :, 0], d[0, :, 1]) and np.allclose(d[1, :, -1], d[1, :, -2])
+        assert np.allclose(d[2, 0, :], d[2, 1, :]) and np.allclose(d[3, -1, :], d[3, -2, :])
+        assert np.allclose(d[1, :, :-1], d[0, :, 1:])  # right distance of i = left distance of i+1
+
+
+def test_input_scale_invariance():
+    cfg = small_cfg()
+    g = inputs.make_grid(16, 16, 1.5)
+    p = onet.init_params(cfg, np.random.default_rng(2))
+    r = np.random.default_rng(3).standard_normal((16, 16))
+    y1 = onet.forward(p, cfg, g, r)
+    y2 = onet.forward(p, cfg, g, 37.5 * r)
+    torch.testing.assert_close(y1, y2, rtol=1e-12, atol=1e-12)
+
+
+def test_branch_translation_equivariance():
+    # On a uniform grid (constant eta and widths) the branch commutes with
+    # shifts by multiples of 2^(L-1), away from the borders.
+    cfg = small_cfg()
+    n, s = 96, 8
+    g = inputs.make_grid(n, n, 0.0)
+    feats = onet.grid_features(g, cfg)
+    p = onet.init_params(cfg, np.random.default_rng(4))
+    x = torch.zeros((1, 2, n, n), dtype=torch.float64)
+    x[0, 0, 36:60, 36:60] = torch.from_numpy(np.random.default_rng(5).standard_normal((24, 24)))
+    xs = torch.roll(x, shifts=(s, s), dims=(2, 3))
+    b1 = onet.branch(p, cfg, x, feats)
+    b2 = onet.branch(p, cfg, xs, feats)
+    # the receptive-field radius of this 3-level U-Net is about 23 pixels, so
+    # the compared windows stay at least 24 pixels from every border
+    torch.testing.assert_close(b2[..., 32 + s:64 + s, 32 + s:64 + s], b1[..., 32:64, 32:64], rtol=1e-10, atol=1e-10)
+
+
+def test_conv_ablation_flag():
+    cfg = small_cfg(use_eta=0)
+    g = inputs.make_grid(16, 16, 2.0)
+    feats = onet.grid_features(g, cfg)
+    p = onet.init_params(cfg, np.random.default_rng(6))
+    eta = onet.eta_map(p, "enc0.a", feats[0][0], 0)
+    assert torch.all(eta == 1)
+
+
+def _apply_torch(g):
+    """Differentiable FP64 operator (the Kronecker form, built independently)."""
+    from oracle import direct
+    A = torch.from_numpy(direct.kron_matrix(g))
+    return lambda grid, y: (A @ y.reshape(-1)).reshape(y.shape)
+
+
+def test_fd_gradients_of_residual_loss():
+    cfg = small_cfg()
+    n = 16
+    rng = np.random.default_rng(7)
+    grids = [inputs.make_grid(n, n, b) for b in (1.2, 2.1)]
+    R = np.stack([inputs.grf(gr, 10 + i, ell=0.2, J=64) for i, gr in enumerate(grids)])
+    R -= R.mean(axis=(1, 2), keepdims=True)
+    p = onet.init_params(cfg, rng)
+    for t in p.values():
+        t.requires_grad_(True)
+    apply = _apply_torch(grids[0])
+    applies = {id(gr): _apply_torch(gr) for gr in grids}
+    app = lambda grid, y: applies[id(grid)](grid, y)
+    loss = onet.residual_loss(p, cfg, grids, R, apply=app)
+    loss.backward()
+    names = ["enc0.a.W", "enc1.b.phi.W2", "dec0.c.phi.W1", "up1.W", "head.b", "trunk0.W", "trunk_out.W",
+             "gamma", "enc2.a.b", "dec1.d.W"]
+    checked = 0
+    for name in names:
+        t = p[name]
+        flat = t.detach().reshape(-1)
+        for idx in rng.choice(flat.numel(), size=min(3, flat.numel()), replace=False):
+            v0 = float(flat[idx])
+            h = 1e-6 * max(1.0, abs(v0))
+            vals = []
+            for sgn in (+1, -1):
+                with torch.no_grad():
+                    q = {k: v.detach().clone() for k, v in p.items()}
+                    q[name].reshape(-1)[idx] = v0 + sgn * h
+                    vals.append(float(onet.residual_loss(q, cfg, grids, R, apply=app)))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = float(t.grad.reshape(-1)[idx])
+            assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * abs(float(loss.detach()))), (name, idx, fd, an)
+            checked += 1
+    assert checked >= 20
