@@ -39,6 +39,24 @@ def workload(n=1024, beta=1.75, seed=0):
     return g, f
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed hardware-counter run, if the
+    kernel sources are unchanged since then (else None)."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "pcg_phases_1024_plain.counters.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for f in rec["kernel_sources"]:
+            h.update(open(os.path.join(here, f), "rb").read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return float(rec["traffic_bytes_per_launch"][kernel])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(g, f, iters_full, sample_iters):
     """Single-threaded FP64 oracle PCG: time `sample_iters` iterations, scale."""
     import oracle
@@ -68,6 +86,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=200)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the phase-kernel timing launches and a 64 MiB calibration copy "
+                         "(for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -84,6 +105,15 @@ def main():
     f = torch.from_numpy(f_np[None]).cuda()
     x = torch.zeros((1, g.ny, g.nx), dtype=torch.float64, device="cuda")
     opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1)
+
+    if args.kernels_only:
+        ms_a, ms_b = ppe.ppe_profile_pcg(prob, f, x, opts, reps=args.profile_reps)
+        src = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        ms_c = ppe.ppe_profile_copy(src, dst, reps=args.profile_reps)
+        torch.cuda.synchronize()
+        print(json.dumps({"phase_a_ms": ms_a, "phase_b_ms": ms_b, "copy_64MiB_ms": ms_c}), flush=True)
+        return
 
     for _ in range(args.warmup):
         ppe.ppe_solve_plain(prob, f, x, opts)
@@ -141,7 +171,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": ach_a / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic("k_pcg_a"),
+            "algorithmic_bytes": BYTES_PHASE_A * N,
         },
     }
     if not args.no_cpu_baseline:

@@ -181,10 +181,11 @@ ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* proble
 
 /* ---- measurement ---- */
 /* Average duration in ms of one phase-A launch (ms_out[0]) and one phase-B
- * launch (ms_out[1]) of the fused PCG iteration on nb systems, timed with HIP
- * events on stream s over `reps` back-to-back launches that repeat one CG
- * iteration's work after a solve setup on (f, x). x is used as the initial
- * guess and its content is left unspecified. ms_out: host [2]. */
+ * launch (ms_out[1]) of the fused PCG iteration on nb systems: after a solve
+ * setup on (f, x), `reps` iterations run eagerly on stream s, as in a solve,
+ * each launch carrying its own start/stop HIP events (hipExtLaunchKernelGGL),
+ * so the elapsed times are kernel execution times. x is used as the
+ * initial guess and its content is left unspecified. ms_out: host [2]. */
 ppe_status ppe_profile_pcg(ppe_problem* p, int32_t nb, const float* f, double* x,
                            const ppe_solve_opts* opts, int32_t reps, double* ms_out, hipStream_t s);
 /* Average ms of a plain device copy of `bytes` bytes (multiple of 16) from src

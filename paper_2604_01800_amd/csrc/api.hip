@@ -375,27 +375,27 @@ ppe_status ppe_profile_pcg(ppe_problem* p, int32_t nb, const float* f, double* x
   const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
   launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
   launch_pcg_setup(a, nb, s);
-  launch_pcg_phase_a(a, nb, 0, s);
-  hipEvent_t e0, e1, e2;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventCreate(&e2));
-  // Repeated phase-A launches of parity 0 all read the setup's state slots and
-  // redo the same CG step; repeated phase-B launches redo one residual update.
-  HIPCHK(hipEventRecord(e0, s));
-  for (int k = 0; k < reps; ++k) launch_pcg_phase_a(a, nb, 0, s);
-  HIPCHK(hipEventRecord(e1, s));
-  for (int k = 0; k < reps; ++k) launch_pcg_phase_b(a, nb, 0, s);
-  HIPCHK(hipEventRecord(e2, s));
-  HIPCHK(hipEventSynchronize(e2));
-  float t1 = 0, t2 = 0;
-  HIPCHK(hipEventElapsedTime(&t1, e0, e1));
-  HIPCHK(hipEventElapsedTime(&t2, e1, e2));
-  ms_out[0] = t1 / reps;
-  ms_out[1] = t2 / reps;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(e2);
+  // The real iteration sequence (A, B alternating with their parities); each
+  // launch carries its own start/stop events (recorded by its dispatch).
+  std::vector<hipEvent_t> ev(4 * reps);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  for (int k = 0; k < reps; ++k) {
+    launch_pcg_phase_timed(a, nb, k & 1, 0, s, ev[4 * k], ev[4 * k + 1]);
+    launch_pcg_phase_timed(a, nb, k & 1, 1, s, ev[4 * k + 2], ev[4 * k + 3]);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventSynchronize(ev[4 * reps - 1]));
+  double ta = 0, tb = 0;
+  for (int k = 0; k < reps; ++k) {
+    float t1 = 0, t2 = 0;
+    HIPCHK(hipEventElapsedTime(&t1, ev[4 * k], ev[4 * k + 1]));
+    HIPCHK(hipEventElapsedTime(&t2, ev[4 * k + 2], ev[4 * k + 3]));
+    ta += t1;
+    tb += t2;
+  }
+  ms_out[0] = ta / reps;
+  ms_out[1] = tb / reps;
+  for (auto& e : ev) (void)hipEventDestroy(e);
   return PPE_OK;
 }
 

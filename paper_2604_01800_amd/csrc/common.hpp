@@ -14,6 +14,9 @@ constexpr int kBlock = kWave * kWaves;
 //   (A v)_ij = hy_j [gx_{i+1}(v_ij - v_{i+1,j}) + gx_i (v_ij - v_{i-1,j})]
 //            + hx_i [gy_{j+1}(v_ij - v_{i,j+1}) + gy_j (v_ij - v_{i,j-1})]
 // gx[k] = 1/(xc[k] - xc[k-1]) for the interior x-face k, 0 at the walls.
+// The arrays are zero-padded in memory: indices in [-kPadX, n + kPadX) for
+// hx/gx and [-kPadY0, n + kPadY1) for hy/gy are valid and read 0 off the grid.
+constexpr int kPadX = 64, kPadY0 = 32, kPadY1 = 128;
 struct Coef {
   int nx, ny;
   const float *hx, *hy, *gx, *gy;          // [nx], [ny], [nx+1], [ny+1]
@@ -34,6 +37,7 @@ struct SolveState {
   int32_t restart[2]; // next CG step uses beta = 0
   int32_t brk[2];     // phase B hit p.Ap <= 0 (breakdown)
   int32_t it_cg[2];
+  int32_t dflag[2];   // done code as seen after phase A of this parity
   // written once per solve
   double bmean, bnorm2, thr2, xmean;
   double rr_final;
@@ -79,16 +83,6 @@ __device__ __forceinline__ double reduce_partials(const double* part, int P, dou
   double s = 0.0;
   for (int k = threadIdx.x; k < P; k += kBlock) s += part[k];
   return block_sum(s, lds);
-}
-
-// Reads the solve's done flag once per workgroup and broadcasts it, so every
-// wavefront of the workgroup takes the same early exit (the flag may be set by
-// another workgroup of the same launch while this one starts).
-__device__ __forceinline__ bool block_done(const SolveState* st) {
-  __shared__ int32_t s_done;
-  if (threadIdx.x == 0) s_done = *(volatile const int32_t*)&st->done;
-  __syncthreads();
-  return s_done != 0;
 }
 
 __device__ __forceinline__ bool is_first_block() {

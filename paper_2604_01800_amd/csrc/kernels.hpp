@@ -30,6 +30,8 @@ void launch_pcg_pair(const PcgArgs& a, int nb, int par, int force, int force_res
 void launch_pcg_phase_a(const PcgArgs& a, int nb, int par, hipStream_t s);
 void launch_pcg_phase_b(const PcgArgs& a, int nb, int par, hipStream_t s);
 void launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
+void launch_pcg_phase_timed(const PcgArgs& a, int nb, int par, int phase, hipStream_t s, hipEvent_t e0,
+                            hipEvent_t e1);
 void launch_pcg_finish(const PcgArgs& a, int nb, hipStream_t s);
 
 }  // namespace ppe

@@ -26,6 +26,8 @@
 // 64 x 4R cells. Each workgroup of the consuming kernel re-reduces the
 // producer's per-workgroup partials in the same order, so all workgroups see
 // bit-identical scalars and take identical decisions without atomics.
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -83,12 +85,35 @@ __device__ __forceinline__ void east_west(double vcur, double vh, double& ve, do
   vw = (lane == 0) ? vh : w;
 }
 
-__device__ __forceinline__ int wave_row0(int R) {
+// Tile placement. A solve's workgroups form a 1D grid of 8 * ceil(T / 8)
+// (T = tiles of 64 columns x 4R rows). Workgroups are dispatched round-robin
+// over the 8 XCDs, so workgroup b runs on XCD b % 8; it takes logical tile
+// (b % 8) * ceil(T / 8) + b / 8. Each XCD thus owns a contiguous band of
+// tiles, and most halo rows and columns it reads sit in its own L2.
+// Workgroups past the last tile are idle (no loads or stores, zero partials).
+struct TileXY {
+  int i0;     // first column of the tile
+  int j0;     // first row of this wavefront
+  bool valid;
+};
+
+__device__ __forceinline__ TileXY tile_xy(int nx, int ny, int R) {
+  const int gxt = (nx + kWave - 1) / kWave;
+  const int gyt = (ny + kWaves * R - 1) / (kWaves * R);
+  const int T = gxt * gyt;
+  const int per = (T + 7) / 8;
+  const int b = blockIdx.x;
+  int t = (b & 7) * per + (b >> 3);
+  TileXY o;
+  o.valid = t < T;
+  if (!o.valid) t = 0;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  return (blockIdx.y * kWaves + w) * R;
+  o.i0 = (t % gxt) * kWave;
+  o.j0 = ((t / gxt) * kWaves + w) * R;
+  return o;
 }
 
-__device__ __forceinline__ int block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
+__device__ __forceinline__ int block_linear() { return blockIdx.x; }
 
 // ---------------------------------------------------------------------------
 // y = A x for a batch (parity checks and the line-search step).
@@ -102,8 +127,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(Coef c, const T* __restrict__ 
   const T* hy = sizeof(T) == 8 ? (const T*)c.hy64 : (const T*)c.hy;
   const T* gx = sizeof(T) == 8 ? (const T*)c.gx64 : (const T*)c.gx;
   const T* gy = sizeof(T) == 8 ? (const T*)c.gy64 : (const T*)c.gy;
-  const ColCtx<T> cc = col_ctx<T>(nx, hx, gx, blockIdx.x * kWave);
-  const int j0 = wave_row0(R);
+  const TileXY tl = tile_xy(nx, ny, R);
+  if (!tl.valid) return;
+  const ColCtx<T> cc = col_ctx<T>(nx, hx, gx, tl.i0);
+  const int j0 = tl.j0;
   if (j0 >= ny) return;
   T vprev = (j0 > 0 && cc.ok) ? x[(size_t)(j0 - 1) * nx + cc.i] : T(0);
   T vcur = cc.ok ? x[(size_t)j0 * nx + cc.i] : T(0);
@@ -128,8 +155,9 @@ __global__ __launch_bounds__(kBlock) void k_rhs_sum(PcgArgs a) {
   __shared__ double lds[kWaves];
   const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
   const float* f = a.call->f + (size_t)s * a.N;
-  const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-  const int j0 = wave_row0(a.R);
+  const TileXY tl = tile_xy(nx, ny, a.R);
+  const int i = tl.valid ? tl.i0 + (threadIdx.x & (kWave - 1)) : nx;
+  const int j0 = tl.j0;
   double sum = 0.0, bad = 0.0;
   if (i < nx) {
     const double hxi = a.c.hx64[i];
@@ -164,8 +192,9 @@ __global__ __launch_bounds__(kBlock) void k_rhs_norm(PcgArgs a) {
     st->nonfinite = bad > 0.0;
   }
   const float* f = a.call->f + (size_t)s * a.N;
-  const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-  const int j0 = wave_row0(a.R);
+  const TileXY tl = tile_xy(nx, ny, a.R);
+  const int i = tl.valid ? tl.i0 + (threadIdx.x & (kWave - 1)) : nx;
+  const int j0 = tl.j0;
   double bb = 0.0;
   if (i < nx && bad == 0.0) {
     const double hxi = a.c.hx64[i];
@@ -202,33 +231,51 @@ struct ColIdx {
   bool ok, hok;
 };
 
-__device__ __forceinline__ ColIdx col_idx(int nx) {
+__device__ __forceinline__ ColIdx col_idx(int nx, const TileXY& tl) {
   ColIdx c;
   const int lane = threadIdx.x & (kWave - 1);
-  c.i = blockIdx.x * kWave + lane;
-  c.ok = c.i < nx;
+  c.i = tl.i0 + lane;
+  c.ok = tl.valid && c.i < nx;
   c.ih = (lane == 0) ? c.i - 1 : c.i + 1;
-  c.hok = (lane == 0 || lane == kWave - 1) && c.ih >= 0 && c.ih < nx;
+  c.hok = tl.valid && (lane == 0 || lane == kWave - 1) && c.ih >= 0 && c.ih < nx;
   return c;
 }
 
-template <typename T, int R>
-__device__ __forceinline__ void load_tile(const T* __restrict__ v, int nx, int ny, int j0, const ColIdx& c,
-                                          Tile<T, R>& t) {
+// Tile loads are raw buffer loads: an offset at or beyond the buffer's size
+// returns 0 in hardware, so rows and columns off the grid need no branches
+// and every load of a tile issues back to back.
+constexpr uint32_t kOOB = 0x80000000u;  // offset that is out of range for any buffer < 2 GiB
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
+__device__ __forceinline__ uint32_t cell_off(bool ok, int j, int ny, int nx, int i) {
+  return (ok && j >= 0 && j < ny) ? (uint32_t)(j * nx + i) * 4u : kOOB;
+}
+
+template <int R>
+__device__ __forceinline__ void load_tile(__amdgpu_buffer_rsrc_t v, int nx, int ny, int j0, const ColIdx& c,
+                                          Tile<float, R>& t) {
 #pragma unroll
-  for (int q = 0; q < R + 2; ++q) {
-    const int j = j0 - 1 + q;
-    t.own[q] = (c.ok && j >= 0 && j < ny) ? v[(size_t)j * nx + c.i] : T(0);
-  }
+  for (int q = 0; q < R + 2; ++q) t.own[q] = bload(v, cell_off(c.ok, j0 - 1 + q, ny, nx, c.i));
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int j = j0 + q;
-    t.halo[q] = (c.hok && j < ny) ? v[(size_t)j * nx + c.ih] : T(0);
-  }
+  for (int q = 0; q < R; ++q) t.halo[q] = bload(v, cell_off(c.hok, j0 + q, ny, nx, c.ih));
+}
+
+template <int R>
+__device__ __forceinline__ void load_rows_own(__amdgpu_buffer_rsrc_t v, int nx, int ny, int j0, const ColIdx& c,
+                                              float (&out)[R]) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) out[q] = bload(v, cell_off(c.ok, j0 + q, ny, nx, c.i));
 }
 
 // Wave-uniform row coefficients for rows j0-1 .. j0+R: hy (R+2 values) and the
-// south faces gy[j0-1 .. j0+R+1] (R+3 values); 0 outside the grid.
+// faces gy[j0-1 .. j0+R+1] (R+3 values); the padded arrays read 0 off the grid.
 template <typename T, int R>
 struct RowCoef {
   T hy[R + 2];
@@ -236,21 +283,16 @@ struct RowCoef {
 };
 
 template <typename T, int R>
-__device__ __forceinline__ void load_rows(const T* __restrict__ hy, const T* __restrict__ gy, int ny, int j0,
+__device__ __forceinline__ void load_rows(const T* __restrict__ hy, const T* __restrict__ gy, int j0,
                                           RowCoef<T, R>& rc) {
 #pragma unroll
-  for (int q = 0; q < R + 2; ++q) {
-    const int j = j0 - 1 + q;
-    rc.hy[q] = (j >= 0 && j < ny) ? hy[j] : T(0);
-  }
+  for (int q = 0; q < R + 2; ++q) rc.hy[q] = hy[j0 - 1 + q];
 #pragma unroll
-  for (int q = 0; q < R + 3; ++q) {
-    const int k = j0 - 1 + q;
-    rc.gy[q] = (k >= 0 && k <= ny) ? gy[k] : T(0);
-  }
+  for (int q = 0; q < R + 3; ++q) rc.gy[q] = gy[j0 - 1 + q];
 }
 
-// Column coefficients of the own column and the halo column.
+// Column coefficients of the own column and the halo column (padded arrays:
+// columns -1 .. nx + 63 are readable and 0 off the grid).
 template <typename T>
 struct ColCoef {
   T hx, gw, ge, hxh, gwh, geh;
@@ -260,12 +302,12 @@ template <typename T>
 __device__ __forceinline__ ColCoef<T> load_cols(const T* __restrict__ hx, const T* __restrict__ gx,
                                                 const ColIdx& c) {
   ColCoef<T> k;
-  k.hx = c.ok ? hx[c.i] : T(0);
-  k.gw = c.ok ? gx[c.i] : T(0);
-  k.ge = c.ok ? gx[c.i + 1] : T(0);
-  k.hxh = c.hok ? hx[c.ih] : T(0);
-  k.gwh = c.hok ? gx[c.ih] : T(0);
-  k.geh = c.hok ? gx[c.ih + 1] : T(0);
+  k.hx = hx[c.i];
+  k.gw = gx[c.i];
+  k.ge = gx[c.i + 1];
+  k.hxh = hx[c.ih];
+  k.gwh = gx[c.ih];
+  k.geh = gx[c.ih + 1];
   return k;
 }
 
@@ -294,8 +336,9 @@ __device__ __forceinline__ void true_residual_rows(const PcgArgs& a, int s, doub
   const double* __restrict__ x = a.call->x + off;
   const float* __restrict__ f = a.call->f + off;
   float* __restrict__ r = a.r + off;
-  const ColIdx ci = col_idx(nx);
-  const int j0 = wave_row0(R);
+  const TileXY tl = tile_xy(nx, ny, R);
+  const ColIdx ci = col_idx(nx, tl);
+  const int j0 = tl.j0;
   if (j0 >= ny) return;
   const ColCoef<double> k = load_cols<double>(a.c.hx64, a.c.gx64, ci);
   const ColCoef<float> kf = load_cols<float>(a.c.hx, a.c.gx, ci);
@@ -350,6 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs a) {
     st->n_dlsm = 0;
     st->n_rej = 0;
     st->done = bad ? DONE_NONFINITE : DONE_NO;
+    st->dflag[0] = st->dflag[1] = bad ? DONE_NONFINITE : DONE_NO;
     st->it_final = 0;
     st->nru_final = 0;
     st->itcg_final = 0;
@@ -359,8 +403,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs a) {
   double rr = 0.0, rz = 0.0;
   if (!bad) {
     const size_t off = (size_t)s * a.N;
-    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-    const int j0 = wave_row0(R);
+    const TileXY tl = tile_xy(nx, ny, R);
+    const int i = tl.valid ? tl.i0 + (threadIdx.x & (kWave - 1)) : nx;
+    const int j0 = tl.j0;
     if (i < nx) {
       for (int q = 0; q < R; ++q) {
         const int j = j0 + q;
@@ -391,47 +436,56 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
   __shared__ double lds[kWaves];
   const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
   SolveState* st = a.st + s;
-  if (block_done(st)) return;
   const int P = a.P, pm = par ^ 1;
   const size_t off = (size_t)s * a.N;
   const float* __restrict__ r = a.r + off;
   float* __restrict__ xc = a.xc + off;
   const float* __restrict__ pold = (par ? a.p0 : a.p1) + off;
   float* __restrict__ pnew = (par ? a.p1 : a.p0) + off;
-  const ColIdx ci = col_idx(nx);
-  const int j0 = wave_row0(R);
+  const TileXY tl = tile_xy(nx, ny, R);
+  const ColIdx ci = col_idx(nx, tl);
+  const int j0 = tl.j0;
 
   // Tile loads first: they do not depend on the scalars reduced below.
+  const uint64_t vbytes = (uint64_t)a.N * 4;
   Tile<float, R> tr, tp;
   float xcv[R];
-  load_tile<float, R>(r, nx, ny, j0, ci, tr);
-  load_tile<float, R>(pold, nx, ny, j0, ci, tp);
-#pragma unroll
-  for (int q = 0; q < R; ++q) xcv[q] = (ci.ok && j0 + q < ny) ? xc[(size_t)(j0 + q) * nx + ci.i] : 0.f;
+  load_tile<R>(make_rsrc(r, vbytes), nx, ny, j0, ci, tr);
+  load_tile<R>(make_rsrc(pold, vbytes), nx, ny, j0, ci, tp);
+  load_rows_own<R>(make_rsrc(xc, vbytes), nx, ny, j0, ci, xcv);
   RowCoef<float, R> rc;
-  load_rows<float, R>(a.c.hy, a.c.gy, ny, j0, rc);
+  load_rows<float, R>(a.c.hy, a.c.gy, j0, rc);
   const ColCoef<float> k = load_cols<float>(a.c.hx, a.c.gx, ci);
 
-  const double* pb = a.partB + (size_t)s * 2 * P;
-  const double rr = reduce_partials(pb, P, lds);
-  const double rz = reduce_partials(pb + P, P, lds);
+  // State of the previous launches (never written by this launch).
+  const int dprev = st->dflag[pm];
   const int max_iter = a.call->max_iter;
+  const double delta2 = a.call->delta2;
   const int prev_mode = st->mode[pm];
   const int it = st->it[pm], nru = st->n_ru[pm], itcg = st->it_cg[pm];
   const int restart = st->restart[pm], brk = st->brk[pm];
+  const double rho_prev = st->rho[pm], alpha_pm = st->alpha[pm], thr2 = st->thr2;
   double rr_ru = st->rr_ru[pm];
+  const bool leader = is_first_block();
+  // The partial sums are reduced before the done test so that the tile loads
+  // above are already in flight whichever way the test goes.
+  const double* pb = a.partB + (size_t)s * 2 * P;
+  const double rr = reduce_partials(pb, P, lds);
+  const double rz = reduce_partials(pb + P, P, lds);
+  if (dprev) {
+    if (leader) st->dflag[par] = dprev;
+    return;
+  }
   int done = DONE_NO;
   bool flush = false;
   if (prev_mode == MODE_TRUE) {
     rr_ru = rr;
     if (!isfinite(rr)) done = DONE_NONFINITE;
-    else if (rr <= st->thr2) done = DONE_CONV;
+    else if (rr <= thr2) done = DONE_CONV;
     else if (it >= max_iter) done = DONE_MAXIT;
   } else {
-    flush = force || brk || !isfinite(rr) || rr <= st->thr2 || rr <= a.call->delta2 * rr_ru ||
-            it >= max_iter;
+    flush = force || brk || !isfinite(rr) || rr <= thr2 || rr <= delta2 * rr_ru || it >= max_iter;
   }
-  const bool leader = is_first_block();
   if (done) {
     if (leader) {
       st->rr_final = rr;
@@ -439,6 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
       st->nru_final = nru;
       st->itcg_final = itcg;
       st->done = done;
+      st->dflag[par] = done;
       a.flags[s] = done;
     }
     return;
@@ -447,7 +502,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
   if (flush) {
     // Reliable update, part 1: x += x_c + alpha p_old in FP64; x_c = 0; p carried over.
     double* __restrict__ x = a.call->x + off;
-    const double al = st->alpha[pm];
+    const double al = alpha_pm;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int j = j0 + q;
@@ -460,11 +515,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
       }
     }
     if (leader) {
+      st->dflag[par] = DONE_NO;
       st->mode[par] = MODE_TRUE;
       st->it[par] = it;
       st->it_cg[par] = itcg;
       st->n_ru[par] = nru + 1;
-      st->rho[par] = st->rho[pm];
+      st->rho[par] = rho_prev;
       st->rr_ru[par] = rr_ru;
       st->rr_last[par] = rr;
       st->restart[par] = (force && force_restart) || brk;
@@ -473,27 +529,24 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
     return;
   }
 
-  double beta_d = (prev_mode == MODE_TRUE && restart) ? 0.0 : rz / st->rho[pm];
+  double beta_d = (prev_mode == MODE_TRUE && restart) ? 0.0 : rz / rho_prev;
   if (!isfinite(beta_d)) beta_d = 0.0;
   const float beta = (float)beta_d;
-  const float alpha_prev = (float)st->alpha[pm];
+  const float alpha_prev = (float)alpha_pm;
   // p = D^-1 r + beta p_old on the own rows (j0-1 .. j0+R) and the halo rows.
+  // Off the grid r = p_old = 0 and the diagonal is 0; the fmax keeps 0/0 out.
   Tile<float, R> pn;
 #pragma unroll
   for (int q = 0; q < R + 2; ++q) {
-    const int j = j0 - 1 + q;
-    const bool ok = ci.ok && j >= 0 && j < ny;
     float z = tr.own[q];
-    if (JAC && ok) z = z / (rc.hy[q] * (k.gw + k.ge) + k.hx * (rc.gy[q] + rc.gy[q + 1]));
-    pn.own[q] = ok ? z + beta * tp.own[q] : 0.f;
+    if (JAC) z = z / fmaxf(rc.hy[q] * (k.gw + k.ge) + k.hx * (rc.gy[q] + rc.gy[q + 1]), 1e-30f);
+    pn.own[q] = z + beta * tp.own[q];
   }
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int j = j0 + q;
-    const bool ok = ci.hok && j < ny;
     float z = tr.halo[q];
-    if (JAC && ok) z = z / (rc.hy[q + 1] * (k.gwh + k.geh) + k.hxh * (rc.gy[q + 1] + rc.gy[q + 2]));
-    pn.halo[q] = ok ? z + beta * tp.halo[q] : 0.f;
+    if (JAC) z = z / fmaxf(rc.hy[q + 1] * (k.gwh + k.geh) + k.hxh * (rc.gy[q + 1] + rc.gy[q + 2]), 1e-30f);
+    pn.halo[q] = z + beta * tp.halo[q];
   }
   float Ap[R];
   stencil_rows<float, R>(pn, rc, k, Ap);
@@ -512,6 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
   acc = block_sum(acc, lds);
   if (threadIdx.x == 0) a.partA[(size_t)s * P + block_linear()] = acc;
   if (leader) {
+    st->dflag[par] = DONE_NO;
     st->mode[par] = MODE_CG;
     st->it[par] = it + 1;
     st->it_cg[par] = itcg + 1;
@@ -530,11 +584,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int par) {
   __shared__ double lds[kWaves];
   const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
   SolveState* st = a.st + s;
-  if (block_done(st)) return;
+  const int dprev = st->dflag[par];  // written by the phase A before this launch
+  const int mode = st->mode[par];
   const int P = a.P;
   const bool leader = is_first_block();
   double acc_rr = 0.0, acc_rz = 0.0;
-  if (st->mode[par] == MODE_TRUE) {
+  if (mode == MODE_TRUE) {
+    if (dprev) return;
     true_residual_rows<R, JAC>(a, s, acc_rr, acc_rz);
     if (leader) {
       st->alpha[par] = 0.0;
@@ -544,18 +600,21 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int par) {
     const size_t off = (size_t)s * a.N;
     float* __restrict__ r = a.r + off;
     const float* __restrict__ p = (par ? a.p1 : a.p0) + off;
-    const ColIdx ci = col_idx(nx);
-    const int j0 = wave_row0(R);
+    const TileXY tl = tile_xy(nx, ny, R);
+    const ColIdx ci = col_idx(nx, tl);
+    const int j0 = tl.j0;
+    const uint64_t vbytes = (uint64_t)a.N * 4;
     Tile<float, R> tp;
     float rv[R];
-    load_tile<float, R>(p, nx, ny, j0, ci, tp);
-#pragma unroll
-    for (int q = 0; q < R; ++q) rv[q] = (ci.ok && j0 + q < ny) ? r[(size_t)(j0 + q) * nx + ci.i] : 0.f;
+    load_tile<R>(make_rsrc(p, vbytes), nx, ny, j0, ci, tp);
+    load_rows_own<R>(make_rsrc(r, vbytes), nx, ny, j0, ci, rv);
     RowCoef<float, R> rc;
-    load_rows<float, R>(a.c.hy, a.c.gy, ny, j0, rc);
+    load_rows<float, R>(a.c.hy, a.c.gy, j0, rc);
     const ColCoef<float> k = load_cols<float>(a.c.hx, a.c.gx, ci);
+    const double rho = st->rho[par];
     const double pq = reduce_partials(a.partA + (size_t)s * P, P, lds);
-    double al = st->rho[par] / pq;
+    if (dprev) return;
+    double al = rho / pq;
     const bool brk = !(pq > 0.0) || !isfinite(al);
     if (brk) al = 0.0;
     const float alf = (float)al;
@@ -592,8 +651,9 @@ __global__ __launch_bounds__(kBlock) void k_x_sum(PcgArgs a) {
   __shared__ double lds[kWaves];
   const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
   const double* x = a.call->x + (size_t)s * a.N;
-  const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-  const int j0 = wave_row0(a.R);
+  const TileXY tl = tile_xy(nx, ny, a.R);
+  const int i = tl.valid ? tl.i0 + (threadIdx.x & (kWave - 1)) : nx;
+  const int j0 = tl.j0;
   double sum = 0.0;
   if (i < nx)
     for (int q = 0; q < a.R; ++q) {
@@ -611,8 +671,9 @@ __global__ __launch_bounds__(kBlock) void k_x_shift(PcgArgs a) {
   const double mean = reduce_partials(a.partA + (size_t)s * a.P, a.P, lds) / (double)a.N;
   if (is_first_block()) a.st[s].xmean = mean;
   double* x = a.call->x + (size_t)s * a.N;
-  const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-  const int j0 = wave_row0(a.R);
+  const TileXY tl = tile_xy(nx, ny, a.R);
+  const int i = tl.valid ? tl.i0 + (threadIdx.x & (kWave - 1)) : nx;
+  const int j0 = tl.j0;
   if (i < nx)
     for (int q = 0; q < a.R; ++q) {
       const int j = j0 + q;
@@ -643,13 +704,14 @@ __global__ void k_set_call(CallArgs* c, const float* f, double* x, int max_iter,
 
 // ---------------------------------------------------------------------------
 // Host-side launchers (template dispatch on the rows-per-wave tile height).
-template <int R>
-static dim3 grid_of(const Coef& c, int nb) {
-  return dim3((c.nx + kWave - 1) / kWave, (c.ny + kWaves * R - 1) / (kWaves * R), nb);
+dim3 stencil_grid(const Coef& c, int R, int nb) {
+  const int T = ((c.nx + kWave - 1) / kWave) * ((c.ny + kWaves * R - 1) / (kWaves * R));
+  return dim3(8 * ((T + 7) / 8), 1, nb);
 }
 
-dim3 stencil_grid(const Coef& c, int R, int nb) {
-  return dim3((c.nx + kWave - 1) / kWave, (c.ny + kWaves * R - 1) / (kWaves * R), nb);
+template <int R>
+static dim3 grid_of(const Coef& c, int nb) {
+  return stencil_grid(c, R, nb);
 }
 
 #define PPE_DISPATCH_R(R, ...)                     \
@@ -709,6 +771,26 @@ void launch_pcg_phase_b(const PcgArgs& a, int nb, int par, hipStream_t s) {
     PPE_DISPATCH_R(a.R, k_pcg_b<RR, true><<<g, kBlock, 0, s>>>(a, par));
   } else {
     PPE_DISPATCH_R(a.R, k_pcg_b<RR, false><<<g, kBlock, 0, s>>>(a, par));
+  }
+}
+
+// One phase launch whose own dispatch carries the start/stop events, so the
+// elapsed time between them is the kernel's execution only.
+void launch_pcg_phase_timed(const PcgArgs& a, int nb, int par, int phase, hipStream_t s, hipEvent_t e0,
+                            hipEvent_t e1) {
+  const dim3 g = stencil_grid(a.c, a.R, nb);
+  if (a.jacobi) {
+    if (phase == 0) {
+      PPE_DISPATCH_R(a.R, hipExtLaunchKernelGGL(k_pcg_a<RR, true>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par, 0, 0));
+    } else {
+      PPE_DISPATCH_R(a.R, hipExtLaunchKernelGGL(k_pcg_b<RR, true>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par));
+    }
+  } else {
+    if (phase == 0) {
+      PPE_DISPATCH_R(a.R, hipExtLaunchKernelGGL(k_pcg_a<RR, false>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par, 0, 0));
+    } else {
+      PPE_DISPATCH_R(a.R, hipExtLaunchKernelGGL(k_pcg_b<RR, false>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par));
+    }
   }
 }
 

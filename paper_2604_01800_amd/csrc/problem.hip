@@ -16,13 +16,21 @@ ppe_status problem_upload(ppe_problem* p) {
   std::vector<double> gx(nx + 1, 0.0), gy(ny + 1, 0.0);
   for (int k = 1; k < nx; ++k) gx[k] = 1.0 / (p->xc[k] - p->xc[k - 1]);
   for (int k = 1; k < ny; ++k) gy[k] = 1.0 / (p->yc[k] - p->yc[k - 1]);
-  const size_t n64 = (size_t)nx + ny + (nx + 1) + (ny + 1);
-  std::vector<double> h64;
-  h64.reserve(n64);
-  h64.insert(h64.end(), p->hx.begin(), p->hx.end());
-  h64.insert(h64.end(), p->hy.begin(), p->hy.end());
-  h64.insert(h64.end(), gx.begin(), gx.end());
-  h64.insert(h64.end(), gy.begin(), gy.end());
+  // Each array is stored with zero padding (kPadX columns on both sides,
+  // kPadY0 rows before and kPadY1 after), so kernels may read indices just
+  // outside the grid without bounds tests: hx[-1], gx[nx + 1], hy[ny + 80] ...
+  const size_t lx = nx + 2 * kPadX, lgx = nx + 1 + 2 * kPadX;
+  const size_t ly = ny + kPadY0 + kPadY1, lgy = ny + 1 + kPadY0 + kPadY1;
+  const size_t n64 = lx + ly + lgx + lgy;
+  std::vector<double> h64(n64, 0.0);
+  double* hxp = h64.data();
+  double* hyp = hxp + lx;
+  double* gxp = hyp + ly;
+  double* gyp = gxp + lgx;
+  for (int i = 0; i < nx; ++i) hxp[kPadX + i] = p->hx[i];
+  for (int j = 0; j < ny; ++j) hyp[kPadY0 + j] = p->hy[j];
+  for (int k = 0; k <= nx; ++k) gxp[kPadX + k] = gx[k];
+  for (int k = 0; k <= ny; ++k) gyp[kPadY0 + k] = gy[k];
   std::vector<float> h32(h64.begin(), h64.end());
   const size_t bytes = n64 * (sizeof(double) + sizeof(float));
   p->dev_coef = dev_alloc(bytes);
@@ -35,14 +43,14 @@ ppe_status problem_upload(ppe_problem* p) {
   Coef& c = p->coef;
   c.nx = nx;
   c.ny = ny;
-  c.hx64 = d64;
-  c.hy64 = d64 + nx;
-  c.gx64 = d64 + nx + ny;
-  c.gy64 = d64 + nx + ny + nx + 1;
-  c.hx = d32;
-  c.hy = d32 + nx;
-  c.gx = d32 + nx + ny;
-  c.gy = d32 + nx + ny + nx + 1;
+  c.hx64 = d64 + kPadX;
+  c.hy64 = d64 + lx + kPadY0;
+  c.gx64 = d64 + lx + ly + kPadX;
+  c.gy64 = d64 + lx + ly + lgx + kPadY0;
+  c.hx = d32 + kPadX;
+  c.hy = d32 + lx + kPadY0;
+  c.gx = d32 + lx + ly + kPadX;
+  c.gy = d32 + lx + ly + lgx + kPadY0;
   if (!p->mask.empty()) {
     p->d_mask = (uint8_t*)dev_alloc(p->mask.size());
     if (!p->d_mask) return set_error(PPE_ERR_HIP, "device allocation of the mask failed");
