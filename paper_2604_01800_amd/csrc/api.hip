@@ -55,7 +55,7 @@ static void free_ws(SolveWs& w) {
   w = SolveWs{};
 }
 
-// Workspace for nb solves: 4 FP32 vectors per solve (x_c, r, p0, p1), the
+// Workspace for nb solves: 5 FP32 vectors per solve (x_c, r, p0, p1, e), the
 // partial-sum arrays, states and polling flags.
 ppe_status ensure_ws(ppe_problem* p, int nb) {
   SolveWs& w = p->ws;
@@ -64,8 +64,8 @@ ppe_status ensure_ws(ppe_problem* p, int nb) {
   const int64_t N = (int64_t)p->nx * p->ny;
   const dim3 g = stencil_grid(p->coef, 2, 1);  // the smallest tile height has the most workgroups
   w.Pmax = (int)(g.x * g.y);
-  w.vec = (float*)dev_alloc(sizeof(float) * 4 * N * nb);
-  w.part = (double*)dev_alloc(sizeof(double) * 3 * (size_t)w.Pmax * nb);
+  w.vec = (float*)dev_alloc(sizeof(float) * 5 * N * nb);
+  w.part = (double*)dev_alloc(sizeof(double) * 6 * (size_t)w.Pmax * nb);
   w.st = (SolveState*)dev_alloc(sizeof(SolveState) * nb);
   w.flags = (int32_t*)dev_alloc(sizeof(int32_t) * nb);
   w.call = (CallArgs*)dev_alloc(sizeof(CallArgs));
@@ -103,6 +103,8 @@ PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int
   a.p1 = w.vec + 3 * N;
   a.partA = w.part;
   a.partB = w.part + (size_t)a.P * nb;
+  a.partD = w.part + (size_t)3 * a.P * nb;
+  a.e = w.vec + 4 * N;
   a.st = w.st;
   a.flags = w.flags;
   a.call = w.call;
@@ -195,8 +197,7 @@ ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_so
   return PPE_OK;
 }
 
-static ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s,
-                             bool hybrid) {
+ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s, bool hybrid) {
   SolveWs& w = p->ws;
   HIPCHK(hipMemcpyAsync(w.h_state, w.st, sizeof(SolveState) * nb, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));

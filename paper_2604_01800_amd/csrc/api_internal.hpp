@@ -14,8 +14,8 @@ namespace ppe {
 struct SolveWs {
   int nb = 0;
   int Pmax = 0;
-  float* vec = nullptr;      // x_c, r, p0, p1: [4][nb][N]
-  double* part = nullptr;    // partial sums: [3][nb][Pmax]
+  float* vec = nullptr;      // x_c, r, p0, p1, e: [5][nb][N]
+  double* part = nullptr;    // partial sums: [6][nb][Pmax]
   SolveState* st = nullptr;  // [nb]
   int32_t* flags = nullptr;  // [nb]
   CallArgs* call = nullptr;
@@ -26,7 +26,8 @@ struct SolveWs {
   int exec_key[4] = {0, 0, 0, 0};
 };
 
-struct NetCache;  // per (problem, net) constants of the network (defined with the net)
+struct NetCache;  // per (grid, net) constants of the network (net_internal.hpp)
+void net_cache_free(NetCache* c);
 
 }  // namespace ppe
 
@@ -54,6 +55,7 @@ ppe_status ensure_ws(ppe_problem* p, int nb);
 PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int tol_kind, int zero_x0);
 int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o);
 ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s);
+ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s, bool hybrid);
 ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, const void* x,
                             const ppe_solve_opts* opts);
 }  // namespace ppe

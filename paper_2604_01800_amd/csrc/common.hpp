@@ -44,10 +44,11 @@ struct SolveState {
   int32_t nonfinite;
   int32_t done;       // 0 running, 1 converged, 2 iteration limit, 3 non-finite
   int32_t it_final, nru_final, itcg_final;
-  // line-search counters (hybrid)
+  // line-search step (hybrid): counters and the hand-over between its two kernels
   int32_t n_dlsm, n_rej;
-  double dl_num, dl_den;
-  int32_t pad[4];
+  int32_t dl_active, dl_it;
+  double dl_alpha;
+  int32_t pad[2];
 };
 
 enum : int32_t { MODE_CG = 0, MODE_TRUE = 1 };

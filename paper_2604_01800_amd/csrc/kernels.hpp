@@ -12,6 +12,8 @@ struct PcgArgs {
   int64_t N;         // cells per solve
   float *xc, *r, *p0, *p1;  // [nb][N] each
   double *partA, *partB;    // [nb][P], [nb][2][P]
+  double* partD;            // [nb][3][P] line-search partial sums
+  const float* e;           // [nb][N] line-search direction
   SolveState* st;           // [nb]
   int32_t* flags;           // [nb] done codes
   const CallArgs* call;
@@ -32,6 +34,8 @@ void launch_pcg_phase_b(const PcgArgs& a, int nb, int par, hipStream_t s);
 void launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
 void launch_pcg_phase_timed(const PcgArgs& a, int nb, int par, int phase, hipStream_t s, hipEvent_t e0,
                             hipEvent_t e1);
+void launch_direction(const PcgArgs& a, int nb, int mode, float* e, hipStream_t s);
+void launch_dlsm_step(const PcgArgs& a, int nb, int par, hipStream_t s);
 void launch_pcg_finish(const PcgArgs& a, int nb, hipStream_t s);
 
 }  // namespace ppe

@@ -1,0 +1,581 @@
+// DeepONet host runtime: parameter layout, initialisation, persistence, the
+// per-grid network constants and the forward pass (Sec. 2.4).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "api_internal.hpp"
+#include "net_internal.hpp"
+#include "net_kernels.hpp"
+
+namespace ppe {
+
+static int pad8(int c) { return (c + 7) / 8 * 8; }
+
+#define HIPCHK(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return set_error(PPE_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// Flat parameter layout, in the order: encoder levels (layers a, b), decoder
+// levels L-2..0 (1x1 up-conv, layers c, d), head, trunk layers, gamma.
+static void build_layout(ppe_net* n) {
+  const ppe_net_config& c = n->cfg;
+  const int L = c.levels, H = c.phi_hidden, sp = 2 * c.use_spacing;
+  auto ch = [&](int l) { return c.base_channels << l; };
+  int64_t o = 0, op = 0;
+  auto mconv = [&](int level, int cin, int cout) {
+    MConvL m;
+    m.level = level;
+    m.cin = cin;
+    m.cout = cout;
+    m.cin8 = pad8(cin);
+    m.oW = o;
+    o += (int64_t)cout * cin * 9;
+    m.ob = o;
+    o += cout;
+    m.oW1 = o;
+    o += (int64_t)H * 4;
+    m.ob1 = o;
+    o += H;
+    m.oW2 = o;
+    o += (int64_t)cin * H;
+    m.ob2 = o;
+    o += cin;
+    m.kp = conv_packed_k(9, m.cin8);
+    m.opack = op;
+    op += (int64_t)cout * m.kp;
+    return m;
+  };
+  n->enc_a.clear();
+  n->enc_b.clear();
+  n->dec_c.assign(L, MConvL{});
+  n->dec_d.assign(L, MConvL{});
+  n->up.assign(L, UpL{});
+  for (int l = 0; l < L; ++l) {
+    n->enc_a.push_back(mconv(l, (l == 0 ? 2 : ch(l - 1)) + sp, ch(l)));
+    n->enc_b.push_back(mconv(l, ch(l), ch(l)));
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    UpL u;
+    u.level = l;
+    u.cin = ch(l + 1);
+    u.cout = ch(l);
+    u.oW = o;
+    o += (int64_t)u.cout * u.cin;
+    u.ob = o;
+    o += u.cout;
+    u.kp = conv_packed_k(1, u.cin);
+    u.opack = op;
+    op += (int64_t)u.cout * u.kp;
+    n->up[l] = u;
+    n->dec_c[l] = mconv(l, 2 * ch(l) + sp, ch(l));
+    n->dec_d[l] = mconv(l, ch(l), ch(l));
+  }
+  n->o_headW = o;
+  o += (int64_t)c.basis * ch(0);
+  n->o_headb = o;
+  o += c.basis;
+  int nin = 2;
+  n->o_tW.clear();
+  n->o_tb.clear();
+  for (int k = 0; k <= c.trunk_hidden; ++k) {
+    const int nout = k == c.trunk_hidden ? c.basis : c.trunk_width;
+    n->o_tW.push_back(o);
+    o += (int64_t)nout * nin;
+    n->o_tb.push_back(o);
+    o += nout;
+    nin = nout;
+  }
+  n->o_gamma = o;
+  o += 1;
+  n->np = o;
+  n->npack = op;
+}
+
+// splitmix64 + Box-Muller: the library's own seeded initialisation.
+static uint64_t splitmix(uint64_t& s) {
+  uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+static double unit(uint64_t& s) { return ((splitmix(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+static double gauss(uint64_t& s) {
+  const double u = unit(s), v = unit(s);
+  return std::sqrt(-2.0 * std::log(u)) * std::cos(6.283185307179586 * v);
+}
+
+static void init_params(ppe_net* n, uint64_t seed, std::vector<float>& w) {
+  w.assign(n->np, 0.f);
+  uint64_t s = seed ^ 0x5bd1e995u;
+  auto fill = [&](int64_t o, int64_t cnt, double sd) {
+    for (int64_t k = 0; k < cnt; ++k) w[o + k] = (float)(sd * gauss(s));
+  };
+  const int H = n->cfg.phi_hidden;
+  auto mconv = [&](const MConvL& m) {
+    fill(m.oW, (int64_t)m.cout * m.cin * 9, std::sqrt(2.0 / (9.0 * m.cin)));
+    fill(m.oW1, (int64_t)H * 4, 0.5);
+    fill(m.oW2, (int64_t)m.cin * H, 0.1 / std::sqrt((double)H));
+  };
+  for (auto& m : n->enc_a) mconv(m);
+  for (auto& m : n->enc_b) mconv(m);
+  for (int l = 0; l < n->cfg.levels - 1; ++l) {
+    const UpL& u = n->up[l];
+    fill(u.oW, (int64_t)u.cout * u.cin, std::sqrt(1.0 / u.cin));
+    mconv(n->dec_c[l]);
+    mconv(n->dec_d[l]);
+  }
+  const int c0 = n->cfg.base_channels;
+  fill(n->o_headW, (int64_t)n->cfg.basis * c0, std::sqrt(1.0 / c0));
+  int nin = 2;
+  for (int k = 0; k <= n->cfg.trunk_hidden; ++k) {
+    const int nout = k == n->cfg.trunk_hidden ? n->cfg.basis : n->cfg.trunk_width;
+    fill(n->o_tW[k], (int64_t)nout * nin, std::sqrt(1.0 / nin));
+    nin = nout;
+  }
+  w[n->o_gamma] = (float)(1.0 / std::sqrt((double)n->cfg.basis));
+}
+
+// Re-packs the BF16 MFMA weights from the FP32 masters and bumps the version
+// (per-grid constants depending on the weights are rebuilt lazily).
+ppe_status net_refresh(ppe_net* n, hipStream_t s) {
+  auto pack = [&](const MConvL& m) {
+    launch_pack_weights(n->d_w + m.oW, m.cout, m.cin, m.cin8, 9, m.kp, n->d_pack + m.opack, s);
+  };
+  for (auto& m : n->enc_a) pack(m);
+  for (auto& m : n->enc_b) pack(m);
+  for (int l = 0; l < n->cfg.levels - 1; ++l) {
+    const UpL& u = n->up[l];
+    launch_pack_weights(n->d_w + u.oW, u.cout, u.cin, u.cin, 1, u.kp, n->d_pack + u.opack, s);
+    pack(n->dec_c[l]);
+    pack(n->dec_d[l]);
+  }
+  HIPCHK(hipGetLastError());
+  n->version++;
+  return PPE_OK;
+}
+
+static ppe_status check_config(const ppe_net_config& c) {
+  if (c.levels < 2 || c.levels > 6) return set_error(PPE_ERR_INVALID_ARG, "levels must be in [2, 6]");
+  if (c.base_channels < 16 || c.base_channels % 16) return set_error(PPE_ERR_INVALID_ARG, "base_channels: multiple of 16");
+  if (c.basis < 1 || c.basis > 128 || c.trunk_width < 1 || c.trunk_width > 128)
+    return set_error(PPE_ERR_INVALID_ARG, "basis and trunk_width must lie in [1, 128]");
+  if (c.trunk_hidden < 1 || c.trunk_hidden > 8) return set_error(PPE_ERR_INVALID_ARG, "trunk_hidden in [1, 8]");
+  if (c.phi_hidden < 1 || c.phi_hidden > 32) return set_error(PPE_ERR_INVALID_ARG, "phi_hidden in [1, 32]");
+  return PPE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Per-grid network constants and activation buffers.
+
+void net_cache_free(NetCache* c) {
+  if (!c) return;
+  dev_free(c->d_lv);
+  dev_free(c->d_eta);
+  dev_free(c->d_fold);
+  dev_free(c->d_act);
+  dev_free(c->d_part);
+  delete c;
+}
+
+// Level coordinates: centres average-pooled pairwise per level, widths merged;
+// neighbour distances with nearest-neighbour padding; all divided by the
+// level's mean spacing (length / pixels).
+static void level_arrays(const std::vector<double>& xc, const std::vector<double>& hx, int levels,
+                         std::vector<std::vector<float>>& dl, std::vector<std::vector<float>>& dr,
+                         std::vector<std::vector<float>>& hn) {
+  double Ltot = 0;
+  for (double h : hx) Ltot += h;
+  std::vector<double> c = xc, h = hx;
+  dl.assign(levels, {});
+  dr.assign(levels, {});
+  hn.assign(levels, {});
+  for (int l = 0; l < levels; ++l) {
+    if (l > 0) {
+      std::vector<double> c2(c.size() / 2), h2(h.size() / 2);
+      for (size_t i = 0; i < c2.size(); ++i) {
+        c2[i] = 0.5 * (c[2 * i] + c[2 * i + 1]);
+        h2[i] = h[2 * i] + h[2 * i + 1];
+      }
+      c.swap(c2);
+      h.swap(h2);
+    }
+    const int n = (int)c.size();
+    const double sc = n / Ltot;
+    dl[l].resize(n);
+    dr[l].resize(n);
+    hn[l].resize(n);
+    for (int i = 0; i < n; ++i) {
+      const double left = i > 0 ? c[i] - c[i - 1] : c[1] - c[0];
+      const double right = i < n - 1 ? c[i + 1] - c[i] : c[n - 1] - c[n - 2];
+      dl[l][i] = (float)(left * sc);
+      dr[l][i] = (float)(right * sc);
+      hn[l][i] = (float)(h[i] * sc);
+    }
+  }
+}
+
+ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
+  const ppe_net_config& cfg = n->cfg;
+  const int L = cfg.levels;
+  NetCache* c = p->net_cache;
+  const bool layout_ok = c && c->net_uid == n->uid && c->L == L && c->nb >= nb && c->use_eta == cfg.use_eta &&
+                         c->use_spacing == cfg.use_spacing && c->c0 == cfg.base_channels;
+  if (layout_ok && c->version == n->version) return PPE_OK;
+  if (!layout_ok) {
+    net_cache_free(c);
+    p->net_cache = c = new NetCache();
+    c->net_uid = n->uid;
+    c->L = L;
+    c->nb = nb;
+    c->use_eta = cfg.use_eta;
+    c->use_spacing = cfg.use_spacing;
+    c->c0 = cfg.base_channels;
+    for (int l = 0; l < L; ++l) {
+      c->H[l] = p->ny >> l;
+      c->W[l] = p->nx >> l;
+    }
+    // 1D level arrays: per level [dxl W][dxr W][hxn W][dyd H][dyu H][hyn H], then trunk inputs.
+    std::vector<std::vector<float>> xl, xr, xh, yd, yu, yh;
+    level_arrays(p->xc, p->hx, L, xl, xr, xh);
+    level_arrays(p->yc, p->hy, L, yd, yu, yh);
+    std::vector<float> lv;
+    for (int l = 0; l < L; ++l) {
+      c->lv_off[l] = (int64_t)lv.size();
+      for (auto* v : {&xl[l], &xr[l], &xh[l], &yd[l], &yu[l], &yh[l]}) lv.insert(lv.end(), v->begin(), v->end());
+    }
+    double Lx = 0, Ly = 0;
+    for (double h : p->hx) Lx += h;
+    for (double h : p->hy) Ly += h;
+    const double x0 = p->xc[0] - 0.5 * p->hx[0], y0 = p->yc[0] - 0.5 * p->hy[0];
+    c->tin_off = (int64_t)lv.size();
+    for (int i = 0; i < p->nx; ++i) lv.push_back((float)(2.0 * (p->xc[i] - x0) / Lx - 1.0));
+    for (int j = 0; j < p->ny; ++j) lv.push_back((float)(2.0 * (p->yc[j] - y0) / Ly - 1.0));
+    c->d_lv = (float*)dev_alloc(lv.size() * sizeof(float));
+    if (!c->d_lv) return set_error(PPE_ERR_HIP, "allocation of level arrays failed");
+    HIPCHK(hipMemcpy(c->d_lv, lv.data(), lv.size() * sizeof(float), hipMemcpyHostToDevice));
+    // eta maps, one per Mesh-Conv layer (shared by the batch)
+    int64_t eo = 0;
+    auto eta_slot = [&](const MConvL& m) {
+      const int64_t o = eo;
+      eo += (int64_t)c->H[m.level] * c->W[m.level] * m.cin8;
+      return o;
+    };
+    for (int l = 0; l < L; ++l) {
+      c->eta_a[l] = eta_slot(n->enc_a[l]);
+      c->eta_b[l] = eta_slot(n->enc_b[l]);
+      if (l < L - 1) {
+        c->eta_c[l] = eta_slot(n->dec_c[l]);
+        c->eta_d[l] = eta_slot(n->dec_d[l]);
+      }
+    }
+    if (cfg.use_eta) {
+      c->d_eta = (bf16_t*)dev_alloc(eo * sizeof(bf16_t));
+      if (!c->d_eta) return set_error(PPE_ERR_HIP, "allocation of eta maps failed");
+    }
+    c->fold_pitch = cfg.base_channels + 1;
+    c->d_fold = (float*)dev_alloc((size_t)p->nx * p->ny * c->fold_pitch * sizeof(float));
+    if (!c->d_fold) return set_error(PPE_ERR_HIP, "allocation of the trunk basis failed");
+    // activation buffers for nb samples
+    int64_t ao = 0;
+    auto act = [&](int l, int pitch) {
+      const int64_t o = ao;
+      ao += (int64_t)c->H[l] * c->W[l] * pitch * nb;
+      ao = (ao + 127) / 128 * 128;
+      return o;
+    };
+    for (int l = 0; l < L; ++l) {
+      const int ch = cfg.base_channels << l;
+      c->p_in[l] = n->enc_a[l].cin8;
+      c->o_in[l] = act(l, c->p_in[l]);
+      c->o_a[l] = act(l, ch);
+      if (l < L - 1) {
+        c->p_cat[l] = n->dec_c[l].cin8;
+        c->o_cat[l] = act(l, c->p_cat[l]);
+        c->o_c[l] = act(l, ch);
+        c->o_d[l] = act(l, ch);
+      } else {
+        c->o_bot = act(l, ch);
+      }
+    }
+    c->act_elems = ao;
+    c->d_act = (bf16_t*)dev_alloc(ao * sizeof(bf16_t));
+    c->d_part = (double*)dev_alloc((size_t)kRedBlocks * nb * sizeof(double));
+    if (!c->d_act || !c->d_part) return set_error(PPE_ERR_HIP, "allocation of network activations failed");
+    HIPCHK(hipMemsetAsync(c->d_act, 0, ao * sizeof(bf16_t), s));
+    // static channels: widths (and the mask at level 0)
+    for (int l = 0; l < L; ++l) {
+      const int ch = cfg.base_channels << l;
+      const float* hxn = c->d_lv + c->lv_off[l] + 2 * c->W[l];
+      const float* hyn = c->d_lv + c->lv_off[l] + 3 * c->W[l] + 2 * c->H[l];
+      const int coff_in = cfg.use_spacing ? (l == 0 ? 2 : (cfg.base_channels << (l - 1))) : -1;
+      const int64_t bs_in = (int64_t)c->H[l] * c->W[l] * c->p_in[l];
+      launch_fill_static(c->H[l], c->W[l], c->p_in[l], coff_in, hxn, hyn, p->d_mask, l == 0 ? 1 : -1,
+                         c->d_act + c->o_in[l], bs_in, nb, s);
+      if (l < L - 1 && cfg.use_spacing) {
+        const int64_t bs_cat = (int64_t)c->H[l] * c->W[l] * c->p_cat[l];
+        launch_fill_static(c->H[l], c->W[l], c->p_cat[l], 2 * ch, hxn, hyn, nullptr, -1, c->d_act + c->o_cat[l],
+                           bs_cat, nb, s);
+      }
+    }
+    HIPCHK(hipGetLastError());
+  }
+  // weight-dependent constants: eta maps and the folded trunk basis
+  if (cfg.use_eta) {
+    auto eta = [&](const MConvL& m, int64_t off) {
+      const int l = m.level;
+      const float* b = c->d_lv + c->lv_off[l];
+      const int W = c->W[l], H = c->H[l];
+      launch_eta(H, W, m.cin, m.cin8, cfg.phi_hidden, b, b + W, b + 3 * W, b + 3 * W + H, n->d_w + m.oW1,
+                 n->d_w + m.ob1, n->d_w + m.oW2, n->d_w + m.ob2, c->d_eta + off, s);
+    };
+    for (int l = 0; l < L; ++l) {
+      eta(n->enc_a[l], c->eta_a[l]);
+      eta(n->enc_b[l], c->eta_b[l]);
+      if (l < L - 1) {
+        eta(n->dec_c[l], c->eta_c[l]);
+        eta(n->dec_d[l], c->eta_d[l]);
+      }
+    }
+  }
+  TrunkDesc td{};
+  td.hidden = cfg.trunk_hidden;
+  td.width = cfg.trunk_width;
+  td.basis = cfg.basis;
+  td.c0 = cfg.base_channels;
+  td.fold_pitch = c->fold_pitch;
+  for (int k = 0; k <= cfg.trunk_hidden; ++k) {
+    td.oW[k] = n->o_tW[k];
+    td.ob[k] = n->o_tb[k];
+  }
+  td.oWh = n->o_headW;
+  td.obh = n->o_headb;
+  launch_trunk_fold(p->ny, p->nx, c->d_lv + c->tin_off, c->d_lv + c->tin_off + p->nx, n->d_w, td, c->d_fold, s);
+  HIPCHK(hipGetLastError());
+  c->version = n->version;
+  return PPE_OK;
+}
+
+static ConvGeo geo(const NetCache* c, int l, int cin8, int cout, int y_pitch, int y_off, int nb_eta_shared) {
+  ConvGeo g;
+  g.H = c->H[l];
+  g.W = c->W[l];
+  g.cin8 = cin8;
+  g.cout = cout;
+  g.y_pitch = y_pitch;
+  g.y_off = y_off;
+  g.x_bstride = (int64_t)g.H * g.W * cin8;
+  g.y_bstride = (int64_t)g.H * g.W * y_pitch;
+  g.e_bstride = nb_eta_shared ? 0 : (int64_t)g.H * g.W * cin8;
+  g.relu = 1;
+  return g;
+}
+
+// y = NN(r) for nb residual fields of one grid (device FP32 in and out).
+ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float* y, hipStream_t s) {
+  ppe_status st = net_cache_ensure(p, n, nb, s);
+  if (st != PPE_OK) return st;
+  NetCache* c = p->net_cache;
+  const ppe_net_config& cfg = n->cfg;
+  const int L = cfg.levels;
+  const int64_t N = (int64_t)p->nx * p->ny;
+  bf16_t* A = c->d_act;
+  const bf16_t* E = c->d_eta;
+  auto ch = [&](int l) { return cfg.base_channels << l; };
+  auto eta = [&](int64_t off) -> const bf16_t* { return cfg.use_eta ? E + off : nullptr; };
+  launch_input_pack(r, N, nb, c->d_part, A + c->o_in[0], c->p_in[0], N * c->p_in[0], s);
+  for (int l = 0; l < L; ++l) {
+    const int64_t hw = (int64_t)c->H[l] * c->W[l];
+    if (l > 0) {
+      // E_{l-1} lives in the decoder concat buffer of level l-1 at channel C_{l-1}
+      const int pc = c->p_cat[l - 1];
+      launch_pool2(c->H[l], c->W[l], ch(l - 1), A + c->o_cat[l - 1], pc, ch(l - 1), 4 * hw * pc, A + c->o_in[l],
+                   c->p_in[l], hw * c->p_in[l], nb, s);
+    }
+    const MConvL& ma = n->enc_a[l];
+    const MConvL& mb = n->enc_b[l];
+    launch_conv(9, false, geo(c, l, ma.cin8, ma.cout, ch(l), 0, 1), nb, A + c->o_in[l], eta(c->eta_a[l]),
+                n->d_pack + ma.opack, ma.kp, n->d_w + ma.ob, A + c->o_a[l], s);
+    if (l < L - 1) {
+      launch_conv(9, false, geo(c, l, mb.cin8, mb.cout, c->p_cat[l], ch(l), 1), nb, A + c->o_a[l], eta(c->eta_b[l]),
+                  n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob, A + c->o_cat[l], s);
+    } else {
+      launch_conv(9, false, geo(c, l, mb.cin8, mb.cout, ch(l), 0, 1), nb, A + c->o_a[l], eta(c->eta_b[l]),
+                  n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob, A + c->o_bot, s);
+    }
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const UpL& u = n->up[l];
+    const bf16_t* src = (l == L - 2) ? A + c->o_bot : A + c->o_d[l + 1];
+    ConvGeo gu = geo(c, l + 1, u.cin, u.cout, c->p_cat[l], 0, 1);
+    gu.y_bstride = (int64_t)c->H[l] * c->W[l] * c->p_cat[l];
+    gu.relu = 0;
+    launch_conv(1, true, gu, nb, src, nullptr, n->d_pack + u.opack, u.kp, n->d_w + u.ob, A + c->o_cat[l], s);
+    const MConvL& mc = n->dec_c[l];
+    const MConvL& md = n->dec_d[l];
+    launch_conv(9, false, geo(c, l, mc.cin8, mc.cout, ch(l), 0, 1), nb, A + c->o_cat[l], eta(c->eta_c[l]),
+                n->d_pack + mc.opack, mc.kp, n->d_w + mc.ob, A + c->o_c[l], s);
+    launch_conv(9, false, geo(c, l, md.cin8, md.cout, ch(l), 0, 1), nb, A + c->o_c[l], eta(c->eta_d[l]),
+                n->d_pack + md.opack, md.kp, n->d_w + md.ob, A + c->o_d[l], s);
+  }
+  launch_deeponet_out(N, cfg.base_channels, A + c->o_d[0], N * cfg.base_channels, c->d_fold, c->fold_pitch,
+                      n->d_w + n->o_gamma, y, nb, s);
+  HIPCHK(hipGetLastError());
+  return PPE_OK;
+}
+
+ppe_status check_net_grid(const ppe_problem* p, const ppe_net* n) {
+  const int L = n->cfg.levels, m = 1 << (L - 1);
+  if (p->nx % m || p->ny % m || p->nx / m < 2 || p->ny / m < 2)
+    return set_error(PPE_ERR_SHAPE, "grid %d x %d: nx, ny must be divisible by %d with at least 2 cells per "
+                                    "axis at the coarsest level", p->nx, p->ny, m);
+  return PPE_OK;
+}
+
+}  // namespace ppe
+
+using namespace ppe;
+
+extern "C" {
+
+void ppe_net_config_default(ppe_net_config* c) {
+  if (!c) return;
+  c->levels = 4;
+  c->base_channels = 32;
+  c->basis = 128;
+  c->trunk_width = 128;
+  c->trunk_hidden = 4;
+  c->phi_hidden = 16;
+  c->use_eta = 1;
+  c->use_spacing = 1;
+}
+
+ppe_status ppe_net_create(const ppe_net_config* cfg, uint64_t seed, ppe_net** out) {
+  if (!out) return set_error(PPE_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ppe_net_config c;
+  ppe_net_config_default(&c);
+  if (cfg) c = *cfg;
+  ppe_status st = check_config(c);
+  if (st != PPE_OK) return st;
+  static std::atomic<uint64_t> next_uid{1};
+  ppe_net* n = new ppe_net();
+  n->uid = next_uid++;
+  n->cfg = c;
+  build_layout(n);
+  n->d_w = (float*)dev_alloc(n->np * sizeof(float));
+  n->d_g = (float*)dev_alloc(n->np * sizeof(float));
+  n->d_m = (float*)dev_alloc(n->np * sizeof(float));
+  n->d_v = (float*)dev_alloc(n->np * sizeof(float));
+  n->d_pack = (bf16_t*)dev_alloc(n->npack * sizeof(bf16_t));
+  if (!n->d_w || !n->d_g || !n->d_m || !n->d_v || !n->d_pack) {
+    ppe_net_destroy(n);
+    return set_error(PPE_ERR_HIP, "device allocation of the network failed");
+  }
+  std::vector<float> w;
+  init_params(n, seed, w);
+  st = ppe_net_set_params(n, w.data(), n->np);
+  if (st != PPE_OK) {
+    ppe_net_destroy(n);
+    return st;
+  }
+  *out = n;
+  return PPE_OK;
+}
+
+void ppe_net_destroy(ppe_net* n) {
+  if (!n) return;
+  dev_free(n->d_w);
+  dev_free(n->d_g);
+  dev_free(n->d_m);
+  dev_free(n->d_v);
+  dev_free(n->d_pack);
+  net_train_free(n);
+  delete n;
+}
+
+int64_t ppe_net_num_params(const ppe_net* n) { return n ? n->np : -1; }
+
+ppe_status ppe_net_set_params(ppe_net* n, const float* host, int64_t count) {
+  if (!n || !host) return set_error(PPE_ERR_INVALID_ARG, "net or params NULL");
+  if (count != n->np) return set_error(PPE_ERR_INVALID_ARG, "expected %lld parameters, got %lld", (long long)n->np,
+                                       (long long)count);
+  HIPCHK(hipMemcpy(n->d_w, host, n->np * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(n->d_m, 0, n->np * sizeof(float)));
+  HIPCHK(hipMemset(n->d_v, 0, n->np * sizeof(float)));
+  HIPCHK(hipMemset(n->d_g, 0, n->np * sizeof(float)));
+  n->step = 0;
+  ppe_status st = net_refresh(n, 0);
+  if (st != PPE_OK) return st;
+  HIPCHK(hipDeviceSynchronize());
+  return PPE_OK;
+}
+
+ppe_status ppe_net_get_params(const ppe_net* n, float* host, int64_t count) {
+  if (!n || !host) return set_error(PPE_ERR_INVALID_ARG, "net or params NULL");
+  if (count != n->np) return set_error(PPE_ERR_INVALID_ARG, "expected %lld parameters", (long long)n->np);
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(host, n->d_w, n->np * sizeof(float), hipMemcpyDeviceToHost));
+  return PPE_OK;
+}
+
+// File: "PPENET01", config, step, parameter count, FP32 params, Adam m, Adam v.
+ppe_status ppe_net_save(const ppe_net* n, const char* path) {
+  if (!n || !path) return set_error(PPE_ERR_INVALID_ARG, "net or path NULL");
+  std::vector<float> w(n->np), m(n->np), v(n->np);
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(w.data(), n->d_w, n->np * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(m.data(), n->d_m, n->np * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(v.data(), n->d_v, n->np * 4, hipMemcpyDeviceToHost));
+  FILE* f = fopen(path, "wb");
+  if (!f) return set_error(PPE_ERR_INVALID_ARG, "cannot open %s for writing", path);
+  bool ok = fwrite("PPENET01", 1, 8, f) == 8 && fwrite(&n->cfg, sizeof n->cfg, 1, f) == 1 &&
+            fwrite(&n->step, sizeof n->step, 1, f) == 1 && fwrite(&n->np, sizeof n->np, 1, f) == 1 &&
+            fwrite(w.data(), 4, n->np, f) == (size_t)n->np && fwrite(m.data(), 4, n->np, f) == (size_t)n->np &&
+            fwrite(v.data(), 4, n->np, f) == (size_t)n->np;
+  ok = (fclose(f) == 0) && ok;
+  return ok ? PPE_OK : set_error(PPE_ERR_INVALID_ARG, "write to %s failed", path);
+}
+
+ppe_status ppe_net_load(ppe_net* n, const char* path) {
+  if (!n || !path) return set_error(PPE_ERR_INVALID_ARG, "net or path NULL");
+  FILE* f = fopen(path, "rb");
+  if (!f) return set_error(PPE_ERR_INVALID_ARG, "cannot open %s", path);
+  char magic[8];
+  ppe_net_config c;
+  int64_t step = 0, np = 0;
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "PPENET01", 8) == 0 && fread(&c, sizeof c, 1, f) == 1 &&
+            fread(&step, sizeof step, 1, f) == 1 && fread(&np, sizeof np, 1, f) == 1;
+  if (!ok || memcmp(&c, &n->cfg, sizeof c) != 0 || np != n->np) {
+    fclose(f);
+    return set_error(PPE_ERR_INVALID_ARG, "%s does not hold a network of this configuration", path);
+  }
+  std::vector<float> w(np), m(np), v(np);
+  ok = fread(w.data(), 4, np, f) == (size_t)np && fread(m.data(), 4, np, f) == (size_t)np &&
+       fread(v.data(), 4, np, f) == (size_t)np;
+  fclose(f);
+  if (!ok) return set_error(PPE_ERR_INVALID_ARG, "%s is truncated", path);
+  ppe_status st = ppe_net_set_params(n, w.data(), np);
+  if (st != PPE_OK) return st;
+  HIPCHK(hipMemcpy(n->d_m, m.data(), np * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(n->d_v, v.data(), np * 4, hipMemcpyHostToDevice));
+  n->step = step;
+  return PPE_OK;
+}
+
+ppe_status ppe_net_forward(ppe_net* n, ppe_problem* p, int32_t nb, const float* r, float* y, hipStream_t s) {
+  if (!n || !p) return set_error(PPE_ERR_INVALID_ARG, "net or problem NULL");
+  if (nb < 0 || (nb > 0 && (!r || !y))) return set_error(PPE_ERR_INVALID_ARG, "bad batch or buffers");
+  ppe_status st = check_net_grid(p, n);
+  if (st != PPE_OK) return st;
+  if (nb == 0) return PPE_OK;
+  return net_forward(p, n, nb, r, y, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+// Device-side definitions shared by the network kernels (BF16 MFMA path).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppe {
+
+typedef uint16_t bf16_t;  // BF16 stored as raw bits
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
+__host__ __device__ __forceinline__ bf16_t f2bf(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (bf16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+
+__host__ __device__ __forceinline__ float bf2f(bf16_t h) {
+  return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+constexpr int kConvTH = 8;   // conv pixel tile: 8 rows x 16 columns
+constexpr int kConvTW = 16;
+constexpr int kConvCK = 32;  // input channels staged per LDS chunk
+
+// Geometry of one MConv / conv layer as the kernels see it.
+struct ConvGeo {
+  int H, W;          // pixels of the layer's level
+  int cin8;          // input channels read (multiple of 8) = input pitch
+  int cout;          // output channels
+  int y_pitch;       // output buffer pitch (channels per pixel)
+  int y_off;         // first output channel in that buffer
+  int64_t x_bstride; // elements between samples of the input
+  int64_t y_bstride; // elements between samples of the output
+  int64_t e_bstride; // elements between samples of eta (0 = shared by the batch)
+  int relu;
+};
+
+// Number of 32-wide MFMA K-steps of an input-channel chunk of ck channels
+// for a kernel with `taps` taps (taps x ck/8 eight-channel groups, rounded up
+// to groups of four).
+__host__ __device__ __forceinline__ int conv_chunk_steps(int taps, int ck) { return (taps * (ck / 8) + 3) / 4; }
+
+// Length of one output channel's row in the packed BF16 weight layout.
+__host__ __device__ __forceinline__ int conv_packed_k(int taps, int cin8) {
+  int k = 0;
+  for (int c0 = 0; c0 < cin8; c0 += kConvCK) {
+    const int ck = (cin8 - c0) < kConvCK ? (cin8 - c0) : kConvCK;
+    k += conv_chunk_steps(taps, ck) * 32;
+  }
+  return k;
+}
+
+}  // namespace ppe

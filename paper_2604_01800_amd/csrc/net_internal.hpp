@@ -1,0 +1,72 @@
+// Host-side internals of the DeepONet: parameter layout, handle, per-grid cache.
+#pragma once
+#include <atomic>
+#include <vector>
+
+#include "../../include/ppe.h"
+#include "net_common.hpp"
+
+namespace ppe {
+
+// One Mesh-Conv layer: offsets into the FP32 parameter vector and its packed
+// BF16 weights (kp values per output channel).
+struct MConvL {
+  int level = 0, cin = 0, cout = 0, cin8 = 0, kp = 0;
+  int64_t oW = 0, ob = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, opack = 0;
+};
+
+// 1x1 up-convolution C_{l+1} -> C_l of decoder level l.
+struct UpL {
+  int level = 0, cin = 0, cout = 0, kp = 0;
+  int64_t oW = 0, ob = 0, opack = 0;
+};
+
+struct TrainState;  // training workspaces (defined with the training kernels)
+
+}  // namespace ppe
+
+struct ppe_net {
+  ppe_net_config cfg{};
+  uint64_t uid = 0;       // unique id (per-grid caches key on it)
+  uint64_t version = 0;   // bumped whenever the weights change
+  int64_t np = 0, npack = 0, step = 0;
+  std::vector<ppe::MConvL> enc_a, enc_b, dec_c, dec_d;
+  std::vector<ppe::UpL> up;
+  int64_t o_headW = 0, o_headb = 0, o_gamma = 0;
+  std::vector<int64_t> o_tW, o_tb;
+  float *d_w = nullptr, *d_g = nullptr, *d_m = nullptr, *d_v = nullptr;  // FP32 masters, grad, Adam moments
+  ppe::bf16_t* d_pack = nullptr;                                         // packed BF16 conv weights
+  ppe::TrainState* train = nullptr;
+};
+
+namespace ppe {
+
+constexpr int kMaxLevels = 6;
+
+// Per-(grid, network, batch) constants and activation buffers of the forward.
+struct NetCache {
+  uint64_t net_uid = 0, version = 0;
+  int nb = 0, L = 0, use_eta = 0, use_spacing = 0, c0 = 0;
+  int H[kMaxLevels] = {}, W[kMaxLevels] = {};
+  float* d_lv = nullptr;  // 1D level arrays and trunk inputs
+  int64_t lv_off[kMaxLevels] = {}, tin_off = 0;
+  bf16_t* d_eta = nullptr;
+  int64_t eta_a[kMaxLevels] = {}, eta_b[kMaxLevels] = {}, eta_c[kMaxLevels] = {}, eta_d[kMaxLevels] = {};
+  float* d_fold = nullptr;  // [N][c0 + 1] trunk basis with the head folded in
+  int fold_pitch = 0;
+  bf16_t* d_act = nullptr;
+  int64_t act_elems = 0;
+  int p_in[kMaxLevels] = {}, p_cat[kMaxLevels] = {};
+  int64_t o_in[kMaxLevels] = {}, o_a[kMaxLevels] = {}, o_cat[kMaxLevels] = {}, o_c[kMaxLevels] = {},
+          o_d[kMaxLevels] = {}, o_bot = 0;
+  double* d_part = nullptr;
+};
+
+void net_cache_free(NetCache* c);
+ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s);
+ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float* y, hipStream_t s);
+ppe_status net_refresh(ppe_net* n, hipStream_t s);
+ppe_status check_net_grid(const ppe_problem* p, const ppe_net* n);
+void net_train_free(ppe_net* n);
+
+}  // namespace ppe

@@ -1,0 +1,422 @@
+// Network kernels: Mesh-Conv implicit-GEMM convolutions on BF16 MFMA, the
+// grid-derived constants of the DeepONet (local weights eta, trunk basis),
+// pooling, input scaling and the DeepONet output (Sec. 2.4, Eqs. 17-18).
+#include "common.hpp"
+#include "net_common.hpp"
+#include "net_kernels.hpp"
+
+namespace ppe {
+
+// ---------------------------------------------------------------------------
+// Convolution as an implicit GEMM: out[px][co] = sum_k Wp[co][k] * Xbar[px, k]
+// with k running over (tap, input channel). One workgroup computes an
+// 8 x 16 pixel tile for TN output channels; wave w owns tile rows 2w, 2w+1.
+// MFMA 16x16x32 BF16 with A = weights (M = output channels) and B = staged
+// inputs (N = 16 pixels of one tile row), FP32 accumulation. Input channels
+// are staged through LDS in chunks of 32 (with the halo for 3x3), multiplied
+// by the Mesh-Conv local weight eta on the way (Eq. 18). Each lane's eight
+// consecutive K values are one (tap, 8-channel group); the packed weight
+// layout enumerates the groups of a chunk in the same order, zero-filled to a
+// multiple of four groups. TAPS = 9 (3x3, zero padding) or 1 (1x1). UP = the
+// output is written to the 2x nearest-upsampled pixels of a finer level.
+
+__device__ __forceinline__ uint4 mul_bf16x8(uint4 v, uint4 e) {
+  uint32_t a[4] = {v.x, v.y, v.z, v.w}, b[4] = {e.x, e.y, e.z, e.w}, o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float lo = bf2f((bf16_t)(a[q] & 0xffff)) * bf2f((bf16_t)(b[q] & 0xffff));
+    const float hi = bf2f((bf16_t)(a[q] >> 16)) * bf2f((bf16_t)(b[q] >> 16));
+    o[q] = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+  }
+  return make_uint4(o[0], o[1], o[2], o[3]);
+}
+
+template <int TN, int TAPS, bool UP>
+__global__ __launch_bounds__(256) void k_conv(ConvGeo g, const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta,
+                                              const bf16_t* __restrict__ wp, int Kp, const float* __restrict__ bias,
+                                              bf16_t* __restrict__ y) {
+  constexpr int HALO = TAPS == 9 ? 1 : 0;
+  constexpr int LW = kConvTW + 2 * HALO, LH = kConvTH + 2 * HALO;
+  constexpr int NPIX = LW * LH;
+  constexpr int CKP = kConvCK + 8;                 // LDS pixel pitch (bank-conflict padding)
+  constexpr int KW = ((TAPS * 4 + 3) / 4) * 32;    // weight columns per chunk (32 channels)
+  constexpr int KWP = KW + 8;
+  constexpr int MT = TN / 16;
+  __shared__ __attribute__((aligned(16))) bf16_t s_x[NPIX * CKP];
+  __shared__ __attribute__((aligned(16))) bf16_t s_w[TN * KWP];
+
+  const int tiles_x = (g.W + kConvTW - 1) / kConvTW;
+  const int px0 = (blockIdx.x % tiles_x) * kConvTW;
+  const int py0 = (blockIdx.x / tiles_x) * kConvTH;
+  const int co0 = blockIdx.y * TN;
+  const int smp = blockIdx.z;
+  x += smp * g.x_bstride;
+  y += smp * g.y_bstride;
+  if (eta) eta += smp * g.e_bstride;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+  f32x4_t acc[MT][2];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  int kbase = 0;
+  for (int c0 = 0; c0 < g.cin8; c0 += kConvCK) {
+    const int ck = min(kConvCK, g.cin8 - c0);
+    const int ck8 = ck / 8;
+    const int steps = conv_chunk_steps(TAPS, ck);
+    const int kw = steps * 32;
+    __syncthreads();
+    for (int u = threadIdx.x; u < NPIX * ck8; u += 256) {
+      const int pix = u / ck8, c8 = u - pix * ck8;
+      const int ly = pix / LW, lx = pix - ly * LW;
+      const int gy = py0 + ly - HALO, gx = px0 + lx - HALO;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (gy >= 0 && gy < g.H && gx >= 0 && gx < g.W) {
+        const size_t off = ((size_t)gy * g.W + gx) * g.cin8 + c0 + c8 * 8;
+        v = *(const uint4*)(x + off);
+        if (eta) v = mul_bf16x8(v, *(const uint4*)(eta + off));
+      }
+      *(uint4*)(s_x + pix * CKP + c8 * 8) = v;
+    }
+    for (int u = threadIdx.x; u < TN * (kw / 8); u += 256) {
+      const int row = u / (kw / 8), k8 = u - row * (kw / 8);
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (co0 + row < g.cout) v = *(const uint4*)(wp + (size_t)(co0 + row) * Kp + kbase + k8 * 8);
+      *(uint4*)(s_w + row * KWP + k8 * 8) = v;
+    }
+    __syncthreads();
+    for (int st = 0; st < steps; ++st) {
+      const int G = st * 4 + (lane >> 4);
+      int tap = G / ck8;
+      const int c8 = G - tap * ck8;
+      if (tap >= TAPS) tap = TAPS - 1;  // zero-weight padding group: any in-bounds input
+      const int dy = TAPS == 9 ? tap / 3 : 0, dx = TAPS == 9 ? tap % 3 : 0;
+      bf16x8_t bfr[2];
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        const int pix = (2 * wv + nt + dy) * LW + (lane & 15) + dx;
+        bfr[nt] = *(const bf16x8_t*)(s_x + pix * CKP + c8 * 8);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const bf16x8_t afr = *(const bf16x8_t*)(s_w + (mt * 16 + (lane & 15)) * KWP + st * 32 + (lane >> 4) * 8);
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[nt], acc[mt][nt], 0, 0, 0);
+      }
+    }
+    kbase += kw;
+  }
+
+  // Epilogue: lane holds out[co0 + mt*16 + 4*(lane>>4) + j][pixel (row 2w+nt, col lane&15)].
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int co = co0 + mt * 16 + 4 * (lane >> 4);
+    if (co >= g.cout) continue;
+    const float b0 = bias[co], b1 = bias[co + 1], b2 = bias[co + 2], b3 = bias[co + 3];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int py = py0 + 2 * wv + nt, px = px0 + (lane & 15);
+      if (py >= g.H || px >= g.W) continue;
+      float v0 = acc[mt][nt][0] + b0, v1 = acc[mt][nt][1] + b1, v2 = acc[mt][nt][2] + b2, v3 = acc[mt][nt][3] + b3;
+      if (g.relu) {
+        v0 = fmaxf(v0, 0.f);
+        v1 = fmaxf(v1, 0.f);
+        v2 = fmaxf(v2, 0.f);
+        v3 = fmaxf(v3, 0.f);
+      }
+      const uint2 packed = make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
+                                      (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+      if (!UP) {
+        *(uint2*)(y + ((size_t)py * g.W + px) * g.y_pitch + g.y_off + co) = packed;
+      } else {
+        const int W2 = 2 * g.W;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            *(uint2*)(y + ((size_t)(2 * py + a) * W2 + 2 * px + b) * g.y_pitch + g.y_off + co) = packed;
+      }
+    }
+  }
+}
+
+// Packed BF16 weights from the FP32 master layout W[co][ci][taps].
+__global__ void k_pack_weights(const float* __restrict__ w, int cout, int cin, int cin8, int taps, int Kp,
+                               bf16_t* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)cout * Kp) return;
+  const int co = (int)(idx / Kp);
+  int k = (int)(idx - (int64_t)co * Kp);
+  float v = 0.f;
+  for (int c0 = 0; c0 < cin8; c0 += kConvCK) {
+    const int ck = min(kConvCK, cin8 - c0), ck8 = ck / 8;
+    const int kw = conv_chunk_steps(taps, ck) * 32;
+    if (k < kw) {
+      const int G = k / 8, e = k - G * 8;
+      if (G < taps * ck8) {
+        const int tap = G / ck8, c8 = G - tap * ck8;
+        const int ci = c0 + c8 * 8 + e;
+        if (ci < cin) v = w[((size_t)co * cin + ci) * taps + tap];
+      }
+      break;
+    }
+    k -= kw;
+  }
+  out[idx] = f2bf(v);
+}
+
+// ---------------------------------------------------------------------------
+// Mesh-Conv local weight (Eq. 17) of one layer at every pixel of its level:
+// eta[p][c] = exp(-Phi(Delta_p)_c^2), Phi = W2 tanh(W1 Delta + b1) + b2, with
+// Delta_p = (left, right, down, up) neighbour distances (1D arrays per level).
+// Channels c >= cin (padding) get 0.
+__global__ void k_eta(int H, int W, int cin, int cin8, int hid, const float* __restrict__ dxl,
+                      const float* __restrict__ dxr, const float* __restrict__ dyd, const float* __restrict__ dyu,
+                      const float* __restrict__ W1, const float* __restrict__ b1, const float* __restrict__ W2,
+                      const float* __restrict__ b2, bf16_t* __restrict__ eta) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)H * W) return;
+  const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
+  const float d[4] = {dxl[i], dxr[i], dyd[j], dyu[j]};
+  float h[32];
+  for (int a = 0; a < hid; ++a) {
+    float s = b1[a];
+    for (int q = 0; q < 4; ++q) s += W1[a * 4 + q] * d[q];
+    h[a] = tanhf(s);
+  }
+  bf16_t* out = eta + p * cin8;
+  for (int c = 0; c < cin8; ++c) {
+    float e = 0.f;
+    if (c < cin) {
+      float phi = b2[c];
+      for (int a = 0; a < hid; ++a) phi += W2[c * hid + a] * h[a];
+      e = expf(-phi * phi);
+    }
+    out[c] = f2bf(e);
+  }
+}
+
+// Trunk basis with the branch head folded in. For each pixel: T = trunk(xy)
+// (tanh hidden layers, linear output, FP32), then
+//   out[p][c] = sum_k Wh[k][c] T_k  (c < C0),   out[p][C0] = sum_k bh[k] T_k,
+// so the DeepONet output sum_k (Wh D + bh)_k T_k = D . out[p][0:C0] + out[p][C0].
+// A workgroup of 256 threads handles 32 pixels; thread t computes neuron
+// t % 128 for pixels 16 * (t / 128) ... +16.
+constexpr int kTrunkPix = 32;
+__global__ __launch_bounds__(256) void k_trunk_fold(int H, int W, const float* __restrict__ xin,
+                                                    const float* __restrict__ yin, const float* __restrict__ params,
+                                                    TrunkDesc td, float* __restrict__ out) {
+  __shared__ float act[kTrunkPix][129];
+  __shared__ float nxt[kTrunkPix][129];
+  const int64_t p0 = (int64_t)blockIdx.x * kTrunkPix;
+  const int64_t npix = (int64_t)H * W;
+  const int t = threadIdx.x, j = t & 127, pg = t >> 7;
+  if (t < kTrunkPix) {
+    const int64_t p = p0 + t;
+    const int64_t pc = p < npix ? p : npix - 1;
+    const int jj = (int)(pc / W), ii = (int)(pc - (int64_t)jj * W);
+    act[t][0] = xin[ii];
+    act[t][1] = yin[jj];
+  }
+  __syncthreads();
+  int nin = 2;
+  for (int layer = 0; layer <= td.hidden; ++layer) {
+    const bool last = layer == td.hidden;
+    const float* Wl = params + td.oW[layer];
+    const float* bl = params + td.ob[layer];
+    const int nout = last ? td.basis : td.width;
+    if (j < nout) {
+      float accv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) accv[q] = bl[j];
+      for (int k = 0; k < nin; ++k) {
+        const float w = Wl[j * nin + k];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) accv[q] += w * act[pg * 16 + q][k];
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) nxt[pg * 16 + q][j] = last ? accv[q] : tanhf(accv[q]);
+    }
+    __syncthreads();
+    for (int u = t; u < kTrunkPix * 128; u += 256) act[u >> 7][u & 127] = nxt[u >> 7][u & 127];
+    __syncthreads();
+    nin = nout;
+  }
+  // fold the head: C0 + 1 outputs per pixel
+  const float* Wh = params + td.oWh;  // [basis][C0]
+  const float* bh = params + td.obh;  // [basis]
+  const int nf = td.c0 + 1;
+  for (int u = t; u < kTrunkPix * nf; u += 256) {
+    const int q = u / nf, c = u - q * nf;
+    const int64_t p = p0 + q;
+    if (p >= npix) continue;
+    float s = 0.f;
+    for (int k = 0; k < td.basis; ++k) s += (c < td.c0 ? Wh[k * td.c0 + c] : bh[k]) * act[q][k];
+    out[p * td.fold_pitch + c] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Static channels of the activation buffers: normalised widths (hx, hy) at
+// channel `coff`, and optionally the mask at channel `moff` (level 0 input).
+__global__ void k_fill_static(int H, int W, int pitch, int coff, const float* __restrict__ hxn,
+                              const float* __restrict__ hyn, const uint8_t* __restrict__ mask, int moff,
+                              bf16_t* __restrict__ buf, int64_t bstride) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)H * W) return;
+  const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
+  bf16_t* b = buf + blockIdx.y * bstride + p * pitch;
+  if (coff >= 0) {
+    b[coff] = f2bf(hxn[i]);
+    b[coff + 1] = f2bf(hyn[j]);
+  }
+  if (moff >= 0) b[moff] = f2bf(mask ? (float)mask[p] : 0.f);
+}
+
+// Partial sums of r^2 per workgroup (fixed grid of kRedBlocks per sample).
+__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ r, int64_t n, double* __restrict__ part) {
+  __shared__ double lds[kWaves];
+  const float* rs = r + (int64_t)blockIdx.y * n;
+  double s = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+    const double v = rs[k];
+    s += v * v;
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+// Channel 0 of the level-0 input: r * sqrt(N) / ||r|| in BF16 (0 for r = 0).
+// ||r||^2 comes from the kRedBlocks partials of k_sumsq, reduced in the same
+// order by every workgroup.
+__global__ __launch_bounds__(256) void k_input_pack(const float* __restrict__ r, int64_t n, const double* __restrict__ part,
+                                                    int nparts, bf16_t* __restrict__ xin, int pitch, int64_t bstride) {
+  __shared__ double lds[kWaves];
+  const int smp = blockIdx.y;
+  const double rr = reduce_partials(part + (int64_t)smp * nparts, nparts, lds);
+  const float scale = rr > 0.0 ? (float)(sqrt((double)n) / sqrt(rr)) : 0.f;
+  const float* rs = r + (int64_t)smp * n;
+  bf16_t* xs = xin + (int64_t)smp * bstride;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
+    xs[k * pitch] = f2bf(rs[k] * scale);
+}
+
+// 2x2 average pooling of C channels (8 per thread) from a buffer of pitch
+// pin at channel offset cin_off into a buffer of pitch pout (channel 0 on).
+__global__ void k_pool2(int Ho, int Wo, int C, const bf16_t* __restrict__ in, int pin, int cin_off, int64_t in_bs,
+                        bf16_t* __restrict__ out, int pout, int64_t out_bs) {
+  const int c8n = C / 8;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)Ho * Wo * c8n) return;
+  const int c8 = (int)(idx % c8n);
+  const int64_t p = idx / c8n;
+  const int yo = (int)(p / Wo), xo = (int)(p - (int64_t)yo * Wo);
+  const int Wi = 2 * Wo;
+  const bf16_t* ib = in + blockIdx.y * in_bs + cin_off + c8 * 8;
+  float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const uint4 v = *(const uint4*)(ib + ((size_t)(2 * yo + a) * Wi + 2 * xo + b) * pin);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        s[2 * q] += bf2f((bf16_t)(w[q] & 0xffff));
+        s[2 * q + 1] += bf2f((bf16_t)(w[q] >> 16));
+      }
+    }
+  uint32_t o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[q] = (uint32_t)f2bf(0.25f * s[2 * q]) | ((uint32_t)f2bf(0.25f * s[2 * q + 1]) << 16);
+  *(uint4*)(out + blockIdx.y * out_bs + p * pout + c8 * 8) = make_uint4(o[0], o[1], o[2], o[3]);
+}
+
+// DeepONet output y = gamma * (D0 . fold[p][0:C0] + fold[p][C0]) in FP32.
+__global__ void k_deeponet_out(int64_t npix, int c0, const bf16_t* __restrict__ d0, int64_t d_bs,
+                               const float* __restrict__ fold, int fold_pitch, const float* __restrict__ gamma,
+                               float* __restrict__ y) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  const int smp = blockIdx.y;
+  const bf16_t* d = d0 + smp * d_bs + p * c0;
+  const float* f = fold + p * fold_pitch;
+  float s = f[c0];
+  for (int c = 0; c < c0; c += 8) {
+    const uint4 v = *(const uint4*)(d + c);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s += bf2f((bf16_t)(w[q] & 0xffff)) * f[c + 2 * q];
+      s += bf2f((bf16_t)(w[q] >> 16)) * f[c + 2 * q + 1];
+    }
+  }
+  y[smp * npix + p] = gamma[0] * s;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
+                 int Kp, const float* bias, bf16_t* y, hipStream_t s) {
+  const int tiles = ((g.W + kConvTW - 1) / kConvTW) * ((g.H + kConvTH - 1) / kConvTH);
+  const int TN = g.cout >= 64 ? 64 : 32;
+  const dim3 grid(tiles, (g.cout + TN - 1) / TN, nb);
+  if (taps == 9) {
+    if (TN == 64) k_conv<64, 9, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
+    else k_conv<32, 9, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
+  } else if (up) {
+    if (TN == 64) k_conv<64, 1, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
+    else k_conv<32, 1, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
+  } else {
+    if (TN == 64) k_conv<64, 1, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
+    else k_conv<32, 1, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
+  }
+}
+
+void launch_pack_weights(const float* w, int cout, int cin, int cin8, int taps, int Kp, bf16_t* out, hipStream_t s) {
+  const int64_t n = (int64_t)cout * Kp;
+  k_pack_weights<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w, cout, cin, cin8, taps, Kp, out);
+}
+
+void launch_eta(int H, int W, int cin, int cin8, int hid, const float* dxl, const float* dxr, const float* dyd,
+                const float* dyu, const float* W1, const float* b1, const float* W2, const float* b2, bf16_t* eta,
+                hipStream_t s) {
+  const int64_t n = (int64_t)H * W;
+  k_eta<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(H, W, cin, cin8, hid, dxl, dxr, dyd, dyu, W1, b1, W2, b2, eta);
+}
+
+void launch_trunk_fold(int H, int W, const float* xin, const float* yin, const float* params, const TrunkDesc& td,
+                       float* out, hipStream_t s) {
+  const int64_t n = (int64_t)H * W;
+  k_trunk_fold<<<(unsigned)((n + kTrunkPix - 1) / kTrunkPix), 256, 0, s>>>(H, W, xin, yin, params, td, out);
+}
+
+void launch_fill_static(int H, int W, int pitch, int coff, const float* hxn, const float* hyn, const uint8_t* mask,
+                        int moff, bf16_t* buf, int64_t bstride, int nb, hipStream_t s) {
+  const int64_t n = (int64_t)H * W;
+  k_fill_static<<<dim3((unsigned)((n + 255) / 256), nb), 256, 0, s>>>(H, W, pitch, coff, hxn, hyn, mask, moff, buf,
+                                                                       bstride);
+}
+
+void launch_input_pack(const float* r, int64_t n, int nb, double* part, bf16_t* xin, int pitch, int64_t bstride,
+                       hipStream_t s) {
+  k_sumsq<<<dim3(kRedBlocks, nb), 256, 0, s>>>(r, n, part);
+  k_input_pack<<<dim3(kRedBlocks, nb), 256, 0, s>>>(r, n, part, kRedBlocks, xin, pitch, bstride);
+}
+
+void launch_pool2(int Ho, int Wo, int C, const bf16_t* in, int pin, int cin_off, int64_t in_bs, bf16_t* out, int pout,
+                  int64_t out_bs, int nb, hipStream_t s) {
+  const int64_t n = (int64_t)Ho * Wo * (C / 8);
+  k_pool2<<<dim3((unsigned)((n + 255) / 256), nb), 256, 0, s>>>(Ho, Wo, C, in, pin, cin_off, in_bs, out, pout, out_bs);
+}
+
+void launch_deeponet_out(int64_t npix, int c0, const bf16_t* d0, int64_t d_bs, const float* fold, int fold_pitch,
+                         const float* gamma, float* y, int nb, hipStream_t s) {
+  k_deeponet_out<<<dim3((unsigned)((npix + 255) / 256), nb), 256, 0, s>>>(npix, c0, d0, d_bs, fold, fold_pitch, gamma,
+                                                                           y);
+}
+
+}  // namespace ppe

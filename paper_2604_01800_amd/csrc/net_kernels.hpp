@@ -1,0 +1,33 @@
+// Host-side declarations of the network kernel launchers.
+#pragma once
+#include "net_common.hpp"
+
+namespace ppe {
+
+constexpr int kRedBlocks = 256;  // workgroups of the fixed-size reductions
+
+// Offsets (into the FP32 parameter vector) of the trunk layers and the head.
+struct TrunkDesc {
+  int hidden, width, basis, c0, fold_pitch;
+  int64_t oW[9], ob[9];  // hidden layers then the output layer
+  int64_t oWh, obh;      // branch head (folded into the basis)
+};
+
+void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
+                 int Kp, const float* bias, bf16_t* y, hipStream_t s);
+void launch_pack_weights(const float* w, int cout, int cin, int cin8, int taps, int Kp, bf16_t* out, hipStream_t s);
+void launch_eta(int H, int W, int cin, int cin8, int hid, const float* dxl, const float* dxr, const float* dyd,
+                const float* dyu, const float* W1, const float* b1, const float* W2, const float* b2, bf16_t* eta,
+                hipStream_t s);
+void launch_trunk_fold(int H, int W, const float* xin, const float* yin, const float* params, const TrunkDesc& td,
+                       float* out, hipStream_t s);
+void launch_fill_static(int H, int W, int pitch, int coff, const float* hxn, const float* hyn, const uint8_t* mask,
+                        int moff, bf16_t* buf, int64_t bstride, int nb, hipStream_t s);
+void launch_input_pack(const float* r, int64_t n, int nb, double* part, bf16_t* xin, int pitch, int64_t bstride,
+                       hipStream_t s);
+void launch_pool2(int Ho, int Wo, int C, const bf16_t* in, int pin, int cin_off, int64_t in_bs, bf16_t* out, int pout,
+                  int64_t out_bs, int nb, hipStream_t s);
+void launch_deeponet_out(int64_t npix, int c0, const bf16_t* d0, int64_t d_bs, const float* fold, int fold_pitch,
+                         const float* gamma, float* y, int nb, hipStream_t s);
+
+}  // namespace ppe

@@ -646,6 +646,134 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int par) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Line-search step of the hybrid solve (Eqs. 12-13) along a direction e:
+//   alpha = r.e / e.Ae,  x += alpha e,  r -= alpha A e.
+// Kernel 1 forms the partial sums r.e, e.Ae, e.e; kernel 2 reduces them,
+// applies the guard (reject when e.Ae <= 1e-30 e.e or a value is not finite:
+// the step is skipped and counted, PCG continues) and updates x_c and r,
+// recomputing A e. par is the parity of the last CG phase-A launch, whose
+// state slots hold the done flag and the iteration count.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_dlsm_a(PcgArgs a, int par) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  SolveState* st = a.st + s;
+  const int dprev = st->dflag[par];
+  const int it = st->it[par];
+  const int active = !dprev && it < a.call->max_iter;
+  if (is_first_block()) {
+    st->dl_active = active;
+    st->dl_it = it + active;
+  }
+  if (!active) return;
+  const size_t off = (size_t)s * a.N;
+  const uint64_t vbytes = (uint64_t)a.N * 4;
+  const TileXY tl = tile_xy(nx, ny, R);
+  const ColIdx ci = col_idx(nx, tl);
+  const int j0 = tl.j0;
+  Tile<float, R> te;
+  float rv[R];
+  load_tile<R>(make_rsrc(a.e + off, vbytes), nx, ny, j0, ci, te);
+  load_rows_own<R>(make_rsrc(a.r + off, vbytes), nx, ny, j0, ci, rv);
+  RowCoef<float, R> rc;
+  load_rows<float, R>(a.c.hy, a.c.gy, j0, rc);
+  const ColCoef<float> k = load_cols<float>(a.c.hx, a.c.gx, ci);
+  float Ae[R];
+  stencil_rows<float, R>(te, rc, k, Ae);
+  double num = 0.0, den = 0.0, ee = 0.0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    if (ci.ok && j0 + q < ny) {
+      const double ev = te.own[q + 1];
+      num += (double)rv[q] * ev;
+      den += ev * (double)Ae[q];
+      ee += ev * ev;
+    }
+  }
+  num = block_sum(num, lds);
+  den = block_sum(den, lds);
+  ee = block_sum(ee, lds);
+  if (threadIdx.x == 0) {
+    double* pd = a.partD + (size_t)s * 3 * a.P;
+    pd[block_linear()] = num;
+    pd[a.P + block_linear()] = den;
+    pd[2 * a.P + block_linear()] = ee;
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_dlsm_b(PcgArgs a, int par) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  SolveState* st = a.st + s;
+  const int active = st->dl_active;
+  const int itn = st->dl_it;
+  const bool leader = is_first_block();
+  if (!active) return;
+  const size_t off = (size_t)s * a.N;
+  const uint64_t vbytes = (uint64_t)a.N * 4;
+  const TileXY tl = tile_xy(nx, ny, R);
+  const ColIdx ci = col_idx(nx, tl);
+  const int j0 = tl.j0;
+  float* __restrict__ r = a.r + off;
+  float* __restrict__ xc = a.xc + off;
+  Tile<float, R> te;
+  float rv[R], xv[R];
+  load_tile<R>(make_rsrc(a.e + off, vbytes), nx, ny, j0, ci, te);
+  load_rows_own<R>(make_rsrc(r, vbytes), nx, ny, j0, ci, rv);
+  load_rows_own<R>(make_rsrc(xc, vbytes), nx, ny, j0, ci, xv);
+  RowCoef<float, R> rc;
+  load_rows<float, R>(a.c.hy, a.c.gy, j0, rc);
+  const ColCoef<float> k = load_cols<float>(a.c.hx, a.c.gx, ci);
+  const double* pd = a.partD + (size_t)s * 3 * a.P;
+  const double num = reduce_partials(pd, a.P, lds);
+  const double den = reduce_partials(pd + a.P, a.P, lds);
+  const double ee = reduce_partials(pd + 2 * a.P, a.P, lds);
+  const double alpha = num / den;
+  const bool ok = isfinite(num) && isfinite(den) && isfinite(alpha) && den > 1e-30 * ee;
+  if (leader) {
+    st->it[par] = itn;
+    st->dl_alpha = ok ? alpha : 0.0;
+    if (ok) st->n_dlsm += 1;
+    else st->n_rej += 1;
+  }
+  if (!ok) return;
+  const float af = (float)alpha;
+  float Ae[R];
+  stencil_rows<float, R>(te, rc, k, Ae);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int j = j0 + q;
+    if (ci.ok && j < ny) {
+      const size_t kk = (size_t)j * nx + ci.i;
+      xc[kk] = xv[q] + af * te.own[q + 1];
+      r[kk] = rv[q] - af * Ae[q];
+    }
+  }
+}
+
+// Test directions that replace the network: 1 zero, 2 Jacobi D^-1 r, 3 NaN, 4 ones.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_direction(PcgArgs a, int mode, float* __restrict__ e) {
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  const size_t off = (size_t)s * a.N;
+  const TileXY tl = tile_xy(nx, ny, R);
+  const ColIdx ci = col_idx(nx, tl);
+  const int j0 = tl.j0;
+  const ColCoef<float> k = load_cols<float>(a.c.hx, a.c.gx, ci);
+  for (int q = 0; q < R; ++q) {
+    const int j = j0 + q;
+    if (!ci.ok || j >= ny) continue;
+    const size_t kk = off + (size_t)j * nx + ci.i;
+    float v = 0.f;
+    if (mode == 2) v = a.r[kk] / (a.c.hy[j] * (k.gw + k.ge) + k.hx * (a.c.gy[j] + a.c.gy[j + 1]));
+    else if (mode == 3) v = __builtin_nanf("");
+    else if (mode == 4) v = 1.f;
+    e[kk] = v;
+  }
+}
+
 // Minimum-norm output: subtract the plain mean of x.
 __global__ __launch_bounds__(kBlock) void k_x_sum(PcgArgs a) {
   __shared__ double lds[kWaves];
@@ -792,6 +920,16 @@ void launch_pcg_phase_timed(const PcgArgs& a, int nb, int par, int phase, hipStr
       PPE_DISPATCH_R(a.R, hipExtLaunchKernelGGL(k_pcg_b<RR, false>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par));
     }
   }
+}
+
+void launch_direction(const PcgArgs& a, int nb, int mode, float* e, hipStream_t s) {
+  const dim3 g = stencil_grid(a.c, a.R, nb);
+  PPE_DISPATCH_R(a.R, k_direction<RR><<<g, kBlock, 0, s>>>(a, mode, e));
+}
+
+void launch_dlsm_step(const PcgArgs& a, int nb, int par, hipStream_t s) {
+  const dim3 g = stencil_grid(a.c, a.R, nb);
+  PPE_DISPATCH_R(a.R, k_dlsm_a<RR><<<g, kBlock, 0, s>>>(a, par); k_dlsm_b<RR><<<g, kBlock, 0, s>>>(a, par));
 }
 
 void launch_pcg_finish(const PcgArgs& a, int nb, hipStream_t s) {

@@ -61,6 +61,8 @@ ppe_status problem_upload(ppe_problem* p) {
 }
 
 void problem_release(ppe_problem* p) {
+  net_cache_free(p->net_cache);
+  p->net_cache = nullptr;
   dev_free(p->dev_coef);
   p->dev_coef = nullptr;
   dev_free(p->d_mask);

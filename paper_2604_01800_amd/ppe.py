@@ -233,3 +233,81 @@ def ppe_profile_copy(src, dst, reps=20, stream=None):
     _check(lib().ppe_profile_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                   src.nbytes, reps, ctypes.cast(out, ctypes.c_void_p), _stream(stream)))
     return out[0]
+
+
+def ppe_net_config_default(**kw) -> ppe_net_config:
+    c = ppe_net_config()
+    lib().ppe_net_config_default(ctypes.byref(c))
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+class Net:
+    """Owns a ppe_net handle (DeepONet weights and optimiser state)."""
+
+    def __init__(self, cfg=None, seed=0):
+        cfg = cfg or ppe_net_config_default()
+        h = ctypes.c_void_p()
+        _check(lib().ppe_net_create(ctypes.byref(cfg), seed, ctypes.byref(h)))
+        self.handle = h
+        self.cfg = cfg
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.ppe_net_destroy(h)
+            self.handle = None
+
+
+def ppe_net_create(cfg=None, seed=0) -> Net:
+    return Net(cfg, seed)
+
+
+def ppe_net_num_params(net: Net) -> int:
+    return int(lib().ppe_net_num_params(net.handle))
+
+
+def ppe_net_set_params(net: Net, flat):
+    a = np.ascontiguousarray(flat, dtype=np.float32)
+    _check(lib().ppe_net_set_params(net.handle, a.ctypes.data, a.size))
+
+
+def ppe_net_get_params(net: Net) -> np.ndarray:
+    n = ppe_net_num_params(net)
+    a = np.empty(n, dtype=np.float32)
+    _check(lib().ppe_net_get_params(net.handle, a.ctypes.data, n))
+    return a
+
+
+def ppe_net_save(net: Net, path: str):
+    _check(lib().ppe_net_save(net.handle, path.encode()))
+
+
+def ppe_net_load(net: Net, path: str):
+    _check(lib().ppe_net_load(net.handle, path.encode()))
+
+
+def ppe_net_forward(net: Net, prob: Problem, r, y, stream=None):
+    import torch
+    nb = _nb(r, prob)
+    _check(lib().ppe_net_forward(net.handle, prob.handle, nb, _dev(r, torch.float32, "r"),
+                                 _dev(y, torch.float32, "y"), _stream(stream)))
+
+
+def ppe_solve_hybrid(prob: Problem, net, f, x, opts=None, stream=None):
+    """Hybrid CG / line-search solve; net may be None for a test direction.
+    Returns (status, [stats dict per solve])."""
+    import torch
+    nb = _nb(f, prob)
+    if _nb(x, prob) != nb:
+        raise ValueError("f and x batch sizes differ")
+    opts = opts or ppe_solve_opts_default()
+    stats = (ppe_solve_stats * max(nb, 1))()
+    st = lib().ppe_solve_hybrid(prob.handle, net.handle if net is not None else None, nb,
+                                _dev(f, torch.float32, "f"), _dev(x, torch.float64, "x"), ctypes.byref(opts),
+                                ctypes.cast(stats, ctypes.c_void_p), _stream(stream))
+    _check(st, (PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))
+    return st, [stats[i].as_dict() for i in range(nb)]
