@@ -479,10 +479,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
   int done = DONE_NO;
   bool flush = false;
   if (prev_mode == MODE_TRUE) {
+    // The last phase B computed the FP64 true residual: judge convergence.
     rr_ru = rr;
     if (!isfinite(rr)) done = DONE_NONFINITE;
     else if (rr <= thr2) done = DONE_CONV;
     else if (it >= max_iter) done = DONE_MAXIT;
+    flush = force;
   } else {
     flush = force || brk || !isfinite(rr) || rr <= thr2 || rr <= delta2 * rr_ru || it >= max_iter;
   }
@@ -735,8 +737,12 @@ __global__ __launch_bounds__(kBlock) void k_dlsm_b(PcgArgs a, int par) {
   if (leader) {
     st->it[par] = itn;
     st->dl_alpha = ok ? alpha : 0.0;
-    if (ok) st->n_dlsm += 1;
-    else st->n_rej += 1;
+    if (ok) {
+      st->n_dlsm += 1;
+      st->mode[par] = MODE_CG;  // r and x_c changed: the next pass must recompute the true residual
+    } else {
+      st->n_rej += 1;
+    }
   }
   if (!ok) return;
   const float af = (float)alpha;
