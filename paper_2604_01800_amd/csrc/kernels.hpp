@@ -36,6 +36,7 @@ void launch_pcg_phase_timed(const PcgArgs& a, int nb, int par, int phase, hipStr
                             hipEvent_t e1);
 void launch_direction(const PcgArgs& a, int nb, int mode, float* e, hipStream_t s);
 void launch_dlsm_step(const PcgArgs& a, int nb, int par, hipStream_t s);
+void launch_apply_multi(const Coef* coefs, int nx, int ny, int nb, const float* x, float* y, hipStream_t s);
 void launch_pcg_finish(const PcgArgs& a, int nb, hipStream_t s);
 
 }  // namespace ppe

@@ -221,6 +221,27 @@ static void level_arrays(const std::vector<double>& xc, const std::vector<double
   }
 }
 
+// Per-grid block of 1D network inputs: for each level l the arrays
+// [dxl W_l][dxr W_l][hxn W_l][dyd H_l][dyu H_l][hyn H_l] (offsets in lv_off),
+// then the trunk inputs [x_hat nx][y_hat ny] (offset *tin_off).
+void grid_block(const ppe_problem* p, int L, std::vector<float>& lv, int64_t* lv_off, int64_t* tin_off) {
+  std::vector<std::vector<float>> xl, xr, xh, yd, yu, yh;
+  level_arrays(p->xc, p->hx, L, xl, xr, xh);
+  level_arrays(p->yc, p->hy, L, yd, yu, yh);
+  lv.clear();
+  for (int l = 0; l < L; ++l) {
+    lv_off[l] = (int64_t)lv.size();
+    for (auto* v : {&xl[l], &xr[l], &xh[l], &yd[l], &yu[l], &yh[l]}) lv.insert(lv.end(), v->begin(), v->end());
+  }
+  double Lx = 0, Ly = 0;
+  for (double h : p->hx) Lx += h;
+  for (double h : p->hy) Ly += h;
+  const double x0 = p->xc[0] - 0.5 * p->hx[0], y0 = p->yc[0] - 0.5 * p->hy[0];
+  *tin_off = (int64_t)lv.size();
+  for (int i = 0; i < p->nx; ++i) lv.push_back((float)(2.0 * (p->xc[i] - x0) / Lx - 1.0));
+  for (int j = 0; j < p->ny; ++j) lv.push_back((float)(2.0 * (p->yc[j] - y0) / Ly - 1.0));
+}
+
 ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
   const ppe_net_config& cfg = n->cfg;
   const int L = cfg.levels;
@@ -241,22 +262,8 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
       c->H[l] = p->ny >> l;
       c->W[l] = p->nx >> l;
     }
-    // 1D level arrays: per level [dxl W][dxr W][hxn W][dyd H][dyu H][hyn H], then trunk inputs.
-    std::vector<std::vector<float>> xl, xr, xh, yd, yu, yh;
-    level_arrays(p->xc, p->hx, L, xl, xr, xh);
-    level_arrays(p->yc, p->hy, L, yd, yu, yh);
     std::vector<float> lv;
-    for (int l = 0; l < L; ++l) {
-      c->lv_off[l] = (int64_t)lv.size();
-      for (auto* v : {&xl[l], &xr[l], &xh[l], &yd[l], &yu[l], &yh[l]}) lv.insert(lv.end(), v->begin(), v->end());
-    }
-    double Lx = 0, Ly = 0;
-    for (double h : p->hx) Lx += h;
-    for (double h : p->hy) Ly += h;
-    const double x0 = p->xc[0] - 0.5 * p->hx[0], y0 = p->yc[0] - 0.5 * p->hy[0];
-    c->tin_off = (int64_t)lv.size();
-    for (int i = 0; i < p->nx; ++i) lv.push_back((float)(2.0 * (p->xc[i] - x0) / Lx - 1.0));
-    for (int j = 0; j < p->ny; ++j) lv.push_back((float)(2.0 * (p->yc[j] - y0) / Ly - 1.0));
+    grid_block(p, L, lv, c->lv_off, &c->tin_off);
     c->d_lv = (float*)dev_alloc(lv.size() * sizeof(float));
     if (!c->d_lv) return set_error(PPE_ERR_HIP, "allocation of level arrays failed");
     HIPCHK(hipMemcpy(c->d_lv, lv.data(), lv.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -373,7 +380,7 @@ static ConvGeo geo(const NetCache* c, int l, int cin8, int cout, int y_pitch, in
   g.x_bstride = (int64_t)g.H * g.W * cin8;
   g.y_bstride = (int64_t)g.H * g.W * y_pitch;
   g.e_bstride = nb_eta_shared ? 0 : (int64_t)g.H * g.W * cin8;
-  g.relu = 1;
+  g.act = 1;
   return g;
 }
 
@@ -415,7 +422,7 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
     const bf16_t* src = (l == L - 2) ? A + c->o_bot : A + c->o_d[l + 1];
     ConvGeo gu = geo(c, l + 1, u.cin, u.cout, c->p_cat[l], 0, 1);
     gu.y_bstride = (int64_t)c->H[l] * c->W[l] * c->p_cat[l];
-    gu.relu = 0;
+    gu.act = 0;
     launch_conv(1, true, gu, nb, src, nullptr, n->d_pack + u.opack, u.kp, n->d_w + u.ob, A + c->o_cat[l], s);
     const MConvL& mc = n->dec_c[l];
     const MConvL& md = n->dec_d[l];

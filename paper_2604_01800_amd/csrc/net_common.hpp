@@ -35,7 +35,7 @@ struct ConvGeo {
   int64_t x_bstride; // elements between samples of the input
   int64_t y_bstride; // elements between samples of the output
   int64_t e_bstride; // elements between samples of eta (0 = shared by the batch)
-  int relu;
+  int act;          // epilogue activation: 0 none, 1 ReLU, 2 tanh
 };
 
 // Number of 32-wide MFMA K-steps of an input-channel chunk of ck channels

@@ -68,5 +68,6 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
 ppe_status net_refresh(ppe_net* n, hipStream_t s);
 ppe_status check_net_grid(const ppe_problem* p, const ppe_net* n);
 void net_train_free(ppe_net* n);
+void grid_block(const ppe_problem* p, int L, std::vector<float>& lv, int64_t* lv_off, int64_t* tin_off);
 
 }  // namespace ppe

@@ -115,17 +115,23 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const bf16_t* __restric
   for (int mt = 0; mt < MT; ++mt) {
     const int co = co0 + mt * 16 + 4 * (lane >> 4);
     if (co >= g.cout) continue;
-    const float b0 = bias[co], b1 = bias[co + 1], b2 = bias[co + 2], b3 = bias[co + 3];
+    const float b0 = bias ? bias[co] : 0.f, b1 = bias ? bias[co + 1] : 0.f;
+    const float b2 = bias ? bias[co + 2] : 0.f, b3 = bias ? bias[co + 3] : 0.f;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
       const int py = py0 + 2 * wv + nt, px = px0 + (lane & 15);
       if (py >= g.H || px >= g.W) continue;
       float v0 = acc[mt][nt][0] + b0, v1 = acc[mt][nt][1] + b1, v2 = acc[mt][nt][2] + b2, v3 = acc[mt][nt][3] + b3;
-      if (g.relu) {
+      if (g.act == 1) {
         v0 = fmaxf(v0, 0.f);
         v1 = fmaxf(v1, 0.f);
         v2 = fmaxf(v2, 0.f);
         v3 = fmaxf(v3, 0.f);
+      } else if (g.act == 2) {
+        v0 = tanhf(v0);
+        v1 = tanhf(v1);
+        v2 = tanhf(v2);
+        v3 = tanhf(v3);
       }
       const uint2 packed = make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
                                       (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
@@ -143,23 +149,32 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const bf16_t* __restric
   }
 }
 
-// Packed BF16 weights from the FP32 master layout W[co][ci][taps].
-__global__ void k_pack_weights(const float* __restrict__ w, int cout, int cin, int cin8, int taps, int Kp,
-                               bf16_t* __restrict__ out) {
+// Packed BF16 weights from the FP32 master layout W[cout_fwd][cin_fwd][taps].
+// mode 0: the forward operator (rows = output channels, K over input channels).
+// mode 1: the input-gradient operator, a 3x3 (or 1x1) convolution from the
+// output-channel space back to the input-channel space with the kernel
+// flipped: rows = input channels, K over output channels, tap -> taps-1-tap.
+// rows x Kp values; kin8 = K-side channel count padded to 8.
+__global__ void k_pack_weights(const float* __restrict__ w, int rows, int kin8, int taps, int Kp, int mode,
+                               int cout_fwd, int cin_fwd, bf16_t* __restrict__ out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)cout * Kp) return;
-  const int co = (int)(idx / Kp);
-  int k = (int)(idx - (int64_t)co * Kp);
+  if (idx >= (int64_t)rows * Kp) return;
+  const int row = (int)(idx / Kp);
+  int k = (int)(idx - (int64_t)row * Kp);
   float v = 0.f;
-  for (int c0 = 0; c0 < cin8; c0 += kConvCK) {
-    const int ck = min(kConvCK, cin8 - c0), ck8 = ck / 8;
+  for (int c0 = 0; c0 < kin8; c0 += kConvCK) {
+    const int ck = min(kConvCK, kin8 - c0), ck8 = ck / 8;
     const int kw = conv_chunk_steps(taps, ck) * 32;
     if (k < kw) {
       const int G = k / 8, e = k - G * 8;
       if (G < taps * ck8) {
         const int tap = G / ck8, c8 = G - tap * ck8;
-        const int ci = c0 + c8 * 8 + e;
-        if (ci < cin) v = w[((size_t)co * cin + ci) * taps + tap];
+        const int ch = c0 + c8 * 8 + e;
+        if (mode == 0) {
+          if (row < cout_fwd && ch < cin_fwd) v = w[((size_t)row * cin_fwd + ch) * taps + tap];
+        } else {
+          if (row < cin_fwd && ch < cout_fwd) v = w[((size_t)ch * cin_fwd + row) * taps + (taps - 1 - tap)];
+        }
       }
       break;
     }
@@ -378,7 +393,13 @@ void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, c
 
 void launch_pack_weights(const float* w, int cout, int cin, int cin8, int taps, int Kp, bf16_t* out, hipStream_t s) {
   const int64_t n = (int64_t)cout * Kp;
-  k_pack_weights<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w, cout, cin, cin8, taps, Kp, out);
+  k_pack_weights<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w, cout, cin8, taps, Kp, 0, cout, cin, out);
+}
+
+void launch_pack_weights_t(const float* w, int cout_fwd, int cin_fwd, int rows, int taps, int Kp, bf16_t* out,
+                           hipStream_t s) {
+  const int64_t n = (int64_t)rows * Kp;
+  k_pack_weights<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w, rows, cout_fwd, taps, Kp, 1, cout_fwd, cin_fwd, out);
 }
 
 void launch_eta(int H, int W, int cin, int cin8, int hid, const float* dxl, const float* dxr, const float* dyd,

@@ -16,6 +16,9 @@ struct TrunkDesc {
 void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
                  int Kp, const float* bias, bf16_t* y, hipStream_t s);
 void launch_pack_weights(const float* w, int cout, int cin, int cin8, int taps, int Kp, bf16_t* out, hipStream_t s);
+// Input-gradient operator: rows = input channels (padded), K over cout_fwd.
+void launch_pack_weights_t(const float* w, int cout_fwd, int cin_fwd, int rows, int taps, int Kp, bf16_t* out,
+                           hipStream_t s);
 void launch_eta(int H, int W, int cin, int cin8, int hid, const float* dxl, const float* dxr, const float* dyd,
                 const float* dyu, const float* W1, const float* b1, const float* W2, const float* b2, bf16_t* eta,
                 hipStream_t s);

@@ -780,6 +780,37 @@ __global__ __launch_bounds__(kBlock) void k_direction(PcgArgs a, int mode, float
   }
 }
 
+// y = A x for nb samples on their own grids of one size (coefs[s] per sample).
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_apply_multi(const Coef* __restrict__ coefs, const float* __restrict__ x,
+                                                        float* __restrict__ y) {
+  const Coef c = coefs[blockIdx.z];
+  const int nx = c.nx, ny = c.ny;
+  const size_t off = (size_t)blockIdx.z * nx * ny;
+  const uint64_t vbytes = (uint64_t)nx * ny * 4;
+  const TileXY tl = tile_xy(nx, ny, R);
+  const ColIdx ci = col_idx(nx, tl);
+  const int j0 = tl.j0;
+  Tile<float, R> tv;
+  load_tile<R>(make_rsrc(x + off, vbytes), nx, ny, j0, ci, tv);
+  RowCoef<float, R> rc;
+  load_rows<float, R>(c.hy, c.gy, j0, rc);
+  const ColCoef<float> k = load_cols<float>(c.hx, c.gx, ci);
+  float Av[R];
+  stencil_rows<float, R>(tv, rc, k, Av);
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (ci.ok && j0 + q < ny) y[off + (size_t)(j0 + q) * nx + ci.i] = Av[q];
+}
+
+void launch_apply_multi(const Coef* coefs, int nx, int ny, int nb, const float* x, float* y, hipStream_t s) {
+  Coef c{};
+  c.nx = nx;
+  c.ny = ny;
+  const dim3 g = stencil_grid(c, 4, nb);
+  k_apply_multi<4><<<g, kBlock, 0, s>>>(coefs, x, y);
+}
+
 // Minimum-norm output: subtract the plain mean of x.
 __global__ __launch_bounds__(kBlock) void k_x_sum(PcgArgs a) {
   __shared__ double lds[kWaves];

@@ -1,0 +1,514 @@
+// Training kernels of the DeepONet: weight gradients on BF16 MFMA (split-K
+// over pixels, fixed-order reduction), activation-gradient masks, the
+// Mesh-Conv local-weight backward, pooling / upsampling / concatenation
+// backward, the DeepONet contraction, the residual loss of Eq. 19, and Adam.
+#include "common.hpp"
+#include "net_common.hpp"
+#include "train_kernels.hpp"
+
+namespace ppe {
+
+// ---------------------------------------------------------------------------
+// Weight gradient of a convolution layer:
+//   dW[co][ci][tap] = sum over pixels p of dPre[p][co] * Xbar[p + off(tap)][ci]
+// with Xbar = eta * X (the layer's weighted input). MFMA 16x16x32 BF16 with
+// A = dPre^T (M = 32 output channels per workgroup, K = pixels) and
+// B = shifted Xbar (N = 32 input channels per workgroup). Wave w owns the
+// (co, ci) sub-tile (w / 2, w % 2) for all taps. Each workgroup (split z)
+// accumulates 8 x 16 pixel tiles z, z + nsplit, ... of all samples and writes
+// its partial sums in the master layout [co][ci < cin][tap]; k_reduce_rows
+// sums the splits in a fixed order.
+template <int TAPS>
+__global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restrict__ dp, const bf16_t* __restrict__ x,
+                                               const bf16_t* __restrict__ eta, float* __restrict__ part) {
+  constexpr int HALO = TAPS == 9 ? 1 : 0;
+  constexpr int TH = 8, TW = 16, NP = TH * TW;
+  constexpr int LH = TH + 2 * HALO;
+  constexpr int NDX = TAPS == 9 ? 3 : 1;
+  constexpr int DPP = NP + 8;   // LDS pitch of a transposed dPre row
+  constexpr int XPP = TW + 8;   // LDS pitch of a staged input row
+  __shared__ __attribute__((aligned(16))) bf16_t s_dp[32 * DPP];
+  __shared__ __attribute__((aligned(16))) bf16_t s_x[NDX * 32 * LH * XPP];
+  const int co0 = blockIdx.x * 32, ci0 = blockIdx.y * 32;
+  const int split = blockIdx.z, nsplit = gridDim.z;
+  const int tiles_x = (g.W + TW - 1) / TW, tiles_y = (g.H + TH - 1) / TH;
+  const int tiles = tiles_x * tiles_y * g.nb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int mt = wv >> 1, nt = wv & 1;
+  f32x4_t acc[TAPS];
+#pragma unroll
+  for (int t = 0; t < TAPS; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  for (int t = split; t < tiles; t += nsplit) {
+    const int smp = t / (tiles_x * tiles_y);
+    const int rem = t - smp * tiles_x * tiles_y;
+    const int py0 = (rem / tiles_x) * TH, px0 = (rem % tiles_x) * TW;
+    const bf16_t* dps = dp + (int64_t)smp * g.dp_bstride;
+    const bf16_t* xs = x + (int64_t)smp * g.x_bstride;
+    const bf16_t* es = eta ? eta + (int64_t)smp * g.e_bstride : nullptr;
+    __syncthreads();
+    // dPre tile, transposed to [co][pixel]
+    for (int u = threadIdx.x; u < NP * 4; u += 256) {
+      const int p = u % NP, cg = u / NP;
+      const int py = py0 + p / TW, px = px0 + p % TW;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (py < g.H && px < g.W && co0 + cg * 8 < g.cout)
+        v = *(const uint4*)(dps + ((int64_t)py * g.W + px) * g.dp_pitch + co0 + cg * 8);
+      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        s_dp[(cg * 8 + 2 * e) * DPP + p] = (bf16_t)(w4[e] & 0xffff);
+        s_dp[(cg * 8 + 2 * e + 1) * DPP + p] = (bf16_t)(w4[e] >> 16);
+      }
+    }
+    // weighted input tile, one copy per column shift dx: s_x[dx][ci][row][col] = Xbar[row - H][col + dx - H]
+    for (int u = threadIdx.x; u < NDX * 4 * LH * TW; u += 256) {
+      const int col = u % TW;
+      int r2 = u / TW;
+      const int row = r2 % LH;
+      r2 /= LH;
+      const int cg = r2 % 4, dx = r2 / 4;
+      const int gy = py0 + row - HALO, gx = px0 + col + dx - HALO;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (gy >= 0 && gy < g.H && gx >= 0 && gx < g.W && ci0 + cg * 8 < g.cin8) {
+        const int64_t off = ((int64_t)gy * g.W + gx) * g.cin8 + ci0 + cg * 8;
+        v = *(const uint4*)(xs + off);
+        if (es) {
+          const uint4 e = *(const uint4*)(es + off);
+          const uint32_t a4[4] = {v.x, v.y, v.z, v.w}, b4[4] = {e.x, e.y, e.z, e.w};
+          uint32_t o4[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float lo = bf2f((bf16_t)(a4[q] & 0xffff)) * bf2f((bf16_t)(b4[q] & 0xffff));
+            const float hi = bf2f((bf16_t)(a4[q] >> 16)) * bf2f((bf16_t)(b4[q] >> 16));
+            o4[q] = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+          }
+          v = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+        }
+      }
+      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+      bf16_t* dst = s_x + ((dx * 32 + cg * 8) * LH + row) * XPP + col;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        dst[(2 * e) * LH * XPP] = (bf16_t)(w4[e] & 0xffff);
+        dst[(2 * e + 1) * LH * XPP] = (bf16_t)(w4[e] >> 16);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < NP / 32; ++st) {
+      const int pk = st * 32 + (lane >> 4) * 8;  // first of this lane's 8 pixels (same tile row)
+      const int prow = pk / TW, pcol = pk % TW;
+      const bf16x8_t afr = *(const bf16x8_t*)(s_dp + (mt * 16 + (lane & 15)) * DPP + pk);
+#pragma unroll
+      for (int tap = 0; tap < TAPS; ++tap) {
+        const int dy = TAPS == 9 ? tap / 3 : 0, dx = TAPS == 9 ? tap % 3 : 0;
+        const bf16x8_t bfr =
+            *(const bf16x8_t*)(s_x + ((dx * 32 + nt * 16 + (lane & 15)) * LH + prow + dy) * XPP + pcol);
+        acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr, acc[tap], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds dW[co = co0 + mt*16 + 4*(lane>>4) + j][ci = ci0 + nt*16 + (lane&15)] per tap
+  const int ci = ci0 + nt * 16 + (lane & 15);
+  float* ps = part + (int64_t)split * g.cout * g.cin * TAPS;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int co = co0 + mt * 16 + 4 * (lane >> 4) + j;
+    if (co >= g.cout || ci >= g.cin) continue;
+#pragma unroll
+    for (int tap = 0; tap < TAPS; ++tap) ps[((int64_t)co * g.cin + ci) * TAPS + tap] = acc[tap][j];
+  }
+}
+
+// out[k] = scale * sum_b part[b][k] (fixed order, FP64 accumulation).
+__global__ void k_reduce_rows(const float* __restrict__ part, int nparts, int64_t len, float scale,
+                              float* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * len + k];
+  out[k] = (float)(scale * s);
+}
+
+// Bias gradient partials: part[b][c] = sum over workgroup b's pixels of d[p][c].
+__global__ __launch_bounds__(256) void k_bias_grad(const bf16_t* __restrict__ d, int64_t npix, int pitch, int off,
+                                                   int C, float* __restrict__ part) {
+  for (int c = threadIdx.x; c < C; c += 256) {
+    float s = 0.f;
+    for (int64_t p = blockIdx.x; p < npix; p += gridDim.x) s += bf2f(d[p * pitch + off + c]);
+    part[(int64_t)blockIdx.x * C + c] = s;
+  }
+}
+
+// In-place activation backward: d *= relu'(out) (mode 1) or tanh'(out) (mode 2).
+__global__ void k_act_bwd(bf16_t* __restrict__ d, int dpitch, const bf16_t* __restrict__ out, int opitch, int ooff,
+                          int C, int64_t npix, int mode) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= npix * C) return;
+  const int64_t p = idx / C;
+  const int c = (int)(idx - p * C);
+  const float o = bf2f(out[p * opitch + ooff + c]);
+  float v = bf2f(d[p * dpitch + c]);
+  v = mode == 1 ? (o > 0.f ? v : 0.f) : v * (1.f - o * o);
+  d[p * dpitch + c] = f2bf(v);
+}
+
+// dst[p][c] (+)= src[p][soff + c], c < C.
+__global__ void k_copy_ch(const bf16_t* __restrict__ src, int spitch, int soff, bf16_t* __restrict__ dst, int dpitch,
+                          int C, int64_t npix, int accumulate) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= npix * C) return;
+  const int64_t p = idx / C;
+  const int c = (int)(idx - p * C);
+  float v = bf2f(src[p * spitch + soff + c]);
+  if (accumulate) v += bf2f(dst[p * dpitch + c]);
+  dst[p * dpitch + c] = f2bf(v);
+}
+
+// Backward of nearest 2x upsampling: coarse[p][c] = sum of the 4 fine pixels.
+__global__ void k_up_bwd(int Hc, int Wc, int C, const bf16_t* __restrict__ fine, int fpitch, int64_t f_bs,
+                         bf16_t* __restrict__ coarse, int64_t c_bs) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)Hc * Wc * C) return;
+  const int c = (int)(idx % C);
+  const int64_t p = idx / C;
+  const int y = (int)(p / Wc), xx = (int)(p - (int64_t)y * Wc);
+  const bf16_t* f = fine + blockIdx.y * f_bs;
+  float s = 0.f;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) s += bf2f(f[((int64_t)(2 * y + a) * 2 * Wc + 2 * xx + b) * fpitch + c]);
+  coarse[blockIdx.y * c_bs + p * C + c] = f2bf(s);
+}
+
+// Backward of 2x2 average pooling: dE[2y+a][2x+b][c] += 0.25 * dpool[y][x][c].
+__global__ void k_pool_bwd(int Hc, int Wc, int C, const bf16_t* __restrict__ dpool, int ppitch, int64_t p_bs,
+                           bf16_t* __restrict__ dE, int64_t e_bs) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)Hc * Wc * C) return;
+  const int c = (int)(idx % C);
+  const int64_t p = idx / C;
+  const int y = (int)(p / Wc), xx = (int)(p - (int64_t)y * Wc);
+  const float g = 0.25f * bf2f(dpool[blockIdx.y * p_bs + p * ppitch + c]);
+  bf16_t* e = dE + blockIdx.y * e_bs;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      bf16_t* q = e + ((int64_t)(2 * y + a) * 2 * Wc + 2 * xx + b) * C + c;
+      *q = f2bf(bf2f(*q) + g);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-sample Mesh-Conv local weights (each sample has its own grid): the
+// level arrays of sample s start at lv + s * lv_stride.
+__global__ void k_eta_multi(int H, int W, int cin, int cin8, int hid, const float* __restrict__ lv, int64_t lv_stride,
+                            const float* __restrict__ W1, const float* __restrict__ b1, const float* __restrict__ W2,
+                            const float* __restrict__ b2, bf16_t* __restrict__ eta, int64_t e_bs) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)H * W) return;
+  const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
+  const float* a = lv + blockIdx.y * lv_stride;
+  const float d[4] = {a[i], a[W + i], a[3 * W + j], a[3 * W + H + j]};
+  float h[32];
+  for (int q = 0; q < hid; ++q) {
+    float s = b1[q];
+    for (int k = 0; k < 4; ++k) s += W1[q * 4 + k] * d[k];
+    h[q] = tanhf(s);
+  }
+  bf16_t* out = eta + blockIdx.y * e_bs + p * cin8;
+  for (int c = 0; c < cin8; ++c) {
+    float e = 0.f;
+    if (c < cin) {
+      float phi = b2[c];
+      for (int q = 0; q < hid; ++q) phi += W2[c * hid + q] * h[q];
+      e = expf(-phi * phi);
+    }
+    out[c] = f2bf(e);
+  }
+}
+
+// Mesh-Conv local-weight backward. Given dXbar (gradient of the weighted
+// input) and the layer input X: dX = eta * dXbar (written in place of dXbar)
+// and, through dEta = dXbar * X and eta = exp(-Phi^2), the gradients of Phi's
+// parameters. A workgroup handles 32-pixel batches of a contiguous pixel
+// range and writes one partial row [W1 (hid*4) | b1 (hid) | W2 (cin*hid) |
+// b2 (cin)] (the layout of these parameters in the flat vector).
+constexpr int kEtaPix = 32;
+__global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8, int hid, int nb,
+                                                 const float* __restrict__ lv, int64_t lv_stride,
+                                                 const float* __restrict__ W1, const float* __restrict__ b1,
+                                                 const float* __restrict__ W2, const float* __restrict__ b2,
+                                                 const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta,
+                                                 int64_t e_bs, bf16_t* __restrict__ dxb, float* __restrict__ part) {
+  extern __shared__ float sm[];
+  float* s_h = sm;                              // [kEtaPix][32]
+  float* s_d = s_h + kEtaPix * 32;              // [kEtaPix][4] distances
+  float* s_dphi = s_d + kEtaPix * 4;            // [kEtaPix][cin]
+  const int64_t npix = (int64_t)H * W, ntot = npix * nb;
+  const int64_t per = (ntot + gridDim.x - 1) / gridDim.x;
+  const int64_t pbeg = blockIdx.x * per, pend = min(ntot, pbeg + per);
+  const int t = threadIdx.x;
+  // per-thread accumulators: channels t and t + 256 (W2 rows, b2), and (a, q) pairs of W1/b1
+  float aw2[2][32], ab2[2] = {0.f, 0.f}, aw1 = 0.f;
+  for (int k = 0; k < 2; ++k)
+    for (int q = 0; q < 32; ++q) aw2[k][q] = 0.f;
+  for (int64_t p0 = pbeg; p0 < pend; p0 += kEtaPix) {
+    const int np = (int)min((int64_t)kEtaPix, pend - p0);
+    __syncthreads();
+    for (int u = t; u < np * hid; u += 256) {
+      const int q = u / hid, a = u - q * hid;
+      const int64_t gp = p0 + q;
+      const int smp = (int)(gp / npix);
+      const int64_t p = gp - (int64_t)smp * npix;
+      const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
+      const float* L = lv + smp * lv_stride;
+      const float d0 = L[i], d1 = L[W + i], d2 = L[3 * W + j], d3 = L[3 * W + H + j];
+      float s = b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3;
+      s_h[q * 32 + a] = tanhf(s);
+      if (a == 0) {
+        s_d[q * 4] = d0;
+        s_d[q * 4 + 1] = d1;
+        s_d[q * 4 + 2] = d2;
+        s_d[q * 4 + 3] = d3;
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < 2; ++k) {
+      const int c = t + 256 * k;
+      if (c >= cin8) continue;
+      for (int q = 0; q < np; ++q) {
+        const int64_t gp = p0 + q;
+        const int smp = (int)(gp / npix);
+        const int64_t p = gp - (int64_t)smp * npix;
+        const int64_t o = gp * cin8 + c;
+        const float g = bf2f(dxb[o]);
+        const float e = bf2f(eta[smp * e_bs + p * cin8 + c]);
+        dxb[o] = f2bf(e * g);
+        if (c >= cin) continue;
+        float phi = b2[c];
+        for (int a = 0; a < hid; ++a) phi += W2[c * hid + a] * s_h[q * 32 + a];
+        const float ef = expf(-phi * phi);
+        const float dphi = g * bf2f(x[o]) * (-2.f * phi * ef);
+        s_dphi[q * cin + c] = dphi;
+        ab2[k] += dphi;
+        for (int a = 0; a < hid; ++a) aw2[k][a] += dphi * s_h[q * 32 + a];
+      }
+    }
+    __syncthreads();
+    // dz[q][a] = (sum_c W2[c][a] dphi[q][c]) (1 - h^2); W1/b1 accumulators, thread t -> (a, k) pair
+    if (t < hid * 5) {
+      const int a = t / 5, kk = t - a * 5;
+      for (int q = 0; q < np; ++q) {
+        float dh = 0.f;
+        for (int c = 0; c < cin; ++c) dh += W2[c * hid + a] * s_dphi[q * cin + c];
+        const float h = s_h[q * 32 + a];
+        const float dz = dh * (1.f - h * h);
+        aw1 += kk < 4 ? dz * s_d[q * 4 + kk] : dz;
+      }
+    }
+  }
+  // partial row: [W1 (hid*4) | b1 (hid) | W2 (cin*hid) | b2 (cin)]
+  const int len = hid * 5 + cin * hid + cin;
+  float* row = part + (int64_t)blockIdx.x * len;
+  if (t < hid * 5) {
+    const int a = t / 5, kk = t - a * 5;
+    if (kk < 4) row[a * 4 + kk] = aw1;
+    else row[hid * 4 + a] = aw1;
+  }
+  for (int k = 0; k < 2; ++k) {
+    const int c = t + 256 * k;
+    if (c >= cin) continue;
+    for (int a = 0; a < hid; ++a) row[hid * 5 + c * hid + a] = aw2[k][a];
+    row[hid * 5 + cin * hid + c] = ab2[k];
+  }
+}
+
+// Static channels of the activation buffers of nb samples on their own grids.
+__global__ void k_fill_static_multi(int H, int W, int pitch, int coff, const float* __restrict__ lv, int64_t lv_stride,
+                                    const uint8_t* const* __restrict__ masks, int moff, bf16_t* __restrict__ buf,
+                                    int64_t bstride) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)H * W) return;
+  const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
+  const float* L = lv + blockIdx.y * lv_stride;
+  bf16_t* b = buf + blockIdx.y * bstride + p * pitch;
+  if (coff >= 0) {
+    b[coff] = f2bf(L[2 * W + i]);
+    b[coff + 1] = f2bf(L[3 * W + 2 * H + j]);
+  }
+  if (moff >= 0) {
+    const uint8_t* m = masks ? masks[blockIdx.y] : nullptr;
+    b[moff] = f2bf(m ? (float)m[p] : 0.f);
+  }
+}
+
+// Trunk input channels (normalised centre coordinates, padded to 8).
+__global__ void k_trunk_input(int H, int W, const float* __restrict__ tin, int64_t t_stride, bf16_t* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)H * W) return;
+  const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
+  const float* tt = tin + blockIdx.y * t_stride;
+  bf16_t* o = out + ((int64_t)blockIdx.y * H * W + p) * 8;
+  o[0] = f2bf(tt[i]);
+  o[1] = f2bf(tt[W + j]);
+  for (int c = 2; c < 8; ++c) o[c] = 0;
+}
+
+// DeepONet contraction y = gamma * sum_k B_k T_k (FP32 sum of BF16 operands).
+__global__ void k_don_fwd(int64_t n, int P, const bf16_t* __restrict__ B, const bf16_t* __restrict__ T,
+                          const float* __restrict__ gamma, float* __restrict__ y) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  float s = 0.f;
+  for (int k = 0; k < P; ++k) s += bf2f(B[p * P + k]) * bf2f(T[p * P + k]);
+  y[p] = gamma[0] * s;
+}
+
+// Its backward for dy = scale * g: dB = gamma dy T, dT = gamma dy B, and
+// per-workgroup partials of dgamma = sum dy sum_k B_k T_k.
+__global__ __launch_bounds__(256) void k_don_bwd(int64_t n, int P, const bf16_t* __restrict__ B,
+                                                 const bf16_t* __restrict__ T, const float* __restrict__ gamma,
+                                                 const float* __restrict__ g, float scale, bf16_t* __restrict__ dB,
+                                                 bf16_t* __restrict__ dT, float* __restrict__ part) {
+  __shared__ double lds[kWaves];
+  double acc = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+    const float dy = scale * g[p];
+    const float gd = gamma[0] * dy;
+    float s = 0.f;
+    for (int k = 0; k < P; ++k) {
+      const float b = bf2f(B[p * P + k]), t = bf2f(T[p * P + k]);
+      s += b * t;
+      dB[p * P + k] = f2bf(gd * t);
+      dT[p * P + k] = f2bf(gd * b);
+    }
+    acc += (double)dy * s;
+  }
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = (float)acc;
+}
+
+// Residual loss pieces: res = R - Ay (stored), per-workgroup partials of res^2.
+__global__ __launch_bounds__(256) void k_loss(int64_t n, const float* __restrict__ R, const float* __restrict__ Ay,
+                                              float* __restrict__ res, double* __restrict__ part) {
+  __shared__ double lds[kWaves];
+  double acc = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+    const float v = R[p] - Ay[p];
+    res[p] = v;
+    acc += (double)v * v;
+  }
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int n, double scale, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s += part[k];
+  out[0] = scale * s;
+}
+
+// Adam (Kingma & Ba 2015, Alg. 1) on the FP32 master parameters.
+__global__ void k_adam(int64_t n, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float gk = g[k];
+  const float mk = b1 * m[k] + (1.f - b1) * gk;
+  const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+void launch_wgrad(int taps, const WgradGeo& g, const bf16_t* dp, const bf16_t* x, const bf16_t* eta, float* part,
+                  int nsplit, hipStream_t s) {
+  const dim3 grid((g.cout + 31) / 32, (g.cin8 + 31) / 32, nsplit);
+  if (taps == 9) k_wgrad<9><<<grid, 256, 0, s>>>(g, dp, x, eta, part);
+  else k_wgrad<1><<<grid, 256, 0, s>>>(g, dp, x, eta, part);
+}
+
+void launch_reduce_rows(const float* part, int nparts, int64_t len, float scale, float* out, hipStream_t s) {
+  k_reduce_rows<<<nblk(len), 256, 0, s>>>(part, nparts, len, scale, out);
+}
+
+void launch_bias_grad(const bf16_t* d, int64_t npix, int pitch, int off, int C, float* part, int nparts,
+                      hipStream_t s) {
+  k_bias_grad<<<nparts, 256, 0, s>>>(d, npix, pitch, off, C, part);
+}
+
+void launch_act_bwd(bf16_t* d, int dpitch, const bf16_t* out, int opitch, int ooff, int C, int64_t npix, int mode,
+                    hipStream_t s) {
+  k_act_bwd<<<nblk(npix * C), 256, 0, s>>>(d, dpitch, out, opitch, ooff, C, npix, mode);
+}
+
+void launch_copy_ch(const bf16_t* src, int spitch, int soff, bf16_t* dst, int dpitch, int C, int64_t npix, int acc,
+                    hipStream_t s) {
+  k_copy_ch<<<nblk(npix * C), 256, 0, s>>>(src, spitch, soff, dst, dpitch, C, npix, acc);
+}
+
+void launch_up_bwd(int Hc, int Wc, int C, const bf16_t* fine, int fpitch, int64_t f_bs, bf16_t* coarse, int64_t c_bs,
+                   int nb, hipStream_t s) {
+  k_up_bwd<<<dim3(nblk((int64_t)Hc * Wc * C), nb), 256, 0, s>>>(Hc, Wc, C, fine, fpitch, f_bs, coarse, c_bs);
+}
+
+void launch_pool_bwd(int Hc, int Wc, int C, const bf16_t* dpool, int ppitch, int64_t p_bs, bf16_t* dE, int64_t e_bs,
+                     int nb, hipStream_t s) {
+  k_pool_bwd<<<dim3(nblk((int64_t)Hc * Wc * C), nb), 256, 0, s>>>(Hc, Wc, C, dpool, ppitch, p_bs, dE, e_bs);
+}
+
+void launch_eta_multi(int H, int W, int cin, int cin8, int hid, const float* lv, int64_t lv_stride, const float* W1,
+                      const float* b1, const float* W2, const float* b2, bf16_t* eta, int64_t e_bs, int nb,
+                      hipStream_t s) {
+  k_eta_multi<<<dim3(nblk((int64_t)H * W), nb), 256, 0, s>>>(H, W, cin, cin8, hid, lv, lv_stride, W1, b1, W2, b2, eta,
+                                                              e_bs);
+}
+
+int eta_bwd_len(int cin, int hid) { return hid * 5 + cin * hid + cin; }
+
+void launch_eta_bwd(int H, int W, int cin, int cin8, int hid, int nb, const float* lv, int64_t lv_stride,
+                    const float* W1, const float* b1, const float* W2, const float* b2, const bf16_t* x,
+                    const bf16_t* eta, int64_t e_bs, bf16_t* dxb, float* part, int nparts, hipStream_t s) {
+  const size_t shm = sizeof(float) * (kEtaPix * 32 + kEtaPix * 4 + (size_t)kEtaPix * cin);
+  k_eta_bwd<<<nparts, 256, shm, s>>>(H, W, cin, cin8, hid, nb, lv, lv_stride, W1, b1, W2, b2, x, eta, e_bs, dxb,
+                                      part);
+}
+
+void launch_fill_static_multi(int H, int W, int pitch, int coff, const float* lv, int64_t lv_stride,
+                              const uint8_t* const* masks, int moff, bf16_t* buf, int64_t bstride, int nb,
+                              hipStream_t s) {
+  k_fill_static_multi<<<dim3(nblk((int64_t)H * W), nb), 256, 0, s>>>(H, W, pitch, coff, lv, lv_stride, masks, moff,
+                                                                      buf, bstride);
+}
+
+void launch_trunk_input(int H, int W, const float* tin, int64_t t_stride, bf16_t* out, int nb, hipStream_t s) {
+  k_trunk_input<<<dim3(nblk((int64_t)H * W), nb), 256, 0, s>>>(H, W, tin, t_stride, out);
+}
+
+void launch_don_fwd(int64_t n, int P, const bf16_t* B, const bf16_t* T, const float* gamma, float* y, hipStream_t s) {
+  k_don_fwd<<<nblk(n), 256, 0, s>>>(n, P, B, T, gamma, y);
+}
+
+void launch_don_bwd(int64_t n, int P, const bf16_t* B, const bf16_t* T, const float* gamma, const float* g,
+                    float scale, bf16_t* dB, bf16_t* dT, float* part, int nparts, hipStream_t s) {
+  k_don_bwd<<<nparts, 256, 0, s>>>(n, P, B, T, gamma, g, scale, dB, dT, part);
+}
+
+void launch_loss(int64_t n, const float* R, const float* Ay, float* res, double* part, int nparts, hipStream_t s) {
+  k_loss<<<nparts, 256, 0, s>>>(n, R, Ay, res, part);
+}
+
+void launch_sum_parts(const double* part, int n, double scale, double* out, hipStream_t s) {
+  k_sum_parts<<<1, 64, 0, s>>>(part, n, scale, out);
+}
+
+void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t s) {
+  k_adam<<<nblk(n), 256, 0, s>>>(n, w, g, m, v, lr, b1, b2, eps, c1, c2);
+}
+
+}  // namespace ppe

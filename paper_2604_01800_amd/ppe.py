@@ -311,3 +311,29 @@ def ppe_solve_hybrid(prob: Problem, net, f, x, opts=None, stream=None):
                                 ctypes.cast(stats, ctypes.c_void_p), _stream(stream))
     _check(st, (PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))
     return st, [stats[i].as_dict() for i in range(nb)]
+
+
+def ppe_train_opts_default(**kw) -> ppe_train_opts:
+    o = ppe_train_opts(1e-3, 0.9, 0.999, 1e-8, 0, 0)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def ppe_net_train_step(net: Net, probs, R, opts=None, want_grad=False, stream=None):
+    """One Adam step (lr = 0: gradient only). probs: list of Problem (one grid per sample),
+    R: device float32 [nb, ny, nx]. Returns (loss, grad ndarray or None)."""
+    import torch
+    nb = len(probs)
+    if R.dim() != 3 or R.shape[0] != nb:
+        raise ValueError("R must be [nb, ny, nx] with one sample per problem")
+    for p in probs:
+        _nb(R[0], p)
+    arr = (ctypes.c_void_p * nb)(*[p.handle.value for p in probs])
+    opts = opts or ppe_train_opts_default()
+    loss = ctypes.c_float()
+    grad = np.empty(ppe_net_num_params(net), dtype=np.float32) if want_grad else None
+    _check(lib().ppe_net_train_step(net.handle, nb, ctypes.cast(arr, ctypes.c_void_p), _dev(R, torch.float32, "R"),
+                                    ctypes.byref(opts), ctypes.byref(loss),
+                                    grad.ctypes.data if want_grad else None, _stream(stream)))
+    return float(loss.value), grad
