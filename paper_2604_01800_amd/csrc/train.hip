@@ -417,7 +417,7 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
     if (!cfg.use_eta) return;
     const int l = m.level;
     const int len = eta_bwd_len(m.cin, HID);
-    const int np = 512;
+    const int np = 2048;
     launch_eta_bwd(t->H[l], t->W[l], m.cin, m.cin8, HID, nb, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
                    W + m.ob1, W + m.oW2, W + m.ob2, x, E + eoff, hw(l) * m.cin8, dxb, part, np, s);
     launch_reduce_rows(part, np, len, 1.f, dG + m.oW1, s);

@@ -2,6 +2,8 @@
 // over pixels, fixed-order reduction), activation-gradient masks, the
 // Mesh-Conv local-weight backward, pooling / upsampling / concatenation
 // backward, the DeepONet contraction, the residual loss of Eq. 19, and Adam.
+#include <algorithm>
+
 #include "common.hpp"
 #include "net_common.hpp"
 #include "train_kernels.hpp"
@@ -121,37 +123,85 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
   }
 }
 
-// out[k] = scale * sum_b part[b][k] (fixed order, FP64 accumulation).
-__global__ void k_reduce_rows(const float* __restrict__ part, int nparts, int64_t len, float scale,
-                              float* __restrict__ out) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= len) return;
+// out[k] = scale * sum_b part[b][k] (fixed order, FP64 accumulation). A
+// workgroup handles 32 consecutive k; its 8 thread groups sum the rows
+// g, g + 8, ... and the 8 group sums are added in order.
+__global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ part, int nparts, int64_t len,
+                                                     float scale, float* __restrict__ out) {
+  __shared__ double red[8][32];
+  const int kk = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const int64_t k = (int64_t)blockIdx.x * 32 + kk;
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * len + k];
-  out[k] = (float)(scale * s);
+  if (k < len)
+    for (int b = g; b < nparts; b += 8) s += part[(int64_t)b * len + k];
+  red[g][kk] = s;
+  __syncthreads();
+  if (g == 0 && k < len) {
+    double tot = 0.0;
+    for (int q = 0; q < 8; ++q) tot += red[q][kk];
+    out[k] = (float)(scale * tot);
+  }
 }
 
 // Bias gradient partials: part[b][c] = sum over workgroup b's pixels of d[p][c].
+// Thread t reads 8 channels (c8 = t % (C/8)) of the pixels of phase t / (C/8);
+// the phases are summed in LDS in a fixed order. Requires C % 8 == 0, C <= 2048.
 __global__ __launch_bounds__(256) void k_bias_grad(const bf16_t* __restrict__ d, int64_t npix, int pitch, int off,
                                                    int C, float* __restrict__ part) {
-  for (int c = threadIdx.x; c < C; c += 256) {
-    float s = 0.f;
-    for (int64_t p = blockIdx.x; p < npix; p += gridDim.x) s += bf2f(d[p * pitch + off + c]);
-    part[(int64_t)blockIdx.x * C + c] = s;
+  __shared__ float red[256 * 8];
+  const int c8n = C / 8;
+  const int G = 256 / c8n;  // pixel phases per workgroup
+  const int t = threadIdx.x;
+  const int c8 = t % c8n, g = t / c8n;
+  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (g < G) {
+    for (int64_t p = (int64_t)blockIdx.x * G + g; p < npix; p += (int64_t)gridDim.x * G) {
+      const uint4 v = *(const uint4*)(d + p * pitch + off + c8 * 8);
+      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[2 * e] += bf2f((bf16_t)(w4[e] & 0xffff));
+        acc[2 * e + 1] += bf2f((bf16_t)(w4[e] >> 16));
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) red[t * 8 + e] = acc[e];
+  __syncthreads();
+  for (int c = t; c < C; c += 256) {
+    float sacc = 0.f;
+    for (int gg = 0; gg < G; ++gg) sacc += red[(gg * c8n + c / 8) * 8 + (c % 8)];
+    part[(int64_t)blockIdx.x * C + c] = sacc;
   }
 }
 
 // In-place activation backward: d *= relu'(out) (mode 1) or tanh'(out) (mode 2).
+// Eight channels per thread (C, pitches and offsets are multiples of 8).
 __global__ void k_act_bwd(bf16_t* __restrict__ d, int dpitch, const bf16_t* __restrict__ out, int opitch, int ooff,
                           int C, int64_t npix, int mode) {
+  const int c8n = C / 8;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= npix * C) return;
-  const int64_t p = idx / C;
-  const int c = (int)(idx - p * C);
-  const float o = bf2f(out[p * opitch + ooff + c]);
-  float v = bf2f(d[p * dpitch + c]);
-  v = mode == 1 ? (o > 0.f ? v : 0.f) : v * (1.f - o * o);
-  d[p * dpitch + c] = f2bf(v);
+  if (idx >= npix * c8n) return;
+  const int64_t p = idx / c8n;
+  const int c = (int)(idx - p * c8n) * 8;
+  uint4* dp = (uint4*)(d + p * dpitch + c);
+  const uint4 dv = *dp, ov = *(const uint4*)(out + p * opitch + ooff + c);
+  const uint32_t a[4] = {dv.x, dv.y, dv.z, dv.w}, b[4] = {ov.x, ov.y, ov.z, ov.w};
+  uint32_t o[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float lo = bf2f((bf16_t)(a[e] & 0xffff)), hi = bf2f((bf16_t)(a[e] >> 16));
+    const float olo = bf2f((bf16_t)(b[e] & 0xffff)), ohi = bf2f((bf16_t)(b[e] >> 16));
+    if (mode == 1) {
+      lo = olo > 0.f ? lo : 0.f;
+      hi = ohi > 0.f ? hi : 0.f;
+    } else {
+      lo *= 1.f - olo * olo;
+      hi *= 1.f - ohi * ohi;
+    }
+    o[e] = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+  }
+  *dp = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // dst[p][c] (+)= src[p][soff + c], c < C.
@@ -200,30 +250,38 @@ __global__ void k_pool_bwd(int Hc, int Wc, int C, const bf16_t* __restrict__ dpo
 
 // ---------------------------------------------------------------------------
 // Per-sample Mesh-Conv local weights (each sample has its own grid): the
-// level arrays of sample s start at lv + s * lv_stride.
-__global__ void k_eta_multi(int H, int W, int cin, int cin8, int hid, const float* __restrict__ lv, int64_t lv_stride,
-                            const float* __restrict__ W1, const float* __restrict__ b1, const float* __restrict__ W2,
-                            const float* __restrict__ b2, bf16_t* __restrict__ eta, int64_t e_bs) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= (int64_t)H * W) return;
-  const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
-  const float* a = lv + blockIdx.y * lv_stride;
-  const float d[4] = {a[i], a[W + i], a[3 * W + j], a[3 * W + H + j]};
-  float h[32];
-  for (int q = 0; q < hid; ++q) {
-    float s = b1[q];
-    for (int k = 0; k < 4; ++k) s += W1[q * 4 + k] * d[k];
-    h[q] = tanhf(s);
+// level arrays of sample s start at lv + s * lv_stride. A workgroup computes
+// the hidden layer of Phi for 32 pixels, then writes eta[p][c] with the
+// channel index fastest across threads.
+__global__ __launch_bounds__(256) void k_eta_multi(int H, int W, int cin, int cin8, int hid,
+                                                   const float* __restrict__ lv, int64_t lv_stride,
+                                                   const float* __restrict__ W1, const float* __restrict__ b1,
+                                                   const float* __restrict__ W2, const float* __restrict__ b2,
+                                                   bf16_t* __restrict__ eta, int64_t e_bs) {
+  __shared__ float s_h[32][33];
+  const int64_t npix = (int64_t)H * W;
+  const int64_t p0 = (int64_t)blockIdx.x * 32;
+  const float* L = lv + blockIdx.y * lv_stride;
+  for (int u = threadIdx.x; u < 32 * hid; u += 256) {
+    const int q = u / hid, a = u - q * hid;
+    const int64_t p = min(p0 + q, npix - 1);
+    const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
+    const float d0 = L[i], d1 = L[W + i], d2 = L[3 * W + j], d3 = L[3 * W + H + j];
+    s_h[q][a] = tanhf(b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3);
   }
-  bf16_t* out = eta + blockIdx.y * e_bs + p * cin8;
-  for (int c = 0; c < cin8; ++c) {
+  __syncthreads();
+  bf16_t* out = eta + blockIdx.y * e_bs;
+  for (int u = threadIdx.x; u < 32 * cin8; u += 256) {
+    const int q = u / cin8, c = u - q * cin8;
+    const int64_t p = p0 + q;
+    if (p >= npix) continue;
     float e = 0.f;
     if (c < cin) {
       float phi = b2[c];
-      for (int q = 0; q < hid; ++q) phi += W2[c * hid + q] * h[q];
+      for (int a = 0; a < hid; ++a) phi += W2[c * hid + a] * s_h[q][a];
       e = expf(-phi * phi);
     }
-    out[c] = f2bf(e);
+    out[p * cin8 + c] = f2bf(e);
   }
 }
 
@@ -231,8 +289,10 @@ __global__ void k_eta_multi(int H, int W, int cin, int cin8, int hid, const floa
 // input) and the layer input X: dX = eta * dXbar (written in place of dXbar)
 // and, through dEta = dXbar * X and eta = exp(-Phi^2), the gradients of Phi's
 // parameters. A workgroup handles 32-pixel batches of a contiguous pixel
-// range and writes one partial row [W1 (hid*4) | b1 (hid) | W2 (cin*hid) |
-// b2 (cin)] (the layout of these parameters in the flat vector).
+// range; thread t owns channel slot t % ns (ns = min(cin8, 256)) and pixel
+// phase t / ns. At the end the per-thread sums are reduced over the phases in
+// a fixed order and one partial row [W1 (hid*4) | b1 (hid) | W2 (cin*hid) |
+// b2 (cin)] (the layout of these parameters in the flat vector) is written.
 constexpr int kEtaPix = 32;
 __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8, int hid, int nb,
                                                  const float* __restrict__ lv, int64_t lv_stride,
@@ -241,17 +301,28 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
                                                  const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta,
                                                  int64_t e_bs, bf16_t* __restrict__ dxb, float* __restrict__ part) {
   extern __shared__ float sm[];
-  float* s_h = sm;                              // [kEtaPix][32]
-  float* s_d = s_h + kEtaPix * 32;              // [kEtaPix][4] distances
-  float* s_dphi = s_d + kEtaPix * 4;            // [kEtaPix][cin]
+  float* s_h = sm;                          // [kEtaPix][32] hidden activations
+  float* s_d = s_h + kEtaPix * 32;          // [kEtaPix][4] distances
+  float* s_dz = s_d + kEtaPix * 4;          // [kEtaPix][32] hidden pre-activation gradients
+  float* s_w2 = s_dz + kEtaPix * 32;        // [hid][cin] (transposed)
+  float* s_dphi = s_w2 + cin * hid;         // [kEtaPix][cin]; reused for the final reduction
   const int64_t npix = (int64_t)H * W, ntot = npix * nb;
   const int64_t per = (ntot + gridDim.x - 1) / gridDim.x;
   const int64_t pbeg = blockIdx.x * per, pend = min(ntot, pbeg + per);
   const int t = threadIdx.x;
-  // per-thread accumulators: channels t and t + 256 (W2 rows, b2), and (a, q) pairs of W1/b1
-  float aw2[2][32], ab2[2] = {0.f, 0.f}, aw1 = 0.f;
-  for (int k = 0; k < 2; ++k)
+  const int ns = cin8 < 256 ? cin8 : 256;
+  const int phases = 256 / ns;
+  const int slot = t % ns, ph = t / ns;
+  const bool active = ph < phases;
+  for (int u = t; u < cin * hid; u += 256) s_w2[(u % hid) * cin + u / hid] = W2[u];
+  float aw2[2][32], ab2[2] = {0.f, 0.f}, aw1 = 0.f, b2r[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int c = slot + ns * k;
+    b2r[k] = c < cin ? b2[c] : 0.f;
+#pragma unroll
     for (int q = 0; q < 32; ++q) aw2[k][q] = 0.f;
+  }
   for (int64_t p0 = pbeg; p0 < pend; p0 += kEtaPix) {
     const int np = (int)min((int64_t)kEtaPix, pend - p0);
     __syncthreads();
@@ -263,8 +334,7 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
       const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
       const float* L = lv + smp * lv_stride;
       const float d0 = L[i], d1 = L[W + i], d2 = L[3 * W + j], d3 = L[3 * W + H + j];
-      float s = b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3;
-      s_h[q * 32 + a] = tanhf(s);
+      s_h[q * 32 + a] = tanhf(b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3);
       if (a == 0) {
         s_d[q * 4] = d0;
         s_d[q * 4 + 1] = d1;
@@ -273,41 +343,49 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
       }
     }
     __syncthreads();
-    for (int k = 0; k < 2; ++k) {
-      const int c = t + 256 * k;
-      if (c >= cin8) continue;
-      for (int q = 0; q < np; ++q) {
-        const int64_t gp = p0 + q;
-        const int smp = (int)(gp / npix);
-        const int64_t p = gp - (int64_t)smp * npix;
-        const int64_t o = gp * cin8 + c;
-        const float g = bf2f(dxb[o]);
-        const float e = bf2f(eta[smp * e_bs + p * cin8 + c]);
-        dxb[o] = f2bf(e * g);
-        if (c >= cin) continue;
-        float phi = b2[c];
-        for (int a = 0; a < hid; ++a) phi += W2[c * hid + a] * s_h[q * 32 + a];
-        const float ef = expf(-phi * phi);
-        const float dphi = g * bf2f(x[o]) * (-2.f * phi * ef);
-        s_dphi[q * cin + c] = dphi;
-        ab2[k] += dphi;
-        for (int a = 0; a < hid; ++a) aw2[k][a] += dphi * s_h[q * 32 + a];
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int c = slot + ns * k;
+        if (c >= cin8) continue;
+        for (int q = ph; q < np; q += phases) {
+          const int64_t gp = p0 + q;
+          const int smp = (int)(gp / npix);
+          const int64_t p = gp - (int64_t)smp * npix;
+          const int64_t o = gp * cin8 + c;
+          const float g = bf2f(dxb[o]);
+          const float e = bf2f(eta[smp * e_bs + p * cin8 + c]);
+          dxb[o] = f2bf(e * g);
+          if (c >= cin) continue;
+          float phi = b2r[k];
+#pragma unroll
+          for (int a = 0; a < 32; ++a)
+            if (a < hid) phi += s_w2[a * cin + c] * s_h[q * 32 + a];
+          const float ef = expf(-phi * phi);
+          const float dphi = g * bf2f(x[o]) * (-2.f * phi * ef);
+          s_dphi[q * cin + c] = dphi;
+          ab2[k] += dphi;
+#pragma unroll
+          for (int a = 0; a < 32; ++a)
+            if (a < hid) aw2[k][a] += dphi * s_h[q * 32 + a];
+        }
       }
     }
     __syncthreads();
-    // dz[q][a] = (sum_c W2[c][a] dphi[q][c]) (1 - h^2); W1/b1 accumulators, thread t -> (a, k) pair
+    // dz[q][a] = (sum_c W2[c][a] dphi[q][c]) (1 - h^2), spread over (q, a) pairs
+    for (int u = t; u < np * hid; u += 256) {
+      const int q = u / hid, a = u - q * hid;
+      float dh = 0.f;
+      for (int c = 0; c < cin; ++c) dh += s_w2[a * cin + c] * s_dphi[q * cin + c];
+      const float h = s_h[q * 32 + a];
+      s_dz[q * 32 + a] = dh * (1.f - h * h);
+    }
+    __syncthreads();
     if (t < hid * 5) {
       const int a = t / 5, kk = t - a * 5;
-      for (int q = 0; q < np; ++q) {
-        float dh = 0.f;
-        for (int c = 0; c < cin; ++c) dh += W2[c * hid + a] * s_dphi[q * cin + c];
-        const float h = s_h[q * 32 + a];
-        const float dz = dh * (1.f - h * h);
-        aw1 += kk < 4 ? dz * s_d[q * 4 + kk] : dz;
-      }
+      for (int q = 0; q < np; ++q) aw1 += kk < 4 ? s_dz[q * 32 + a] * s_d[q * 4 + kk] : s_dz[q * 32 + a];
     }
   }
-  // partial row: [W1 (hid*4) | b1 (hid) | W2 (cin*hid) | b2 (cin)]
   const int len = hid * 5 + cin * hid + cin;
   float* row = part + (int64_t)blockIdx.x * len;
   if (t < hid * 5) {
@@ -315,11 +393,24 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
     if (kk < 4) row[a * 4 + kk] = aw1;
     else row[hid * 4 + a] = aw1;
   }
+  // reduce the per-phase sums of each channel (s_dphi holds >= 256 * 33 floats)
+  float* red = s_dphi;
+#pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const int c = t + 256 * k;
-    if (c >= cin) continue;
-    for (int a = 0; a < hid; ++a) row[hid * 5 + c * hid + a] = aw2[k][a];
-    row[hid * 5 + cin * hid + c] = ab2[k];
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 32; ++a)
+      if (a <= hid) red[t * 33 + a] = a < hid ? aw2[k][a] : ab2[k];
+    __syncthreads();
+    for (int u = t; u < ns * (hid + 1); u += 256) {
+      const int sl = u / (hid + 1), a = u - sl * (hid + 1);
+      const int c = sl + ns * k;
+      if (c >= cin) continue;
+      float acc = 0.f;
+      for (int q = 0; q < phases; ++q) acc += red[(q * ns + sl) * 33 + a];
+      if (a < hid) row[hid * 5 + c * hid + a] = acc;
+      else row[hid * 5 + cin * hid + c] = acc;
+    }
   }
 }
 
@@ -355,13 +446,42 @@ __global__ void k_trunk_input(int H, int W, const float* __restrict__ tin, int64
 }
 
 // DeepONet contraction y = gamma * sum_k B_k T_k (FP32 sum of BF16 operands).
-__global__ void k_don_fwd(int64_t n, int P, const bf16_t* __restrict__ B, const bf16_t* __restrict__ T,
-                          const float* __restrict__ gamma, float* __restrict__ y) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+// 16 lanes per pixel, 8 basis terms per lane per pass (P % 8 == 0).
+__device__ __forceinline__ float dot8(uint4 a, uint4 b) {
+  const uint32_t x[4] = {a.x, a.y, a.z, a.w}, y[4] = {b.x, b.y, b.z, b.w};
   float s = 0.f;
-  for (int k = 0; k < P; ++k) s += bf2f(B[p * P + k]) * bf2f(T[p * P + k]);
-  y[p] = gamma[0] * s;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    s += bf2f((bf16_t)(x[e] & 0xffff)) * bf2f((bf16_t)(y[e] & 0xffff)) +
+         bf2f((bf16_t)(x[e] >> 16)) * bf2f((bf16_t)(y[e] >> 16));
+  return s;
+}
+
+__device__ __forceinline__ float sum16(float v) {
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_don_fwd(int64_t n, int P, const bf16_t* __restrict__ B,
+                                                 const bf16_t* __restrict__ T, const float* __restrict__ gamma,
+                                                 float* __restrict__ y) {
+  const int64_t p = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int l = threadIdx.x & 15;
+  float s = 0.f;
+  if (p < n)
+    for (int k = l * 8; k < P; k += 128) s += dot8(*(const uint4*)(B + p * P + k), *(const uint4*)(T + p * P + k));
+  s = sum16(s);
+  if (p < n && l == 0) y[p] = gamma[0] * s;
+}
+
+__device__ __forceinline__ uint4 scale8(uint4 a, float c) {
+  const uint32_t x[4] = {a.x, a.y, a.z, a.w};
+  uint32_t o[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    o[e] = (uint32_t)f2bf(c * bf2f((bf16_t)(x[e] & 0xffff))) | ((uint32_t)f2bf(c * bf2f((bf16_t)(x[e] >> 16))) << 16);
+  return make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // Its backward for dy = scale * g: dB = gamma dy T, dT = gamma dy B, and
@@ -371,18 +491,20 @@ __global__ __launch_bounds__(256) void k_don_bwd(int64_t n, int P, const bf16_t*
                                                  const float* __restrict__ g, float scale, bf16_t* __restrict__ dB,
                                                  bf16_t* __restrict__ dT, float* __restrict__ part) {
   __shared__ double lds[kWaves];
+  const int l = threadIdx.x & 15;
   double acc = 0.0;
-  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+  for (int64_t p = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4); p < n; p += (int64_t)gridDim.x * 16) {
     const float dy = scale * g[p];
     const float gd = gamma[0] * dy;
     float s = 0.f;
-    for (int k = 0; k < P; ++k) {
-      const float b = bf2f(B[p * P + k]), t = bf2f(T[p * P + k]);
-      s += b * t;
-      dB[p * P + k] = f2bf(gd * t);
-      dT[p * P + k] = f2bf(gd * b);
+    for (int k = l * 8; k < P; k += 128) {
+      const uint4 b = *(const uint4*)(B + p * P + k), t = *(const uint4*)(T + p * P + k);
+      s += dot8(b, t);
+      *(uint4*)(dB + p * P + k) = scale8(t, gd);
+      *(uint4*)(dT + p * P + k) = scale8(b, gd);
     }
-    acc += (double)dy * s;
+    const float tot = sum16(s);  // all 16 lanes of the pixel take part
+    if (l == 0) acc += (double)dy * (double)tot;
   }
   acc = block_sum(acc, lds);
   if (threadIdx.x == 0) part[blockIdx.x] = (float)acc;
@@ -433,7 +555,7 @@ void launch_wgrad(int taps, const WgradGeo& g, const bf16_t* dp, const bf16_t* x
 }
 
 void launch_reduce_rows(const float* part, int nparts, int64_t len, float scale, float* out, hipStream_t s) {
-  k_reduce_rows<<<nblk(len), 256, 0, s>>>(part, nparts, len, scale, out);
+  k_reduce_rows<<<(unsigned)((len + 31) / 32), 256, 0, s>>>(part, nparts, len, scale, out);
 }
 
 void launch_bias_grad(const bf16_t* d, int64_t npix, int pitch, int off, int C, float* part, int nparts,
@@ -443,7 +565,7 @@ void launch_bias_grad(const bf16_t* d, int64_t npix, int pitch, int off, int C, 
 
 void launch_act_bwd(bf16_t* d, int dpitch, const bf16_t* out, int opitch, int ooff, int C, int64_t npix, int mode,
                     hipStream_t s) {
-  k_act_bwd<<<nblk(npix * C), 256, 0, s>>>(d, dpitch, out, opitch, ooff, C, npix, mode);
+  k_act_bwd<<<nblk(npix * (C / 8)), 256, 0, s>>>(d, dpitch, out, opitch, ooff, C, npix, mode);
 }
 
 void launch_copy_ch(const bf16_t* src, int spitch, int soff, bf16_t* dst, int dpitch, int C, int64_t npix, int acc,
@@ -464,8 +586,8 @@ void launch_pool_bwd(int Hc, int Wc, int C, const bf16_t* dpool, int ppitch, int
 void launch_eta_multi(int H, int W, int cin, int cin8, int hid, const float* lv, int64_t lv_stride, const float* W1,
                       const float* b1, const float* W2, const float* b2, bf16_t* eta, int64_t e_bs, int nb,
                       hipStream_t s) {
-  k_eta_multi<<<dim3(nblk((int64_t)H * W), nb), 256, 0, s>>>(H, W, cin, cin8, hid, lv, lv_stride, W1, b1, W2, b2, eta,
-                                                              e_bs);
+  k_eta_multi<<<dim3((unsigned)(((int64_t)H * W + 31) / 32), nb), 256, 0, s>>>(H, W, cin, cin8, hid, lv, lv_stride,
+                                                                                W1, b1, W2, b2, eta, e_bs);
 }
 
 int eta_bwd_len(int cin, int hid) { return hid * 5 + cin * hid + cin; }
@@ -473,7 +595,8 @@ int eta_bwd_len(int cin, int hid) { return hid * 5 + cin * hid + cin; }
 void launch_eta_bwd(int H, int W, int cin, int cin8, int hid, int nb, const float* lv, int64_t lv_stride,
                     const float* W1, const float* b1, const float* W2, const float* b2, const bf16_t* x,
                     const bf16_t* eta, int64_t e_bs, bf16_t* dxb, float* part, int nparts, hipStream_t s) {
-  const size_t shm = sizeof(float) * (kEtaPix * 32 + kEtaPix * 4 + (size_t)kEtaPix * cin);
+  const size_t shm = sizeof(float) * (kEtaPix * 32 + kEtaPix * 4 + kEtaPix * 32 + (size_t)cin * hid +
+                                      std::max<size_t>((size_t)kEtaPix * cin, 256 * 33));
   k_eta_bwd<<<nparts, 256, shm, s>>>(H, W, cin, cin8, hid, nb, lv, lv_stride, W1, b1, W2, b2, x, eta, e_bs, dxb,
                                       part);
 }
@@ -490,7 +613,7 @@ void launch_trunk_input(int H, int W, const float* tin, int64_t t_stride, bf16_t
 }
 
 void launch_don_fwd(int64_t n, int P, const bf16_t* B, const bf16_t* T, const float* gamma, float* y, hipStream_t s) {
-  k_don_fwd<<<nblk(n), 256, 0, s>>>(n, P, B, T, gamma, y);
+  k_don_fwd<<<(unsigned)((n + 15) / 16), 256, 0, s>>>(n, P, B, T, gamma, y);
 }
 
 void launch_don_bwd(int64_t n, int P, const bf16_t* B, const bf16_t* T, const float* gamma, const float* g,
