@@ -10,9 +10,10 @@ system from x0 = 0 to relative residual 1e-6 (FP64 true residual) with
 Jacobi-PCG, and, when a network is available (--hybrid), with the hybrid
 PCG + line-search method as well.
 
-Prints one JSON line. `roofline` reports the dominant kernel (PCG phase A)
-with its algorithmic bytes per launch divided by its average launch duration
-(HIP events on the launch stream). `cpu_baseline` times the FP64 oracle on a
+Prints one JSON line. `roofline` reports the dominant kernel (the
+single-reduction PCG iteration, one launch per iteration; or phase A of the
+two-phase form with --variant two_phase) with its algorithmic bytes per launch
+divided by its average launch duration (HIP events attached to the launches). `cpu_baseline` times the FP64 oracle on a
 bounded sample (a fixed number of PCG iterations on the same system, scaled to
 the iteration count of a full solve).
 """
@@ -28,6 +29,7 @@ import numpy as np
 
 METRIC = "PPE solves/sec to rel-res 1e-6, hybrid vs plain PCG, 1024² grid; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+BYTES_PCG1 = 24     # per cell: reads r, p, x_c; writes r, p, x_c (FP32)
 BYTES_PHASE_A = 20  # per cell: reads r, p_old, x_c; writes p, x_c (FP32)
 BYTES_PHASE_B = 12  # per cell: reads p, r; writes r (FP32)
 
@@ -39,12 +41,12 @@ def workload(n=1024, beta=1.75, seed=0):
     return g, f
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed hardware-counter run, if the
+def measured_traffic(kernel, record):
+    """HBM bytes per launch from a committed hardware-counter run, if the
     kernel sources are unchanged since then (else None)."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(here, "profiles", "pcg_phases_1024_plain.counters.json")
+    path = os.path.join(here, "profiles", record)
     try:
         rec = json.load(open(path))
         h = hashlib.sha256()
@@ -86,6 +88,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=200)
+    ap.add_argument("--variant", choices=["single", "two_phase"], default="single",
+                    help="PCG iteration form: one reduction per iteration (default) or two")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the phase-kernel timing launches and a 64 MiB calibration copy "
                          "(for hardware-counter runs)")
@@ -104,7 +108,9 @@ def main():
     prob = ppe.ppe_problem_create(g)
     f = torch.from_numpy(f_np[None]).cuda()
     x = torch.zeros((1, g.ny, g.nx), dtype=torch.float64, device="cuda")
-    opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1)
+    variant = ppe.PPE_PCG_SINGLE_REDUCTION if args.variant == "single" else ppe.PPE_PCG_TWO_PHASE
+    opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, variant=variant)
+    single = variant == ppe.PPE_PCG_SINGLE_REDUCTION
 
     if args.kernels_only:
         ms_a, ms_b = ppe.ppe_profile_pcg(prob, f, x, opts, reps=args.profile_reps)
@@ -112,7 +118,7 @@ def main():
         dst = torch.empty_like(src)
         ms_c = ppe.ppe_profile_copy(src, dst, reps=args.profile_reps)
         torch.cuda.synchronize()
-        print(json.dumps({"phase_a_ms": ms_a, "phase_b_ms": ms_b, "copy_64MiB_ms": ms_c}), flush=True)
+        print(json.dumps({"variant": args.variant, "kernel_ms": [ms_a, ms_b], "copy_64MiB_ms": ms_c}), flush=True)
         return
 
     for _ in range(args.warmup):
@@ -130,14 +136,21 @@ def main():
     if st != ppe.PPE_OK:
         print(f"solve did not converge: {s0}", file=sys.stderr)
 
-    # Dominant kernel: PCG phase A, timed alone with HIP events on the stream.
+    # Dominant kernel, timed with HIP events attached to its own launches.
     xt = torch.zeros_like(x)
     ms_a, ms_b = ppe.ppe_profile_pcg(prob, f, xt, opts, reps=args.profile_reps)
     N = g.nx * g.ny
-    ach_a = BYTES_PHASE_A * N / (ms_a * 1e-3) / 1e9
-    ach_b = BYTES_PHASE_B * N / (ms_b * 1e-3) / 1e9
     iters = s0["iters_total"]
-    pcg_gbs = 32.0 * N * iters / (ms_per_step * 1e-3) / 1e9
+    if single:
+        kname, kbytes, record = "k_pcg1 (single-reduction PCG iteration)", BYTES_PCG1, "pcg1_1024_plain.counters.json"
+        tkey = "k_pcg1"
+        per_iter_bytes = BYTES_PCG1
+    else:
+        kname, kbytes, record = "k_pcg_a (PCG phase A)", BYTES_PHASE_A, "pcg_phases_1024_plain.counters.json"
+        tkey = "k_pcg_a"
+        per_iter_bytes = BYTES_PHASE_A + BYTES_PHASE_B
+    ach = kbytes * N / (ms_a * 1e-3) / 1e9
+    pcg_gbs = per_iter_bytes * N * iters / (ms_per_step * 1e-3) / 1e9
 
     out = {
         "metric": METRIC,
@@ -155,24 +168,23 @@ def main():
         "config": {
             "workload": f"plain Jacobi-PCG, {g.nx}x{g.ny} tanh grid beta 1.75, ellipse mask, GRF source "
                         f"l=0.05, x0=0, rel-res {args.tol:g} on the FP64 true residual",
+            "pcg_form": args.variant,
             "iters": iters,
             "reliable_updates": s0["reliable_updates"],
             "rel_res_true": s0["rel_res_true"],
             "precision": "FP32 vectors, FP64 reductions and solution accumulator",
             "effective_pcg_GBps": pcg_gbs,
-            "phase_a_ms": ms_a,
-            "phase_b_ms": ms_b,
-            "phase_b_GBps": ach_b,
+            "kernel_ms": [ms_a, ms_b],
         },
         "roofline": {
-            "kernel": "k_pcg_a (PCG phase A)",
+            "kernel": kname,
             "bound": "hbm",
-            "achieved": ach_a,
+            "achieved": ach,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": ach_a / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_pcg_a"),
-            "algorithmic_bytes": BYTES_PHASE_A * N,
+            "frac": ach / HBM_PEAK_GBS,
+            "traffic": measured_traffic(tkey, record),
+            "algorithmic_bytes": kbytes * N,
         },
     }
     if not args.no_cpu_baseline:

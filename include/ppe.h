@@ -57,6 +57,13 @@ typedef struct ppe_net ppe_net;         /* opaque: DeepONet weights, optimiser s
 enum { PPE_PC_NONE = 0, PPE_PC_JACOBI = 1 };           /* vanilla CG / Jacobi-PCG (Sec. 2.5) */
 enum { PPE_TOL_RELATIVE = 0, PPE_TOL_ABSOLUTE = 1 };   /* ||b-Ax||2 <= tol*||b||2 or <= tol */
 
+/* Form of the plain PCG iteration (the same iterates in exact arithmetic):
+ * SINGLE_REDUCTION regroups the recurrences so that one launch and one
+ * grid-wide reduction make an iteration (p.Ap from an exact expansion in
+ * sums of the previous launch); TWO_PHASE is the textbook order with two
+ * reductions per iteration. The hybrid solve always uses TWO_PHASE. */
+enum { PPE_PCG_SINGLE_REDUCTION = 0, PPE_PCG_TWO_PHASE = 1 };
+
 /* Error-direction provider of the hybrid solve. NET is the DeepONet; the others
  * replace it for testing the controller and its fallback. */
 enum {
@@ -70,6 +77,7 @@ enum {
 /* Grid description (Sec. 2.5 / Table 1: a stretched Cartesian grid).
  * xc, yc: host, [nx], [ny] strictly increasing cell centres.
  * hx, hy: host, [nx], [ny] cell widths > 0 (face length of the other axis).
+ * At most 2^28 cells (16384^2) per grid.
  * mask:   host [ny*nx] or NULL, 1 = solid. The obstacle does not enter M (the
  *         immersed boundary acts through the source); it is an input channel
  *         of the network. */
@@ -93,6 +101,7 @@ typedef struct {
   int32_t use_graph;       /* 1 (default) = replay iteration chunks as a HIP graph, 0 = eager launches */
   int32_t chunk;           /* iterations per polled chunk (0 = default 64) */
   int32_t zero_x0;         /* 1 = ignore x on entry and start from x0 = 0 */
+  int32_t variant;         /* plain solve: PPE_PCG_SINGLE_REDUCTION (default) or PPE_PCG_TWO_PHASE */
 } ppe_solve_opts;
 
 typedef struct {
@@ -180,9 +189,11 @@ ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* proble
                               hipStream_t s);
 
 /* ---- measurement ---- */
-/* Average duration in ms of one phase-A launch (ms_out[0]) and one phase-B
- * launch (ms_out[1]) of the fused PCG iteration on nb systems: after a solve
- * setup on (f, x), `reps` iterations run eagerly on stream s, as in a solve,
+/* Average kernel durations in ms of the PCG iteration on nb systems, for the
+ * form opts->variant selects: TWO_PHASE gives one phase-A launch in ms_out[0]
+ * and one phase-B launch in ms_out[1]; SINGLE_REDUCTION gives its one launch
+ * per iteration in ms_out[0] and 0 in ms_out[1]. After a solve setup on
+ * (f, x), `reps` iterations run eagerly on stream s, as in a solve,
  * each launch carrying its own start/stop HIP events (hipExtLaunchKernelGGL),
  * so the elapsed times are kernel execution times. x is used as the
  * initial guess and its content is left unspecified. ms_out: host [2]. */

@@ -55,8 +55,8 @@ static void free_ws(SolveWs& w) {
   w = SolveWs{};
 }
 
-// Workspace for nb solves: 5 FP32 vectors per solve (x_c, r, p0, p1, e), the
-// partial-sum arrays, states and polling flags.
+// Workspace for nb solves: 6 FP32 vectors per solve (x_c, r, p0, p1, e, r1),
+// the partial-sum arrays (16 per workgroup and solve), states and polling flags.
 ppe_status ensure_ws(ppe_problem* p, int nb) {
   SolveWs& w = p->ws;
   if (w.nb >= nb && w.vec) return PPE_OK;
@@ -64,8 +64,8 @@ ppe_status ensure_ws(ppe_problem* p, int nb) {
   const int64_t N = (int64_t)p->nx * p->ny;
   const dim3 g = stencil_grid(p->coef, 2, 1);  // the smallest tile height has the most workgroups
   w.Pmax = (int)(g.x * g.y);
-  w.vec = (float*)dev_alloc(sizeof(float) * 5 * N * nb);
-  w.part = (double*)dev_alloc(sizeof(double) * 6 * (size_t)w.Pmax * nb);
+  w.vec = (float*)dev_alloc(sizeof(float) * 6 * N * nb);
+  w.part = (double*)dev_alloc(sizeof(double) * 16 * (size_t)w.Pmax * nb);
   w.st = (SolveState*)dev_alloc(sizeof(SolveState) * nb);
   w.flags = (int32_t*)dev_alloc(sizeof(int32_t) * nb);
   w.call = (CallArgs*)dev_alloc(sizeof(CallArgs));
@@ -105,6 +105,8 @@ PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int
   a.partB = w.part + (size_t)a.P * nb;
   a.partD = w.part + (size_t)3 * a.P * nb;
   a.e = w.vec + 4 * N;
+  a.r1 = w.vec + 5 * N;
+  a.part1 = w.part + (size_t)6 * a.P * nb;
   a.st = w.st;
   a.flags = w.flags;
   a.call = w.call;
@@ -124,6 +126,8 @@ int default_rows(const ppe_problem* p, int nb) {
   return 2;
 }
 
+bool use_single_reduction(const ppe_solve_opts& o) { return o.variant != PPE_PCG_TWO_PHASE; }
+
 int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o) {
   const int r = o.rows_per_wave;
   if (r == 2 || r == 4 || r == 8 || r == 16) return r;
@@ -137,12 +141,20 @@ int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o) {
       return set_error(PPE_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
   } while (0)
 
-// Capture (once per workspace shape) a graph of `chunk` CG iteration pairs
-// with alternating parity.
-static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int chunk) {
+// One chunk of `chunk` iterations with alternating parity: pairs of phase
+// launches (two-phase iteration) or single launches (single reduction).
+static void launch_chunk(const PcgArgs& a, int nb, int chunk, bool single, hipStream_t s) {
+  for (int k = 0; k < chunk; ++k) {
+    if (single) launch_pcg1_step(a, nb, k & 1, s);
+    else launch_pcg_pair(a, nb, k & 1, 0, 0, s);
+  }
+}
+
+// Capture (once per workspace shape and iteration form) the chunk as a graph.
+static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int chunk, bool single) {
   SolveWs& w = p->ws;
-  const int key[4] = {nb, a.R, a.jacobi, chunk};
-  if (w.exec && std::equal(key, key + 4, w.exec_key)) return PPE_OK;
+  const int key[5] = {nb, a.R, a.jacobi, chunk, (int)single};
+  if (w.exec && std::equal(key, key + 5, w.exec_key)) return PPE_OK;
   if (w.exec) {
     (void)hipGraphExecDestroy(w.exec);
     w.exec = nullptr;
@@ -150,7 +162,7 @@ static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int 
   if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < chunk; ++k) launch_pcg_pair(a, nb, k & 1, 0, 0, p->cap_stream);
+  launch_chunk(a, nb, chunk, single, p->cap_stream);
   hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
   if (e != hipSuccess) return set_error(PPE_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(&w.exec, graph, nullptr, nullptr, 0);
@@ -159,28 +171,30 @@ static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int 
     w.exec = nullptr;
     return set_error(PPE_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
   }
-  std::copy(key, key + 4, w.exec_key);
+  std::copy(key, key + 5, w.exec_key);
   return PPE_OK;
 }
 
 // Replays iteration chunks until every solve of the batch has finished. The
 // next chunk is enqueued before the previous chunk's flags are inspected, so
 // the device never waits for the host.
-ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o,
-                          hipStream_t s) {
+ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s,
+                          bool single) {
   SolveWs& w = p->ws;
   int chunk = o.chunk > 0 ? o.chunk : 64;
   chunk += chunk & 1;
   if (o.use_graph) {
-    ppe_status st = get_chunk_graph(p, a, nb, chunk);
+    ppe_status st = get_chunk_graph(p, a, nb, chunk, single);
     if (st != PPE_OK) return st;
   }
-  const int64_t max_chunks = (2 * (int64_t)o.max_iter + 4) / chunk + 2;
+  // Launches a solve can take: a CG iteration is one pair (two-phase) or one
+  // launch (single reduction), a reliable update one pair or two launches.
+  const int64_t max_chunks = (3 * (int64_t)o.max_iter + 8) / chunk + 2;
   for (int64_t c = 0; c < max_chunks; ++c) {
     if (o.use_graph) {
       HIPCHK(hipGraphLaunch(w.exec, s));
     } else {
-      for (int k = 0; k < chunk; ++k) launch_pcg_pair(a, nb, k & 1, 0, 0, s);
+      launch_chunk(a, nb, chunk, single, s);
       HIPCHK(hipGetLastError());
     }
     HIPCHK(hipMemcpyAsync(w.h_flags + (c & 1) * nb, w.flags, sizeof(int32_t) * nb,
@@ -256,10 +270,12 @@ ppe_status solve_plain_impl(ppe_problem* p, int32_t nb, const float* f, double* 
   if (st != PPE_OK) return st;
   const int R = rows_of(p, nb, o);
   const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  const bool single = use_single_reduction(o);
   launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
-  launch_pcg_setup(a, nb, s);
+  if (single) launch_pcg1_setup(a, nb, s);
+  else launch_pcg_setup(a, nb, s);
   HIPCHK(hipGetLastError());
-  st = run_pcg_chunks(p, a, nb, o, s);
+  st = run_pcg_chunks(p, a, nb, o, s, single);
   if (st != PPE_OK) return st;
   launch_pcg_finish(a, nb, s);
   HIPCHK(hipGetLastError());
@@ -291,6 +307,7 @@ void ppe_solve_opts_default(ppe_solve_opts* o) {
   o->rows_per_wave = 0;
   o->use_graph = 1;
   o->chunk = 0;
+  o->variant = PPE_PCG_SINGLE_REDUCTION;
 }
 
 ppe_status ppe_problem_create(const ppe_grid_desc* g, ppe_problem** out) {
@@ -298,7 +315,7 @@ ppe_status ppe_problem_create(const ppe_grid_desc* g, ppe_problem** out) {
   *out = nullptr;
   const int nx = g->nx, ny = g->ny;
   if (nx < 2 || ny < 2) return set_error(PPE_ERR_SHAPE, "nx, ny must be >= 2 (got %d x %d)", nx, ny);
-  if ((int64_t)nx * ny > ((int64_t)1 << 30)) return set_error(PPE_ERR_SHAPE, "grid too large");
+  if ((int64_t)nx * ny > ((int64_t)1 << 28)) return set_error(PPE_ERR_SHAPE, "grid too large (at most 2^28 cells)");
   if (!g->xc || !g->yc || !g->hx || !g->hy) return set_error(PPE_ERR_INVALID_ARG, "NULL coordinate array");
   for (int i = 0; i < nx; ++i) {
     if (!std::isfinite(g->xc[i]) || !(g->hx[i] > 0.0) || !std::isfinite(g->hx[i]))
@@ -374,15 +391,23 @@ ppe_status ppe_profile_pcg(ppe_problem* p, int32_t nb, const float* f, double* x
   if (st != PPE_OK) return st;
   const int R = rows_of(p, nb, o);
   const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  const bool single = use_single_reduction(o);
   launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
-  launch_pcg_setup(a, nb, s);
-  // The real iteration sequence (A, B alternating with their parities); each
-  // launch carries its own start/stop events (recorded by its dispatch).
+  if (single) launch_pcg1_setup(a, nb, s);
+  else launch_pcg_setup(a, nb, s);
+  // The real iteration sequence (alternating parities); each launch carries
+  // its own start/stop events (recorded by its dispatch). The single-reduction
+  // form has one launch per iteration, reported in ms_out[0].
   std::vector<hipEvent_t> ev(4 * reps);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   for (int k = 0; k < reps; ++k) {
-    launch_pcg_phase_timed(a, nb, k & 1, 0, s, ev[4 * k], ev[4 * k + 1]);
-    launch_pcg_phase_timed(a, nb, k & 1, 1, s, ev[4 * k + 2], ev[4 * k + 3]);
+    if (single) {
+      launch_pcg1_step_timed(a, nb, k & 1, s, ev[4 * k], ev[4 * k + 1]);
+      launch_pcg1_step_timed(a, nb, (k & 1) ^ 1, s, ev[4 * k + 2], ev[4 * k + 3]);
+    } else {
+      launch_pcg_phase_timed(a, nb, k & 1, 0, s, ev[4 * k], ev[4 * k + 1]);
+      launch_pcg_phase_timed(a, nb, k & 1, 1, s, ev[4 * k + 2], ev[4 * k + 3]);
+    }
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventSynchronize(ev[4 * reps - 1]));
@@ -394,8 +419,13 @@ ppe_status ppe_profile_pcg(ppe_problem* p, int32_t nb, const float* f, double* x
     ta += t1;
     tb += t2;
   }
-  ms_out[0] = ta / reps;
-  ms_out[1] = tb / reps;
+  if (single) {
+    ms_out[0] = (ta + tb) / (2.0 * reps);
+    ms_out[1] = 0.0;
+  } else {
+    ms_out[0] = ta / reps;
+    ms_out[1] = tb / reps;
+  }
   for (auto& e : ev) (void)hipEventDestroy(e);
   return PPE_OK;
 }

@@ -23,7 +23,7 @@ struct SolveWs {
   SolveState* h_state = nullptr;  // pinned [nb]
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipGraphExec_t exec = nullptr;
-  int exec_key[4] = {0, 0, 0, 0};
+  int exec_key[5] = {0, 0, 0, 0, 0};
 };
 
 struct NetCache;  // per (grid, net) constants of the network (net_internal.hpp)
@@ -54,7 +54,9 @@ void problem_release(ppe_problem* p);
 ppe_status ensure_ws(ppe_problem* p, int nb);
 PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int tol_kind, int zero_x0);
 int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o);
-ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s);
+ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s,
+                          bool single);
+bool use_single_reduction(const ppe_solve_opts& o);
 ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s, bool hybrid);
 ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, const void* x,
                             const ppe_solve_opts* opts);

@@ -16,7 +16,7 @@ constexpr int kBlock = kWave * kWaves;
 // gx[k] = 1/(xc[k] - xc[k-1]) for the interior x-face k, 0 at the walls.
 // The arrays are zero-padded in memory: indices in [-kPadX, n + kPadX) for
 // hx/gx and [-kPadY0, n + kPadY1) for hy/gy are valid and read 0 off the grid.
-constexpr int kPadX = 64, kPadY0 = 32, kPadY1 = 128;
+constexpr int kPadX = 128, kPadY0 = 32, kPadY1 = 128;
 struct Coef {
   int nx, ny;
   const float *hx, *hy, *gx, *gy;          // [nx], [ny], [nx+1], [ny+1]
@@ -51,7 +51,9 @@ struct SolveState {
   int32_t pad[2];
 };
 
-enum : int32_t { MODE_CG = 0, MODE_TRUE = 1 };
+// MODE_FLUSH is used by the single-reduction iteration only (x += x_c, then
+// a MODE_TRUE launch).
+enum : int32_t { MODE_CG = 0, MODE_TRUE = 1, MODE_FLUSH = 2 };
 enum : int32_t { DONE_NO = 0, DONE_CONV = 1, DONE_MAXIT = 2, DONE_NONFINITE = 3 };
 
 // Per-call pointers kept in device memory so that a captured graph can be

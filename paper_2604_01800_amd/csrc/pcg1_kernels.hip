@@ -1,0 +1,508 @@
+// Single-reduction Jacobi-PCG: one launch and one grid-wide reduction per CG
+// iteration (HIP, gfx950).
+//
+// The textbook PCG recurrences (Saad, Alg. 9.1; D = diag(A)) are regrouped so
+// that a launch needs only the scalars reduced at the end of the launch
+// before it. Given r_k, p_{k-1} and the sums over the grid
+//   gamma_k = r_k.z_k,  delta_k = z_k.A z_k,  zeta_k = z_k.A p_{k-1},
+//   pi_k = p_{k-1}.A p_{k-1}        (z = D^-1 r),
+// one launch computes
+//   beta_{k-1} = gamma_k / gamma_{k-1}                    (0 after a restart)
+//   p_k        = z_k + beta_{k-1} p_{k-1}
+//   p_k.A p_k  = delta_k + 2 beta zeta_k + beta^2 pi_k    (exact expansion)
+//   alpha_k    = gamma_k / p_k.A p_k
+//   x_c += alpha_k p_k,  s = A p_k,  r_{k+1} = r_k - alpha_k s
+// and the partial sums of gamma, delta, zeta, pi and |r|^2 for k + 1. The
+// expansion of p.Ap is an identity of bilinear forms, not a consequence of
+// orthogonality, so the iterates equal the two-reduction form's in exact
+// arithmetic. Each workgroup recomputes p on a two-cell halo and s, r_{k+1},
+// z_{k+1} on a one-cell halo of its tile, which removes the second grid-wide
+// dependency of the iteration. HBM traffic per cell: read r, p, x_c and
+// write them (24 B); r and p alternate between two buffers by launch parity
+// because neighbouring workgroups read their halos.
+//
+// Reliable updates take two launches: FLUSH adds x_c into the FP64 solution,
+// TRUE recomputes r = b - A x in FP64 together with the five sums (ζ and π
+// from the kept direction p). Convergence is declared only on the FP64 true
+// residual. Every launch reads the state slots of the other parity, so no
+// workgroup reads what the same launch writes.
+#include <hip/hip_ext.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "stencil.hpp"
+
+namespace ppe {
+
+constexpr int kSums = 5;  // gamma, delta, zeta, pi, |r|^2
+
+__device__ __forceinline__ double* sums_of(const PcgArgs& a, int par, int s) {
+  return a.part1 + ((size_t)par * gridDim.z + s) * kSums * a.P;
+}
+
+// Fixed-order reduction of the five partial arrays ([5][P]); every workgroup
+// obtains the same bits.
+__device__ __forceinline__ void reduce5(const double* __restrict__ part, int P, double* lds, double (&out)[kSums]) {
+  double v[kSums];
+#pragma unroll
+  for (int m = 0; m < kSums; ++m) v[m] = 0.0;
+  for (int k = threadIdx.x; k < P; k += kBlock) {
+#pragma unroll
+    for (int m = 0; m < kSums; ++m) v[m] += part[(size_t)m * P + k];
+  }
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int m = 0; m < kSums; ++m) v[m] = wave_sum(v[m]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < kSums; ++m) lds[m * kWaves + w] = v[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kSums; ++m)
+    out[m] = ((lds[m * kWaves] + lds[m * kWaves + 1]) + lds[m * kWaves + 2]) + lds[m * kWaves + 3];
+}
+
+// Workgroup sums of five values, stored by thread 0 into part ([5][P]).
+__device__ __forceinline__ void store5(double (&v)[kSums], double* lds, double* __restrict__ part, int P) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int m = 0; m < kSums; ++m) v[m] = wave_sum(v[m]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < kSums; ++m) lds[m * kWaves + w] = v[m];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < kSums; ++m)
+      part[(size_t)m * P + blockIdx.x] =
+          ((lds[m * kWaves] + lds[m * kWaves + 1]) + lds[m * kWaves + 2]) + lds[m * kWaves + 3];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T diag_of(T hyj, T gs, T gn, T hx, T gw, T ge) {
+  return hyj * (gw + ge) + hx * (gs + gn);
+}
+
+// Jacobi preconditioner of this iteration form: z = r * dinv with dinv the
+// hardware reciprocal of the diagonal (one rounding of 1/D, the same value in
+// every launch, so the preconditioner is a fixed diagonal matrix). Cells off
+// the grid have D = 0 and r = 0, and get z = 0.
+__device__ __forceinline__ float inv_diag(float hyj, float gs, float gn, float hx, float gw, float ge) {
+  return __builtin_amdgcn_rcpf(fmaxf(diag_of(hyj, gs, gn, hx, gw, ge), 1e-30f));
+}
+
+// Second halo column: lane 0 takes column i0 - 2, lane 63 column i0 + 65.
+struct Halo2 {
+  int i;
+  bool ok;
+};
+
+__device__ __forceinline__ Halo2 halo2(int nx, const TileXY& tl) {
+  const int lane = threadIdx.x & (kWave - 1);
+  Halo2 h;
+  h.i = (lane == 0) ? tl.i0 - 2 : tl.i0 + kWave + 1;
+  h.ok = tl.valid && (lane == 0 || lane == kWave - 1) && h.i >= 0 && h.i < nx;
+  if (!h.ok) h.i = tl.i0;  // any readable column; its values are not used
+  return h;
+}
+
+// FP64 true residual r = b - A x at (i, j) with b = hx hy f - mean(b); x
+// holds the centre and its four neighbours.
+__device__ __forceinline__ double true_res(const Coef& c, int i, int j, double xc_, double xe, double xw, double xn,
+                                           double xs, float f, double bmean) {
+  const double hyj = c.hy64[j];
+  const double Ax = stencil5(xc_, xe, xw, xn, xs, hyj, c.gy64[j], c.gy64[j + 1], c.hx64[i], c.gx64[i],
+                             c.gx64[i + 1]);
+  return (c.hx64[i] * hyj * (double)f - bmean) - Ax;
+}
+
+template <int R, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_pcg1(PcgArgs a, int par) {
+  __shared__ double lds[kSums * kWaves];
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  SolveState* st = a.st + s;
+  const int P = a.P, pm = par ^ 1;
+  const size_t off = (size_t)s * a.N;
+  const float* __restrict__ rin = (pm ? a.r1 : a.r) + off;
+  float* __restrict__ rout = (par ? a.r1 : a.r) + off;
+  const float* __restrict__ pin = (pm ? a.p1 : a.p0) + off;
+  float* __restrict__ pout = (par ? a.p1 : a.p0) + off;
+  float* __restrict__ xc = a.xc + off;
+  const int lane = threadIdx.x & (kWave - 1);
+  const TileXY tl = tile_xy(nx, ny, R);
+  const ColIdx ci = col_idx(nx, tl);
+  const Halo2 h2 = halo2(nx, tl);
+  const int j0 = tl.j0;
+
+  // Tile loads of the CG step first (they do not depend on the scalars):
+  // own column rows j0-2 .. j0+R+1, first halo column rows j0-1 .. j0+R,
+  // second halo column rows j0 .. j0+R-1.
+  const uint64_t vbytes = (uint64_t)a.N * 4;
+  const auto rsr = make_rsrc(rin, vbytes), psr = make_rsrc(pin, vbytes);
+  float ro[R + 4], po[R + 4], r1[R + 2], p1[R + 2], r2[R], p2[R], xcv[R];
+#pragma unroll
+  for (int q = 0; q < R + 4; ++q) {
+    const uint32_t o = cell_off(ci.ok, j0 - 2 + q, ny, nx, ci.i);
+    ro[q] = bload(rsr, o);
+    po[q] = bload(psr, o);
+  }
+#pragma unroll
+  for (int q = 0; q < R + 2; ++q) {
+    const uint32_t o = cell_off(ci.hok, j0 - 1 + q, ny, nx, ci.ih);
+    r1[q] = bload(rsr, o);
+    p1[q] = bload(psr, o);
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const uint32_t o = cell_off(h2.ok, j0 + q, ny, nx, h2.i);
+    r2[q] = bload(rsr, o);
+    p2[q] = bload(psr, o);
+  }
+  load_rows_own<R>(make_rsrc(xc, vbytes), nx, ny, j0, ci, xcv);
+  // Row coefficients of rows j0-2 .. j0+R+1 (faces j0-2 .. j0+R+2); padded arrays.
+  float hy[R + 4], gy[R + 5];
+#pragma unroll
+  for (int q = 0; q < R + 4; ++q) hy[q] = a.c.hy[j0 - 2 + q];
+#pragma unroll
+  for (int q = 0; q < R + 5; ++q) gy[q] = a.c.gy[j0 - 2 + q];
+  const ColCoef<float> k = load_cols<float>(a.c.hx, a.c.gx, ci);
+  float hx2 = a.c.hx[h2.i], gw2 = a.c.gx[h2.i], ge2 = a.c.gx[h2.i + 1];
+  if (!h2.ok) hx2 = gw2 = ge2 = 0.f;
+
+  // State of the previous launch (never written by this launch).
+  const int dprev = st->dflag[pm];
+  const int pmode = st->mode[pm];
+  const int max_iter = a.call->max_iter;
+  const double delta2 = a.call->delta2;
+  const int it = st->it[pm], nru = st->n_ru[pm], itcg = st->it_cg[pm];
+  const int restart = st->restart[pm];
+  const double gam_prev = st->rho[pm], thr2 = st->thr2;
+  double rr_ru = st->rr_ru[pm];
+  const bool leader = is_first_block();
+  double sum[kSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (pmode != MODE_FLUSH) reduce5(sums_of(a, pm, s), P, lds, sum);
+  if (dprev) {
+    if (leader) st->dflag[par] = dprev;
+    return;
+  }
+
+  // What this launch does.
+  int todo = MODE_CG, done = DONE_NO, rst_next = 0;
+  double alpha = 0.0, beta = 0.0;
+  if (pmode == MODE_FLUSH) {
+    todo = MODE_TRUE;
+  } else {
+    const double gam = sum[0], del = sum[1], zet = sum[2], pip = sum[3], rr = sum[4];
+    bool flush;
+    bool rst = false;
+    if (pmode == MODE_TRUE) {
+      rr_ru = rr;
+      if (!isfinite(rr)) done = DONE_NONFINITE;
+      else if (rr <= thr2) done = DONE_CONV;
+      else if (it >= max_iter) done = DONE_MAXIT;
+      flush = false;
+      rst = restart;
+    } else {
+      flush = !isfinite(rr) || rr <= thr2 || rr <= delta2 * rr_ru || it >= max_iter;
+    }
+    if (done) {
+      if (leader) {
+        st->rr_final = rr;
+        st->it_final = it;
+        st->nru_final = nru;
+        st->itcg_final = itcg;
+        st->done = done;
+        st->dflag[par] = done;
+        a.flags[s] = done;
+      }
+      return;
+    }
+    if (!flush) {
+      beta = rst ? 0.0 : gam / gam_prev;
+      if (!isfinite(beta)) beta = 0.0;
+      const double pap = del + 2.0 * beta * zet + beta * beta * pip;
+      alpha = gam / pap;
+      if (!(pap > 0.0) || !isfinite(alpha)) {
+        flush = true;  // breakdown: recompute the residual and restart
+        rst_next = 1;
+      }
+    }
+    if (flush) todo = MODE_FLUSH;
+    if (leader && todo == MODE_CG) {
+      st->mode[par] = MODE_CG;
+      st->it[par] = it + 1;
+      st->it_cg[par] = itcg + 1;
+      st->n_ru[par] = nru;
+      st->rho[par] = gam;
+      st->rr_ru[par] = rr_ru;
+      st->rr_last[par] = rr;
+      st->restart[par] = 0;
+      st->alpha[par] = alpha;
+      st->dflag[par] = DONE_NO;
+    }
+  }
+
+  if (todo == MODE_FLUSH) {
+    // Reliable update, part 1: x += x_c in FP64, x_c = 0, p carried over.
+    const auto xsr = make_rsrc(a.call->x + off, (uint64_t)a.N * 8);
+    const auto xcs = make_rsrc(xc, vbytes), pso = make_rsrc(pout, vbytes);
+    double xv[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) xv[q] = bload64(xsr, cell_off8(ci.ok, j0 + q, ny, nx, ci.i));
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      bstore64(xsr, cell_off8(ci.ok, j0 + q, ny, nx, ci.i), xv[q] + (double)xcv[q]);
+      const uint32_t o = cell_off(ci.ok, j0 + q, ny, nx, ci.i);
+      bstore(xcs, o, 0.f);
+      bstore(pso, o, po[q + 2]);
+    }
+    if (leader) {
+      st->mode[par] = MODE_FLUSH;
+      st->it[par] = it;
+      st->it_cg[par] = itcg;
+      st->n_ru[par] = nru + 1;
+      st->rho[par] = gam_prev;
+      st->rr_ru[par] = rr_ru;
+      st->restart[par] = rst_next;
+      st->dflag[par] = DONE_NO;
+    }
+    return;
+  }
+
+  double acc[kSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (todo == MODE_TRUE) {
+    // Reliable update, part 2: r = b - A x in FP64 on the tile and its
+    // one-cell halo, z = D^-1 r, and the five sums with the kept direction p.
+    const auto xsr = make_rsrc(a.call->x + off, (uint64_t)a.N * 8);
+    const auto fsr = make_rsrc(a.call->f + off, vbytes);
+    const double bmean = st->bmean;
+    // x: own column rows j0-2 .. j0+R+1, first halo rows j0-2 .. j0+R+1,
+    // second halo rows j0 .. j0+R-1; f: own rows j0-1 .. j0+R, first halo
+    // rows j0 .. j0+R-1. Off the grid the loads return 0.
+    double xo[R + 4], x1[R + 4], x2[R];
+    float fo[R + 2], f1[R];
+#pragma unroll
+    for (int q = 0; q < R + 4; ++q) {
+      xo[q] = bload64(xsr, cell_off8(ci.ok, j0 - 2 + q, ny, nx, ci.i));
+      x1[q] = bload64(xsr, cell_off8(ci.hok, j0 - 2 + q, ny, nx, ci.ih));
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) x2[q] = bload64(xsr, cell_off8(h2.ok, j0 + q, ny, nx, h2.i));
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) fo[q] = bload(fsr, cell_off(ci.ok, j0 - 1 + q, ny, nx, ci.i));
+#pragma unroll
+    for (int q = 0; q < R; ++q) f1[q] = bload(fsr, cell_off(ci.hok, j0 + q, ny, nx, ci.ih));
+    float rf[R + 2], rfh[R];
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) {  // own column, row j0-1+q
+      const int j = j0 - 1 + q;
+      double xe, xw;
+      east_west(xo[q + 1], x1[q + 1], xe, xw);
+      const bool own_ok = ci.ok && j >= 0 && j < ny;
+      const double rv = true_res(a.c, ci.i, j, xo[q + 1], xe, xw, xo[q + 2], xo[q], fo[q], bmean);
+      rf[q] = own_ok ? (float)rv : 0.f;
+      if (q >= 1 && q <= R) acc[4] += own_ok ? rv * rv : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {  // first halo column, row j0+q
+      const int j = j0 + q;
+      const double he = (lane == 0) ? xo[q + 2] : x2[q], hw = (lane == 0) ? x2[q] : xo[q + 2];
+      const double rv = true_res(a.c, ci.ih, j, x1[q + 2], he, hw, x1[q + 3], x1[q + 1], f1[q], bmean);
+      rfh[q] = (ci.hok && j < ny) ? (float)rv : 0.f;
+    }
+    float z[R + 2], zh[R];
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) {
+      z[q] = rf[q];
+      if (JAC) z[q] = rf[q] * inv_diag(hy[q + 1], gy[q + 1], gy[q + 2], k.hx, k.gw, k.ge);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      zh[q] = rfh[q];
+      if (JAC) zh[q] = rfh[q] * inv_diag(hy[q + 2], gy[q + 2], gy[q + 3], k.hxh, k.gwh, k.geh);
+    }
+    const auto rso = make_rsrc(rout, vbytes), pso = make_rsrc(pout, vbytes);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int j = j0 + q;
+      float ze, zw, pe, pw;
+      east_west(z[q + 1], zh[q], ze, zw);
+      east_west(po[q + 2], p1[q + 1], pe, pw);
+      const float Az = stencil5(z[q + 1], ze, zw, z[q + 2], z[q], hy[q + 2], gy[q + 2], gy[q + 3], k.hx, k.gw, k.ge);
+      const float sp = stencil5(po[q + 2], pe, pw, po[q + 3], po[q + 1], hy[q + 2], gy[q + 2], gy[q + 3], k.hx, k.gw,
+                                k.ge);
+      const uint32_t o = cell_off(ci.ok, j, ny, nx, ci.i);
+      bstore(rso, o, rf[q + 1]);
+      bstore(pso, o, po[q + 2]);
+      // Off the grid every value and coefficient is 0, so the products are 0.
+      acc[0] += (double)rf[q + 1] * (double)z[q + 1];
+      acc[1] += (double)z[q + 1] * (double)Az;
+      acc[2] += (double)z[q + 1] * (double)sp;
+      acc[3] += (double)po[q + 2] * (double)sp;
+    }
+    if (leader) {
+      st->mode[par] = MODE_TRUE;
+      st->it[par] = it;
+      st->it_cg[par] = itcg;
+      st->n_ru[par] = nru;
+      st->rho[par] = gam_prev;
+      st->rr_ru[par] = rr_ru;
+      st->restart[par] = restart;
+      st->dflag[par] = DONE_NO;
+    }
+  } else {
+    // CG step. z and p on the two-cell halo ...
+    const float bet = (float)beta;
+    const bool rst = beta == 0.0;
+    float pv[R + 4], pv1[R + 2], pv2[R], dv[R + 4], dv1[R + 2];
+#pragma unroll
+    for (int q = 0; q < R + 4; ++q) {
+      dv[q] = JAC ? inv_diag(hy[q], gy[q], gy[q + 1], k.hx, k.gw, k.ge) : 1.f;
+      const float zv = ro[q] * dv[q];
+      pv[q] = rst ? zv : zv + bet * po[q];
+    }
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) {
+      dv1[q] = JAC ? inv_diag(hy[q + 1], gy[q + 1], gy[q + 2], k.hxh, k.gwh, k.geh) : 1.f;
+      const float zv = r1[q] * dv1[q];
+      pv1[q] = rst ? zv : zv + bet * p1[q];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const float d2 = JAC ? inv_diag(hy[q + 2], gy[q + 2], gy[q + 3], hx2, gw2, ge2) : 1.f;
+      const float zv = r2[q] * d2;
+      pv2[q] = rst ? zv : zv + bet * p2[q];
+    }
+    // ... s = A p, r_{k+1} = r_k - alpha s and z_{k+1} on the one-cell halo ...
+    const float alf = (float)alpha;
+    float sv[R + 2], rn[R + 2], zn[R + 2], rn1[R], zn1[R];
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) {  // own column, row j0-1+q
+      float pe, pw;
+      east_west(pv[q + 1], pv1[q], pe, pw);
+      sv[q] = stencil5(pv[q + 1], pe, pw, pv[q + 2], pv[q], hy[q + 1], gy[q + 1], gy[q + 2], k.hx, k.gw, k.ge);
+      rn[q] = ro[q + 1] - alf * sv[q];
+      zn[q] = rn[q] * dv[q + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {  // first halo column, row j0+q
+      const float pe = (lane == 0) ? pv[q + 2] : pv2[q];
+      const float pw = (lane == 0) ? pv2[q] : pv[q + 2];
+      const float s1 = stencil5(pv1[q + 1], pe, pw, pv1[q + 2], pv1[q], hy[q + 2], gy[q + 2], gy[q + 3], k.hxh,
+                                k.gwh, k.geh);
+      rn1[q] = r1[q + 1] - alf * s1;
+      zn1[q] = rn1[q] * dv1[q + 1];
+    }
+    // ... then A z_{k+1} on the tile, the stores and the sums.
+    const auto rso = make_rsrc(rout, vbytes), pso = make_rsrc(pout, vbytes), xso = make_rsrc(xc, vbytes);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int j = j0 + q;
+      float ze, zw;
+      east_west(zn[q + 1], zn1[q], ze, zw);
+      const float Az = stencil5(zn[q + 1], ze, zw, zn[q + 2], zn[q], hy[q + 2], gy[q + 2], gy[q + 3], k.hx, k.gw,
+                                k.ge);
+      const float pk = pv[q + 2];
+      const uint32_t o = cell_off(ci.ok, j, ny, nx, ci.i);
+      bstore(rso, o, rn[q + 1]);
+      bstore(pso, o, pk);
+      bstore(xso, o, xcv[q] + alf * pk);
+      // Off the grid every value and coefficient is 0, so the products are 0.
+      acc[0] += (double)rn[q + 1] * (double)zn[q + 1];
+      acc[1] += (double)zn[q + 1] * (double)Az;
+      acc[2] += (double)zn[q + 1] * (double)sv[q + 1];
+      acc[3] += (double)pk * (double)sv[q + 1];
+      acc[4] += (double)rn[q + 1] * (double)rn[q + 1];
+    }
+  }
+  store5(acc, lds, sums_of(a, par, s), P);
+}
+
+// Set-up after the right-hand side: zero x_c and both p buffers and leave the
+// state as after a FLUSH of parity 0, so that the first launch (parity 1)
+// computes the true residual of the initial guess with p = 0 and a restart.
+__global__ __launch_bounds__(kBlock) void k_pcg1_init(PcgArgs a) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+  SolveState* st = a.st + s;
+  const double bb = reduce_partials(a.partA + (size_t)s * a.P, a.P, lds);
+  const bool bad = st->nonfinite;
+  if (is_first_block()) {
+    st->bnorm2 = bb;
+    st->thr2 = a.tol_kind == 1 ? a.tol * a.tol : a.tol * a.tol * bb;
+    st->mode[0] = MODE_FLUSH;
+    st->restart[0] = 1;
+    st->it[0] = 0;
+    st->it_cg[0] = 0;
+    st->n_ru[0] = 0;
+    st->alpha[0] = 0.0;
+    st->rho[0] = 0.0;
+    st->rr_ru[0] = 0.0;
+    st->rr_last[0] = 0.0;
+    st->brk[0] = 0;
+    st->n_dlsm = 0;
+    st->n_rej = 0;
+    st->done = bad ? DONE_NONFINITE : DONE_NO;
+    st->dflag[0] = st->dflag[1] = bad ? DONE_NONFINITE : DONE_NO;
+    st->it_final = 0;
+    st->nru_final = 0;
+    st->itcg_final = 0;
+    st->rr_final = 0.0;
+    a.flags[s] = bad ? DONE_NONFINITE : DONE_NO;
+  }
+  const size_t off = (size_t)s * a.N;
+  const TileXY tl = tile_xy(nx, ny, a.R);
+  const int i = tl.valid ? tl.i0 + (threadIdx.x & (kWave - 1)) : nx;
+  if (i < nx)
+    for (int q = 0; q < a.R; ++q) {
+      const int j = tl.j0 + q;
+      if (j >= ny) break;
+      const size_t kk = off + (size_t)j * nx + i;
+      a.xc[kk] = 0.f;
+      a.p0[kk] = 0.f;
+      a.p1[kk] = 0.f;
+    }
+}
+
+#define PPE1_DISPATCH(R, JAC, ...)                                                   \
+  do {                                                                               \
+    if (JAC) {                                                                       \
+      switch (R) {                                                                   \
+        case 2: { constexpr int RR = 2; constexpr bool JJ = true; __VA_ARGS__; } break;  \
+        case 4: { constexpr int RR = 4; constexpr bool JJ = true; __VA_ARGS__; } break;  \
+        case 8: { constexpr int RR = 8; constexpr bool JJ = true; __VA_ARGS__; } break;  \
+        default: { constexpr int RR = 16; constexpr bool JJ = true; __VA_ARGS__; } break; \
+      }                                                                              \
+    } else {                                                                         \
+      switch (R) {                                                                   \
+        case 2: { constexpr int RR = 2; constexpr bool JJ = false; __VA_ARGS__; } break;  \
+        case 4: { constexpr int RR = 4; constexpr bool JJ = false; __VA_ARGS__; } break;  \
+        case 8: { constexpr int RR = 8; constexpr bool JJ = false; __VA_ARGS__; } break;  \
+        default: { constexpr int RR = 16; constexpr bool JJ = false; __VA_ARGS__; } break; \
+      }                                                                              \
+    }                                                                                \
+  } while (0)
+
+void launch_pcg1_setup(const PcgArgs& a, int nb, hipStream_t s) {
+  const dim3 g = stencil_grid(a.c, a.R, nb);
+  launch_rhs(a, nb, s);
+  k_pcg1_init<<<g, kBlock, 0, s>>>(a);
+  launch_pcg1_step(a, nb, 1, s);
+}
+
+void launch_pcg1_step(const PcgArgs& a, int nb, int par, hipStream_t s) {
+  const dim3 g = stencil_grid(a.c, a.R, nb);
+  PPE1_DISPATCH(a.R, a.jacobi, k_pcg1<RR, JJ><<<g, kBlock, 0, s>>>(a, par));
+}
+
+void launch_pcg1_step_timed(const PcgArgs& a, int nb, int par, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 g = stencil_grid(a.c, a.R, nb);
+  PPE1_DISPATCH(a.R, a.jacobi, hipExtLaunchKernelGGL(k_pcg1<RR, JJ>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par));
+}
+
+}  // namespace ppe

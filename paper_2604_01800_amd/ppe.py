@@ -20,6 +20,7 @@ PPE_OK, PPE_NOT_CONVERGED = 0, 1
 PPE_ERR_INVALID_ARG, PPE_ERR_SHAPE, PPE_ERR_UNSUPPORTED, PPE_ERR_HIP, PPE_ERR_NONFINITE = -1, -2, -3, -4, -5
 PPE_PC_NONE, PPE_PC_JACOBI = 0, 1
 PPE_TOL_RELATIVE, PPE_TOL_ABSOLUTE = 0, 1
+PPE_PCG_SINGLE_REDUCTION, PPE_PCG_TWO_PHASE = 0, 1
 PPE_DIR_NET, PPE_DIR_ZERO, PPE_DIR_JACOBI, PPE_DIR_NAN, PPE_DIR_ONES = 0, 1, 2, 3, 4
 
 
@@ -41,7 +42,7 @@ class ppe_solve_opts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("num_cg", ctypes.c_int32), ("num_dlsm", ctypes.c_int32),
                 ("direction", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
                 ("rows_per_wave", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("zero_x0", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("zero_x0", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 class ppe_solve_stats(ctypes.Structure):

@@ -75,13 +75,14 @@ def _solve(T, prob, f, x0=None, **kw):
 
 
 @pytest.mark.parametrize("k", [1, 2, 5, 17, 40])
-@pytest.mark.parametrize("nx,ny,beta", [(64, 64, 1.5), (70, 45, 2.0), (130, 67, 2.5)])
-def test_fixed_iterations_match_oracle(T, orc, k, nx, ny, beta):
+@pytest.mark.parametrize("nx,ny,beta", [(64, 64, 1.5), (70, 45, 2.0), (130, 67, 2.5), (65, 41, 1.2)])
+@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+def test_fixed_iterations_match_oracle(T, orc, variant, k, nx, ny, beta):
     ppe = _ppe()
     g = inputs.make_grid(nx, ny, beta)
     prob = ppe.ppe_problem_create(g)
     f = inputs.gaussian_bumps(g, 7).astype(np.float32)
-    st, stats, x = _solve(T, prob, f, tol=0.0, max_iter=k)
+    st, stats, x = _solve(T, prob, f, tol=0.0, max_iter=k, variant=variant)
     assert st == ppe.PPE_NOT_CONVERGED and stats[0]["iters_total"] == k
     b, mean = orc.rhs(g, f)
     xo, so, _ = orc.pcg(g, b, tol=0.0, max_iter=k)
@@ -92,7 +93,8 @@ def test_fixed_iterations_match_oracle(T, orc, k, nx, ny, beta):
 
 
 @pytest.mark.parametrize("seed", range(10))
-def test_c1_converged_solves(T, orc, seed):
+@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+def test_c1_converged_solves(T, orc, variant, seed):
     """64x64, beta 1.5, 8 Gaussian bumps: tol 1e-6 and 1e-8 on the FP64 true residual;
     at 1e-8 the solution matches the direct solve to 1e-6."""
     from oracle import direct
@@ -104,7 +106,7 @@ def test_c1_converged_solves(T, orc, seed):
     xs = direct.separable_solve(g, b)
     iters = {}
     for tol in (1e-6, 1e-8):
-        st, stats, x = _solve(T, prob, f, tol=tol)
+        st, stats, x = _solve(T, prob, f, tol=tol, variant=variant)
         assert st == ppe.PPE_OK
         res = np.linalg.norm(b - orc.apply(g, x[0])) / np.linalg.norm(b)
         assert res <= tol * 1.001, (res, stats)
@@ -122,28 +124,30 @@ def test_c1_converged_solves(T, orc, seed):
     assert so8.iters_total - 3 <= iters[1e-8] <= 1.3 * so8.iters_total + 3, (iters, so8.iters_total)
 
 
-def test_batched_matches_single(T, orc):
+@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+def test_batched_matches_single(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(96, 80, 2.0, 1.3)
     prob = ppe.ppe_problem_create(g)
     fs = np.stack([inputs.grf(g, s) for s in range(5)]).astype(np.float32)
-    st, stats, x = _solve(T, prob, fs, tol=1e-7)
+    st, stats, x = _solve(T, prob, fs, tol=1e-7, variant=variant)
     assert st == ppe.PPE_OK
     for s in range(5):
         b, _ = orc.rhs(g, fs[s])
         res = np.linalg.norm(b - orc.apply(g, x[s])) / np.linalg.norm(b)
         assert res <= 1e-7 * 1.001
-        st1, stats1, x1 = _solve(T, prob, fs[s], tol=1e-7)
+        st1, stats1, x1 = _solve(T, prob, fs[s], tol=1e-7, variant=variant)
         assert stats1[0]["iters_total"] == stats[s]["iters_total"]
         np.testing.assert_array_equal(x1[0], x[s])
 
 
-def test_deterministic_and_graph_equals_eager(T, orc):
+@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+def test_deterministic_and_graph_equals_eager(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(128, 96, 2.2)
     prob = ppe.ppe_problem_create(g)
     f = inputs.grf(g, 3).astype(np.float32)
-    runs = [_solve(T, prob, f, tol=1e-6, use_graph=ug) for ug in (1, 1, 0)]
+    runs = [_solve(T, prob, f, tol=1e-6, use_graph=ug, variant=variant) for ug in (1, 1, 0)]
     for st, stats, x in runs[1:]:
         np.testing.assert_array_equal(x, runs[0][2])
         assert stats[0]["iters_total"] == runs[0][1][0]["iters_total"]
@@ -151,56 +155,59 @@ def test_deterministic_and_graph_equals_eager(T, orc):
 
 
 @pytest.mark.parametrize("rows", [2, 4, 8, 16])
-def test_tile_heights_agree(T, orc, rows):
+@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+def test_tile_heights_agree(T, orc, variant, rows):
     ppe = _ppe()
     g = inputs.make_grid(150, 77, 1.7)
     prob = ppe.ppe_problem_create(g)
     f = inputs.grf(g, 4).astype(np.float32)
-    st, stats, x = _solve(T, prob, f, tol=1e-8, rows_per_wave=rows)
+    st, stats, x = _solve(T, prob, f, tol=1e-8, rows_per_wave=rows, variant=variant)
     assert st == ppe.PPE_OK
     b, _ = orc.rhs(g, f)
     assert np.linalg.norm(b - orc.apply(g, x[0])) / np.linalg.norm(b) <= 1e-8 * 1.001
 
 
-def test_vanilla_cg(T, orc):
+@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+def test_vanilla_cg(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(64, 48, 1.0)
     prob = ppe.ppe_problem_create(g)
     f = inputs.gaussian_bumps(g, 2).astype(np.float32)
-    st, stats, x = _solve(T, prob, f, tol=1e-7, precond=ppe.PPE_PC_NONE)
+    st, stats, x = _solve(T, prob, f, tol=1e-7, precond=ppe.PPE_PC_NONE, variant=variant)
     assert st == ppe.PPE_OK
     b, _ = orc.rhs(g, f)
     xo, so, _ = orc.pcg(g, b, precond=0, tol=0, max_iter=7)
-    st7, _, x7 = _solve(T, prob, f, tol=0.0, max_iter=7, precond=ppe.PPE_PC_NONE)
+    st7, _, x7 = _solve(T, prob, f, tol=0.0, max_iter=7, precond=ppe.PPE_PC_NONE, variant=variant)
     assert np.linalg.norm(x7[0] - orc.remove_mean(xo)) / np.linalg.norm(xo) <= 1e-5
 
 
-def test_edge_cases(T, orc):
+@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+def test_edge_cases(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(33, 21, 1.5)
     prob = ppe.ppe_problem_create(g)
     # zero source from a zero start: converged at once with x = 0
-    st, stats, x = _solve(T, prob, np.zeros((21, 33)))
+    st, stats, x = _solve(T, prob, np.zeros((21, 33)), variant=variant)
     assert st == ppe.PPE_OK and stats[0]["iters_total"] == 0
     assert np.all(x == 0)
     # non-finite source
     f = inputs.gaussian_bumps(g, 1).astype(np.float32)
     f[5, 7] = np.nan
-    st, stats, x = _solve(T, prob, f)
+    st, stats, x = _solve(T, prob, f, variant=variant)
     assert st == ppe.PPE_ERR_NONFINITE and stats[0]["status"] == ppe.PPE_ERR_NONFINITE
     # iteration limit: best iterate with its true residual
     f = inputs.gaussian_bumps(g, 1).astype(np.float32)
-    st, stats, x = _solve(T, prob, f, tol=1e-10, max_iter=9)
+    st, stats, x = _solve(T, prob, f, tol=1e-10, max_iter=9, variant=variant)
     assert st == ppe.PPE_NOT_CONVERGED and stats[0]["iters_total"] == 9
     b, _ = orc.rhs(g, f)
     res = np.linalg.norm(b - orc.apply(g, x[0])) / np.linalg.norm(b)
     assert abs(res - stats[0]["rel_res_true"]) <= 1e-6 * res
     # warm start from the converged solution needs no iterations
-    st, stats, xs = _solve(T, prob, f, tol=1e-8)
-    st2, stats2, _ = _solve(T, prob, f, x0=xs, tol=1e-8)
+    st, stats, xs = _solve(T, prob, f, tol=1e-8, variant=variant)
+    st2, stats2, _ = _solve(T, prob, f, x0=xs, tol=1e-8, variant=variant)
     assert st2 == ppe.PPE_OK and stats2[0]["iters_total"] == 0
     # absolute tolerance
-    st, stats, x = _solve(T, prob, f, tol=1e-9, tol_kind=ppe.PPE_TOL_ABSOLUTE)
+    st, stats, x = _solve(T, prob, f, tol=1e-9, tol_kind=ppe.PPE_TOL_ABSOLUTE, variant=variant)
     assert st == ppe.PPE_OK and stats[0]["abs_res_true"] <= 1e-9
     # empty batch
     assert ppe.lib().ppe_solve_plain(prob.handle, 0, None, None, None, None, None) == 0
@@ -225,7 +232,8 @@ def test_invalid_arguments(T):
         ppe.ppe_solve_plain(prob, f, x, ppe.ppe_solve_opts_default(tol=-1.0))
 
 
-def test_full_size_1024(T, orc):
+@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+def test_full_size_1024(T, orc, variant):
     """The benchmark's workload: 1024^2, beta 1.75, ellipse mask, GRF source,
     solved to 1e-6 in the benchmark's launch configuration; the FP64 true residual
     is recomputed by the oracle, and at 1e-8 the solution matches the direct solve."""
@@ -235,12 +243,12 @@ def test_full_size_1024(T, orc):
     prob = ppe.ppe_problem_create(g)
     f = inputs.grf(g, 0).astype(np.float32)
     b, _ = orc.rhs(g, f)
-    st, stats, x = _solve(T, prob, f, tol=1e-6)
+    st, stats, x = _solve(T, prob, f, tol=1e-6, variant=variant)
     assert st == ppe.PPE_OK
     res = np.linalg.norm(b - orc.apply(g, x[0])) / np.linalg.norm(b)
     assert res <= 1e-6 * 1.001
     assert 4000 <= stats[0]["iters_total"] <= 7000, stats
-    st, stats, x = _solve(T, prob, f, tol=1e-8)
+    st, stats, x = _solve(T, prob, f, tol=1e-8, variant=variant)
     assert st == ppe.PPE_OK
     xs = direct.separable_solve(g, b)
     assert np.linalg.norm(x[0] - xs) / np.linalg.norm(xs) <= 1e-6
