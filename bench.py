@@ -85,11 +85,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--cpu-iters", type=int, default=600)
+    ap.add_argument("--cpu-iters", type=int, default=2400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=200)
-    ap.add_argument("--variant", choices=["single", "two_phase"], default="single",
-                    help="PCG iteration form: one reduction per iteration (default) or two")
+    ap.add_argument("--variant", choices=["auto", "single", "two_phase"], default="auto",
+                    help="PCG iteration form: tuned on the workload before timing (auto, default), "
+                         "one reduction per iteration, or two")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the phase-kernel timing launches and a 64 MiB calibration copy "
                          "(for hardware-counter runs)")
@@ -108,8 +109,19 @@ def main():
     prob = ppe.ppe_problem_create(g)
     f = torch.from_numpy(f_np[None]).cuda()
     x = torch.zeros((1, g.ny, g.nx), dtype=torch.float64, device="cuda")
-    variant = ppe.PPE_PCG_SINGLE_REDUCTION if args.variant == "single" else ppe.PPE_PCG_TWO_PHASE
+    variant = {"auto": ppe.PPE_PCG_AUTO, "single": ppe.PPE_PCG_SINGLE_REDUCTION,
+               "two_phase": ppe.PPE_PCG_TWO_PHASE}[args.variant]
     opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, variant=variant)
+    tuning = None
+    if variant == ppe.PPE_PCG_AUTO and not args.kernels_only:
+        # Launch-configuration tuning on the workload itself, before any timing.
+        tuning = ppe.ppe_tune_pcg(prob, f, torch.zeros_like(x), reps=20)
+        variant, rows = tuning["variant"], tuning["rows_per_wave"]
+    else:
+        rows = ppe.ppe_get_tuning(prob, 1)[1] if variant == ppe.PPE_PCG_AUTO else 0
+        if variant == ppe.PPE_PCG_AUTO:
+            variant = ppe.ppe_get_tuning(prob, 1)[0]
+    opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, variant=variant, rows_per_wave=rows)
     single = variant == ppe.PPE_PCG_SINGLE_REDUCTION
 
     if args.kernels_only:
@@ -168,7 +180,10 @@ def main():
         "config": {
             "workload": f"plain Jacobi-PCG, {g.nx}x{g.ny} tanh grid beta 1.75, ellipse mask, GRF source "
                         f"l=0.05, x0=0, rel-res {args.tol:g} on the FP64 true residual",
-            "pcg_form": args.variant,
+            "pcg_form": "single" if single else "two_phase",
+            "rows_per_wave": rows,
+            "tuning_us_per_iter": None if tuning is None else
+                {f"{k[0]}/R{k[1]}": round(v, 2) for k, v in tuning["us_per_iter"].items()},
             "iters": iters,
             "reliable_updates": s0["reliable_updates"],
             "rel_res_true": s0["rel_res_true"],

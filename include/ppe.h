@@ -61,8 +61,11 @@ enum { PPE_TOL_RELATIVE = 0, PPE_TOL_ABSOLUTE = 1 };   /* ||b-Ax||2 <= tol*||b||
  * SINGLE_REDUCTION regroups the recurrences so that one launch and one
  * grid-wide reduction make an iteration (p.Ap from an exact expansion in
  * sums of the previous launch); TWO_PHASE is the textbook order with two
- * reductions per iteration. The hybrid solve always uses TWO_PHASE. */
-enum { PPE_PCG_SINGLE_REDUCTION = 0, PPE_PCG_TWO_PHASE = 1 };
+ * reductions per iteration. AUTO takes the problem's tuned choice for the
+ * batch size (ppe_tune_pcg, ppe_set_tuning), else single reduction below
+ * 2^21 cells per launch and two-phase above. The hybrid solve always uses
+ * TWO_PHASE. */
+enum { PPE_PCG_AUTO = 0, PPE_PCG_SINGLE_REDUCTION = 1, PPE_PCG_TWO_PHASE = 2 };
 
 /* Error-direction provider of the hybrid solve. NET is the DeepONet; the others
  * replace it for testing the controller and its fallback. */
@@ -97,11 +100,11 @@ typedef struct {
   int32_t num_dlsm;        /* hybrid: line-search steps per round (default 2) */
   int32_t direction;       /* hybrid: PPE_DIR_* (default PPE_DIR_NET) */
   double reliable_delta;   /* true-residual update when ||r|| < delta*||r_true|| (default 0.3) */
-  int32_t rows_per_wave;   /* stencil tile height per wavefront: 0 = tuned default, else 2,4,8,16 */
+  int32_t rows_per_wave;   /* stencil tile height per wavefront: 0 = tuned or default, else 2,4,8,16 */
   int32_t use_graph;       /* 1 (default) = replay iteration chunks as a HIP graph, 0 = eager launches */
   int32_t chunk;           /* iterations per polled chunk (0 = default 64) */
   int32_t zero_x0;         /* 1 = ignore x on entry and start from x0 = 0 */
-  int32_t variant;         /* plain solve: PPE_PCG_SINGLE_REDUCTION (default) or PPE_PCG_TWO_PHASE */
+  int32_t variant;         /* plain solve: PPE_PCG_AUTO (default), _SINGLE_REDUCTION or _TWO_PHASE */
 } ppe_solve_opts;
 
 typedef struct {
@@ -189,6 +192,26 @@ ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* proble
                               hipStream_t s);
 
 /* ---- measurement ---- */
+/* Launch-configuration tuning of the plain solve (per problem and batch
+ * size nb). ppe_tune_pcg runs every iteration form x tile height (2, 4, 8,
+ * 16 rows per wavefront) for `reps` iterations on the caller's system
+ * (f: device FP32 [nb][ny][nx]; x: device FP64 [nb][ny][nx], overwritten),
+ * timing each launch with HIP events, and stores the fastest in the problem;
+ * later solves with variant PPE_PCG_AUTO and rows_per_wave 0 use it.
+ * out (host, optional) receives the choice and the per-iteration times in
+ * microseconds, us_per_iter[form][k] for form 0 single reduction, 1
+ * two-phase and k indexing the heights 2, 4, 8, 16. ppe_set_tuning stores a
+ * choice directly (e.g. from a cache the caller keeps); ppe_get_tuning
+ * reports what PPE_PCG_AUTO resolves to for nb. */
+typedef struct {
+  int32_t variant, rows_per_wave;
+  double us_per_iter[2][4];
+} ppe_tune_result;
+ppe_status ppe_tune_pcg(ppe_problem* p, int32_t nb, const float* f, double* x, int32_t reps,
+                        ppe_tune_result* out, hipStream_t s);
+ppe_status ppe_set_tuning(ppe_problem* p, int32_t nb, int32_t variant, int32_t rows_per_wave);
+ppe_status ppe_get_tuning(const ppe_problem* p, int32_t nb, int32_t* variant, int32_t* rows_per_wave);
+
 /* Average kernel durations in ms of the PCG iteration on nb systems, for the
  * form opts->variant selects: TWO_PHASE gives one phase-A launch in ms_out[0]
  * and one phase-B launch in ms_out[1]; SINGLE_REDUCTION gives its one launch

@@ -126,7 +126,32 @@ int default_rows(const ppe_problem* p, int nb) {
   return 2;
 }
 
-bool use_single_reduction(const ppe_solve_opts& o) { return o.variant != PPE_PCG_TWO_PHASE; }
+// Size heuristic (measured on MI355X): below ~2M cells per launch the
+// iteration is latency-bound and one reduction per iteration wins; above, the
+// two-phase form streams closer to the HBM bandwidth.
+static constexpr int64_t kSingleMaxCells = (int64_t)2 << 20;
+
+static int default_rows_single(int64_t cells) {
+  if (cells >= (int64_t)1 << 20) return 8;
+  if (cells >= (int64_t)1 << 17) return 4;
+  return 2;
+}
+
+void resolve_plain(const ppe_problem* p, int nb, const ppe_solve_opts& o, bool* single, int* rows) {
+  const int64_t cells = (int64_t)p->nx * p->ny * nb;
+  int v = o.variant, R = o.rows_per_wave;
+  if (v == PPE_PCG_AUTO) {
+    for (const auto& t : p->tuned)
+      if (t[0] == nb) {
+        v = t[1];
+        if (R == 0) R = t[2];
+      }
+  }
+  if (v == PPE_PCG_AUTO) v = cells < kSingleMaxCells ? PPE_PCG_SINGLE_REDUCTION : PPE_PCG_TWO_PHASE;
+  *single = v == PPE_PCG_SINGLE_REDUCTION;
+  if (!(R == 2 || R == 4 || R == 8 || R == 16)) R = *single ? default_rows_single(cells) : default_rows(p, nb);
+  *rows = R;
+}
 
 int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o) {
   const int r = o.rows_per_wave;
@@ -268,9 +293,10 @@ ppe_status solve_plain_impl(ppe_problem* p, int32_t nb, const float* f, double* 
   const auto t0 = std::chrono::steady_clock::now();
   ppe_status st = ensure_ws(p, nb);
   if (st != PPE_OK) return st;
-  const int R = rows_of(p, nb, o);
+  bool single;
+  int R;
+  resolve_plain(p, nb, o, &single, &R);
   const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
-  const bool single = use_single_reduction(o);
   launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
   if (single) launch_pcg1_setup(a, nb, s);
   else launch_pcg_setup(a, nb, s);
@@ -283,6 +309,48 @@ ppe_status solve_plain_impl(ppe_problem* p, int32_t nb, const float* f, double* 
   const double ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return fill_stats(p, nb, stats, ms, s, false);
+}
+
+// Average kernel durations of `reps` iterations of one launch configuration
+// (setup first), each launch carrying its own start/stop events.
+ppe_status profile_form(ppe_problem* p, int nb, const float* f, double* x, const ppe_solve_opts& o, bool single,
+                        int R, int reps, double* ms_out, hipStream_t s) {
+  ppe_status st = ensure_ws(p, nb);
+  if (st != PPE_OK) return st;
+  const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
+  if (single) launch_pcg1_setup(a, nb, s);
+  else launch_pcg_setup(a, nb, s);
+  std::vector<hipEvent_t> ev(4 * reps);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  for (int k = 0; k < reps; ++k) {
+    if (single) {
+      launch_pcg1_step_timed(a, nb, k & 1, s, ev[4 * k], ev[4 * k + 1]);
+      launch_pcg1_step_timed(a, nb, (k & 1) ^ 1, s, ev[4 * k + 2], ev[4 * k + 3]);
+    } else {
+      launch_pcg_phase_timed(a, nb, k & 1, 0, s, ev[4 * k], ev[4 * k + 1]);
+      launch_pcg_phase_timed(a, nb, k & 1, 1, s, ev[4 * k + 2], ev[4 * k + 3]);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventSynchronize(ev[4 * reps - 1]));
+  double ta = 0, tb = 0;
+  for (int k = 0; k < reps; ++k) {
+    float t1 = 0, t2 = 0;
+    HIPCHK(hipEventElapsedTime(&t1, ev[4 * k], ev[4 * k + 1]));
+    HIPCHK(hipEventElapsedTime(&t2, ev[4 * k + 2], ev[4 * k + 3]));
+    ta += t1;
+    tb += t2;
+  }
+  if (single) {
+    ms_out[0] = (ta + tb) / (2.0 * reps);
+    ms_out[1] = 0.0;
+  } else {
+    ms_out[0] = ta / reps;
+    ms_out[1] = tb / reps;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return PPE_OK;
 }
 
 }  // namespace ppe
@@ -307,7 +375,7 @@ void ppe_solve_opts_default(ppe_solve_opts* o) {
   o->rows_per_wave = 0;
   o->use_graph = 1;
   o->chunk = 0;
-  o->variant = PPE_PCG_SINGLE_REDUCTION;
+  o->variant = PPE_PCG_AUTO;
 }
 
 ppe_status ppe_problem_create(const ppe_grid_desc* g, ppe_problem** out) {
@@ -387,46 +455,72 @@ ppe_status ppe_profile_pcg(ppe_problem* p, int32_t nb, const float* f, double* x
   ppe_status st = check_solve_args(p, nb, f, x, &o);
   if (st != PPE_OK) return st;
   if (nb < 1 || reps < 1 || !ms_out) return set_error(PPE_ERR_INVALID_ARG, "nb, reps >= 1 and ms_out required");
-  st = ensure_ws(p, nb);
+  bool single;
+  int R;
+  resolve_plain(p, nb, o, &single, &R);
+  return profile_form(p, nb, f, x, o, single, R, reps, ms_out, s);
+}
+
+ppe_status ppe_tune_pcg(ppe_problem* p, int32_t nb, const float* f, double* x, int32_t reps,
+                        ppe_tune_result* out, hipStream_t s) {
+  ppe_solve_opts o;
+  ppe_solve_opts_default(&o);
+  ppe_status st = check_solve_args(p, nb, f, x, &o);
   if (st != PPE_OK) return st;
-  const int R = rows_of(p, nb, o);
-  const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
-  const bool single = use_single_reduction(o);
-  launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
-  if (single) launch_pcg1_setup(a, nb, s);
-  else launch_pcg_setup(a, nb, s);
-  // The real iteration sequence (alternating parities); each launch carries
-  // its own start/stop events (recorded by its dispatch). The single-reduction
-  // form has one launch per iteration, reported in ms_out[0].
-  std::vector<hipEvent_t> ev(4 * reps);
-  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-  for (int k = 0; k < reps; ++k) {
-    if (single) {
-      launch_pcg1_step_timed(a, nb, k & 1, s, ev[4 * k], ev[4 * k + 1]);
-      launch_pcg1_step_timed(a, nb, (k & 1) ^ 1, s, ev[4 * k + 2], ev[4 * k + 3]);
-    } else {
-      launch_pcg_phase_timed(a, nb, k & 1, 0, s, ev[4 * k], ev[4 * k + 1]);
-      launch_pcg_phase_timed(a, nb, k & 1, 1, s, ev[4 * k + 2], ev[4 * k + 3]);
+  if (nb < 1 || reps < 2) return set_error(PPE_ERR_INVALID_ARG, "nb >= 1 and reps >= 2 required");
+  // Candidates run the real iteration on (f, x) without a stopping test.
+  o.tol = 0.0;
+  o.max_iter = 1 << 30;
+  o.zero_x0 = 1;
+  static const int kRows[4] = {2, 4, 8, 16};
+  double best = 1e300;
+  int bv = PPE_PCG_SINGLE_REDUCTION, br = 8;
+  ppe_tune_result res{};
+  for (int v = 0; v < 2; ++v)
+    for (int k = 0; k < 4; ++k) {
+      double ms[2] = {0, 0};
+      st = profile_form(p, nb, f, x, o, v == 0, kRows[k], reps, ms, s);
+      if (st != PPE_OK) return st;
+      const double us = (ms[0] + ms[1]) * 1e3;
+      res.us_per_iter[v][k] = us;
+      if (us < best) {
+        best = us;
+        bv = v == 0 ? PPE_PCG_SINGLE_REDUCTION : PPE_PCG_TWO_PHASE;
+        br = kRows[k];
+      }
     }
-  }
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipEventSynchronize(ev[4 * reps - 1]));
-  double ta = 0, tb = 0;
-  for (int k = 0; k < reps; ++k) {
-    float t1 = 0, t2 = 0;
-    HIPCHK(hipEventElapsedTime(&t1, ev[4 * k], ev[4 * k + 1]));
-    HIPCHK(hipEventElapsedTime(&t2, ev[4 * k + 2], ev[4 * k + 3]));
-    ta += t1;
-    tb += t2;
-  }
-  if (single) {
-    ms_out[0] = (ta + tb) / (2.0 * reps);
-    ms_out[1] = 0.0;
-  } else {
-    ms_out[0] = ta / reps;
-    ms_out[1] = tb / reps;
-  }
-  for (auto& e : ev) (void)hipEventDestroy(e);
+  res.variant = bv;
+  res.rows_per_wave = br;
+  st = ppe_set_tuning(p, nb, bv, br);
+  if (st != PPE_OK) return st;
+  if (out) *out = res;
+  return PPE_OK;
+}
+
+ppe_status ppe_set_tuning(ppe_problem* p, int32_t nb, int32_t variant, int32_t rows_per_wave) {
+  if (!p || nb < 1) return set_error(PPE_ERR_INVALID_ARG, "problem and nb >= 1 required");
+  if (variant != PPE_PCG_SINGLE_REDUCTION && variant != PPE_PCG_TWO_PHASE)
+    return set_error(PPE_ERR_INVALID_ARG, "variant must be single-reduction or two-phase");
+  if (!(rows_per_wave == 2 || rows_per_wave == 4 || rows_per_wave == 8 || rows_per_wave == 16))
+    return set_error(PPE_ERR_INVALID_ARG, "rows_per_wave must be 2, 4, 8 or 16");
+  for (auto& t : p->tuned)
+    if (t[0] == nb) {
+      t = {nb, variant, rows_per_wave};
+      return PPE_OK;
+    }
+  p->tuned.push_back({nb, variant, rows_per_wave});
+  return PPE_OK;
+}
+
+ppe_status ppe_get_tuning(const ppe_problem* p, int32_t nb, int32_t* variant, int32_t* rows_per_wave) {
+  if (!p || nb < 1 || !variant || !rows_per_wave) return set_error(PPE_ERR_INVALID_ARG, "bad arguments");
+  ppe_solve_opts o;
+  ppe_solve_opts_default(&o);
+  bool single;
+  int R;
+  resolve_plain(p, nb, o, &single, &R);
+  *variant = single ? PPE_PCG_SINGLE_REDUCTION : PPE_PCG_TWO_PHASE;
+  *rows_per_wave = R;
   return PPE_OK;
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,8 @@ void net_cache_free(NetCache* c);
 
 struct ppe_problem {
   int nx = 0, ny = 0;
+  // Tuned PCG launch configuration per batch size: {nb, variant, rows_per_wave}.
+  std::vector<std::array<int, 3>> tuned;
   std::vector<double> xc, yc, hx, hy;
   std::vector<uint8_t> mask;  // empty = no obstacle
   // device copies of the 1D coefficients
@@ -56,7 +59,11 @@ PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int
 int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o);
 ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s,
                           bool single);
-bool use_single_reduction(const ppe_solve_opts& o);
+// Resolves PPE_PCG_AUTO and rows_per_wave = 0 for a plain solve of nb systems:
+// the tuned entry for nb if there is one, else the size heuristic.
+void resolve_plain(const ppe_problem* p, int nb, const ppe_solve_opts& o, bool* single, int* rows);
+ppe_status profile_form(ppe_problem* p, int nb, const float* f, double* x, const ppe_solve_opts& o, bool single,
+                        int R, int reps, double* ms_out, hipStream_t s);
 ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s, bool hybrid);
 ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, const void* x,
                             const ppe_solve_opts* opts);

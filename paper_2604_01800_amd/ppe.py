@@ -20,7 +20,7 @@ PPE_OK, PPE_NOT_CONVERGED = 0, 1
 PPE_ERR_INVALID_ARG, PPE_ERR_SHAPE, PPE_ERR_UNSUPPORTED, PPE_ERR_HIP, PPE_ERR_NONFINITE = -1, -2, -3, -4, -5
 PPE_PC_NONE, PPE_PC_JACOBI = 0, 1
 PPE_TOL_RELATIVE, PPE_TOL_ABSOLUTE = 0, 1
-PPE_PCG_SINGLE_REDUCTION, PPE_PCG_TWO_PHASE = 0, 1
+PPE_PCG_AUTO, PPE_PCG_SINGLE_REDUCTION, PPE_PCG_TWO_PHASE = 0, 1, 2
 PPE_DIR_NET, PPE_DIR_ZERO, PPE_DIR_JACOBI, PPE_DIR_NAN, PPE_DIR_ONES = 0, 1, 2, 3, 4
 
 
@@ -43,6 +43,11 @@ class ppe_solve_opts(ctypes.Structure):
                 ("direction", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
                 ("rows_per_wave", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("zero_x0", ctypes.c_int32), ("variant", ctypes.c_int32)]
+
+
+class ppe_tune_result(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
+                ("us_per_iter", (ctypes.c_double * 4) * 2)]
 
 
 class ppe_solve_stats(ctypes.Structure):
@@ -90,6 +95,9 @@ SIGNATURES = {
     "ppe_net_train_step": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_train_opts), _vp, _vp, _vp]),
     "ppe_profile_pcg": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_solve_opts), _i32, _vp, _vp]),
     "ppe_profile_copy": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),
+    "ppe_tune_pcg": (_i32, [_vp, _i32, _vp, _vp, _i32, _P(ppe_tune_result), _vp]),
+    "ppe_set_tuning": (_i32, [_vp, _i32, _i32, _i32]),
+    "ppe_get_tuning": (_i32, [_vp, _i32, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
     "ppe_last_error": (ctypes.c_char_p, []),
 }
 
@@ -224,6 +232,30 @@ def ppe_profile_pcg(prob: Problem, f, x, opts=None, reps=50, stream=None):
     _check(lib().ppe_profile_pcg(prob.handle, nb, _dev(f, torch.float32, "f"), _dev(x, torch.float64, "x"),
                                  ctypes.byref(opts), reps, ctypes.cast(out, ctypes.c_void_p), _stream(stream)))
     return out[0], out[1]
+
+
+def ppe_tune_pcg(prob: Problem, f, x, reps=20, stream=None):
+    """Times every iteration form x tile height on (f, x) (x is overwritten),
+    stores the fastest in the problem for this batch size and returns
+    {"variant", "rows_per_wave", "us_per_iter": {(form, rows): us}}."""
+    import torch
+    nb = _nb(f, prob)
+    res = ppe_tune_result()
+    _check(lib().ppe_tune_pcg(prob.handle, nb, _dev(f, torch.float32, "f"), _dev(x, torch.float64, "x"), reps,
+                              ctypes.byref(res), _stream(stream)))
+    forms = ("single", "two_phase")
+    table = {(forms[v], r): res.us_per_iter[v][k] for v in range(2) for k, r in enumerate((2, 4, 8, 16))}
+    return {"variant": res.variant, "rows_per_wave": res.rows_per_wave, "us_per_iter": table}
+
+
+def ppe_set_tuning(prob: Problem, nb: int, variant: int, rows_per_wave: int):
+    _check(lib().ppe_set_tuning(prob.handle, nb, variant, rows_per_wave))
+
+
+def ppe_get_tuning(prob: Problem, nb: int):
+    v, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().ppe_get_tuning(prob.handle, nb, ctypes.byref(v), ctypes.byref(r)))
+    return v.value, r.value
 
 
 def ppe_profile_copy(src, dst, reps=20, stream=None):

@@ -76,7 +76,7 @@ def _solve(T, prob, f, x0=None, **kw):
 
 @pytest.mark.parametrize("k", [1, 2, 5, 17, 40])
 @pytest.mark.parametrize("nx,ny,beta", [(64, 64, 1.5), (70, 45, 2.0), (130, 67, 2.5), (65, 41, 1.2)])
-@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
 def test_fixed_iterations_match_oracle(T, orc, variant, k, nx, ny, beta):
     ppe = _ppe()
     g = inputs.make_grid(nx, ny, beta)
@@ -93,7 +93,7 @@ def test_fixed_iterations_match_oracle(T, orc, variant, k, nx, ny, beta):
 
 
 @pytest.mark.parametrize("seed", range(10))
-@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
 def test_c1_converged_solves(T, orc, variant, seed):
     """64x64, beta 1.5, 8 Gaussian bumps: tol 1e-6 and 1e-8 on the FP64 true residual;
     at 1e-8 the solution matches the direct solve to 1e-6."""
@@ -124,7 +124,7 @@ def test_c1_converged_solves(T, orc, variant, seed):
     assert so8.iters_total - 3 <= iters[1e-8] <= 1.3 * so8.iters_total + 3, (iters, so8.iters_total)
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
 def test_batched_matches_single(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(96, 80, 2.0, 1.3)
@@ -141,7 +141,7 @@ def test_batched_matches_single(T, orc, variant):
         np.testing.assert_array_equal(x1[0], x[s])
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
 def test_deterministic_and_graph_equals_eager(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(128, 96, 2.2)
@@ -155,7 +155,7 @@ def test_deterministic_and_graph_equals_eager(T, orc, variant):
 
 
 @pytest.mark.parametrize("rows", [2, 4, 8, 16])
-@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
 def test_tile_heights_agree(T, orc, variant, rows):
     ppe = _ppe()
     g = inputs.make_grid(150, 77, 1.7)
@@ -167,7 +167,7 @@ def test_tile_heights_agree(T, orc, variant, rows):
     assert np.linalg.norm(b - orc.apply(g, x[0])) / np.linalg.norm(b) <= 1e-8 * 1.001
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
 def test_vanilla_cg(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(64, 48, 1.0)
@@ -181,7 +181,7 @@ def test_vanilla_cg(T, orc, variant):
     assert np.linalg.norm(x7[0] - orc.remove_mean(xo)) / np.linalg.norm(xo) <= 1e-5
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
 def test_edge_cases(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(33, 21, 1.5)
@@ -232,7 +232,7 @@ def test_invalid_arguments(T):
         ppe.ppe_solve_plain(prob, f, x, ppe.ppe_solve_opts_default(tol=-1.0))
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
 def test_full_size_1024(T, orc, variant):
     """The benchmark's workload: 1024^2, beta 1.75, ellipse mask, GRF source,
     solved to 1e-6 in the benchmark's launch configuration; the FP64 true residual
@@ -252,3 +252,34 @@ def test_full_size_1024(T, orc, variant):
     assert st == ppe.PPE_OK
     xs = direct.separable_solve(g, b)
     assert np.linalg.norm(x[0] - xs) / np.linalg.norm(xs) <= 1e-6
+
+
+def test_tuner_choice_is_used(T, orc):
+    """The tuner times every form and tile height, stores the fastest, and an
+    AUTO solve then runs exactly that configuration (identical bits)."""
+    ppe = _ppe()
+    g = inputs.make_grid(192, 128, 2.0)
+    prob = ppe.ppe_problem_create(g)
+    fs = np.stack([inputs.grf(g, s) for s in range(3)]).astype(np.float32)
+    fd = _dev(T, fs, T.float32)
+    xd = T.zeros(fs.shape, dtype=T.float64, device="cuda")
+    res = ppe.ppe_tune_pcg(prob, fd, xd, reps=6)
+    assert res["variant"] in (ppe.PPE_PCG_SINGLE_REDUCTION, ppe.PPE_PCG_TWO_PHASE)
+    assert res["rows_per_wave"] in (2, 4, 8, 16)
+    assert len(res["us_per_iter"]) == 8 and all(v > 0 for v in res["us_per_iter"].values())
+    best = min(res["us_per_iter"], key=res["us_per_iter"].get)
+    assert res["us_per_iter"][best] == res["us_per_iter"][("single" if res["variant"] == 1 else "two_phase",
+                                                          res["rows_per_wave"])]
+    assert ppe.ppe_get_tuning(prob, 3) == (res["variant"], res["rows_per_wave"])
+    st, stats, x_auto = _solve(T, prob, fs, tol=1e-7)
+    st2, stats2, x_expl = _solve(T, prob, fs, tol=1e-7, variant=res["variant"], rows_per_wave=res["rows_per_wave"])
+    assert st == st2 == ppe.PPE_OK
+    np.testing.assert_array_equal(x_auto, x_expl)
+    # a stored choice replaces the tuned one; other batch sizes keep the heuristic
+    ppe.ppe_set_tuning(prob, 3, ppe.PPE_PCG_TWO_PHASE, 4)
+    assert ppe.ppe_get_tuning(prob, 3) == (ppe.PPE_PCG_TWO_PHASE, 4)
+    assert ppe.ppe_get_tuning(prob, 1) == (ppe.PPE_PCG_SINGLE_REDUCTION, 2)
+    with pytest.raises(ppe.PPEError):
+        ppe.ppe_set_tuning(prob, 3, ppe.PPE_PCG_AUTO, 4)
+    with pytest.raises(ppe.PPEError):
+        ppe.ppe_set_tuning(prob, 3, ppe.PPE_PCG_TWO_PHASE, 5)
