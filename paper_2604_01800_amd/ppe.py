@@ -114,7 +114,7 @@ def lib():
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name, None)
             if fn is None:
-                continue
+                raise ImportError(f"{LIB_PATH} does not export {name}: rebuild the library")
             fn.restype = res
             fn.argtypes = args
         _lib = L
