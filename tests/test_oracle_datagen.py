@@ -1,0 +1,69 @@
+"""Pins of the training-data generator's reference (oracle/datagen.py):
+Philox4x32-10 against the known-answer vectors published with the Random123
+library (Salmon et al., SC 2011), the uniform map's moments, and the random
+Fourier-feature field's covariance against exp(-d^2 / (2 l^2)) within three
+standard errors (Rahimi & Recht, 2007)."""
+import numpy as np
+
+from oracle import datagen
+from paper_2604_01800_amd import inputs
+
+# Random123 known-answer vectors for philox4x32 with 10 rounds: (counter, key) -> output.
+KAT = [
+    ((0x00000000, 0x00000000, 0x00000000, 0x00000000), (0x00000000, 0x00000000),
+     (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+    ((0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF), (0xFFFFFFFF, 0xFFFFFFFF),
+     (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+    ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+     (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+]
+
+
+def test_philox_known_answers():
+    for ctr, key, out in KAT:
+        assert datagen.philox4x32_10(ctr, key) == out
+
+
+def test_vectorised_philox_matches_scalar():
+    seed, step, s = 0x123456789ABC, (7 << 32) + 11, 5
+    got = datagen.philox_vec(np.arange(40), s, step, seed)
+    for d in range(40):
+        want = datagen.philox4x32_10((d, s, step & 0xFFFFFFFF, step >> 32), (seed & 0xFFFFFFFF, seed >> 32))
+        assert tuple(int(v) for v in got[d]) == want
+
+
+def test_uniform_moments():
+    u = datagen.to_unit(datagen.philox_vec(np.arange(50000), 0, 0, 1).reshape(-1))
+    assert 0.0 < u.min() and u.max() < 1.0
+    n = u.size
+    assert abs(u.mean() - 0.5) <= 4 * np.sqrt(1 / 12 / n)
+    assert abs(u.var() - 1 / 12) <= 4 * np.sqrt(1 / 180 / n)
+
+
+def test_field_covariance_matches_kernel():
+    """Independent fields (one per step) at fixed l: the empirical covariance of
+    g at separations d matches exp(-d^2 / (2 l^2)) within 3 standard errors."""
+    ell, J, n_fields = 0.1, 256, 400
+    xs = np.array([0.3, 0.3 + 0.05, 0.3 + 0.1, 0.3 + 0.2])
+    ys = np.array([0.4])
+    vals = np.empty((n_fields, len(xs)))
+    for k in range(n_fields):
+        _, wx, wy, phi = datagen.features(0, k, 99, J, ell, ell)
+        vals[k] = datagen.grf_field(xs, ys, wx, wy, phi)[0]
+    for m in range(len(xs)):
+        d = xs[m] - xs[0]
+        prod = vals[:, 0] * vals[:, m]
+        se = prod.std(ddof=1) / np.sqrt(n_fields)
+        assert abs(prod.mean() - np.exp(-d * d / (2 * ell * ell))) <= 3 * se + 1e-3, (d, prod.mean(), se)
+
+
+def test_generated_batch_properties():
+    rng = np.random.default_rng(0)
+    grids = [inputs.random_stretched_grid(40, 24, rng) for _ in range(3)]
+    R = datagen.generate(grids, seed=5, step=2, J=64)
+    for s in range(3):
+        assert abs(R[s].mean()) <= 1e-12
+        assert abs(np.sqrt(np.mean(R[s] ** 2)) - 1.0) <= 1e-12
+    assert np.array_equal(R, datagen.generate(grids, seed=5, step=2, J=64))
+    other = datagen.generate(grids, seed=5, step=3, J=64)
+    assert np.abs(other - R).max() > 0.1
