@@ -115,6 +115,8 @@ typedef struct {
   double bnorm;            /* ||b||2 after projection */
   double rhs_mean_removed; /* plain mean removed from b = area * f */
   double ms_total;         /* wall time of the call (host clock), same for all solves of a call */
+  double ms_device;        /* this solve's time from its set-up to its convergence decision, on the
+                              device's real-time clock (per solve within a batch) */
 } ppe_solve_stats;
 
 /* Network configuration (Sec. 2.4). Defaults (ppe_net_config_default): 4 levels,
@@ -130,7 +132,15 @@ typedef struct {
 typedef struct {
   float lr, beta1, beta2, eps;  /* Adam; defaults 1e-3, 0.9, 0.999, 1e-8 */
   uint64_t seed;                /* data generator seed (used when R == NULL) */
-  int64_t step;                 /* data generator step counter */
+  int64_t step;                 /* data generator step counter (>= 0) */
+  /* Data generator (ppe_generate_rhs, and ppe_net_train_step with R == NULL):
+   * Gaussian random fields with squared-exponential covariance of length
+   * scale l, log-uniform in [grf_len_lo, grf_len_hi] per sample (defaults
+   * 0.05, 0.5; FP32 values), from grf_features random Fourier features
+   * (default 512). */
+  float grf_len_lo, grf_len_hi;
+  int32_t grf_features;
+  int32_t reserved;
 } ppe_train_opts;
 
 /* ---- problem (Sec. 8 a1: per-grid setup, built once and reused, as the paper
@@ -153,6 +163,18 @@ ppe_status ppe_apply_f64(const ppe_problem* p, int32_t nb, const double* x, doub
  * PPE_ERR_NONFINITE if any source held NaN/Inf. */
 ppe_status ppe_solve_plain(ppe_problem* p, int32_t nb, const float* f, double* x,
                            const ppe_solve_opts* opts, ppe_solve_stats* stats, hipStream_t s);
+
+/* Plain (Jacobi-)PCG solves of n systems on grids of different sizes, one
+ * right-hand side per grid, batched into one launch per iteration (a work
+ * list of (solve, workgroup) entries over all grids; single-reduction form).
+ * problems: host array of n distinct problems; f: host array of n device
+ * FP32 sources [ny_i][nx_i]; x: host array of n device FP64 solutions
+ * (in: initial guess, out: zero-mean solution); stats: host [n] or NULL,
+ * with ms_device the solve's own time to its convergence decision. net must
+ * be NULL (hybrid batches over mixed sizes are not built:
+ * PPE_ERR_UNSUPPORTED). Statuses as for ppe_solve_plain. */
+ppe_status ppe_solve_batch(int32_t n, ppe_problem* const* problems, const ppe_net* net, const float* const* f,
+                           double* const* x, const ppe_solve_opts* opts, ppe_solve_stats* stats, hipStream_t s);
 
 /* Hybrid solve (Sec. 2.2): rounds of num_cg PCG iterations and num_dlsm
  * line-search steps along e = NN(r) (Eqs. 12-13), restarting PCG after each
@@ -181,10 +203,25 @@ ppe_status ppe_net_load(ppe_net* n, const char* path);
 ppe_status ppe_net_forward(ppe_net* n, ppe_problem* p, int32_t nb, const float* r, float* y,
                            hipStream_t s);
 
+/* Fabricated right-hand sides on the device (stand-in for the Lanczos-Ritz
+ * vectors of Eqs. 14-16): for sample s of the batch, a Gaussian random field
+ * from random Fourier features (Rahimi & Recht) at the cell centres of
+ * problems[s], times the cell area, minus its mean, scaled to unit RMS. The
+ * random numbers are Philox4x32-10 (Salmon et al., SC 2011) with key = seed
+ * and counter = (draw, s, step): draw 0 gives the sample's length scale,
+ * draw 1 + f feature f (frequency by Box-Muller, phase). The same
+ * (seed, step, s) always gives the same field.
+ * problems: host array of nb grids of one size; R: device FP32 [nb][ny][nx].
+ * Uses and synchronises stream s. */
+ppe_status ppe_generate_rhs(int32_t nb, ppe_problem* const* problems, const ppe_train_opts* opts, float* R,
+                            hipStream_t s);
+
 /* One Adam step on nb fabricated systems with the residual loss of Eq. 19,
  * Loss = mean over cells of (R - A NN(R))^2, averaged over the batch.
  * problems: host array of nb grids of one size (each sample has its own grid);
- * R: device FP32 [nb][ny][nx] (zero-sum residual fields).
+ * R: device FP32 [nb][ny][nx] (zero-sum residual fields), or NULL: the
+ * library then generates the batch with ppe_generate_rhs from opts (seed,
+ * step, length-scale range, features).
  * loss_out: host, the batch loss before the step. grad_out: host or NULL;
  * when given, receives the FP32 gradient (ppe_net_num_params values). */
 ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* problems, const float* R,

@@ -236,6 +236,20 @@ ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_so
   return PPE_OK;
 }
 
+// Rate of the device real-time clock (wall_clock64) in kHz.
+double wall_clock_khz() {
+  static double khz = 0.0;
+  if (khz == 0.0) {
+    int dev = 0, rate = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) == hipSuccess && rate > 0)
+      khz = (double)rate;
+    else
+      khz = 1e5;  // the documented 100 MHz counter
+  }
+  return khz;
+}
+
 ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s, bool hybrid) {
   SolveWs& w = p->ws;
   HIPCHK(hipMemcpyAsync(w.h_state, w.st, sizeof(SolveState) * nb, hipMemcpyDeviceToHost, s));
@@ -262,6 +276,7 @@ ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms,
       o.rel_res_true = S.bnorm2 > 0 ? std::sqrt(S.rr_final / S.bnorm2) : o.abs_res_true;
       o.rhs_mean_removed = S.bmean;
       o.ms_total = ms;
+      o.ms_device = (double)(S.t_done - S.t_start) / wall_clock_khz();
     }
   }
   if (worst == PPE_ERR_NONFINITE) set_error(worst, "non-finite value in a source field or iteration");

@@ -27,6 +27,16 @@ struct SolveWs {
   int exec_key[5] = {0, 0, 0, 0, 0};
 };
 
+// Device workspace of the training-data generator (grown on demand).
+struct GenWs {
+  int nb = 0, J = 0, P = 0;
+  int64_t N = 0;
+  void* feat = nullptr;     // [nb][J] double4 (w_x, w_y, phi, l)
+  double* raw = nullptr;    // [nb][N]
+  double* part = nullptr;   // [nb][2][P]
+  Coef* coefs = nullptr;    // [nb]
+};
+
 struct NetCache;  // per (grid, net) constants of the network (net_internal.hpp)
 void net_cache_free(NetCache* c);
 
@@ -61,6 +71,14 @@ ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_so
                           bool single);
 // Resolves PPE_PCG_AUTO and rows_per_wave = 0 for a plain solve of nb systems:
 // the tuned entry for nb if there is one, else the size heuristic.
+ppe_status gen_ensure(GenWs& w, int nb, int64_t N, int J, int P);
+void gen_free(GenWs& w);
+ppe_status check_gen_opts(const ppe_train_opts& o);
+// R [nb][N] FP32 for the batch of grids probs (one size), from opts' seed,
+// step, length-scale range and feature count; synchronises stream s.
+ppe_status generate_rhs(GenWs& w, int nb, ppe_problem* const* probs, const ppe_train_opts& o, float* R,
+                        hipStream_t s);
+double wall_clock_khz();
 void resolve_plain(const ppe_problem* p, int nb, const ppe_solve_opts& o, bool* single, int* rows);
 ppe_status profile_form(ppe_problem* p, int nb, const float* f, double* x, const ppe_solve_opts& o, bool single,
                         int R, int reps, double* ms_out, hipStream_t s);

@@ -21,6 +21,7 @@ struct Coef {
   int nx, ny;
   const float *hx, *hy, *gx, *gy;          // [nx], [ny], [nx+1], [ny+1]
   const double *hx64, *hy64, *gx64, *gy64; // same in FP64
+  const double *xc64, *yc64;               // cell centres [nx], [ny] (not padded)
 };
 
 // Per-solve iteration state. Fields with a [2] index are written by the
@@ -49,6 +50,8 @@ struct SolveState {
   int32_t dl_active, dl_it;
   double dl_alpha;
   int32_t pad[2];
+  // device real-time clock (wall_clock64) at set-up and when the solve finished
+  uint64_t t_start, t_done;
 };
 
 // MODE_FLUSH is used by the single-reduction iteration only (x += x_c, then

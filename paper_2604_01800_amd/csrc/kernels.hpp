@@ -33,6 +33,9 @@ void launch_rhs(const PcgArgs& a, int nb, hipStream_t s);
 void launch_pcg_setup(const PcgArgs& a, int nb, hipStream_t s);
 void launch_pcg1_setup(const PcgArgs& a, int nb, hipStream_t s);
 void launch_pcg1_step(const PcgArgs& a, int nb, int par, hipStream_t s);
+void launch_pcg1_init(const PcgArgs& a, int nb, hipStream_t s);
+void launch_pcg1_multi_step(const PcgArgs* descs, const uint32_t* work, int nblocks, int R, bool jacobi, int par,
+                            hipStream_t s);
 void launch_pcg1_step_timed(const PcgArgs& a, int nb, int par, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 void launch_pcg_pair(const PcgArgs& a, int nb, int par, int force, int force_restart, hipStream_t s);
 void launch_pcg_phase_a(const PcgArgs& a, int nb, int par, hipStream_t s);

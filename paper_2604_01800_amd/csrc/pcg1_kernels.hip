@@ -36,8 +36,9 @@ namespace ppe {
 
 constexpr int kSums = 5;  // gamma, delta, zeta, pi, |r|^2
 
-__device__ __forceinline__ double* sums_of(const PcgArgs& a, int par, int s) {
-  return a.part1 + ((size_t)par * gridDim.z + s) * kSums * a.P;
+// Sums of solve s (of nbs solves sharing a.part1) written by launch parity par.
+__device__ __forceinline__ double* sums_of(const PcgArgs& a, int par, int s, int nbs) {
+  return a.part1 + ((size_t)par * nbs + s) * kSums * a.P;
 }
 
 // Fixed-order reduction of the five partial arrays ([5][P]); every workgroup
@@ -64,8 +65,8 @@ __device__ __forceinline__ void reduce5(const double* __restrict__ part, int P, 
     out[m] = ((lds[m * kWaves] + lds[m * kWaves + 1]) + lds[m * kWaves + 2]) + lds[m * kWaves + 3];
 }
 
-// Workgroup sums of five values, stored by thread 0 into part ([5][P]).
-__device__ __forceinline__ void store5(double (&v)[kSums], double* lds, double* __restrict__ part, int P) {
+// Workgroup sums of five values, stored by thread 0 into part[.][blk] ([5][P]).
+__device__ __forceinline__ void store5(double (&v)[kSums], double* lds, double* __restrict__ part, int P, int blk) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
   for (int m = 0; m < kSums; ++m) v[m] = wave_sum(v[m]);
@@ -78,7 +79,7 @@ __device__ __forceinline__ void store5(double (&v)[kSums], double* lds, double* 
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int m = 0; m < kSums; ++m)
-      part[(size_t)m * P + blockIdx.x] =
+      part[(size_t)m * P + blk] =
           ((lds[m * kWaves] + lds[m * kWaves + 1]) + lds[m * kWaves + 2]) + lds[m * kWaves + 3];
   }
 }
@@ -121,10 +122,11 @@ __device__ __forceinline__ double true_res(const Coef& c, int i, int j, double x
   return (c.hx64[i] * hyj * (double)f - bmean) - Ax;
 }
 
+// One launch of the iteration for solve s of the nbs solves described by a,
+// run by the solve's workgroup blk.
 template <int R, bool JAC>
-__global__ __launch_bounds__(kBlock) void k_pcg1(PcgArgs a, int par) {
-  __shared__ double lds[kSums * kWaves];
-  const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
+__device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int blk, int par, double* lds) {
+  const int nx = a.c.nx, ny = a.c.ny;
   SolveState* st = a.st + s;
   const int P = a.P, pm = par ^ 1;
   const size_t off = (size_t)s * a.N;
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg1(PcgArgs a, int par) {
   float* __restrict__ pout = (par ? a.p1 : a.p0) + off;
   float* __restrict__ xc = a.xc + off;
   const int lane = threadIdx.x & (kWave - 1);
-  const TileXY tl = tile_xy(nx, ny, R);
+  const TileXY tl = tile_xy_at(nx, ny, R, blk);
   const ColIdx ci = col_idx(nx, tl);
   const Halo2 h2 = halo2(nx, tl);
   const int j0 = tl.j0;
@@ -183,9 +185,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg1(PcgArgs a, int par) {
   const int restart = st->restart[pm];
   const double gam_prev = st->rho[pm], thr2 = st->thr2;
   double rr_ru = st->rr_ru[pm];
-  const bool leader = is_first_block();
+  const bool leader = blk == 0 && threadIdx.x == 0;
   double sum[kSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (pmode != MODE_FLUSH) reduce5(sums_of(a, pm, s), P, lds, sum);
+  if (pmode != MODE_FLUSH) reduce5(sums_of(a, pm, s, nbs), P, lds, sum);
   if (dprev) {
     if (leader) st->dflag[par] = dprev;
     return;
@@ -217,6 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg1(PcgArgs a, int par) {
         st->nru_final = nru;
         st->itcg_final = itcg;
         st->done = done;
+        st->t_done = wall_clock64();
         st->dflag[par] = done;
         a.flags[s] = done;
       }
@@ -420,7 +423,24 @@ __global__ __launch_bounds__(kBlock) void k_pcg1(PcgArgs a, int par) {
       acc[4] += (double)rn[q + 1] * (double)rn[q + 1];
     }
   }
-  store5(acc, lds, sums_of(a, par, s), P);
+  store5(acc, lds, sums_of(a, par, s, nbs), P, blk);
+}
+
+template <int R, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_pcg1(PcgArgs a, int par) {
+  __shared__ double lds[kSums * kWaves];
+  pcg1_body<R, JAC>(a, blockIdx.z, gridDim.z, blockIdx.x, par, lds);
+}
+
+// Solves on grids of different sizes in one launch: work[b] = (solve << 20) |
+// (workgroup within the solve) for the launch's workgroup b; descs[solve] is
+// that solve's argument block (one solve each).
+template <int R, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_pcg1_multi(const PcgArgs* __restrict__ descs,
+                                                       const uint32_t* __restrict__ work, int par) {
+  __shared__ double lds[kSums * kWaves];
+  const uint32_t wv = work[blockIdx.x];
+  pcg1_body<R, JAC>(descs[wv >> 20], 0, 1, (int)(wv & 0xFFFFFu), par, lds);
 }
 
 // Set-up after the right-hand side: zero x_c and both p buffers and leave the
@@ -453,6 +473,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg1_init(PcgArgs a) {
     st->nru_final = 0;
     st->itcg_final = 0;
     st->rr_final = 0.0;
+    st->t_start = wall_clock64();
+    st->t_done = st->t_start;
     a.flags[s] = bad ? DONE_NONFINITE : DONE_NO;
   }
   const size_t off = (size_t)s * a.N;
@@ -498,6 +520,15 @@ void launch_pcg1_setup(const PcgArgs& a, int nb, hipStream_t s) {
 void launch_pcg1_step(const PcgArgs& a, int nb, int par, hipStream_t s) {
   const dim3 g = stencil_grid(a.c, a.R, nb);
   PPE1_DISPATCH(a.R, a.jacobi, k_pcg1<RR, JJ><<<g, kBlock, 0, s>>>(a, par));
+}
+
+void launch_pcg1_multi_step(const PcgArgs* descs, const uint32_t* work, int nblocks, int R, bool jacobi, int par,
+                            hipStream_t s) {
+  PPE1_DISPATCH(R, jacobi, k_pcg1_multi<RR, JJ><<<nblocks, kBlock, 0, s>>>(descs, work, par));
+}
+
+void launch_pcg1_init(const PcgArgs& a, int nb, hipStream_t s) {
+  k_pcg1_init<<<stencil_grid(a.c, a.R, nb), kBlock, 0, s>>>(a);
 }
 
 void launch_pcg1_step_timed(const PcgArgs& a, int nb, int par, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {

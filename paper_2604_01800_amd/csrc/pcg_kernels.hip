@@ -209,6 +209,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs a) {
     st->nru_final = 0;
     st->itcg_final = 0;
     st->rr_final = 0.0;
+    st->t_start = wall_clock64();
+    st->t_done = st->t_start;
     a.flags[s] = bad ? DONE_NONFINITE : DONE_NO;
   }
   double rr = 0.0, rz = 0.0;
@@ -306,6 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
       st->nru_final = nru;
       st->itcg_final = itcg;
       st->done = done;
+      st->t_done = wall_clock64();
       st->dflag[par] = done;
       a.flags[s] = done;
     }

@@ -21,7 +21,7 @@ ppe_status problem_upload(ppe_problem* p) {
   // outside the grid without bounds tests: hx[-1], gx[nx + 1], hy[ny + 80] ...
   const size_t lx = nx + 2 * kPadX, lgx = nx + 1 + 2 * kPadX;
   const size_t ly = ny + kPadY0 + kPadY1, lgy = ny + 1 + kPadY0 + kPadY1;
-  const size_t n64 = lx + ly + lgx + lgy;
+  const size_t n64 = lx + ly + lgx + lgy + nx + ny;
   std::vector<double> h64(n64, 0.0);
   double* hxp = h64.data();
   double* hyp = hxp + lx;
@@ -31,6 +31,10 @@ ppe_status problem_upload(ppe_problem* p) {
   for (int j = 0; j < ny; ++j) hyp[kPadY0 + j] = p->hy[j];
   for (int k = 0; k <= nx; ++k) gxp[kPadX + k] = gx[k];
   for (int k = 0; k <= ny; ++k) gyp[kPadY0 + k] = gy[k];
+  double* xcp = gyp + lgy;
+  double* ycp = xcp + nx;
+  for (int i = 0; i < nx; ++i) xcp[i] = p->xc[i];
+  for (int j = 0; j < ny; ++j) ycp[j] = p->yc[j];
   std::vector<float> h32(h64.begin(), h64.end());
   const size_t bytes = n64 * (sizeof(double) + sizeof(float));
   p->dev_coef = dev_alloc(bytes);
@@ -47,6 +51,8 @@ ppe_status problem_upload(ppe_problem* p) {
   c.hy64 = d64 + lx + kPadY0;
   c.gx64 = d64 + lx + ly + kPadX;
   c.gy64 = d64 + lx + ly + lgx + kPadY0;
+  c.xc64 = d64 + lx + ly + lgx + lgy;
+  c.yc64 = c.xc64 + nx;
   c.hx = d32 + kPadX;
   c.hy = d32 + lx + kPadY0;
   c.gx = d32 + lx + ly + kPadX;

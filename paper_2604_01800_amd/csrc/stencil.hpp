@@ -69,12 +69,13 @@ struct TileXY {
   bool valid;
 };
 
-__device__ __forceinline__ TileXY tile_xy(int nx, int ny, int R) {
+// b: the workgroup's index within its solve; a solve's workgroups start at a
+// multiple of 8 in the launch, so b % 8 is still the XCD.
+__device__ __forceinline__ TileXY tile_xy_at(int nx, int ny, int R, int b) {
   const int gxt = (nx + kWave - 1) / kWave;
   const int gyt = (ny + kWaves * R - 1) / (kWaves * R);
   const int T = gxt * gyt;
   const int per = (T + 7) / 8;
-  const int b = blockIdx.x;
   int t = (b & 7) * per + (b >> 3);
   TileXY o;
   o.valid = t < T;
@@ -84,6 +85,8 @@ __device__ __forceinline__ TileXY tile_xy(int nx, int ny, int R) {
   o.j0 = ((t / gxt) * kWaves + w) * R;
   return o;
 }
+
+__device__ __forceinline__ TileXY tile_xy(int nx, int ny, int R) { return tile_xy_at(nx, ny, R, blockIdx.x); }
 
 __device__ __forceinline__ int block_linear() { return blockIdx.x; }
 

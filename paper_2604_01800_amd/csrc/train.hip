@@ -55,6 +55,9 @@ struct TrainState {
   float* part = nullptr;
   int64_t part_len = 0;
   double* dpart = nullptr;  // [nb][kRedBlocks] input-scale partials, then loss partials and the loss value
+  // generated right-hand sides (R == NULL)
+  GenWs gen;
+  float* d_R = nullptr;  // [nb][N]
 };
 
 static int pad8(int c) { return (c + 7) / 8 * 8; }
@@ -65,6 +68,8 @@ void net_train_free(ppe_net* n) {
   dev_free(t->d_lv);
   dev_free(t->d_coefs);
   dev_free((void*)t->d_masks);
+  gen_free(t->gen);
+  dev_free(t->d_R);
   dev_free(t->act);
   dev_free(t->grad);
   dev_free(t->eta);
@@ -210,7 +215,10 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
                                          hipStream_t s) {
   if (!n || !problems || !opts) return set_error(PPE_ERR_INVALID_ARG, "net, problems or opts NULL");
   if (nb < 1 || nb > 4096) return set_error(PPE_ERR_INVALID_ARG, "nb must lie in [1, 4096]");
-  if (!R) return set_error(PPE_ERR_UNSUPPORTED, "R == NULL: pass the residual fields");
+  if (!R) {
+    ppe_status sg = check_gen_opts(*opts);
+    if (sg != PPE_OK) return sg;
+  }
   for (int i = 0; i < nb; ++i) {
     if (!problems[i]) return set_error(PPE_ERR_INVALID_ARG, "problems[%d] is NULL", i);
     if (problems[i]->nx != problems[0]->nx || problems[i]->ny != problems[0]->ny)
@@ -225,6 +233,13 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
   ppe_status st = train_state(n, nb, nx, ny);
   if (st != PPE_OK) return st;
   TrainState* t = n->train;
+  if (!R) {
+    if (!t->d_R) t->d_R = (float*)dev_alloc(sizeof(float) * N * nb);
+    if (!t->d_R) return set_error(PPE_ERR_HIP, "allocation of the generated batch failed");
+    st = generate_rhs(t->gen, nb, problems, *opts, t->d_R, s);
+    if (st != PPE_OK) return st;
+    R = t->d_R;
+  }
   auto ch = [&](int l) { return C0 << l; };
   auto hw = [&](int l) { return (int64_t)t->H[l] * t->W[l]; };
 

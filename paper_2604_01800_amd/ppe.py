@@ -55,7 +55,7 @@ class ppe_solve_stats(ctypes.Structure):
                 ("iters_dlsm", ctypes.c_int32), ("dlsm_rejected", ctypes.c_int32),
                 ("reliable_updates", ctypes.c_int32), ("rel_res_true", ctypes.c_double),
                 ("abs_res_true", ctypes.c_double), ("bnorm", ctypes.c_double),
-                ("rhs_mean_removed", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("rhs_mean_removed", ctypes.c_double), ("ms_total", ctypes.c_double), ("ms_device", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -69,7 +69,9 @@ class ppe_net_config(ctypes.Structure):
 
 class ppe_train_opts(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
-                ("eps", ctypes.c_float), ("seed", ctypes.c_uint64), ("step", ctypes.c_int64)]
+                ("eps", ctypes.c_float), ("seed", ctypes.c_uint64), ("step", ctypes.c_int64),
+                ("grf_len_lo", ctypes.c_float), ("grf_len_hi", ctypes.c_float), ("grf_features", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/ppe.h
@@ -95,6 +97,8 @@ SIGNATURES = {
     "ppe_net_train_step": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_train_opts), _vp, _vp, _vp]),
     "ppe_profile_pcg": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_solve_opts), _i32, _vp, _vp]),
     "ppe_profile_copy": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),
+    "ppe_solve_batch": (_i32, [_i32, _vp, _vp, _vp, _vp, _P(ppe_solve_opts), _vp, _vp]),
+    "ppe_generate_rhs": (_i32, [_i32, _vp, _P(ppe_train_opts), _vp, _vp]),
     "ppe_tune_pcg": (_i32, [_vp, _i32, _vp, _vp, _i32, _P(ppe_tune_result), _vp]),
     "ppe_set_tuning": (_i32, [_vp, _i32, _i32, _i32]),
     "ppe_get_tuning": (_i32, [_vp, _i32, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
@@ -347,15 +351,39 @@ def ppe_solve_hybrid(prob: Problem, net, f, x, opts=None, stream=None):
 
 
 def ppe_train_opts_default(**kw) -> ppe_train_opts:
-    o = ppe_train_opts(1e-3, 0.9, 0.999, 1e-8, 0, 0)
+    o = ppe_train_opts(1e-3, 0.9, 0.999, 1e-8, 0, 0, 0.05, 0.5, 512, 0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
 
 
-def ppe_net_train_step(net: Net, probs, R, opts=None, want_grad=False, stream=None):
-    """One Adam step (lr = 0: gradient only). probs: list of Problem (one grid per sample),
-    R: device float32 [nb, ny, nx]. Returns (loss, grad ndarray or None)."""
+def ppe_solve_batch(probs, fs, xs, opts=None, stream=None):
+    """Plain solves of one right-hand side on each of len(probs) grids of any
+    sizes, batched per iteration. fs[i]: device float32 [ny_i, nx_i] (or
+    [1, ny_i, nx_i]); xs[i]: device float64 of the same shape. Returns
+    (status, list of stats dicts)."""
+    import torch
+    n = len(probs)
+    if len(fs) != n or len(xs) != n:
+        raise ValueError("one source and one solution per problem")
+    for p, f, x in zip(probs, fs, xs):
+        for t in (f, x):
+            if t.numel() != p.nx * p.ny:
+                raise ValueError("array size does not match its grid")
+    parr = (ctypes.c_void_p * n)(*[p.handle.value for p in probs])
+    farr = (ctypes.c_void_p * n)(*[_dev(f, torch.float32, "f") for f in fs])
+    xarr = (ctypes.c_void_p * n)(*[_dev(x, torch.float64, "x") for x in xs])
+    opts = opts or ppe_solve_opts_default()
+    stats = (ppe_solve_stats * n)()
+    st = lib().ppe_solve_batch(n, ctypes.cast(parr, ctypes.c_void_p), None, ctypes.cast(farr, ctypes.c_void_p),
+                               ctypes.cast(xarr, ctypes.c_void_p), ctypes.byref(opts),
+                               ctypes.cast(stats, ctypes.c_void_p), _stream(stream))
+    _check(st, allow=(PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))
+    return st, [s.as_dict() for s in stats]
+
+
+def ppe_generate_rhs(probs, opts, R, stream=None):
+    """Fabricated right-hand sides on the device into R (float32 [nb, ny, nx])."""
     import torch
     nb = len(probs)
     if R.dim() != 3 or R.shape[0] != nb:
@@ -363,10 +391,27 @@ def ppe_net_train_step(net: Net, probs, R, opts=None, want_grad=False, stream=No
     for p in probs:
         _nb(R[0], p)
     arr = (ctypes.c_void_p * nb)(*[p.handle.value for p in probs])
+    _check(lib().ppe_generate_rhs(nb, ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(opts),
+                                  _dev(R, torch.float32, "R"), _stream(stream)))
+
+
+def ppe_net_train_step(net: Net, probs, R, opts=None, want_grad=False, stream=None):
+    """One Adam step (lr = 0: gradient only). probs: list of Problem (one grid per sample),
+    R: device float32 [nb, ny, nx], or None to generate the batch on the device from
+    opts (seed, step, length scales, features). Returns (loss, grad ndarray or None)."""
+    import torch
+    nb = len(probs)
+    if R is not None:
+        if R.dim() != 3 or R.shape[0] != nb:
+            raise ValueError("R must be [nb, ny, nx] with one sample per problem")
+        for p in probs:
+            _nb(R[0], p)
+    arr = (ctypes.c_void_p * nb)(*[p.handle.value for p in probs])
     opts = opts or ppe_train_opts_default()
     loss = ctypes.c_float()
     grad = np.empty(ppe_net_num_params(net), dtype=np.float32) if want_grad else None
-    _check(lib().ppe_net_train_step(net.handle, nb, ctypes.cast(arr, ctypes.c_void_p), _dev(R, torch.float32, "R"),
+    Rp = None if R is None else _dev(R, torch.float32, "R")
+    _check(lib().ppe_net_train_step(net.handle, nb, ctypes.cast(arr, ctypes.c_void_p), Rp,
                                     ctypes.byref(opts), ctypes.byref(loss),
                                     grad.ctypes.data if want_grad else None, _stream(stream)))
     return float(loss.value), grad

@@ -1,0 +1,121 @@
+"""Mixed-size batches (one launch per iteration over a work list of all
+grids) against single solves and the oracle: every solve of the batch is
+bit-identical to the same solve alone (same iteration form and tile height:
+identical arithmetic and reduction order), reaches the tolerance on the FP64
+true residual the oracle recomputes, and keeps its own status and timing."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2604_01800_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ppe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_01800_amd import ppe as P
+    P.lib()
+    return P
+
+
+def systems(shapes, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, (nx, ny) in enumerate(shapes):
+        g = inputs.with_ellipse(inputs.random_stretched_grid(nx, ny, rng), rng)
+        out.append((g, inputs.grf(g, seed * 100 + k).astype(np.float32)))
+    return out
+
+
+def run_batch(ppe, sys_, **kw):
+    probs = [ppe.ppe_problem_create(g) for g, _ in sys_]
+    fs = [torch.from_numpy(f).cuda() for _, f in sys_]
+    xs = [torch.zeros(f.shape, dtype=torch.float64, device="cuda") for _, f in sys_]
+    st, stats = ppe.ppe_solve_batch(probs, fs, xs, ppe.ppe_solve_opts_default(**kw))
+    return st, stats, [x.cpu().numpy() for x in xs], probs
+
+
+def true_res(g, f, x):
+    b, _ = oracle.rhs(g, f)
+    return np.linalg.norm(b - oracle.apply(g, x)) / np.linalg.norm(b)
+
+
+def test_mixed_batch_equals_single_solves(ppe):
+    sys_ = systems([(130, 67), (64, 64), (200, 150), (96, 256), (33, 21)], seed=1)
+    st, stats, xs, probs = run_batch(ppe, sys_, tol=1e-7, rows_per_wave=4)
+    assert st == ppe.PPE_OK
+    for (g, f), x, s, p in zip(sys_, xs, stats, probs):
+        assert true_res(g, f, x) <= 1e-7 * 1.001
+        assert abs(x.mean()) <= 1e-12 * np.abs(x).max()
+        fd = torch.from_numpy(f[None]).cuda()
+        xd = torch.zeros((1,) + f.shape, dtype=torch.float64, device="cuda")
+        st1, s1 = ppe.ppe_solve_plain(p, fd, xd, ppe.ppe_solve_opts_default(
+            tol=1e-7, rows_per_wave=4, variant=ppe.PPE_PCG_SINGLE_REDUCTION))
+        assert st1 == ppe.PPE_OK and s1[0]["iters_total"] == s["iters_total"]
+        np.testing.assert_array_equal(xd[0].cpu().numpy(), x)
+        assert 0.0 < s["ms_device"] <= s["ms_total"]
+
+
+def test_batch_statuses_are_per_solve(ppe):
+    sys_ = systems([(48, 40), (64, 32), (40, 40)], seed=2)
+    bad = sys_[1][1].copy()
+    bad[3, 5] = np.nan
+    sys_[1] = (sys_[1][0], bad)
+    st, stats, xs, _ = run_batch(ppe, sys_, tol=1e-6)
+    assert st == ppe.PPE_ERR_NONFINITE
+    assert [s["status"] for s in stats] == [ppe.PPE_OK, ppe.PPE_ERR_NONFINITE, ppe.PPE_OK]
+    for k in (0, 2):
+        assert true_res(sys_[k][0], sys_[k][1], xs[k]) <= 1e-6 * 1.001
+    # iteration limit: only the solve that needs more iterations stops short
+    sys_ = systems([(32, 32), (256, 256)], seed=3)
+    st, stats, xs, _ = run_batch(ppe, sys_, tol=1e-6, max_iter=300)
+    assert st == ppe.PPE_NOT_CONVERGED
+    assert stats[0]["status"] == ppe.PPE_OK and stats[1]["status"] == ppe.PPE_NOT_CONVERGED
+    assert stats[1]["iters_total"] == 300
+    assert abs(true_res(sys_[1][0], sys_[1][1], xs[1]) - stats[1]["rel_res_true"]) <= 1e-6 * stats[1]["rel_res_true"]
+
+
+def test_uneven_grids_workload(ppe):
+    """Twelve grids between 128^2 and 1024^2 (ellipse masks, GRF sources) in one
+    batch to 1e-6: every solve converges on the oracle's true residual; small
+    grids finish first on the device clock; aggregate rate printed."""
+    rng = np.random.default_rng(4)
+    sizes = [128, 256, 384, 512, 768, 1024]
+    shapes = [(int(rng.choice(sizes)), int(rng.choice(sizes))) for _ in range(12)]
+    sys_ = systems(shapes, seed=4)
+    st, stats, xs, _ = run_batch(ppe, sys_, tol=1e-6)
+    assert st == ppe.PPE_OK
+    for (g, f), x in zip(sys_, xs):
+        assert true_res(g, f, x) <= 1e-6 * 1.001
+    cells = [nx * ny for nx, ny in shapes]
+    small, large = int(np.argmin(cells)), int(np.argmax(cells))
+    assert stats[small]["ms_device"] < stats[large]["ms_device"]
+    print("uneven batch of %d grids: %.1f ms wall, %.2f solves/s; per-solve device ms %s" % (
+        len(shapes), stats[0]["ms_total"], 1e3 * len(shapes) / stats[0]["ms_total"],
+        [round(s["ms_device"], 1) for s in stats]))
+
+
+def test_batch_argument_checks(ppe):
+    sys_ = systems([(32, 32)], seed=5)
+    p = ppe.ppe_problem_create(sys_[0][0])
+    f = torch.from_numpy(sys_[0][1]).cuda()
+    x = torch.zeros(f.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(ppe.PPEError):  # the same problem twice
+        ppe.ppe_solve_batch([p, p], [f, f], [x, x.clone()])
+    with pytest.raises(ValueError):
+        ppe.ppe_solve_batch([p], [f[:16]], [x])
+    # a network is rejected before anything runs
+    arr = (ctypes.c_void_p * 1)(p.handle.value)
+    fa = (ctypes.c_void_p * 1)(f.data_ptr())
+    xa = (ctypes.c_void_p * 1)(x.data_ptr())
+    st = ppe.lib().ppe_solve_batch(1, ctypes.cast(arr, ctypes.c_void_p), ctypes.c_void_p(8),
+                                   ctypes.cast(fa, ctypes.c_void_p), ctypes.cast(xa, ctypes.c_void_p), None, None,
+                                   None)
+    assert st == ppe.PPE_ERR_UNSUPPORTED
+    assert ppe.lib().ppe_solve_batch(0, None, None, None, None, None, None, None) == ppe.PPE_OK
