@@ -63,3 +63,57 @@ def train(net, grids, R_dev, steps: int, batch: int, lr: float = 1e-3, log_every
             print(f"train step {k + 1}/{steps} loss {np.mean(losses[-log_every:]):.4e} "
                   f"({time.perf_counter() - t0:.1f} s)", flush=True)
     return losses
+
+
+def evaluate(net, n, count=6, seed=12345, tol=1e-6, max_iter=20000):
+    """Hybrid (with net) against plain Jacobi-PCG on held-out n x n systems
+    (random stretching and ellipse, GRF source); returns one dict per system."""
+    import torch
+    rng = np.random.default_rng(seed)
+    rows = []
+    for k in range(count):
+        g = inputs.with_ellipse(inputs.random_stretched_grid(n, n, rng), rng)
+        prob = ppe.ppe_problem_create(g)
+        f = torch.from_numpy(inputs.grf(g, 900 + k).astype(np.float32)[None]).cuda()
+        x = torch.zeros((1, n, n), dtype=torch.float64, device="cuda")
+        o = ppe.ppe_solve_opts_default(tol=tol, zero_x0=1, max_iter=max_iter)
+        st_p, sp = ppe.ppe_solve_plain(prob, f, x, o)
+        st_h, sh = ppe.ppe_solve_hybrid(prob, net, f, x, o)
+        rows.append({"n": n, "system": k, "plain_iters": sp[0]["iters_total"], "plain_ms": sp[0]["ms_device"],
+                     "hybrid_iters": sh[0]["iters_total"], "hybrid_dlsm": sh[0]["iters_dlsm"],
+                     "hybrid_ms": sh[0]["ms_device"], "hybrid_converged": st_h == ppe.PPE_OK})
+    return rows
+
+
+def main(argv=None):
+    """Train a DeepONet on fabricated n x n systems and compare the hybrid
+    solve with plain PCG on held-out systems (one JSON line per system)."""
+    import argparse
+    import json
+
+    import torch
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--pool", type=int, default=2048)
+    ap.add_argument("--steps", type=int, default=120000)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--out", default=None, help="save the trained network here")
+    ap.add_argument("--eval-sizes", default="64,128,256")
+    args = ap.parse_args(argv)
+    ppe.lib()
+    grids, R = make_pool(args.n, args.pool, seed=1)
+    net = ppe.Net(ppe.ppe_net_config_default(), seed=args.seed)
+    probs = [ppe.ppe_problem_create(g) for g in grids]
+    train(net, grids, torch.from_numpy(R).cuda(), steps=args.steps, batch=args.batch, lr=args.lr,
+          log_every=max(1, args.steps // 20), problems=probs, schedule="cosine")
+    if args.out:
+        ppe.ppe_net_save(net, args.out)
+    for n in (int(v) for v in args.eval_sizes.split(",") if v):
+        for row in evaluate(net, n, count=6 if n == args.n else 3):
+            print(json.dumps(row), flush=True)
+
+
+if __name__ == "__main__":
+    main()
