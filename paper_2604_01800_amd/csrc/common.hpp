@@ -54,9 +54,9 @@ struct SolveState {
   uint64_t t_start, t_done;
 };
 
-// MODE_FLUSH is used by the single-reduction iteration only (x += x_c, then
-// a MODE_TRUE launch).
-enum : int32_t { MODE_CG = 0, MODE_TRUE = 1, MODE_FLUSH = 2 };
+// MODE_FLUSH and MODE_SUMS are used by the single-reduction iteration only
+// (x += x_c, then MODE_TRUE, then MODE_SUMS before the next CG step).
+enum : int32_t { MODE_CG = 0, MODE_TRUE = 1, MODE_FLUSH = 2, MODE_SUMS = 3 };
 enum : int32_t { DONE_NO = 0, DONE_CONV = 1, DONE_MAXIT = 2, DONE_NONFINITE = 3 };
 
 // Per-call pointers kept in device memory so that a captured graph can be

@@ -21,10 +21,11 @@
 // write them (24 B); r and p alternate between two buffers by launch parity
 // because neighbouring workgroups read their halos.
 //
-// Reliable updates take two launches: FLUSH adds x_c into the FP64 solution,
-// TRUE recomputes r = b - A x in FP64 together with the five sums (ζ and π
-// from the kept direction p). Convergence is declared only on the FP64 true
-// residual. Every launch reads the state slots of the other parity, so no
+// Reliable updates take three launches: FLUSH adds x_c into the FP64
+// solution, TRUE recomputes r = b - A x in FP64 on each tile with |r|^2 (the
+// convergence judge), and SUMS forms the four sums of the next CG step from
+// the stored true residual and the kept direction p. Each of them needs no
+// more registers than the CG step, which keeps its occupancy. Every launch reads the state slots of the other parity, so no
 // workgroup reads what the same launch writes.
 #include <hip/hip_ext.h>
 
@@ -41,6 +42,34 @@ __device__ __forceinline__ double* sums_of(const PcgArgs& a, int par, int s, int
   return a.part1 + ((size_t)par * nbs + s) * kSums * a.P;
 }
 
+// FP64 sum over a wavefront on DPP lane moves (no LDS traffic): within each
+// row of 16 lanes, quad xor 1, quad xor 2, half-row mirror and row mirror
+// leave the row sum in every lane of the row (each step adds commuted equal
+// pairs, so all lanes hold the same bits); the four row sums are then added
+// in a fixed order. Every lane returns the same value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return ((readlane_f64(v, 0) + readlane_f64(v, 16)) + readlane_f64(v, 32)) + readlane_f64(v, 48);
+}
+
 // Fixed-order reduction of the five partial arrays ([5][P]); every workgroup
 // obtains the same bits.
 __device__ __forceinline__ void reduce5(const double* __restrict__ part, int P, double* lds, double (&out)[kSums]) {
@@ -53,7 +82,7 @@ __device__ __forceinline__ void reduce5(const double* __restrict__ part, int P, 
   }
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
-  for (int m = 0; m < kSums; ++m) v[m] = wave_sum(v[m]);
+  for (int m = 0; m < kSums; ++m) v[m] = wave_sum_dpp(v[m]);
   __syncthreads();
   if (lane == 0) {
 #pragma unroll
@@ -69,7 +98,7 @@ __device__ __forceinline__ void reduce5(const double* __restrict__ part, int P, 
 __device__ __forceinline__ void store5(double (&v)[kSums], double* lds, double* __restrict__ part, int P, int blk) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
-  for (int m = 0; m < kSums; ++m) v[m] = wave_sum(v[m]);
+  for (int m = 0; m < kSums; ++m) v[m] = wave_sum_dpp(v[m]);
   __syncthreads();
   if (lane == 0) {
 #pragma unroll
@@ -186,32 +215,27 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
   const double gam_prev = st->rho[pm], thr2 = st->thr2;
   double rr_ru = st->rr_ru[pm];
   const bool leader = blk == 0 && threadIdx.x == 0;
-  double sum[kSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (pmode != MODE_FLUSH) reduce5(sums_of(a, pm, s, nbs), P, lds, sum);
+  // Reduced whatever the previous mode (after a FLUSH the sums are stale and
+  // unused), so that these loads do not wait for the mode word.
+  double sum[kSums];
+  reduce5(sums_of(a, pm, s, nbs), P, lds, sum);
   if (dprev) {
     if (leader) st->dflag[par] = dprev;
     return;
   }
 
   // What this launch does.
-  int todo = MODE_CG, done = DONE_NO, rst_next = 0;
+  int todo = MODE_CG, rst_next = 0;
   double alpha = 0.0, beta = 0.0;
   if (pmode == MODE_FLUSH) {
     todo = MODE_TRUE;
-  } else {
-    const double gam = sum[0], del = sum[1], zet = sum[2], pip = sum[3], rr = sum[4];
-    bool flush;
-    bool rst = false;
-    if (pmode == MODE_TRUE) {
-      rr_ru = rr;
-      if (!isfinite(rr)) done = DONE_NONFINITE;
-      else if (rr <= thr2) done = DONE_CONV;
-      else if (it >= max_iter) done = DONE_MAXIT;
-      flush = false;
-      rst = restart;
-    } else {
-      flush = !isfinite(rr) || rr <= thr2 || rr <= delta2 * rr_ru || it >= max_iter;
-    }
+  } else if (pmode == MODE_TRUE) {
+    // The last launch computed the FP64 true residual: judge convergence.
+    const double rr = sum[4];
+    int done = DONE_NO;
+    if (!isfinite(rr)) done = DONE_NONFINITE;
+    else if (rr <= thr2) done = DONE_CONV;
+    else if (it >= max_iter) done = DONE_MAXIT;
     if (done) {
       if (leader) {
         st->rr_final = rr;
@@ -225,8 +249,15 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
       }
       return;
     }
+    todo = MODE_SUMS;
+    rr_ru = rr;
+  } else {
+    // CG step from the sums of a CG or SUMS launch; after SUMS the residual is
+    // fresh, so only a breakdown can send it back to a reliable update.
+    const double gam = sum[0], del = sum[1], zet = sum[2], pip = sum[3], rr = sum[4];
+    bool flush = pmode == MODE_CG && (!isfinite(rr) || rr <= thr2 || rr <= delta2 * rr_ru || it >= max_iter);
     if (!flush) {
-      beta = rst ? 0.0 : gam / gam_prev;
+      beta = (pmode == MODE_SUMS && restart) ? 0.0 : gam / gam_prev;
       if (!isfinite(beta)) beta = 0.0;
       const double pap = del + 2.0 * beta * zet + beta * beta * pip;
       alpha = gam / pap;
@@ -279,56 +310,54 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
 
   double acc[kSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (todo == MODE_TRUE) {
-    // Reliable update, part 2: r = b - A x in FP64 on the tile and its
-    // one-cell halo, z = D^-1 r, and the five sums with the kept direction p.
+    // Reliable update, part 2: r = b - A x in FP64 on the own rows (the x
+    // window walks down the column; the halo column gives east/west), and
+    // |r|^2 in FP64, the convergence judge. p is carried over.
     const auto xsr = make_rsrc(a.call->x + off, (uint64_t)a.N * 8);
     const auto fsr = make_rsrc(a.call->f + off, vbytes);
+    const auto rso = make_rsrc(rout, vbytes), pso = make_rsrc(pout, vbytes);
     const double bmean = st->bmean;
-    // x: own column rows j0-2 .. j0+R+1, first halo rows j0-2 .. j0+R+1,
-    // second halo rows j0 .. j0+R-1; f: own rows j0-1 .. j0+R, first halo
-    // rows j0 .. j0+R-1. Off the grid the loads return 0.
-    double xo[R + 4], x1[R + 4], x2[R];
-    float fo[R + 2], f1[R];
-#pragma unroll
-    for (int q = 0; q < R + 4; ++q) {
-      xo[q] = bload64(xsr, cell_off8(ci.ok, j0 - 2 + q, ny, nx, ci.i));
-      x1[q] = bload64(xsr, cell_off8(ci.hok, j0 - 2 + q, ny, nx, ci.ih));
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) x2[q] = bload64(xsr, cell_off8(h2.ok, j0 + q, ny, nx, h2.i));
-#pragma unroll
-    for (int q = 0; q < R + 2; ++q) fo[q] = bload(fsr, cell_off(ci.ok, j0 - 1 + q, ny, nx, ci.i));
-#pragma unroll
-    for (int q = 0; q < R; ++q) f1[q] = bload(fsr, cell_off(ci.hok, j0 + q, ny, nx, ci.ih));
-    float rf[R + 2], rfh[R];
-#pragma unroll
-    for (int q = 0; q < R + 2; ++q) {  // own column, row j0-1+q
-      const int j = j0 - 1 + q;
-      double xe, xw;
-      east_west(xo[q + 1], x1[q + 1], xe, xw);
-      const bool own_ok = ci.ok && j >= 0 && j < ny;
-      const double rv = true_res(a.c, ci.i, j, xo[q + 1], xe, xw, xo[q + 2], xo[q], fo[q], bmean);
-      rf[q] = own_ok ? (float)rv : 0.f;
-      if (q >= 1 && q <= R) acc[4] += own_ok ? rv * rv : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) {  // first halo column, row j0+q
+    const auto psr2 = make_rsrc(pin, vbytes);
+    double x_p = bload64(xsr, cell_off8(ci.ok, j0 - 1, ny, nx, ci.i));
+    double x_c = bload64(xsr, cell_off8(ci.ok, j0, ny, nx, ci.i));
+#pragma unroll 1
+    for (int q = 0; q < R; ++q) {
       const int j = j0 + q;
-      const double he = (lane == 0) ? xo[q + 2] : x2[q], hw = (lane == 0) ? x2[q] : xo[q + 2];
-      const double rv = true_res(a.c, ci.ih, j, x1[q + 2], he, hw, x1[q + 3], x1[q + 1], f1[q], bmean);
-      rfh[q] = (ci.hok && j < ny) ? (float)rv : 0.f;
+      const double x_n = bload64(xsr, cell_off8(ci.ok, j + 1, ny, nx, ci.i));
+      const double xh = bload64(xsr, cell_off8(ci.hok, j, ny, nx, ci.ih));
+      const float fv = bload(fsr, cell_off(ci.ok, j, ny, nx, ci.i));
+      double xe, xw;
+      east_west(x_c, xh, xe, xw);
+      const bool own_ok = ci.ok && j < ny;
+      const double rv = true_res(a.c, ci.i, j, x_c, xe, xw, x_n, x_p, fv, bmean);
+      const uint32_t o = cell_off(ci.ok, j, ny, nx, ci.i);
+      bstore(rso, o, (float)rv);
+      bstore(pso, o, bload(psr2, o));
+      acc[4] += own_ok ? rv * rv : 0.0;
+      x_p = x_c;
+      x_c = x_n;
     }
+    if (leader) {
+      st->mode[par] = MODE_TRUE;
+      st->it[par] = it;
+      st->it_cg[par] = itcg;
+      st->n_ru[par] = nru;
+      st->rho[par] = gam_prev;
+      st->rr_ru[par] = rr_ru;
+      st->restart[par] = restart;
+      st->dflag[par] = DONE_NO;
+    }
+  } else if (todo == MODE_SUMS) {
+    // Reliable update, part 3: the sums of the next CG step for the true
+    // residual r (now in memory with its halo) and the kept direction p:
+    // r.z, z.Az, z.Ap and p.Ap, with z = D^-1 r on the tile's one-cell halo.
     float z[R + 2], zh[R];
 #pragma unroll
-    for (int q = 0; q < R + 2; ++q) {
-      z[q] = rf[q];
-      if (JAC) z[q] = rf[q] * inv_diag(hy[q + 1], gy[q + 1], gy[q + 2], k.hx, k.gw, k.ge);
-    }
+    for (int q = 0; q < R + 2; ++q)
+      z[q] = ro[q + 1] * (JAC ? inv_diag(hy[q + 1], gy[q + 1], gy[q + 2], k.hx, k.gw, k.ge) : 1.f);
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      zh[q] = rfh[q];
-      if (JAC) zh[q] = rfh[q] * inv_diag(hy[q + 2], gy[q + 2], gy[q + 3], k.hxh, k.gwh, k.geh);
-    }
+    for (int q = 0; q < R; ++q)
+      zh[q] = r1[q + 1] * (JAC ? inv_diag(hy[q + 2], gy[q + 2], gy[q + 3], k.hxh, k.gwh, k.geh) : 1.f);
     const auto rso = make_rsrc(rout, vbytes), pso = make_rsrc(pout, vbytes);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -340,16 +369,17 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
       const float sp = stencil5(po[q + 2], pe, pw, po[q + 3], po[q + 1], hy[q + 2], gy[q + 2], gy[q + 3], k.hx, k.gw,
                                 k.ge);
       const uint32_t o = cell_off(ci.ok, j, ny, nx, ci.i);
-      bstore(rso, o, rf[q + 1]);
+      bstore(rso, o, ro[q + 2]);
       bstore(pso, o, po[q + 2]);
       // Off the grid every value and coefficient is 0, so the products are 0.
-      acc[0] += (double)rf[q + 1] * (double)z[q + 1];
+      acc[0] += (double)ro[q + 2] * (double)z[q + 1];
       acc[1] += (double)z[q + 1] * (double)Az;
       acc[2] += (double)z[q + 1] * (double)sp;
       acc[3] += (double)po[q + 2] * (double)sp;
+      acc[4] += (double)ro[q + 2] * (double)ro[q + 2];
     }
     if (leader) {
-      st->mode[par] = MODE_TRUE;
+      st->mode[par] = MODE_SUMS;
       st->it[par] = it;
       st->it_cg[par] = itcg;
       st->n_ru[par] = nru;
@@ -439,7 +469,7 @@ template <int R, bool JAC>
 __global__ __launch_bounds__(kBlock) void k_pcg1_multi(const PcgArgs* __restrict__ descs,
                                                        const uint32_t* __restrict__ work, int par) {
   __shared__ double lds[kSums * kWaves];
-  const uint32_t wv = work[blockIdx.x];
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(work[blockIdx.x]);
   pcg1_body<R, JAC>(descs[wv >> 20], 0, 1, (int)(wv & 0xFFFFFu), par, lds);
 }
 
