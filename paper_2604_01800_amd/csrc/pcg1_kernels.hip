@@ -126,19 +126,42 @@ __device__ __forceinline__ float inv_diag(float hyj, float gs, float gn, float h
   return __builtin_amdgcn_rcpf(fmaxf(diag_of(hyj, gs, gn, hx, gw, ge), 1e-30f));
 }
 
-// Second halo column: lane 0 takes column i0 - 2, lane 63 column i0 + 65.
-struct Halo2 {
-  int i;
-  bool ok;
+// Halo columns in transposed form: lanes 0-31 work on the west side and
+// lanes 32-63 on the east side of the wavefront's 64-column strip, one row
+// per lane (lane t of a side takes row j0 - 1 + t). On each side, column e is
+// the strip's edge column (i0 or i0 + 63), column h1 the first halo column
+// (i0 - 1 or i0 + 64) and column h2 the second (i0 - 2 or i0 + 65). A lane
+// loads and recomputes these few values itself, so the halo costs a handful
+// of wavefront instructions instead of a full pass per halo row; the edge
+// lanes 0 and 63 read the halo values back with readlane.
+struct HaloT {
+  int ce, c1, c2, j;         // columns and row of this lane's halo cell
+  bool oke, ok1, ok2;        // columns on the grid (and the tile valid)
+  bool east;                 // side
 };
 
-__device__ __forceinline__ Halo2 halo2(int nx, const TileXY& tl) {
+__device__ __forceinline__ HaloT halo_t(int nx, const TileXY& tl) {
   const int lane = threadIdx.x & (kWave - 1);
-  Halo2 h;
-  h.i = (lane == 0) ? tl.i0 - 2 : tl.i0 + kWave + 1;
-  h.ok = tl.valid && (lane == 0 || lane == kWave - 1) && h.i >= 0 && h.i < nx;
-  if (!h.ok) h.i = tl.i0;  // any readable column; its values are not used
+  HaloT h;
+  h.east = lane >= 32;
+  const int t = lane & 31;
+  h.j = tl.j0 - 1 + t;
+  h.ce = h.east ? tl.i0 + kWave - 1 : tl.i0;
+  h.c1 = h.east ? tl.i0 + kWave : tl.i0 - 1;
+  h.c2 = h.east ? tl.i0 + kWave + 1 : tl.i0 - 2;
+  h.oke = tl.valid && h.ce < nx;
+  h.ok1 = tl.valid && h.c1 >= 0 && h.c1 < nx;
+  h.ok2 = tl.valid && h.c2 >= 0 && h.c2 < nx;
   return h;
+}
+
+// Value of the halo lane for side row q (west: lane q, east: lane 32 + q) in
+// the edge lane of that side (lane 0 west, lane 63 east).
+__device__ __forceinline__ float from_halo(float v, int q) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+  const float e = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + q));
+  return lane < 32 ? w : e;
 }
 
 // FP64 true residual r = b - A x at (i, j) with b = hx hy f - mean(b); x
@@ -167,33 +190,25 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
   const int lane = threadIdx.x & (kWave - 1);
   const TileXY tl = tile_xy_at(nx, ny, R, blk);
   const ColIdx ci = col_idx(nx, tl);
-  const Halo2 h2 = halo2(nx, tl);
+  const HaloT ht = halo_t(nx, tl);
   const int j0 = tl.j0;
 
-  // Tile loads of the CG step first (they do not depend on the scalars):
-  // own column rows j0-2 .. j0+R+1, first halo column rows j0-1 .. j0+R,
-  // second halo column rows j0 .. j0+R-1.
+  // Tile loads of the CG step first (they do not depend on the scalars): own
+  // column rows j0-2 .. j0+R+1, and the transposed halo cells.
   const uint64_t vbytes = (uint64_t)a.N * 4;
   const auto rsr = make_rsrc(rin, vbytes), psr = make_rsrc(pin, vbytes);
-  float ro[R + 4], po[R + 4], r1[R + 2], p1[R + 2], r2[R], p2[R], xcv[R];
+  float ro[R + 4], po[R + 4], xcv[R];
 #pragma unroll
   for (int q = 0; q < R + 4; ++q) {
     const uint32_t o = cell_off(ci.ok, j0 - 2 + q, ny, nx, ci.i);
     ro[q] = bload(rsr, o);
     po[q] = bload(psr, o);
   }
-#pragma unroll
-  for (int q = 0; q < R + 2; ++q) {
-    const uint32_t o = cell_off(ci.hok, j0 - 1 + q, ny, nx, ci.ih);
-    r1[q] = bload(rsr, o);
-    p1[q] = bload(psr, o);
-  }
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const uint32_t o = cell_off(h2.ok, j0 + q, ny, nx, h2.i);
-    r2[q] = bload(rsr, o);
-    p2[q] = bload(psr, o);
-  }
+  const uint32_t oe = cell_off(ht.oke, ht.j, ny, nx, ht.ce), o1 = cell_off(ht.ok1, ht.j, ny, nx, ht.c1),
+                 o2 = cell_off(ht.ok2, ht.j, ny, nx, ht.c2);
+  const float hre = bload(rsr, oe), hpe = bload(psr, oe);
+  const float hr1 = bload(rsr, o1), hp1 = bload(psr, o1);
+  const float hr2 = bload(rsr, o2), hp2 = bload(psr, o2);
   load_rows_own<R>(make_rsrc(xc, vbytes), nx, ny, j0, ci, xcv);
   // Row coefficients of rows j0-2 .. j0+R+1 (faces j0-2 .. j0+R+2); padded arrays.
   float hy[R + 4], gy[R + 5];
@@ -202,8 +217,11 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
 #pragma unroll
   for (int q = 0; q < R + 5; ++q) gy[q] = a.c.gy[j0 - 2 + q];
   const ColCoef<float> k = load_cols<float>(a.c.hx, a.c.gx, ci);
-  float hx2 = a.c.hx[h2.i], gw2 = a.c.gx[h2.i], ge2 = a.c.gx[h2.i + 1];
-  if (!h2.ok) hx2 = gw2 = ge2 = 0.f;
+  // the halo lane's row and columns
+  const float hy_t = a.c.hy[ht.j], gs_t = a.c.gy[ht.j], gn_t = a.c.gy[ht.j + 1];
+  const float hxe = a.c.hx[ht.ce], gwe = a.c.gx[ht.ce], gee = a.c.gx[ht.ce + 1];
+  const float hx1 = a.c.hx[ht.c1], gw1 = a.c.gx[ht.c1], ge1 = a.c.gx[ht.c1 + 1];
+  const float hx2 = a.c.hx[ht.c2], gw2 = a.c.gx[ht.c2], ge2 = a.c.gx[ht.c2 + 1];
 
   // State of the previous launch (never written by this launch).
   const int dprev = st->dflag[pm];
@@ -351,20 +369,23 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
     // Reliable update, part 3: the sums of the next CG step for the true
     // residual r (now in memory with its halo) and the kept direction p:
     // r.z, z.Az, z.Ap and p.Ap, with z = D^-1 r on the tile's one-cell halo.
-    float z[R + 2], zh[R];
+    float z[R + 2], zh[R], ph[R];
 #pragma unroll
     for (int q = 0; q < R + 2; ++q)
       z[q] = ro[q + 1] * (JAC ? inv_diag(hy[q + 1], gy[q + 1], gy[q + 2], k.hx, k.gw, k.ge) : 1.f);
+    const float zt = hr1 * (JAC ? inv_diag(hy_t, gs_t, gn_t, hx1, gw1, ge1) : 1.f);
 #pragma unroll
-    for (int q = 0; q < R; ++q)
-      zh[q] = r1[q + 1] * (JAC ? inv_diag(hy[q + 2], gy[q + 2], gy[q + 3], k.hxh, k.gwh, k.geh) : 1.f);
+    for (int q = 0; q < R; ++q) {
+      zh[q] = from_halo(zt, q + 1);
+      ph[q] = from_halo(hp1, q + 1);
+    }
     const auto rso = make_rsrc(rout, vbytes), pso = make_rsrc(pout, vbytes);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int j = j0 + q;
       float ze, zw, pe, pw;
       east_west(z[q + 1], zh[q], ze, zw);
-      east_west(po[q + 2], p1[q + 1], pe, pw);
+      east_west(po[q + 2], ph[q], pe, pw);
       const float Az = stencil5(z[q + 1], ze, zw, z[q + 2], z[q], hy[q + 2], gy[q + 2], gy[q + 3], k.hx, k.gw, k.ge);
       const float sp = stencil5(po[q + 2], pe, pw, po[q + 3], po[q + 1], hy[q + 2], gy[q + 2], gy[q + 3], k.hx, k.gw,
                                 k.ge);
@@ -389,47 +410,46 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
       st->dflag[par] = DONE_NO;
     }
   } else {
-    // CG step. z and p on the two-cell halo ...
+    // CG step. z and p on the own rows and, in the halo lanes, on the edge
+    // and halo cells of this lane's row ...
     const float bet = (float)beta;
     const bool rst = beta == 0.0;
-    float pv[R + 4], pv1[R + 2], pv2[R], dv[R + 4], dv1[R + 2];
+    float pv[R + 4], dv[R + 4];
 #pragma unroll
     for (int q = 0; q < R + 4; ++q) {
       dv[q] = JAC ? inv_diag(hy[q], gy[q], gy[q + 1], k.hx, k.gw, k.ge) : 1.f;
       const float zv = ro[q] * dv[q];
       pv[q] = rst ? zv : zv + bet * po[q];
     }
-#pragma unroll
-    for (int q = 0; q < R + 2; ++q) {
-      dv1[q] = JAC ? inv_diag(hy[q + 1], gy[q + 1], gy[q + 2], k.hxh, k.gwh, k.geh) : 1.f;
-      const float zv = r1[q] * dv1[q];
-      pv1[q] = rst ? zv : zv + bet * p1[q];
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const float d2 = JAC ? inv_diag(hy[q + 2], gy[q + 2], gy[q + 3], hx2, gw2, ge2) : 1.f;
-      const float zv = r2[q] * d2;
-      pv2[q] = rst ? zv : zv + bet * p2[q];
-    }
-    // ... s = A p, r_{k+1} = r_k - alpha s and z_{k+1} on the one-cell halo ...
+    const float de = JAC ? inv_diag(hy_t, gs_t, gn_t, hxe, gwe, gee) : 1.f;
+    const float d1 = JAC ? inv_diag(hy_t, gs_t, gn_t, hx1, gw1, ge1) : 1.f;
+    const float d2 = JAC ? inv_diag(hy_t, gs_t, gn_t, hx2, gw2, ge2) : 1.f;
+    const float pte = rst ? hre * de : hre * de + bet * hpe;
+    const float pt1 = rst ? hr1 * d1 : hr1 * d1 + bet * hp1;
+    const float pt2 = rst ? hr2 * d2 : hr2 * d2 + bet * hp2;
+    // ... s = A p, r_{k+1} = r_k - alpha s and z_{k+1} on the halo column
+    // (rows from the neighbouring lanes of the same side) ...
     const float alf = (float)alpha;
-    float sv[R + 2], rn[R + 2], zn[R + 2], rn1[R], zn1[R];
+    const int pbits = __float_as_int(pt1);
+    const float pt1n = __int_as_float(__builtin_amdgcn_update_dpp(0, pbits, 0x130, 0xf, 0xf, false));  // row + 1
+    const float pt1s = __int_as_float(__builtin_amdgcn_update_dpp(0, pbits, 0x138, 0xf, 0xf, false));  // row - 1
+    const float hve = ht.east ? pt2 : pte, hvw = ht.east ? pte : pt2;
+    const float st1 = stencil5(pt1, hve, hvw, pt1n, pt1s, hy_t, gs_t, gn_t, hx1, gw1, ge1);
+    const float zt1 = (hr1 - alf * st1) * d1;
+    float p1h[R + 2], z1h[R];
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) p1h[q] = from_halo(pt1, q);
+#pragma unroll
+    for (int q = 0; q < R; ++q) z1h[q] = from_halo(zt1, q + 1);
+    // ... and on the own rows j0-1 .. j0+R ...
+    float sv[R + 2], rn[R + 2], zn[R + 2];
 #pragma unroll
     for (int q = 0; q < R + 2; ++q) {  // own column, row j0-1+q
       float pe, pw;
-      east_west(pv[q + 1], pv1[q], pe, pw);
+      east_west(pv[q + 1], p1h[q], pe, pw);
       sv[q] = stencil5(pv[q + 1], pe, pw, pv[q + 2], pv[q], hy[q + 1], gy[q + 1], gy[q + 2], k.hx, k.gw, k.ge);
       rn[q] = ro[q + 1] - alf * sv[q];
       zn[q] = rn[q] * dv[q + 1];
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) {  // first halo column, row j0+q
-      const float pe = (lane == 0) ? pv[q + 2] : pv2[q];
-      const float pw = (lane == 0) ? pv2[q] : pv[q + 2];
-      const float s1 = stencil5(pv1[q + 1], pe, pw, pv1[q + 2], pv1[q], hy[q + 2], gy[q + 2], gy[q + 3], k.hxh,
-                                k.gwh, k.geh);
-      rn1[q] = r1[q + 1] - alf * s1;
-      zn1[q] = rn1[q] * dv1[q + 1];
     }
     // ... then A z_{k+1} on the tile, the stores and the sums.
     const auto rso = make_rsrc(rout, vbytes), pso = make_rsrc(pout, vbytes), xso = make_rsrc(xc, vbytes);
@@ -437,7 +457,7 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
     for (int q = 0; q < R; ++q) {
       const int j = j0 + q;
       float ze, zw;
-      east_west(zn[q + 1], zn1[q], ze, zw);
+      east_west(zn[q + 1], z1h[q], ze, zw);
       const float Az = stencil5(zn[q + 1], ze, zw, zn[q + 2], zn[q], hy[q + 2], gy[q + 2], gy[q + 3], k.hx, k.gw,
                                 k.ge);
       const float pk = pv[q + 2];
