@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--variant", choices=["auto", "single", "two_phase"], default="auto",
                     help="PCG iteration form: tuned on the workload before timing (auto, default), "
                          "one reduction per iteration, or two")
+    ap.add_argument("--rows", type=int, default=0, choices=[0, 2, 4, 8, 16],
+                    help="tile height (rows per wavefront); 0 = tuned or default")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the phase-kernel timing launches and a 64 MiB calibration copy "
                          "(for hardware-counter runs)")
@@ -113,12 +115,12 @@ def main():
                "two_phase": ppe.PPE_PCG_TWO_PHASE}[args.variant]
     opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, variant=variant)
     tuning = None
-    if variant == ppe.PPE_PCG_AUTO and not args.kernels_only:
+    if variant == ppe.PPE_PCG_AUTO and not args.kernels_only and args.rows == 0:
         # Launch-configuration tuning on the workload itself, before any timing.
         tuning = ppe.ppe_tune_pcg(prob, f, torch.zeros_like(x), reps=20)
         variant, rows = tuning["variant"], tuning["rows_per_wave"]
     else:
-        rows = ppe.ppe_get_tuning(prob, 1)[1] if variant == ppe.PPE_PCG_AUTO else 0
+        rows = args.rows or (ppe.ppe_get_tuning(prob, 1)[1] if variant == ppe.PPE_PCG_AUTO else 0)
         if variant == ppe.PPE_PCG_AUTO:
             variant = ppe.ppe_get_tuning(prob, 1)[0]
     opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, variant=variant, rows_per_wave=rows)

@@ -132,8 +132,9 @@ int default_rows(const ppe_problem* p, int nb) {
 static constexpr int64_t kSingleMaxCells = (int64_t)2 << 20;
 
 static int default_rows_single(int64_t cells) {
-  if (cells >= (int64_t)1 << 20) return 8;
-  if (cells >= (int64_t)1 << 17) return 4;
+  if (cells >= (int64_t)1 << 20) return 16;
+  if (cells >= (int64_t)1 << 18) return 8;
+  if (cells >= (int64_t)1 << 16) return 4;
   return 2;
 }
 
