@@ -9,12 +9,18 @@ typedef uint16_t bf16_t;  // BF16 stored as raw bits
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
+// Round-to-nearest-even FP32 -> BF16 (NaN kept quiet): the hardware
+// conversion (v_cvt_pk_bf16_f32) in device code, the same rounding in
+// software on the host.
 __host__ __device__ __forceinline__ bf16_t f2bf(float f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_bit_cast(bf16_t, (__bf16)f);
+#else
   uint32_t u = __builtin_bit_cast(uint32_t, f);
   if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (bf16_t)((u >> 16) | 0x40);
   u += 0x7fffu + ((u >> 16) & 1u);
   return (bf16_t)(u >> 16);
+#endif
 }
 
 __host__ __device__ __forceinline__ float bf2f(bf16_t h) {

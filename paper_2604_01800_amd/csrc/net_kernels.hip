@@ -9,16 +9,22 @@ namespace ppe {
 
 // ---------------------------------------------------------------------------
 // Convolution as an implicit GEMM: out[px][co] = sum_k Wp[co][k] * Xbar[px, k]
-// with k running over (tap, input channel). One workgroup computes an
-// 8 x 16 pixel tile for TN output channels; wave w owns tile rows 2w, 2w+1.
-// MFMA 16x16x32 BF16 with A = weights (M = output channels) and B = staged
-// inputs (N = 16 pixels of one tile row), FP32 accumulation. Input channels
-// are staged through LDS in chunks of 32 (with the halo for 3x3), multiplied
-// by the Mesh-Conv local weight eta on the way (Eq. 18). Each lane's eight
-// consecutive K values are one (tap, 8-channel group); the packed weight
-// layout enumerates the groups of a chunk in the same order, zero-filled to a
-// multiple of four groups. TAPS = 9 (3x3, zero padding) or 1 (1x1). UP = the
-// output is written to the 2x nearest-upsampled pixels of a finer level.
+// with k running over (tap, input channel). One workgroup computes a 16 x 16
+// pixel tile for TN output channels; wave w owns tile rows 4w .. 4w+3, so each
+// K-step issues (TN/16) x 4 MFMA 16x16x32 BF16 (A = weights, M = output
+// channels; B = staged inputs, N = 16 pixels of one tile row; FP32
+// accumulation) and every operand fragment feeds 4 (or TN/16) of them. Input
+// channels are staged through LDS in chunks of 32 (with the 3x3 halo),
+// multiplied by the Mesh-Conv local weight eta on the way (Eq. 18). The
+// weight fragments are read straight from the packed weights (L2-resident,
+// shared by all workgroups) one K-step ahead, through a buffer resource whose
+// size ends at the last output channel, so channels past cout read as 0. Each
+// lane's eight consecutive K values are one (tap, 8-channel group); the packed
+// weight layout enumerates the groups of a chunk in the same order,
+// zero-filled to a multiple of four groups. TAPS = 9 (3x3, zero padding) or 1
+// (1x1). UP = the output is written to the 2x nearest-upsampled pixels of a
+// finer level.
+constexpr int kCTH = 16, kCTW = 16;  // pixel tile of the convolution kernel
 
 __device__ __forceinline__ uint4 mul_bf16x8(uint4 v, uint4 e) {
   uint32_t a[4] = {v.x, v.y, v.z, v.w}, b[4] = {e.x, e.y, e.z, e.w}, o[4];
@@ -31,42 +37,52 @@ __device__ __forceinline__ uint4 mul_bf16x8(uint4 v, uint4 e) {
   return make_uint4(o[0], o[1], o[2], o[3]);
 }
 
+__device__ __forceinline__ bf16x8_t load_wfrag(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0);
+  return __builtin_bit_cast(bf16x8_t, v);
+}
+
 template <int TN, int TAPS, bool UP>
 __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta,
                                               const bf16_t* __restrict__ wp, int Kp, const float* __restrict__ bias,
                                               bf16_t* __restrict__ y) {
   constexpr int HALO = TAPS == 9 ? 1 : 0;
-  constexpr int LW = kConvTW + 2 * HALO, LH = kConvTH + 2 * HALO;
+  constexpr int LW = kCTW + 2 * HALO, LH = kCTH + 2 * HALO;
   constexpr int NPIX = LW * LH;
-  constexpr int CKP = kConvCK + 8;                 // LDS pixel pitch (bank-conflict padding)
-  constexpr int KW = ((TAPS * 4 + 3) / 4) * 32;    // weight columns per chunk (32 channels)
-  constexpr int KWP = KW + 8;
-  constexpr int MT = TN / 16;
+  constexpr int CKP = kConvCK + 8;  // LDS pixel pitch (bank-conflict padding)
+  constexpr int MT = TN / 16, NT = 4;
   __shared__ __attribute__((aligned(16))) bf16_t s_x[NPIX * CKP];
-  __shared__ __attribute__((aligned(16))) bf16_t s_w[TN * KWP];
 
-  const int tiles_x = (g.W + kConvTW - 1) / kConvTW;
-  const int px0 = (blockIdx.x % tiles_x) * kConvTW;
-  const int py0 = (blockIdx.x / tiles_x) * kConvTH;
+  const int tiles_x = (g.W + kCTW - 1) / kCTW;
+  const int px0 = (blockIdx.x % tiles_x) * kCTW;
+  const int py0 = (blockIdx.x / tiles_x) * kCTH;
   const int co0 = blockIdx.y * TN;
   const int smp = blockIdx.z;
   x += smp * g.x_bstride;
   y += smp * g.y_bstride;
   if (eta) eta += smp * g.e_bstride;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const __amdgpu_buffer_rsrc_t wr =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(wp), (short)0, (int)((int64_t)g.cout * Kp * 2), 0x00020000);
+  // byte offset of this lane's A fragment for output-channel tile mt at K = k
+  auto woff = [&](int mt, int k) -> uint32_t {
+    return (uint32_t)(((co0 + mt * 16 + (lane & 15)) * Kp + k + (lane >> 4) * 8) * 2);
+  };
 
-  f32x4_t acc[MT][2];
+  f32x4_t acc[MT][NT];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
-    for (int n = 0; n < 2; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int n = 0; n < NT; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
   int kbase = 0;
   for (int c0 = 0; c0 < g.cin8; c0 += kConvCK) {
     const int ck = min(kConvCK, g.cin8 - c0);
     const int ck8 = ck / 8;
     const int steps = conv_chunk_steps(TAPS, ck);
-    const int kw = steps * 32;
+    bf16x8_t afr[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) afr[mt] = load_wfrag(wr, woff(mt, kbase));
     __syncthreads();
     for (int u = threadIdx.x; u < NPIX * ck8; u += 256) {
       const int pix = u / ck8, c8 = u - pix * ck8;
@@ -80,37 +96,38 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const bf16_t* __restric
       }
       *(uint4*)(s_x + pix * CKP + c8 * 8) = v;
     }
-    for (int u = threadIdx.x; u < TN * (kw / 8); u += 256) {
-      const int row = u / (kw / 8), k8 = u - row * (kw / 8);
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (co0 + row < g.cout) v = *(const uint4*)(wp + (size_t)(co0 + row) * Kp + kbase + k8 * 8);
-      *(uint4*)(s_w + row * KWP + k8 * 8) = v;
-    }
     __syncthreads();
     for (int st = 0; st < steps; ++st) {
+      bf16x8_t anx[MT];
+      if (st + 1 < steps) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) anx[mt] = load_wfrag(wr, woff(mt, kbase + (st + 1) * 32));
+      }
       const int G = st * 4 + (lane >> 4);
       int tap = G / ck8;
       const int c8 = G - tap * ck8;
       if (tap >= TAPS) tap = TAPS - 1;  // zero-weight padding group: any in-bounds input
       const int dy = TAPS == 9 ? tap / 3 : 0, dx = TAPS == 9 ? tap % 3 : 0;
-      bf16x8_t bfr[2];
+      bf16x8_t bfr[NT];
 #pragma unroll
-      for (int nt = 0; nt < 2; ++nt) {
-        const int pix = (2 * wv + nt + dy) * LW + (lane & 15) + dx;
+      for (int nt = 0; nt < NT; ++nt) {
+        const int pix = (NT * wv + nt + dy) * LW + (lane & 15) + dx;
         bfr[nt] = *(const bf16x8_t*)(s_x + pix * CKP + c8 * 8);
       }
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const bf16x8_t afr = *(const bf16x8_t*)(s_w + (mt * 16 + (lane & 15)) * KWP + st * 32 + (lane >> 4) * 8);
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[nt], acc[mt][nt], 0, 0, 0);
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[mt], bfr[nt], acc[mt][nt], 0, 0, 0);
+      if (st + 1 < steps) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) afr[mt] = anx[mt];
       }
     }
-    kbase += kw;
+    kbase += steps * 32;
   }
 
-  // Epilogue: lane holds out[co0 + mt*16 + 4*(lane>>4) + j][pixel (row 2w+nt, col lane&15)].
+  // Epilogue: lane holds out[co0 + mt*16 + 4*(lane>>4) + j][pixel (row NT*w+nt, col lane&15)].
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const int co = co0 + mt * 16 + 4 * (lane >> 4);
@@ -118,8 +135,8 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const bf16_t* __restric
     const float b0 = bias ? bias[co] : 0.f, b1 = bias ? bias[co + 1] : 0.f;
     const float b2 = bias ? bias[co + 2] : 0.f, b3 = bias ? bias[co + 3] : 0.f;
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const int py = py0 + 2 * wv + nt, px = px0 + (lane & 15);
+    for (int nt = 0; nt < NT; ++nt) {
+      const int py = py0 + NT * wv + nt, px = px0 + (lane & 15);
       if (py >= g.H || px >= g.W) continue;
       float v0 = acc[mt][nt][0] + b0, v1 = acc[mt][nt][1] + b1, v2 = acc[mt][nt][2] + b2, v3 = acc[mt][nt][3] + b3;
       if (g.act == 1) {
@@ -376,7 +393,7 @@ __global__ void k_deeponet_out(int64_t npix, int c0, const bf16_t* __restrict__ 
 // Launchers.
 void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
                  int Kp, const float* bias, bf16_t* y, hipStream_t s) {
-  const int tiles = ((g.W + kConvTW - 1) / kConvTW) * ((g.H + kConvTH - 1) / kConvTH);
+  const int tiles = ((g.W + kCTW - 1) / kCTW) * ((g.H + kCTH - 1) / kCTH);
   const int TN = g.cout >= 64 ? 64 : 32;
   const dim3 grid(tiles, (g.cout + TN - 1) / TN, nb);
   if (taps == 9) {
