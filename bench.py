@@ -93,6 +93,9 @@ def main():
                          "one reduction per iteration, or two")
     ap.add_argument("--rows", type=int, default=0, choices=[0, 2, 4, 8, 16],
                     help="tile height (rows per wavefront); 0 = tuned or default")
+    ap.add_argument("--network-forward", type=int, default=0, metavar="K",
+                    help="time K forwards of the default DeepONet (random weights) on the workload's grid "
+                         "instead (for kernel traces of the network)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the phase-kernel timing launches and a 64 MiB calibration copy "
                          "(for hardware-counter runs)")
@@ -111,6 +114,22 @@ def main():
     prob = ppe.ppe_problem_create(g)
     f = torch.from_numpy(f_np[None]).cuda()
     x = torch.zeros((1, g.ny, g.nx), dtype=torch.float64, device="cuda")
+    if args.network_forward:
+        net = ppe.Net(ppe.ppe_net_config_default(), seed=1)
+        r = torch.from_numpy(f_np[None]).cuda()
+        y = torch.zeros_like(r)
+        for _ in range(3):
+            ppe.ppe_net_forward(net, prob, r, y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.network_forward):
+            ppe.ppe_net_forward(net, prob, r, y)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.network_forward * 1e3
+        print(json.dumps({"network_forward_ms": ms, "grid": [g.nx, g.ny], "forwards": args.network_forward}),
+              flush=True)
+        return
+
     variant = {"auto": ppe.PPE_PCG_AUTO, "single": ppe.PPE_PCG_SINGLE_REDUCTION,
                "two_phase": ppe.PPE_PCG_TWO_PHASE}[args.variant]
     opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, variant=variant)
