@@ -140,7 +140,7 @@ typedef struct {
    * (default 512). */
   float grf_len_lo, grf_len_hi;
   int32_t grf_features;
-  int32_t reserved;
+  float clip_norm;              /* > 0: scale the gradient to this L2 norm before Adam when larger (default 0) */
 } ppe_train_opts;
 
 /* ---- problem (Sec. 8 a1: per-grid setup, built once and reused, as the paper

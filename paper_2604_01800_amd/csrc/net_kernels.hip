@@ -439,6 +439,10 @@ void launch_fill_static(int H, int W, int pitch, int coff, const float* hxn, con
                                                                        bstride);
 }
 
+void launch_sumsq(const float* r, int64_t n, int nb, double* part, hipStream_t s) {
+  k_sumsq<<<dim3(kRedBlocks, nb), 256, 0, s>>>(r, n, part);
+}
+
 void launch_input_pack(const float* r, int64_t n, int nb, double* part, bf16_t* xin, int pitch, int64_t bstride,
                        hipStream_t s) {
   k_sumsq<<<dim3(kRedBlocks, nb), 256, 0, s>>>(r, n, part);

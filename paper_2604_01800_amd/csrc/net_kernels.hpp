@@ -26,6 +26,8 @@ void launch_trunk_fold(int H, int W, const float* xin, const float* yin, const f
                        float* out, hipStream_t s);
 void launch_fill_static(int H, int W, int pitch, int coff, const float* hxn, const float* hyn, const uint8_t* mask,
                         int moff, bf16_t* buf, int64_t bstride, int nb, hipStream_t s);
+// Per-sample partial sums of r^2 (kRedBlocks per sample, [nb][kRedBlocks]).
+void launch_sumsq(const float* r, int64_t n, int nb, double* part, hipStream_t s);
 void launch_input_pack(const float* r, int64_t n, int nb, double* part, bf16_t* xin, int pitch, int64_t bstride,
                        hipStream_t s);
 void launch_pool2(int Ho, int Wo, int C, const bf16_t* in, int pin, int cin_off, int64_t in_bs, bf16_t* out, int pout,

@@ -237,7 +237,7 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
   // unused), so that these loads do not wait for the mode word.
   double sum[kSums];
   reduce5(sums_of(a, pm, s, nbs), P, lds, sum);
-  if (dprev) {
+  if (__builtin_expect(dprev != 0, 0)) {
     if (leader) st->dflag[par] = dprev;
     return;
   }
@@ -245,9 +245,9 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
   // What this launch does.
   int todo = MODE_CG, rst_next = 0;
   double alpha = 0.0, beta = 0.0;
-  if (pmode == MODE_FLUSH) {
+  if (__builtin_expect(pmode == MODE_FLUSH, 0)) {
     todo = MODE_TRUE;
-  } else if (pmode == MODE_TRUE) {
+  } else if (__builtin_expect(pmode == MODE_TRUE, 0)) {
     // The last launch computed the FP64 true residual: judge convergence.
     const double rr = sum[4];
     int done = DONE_NO;
@@ -299,7 +299,7 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
     }
   }
 
-  if (todo == MODE_FLUSH) {
+  if (__builtin_expect(todo == MODE_FLUSH, 0)) {
     // Reliable update, part 1: x += x_c in FP64, x_c = 0, p carried over.
     const auto xsr = make_rsrc(a.call->x + off, (uint64_t)a.N * 8);
     const auto xcs = make_rsrc(xc, vbytes), pso = make_rsrc(pout, vbytes);
@@ -327,7 +327,7 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
   }
 
   double acc[kSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (todo == MODE_TRUE) {
+  if (__builtin_expect(todo == MODE_TRUE, 0)) {
     // Reliable update, part 2: r = b - A x in FP64 on the own rows (the x
     // window walks down the column; the halo column gives east/west), and
     // |r|^2 in FP64, the convergence judge. p is carried over.
@@ -365,7 +365,7 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
       st->restart[par] = restart;
       st->dflag[par] = DONE_NO;
     }
-  } else if (todo == MODE_SUMS) {
+  } else if (__builtin_expect(todo == MODE_SUMS, 0)) {
     // Reliable update, part 3: the sums of the next CG step for the true
     // residual r (now in memory with its halo) and the kept direction p:
     // r.z, z.Az, z.Ap and p.Ap, with z = D^-1 r on the tile's one-cell halo.

@@ -58,6 +58,7 @@ struct TrainState {
   // generated right-hand sides (R == NULL)
   GenWs gen;
   float* d_R = nullptr;  // [nb][N]
+  double* gpart = nullptr;  // [kRedBlocks] partial sums of the squared gradient (clipping)
 };
 
 static int pad8(int c) { return (c + 7) / 8 * 8; }
@@ -70,6 +71,7 @@ void net_train_free(ppe_net* n) {
   dev_free((void*)t->d_masks);
   gen_free(t->gen);
   dev_free(t->d_R);
+  dev_free(t->gpart);
   dev_free(t->act);
   dev_free(t->grad);
   dev_free(t->eta);
@@ -219,6 +221,8 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
     ppe_status sg = check_gen_opts(*opts);
     if (sg != PPE_OK) return sg;
   }
+  if (!(opts->clip_norm >= 0.f) || !std::isfinite(opts->clip_norm))
+    return set_error(PPE_ERR_INVALID_ARG, "clip_norm must be finite and >= 0");
   for (int i = 0; i < nb; ++i) {
     if (!problems[i]) return set_error(PPE_ERR_INVALID_ARG, "problems[%d] is NULL", i);
     if (problems[i]->nx != problems[0]->nx || problems[i]->ny != problems[0]->ny)
@@ -512,7 +516,13 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
     n->step += 1;
     const float c1 = 1.f - std::pow(opts->beta1, (float)n->step);
     const float c2 = 1.f - std::pow(opts->beta2, (float)n->step);
-    launch_adam(n->np, n->d_w, dG, n->d_m, n->d_v, opts->lr, opts->beta1, opts->beta2, opts->eps, c1, c2, s);
+    if (opts->clip_norm > 0.f) {
+      if (!t->gpart) t->gpart = (double*)dev_alloc(sizeof(double) * kRedBlocks);
+      if (!t->gpart) return set_error(PPE_ERR_HIP, "allocation of the gradient-norm partials failed");
+      launch_sumsq(dG, n->np, 1, t->gpart, s);
+    }
+    launch_adam(n->np, n->d_w, dG, n->d_m, n->d_v, opts->lr, opts->beta1, opts->beta2, opts->eps, c1, c2, t->gpart,
+                opts->clip_norm, s);
     st = net_refresh(n, s);
     if (st != PPE_OK) return st;
   }

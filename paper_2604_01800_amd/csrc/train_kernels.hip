@@ -6,6 +6,7 @@
 
 #include "common.hpp"
 #include "net_common.hpp"
+#include "net_kernels.hpp"
 #include "train_kernels.hpp"
 
 namespace ppe {
@@ -531,12 +532,23 @@ __global__ void k_sum_parts(const double* __restrict__ part, int n, double scale
   out[0] = scale * s;
 }
 
-// Adam (Kingma & Ba 2015, Alg. 1) on the FP32 master parameters.
-__global__ void k_adam(int64_t n, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+// Adam (Kingma & Ba 2015, Alg. 1) on the FP32 master parameters. With
+// clip > 0 the gradient is first scaled by min(1, clip / ||g||), ||g||^2 being
+// the fixed-order sum of the kRedBlocks partial sums in gpart (the same bits
+// in every workgroup).
+__global__ __launch_bounds__(256) void k_adam(int64_t n, float* __restrict__ w, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                                              float b2, float eps, float c1, float c2, const double* __restrict__ gpart,
+                                              float clip) {
+  __shared__ double lds[kWaves];
+  float scale = 1.f;
+  if (clip > 0.f) {
+    const double gn = sqrt(reduce_partials(gpart, kRedBlocks, lds));
+    if (gn > (double)clip) scale = (float)((double)clip / gn);
+  }
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  const float gk = g[k];
+  const float gk = g[k] * scale;
   const float mk = b1 * m[k] + (1.f - b1) * gk;
   const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
   m[k] = mk;
@@ -630,8 +642,8 @@ void launch_sum_parts(const double* part, int n, double scale, double* out, hipS
 }
 
 void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
-                 float c1, float c2, hipStream_t s) {
-  k_adam<<<nblk(n), 256, 0, s>>>(n, w, g, m, v, lr, b1, b2, eps, c1, c2);
+                 float c1, float c2, const double* gpart, float clip, hipStream_t s) {
+  k_adam<<<nblk(n), 256, 0, s>>>(n, w, g, m, v, lr, b1, b2, eps, c1, c2, gpart, clip);
 }
 
 }  // namespace ppe

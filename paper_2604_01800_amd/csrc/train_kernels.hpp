@@ -42,7 +42,9 @@ void launch_don_bwd(int64_t n, int P, const bf16_t* B, const bf16_t* T, const fl
                     float scale, bf16_t* dB, bf16_t* dT, float* part, int nparts, hipStream_t s);
 void launch_loss(int64_t n, const float* R, const float* Ay, float* res, double* part, int nparts, hipStream_t s);
 void launch_sum_parts(const double* part, int n, double scale, double* out, hipStream_t s);
+// Adam step; clip > 0 scales the gradient to norm <= clip first, with ||g||^2
+// from the kRedBlocks partials in gpart (launch_sumsq on g).
 void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
-                 float c1, float c2, hipStream_t s);
+                 float c1, float c2, const double* gpart, float clip, hipStream_t s);
 
 }  // namespace ppe

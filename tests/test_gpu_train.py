@@ -161,3 +161,31 @@ def test_train_step_argument_checks(ppe):
     R = torch.zeros((2, 32, 32), dtype=torch.float32, device="cuda")
     with pytest.raises(Exception):
         ppe.ppe_net_train_step(net, probs, R)
+
+
+def test_gradient_clipping(ppe):
+    """clip_norm scales the gradient to that L2 norm before Adam. On the first
+    step Adam moves each weight by lr * g / (|g| + eps), so clipping shows
+    where the scaled gradient is comparable with eps; the update must equal the
+    host formula with g * clip / ||g||."""
+    cfg = small_cfg()
+    grids, R = batch(32, [(1.4, 1.8), (2.1, 1.2)], seed=8)
+    probs = [ppe.ppe_problem_create(g) for g in grids]
+    Rd = torch.from_numpy(R.astype(np.float32)).cuda()
+    net = ppe.Net(gpu_cfg(ppe, cfg), seed=5)
+    w0 = ppe.ppe_net_get_params(net).astype(np.float64)
+    _, g = ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(lr=0.0), want_grad=True)
+    g = g.astype(np.float64)
+    gn = np.linalg.norm(g)
+    eps, lr = 1e-8, 1e-3
+    clip = 3e-8 * np.sqrt(g.size)  # the clipped gradient has RMS 3 eps
+    assert clip < gn
+    ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(lr=lr, eps=eps, clip_norm=clip))
+    step = ppe.ppe_net_get_params(net).astype(np.float64) - w0
+    gs = g * (clip / gn)
+    want = -lr * gs / (np.abs(gs) + eps)
+    assert np.abs(step - want).max() <= 2e-3 * lr
+    unclipped = -lr * np.sign(g)
+    assert np.abs(step - unclipped).max() >= 0.2 * lr  # clipping changed the update
+    with pytest.raises(ppe.PPEError):
+        ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(clip_norm=-1.0))
