@@ -10,9 +10,10 @@ system from x0 = 0 to relative residual 1e-6 (FP64 true residual) with
 Jacobi-PCG, and, when a network is available (--hybrid), with the hybrid
 PCG + line-search method as well.
 
-Prints one JSON line. `roofline` reports the dominant kernel (the
-single-reduction PCG iteration, one launch per iteration; or phase A of the
-two-phase form with --variant two_phase) with its algorithmic bytes per launch
+Prints one JSON line. `roofline` reports the dominant kernel (the launch of
+the PCG form that runs: two-step, two iterations per launch; single-reduction,
+one iteration per launch; or phase A of the two-phase form) with its
+algorithmic bytes per launch
 divided by its average launch duration (HIP events attached to the launches). `cpu_baseline` times the FP64 oracle on a
 bounded sample (a fixed number of PCG iterations on the same system, scaled to
 the iteration count of a full solve).
@@ -30,6 +31,7 @@ import numpy as np
 METRIC = "PPE solves/sec to rel-res 1e-6, hybrid vs plain PCG, 1024² grid; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 BYTES_PCG1 = 24     # per cell: reads r, p, x_c; writes r, p, x_c (FP32)
+BYTES_PCG2 = 24     # per cell and launch of two iterations: the same six FP32 vectors
 BYTES_PHASE_A = 20  # per cell: reads r, p_old, x_c; writes p, x_c (FP32)
 BYTES_PHASE_B = 12  # per cell: reads p, r; writes r (FP32)
 
@@ -88,10 +90,10 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=200)
-    ap.add_argument("--variant", choices=["auto", "single", "two_phase"], default="auto",
+    ap.add_argument("--variant", choices=["auto", "single", "two_phase", "two_step"], default="auto",
                     help="PCG iteration form: tuned on the workload before timing (auto, default), "
                          "one reduction per iteration, or two")
-    ap.add_argument("--rows", type=int, default=0, choices=[0, 2, 4, 8, 16],
+    ap.add_argument("--rows", type=int, default=0, choices=[0, 2, 4, 8, 16, 20, 24],
                     help="tile height (rows per wavefront); 0 = tuned or default")
     ap.add_argument("--network-forward", type=int, default=0, metavar="K",
                     help="time K forwards of the default DeepONet (random weights) on the workload's grid "
@@ -131,7 +133,7 @@ def main():
         return
 
     variant = {"auto": ppe.PPE_PCG_AUTO, "single": ppe.PPE_PCG_SINGLE_REDUCTION,
-               "two_phase": ppe.PPE_PCG_TWO_PHASE}[args.variant]
+               "two_phase": ppe.PPE_PCG_TWO_PHASE, "two_step": ppe.PPE_PCG_TWO_STEP}[args.variant]
     opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, variant=variant)
     tuning = None
     if variant == ppe.PPE_PCG_AUTO and not args.kernels_only and args.rows == 0:
@@ -143,7 +145,8 @@ def main():
         if variant == ppe.PPE_PCG_AUTO:
             variant = ppe.ppe_get_tuning(prob, 1)[0]
     opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, variant=variant, rows_per_wave=rows)
-    single = variant == ppe.PPE_PCG_SINGLE_REDUCTION
+    form = {ppe.PPE_PCG_SINGLE_REDUCTION: "single", ppe.PPE_PCG_TWO_PHASE: "two_phase",
+            ppe.PPE_PCG_TWO_STEP: "two_step"}[variant]
 
     if args.kernels_only:
         ms_a, ms_b = ppe.ppe_profile_pcg(prob, f, x, opts, reps=args.profile_reps)
@@ -174,16 +177,19 @@ def main():
     ms_a, ms_b = ppe.ppe_profile_pcg(prob, f, xt, opts, reps=args.profile_reps)
     N = g.nx * g.ny
     iters = s0["iters_total"]
-    if single:
+    if form == "two_step":
+        kname, kbytes, record = "k_pcg2 (two PCG iterations per launch)", BYTES_PCG2, "pcg2_1024_plain.counters.json"
+        tkey = "k_pcg2"
+    elif form == "single":
         kname, kbytes, record = "k_pcg1 (single-reduction PCG iteration)", BYTES_PCG1, "pcg1_1024_plain.counters.json"
         tkey = "k_pcg1"
-        per_iter_bytes = BYTES_PCG1
     else:
         kname, kbytes, record = "k_pcg_a (PCG phase A)", BYTES_PHASE_A, "pcg_phases_1024_plain.counters.json"
         tkey = "k_pcg_a"
-        per_iter_bytes = BYTES_PHASE_A + BYTES_PHASE_B
     ach = kbytes * N / (ms_a * 1e-3) / 1e9
-    pcg_gbs = per_iter_bytes * N * iters / (ms_per_step * 1e-3) / 1e9
+    # Whole-solve rate in the bytes a one-reduction iteration must move (24 B
+    # per cell and iteration), whatever form ran: comparable across forms.
+    pcg_gbs = BYTES_PCG1 * N * iters / (ms_per_step * 1e-3) / 1e9
 
     out = {
         "metric": METRIC,
@@ -201,7 +207,7 @@ def main():
         "config": {
             "workload": f"plain Jacobi-PCG, {g.nx}x{g.ny} tanh grid beta 1.75, ellipse mask, GRF source "
                         f"l=0.05, x0=0, rel-res {args.tol:g} on the FP64 true residual",
-            "pcg_form": "single" if single else "two_phase",
+            "pcg_form": form,
             "rows_per_wave": rows,
             "tuning_us_per_iter": None if tuning is None else
                 {f"{k[0]}/R{k[1]}": round(v, 2) for k, v in tuning["us_per_iter"].items()},

@@ -61,11 +61,18 @@ enum { PPE_TOL_RELATIVE = 0, PPE_TOL_ABSOLUTE = 1 };   /* ||b-Ax||2 <= tol*||b||
  * SINGLE_REDUCTION regroups the recurrences so that one launch and one
  * grid-wide reduction make an iteration (p.Ap from an exact expansion in
  * sums of the previous launch); TWO_PHASE is the textbook order with two
- * reductions per iteration. AUTO takes the problem's tuned choice for the
- * batch size (ppe_tune_pcg, ppe_set_tuning), else single reduction below
- * 2^21 cells per launch and two-phase above. The hybrid solve always uses
- * TWO_PHASE. */
-enum { PPE_PCG_AUTO = 0, PPE_PCG_SINGLE_REDUCTION = 1, PPE_PCG_TWO_PHASE = 2 };
+ * reductions per iteration; TWO_STEP makes two iterations per launch and
+ * per reduction (s-step CG with s = 2: the second iteration's scalars are
+ * exact expansions in eleven sums of the previous launch, and every
+ * workgroup carries a 4-cell halo). A launch of TWO_STEP may do a single
+ * iteration (next to max_iter, or when the expansion is not positive), so
+ * iteration counts keep their meaning. AUTO takes the problem's tuned
+ * choice for the batch size (ppe_tune_pcg, ppe_set_tuning), else the size
+ * heuristic (two-step below 2^21 cells per launch and two-phase above). The
+ * hybrid solve always uses TWO_PHASE; the mixed-size batch (ppe_solve_batch)
+ * runs TWO_STEP for AUTO and TWO_STEP, SINGLE_REDUCTION on request, and
+ * rejects TWO_PHASE. */
+enum { PPE_PCG_AUTO = 0, PPE_PCG_SINGLE_REDUCTION = 1, PPE_PCG_TWO_PHASE = 2, PPE_PCG_TWO_STEP = 3 };
 
 /* Error-direction provider of the hybrid solve. NET is the DeepONet; the others
  * replace it for testing the controller and its fallback. */
@@ -100,11 +107,12 @@ typedef struct {
   int32_t num_dlsm;        /* hybrid: line-search steps per round (default 2) */
   int32_t direction;       /* hybrid: PPE_DIR_* (default PPE_DIR_NET) */
   double reliable_delta;   /* true-residual update when ||r|| < delta*||r_true|| (default 0.3) */
-  int32_t rows_per_wave;   /* stencil tile height per wavefront: 0 = tuned or default, else 2,4,8,16 */
+  int32_t rows_per_wave;   /* stencil tile height per wavefront: 0 = tuned or default, else 2,4,8,16
+                              (the two-step form also 20, 24) */
   int32_t use_graph;       /* 1 (default) = replay iteration chunks as a HIP graph, 0 = eager launches */
   int32_t chunk;           /* iterations per polled chunk (0 = default 64) */
   int32_t zero_x0;         /* 1 = ignore x on entry and start from x0 = 0 */
-  int32_t variant;         /* plain solve: PPE_PCG_AUTO (default), _SINGLE_REDUCTION or _TWO_PHASE */
+  int32_t variant;         /* plain solve: PPE_PCG_AUTO (default), _SINGLE_REDUCTION, _TWO_PHASE or _TWO_STEP */
 } ppe_solve_opts;
 
 typedef struct {
@@ -165,8 +173,11 @@ ppe_status ppe_solve_plain(ppe_problem* p, int32_t nb, const float* f, double* x
                            const ppe_solve_opts* opts, ppe_solve_stats* stats, hipStream_t s);
 
 /* Plain (Jacobi-)PCG solves of n systems on grids of different sizes, one
- * right-hand side per grid, batched into one launch per iteration (a work
- * list of (solve, workgroup) entries over all grids; single-reduction form).
+ * right-hand side per grid, batched into one launch per two iterations
+ * (two-step form) or per iteration (single-reduction form, on request via
+ * opts->variant): a work list of (solve, workgroup) entries over all grids.
+ * Each solve's result is bit-identical to the same solve alone with the same
+ * form and tile height.
  * problems: host array of n distinct problems; f: host array of n device
  * FP32 sources [ny_i][nx_i]; x: host array of n device FP64 solutions
  * (in: initial guess, out: zero-mean solution); stats: host [n] or NULL,
@@ -236,13 +247,15 @@ ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* proble
  * timing each launch with HIP events, and stores the fastest in the problem;
  * later solves with variant PPE_PCG_AUTO and rows_per_wave 0 use it.
  * out (host, optional) receives the choice and the per-iteration times in
- * microseconds, us_per_iter[form][k] for form 0 single reduction, 1
- * two-phase and k indexing the heights 2, 4, 8, 16. ppe_set_tuning stores a
+ * microseconds (per CG iteration: a two-step launch counts as two),
+ * us_per_iter[form][k] for form 0 single reduction, 1 two-phase, 2 two-step
+ * and k indexing the heights 2, 4, 8, 16, 20, 24 (0 where the form has no
+ * such height: 20 and 24 are built for the two-step form only). ppe_set_tuning stores a
  * choice directly (e.g. from a cache the caller keeps); ppe_get_tuning
  * reports what PPE_PCG_AUTO resolves to for nb. */
 typedef struct {
   int32_t variant, rows_per_wave;
-  double us_per_iter[2][4];
+  double us_per_iter[3][6];
 } ppe_tune_result;
 ppe_status ppe_tune_pcg(ppe_problem* p, int32_t nb, const float* f, double* x, int32_t reps,
                         ppe_tune_result* out, hipStream_t s);
@@ -251,8 +264,8 @@ ppe_status ppe_get_tuning(const ppe_problem* p, int32_t nb, int32_t* variant, in
 
 /* Average kernel durations in ms of the PCG iteration on nb systems, for the
  * form opts->variant selects: TWO_PHASE gives one phase-A launch in ms_out[0]
- * and one phase-B launch in ms_out[1]; SINGLE_REDUCTION gives its one launch
- * per iteration in ms_out[0] and 0 in ms_out[1]. After a solve setup on
+ * and one phase-B launch in ms_out[1]; SINGLE_REDUCTION and TWO_STEP give
+ * one launch (one, resp. two iterations) in ms_out[0] and 0 in ms_out[1]. After a solve setup on
  * (f, x), `reps` iterations run eagerly on stream s, as in a solve,
  * each launch carrying its own start/stop HIP events (hipExtLaunchKernelGGL),
  * so the elapsed times are kernel execution times. x is used as the

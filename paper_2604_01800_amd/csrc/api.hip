@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -56,7 +57,9 @@ static void free_ws(SolveWs& w) {
 }
 
 // Workspace for nb solves: 6 FP32 vectors per solve (x_c, r, p0, p1, e, r1),
-// the partial-sum arrays (16 per workgroup and solve), states and polling flags.
+// the partial-sum arrays (16 per workgroup and solve of the 64-column tiles,
+// then 22 per workgroup and solve of the two-iteration form's 56-column
+// tiles), states and polling flags.
 ppe_status ensure_ws(ppe_problem* p, int nb) {
   SolveWs& w = p->ws;
   if (w.nb >= nb && w.vec) return PPE_OK;
@@ -64,8 +67,9 @@ ppe_status ensure_ws(ppe_problem* p, int nb) {
   const int64_t N = (int64_t)p->nx * p->ny;
   const dim3 g = stencil_grid(p->coef, 2, 1);  // the smallest tile height has the most workgroups
   w.Pmax = (int)(g.x * g.y);
+  w.P2max = (int)stencil_grid2(p->coef, 2, 1).x;
   w.vec = (float*)dev_alloc(sizeof(float) * 6 * N * nb);
-  w.part = (double*)dev_alloc(sizeof(double) * 16 * (size_t)w.Pmax * nb);
+  w.part = (double*)dev_alloc(sizeof(double) * (16 * (size_t)w.Pmax + 22 * (size_t)w.P2max) * nb);
   w.st = (SolveState*)dev_alloc(sizeof(SolveState) * nb);
   w.flags = (int32_t*)dev_alloc(sizeof(int32_t) * nb);
   w.call = (CallArgs*)dev_alloc(sizeof(CallArgs));
@@ -107,6 +111,8 @@ PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int
   a.e = w.vec + 4 * N;
   a.r1 = w.vec + 5 * N;
   a.part1 = w.part + (size_t)6 * a.P * nb;
+  a.P2 = (int)stencil_grid2(p->coef, R, 1).x;
+  a.part2 = w.part + (size_t)16 * w.Pmax * nb;
   a.st = w.st;
   a.flags = w.flags;
   a.call = w.call;
@@ -127,8 +133,9 @@ int default_rows(const ppe_problem* p, int nb) {
 }
 
 // Size heuristic (measured on MI355X): below ~2M cells per launch the
-// iteration is latency-bound and one reduction per iteration wins; above, the
-// two-phase form streams closer to the HBM bandwidth.
+// iteration is latency-bound and the two-step form (one reduction per two
+// iterations) wins; above, the two-phase form streams closer to the HBM
+// bandwidth.
 static constexpr int64_t kSingleMaxCells = (int64_t)2 << 20;
 
 static int default_rows_single(int64_t cells) {
@@ -138,7 +145,47 @@ static int default_rows_single(int64_t cells) {
   return 2;
 }
 
-void resolve_plain(const ppe_problem* p, int nb, const ppe_solve_opts& o, bool* single, int* rows) {
+// Tile heights (rows per wavefront) built for each iteration form.
+bool height_ok(int form, int R) {
+  if (R == 2 || R == 4 || R == 8 || R == 16) return true;
+  return form == PPE_PCG_TWO_STEP && (R == 20 || R == 24);
+}
+
+// Number of compute units of the current device (256 on MI355X).
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+// Two-step form: the launch is bound by the instruction stream of its
+// busiest CU, about (workgroups per CU, rounded up) x (rows per wavefront +
+// the 8 halo rows); take the height that minimises that over the launch's
+// workgroups (nb solves on each of the n grids).
+int default_rows_two_step(const ppe_problem* const* probs, int n, int nb) {
+  static const int kH[6] = {2, 4, 8, 16, 20, 24};
+  int best = 2;
+  int64_t best_cost = INT64_MAX;
+  for (int R : kH) {
+    int64_t wg = 0;
+    for (int i = 0; i < n; ++i) wg += (int64_t)stencil_grid2(probs[i]->coef, R, 1).x * nb;
+    const int64_t cost = ((wg + device_cus() - 1) / device_cus()) * (R + 8);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = R;
+    }
+  }
+  return best;
+}
+
+void resolve_plain(const ppe_problem* p, int nb, const ppe_solve_opts& o, int* form, int* rows) {
   const int64_t cells = (int64_t)p->nx * p->ny * nb;
   int v = o.variant, R = o.rows_per_wave;
   if (v == PPE_PCG_AUTO) {
@@ -148,9 +195,12 @@ void resolve_plain(const ppe_problem* p, int nb, const ppe_solve_opts& o, bool* 
         if (R == 0) R = t[2];
       }
   }
-  if (v == PPE_PCG_AUTO) v = cells < kSingleMaxCells ? PPE_PCG_SINGLE_REDUCTION : PPE_PCG_TWO_PHASE;
-  *single = v == PPE_PCG_SINGLE_REDUCTION;
-  if (!(R == 2 || R == 4 || R == 8 || R == 16)) R = *single ? default_rows_single(cells) : default_rows(p, nb);
+  if (v == PPE_PCG_AUTO) v = cells < kSingleMaxCells ? PPE_PCG_TWO_STEP : PPE_PCG_TWO_PHASE;
+  *form = v;
+  if (!height_ok(v, R))
+    R = v == PPE_PCG_TWO_PHASE ? default_rows(p, nb)
+        : v == PPE_PCG_TWO_STEP ? default_rows_two_step(&p, 1, nb)
+                                : default_rows_single(cells);
   *rows = R;
 }
 
@@ -167,19 +217,21 @@ int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o) {
       return set_error(PPE_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
   } while (0)
 
-// One chunk of `chunk` iterations with alternating parity: pairs of phase
-// launches (two-phase iteration) or single launches (single reduction).
-static void launch_chunk(const PcgArgs& a, int nb, int chunk, bool single, hipStream_t s) {
+// One chunk of `chunk` launches with alternating parity: pairs of phase
+// launches (two-phase form) or single launches (single-reduction and
+// two-step forms).
+static void launch_chunk(const PcgArgs& a, int nb, int chunk, int form, hipStream_t s) {
   for (int k = 0; k < chunk; ++k) {
-    if (single) launch_pcg1_step(a, nb, k & 1, s);
+    if (form == PPE_PCG_SINGLE_REDUCTION) launch_pcg1_step(a, nb, k & 1, s);
+    else if (form == PPE_PCG_TWO_STEP) launch_pcg2_step(a, nb, k & 1, s);
     else launch_pcg_pair(a, nb, k & 1, 0, 0, s);
   }
 }
 
 // Capture (once per workspace shape and iteration form) the chunk as a graph.
-static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int chunk, bool single) {
+static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int chunk, int form) {
   SolveWs& w = p->ws;
-  const int key[5] = {nb, a.R, a.jacobi, chunk, (int)single};
+  const int key[5] = {nb, a.R, a.jacobi, chunk, form};
   if (w.exec && std::equal(key, key + 5, w.exec_key)) return PPE_OK;
   if (w.exec) {
     (void)hipGraphExecDestroy(w.exec);
@@ -188,7 +240,7 @@ static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int 
   if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-  launch_chunk(a, nb, chunk, single, p->cap_stream);
+  launch_chunk(a, nb, chunk, form, p->cap_stream);
   hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
   if (e != hipSuccess) return set_error(PPE_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(&w.exec, graph, nullptr, nullptr, 0);
@@ -205,22 +257,23 @@ static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int 
 // next chunk is enqueued before the previous chunk's flags are inspected, so
 // the device never waits for the host.
 ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s,
-                          bool single) {
+                          int form) {
   SolveWs& w = p->ws;
   int chunk = o.chunk > 0 ? o.chunk : 64;
   chunk += chunk & 1;
   if (o.use_graph) {
-    ppe_status st = get_chunk_graph(p, a, nb, chunk, single);
+    ppe_status st = get_chunk_graph(p, a, nb, chunk, form);
     if (st != PPE_OK) return st;
   }
-  // Launches a solve can take: a CG iteration is one pair (two-phase) or one
-  // launch (single reduction), a reliable update one pair or two launches.
+  // Launches a solve can take: a CG iteration is one pair (two-phase) or at
+  // most one launch (single reduction, two-step), a reliable update one pair
+  // or three launches.
   const int64_t max_chunks = (3 * (int64_t)o.max_iter + 8) / chunk + 2;
   for (int64_t c = 0; c < max_chunks; ++c) {
     if (o.use_graph) {
       HIPCHK(hipGraphLaunch(w.exec, s));
     } else {
-      launch_chunk(a, nb, chunk, single, s);
+      launch_chunk(a, nb, chunk, form, s);
       HIPCHK(hipGetLastError());
     }
     HIPCHK(hipMemcpyAsync(w.h_flags + (c & 1) * nb, w.flags, sizeof(int32_t) * nb,
@@ -304,20 +357,24 @@ ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, con
   return PPE_OK;
 }
 
+static void launch_setup(const PcgArgs& a, int nb, int form, hipStream_t s) {
+  if (form == PPE_PCG_SINGLE_REDUCTION) launch_pcg1_setup(a, nb, s);
+  else if (form == PPE_PCG_TWO_STEP) launch_pcg2_setup(a, nb, s);
+  else launch_pcg_setup(a, nb, s);
+}
+
 ppe_status solve_plain_impl(ppe_problem* p, int32_t nb, const float* f, double* x,
                             const ppe_solve_opts& o, ppe_solve_stats* stats, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
   ppe_status st = ensure_ws(p, nb);
   if (st != PPE_OK) return st;
-  bool single;
-  int R;
-  resolve_plain(p, nb, o, &single, &R);
+  int form, R;
+  resolve_plain(p, nb, o, &form, &R);
   const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
   launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
-  if (single) launch_pcg1_setup(a, nb, s);
-  else launch_pcg_setup(a, nb, s);
+  launch_setup(a, nb, form, s);
   HIPCHK(hipGetLastError());
-  st = run_pcg_chunks(p, a, nb, o, s, single);
+  st = run_pcg_chunks(p, a, nb, o, s, form);
   if (st != PPE_OK) return st;
   launch_pcg_finish(a, nb, s);
   HIPCHK(hipGetLastError());
@@ -329,20 +386,23 @@ ppe_status solve_plain_impl(ppe_problem* p, int32_t nb, const float* f, double* 
 
 // Average kernel durations of `reps` iterations of one launch configuration
 // (setup first), each launch carrying its own start/stop events.
-ppe_status profile_form(ppe_problem* p, int nb, const float* f, double* x, const ppe_solve_opts& o, bool single,
+ppe_status profile_form(ppe_problem* p, int nb, const float* f, double* x, const ppe_solve_opts& o, int form,
                         int R, int reps, double* ms_out, hipStream_t s) {
   ppe_status st = ensure_ws(p, nb);
   if (st != PPE_OK) return st;
   const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
   launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
-  if (single) launch_pcg1_setup(a, nb, s);
-  else launch_pcg_setup(a, nb, s);
+  launch_setup(a, nb, form, s);
+  const bool single = form != PPE_PCG_TWO_PHASE;
   std::vector<hipEvent_t> ev(4 * reps);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   for (int k = 0; k < reps; ++k) {
-    if (single) {
-      launch_pcg1_step_timed(a, nb, k & 1, s, ev[4 * k], ev[4 * k + 1]);
-      launch_pcg1_step_timed(a, nb, (k & 1) ^ 1, s, ev[4 * k + 2], ev[4 * k + 3]);
+    if (form == PPE_PCG_SINGLE_REDUCTION) {
+      launch_pcg1_step_timed(a, nb, 0, s, ev[4 * k], ev[4 * k + 1]);
+      launch_pcg1_step_timed(a, nb, 1, s, ev[4 * k + 2], ev[4 * k + 3]);
+    } else if (form == PPE_PCG_TWO_STEP) {
+      launch_pcg2_step_timed(a, nb, 0, s, ev[4 * k], ev[4 * k + 1]);
+      launch_pcg2_step_timed(a, nb, 1, s, ev[4 * k + 2], ev[4 * k + 3]);
     } else {
       launch_pcg_phase_timed(a, nb, k & 1, 0, s, ev[4 * k], ev[4 * k + 1]);
       launch_pcg_phase_timed(a, nb, k & 1, 1, s, ev[4 * k + 2], ev[4 * k + 3]);
@@ -471,10 +531,9 @@ ppe_status ppe_profile_pcg(ppe_problem* p, int32_t nb, const float* f, double* x
   ppe_status st = check_solve_args(p, nb, f, x, &o);
   if (st != PPE_OK) return st;
   if (nb < 1 || reps < 1 || !ms_out) return set_error(PPE_ERR_INVALID_ARG, "nb, reps >= 1 and ms_out required");
-  bool single;
-  int R;
-  resolve_plain(p, nb, o, &single, &R);
-  return profile_form(p, nb, f, x, o, single, R, reps, ms_out, s);
+  int form, R;
+  resolve_plain(p, nb, o, &form, &R);
+  return profile_form(p, nb, f, x, o, form, R, reps, ms_out, s);
 }
 
 ppe_status ppe_tune_pcg(ppe_problem* p, int32_t nb, const float* f, double* x, int32_t reps,
@@ -488,20 +547,22 @@ ppe_status ppe_tune_pcg(ppe_problem* p, int32_t nb, const float* f, double* x, i
   o.tol = 0.0;
   o.max_iter = 1 << 30;
   o.zero_x0 = 1;
-  static const int kRows[4] = {2, 4, 8, 16};
+  static const int kRows[6] = {2, 4, 8, 16, 20, 24};
+  static const int kForms[3] = {PPE_PCG_SINGLE_REDUCTION, PPE_PCG_TWO_PHASE, PPE_PCG_TWO_STEP};
   double best = 1e300;
   int bv = PPE_PCG_SINGLE_REDUCTION, br = 8;
   ppe_tune_result res{};
-  for (int v = 0; v < 2; ++v)
-    for (int k = 0; k < 4; ++k) {
+  for (int v = 0; v < 3; ++v)
+    for (int k = 0; k < 6; ++k) {
+      if (!height_ok(kForms[v], kRows[k])) continue;
       double ms[2] = {0, 0};
-      st = profile_form(p, nb, f, x, o, v == 0, kRows[k], reps, ms, s);
+      st = profile_form(p, nb, f, x, o, kForms[v], kRows[k], reps, ms, s);
       if (st != PPE_OK) return st;
-      const double us = (ms[0] + ms[1]) * 1e3;
+      const double us = (ms[0] + ms[1]) * 1e3 / (kForms[v] == PPE_PCG_TWO_STEP ? 2.0 : 1.0);
       res.us_per_iter[v][k] = us;
       if (us < best) {
         best = us;
-        bv = v == 0 ? PPE_PCG_SINGLE_REDUCTION : PPE_PCG_TWO_PHASE;
+        bv = kForms[v];
         br = kRows[k];
       }
     }
@@ -515,10 +576,10 @@ ppe_status ppe_tune_pcg(ppe_problem* p, int32_t nb, const float* f, double* x, i
 
 ppe_status ppe_set_tuning(ppe_problem* p, int32_t nb, int32_t variant, int32_t rows_per_wave) {
   if (!p || nb < 1) return set_error(PPE_ERR_INVALID_ARG, "problem and nb >= 1 required");
-  if (variant != PPE_PCG_SINGLE_REDUCTION && variant != PPE_PCG_TWO_PHASE)
-    return set_error(PPE_ERR_INVALID_ARG, "variant must be single-reduction or two-phase");
-  if (!(rows_per_wave == 2 || rows_per_wave == 4 || rows_per_wave == 8 || rows_per_wave == 16))
-    return set_error(PPE_ERR_INVALID_ARG, "rows_per_wave must be 2, 4, 8 or 16");
+  if (variant != PPE_PCG_SINGLE_REDUCTION && variant != PPE_PCG_TWO_PHASE && variant != PPE_PCG_TWO_STEP)
+    return set_error(PPE_ERR_INVALID_ARG, "variant must be single-reduction, two-phase or two-step");
+  if (!height_ok(variant, rows_per_wave))
+    return set_error(PPE_ERR_INVALID_ARG, "rows_per_wave must be 2, 4, 8 or 16 (two-step: also 20 or 24)");
   for (auto& t : p->tuned)
     if (t[0] == nb) {
       t = {nb, variant, rows_per_wave};
@@ -532,10 +593,9 @@ ppe_status ppe_get_tuning(const ppe_problem* p, int32_t nb, int32_t* variant, in
   if (!p || nb < 1 || !variant || !rows_per_wave) return set_error(PPE_ERR_INVALID_ARG, "bad arguments");
   ppe_solve_opts o;
   ppe_solve_opts_default(&o);
-  bool single;
-  int R;
-  resolve_plain(p, nb, o, &single, &R);
-  *variant = single ? PPE_PCG_SINGLE_REDUCTION : PPE_PCG_TWO_PHASE;
+  int form, R;
+  resolve_plain(p, nb, o, &form, &R);
+  *variant = form;
   *rows_per_wave = R;
   return PPE_OK;
 }

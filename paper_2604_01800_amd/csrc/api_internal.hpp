@@ -15,8 +15,9 @@ namespace ppe {
 struct SolveWs {
   int nb = 0;
   int Pmax = 0;
-  float* vec = nullptr;      // x_c, r, p0, p1, e: [5][nb][N]
-  double* part = nullptr;    // partial sums: [6][nb][Pmax]
+  int P2max = 0;
+  float* vec = nullptr;      // x_c, r, p0, p1, e, r1: [6][nb][N]
+  double* part = nullptr;    // partial sums: [16][nb][Pmax], then [22][nb][P2max]
   SolveState* st = nullptr;  // [nb]
   int32_t* flags = nullptr;  // [nb]
   CallArgs* call = nullptr;
@@ -68,7 +69,7 @@ ppe_status ensure_ws(ppe_problem* p, int nb);
 PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int tol_kind, int zero_x0);
 int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o);
 ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s,
-                          bool single);
+                          int form);
 // Resolves PPE_PCG_AUTO and rows_per_wave = 0 for a plain solve of nb systems:
 // the tuned entry for nb if there is one, else the size heuristic.
 ppe_status gen_ensure(GenWs& w, int nb, int64_t N, int J, int P);
@@ -79,8 +80,10 @@ ppe_status check_gen_opts(const ppe_train_opts& o);
 ppe_status generate_rhs(GenWs& w, int nb, ppe_problem* const* probs, const ppe_train_opts& o, float* R,
                         hipStream_t s);
 double wall_clock_khz();
-void resolve_plain(const ppe_problem* p, int nb, const ppe_solve_opts& o, bool* single, int* rows);
-ppe_status profile_form(ppe_problem* p, int nb, const float* f, double* x, const ppe_solve_opts& o, bool single,
+bool height_ok(int form, int R);
+int default_rows_two_step(const ppe_problem* const* probs, int n, int nb);
+void resolve_plain(const ppe_problem* p, int nb, const ppe_solve_opts& o, int* form, int* rows);
+ppe_status profile_form(ppe_problem* p, int nb, const float* f, double* x, const ppe_solve_opts& o, int form,
                         int R, int reps, double* ms_out, hipStream_t s);
 ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s, bool hybrid);
 ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, const void* x,

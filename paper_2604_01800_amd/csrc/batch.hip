@@ -1,7 +1,7 @@
-// Plain solves on grids of different sizes in one batch: every iteration is
-// one launch of the single-reduction kernel over a work list of (solve,
-// workgroup) entries, so small grids ride along with large ones instead of
-// leaving the GPU idle. Each solve keeps its own workspace, scalars, partial
+// Plain solves on grids of different sizes in one batch: every launch of the
+// two-step kernel (two iterations) or of the single-reduction kernel (one
+// iteration) runs over a work list of (solve, workgroup) entries, so small
+// grids ride along with large ones instead of leaving the GPU idle. Each solve keeps its own workspace, scalars, partial
 // sums and done flag; converged solves' workgroups exit at once. Chunks of
 // iterations are captured as one HIP graph and replayed until every flag is
 // set; the device records each solve's finishing time.
@@ -24,7 +24,7 @@ namespace ppe {
 
 struct BatchWs {
   std::vector<const ppe_problem*> key;  // problems the work list was built for
-  int R = 0, chunk = 0, jacobi = -1, n = 0, nblocks = 0;
+  int form = 0, R = 0, chunk = 0, jacobi = -1, n = 0, nblocks = 0;
   PcgArgs* d_descs = nullptr;
   uint32_t* d_work = nullptr;
   int32_t* d_flags = nullptr;
@@ -46,15 +46,16 @@ static void batch_free(BatchWs& w) {
   w = BatchWs{};
 }
 
-// (Re)builds the work list and buffers when the problem list or the tile
-// height changes.
-static ppe_status batch_prepare(BatchWs& w, int n, ppe_problem* const* probs, int R) {
+// (Re)builds the work list and buffers when the problem list, the form or
+// the tile height changes.
+static ppe_status batch_prepare(BatchWs& w, int n, ppe_problem* const* probs, int form, int R) {
   const std::vector<const ppe_problem*> key(probs, probs + n);
-  if (w.d_descs && w.key == key && w.R == R) return PPE_OK;
+  if (w.d_descs && w.key == key && w.form == form && w.R == R) return PPE_OK;
   batch_free(w);
   std::vector<uint32_t> work;
   for (int i = 0; i < n; ++i) {
-    const uint32_t P = stencil_grid(probs[i]->coef, R, 1).x;  // a multiple of 8
+    // a multiple of 8, so that each solve's workgroups keep their XCD banding
+    const uint32_t P = (form == PPE_PCG_TWO_STEP ? stencil_grid2(probs[i]->coef, R, 1) : stencil_grid(probs[i]->coef, R, 1)).x;
     if (P >= (1u << 20)) return set_error(PPE_ERR_SHAPE, "grid %d has too many tiles for a batch", i);
     for (uint32_t b = 0; b < P; ++b) work.push_back(((uint32_t)i << 20) | b);
   }
@@ -73,17 +74,25 @@ static ppe_status batch_prepare(BatchWs& w, int n, ppe_problem* const* probs, in
   HIPCHK(hipStreamCreateWithFlags(&w.cap, hipStreamNonBlocking));
   HIPCHK(hipMemcpy(w.d_work, work.data(), sizeof(uint32_t) * work.size(), hipMemcpyHostToDevice));
   w.key = key;
+  w.form = form;
   w.R = R;
   w.n = n;
   w.nblocks = (int)work.size();
   return PPE_OK;
 }
 
+static void launch_batch_step(const BatchWs& w, bool jacobi, int par, hipStream_t s) {
+  if (w.form == PPE_PCG_TWO_STEP) launch_pcg2_multi_step(w.d_descs, w.d_work, w.nblocks, w.R, jacobi, par, s);
+  else launch_pcg1_multi_step(w.d_descs, w.d_work, w.nblocks, w.R, jacobi, par, s);
+}
+
 static void launch_batch_chunk(const BatchWs& w, bool jacobi, int chunk, hipStream_t s) {
-  for (int k = 0; k < chunk; ++k) launch_pcg1_multi_step(w.d_descs, w.d_work, w.nblocks, w.R, jacobi, k & 1, s);
+  for (int k = 0; k < chunk; ++k) launch_batch_step(w, jacobi, k & 1, s);
 }
 
 static ppe_status batch_graph(BatchWs& w, bool jacobi, int chunk) {
+  // The work list, form and height are fixed per BatchWs build (the graph is
+  // destroyed with it), so chunk and preconditioner complete the key.
   if (w.exec && w.chunk == chunk && w.jacobi == (int)jacobi) return PPE_OK;
   if (w.exec) {
     (void)hipGraphExecDestroy(w.exec);
@@ -132,12 +141,16 @@ extern "C" ppe_status ppe_solve_batch(int32_t n, ppe_problem* const* problems, c
       if (problems[k] == problems[i]) return set_error(PPE_ERR_INVALID_ARG, "problem %d appears twice", i);
     cells += (int64_t)problems[i]->nx * problems[i]->ny;
   }
-  const int R = (o.rows_per_wave == 2 || o.rows_per_wave == 4 || o.rows_per_wave == 8 || o.rows_per_wave == 16)
-                    ? o.rows_per_wave
-                    : (cells >= ((int64_t)1 << 20) ? 8 : cells >= ((int64_t)1 << 17) ? 4 : 2);
+  if (o.variant == PPE_PCG_TWO_PHASE)
+    return set_error(PPE_ERR_UNSUPPORTED, "the mixed-size batch runs the two-step or single-reduction form");
+  const int form = o.variant == PPE_PCG_SINGLE_REDUCTION ? PPE_PCG_SINGLE_REDUCTION : PPE_PCG_TWO_STEP;
+  int R = o.rows_per_wave;
+  if (!height_ok(form, R))
+    R = form == PPE_PCG_TWO_STEP ? default_rows_two_step(problems, n, 1)
+        : (cells >= ((int64_t)1 << 20) ? 8 : cells >= ((int64_t)1 << 17) ? 4 : 2);
   const bool jacobi = o.precond == PPE_PC_JACOBI;
   static thread_local BatchWs w;
-  ppe_status st = batch_prepare(w, n, problems, R);
+  ppe_status st = batch_prepare(w, n, problems, form, R);
   if (st != PPE_OK) return st;
   std::vector<PcgArgs> descs(n);
   for (int i = 0; i < n; ++i) {
@@ -152,7 +165,7 @@ extern "C" ppe_status ppe_solve_batch(int32_t n, ppe_problem* const* problems, c
     launch_rhs(descs[i], 1, s);
     launch_pcg1_init(descs[i], 1, s);
   }
-  launch_pcg1_multi_step(w.d_descs, w.d_work, w.nblocks, R, jacobi, 1, s);  // true residual of x0
+  launch_batch_step(w, jacobi, 1, s);  // true residual of x0
   HIPCHK(hipGetLastError());
   int chunk = o.chunk > 0 ? o.chunk : 64;
   chunk += chunk & 1;

@@ -14,6 +14,8 @@ struct PcgArgs {
   float* r1;                // [nb][N] second residual buffer (single-reduction iteration)
   double *partA, *partB;    // [nb][P], [nb][2][P]
   double* part1;            // [2][nb][5][P] sums of the single-reduction iteration
+  int P2;                   // workgroups per solve of the two-iteration form (56-column tiles)
+  double* part2;            // [2][nb][11][P2] sums of the two-iteration form
   double* partD;            // [nb][3][P] line-search partial sums
   const float* e;           // [nb][N] line-search direction
   SolveState* st;           // [nb]
@@ -26,6 +28,7 @@ struct PcgArgs {
 };
 
 dim3 stencil_grid(const Coef& c, int R, int nb);
+dim3 stencil_grid2(const Coef& c, int R, int nb);
 void launch_apply_f32(const Coef& c, int nb, const float* x, float* y, int R, hipStream_t s);
 void launch_apply_f64(const Coef& c, int nb, const double* x, double* y, int R, hipStream_t s);
 void launch_set_call(CallArgs* c, const float* f, double* x, int max_iter, double delta2, hipStream_t s);
@@ -37,6 +40,11 @@ void launch_pcg1_init(const PcgArgs& a, int nb, hipStream_t s);
 void launch_pcg1_multi_step(const PcgArgs* descs, const uint32_t* work, int nblocks, int R, bool jacobi, int par,
                             hipStream_t s);
 void launch_pcg1_step_timed(const PcgArgs& a, int nb, int par, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+void launch_pcg2_setup(const PcgArgs& a, int nb, hipStream_t s);
+void launch_pcg2_step(const PcgArgs& a, int nb, int par, hipStream_t s);
+void launch_pcg2_multi_step(const PcgArgs* descs, const uint32_t* work, int nblocks, int R, bool jacobi, int par,
+                            hipStream_t s);
+void launch_pcg2_step_timed(const PcgArgs& a, int nb, int par, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 void launch_pcg_pair(const PcgArgs& a, int nb, int par, int force, int force_restart, hipStream_t s);
 void launch_pcg_phase_a(const PcgArgs& a, int nb, int par, hipStream_t s);
 void launch_pcg_phase_b(const PcgArgs& a, int nb, int par, hipStream_t s);

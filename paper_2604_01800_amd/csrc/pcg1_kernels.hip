@@ -42,90 +42,6 @@ __device__ __forceinline__ double* sums_of(const PcgArgs& a, int par, int s, int
   return a.part1 + ((size_t)par * nbs + s) * kSums * a.P;
 }
 
-// FP64 sum over a wavefront on DPP lane moves (no LDS traffic): within each
-// row of 16 lanes, quad xor 1, quad xor 2, half-row mirror and row mirror
-// leave the row sum in every lane of the row (each step adds commuted equal
-// pairs, so all lanes hold the same bits); the four row sums are then added
-// in a fixed order. Every lane returns the same value.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x140>(v);  // row_mirror
-  return ((readlane_f64(v, 0) + readlane_f64(v, 16)) + readlane_f64(v, 32)) + readlane_f64(v, 48);
-}
-
-// Fixed-order reduction of the five partial arrays ([5][P]); every workgroup
-// obtains the same bits.
-__device__ __forceinline__ void reduce5(const double* __restrict__ part, int P, double* lds, double (&out)[kSums]) {
-  double v[kSums];
-#pragma unroll
-  for (int m = 0; m < kSums; ++m) v[m] = 0.0;
-  for (int k = threadIdx.x; k < P; k += kBlock) {
-#pragma unroll
-    for (int m = 0; m < kSums; ++m) v[m] += part[(size_t)m * P + k];
-  }
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-#pragma unroll
-  for (int m = 0; m < kSums; ++m) v[m] = wave_sum_dpp(v[m]);
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int m = 0; m < kSums; ++m) lds[m * kWaves + w] = v[m];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < kSums; ++m)
-    out[m] = ((lds[m * kWaves] + lds[m * kWaves + 1]) + lds[m * kWaves + 2]) + lds[m * kWaves + 3];
-}
-
-// Workgroup sums of five values, stored by thread 0 into part[.][blk] ([5][P]).
-__device__ __forceinline__ void store5(double (&v)[kSums], double* lds, double* __restrict__ part, int P, int blk) {
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-#pragma unroll
-  for (int m = 0; m < kSums; ++m) v[m] = wave_sum_dpp(v[m]);
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int m = 0; m < kSums; ++m) lds[m * kWaves + w] = v[m];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int m = 0; m < kSums; ++m)
-      part[(size_t)m * P + blk] =
-          ((lds[m * kWaves] + lds[m * kWaves + 1]) + lds[m * kWaves + 2]) + lds[m * kWaves + 3];
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ T diag_of(T hyj, T gs, T gn, T hx, T gw, T ge) {
-  return hyj * (gw + ge) + hx * (gs + gn);
-}
-
-// Jacobi preconditioner of this iteration form: z = r * dinv with dinv the
-// hardware reciprocal of the diagonal (one rounding of 1/D, the same value in
-// every launch, so the preconditioner is a fixed diagonal matrix). Cells off
-// the grid have D = 0 and r = 0, and get z = 0.
-__device__ __forceinline__ float inv_diag(float hyj, float gs, float gn, float hx, float gw, float ge) {
-  return __builtin_amdgcn_rcpf(fmaxf(diag_of(hyj, gs, gn, hx, gw, ge), 1e-30f));
-}
-
 // Halo columns in transposed form: lanes 0-31 work on the west side and
 // lanes 32-63 on the east side of the wavefront's 64-column strip, one row
 // per lane (lane t of a side takes row j0 - 1 + t). On each side, column e is
@@ -162,16 +78,6 @@ __device__ __forceinline__ float from_halo(float v, int q) {
   const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
   const float e = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + q));
   return lane < 32 ? w : e;
-}
-
-// FP64 true residual r = b - A x at (i, j) with b = hx hy f - mean(b); x
-// holds the centre and its four neighbours.
-__device__ __forceinline__ double true_res(const Coef& c, int i, int j, double xc_, double xe, double xw, double xn,
-                                           double xs, float f, double bmean) {
-  const double hyj = c.hy64[j];
-  const double Ax = stencil5(xc_, xe, xw, xn, xs, hyj, c.gy64[j], c.gy64[j + 1], c.hx64[i], c.gx64[i],
-                             c.gx64[i + 1]);
-  return (c.hx64[i] * hyj * (double)f - bmean) - Ax;
 }
 
 // One launch of the iteration for solve s of the nbs solves described by a,
@@ -236,7 +142,7 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
   // Reduced whatever the previous mode (after a FLUSH the sums are stale and
   // unused), so that these loads do not wait for the mode word.
   double sum[kSums];
-  reduce5(sums_of(a, pm, s, nbs), P, lds, sum);
+  reduce_sums<kSums>(sums_of(a, pm, s, nbs), P, lds, sum);
   if (__builtin_expect(dprev != 0, 0)) {
     if (leader) st->dflag[par] = dprev;
     return;
@@ -301,7 +207,7 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
 
   if (__builtin_expect(todo == MODE_FLUSH, 0)) {
     // Reliable update, part 1: x += x_c in FP64, x_c = 0, p carried over.
-    const auto xsr = make_rsrc(a.call->x + off, (uint64_t)a.N * 8);
+    const auto xsr = make_rsrc(uniform_ptr(a.call->x) + off, (uint64_t)a.N * 8);
     const auto xcs = make_rsrc(xc, vbytes), pso = make_rsrc(pout, vbytes);
     double xv[R];
 #pragma unroll
@@ -331,8 +237,8 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
     // Reliable update, part 2: r = b - A x in FP64 on the own rows (the x
     // window walks down the column; the halo column gives east/west), and
     // |r|^2 in FP64, the convergence judge. p is carried over.
-    const auto xsr = make_rsrc(a.call->x + off, (uint64_t)a.N * 8);
-    const auto fsr = make_rsrc(a.call->f + off, vbytes);
+    const auto xsr = make_rsrc(uniform_ptr(a.call->x) + off, (uint64_t)a.N * 8);
+    const auto fsr = make_rsrc(uniform_ptr(a.call->f) + off, vbytes);
     const auto rso = make_rsrc(rout, vbytes), pso = make_rsrc(pout, vbytes);
     const double bmean = st->bmean;
     const auto psr2 = make_rsrc(pin, vbytes);
@@ -473,7 +379,7 @@ __device__ __forceinline__ void pcg1_body(const PcgArgs& a, int s, int nbs, int 
       acc[4] += (double)rn[q + 1] * (double)rn[q + 1];
     }
   }
-  store5(acc, lds, sums_of(a, par, s, nbs), P, blk);
+  store_sums<kSums>(acc, lds, sums_of(a, par, s, nbs), P, blk);
 }
 
 template <int R, bool JAC>

@@ -123,6 +123,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
+// A pointer loaded from device memory that is the same in every lane, moved
+// to scalar registers. The compiler cannot always prove such a load uniform;
+// a buffer descriptor built from a vector register would make every buffer
+// access a loop over the distinct descriptors.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (T*)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
@@ -219,5 +231,165 @@ __device__ __forceinline__ void stencil_rows(const Tile<T, R>& v, const RowCoef<
   }
 }
 
+// FP64 sum over a wavefront on DPP lane moves (no LDS traffic): within each
+// row of 16 lanes, quad xor 1, quad xor 2, half-row mirror and row mirror
+// leave the row sum in every lane of the row (each step adds commuted equal
+// pairs, so all lanes hold the same bits); the four row sums are then added
+// in a fixed order. Every lane returns the same value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xf, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return ((readlane_f64(v, 0) + readlane_f64(v, 16)) + readlane_f64(v, 32)) + readlane_f64(v, 48);
+}
+
+// Fixed-order reduction of N partial arrays ([N][P]); every workgroup obtains
+// the same bits. lds holds N * kWaves doubles.
+template <int N>
+__device__ __forceinline__ void reduce_sums(const double* __restrict__ part, int P, double* lds, double (&out)[N]) {
+  double v[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) v[m] = 0.0;
+  for (int k = threadIdx.x; k < P; k += kBlock) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] += part[(size_t)m * P + k];
+  }
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int m = 0; m < N; ++m) v[m] = wave_sum_dpp(v[m]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) lds[m * kWaves + w] = v[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < N; ++m)
+    out[m] = ((lds[m * kWaves] + lds[m * kWaves + 1]) + lds[m * kWaves + 2]) + lds[m * kWaves + 3];
+}
+
+// Workgroup sums of N values, stored by thread 0 into part[.][blk] ([N][P]).
+template <int N>
+__device__ __forceinline__ void store_sums(double (&v)[N], double* lds, double* __restrict__ part, int P, int blk) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int m = 0; m < N; ++m) v[m] = wave_sum_dpp(v[m]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) lds[m * kWaves + w] = v[m];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < N; ++m)
+      part[(size_t)m * P + blk] =
+          ((lds[m * kWaves] + lds[m * kWaves + 1]) + lds[m * kWaves + 2]) + lds[m * kWaves + 3];
+  }
+}
+
+// FP64 sum over each row of 16 lanes (quad xor 1, quad xor 2, half-row
+// mirror, row mirror); every lane of the row gets the row's sum.
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  return v;
+}
+
+// Fixed-order reduction of N partial arrays ([N][P]) in every workgroup, with
+// one 16-lane row per sum: thread 16m + c adds the partials k = c, c + 16, ...
+// of sum m (four running sums over k mod 64, then added in order), the row
+// adds its 16 values, and thread 16m leaves the total in lds[m]; all threads
+// then read the N totals. Every workgroup does the same operations in the
+// same order, so all obtain the same bits. Needs 16 N <= kBlock.
+template <int N>
+__device__ __forceinline__ void reduce_sums16(const double* __restrict__ part, int P, double* lds, double (&out)[N]) {
+  static_assert(16 * N <= kBlock, "one 16-lane row per sum");
+  const int t = threadIdx.x;
+  if (t < 16 * N) {
+    const int m = t >> 4, c = t & 15;
+    const double* __restrict__ pm = part + (size_t)m * P;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int k = c;
+    for (; k + 48 < P; k += 64) {
+      a0 += pm[k];
+      a1 += pm[k + 16];
+      a2 += pm[k + 32];
+      a3 += pm[k + 48];
+    }
+    if (k < P) a0 += pm[k];
+    if (k + 16 < P) a1 += pm[k + 16];
+    if (k + 32 < P) a2 += pm[k + 32];
+    const double v = row_sum16(((a0 + a1) + a2) + a3);
+    if (c == 0) lds[m] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < N; ++m) out[m] = lds[m];
+}
+
+// Workgroup sums of N values per thread, stored by one thread per sum into
+// part[m][blk] ([N][P]). The values go through LDS (lds: N * kBlock doubles):
+// thread 16m + c adds threads c, c + 16, ..., c + 240 of sum m, and the
+// 16-lane row adds those. Fixed order; needs 16 N <= kBlock.
+template <int N>
+__device__ __forceinline__ void store_sums16(const double (&v)[N], double* lds, double* __restrict__ part, int P,
+                                             int blk) {
+  static_assert(16 * N <= kBlock, "one 16-lane row per sum");
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int m = 0; m < N; ++m) lds[m * kBlock + t] = v[m];
+  __syncthreads();
+  if (t < 16 * N) {
+    const int m = t >> 4, c = t & 15;
+    const double* l = lds + m * kBlock + c;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 16; ++k) s += l[16 * k];
+    s = row_sum16(s);
+    if (c == 0) part[(size_t)m * P + blk] = s;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T diag_of(T hyj, T gs, T gn, T hx, T gw, T ge) {
+  return hyj * (gw + ge) + hx * (gs + gn);
+}
+
+// Jacobi preconditioner of this iteration form: z = r * dinv with dinv the
+// hardware reciprocal of the diagonal (one rounding of 1/D, the same value in
+// every launch, so the preconditioner is a fixed diagonal matrix). Cells off
+// the grid have D = 0 and r = 0, and get z = 0.
+__device__ __forceinline__ float inv_diag(float hyj, float gs, float gn, float hx, float gw, float ge) {
+  return __builtin_amdgcn_rcpf(fmaxf(diag_of(hyj, gs, gn, hx, gw, ge), 1e-30f));
+}
+
+// FP64 true residual r = b - A x at (i, j) with b = hx hy f - mean(b); x
+// holds the centre and its four neighbours.
+__device__ __forceinline__ double true_res(const Coef& c, int i, int j, double xc_, double xe, double xw, double xn,
+                                           double xs, float f, double bmean) {
+  const double hyj = c.hy64[j];
+  const double Ax = stencil5(xc_, xe, xw, xn, xs, hyj, c.gy64[j], c.gy64[j + 1], c.hx64[i], c.gx64[i],
+                             c.gx64[i + 1]);
+  return (c.hx64[i] * hyj * (double)f - bmean) - Ax;
+}
 
 }  // namespace ppe

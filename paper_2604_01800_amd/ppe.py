@@ -20,7 +20,7 @@ PPE_OK, PPE_NOT_CONVERGED = 0, 1
 PPE_ERR_INVALID_ARG, PPE_ERR_SHAPE, PPE_ERR_UNSUPPORTED, PPE_ERR_HIP, PPE_ERR_NONFINITE = -1, -2, -3, -4, -5
 PPE_PC_NONE, PPE_PC_JACOBI = 0, 1
 PPE_TOL_RELATIVE, PPE_TOL_ABSOLUTE = 0, 1
-PPE_PCG_AUTO, PPE_PCG_SINGLE_REDUCTION, PPE_PCG_TWO_PHASE = 0, 1, 2
+PPE_PCG_AUTO, PPE_PCG_SINGLE_REDUCTION, PPE_PCG_TWO_PHASE, PPE_PCG_TWO_STEP = 0, 1, 2, 3
 PPE_DIR_NET, PPE_DIR_ZERO, PPE_DIR_JACOBI, PPE_DIR_NAN, PPE_DIR_ONES = 0, 1, 2, 3, 4
 
 
@@ -47,7 +47,7 @@ class ppe_solve_opts(ctypes.Structure):
 
 class ppe_tune_result(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
-                ("us_per_iter", (ctypes.c_double * 4) * 2)]
+                ("us_per_iter", (ctypes.c_double * 6) * 3)]
 
 
 class ppe_solve_stats(ctypes.Structure):
@@ -247,8 +247,9 @@ def ppe_tune_pcg(prob: Problem, f, x, reps=20, stream=None):
     res = ppe_tune_result()
     _check(lib().ppe_tune_pcg(prob.handle, nb, _dev(f, torch.float32, "f"), _dev(x, torch.float64, "x"), reps,
                               ctypes.byref(res), _stream(stream)))
-    forms = ("single", "two_phase")
-    table = {(forms[v], r): res.us_per_iter[v][k] for v in range(2) for k, r in enumerate((2, 4, 8, 16))}
+    forms = ("single", "two_phase", "two_step")
+    table = {(forms[v], r): res.us_per_iter[v][k] for v in range(3) for k, r in enumerate((2, 4, 8, 16, 20, 24))
+             if res.us_per_iter[v][k] > 0}
     return {"variant": res.variant, "rows_per_wave": res.rows_per_wave, "us_per_iter": table}
 
 

@@ -48,7 +48,8 @@ def test_enum_values_match_header():
     text = open(HEADER).read()
     for name in ["PPE_OK", "PPE_NOT_CONVERGED", "PPE_ERR_INVALID_ARG", "PPE_ERR_SHAPE", "PPE_ERR_UNSUPPORTED",
                  "PPE_ERR_HIP", "PPE_ERR_NONFINITE", "PPE_PC_NONE", "PPE_PC_JACOBI", "PPE_TOL_RELATIVE",
-                 "PPE_TOL_ABSOLUTE", "PPE_PCG_AUTO", "PPE_PCG_SINGLE_REDUCTION", "PPE_PCG_TWO_PHASE", "PPE_DIR_NET",
+                 "PPE_TOL_ABSOLUTE", "PPE_PCG_AUTO", "PPE_PCG_SINGLE_REDUCTION", "PPE_PCG_TWO_PHASE", "PPE_PCG_TWO_STEP",
+                 "PPE_DIR_NET",
                  "PPE_DIR_ZERO", "PPE_DIR_JACOBI", "PPE_DIR_NAN", "PPE_DIR_ONES"]:
         m = re.search(r"\b" + name + r"\s*=\s*(-?\d+)", text)
         assert m, name

@@ -1,8 +1,9 @@
-"""Mixed-size batches (one launch per iteration over a work list of all
-grids) against single solves and the oracle: every solve of the batch is
-bit-identical to the same solve alone (same iteration form and tile height:
-identical arithmetic and reduction order), reaches the tolerance on the FP64
-true residual the oracle recomputes, and keeps its own status and timing."""
+"""Mixed-size batches (one launch per two iterations, or per iteration, over a
+work list of all grids) against single solves and the oracle: every solve of
+the batch is bit-identical to the same solve alone (same iteration form and
+tile height: identical arithmetic and reduction order), reaches the tolerance
+on the FP64 true residual the oracle recomputes, and keeps its own status and
+timing."""
 import ctypes
 
 import numpy as np
@@ -46,9 +47,10 @@ def true_res(g, f, x):
     return np.linalg.norm(b - oracle.apply(g, x)) / np.linalg.norm(b)
 
 
-def test_mixed_batch_equals_single_solves(ppe):
+@pytest.mark.parametrize("variant,rows", [(3, 4), (3, 20), (1, 4)], ids=["two_step_R4", "two_step_R20", "single_R4"])
+def test_mixed_batch_equals_single_solves(ppe, variant, rows):
     sys_ = systems([(130, 67), (64, 64), (200, 150), (96, 256), (33, 21)], seed=1)
-    st, stats, xs, probs = run_batch(ppe, sys_, tol=1e-7, rows_per_wave=4)
+    st, stats, xs, probs = run_batch(ppe, sys_, tol=1e-7, rows_per_wave=rows, variant=variant)
     assert st == ppe.PPE_OK
     for (g, f), x, s, p in zip(sys_, xs, stats, probs):
         assert true_res(g, f, x) <= 1e-7 * 1.001
@@ -56,7 +58,7 @@ def test_mixed_batch_equals_single_solves(ppe):
         fd = torch.from_numpy(f[None]).cuda()
         xd = torch.zeros((1,) + f.shape, dtype=torch.float64, device="cuda")
         st1, s1 = ppe.ppe_solve_plain(p, fd, xd, ppe.ppe_solve_opts_default(
-            tol=1e-7, rows_per_wave=4, variant=ppe.PPE_PCG_SINGLE_REDUCTION))
+            tol=1e-7, rows_per_wave=rows, variant=variant))
         assert st1 == ppe.PPE_OK and s1[0]["iters_total"] == s["iters_total"]
         np.testing.assert_array_equal(xd[0].cpu().numpy(), x)
         assert 0.0 < s["ms_device"] <= s["ms_total"]
@@ -110,6 +112,8 @@ def test_batch_argument_checks(ppe):
         ppe.ppe_solve_batch([p, p], [f, f], [x, x.clone()])
     with pytest.raises(ValueError):
         ppe.ppe_solve_batch([p], [f[:16]], [x])
+    with pytest.raises(ppe.PPEError):  # the two-phase form is not batched over mixed sizes
+        ppe.ppe_solve_batch([p], [f], [x], ppe.ppe_solve_opts_default(variant=ppe.PPE_PCG_TWO_PHASE))
     # a network is rejected before anything runs
     arr = (ctypes.c_void_p * 1)(p.handle.value)
     fa = (ctypes.c_void_p * 1)(f.data_ptr())

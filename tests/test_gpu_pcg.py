@@ -76,7 +76,7 @@ def _solve(T, prob, f, x0=None, **kw):
 
 @pytest.mark.parametrize("k", [1, 2, 5, 17, 40])
 @pytest.mark.parametrize("nx,ny,beta", [(64, 64, 1.5), (70, 45, 2.0), (130, 67, 2.5), (65, 41, 1.2)])
-@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["single", "two_phase", "two_step"])
 def test_fixed_iterations_match_oracle(T, orc, variant, k, nx, ny, beta):
     ppe = _ppe()
     g = inputs.make_grid(nx, ny, beta)
@@ -93,7 +93,7 @@ def test_fixed_iterations_match_oracle(T, orc, variant, k, nx, ny, beta):
 
 
 @pytest.mark.parametrize("seed", range(10))
-@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["single", "two_phase", "two_step"])
 def test_c1_converged_solves(T, orc, variant, seed):
     """64x64, beta 1.5, 8 Gaussian bumps: tol 1e-6 and 1e-8 on the FP64 true residual;
     at 1e-8 the solution matches the direct solve to 1e-6."""
@@ -124,7 +124,7 @@ def test_c1_converged_solves(T, orc, variant, seed):
     assert so8.iters_total - 3 <= iters[1e-8] <= 1.3 * so8.iters_total + 3, (iters, so8.iters_total)
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["single", "two_phase", "two_step"])
 def test_batched_matches_single(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(96, 80, 2.0, 1.3)
@@ -141,7 +141,7 @@ def test_batched_matches_single(T, orc, variant):
         np.testing.assert_array_equal(x1[0], x[s])
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["single", "two_phase", "two_step"])
 def test_deterministic_and_graph_equals_eager(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(128, 96, 2.2)
@@ -154,10 +154,14 @@ def test_deterministic_and_graph_equals_eager(T, orc, variant):
         assert stats[0]["rel_res_true"] == runs[0][1][0]["rel_res_true"]
 
 
-@pytest.mark.parametrize("rows", [2, 4, 8, 16])
-@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
+@pytest.mark.parametrize("rows", [2, 4, 8, 16, 20, 24])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["single", "two_phase", "two_step"])
 def test_tile_heights_agree(T, orc, variant, rows):
     ppe = _ppe()
+    if rows > 16 and variant != ppe.PPE_PCG_TWO_STEP:
+        with pytest.raises(ppe.PPEError):
+            ppe.ppe_set_tuning(ppe.ppe_problem_create(inputs.make_grid(8, 8, 0.0)), 1, variant, rows)
+        return
     g = inputs.make_grid(150, 77, 1.7)
     prob = ppe.ppe_problem_create(g)
     f = inputs.grf(g, 4).astype(np.float32)
@@ -167,7 +171,7 @@ def test_tile_heights_agree(T, orc, variant, rows):
     assert np.linalg.norm(b - orc.apply(g, x[0])) / np.linalg.norm(b) <= 1e-8 * 1.001
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["single", "two_phase", "two_step"])
 def test_vanilla_cg(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(64, 48, 1.0)
@@ -181,7 +185,7 @@ def test_vanilla_cg(T, orc, variant):
     assert np.linalg.norm(x7[0] - orc.remove_mean(xo)) / np.linalg.norm(xo) <= 1e-5
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["single", "two_phase", "two_step"])
 def test_edge_cases(T, orc, variant):
     ppe = _ppe()
     g = inputs.make_grid(33, 21, 1.5)
@@ -232,7 +236,7 @@ def test_invalid_arguments(T):
         ppe.ppe_solve_plain(prob, f, x, ppe.ppe_solve_opts_default(tol=-1.0))
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["single", "two_phase"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["single", "two_phase", "two_step"])
 def test_full_size_1024(T, orc, variant):
     """The benchmark's workload: 1024^2, beta 1.75, ellipse mask, GRF source,
     solved to 1e-6 in the benchmark's launch configuration; the FP64 true residual
@@ -264,12 +268,12 @@ def test_tuner_choice_is_used(T, orc):
     fd = _dev(T, fs, T.float32)
     xd = T.zeros(fs.shape, dtype=T.float64, device="cuda")
     res = ppe.ppe_tune_pcg(prob, fd, xd, reps=6)
-    assert res["variant"] in (ppe.PPE_PCG_SINGLE_REDUCTION, ppe.PPE_PCG_TWO_PHASE)
-    assert res["rows_per_wave"] in (2, 4, 8, 16)
-    assert len(res["us_per_iter"]) == 8 and all(v > 0 for v in res["us_per_iter"].values())
+    assert res["variant"] in (ppe.PPE_PCG_SINGLE_REDUCTION, ppe.PPE_PCG_TWO_PHASE, ppe.PPE_PCG_TWO_STEP)
+    assert res["rows_per_wave"] in (2, 4, 8, 16, 20, 24)
+    assert len(res["us_per_iter"]) == 14 and all(v > 0 for v in res["us_per_iter"].values())
     best = min(res["us_per_iter"], key=res["us_per_iter"].get)
-    assert res["us_per_iter"][best] == res["us_per_iter"][("single" if res["variant"] == 1 else "two_phase",
-                                                          res["rows_per_wave"])]
+    name = {1: "single", 2: "two_phase", 3: "two_step"}[res["variant"]]
+    assert res["us_per_iter"][best] == res["us_per_iter"][(name, res["rows_per_wave"])]
     assert ppe.ppe_get_tuning(prob, 3) == (res["variant"], res["rows_per_wave"])
     st, stats, x_auto = _solve(T, prob, fs, tol=1e-7)
     st2, stats2, x_expl = _solve(T, prob, fs, tol=1e-7, variant=res["variant"], rows_per_wave=res["rows_per_wave"])
@@ -278,8 +282,30 @@ def test_tuner_choice_is_used(T, orc):
     # a stored choice replaces the tuned one; other batch sizes keep the heuristic
     ppe.ppe_set_tuning(prob, 3, ppe.PPE_PCG_TWO_PHASE, 4)
     assert ppe.ppe_get_tuning(prob, 3) == (ppe.PPE_PCG_TWO_PHASE, 4)
-    assert ppe.ppe_get_tuning(prob, 1) == (ppe.PPE_PCG_SINGLE_REDUCTION, 2)
+    assert ppe.ppe_get_tuning(prob, 1) == (ppe.PPE_PCG_TWO_STEP, 2)
     with pytest.raises(ppe.PPEError):
         ppe.ppe_set_tuning(prob, 3, ppe.PPE_PCG_AUTO, 4)
     with pytest.raises(ppe.PPEError):
         ppe.ppe_set_tuning(prob, 3, ppe.PPE_PCG_TWO_PHASE, 5)
+
+
+@pytest.mark.parametrize("n,beta", [(256, 2.0), (512, 1.75)])
+def test_two_step_iterations_track_single(T, orc, n, beta):
+    """Two iterations per launch take the second step's scalars from an exact
+    expansion in the previous launch's sums, so the iteration count to 1e-6
+    must track the one-iteration form's (FP32 vectors make them differ by
+    rounding only), and the true residual recomputed by the oracle must meet
+    the tolerance."""
+    ppe = _ppe()
+    g = inputs.with_ellipse(inputs.make_grid(n, n, beta), np.random.default_rng(n))
+    prob = ppe.ppe_problem_create(g)
+    f = inputs.grf(g, n).astype(np.float32)
+    b, _ = orc.rhs(g, f)
+    its = {}
+    for v in (ppe.PPE_PCG_SINGLE_REDUCTION, ppe.PPE_PCG_TWO_STEP):
+        st, stats, x = _solve(T, prob, f, tol=1e-6, variant=v)
+        assert st == ppe.PPE_OK
+        assert np.linalg.norm(b - orc.apply(g, x[0])) / np.linalg.norm(b) <= 1e-6 * 1.001
+        its[v] = stats[0]["iters_total"]
+    one, two = its[ppe.PPE_PCG_SINGLE_REDUCTION], its[ppe.PPE_PCG_TWO_STEP]
+    assert abs(two - one) <= 0.02 * one + 2, its
