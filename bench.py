@@ -138,7 +138,7 @@ def main():
     tuning = None
     if variant == ppe.PPE_PCG_AUTO and not args.kernels_only and args.rows == 0:
         # Launch-configuration tuning on the workload itself, before any timing.
-        tuning = ppe.ppe_tune_pcg(prob, f, torch.zeros_like(x), reps=20)
+        tuning = ppe.ppe_tune_pcg(prob, f, torch.zeros_like(x), reps=50)
         variant, rows = tuning["variant"], tuning["rows_per_wave"]
     else:
         rows = args.rows or (ppe.ppe_get_tuning(prob, 1)[1] if variant == ppe.PPE_PCG_AUTO else 0)

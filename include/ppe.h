@@ -67,8 +67,8 @@ enum { PPE_TOL_RELATIVE = 0, PPE_TOL_ABSOLUTE = 1 };   /* ||b-Ax||2 <= tol*||b||
  * workgroup carries a 4-cell halo). A launch of TWO_STEP may do a single
  * iteration (next to max_iter, or when the expansion is not positive), so
  * iteration counts keep their meaning. AUTO takes the problem's tuned
- * choice for the batch size (ppe_tune_pcg, ppe_set_tuning), else the size
- * heuristic (two-step below 2^21 cells per launch and two-phase above). The
+ * choice for the batch size (ppe_tune_pcg, ppe_set_tuning), else TWO_STEP
+ * (the fastest form on MI355X at every size measured, 256^2 to 2 x 2048^2). The
  * hybrid solve always uses TWO_PHASE; the mixed-size batch (ppe_solve_batch)
  * runs TWO_STEP for AUTO and TWO_STEP, SINGLE_REDUCTION on request, and
  * rejects TWO_PHASE. */
@@ -244,8 +244,9 @@ ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* proble
  * size nb). ppe_tune_pcg runs every iteration form x tile height (2, 4, 8,
  * 16 rows per wavefront) for `reps` iterations on the caller's system
  * (f: device FP32 [nb][ny][nx]; x: device FP64 [nb][ny][nx], overwritten),
- * timing each launch with HIP events, and stores the fastest in the problem;
- * later solves with variant PPE_PCG_AUTO and rows_per_wave 0 use it.
+ * timing each launch with HIP events, and stores the fastest in the problem
+ * (the untuned default stays unless another candidate is more than 3 %
+ * faster); later solves with variant PPE_PCG_AUTO and rows_per_wave 0 use it.
  * out (host, optional) receives the choice and the per-iteration times in
  * microseconds (per CG iteration: a two-step launch counts as two),
  * us_per_iter[form][k] for form 0 single reduction, 1 two-phase, 2 two-step

@@ -51,6 +51,7 @@ namespace ppe {
 constexpr int kSums2 = 11;
 constexpr int kH2 = 4;                  // halo depth of a launch (cells)
 constexpr int kOwn2 = kWave - 2 * kH2;  // columns owned by a wavefront
+constexpr int kPre = 16;                // partials per thread loaded ahead (P2 <= 256 in one go)
 
 // Sums of solve s (of nbs solves sharing a.part2) written by launch parity par.
 __device__ __forceinline__ double* sums2_of(const PcgArgs& a, int par, int s, int nbs) {
@@ -88,23 +89,24 @@ __device__ __forceinline__ float shr1(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 
-// Coefficients of one row in one lane: east and west face weights times the
-// row height (cE, and -cW), the north face weight times the column width
-// (cN; the south weight of a row is the north weight of the row below), and
-// the reciprocal diagonal.
+// Coefficients of one row in one lane: the east and west face weights times
+// the row height (cE, and -cW) and the reciprocal diagonal. The weights of
+// the faces between rows (times the column width) are kept per face: cF[q]
+// for the face below row q, so row q has south weight cF[q] and north weight
+// cF[q + 1].
 struct RowW {
-  float cE, ncW, cN, mi;
+  float cE, ncW, mi;
 };
 
 // (A v) at a cell from its east difference dE = v - v_east (the west
-// difference is minus the east difference of the lane to the west) and its
-// north differences dN = v - v_north of this row and of the row below:
+// difference is minus the east difference of the lane to the west) and the
+// differences dN = v - v_north of this row and dNs of the row below:
 //   A v = cE dE + cW (v - v_west) + cN (v - v_north) + cS (v - v_south).
-__device__ __forceinline__ float stencil_d(const RowW& w, float cNs, float dE, float dN, float dNs) {
+__device__ __forceinline__ float stencil_d(const RowW& w, float cN, float cS, float dE, float dN, float dNs) {
   float t = w.cE * dE;
   t += w.ncW * shr1(dE);
-  t = fmaf(w.cN, dN, t);
-  return fmaf(-cNs, dNs, t);
+  t = fmaf(cN, dN, t);
+  return fmaf(-cS, dNs, t);
 }
 
 template <int R, bool JAC>
@@ -126,18 +128,31 @@ __device__ __forceinline__ void pcg2_body(const PcgArgs& a, int s, int nbs, int 
   const bool inx = tl.valid && i >= 0 && i < nx;
   const bool own = inx && lane >= kH2 && lane < kWave - kH2;
 
-  // Loads first: r and p on all Q rows, x_c on the owned rows.
+  // Byte offsets of cells: a lane part (kOOB for columns off the grid, or not
+  // owned) plus a row part (kOOB for rows off the grid, a scalar), added with
+  // unsigned saturation, so any part off the grid gives an out-of-range
+  // offset: the buffer access reads 0 or is dropped.
+  const uint32_t lane4 = inx ? (uint32_t)i * 4u : kOOB, own4 = own ? (uint32_t)i * 4u : kOOB;
+  auto row4 = [&](int j) { return (j >= 0 && j < ny) ? (uint32_t)(j * nx) * 4u : kOOB; };
+  auto at = [](uint32_t l, uint32_t r) { return __builtin_elementwise_add_sat(l, r); };
+
+  // Loads first: the previous launch's partial sums (their scalars gate all
+  // the arithmetic, and loads complete in issue order), then r and p on all
+  // Q rows and x_c on the owned rows.
+  double pre[kPre];
+  sums16_load<kSums2, kPre>(sums2_of(a, pm, s, nbs), a.P2, pre);
+  __builtin_amdgcn_sched_barrier(0);  // keep these loads ahead of the tile loads
   const uint64_t vbytes = (uint64_t)a.N * 4;
   const auto rsr = make_rsrc(rin, vbytes), psr = make_rsrc(pin, vbytes), xsr = make_rsrc(xc, vbytes);
   float ro[Q], po[Q], xcv[R];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const uint32_t o = cell_off(inx, j0 - kH2 + q, ny, nx, i);
+    const uint32_t o = at(lane4, row4(j0 - kH2 + q));
     ro[q] = bload(rsr, o);
     po[q] = bload(psr, o);
   }
 #pragma unroll
-  for (int q = 0; q < R; ++q) xcv[q] = bload(xsr, cell_off(own, j0 + q, ny, nx, i));
+  for (int q = 0; q < R; ++q) xcv[q] = bload(xsr, at(own4, row4(j0 + q)));
   // Row coefficients of rows j0-4 .. j0+R+3 (faces j0-4 .. j0+R+4): lane q
   // holds those of row j0-4+q (the padded arrays read 0 off the grid), and
   // each row's values are taken with readlane where the row is processed, so
@@ -156,7 +171,7 @@ __device__ __forceinline__ void pcg2_body(const PcgArgs& a, int s, int nbs, int 
   double rr_ru = st->rr_ru[pm];
   const bool leader = blk == 0 && threadIdx.x == 0;
   double sum[kSums2];
-  reduce_sums16<kSums2>(sums2_of(a, pm, s, nbs), a.P2, lds_red, sum);
+  sums16_finish<kSums2, kPre>(sums2_of(a, pm, s, nbs), a.P2, pre, lds_red, sum);
   if (__builtin_expect(dprev != 0, 0)) {
     if (leader) st->dflag[par] = dprev;
     return;
@@ -337,31 +352,32 @@ __device__ __forceinline__ void pcg2_body(const PcgArgs& a, int s, int nbs, int 
     // Per row: coefficients; per field and row: the value and its north
     // difference (value minus the value of the row above).
     RowW W[Q];
+    float cF[Q + 1];
     float pk[Q], dpk[Q], r1[Q], pk1[Q], dpk1[Q], z2[Q], dz2[Q], v1[Q], dv1[Q], u1[Q], du1[Q];
+    const float gew = ge + gw;
+    cF[0] = hx * lane_f32(gyv, 0);
 #pragma unroll
     for (int t = 0; t < Q; ++t) {
       {  // coefficients and stage 0 (p_k) on row t
-        const float hyq = lane_f32(hyv, t), gs = lane_f32(gyv, t), gn = lane_f32(gyv, t + 1);
+        const float hyq = lane_f32(hyv, t);
+        cF[t + 1] = hx * lane_f32(gyv, t + 1);
         W[t].cE = hyq * ge;
         W[t].ncW = -(hyq * gw);
-        W[t].cN = hx * gn;
-        W[t].mi = JAC ? __builtin_amdgcn_rcpf(fmaxf(hyq * (ge + gw) + hx * (gn + gs), 1e-30f)) : 1.f;
+        W[t].mi = JAC ? __builtin_amdgcn_rcpf(fmaxf(fmaf(hyq, gew, cF[t] + cF[t + 1]), 1e-30f)) : 1.f;
         const float z = ro[t] * W[t].mi;
         pk[t] = rst ? fc0 * z : fc0 * z + fbet * po[t];
         if (t >= 1) dpk[t - 1] = pk[t - 1] - pk[t];
       }
       if (t >= 2) {  // stage 1, row q = t - 1: A p_k, r_{k+1}, p_{k+1}
         const int q = t - 1;
-        const float cNs = hx * lane_f32(gyv, q);
-        const float s0 = stencil_d(W[q], cNs, pk[q] - shl1(pk[q]), dpk[q], dpk[q - 1]);
+        const float s0 = stencil_d(W[q], cF[q + 1], cF[q], pk[q] - shl1(pk[q]), dpk[q], dpk[q - 1]);
         r1[q] = ro[q] - falf * s0;
         pk1[q] = fcz * (r1[q] * W[q].mi) + fbet1 * pk[q];
         if (q >= 2) dpk1[q - 1] = pk1[q - 1] - pk1[q];
       }
       if (t >= 4) {  // stage 2, row q = t - 2: A p_{k+1}, r_{k+2}, z_{k+2}, v1; stores
         const int q = t - 2;
-        const float cNs = hx * lane_f32(gyv, q);
-        const float s1 = stencil_d(W[q], cNs, pk1[q] - shl1(pk1[q]), dpk1[q], dpk1[q - 1]);
+        const float s1 = stencil_d(W[q], cF[q + 1], cF[q], pk1[q] - shl1(pk1[q]), dpk1[q], dpk1[q - 1]);
         const float r2 = r1[q] - falf1 * s1;
         z2[q] = r2 * W[q].mi;
         v1[q] = W[q].mi * s1;
@@ -370,7 +386,7 @@ __device__ __forceinline__ void pcg2_body(const PcgArgs& a, int s, int nbs, int 
           dv1[q - 1] = v1[q - 1] - v1[q];
         }
         if (q >= kH2 && q < kH2 + R) {
-          const uint32_t o = cell_off(own, j0 - kH2 + q, ny, nx, i);
+          const uint32_t o = at(own4, row4(j0 - kH2 + q));
           bstore(rso, o, r2);
           bstore(pso, o, pk1[q]);
           bstore(xsr, o, xcv[q - kH2] + falf * pk[q] + falf1 * pk1[q]);
@@ -384,8 +400,7 @@ __device__ __forceinline__ void pcg2_body(const PcgArgs& a, int s, int nbs, int 
       }
       if (t >= 6) {  // stage 3, row q = t - 3: A z_{k+2}, u1
         const int q = t - 3;
-        const float cNs = hx * lane_f32(gyv, q);
-        const float az = stencil_d(W[q], cNs, z2[q] - shl1(z2[q]), dz2[q], dz2[q - 1]);
+        const float az = stencil_d(W[q], cF[q + 1], cF[q], z2[q] - shl1(z2[q]), dz2[q], dz2[q - 1]);
         u1[q] = W[q].mi * az;
         if (q >= 4) du1[q - 1] = u1[q - 1] - u1[q];
         if (q >= kH2 && q < kH2 + R) {
@@ -397,9 +412,8 @@ __device__ __forceinline__ void pcg2_body(const PcgArgs& a, int s, int nbs, int 
       }
       if (t >= 8) {  // stage 4, row q = t - 4 (an owned row): A u1, A v1
         const int q = t - 4;
-        const float cNs = hx * lane_f32(gyv, q);
-        const float au = stencil_d(W[q], cNs, u1[q] - shl1(u1[q]), du1[q], du1[q - 1]);
-        const float av = stencil_d(W[q], cNs, v1[q] - shl1(v1[q]), dv1[q], dv1[q - 1]);
+        const float au = stencil_d(W[q], cF[q + 1], cF[q], u1[q] - shl1(u1[q]), du1[q], du1[q - 1]);
+        const float av = stencil_d(W[q], cF[q + 1], cF[q], v1[q] - shl1(v1[q]), dv1[q], dv1[q - 1]);
         const double du = u1[q], dv = v1[q], dau = au, dav = av;
         acc[7] += own ? du * dau : 0.0;
         acc[8] += own ? dau * dv : 0.0;

@@ -346,6 +346,44 @@ __device__ __forceinline__ void reduce_sums16(const double* __restrict__ part, i
   for (int m = 0; m < N; ++m) out[m] = lds[m];
 }
 
+// The same reduction split in two, so that a kernel can issue the loads of
+// the partials before its own tile loads: loads complete in issue order, and
+// the scalars that the tile's arithmetic needs then arrive first.
+// sums16_load: thread 16m + c loads partials k = c + 16 i (i < K) of sum m
+// (0 past P; part is [N][P]). sums16_finish: adds them in order of i, then
+// any partials past 16 K, and finishes as reduce_sums16. The order is fixed
+// for a given P, so every workgroup obtains the same bits.
+template <int N, int K>
+__device__ __forceinline__ void sums16_load(const double* __restrict__ part, int P, double (&pre)[K]) {
+  static_assert(16 * N <= kBlock, "one 16-lane row per sum");
+  const int t = threadIdx.x;
+  const int m = t >> 4, c = t & 15;
+  const auto rs = make_rsrc(part, (uint64_t)N * P * 8);
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const int k = c + 16 * i;
+    pre[i] = bload64(rs, (t < 16 * N && k < P) ? (uint32_t)(m * P + k) * 8u : kOOB);
+  }
+}
+
+template <int N, int K>
+__device__ __forceinline__ void sums16_finish(const double* __restrict__ part, int P, const double (&pre)[K],
+                                              double* lds, double (&out)[N]) {
+  const int t = threadIdx.x;
+  if (t < 16 * N) {
+    const int m = t >> 4, c = t & 15;
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) v += pre[i];
+    for (int k = c + 16 * K; k < P; k += 16) v += part[(size_t)m * P + k];
+    v = row_sum16(v);
+    if (c == 0) lds[m] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < N; ++m) out[m] = lds[m];
+}
+
 // Workgroup sums of N values per thread, stored by one thread per sum into
 // part[m][blk] ([N][P]). The values go through LDS (lds: N * kBlock doubles):
 // thread 16m + c adds threads c, c + 16, ..., c + 240 of sum m, and the

@@ -259,7 +259,7 @@ def test_full_size_1024(T, orc, variant):
 
 
 def test_tuner_choice_is_used(T, orc):
-    """The tuner times every form and tile height, stores the fastest, and an
+    """The tuner times every form and tile height, stores its choice, and an
     AUTO solve then runs exactly that configuration (identical bits)."""
     ppe = _ppe()
     g = inputs.make_grid(192, 128, 2.0)
@@ -271,9 +271,10 @@ def test_tuner_choice_is_used(T, orc):
     assert res["variant"] in (ppe.PPE_PCG_SINGLE_REDUCTION, ppe.PPE_PCG_TWO_PHASE, ppe.PPE_PCG_TWO_STEP)
     assert res["rows_per_wave"] in (2, 4, 8, 16, 20, 24)
     assert len(res["us_per_iter"]) == 14 and all(v > 0 for v in res["us_per_iter"].values())
-    best = min(res["us_per_iter"], key=res["us_per_iter"].get)
+    # the choice is the fastest candidate, or the untuned default when nothing
+    # beats it by more than 3 %
     name = {1: "single", 2: "two_phase", 3: "two_step"}[res["variant"]]
-    assert res["us_per_iter"][best] == res["us_per_iter"][(name, res["rows_per_wave"])]
+    assert res["us_per_iter"][(name, res["rows_per_wave"])] <= min(res["us_per_iter"].values()) / 0.97
     assert ppe.ppe_get_tuning(prob, 3) == (res["variant"], res["rows_per_wave"])
     st, stats, x_auto = _solve(T, prob, fs, tol=1e-7)
     st2, stats2, x_expl = _solve(T, prob, fs, tol=1e-7, variant=res["variant"], rows_per_wave=res["rows_per_wave"])
