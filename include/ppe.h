@@ -149,6 +149,8 @@ typedef struct {
   float grf_len_lo, grf_len_hi;
   int32_t grf_features;
   float clip_norm;              /* > 0: scale the gradient to this L2 norm before Adam when larger (default 0) */
+  float sam_rho;                /* > 0: sharpness-aware step (Sec. 2.4): the gradient Adam uses is taken at
+                                   w + sam_rho g / |g| (two forward/backward passes; default 0) */
 } ppe_train_opts;
 
 /* ---- problem (Sec. 8 a1: per-grid setup, built once and reused, as the paper
@@ -234,7 +236,8 @@ ppe_status ppe_generate_rhs(int32_t nb, ppe_problem* const* problems, const ppe_
  * library then generates the batch with ppe_generate_rhs from opts (seed,
  * step, length-scale range, features).
  * loss_out: host, the batch loss before the step. grad_out: host or NULL;
- * when given, receives the FP32 gradient (ppe_net_num_params values). */
+ * when given, receives the FP32 gradient that Adam uses (ppe_net_num_params
+ * values; with sam_rho > 0 the one at the perturbed weights). */
 ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* problems, const float* R,
                               const ppe_train_opts* opts, float* loss_out, float* grad_out,
                               hipStream_t s);

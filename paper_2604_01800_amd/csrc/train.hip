@@ -58,7 +58,8 @@ struct TrainState {
   // generated right-hand sides (R == NULL)
   GenWs gen;
   float* d_R = nullptr;  // [nb][N]
-  double* gpart = nullptr;  // [kRedBlocks] partial sums of the squared gradient (clipping)
+  double* gpart = nullptr;  // [kRedBlocks] partial sums of the squared gradient (clipping, SAM)
+  float* w_save = nullptr;  // [np] weights kept during a sharpness-aware step
 };
 
 static int pad8(int c) { return (c + 7) / 8 * 8; }
@@ -72,6 +73,7 @@ void net_train_free(ppe_net* n) {
   gen_free(t->gen);
   dev_free(t->d_R);
   dev_free(t->gpart);
+  dev_free(t->w_save);
   dev_free(t->act);
   dev_free(t->grad);
   dev_free(t->eta);
@@ -223,6 +225,8 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
   }
   if (!(opts->clip_norm >= 0.f) || !std::isfinite(opts->clip_norm))
     return set_error(PPE_ERR_INVALID_ARG, "clip_norm must be finite and >= 0");
+  if (!(opts->sam_rho >= 0.f) || !std::isfinite(opts->sam_rho))
+    return set_error(PPE_ERR_INVALID_ARG, "sam_rho must be finite and >= 0");
   for (int i = 0; i < nb; ++i) {
     if (!problems[i]) return set_error(PPE_ERR_INVALID_ARG, "problems[%d] is NULL", i);
     if (problems[i]->nx != problems[0]->nx || problems[i]->ny != problems[0]->ny)
@@ -282,234 +286,259 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
   const float* W = n->d_w;
   float* dG = n->d_g;
 
-  // packed weights of this step (transposed operators and the head / trunk forward)
-  for (int l = 0; l < L; ++l) {
-    const MConvL& a = n->enc_a[l];
-    const MConvL& b = n->enc_b[l];
-    launch_pack_weights_t(W + a.oW, a.cout, a.cin, a.cin8, 9, t->kT_a[l], PK + t->pT_a[l], s);
-    launch_pack_weights_t(W + b.oW, b.cout, b.cin, b.cin8, 9, t->kT_b[l], PK + t->pT_b[l], s);
-    if (l < L - 1) {
-      const MConvL& c = n->dec_c[l];
-      const MConvL& d = n->dec_d[l];
-      const UpL& u = n->up[l];
-      launch_pack_weights_t(W + c.oW, c.cout, c.cin, c.cin8, 9, t->kT_c[l], PK + t->pT_c[l], s);
-      launch_pack_weights_t(W + d.oW, d.cout, d.cin, d.cin8, 9, t->kT_d[l], PK + t->pT_d[l], s);
-      launch_pack_weights_t(W + u.oW, u.cout, u.cin, u.cin, 1, t->kT_up[l], PK + t->pT_up[l], s);
-    }
-  }
-  launch_pack_weights(W + n->o_headW, P, C0, C0, 1, t->kF_head, PK + t->pF_head, s);
-  launch_pack_weights_t(W + n->o_headW, P, C0, C0, 1, t->kT_head, PK + t->pT_head, s);
-  for (int k = 0; k <= TH; ++k) {
-    const int cin = k == 0 ? 2 : TWd, cin8 = k == 0 ? 8 : TWd, cout = k == TH ? P : TWd;
-    launch_pack_weights(W + n->o_tW[k], cout, cin, cin8, 1, t->kF_tr[k], PK + t->pF_tr[k], s);
-    launch_pack_weights_t(W + n->o_tW[k], cout, cin, cin8, 1, t->kT_tr[k], PK + t->pT_tr[k], s);
-  }
-
-  // static channels, trunk input and per-sample eta maps
-  for (int l = 0; l < L; ++l) {
-    const float* lvl = t->d_lv + t->lv_off[l];
-    const int coff_in = cfg.use_spacing ? (l == 0 ? 2 : ch(l - 1)) : -1;
-    launch_fill_static_multi(t->H[l], t->W[l], t->p_in[l], coff_in, lvl, t->lv_stride, t->d_masks, l == 0 ? 1 : -1,
-                             Ab + t->o_in[l], hw(l) * t->p_in[l], nb, s);
-    if (l < L - 1 && cfg.use_spacing)
-      launch_fill_static_multi(t->H[l], t->W[l], t->p_cat[l], 2 * ch(l), lvl, t->lv_stride, nullptr, -1,
-                               Ab + t->o_cat[l], hw(l) * t->p_cat[l], nb, s);
-  }
-  launch_trunk_input(ny, nx, t->d_lv + t->tin_off, t->lv_stride, Ab + t->o_t0, nb, s);
-  auto eta_fwd = [&](const MConvL& m, int64_t off) {
-    const int l = m.level;
-    launch_eta_multi(t->H[l], t->W[l], m.cin, m.cin8, HID, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
-                     W + m.ob1, W + m.oW2, W + m.ob2, E + off, hw(l) * m.cin8, nb, s);
-  };
-  if (cfg.use_eta)
+  double* lpart = t->dpart + (size_t)kRedBlocks * nb;
+  // One forward and backward pass at the current weights: the loss sum in
+  // lpart[kRedBlocks] and the gradient in dG.
+  auto fwd_bwd = [&]() -> ppe_status {
+    // packed weights of this step (transposed operators and the head / trunk forward)
     for (int l = 0; l < L; ++l) {
-      eta_fwd(n->enc_a[l], t->e_a[l]);
-      eta_fwd(n->enc_b[l], t->e_b[l]);
+      const MConvL& a = n->enc_a[l];
+      const MConvL& b = n->enc_b[l];
+      launch_pack_weights_t(W + a.oW, a.cout, a.cin, a.cin8, 9, t->kT_a[l], PK + t->pT_a[l], s);
+      launch_pack_weights_t(W + b.oW, b.cout, b.cin, b.cin8, 9, t->kT_b[l], PK + t->pT_b[l], s);
       if (l < L - 1) {
-        eta_fwd(n->dec_c[l], t->e_c[l]);
-        eta_fwd(n->dec_d[l], t->e_d[l]);
+        const MConvL& c = n->dec_c[l];
+        const MConvL& d = n->dec_d[l];
+        const UpL& u = n->up[l];
+        launch_pack_weights_t(W + c.oW, c.cout, c.cin, c.cin8, 9, t->kT_c[l], PK + t->pT_c[l], s);
+        launch_pack_weights_t(W + d.oW, d.cout, d.cin, d.cin8, 9, t->kT_d[l], PK + t->pT_d[l], s);
+        launch_pack_weights_t(W + u.oW, u.cout, u.cin, u.cin, 1, t->kT_up[l], PK + t->pT_up[l], s);
       }
     }
-  auto etap = [&](int64_t off) -> const bf16_t* { return cfg.use_eta ? E + off : nullptr; };
-  auto geo = [&](int l, int cin8, int cout, int y_pitch, int y_off, int act) {
-    ConvGeo g;
-    g.H = t->H[l];
-    g.W = t->W[l];
-    g.cin8 = cin8;
-    g.cout = cout;
-    g.y_pitch = y_pitch;
-    g.y_off = y_off;
-    g.x_bstride = hw(l) * cin8;
-    g.y_bstride = hw(l) * y_pitch;
-    g.e_bstride = hw(l) * cin8;
-    g.act = act;
-    return g;
-  };
-
-  // ---- forward, saving activations ----
-  float* y = t->f32;
-  float* Ay = y + N * nb;
-  float* res = Ay + N * nb;
-  float* gAy = res + N * nb;
-  launch_input_pack(R, N, nb, t->dpart, Ab + t->o_in[0], t->p_in[0], N * t->p_in[0], s);
-  for (int l = 0; l < L; ++l) {
-    if (l > 0)
-      launch_pool2(t->H[l], t->W[l], ch(l - 1), Ab + t->o_cat[l - 1], t->p_cat[l - 1], ch(l - 1),
-                   4 * hw(l) * t->p_cat[l - 1], Ab + t->o_in[l], t->p_in[l], hw(l) * t->p_in[l], nb, s);
-    const MConvL& ma = n->enc_a[l];
-    const MConvL& mb = n->enc_b[l];
-    launch_conv(9, false, geo(l, ma.cin8, ma.cout, ch(l), 0, 1), nb, Ab + t->o_in[l], etap(t->e_a[l]),
-                n->d_pack + ma.opack, ma.kp, W + ma.ob, Ab + t->o_a[l], s);
-    if (l < L - 1)
-      launch_conv(9, false, geo(l, mb.cin8, mb.cout, t->p_cat[l], ch(l), 1), nb, Ab + t->o_a[l], etap(t->e_b[l]),
-                  n->d_pack + mb.opack, mb.kp, W + mb.ob, Ab + t->o_cat[l], s);
-    else
-      launch_conv(9, false, geo(l, mb.cin8, mb.cout, ch(l), 0, 1), nb, Ab + t->o_a[l], etap(t->e_b[l]),
-                  n->d_pack + mb.opack, mb.kp, W + mb.ob, Ab + t->o_bot, s);
-  }
-  for (int l = L - 2; l >= 0; --l) {
-    const UpL& u = n->up[l];
-    const bf16_t* src = (l == L - 2) ? Ab + t->o_bot : Ab + t->o_d[l + 1];
-    ConvGeo gu = geo(l + 1, u.cin, u.cout, t->p_cat[l], 0, 0);
-    gu.y_bstride = hw(l) * t->p_cat[l];
-    launch_conv(1, true, gu, nb, src, nullptr, n->d_pack + u.opack, u.kp, W + u.ob, Ab + t->o_cat[l], s);
-    const MConvL& mc = n->dec_c[l];
-    const MConvL& md = n->dec_d[l];
-    launch_conv(9, false, geo(l, mc.cin8, mc.cout, ch(l), 0, 1), nb, Ab + t->o_cat[l], etap(t->e_c[l]),
-                n->d_pack + mc.opack, mc.kp, W + mc.ob, Ab + t->o_c[l], s);
-    launch_conv(9, false, geo(l, md.cin8, md.cout, ch(l), 0, 1), nb, Ab + t->o_c[l], etap(t->e_d[l]),
-                n->d_pack + md.opack, md.kp, W + md.ob, Ab + t->o_d[l], s);
-  }
-  // head B = Wh D0 + bh and trunk T (BF16 MFMA, tanh hidden layers), then y
-  launch_conv(1, false, geo(0, C0, P, P, 0, 0), nb, Ab + t->o_d[0], nullptr, PK + t->pF_head, t->kF_head,
-              W + n->o_headb, Ab + t->o_B, s);
-  for (int k = 0; k <= TH; ++k) {
-    const int cin8 = k == 0 ? 8 : TWd, cout = k == TH ? P : TWd;
-    const bf16_t* src = k == 0 ? Ab + t->o_t0 : Ab + t->o_h[k - 1];
-    bf16_t* dst = k == TH ? Ab + t->o_T : Ab + t->o_h[k];
-    launch_conv(1, false, geo(0, cin8, cout, cout, 0, k == TH ? 0 : 2), nb, src, nullptr, PK + t->pF_tr[k],
-                t->kF_tr[k], W + n->o_tb[k], dst, s);
-  }
-  launch_don_fwd(N * nb, P, Ab + t->o_B, Ab + t->o_T, W + n->o_gamma, y, s);
-
-  // ---- loss (Eq. 19): res = R - A y, L = mean(res^2); dL/dy = -2/(nb N) A res ----
-  launch_apply_multi(t->d_coefs, nx, ny, nb, y, Ay, s);
-  double* lpart = t->dpart + (size_t)kRedBlocks * nb;
-  launch_loss(N * nb, R, Ay, res, lpart, kRedBlocks, s);
-  launch_sum_parts(lpart, kRedBlocks, 1.0 / ((double)N * nb), lpart + kRedBlocks, s);
-  launch_apply_multi(t->d_coefs, nx, ny, nb, res, gAy, s);
-  const float dscale = (float)(-2.0 / ((double)N * nb));
-
-  // ---- backward ----
-  HIPCHK(hipMemsetAsync(dG, 0, n->np * sizeof(float), s));
-  float* part = t->part;
-  const int64_t cap = t->part_len;
-  auto tiles_of = [&](int l) {
-    return (int64_t)((t->W[l] + 15) / 16) * ((t->H[l] + 7) / 8) * nb;
-  };
-  auto wgrad = [&](int taps, int l, const bf16_t* dp, int dp_pitch, int cout, const bf16_t* x, int cin8, int cin,
-                   const bf16_t* eta, int64_t oW) {
-    WgradGeo g;
-    g.H = t->H[l];
-    g.W = t->W[l];
-    g.nb = nb;
-    g.cin8 = cin8;
-    g.cin = cin;
-    g.cout = cout;
-    g.dp_pitch = dp_pitch;
-    g.x_bstride = hw(l) * cin8;
-    g.dp_bstride = hw(l) * dp_pitch;
-    g.e_bstride = hw(l) * cin8;
-    const int ns = wgrad_splits(cout, cin8, taps, tiles_of(l), cap);
-    launch_wgrad(taps, g, dp, x, eta, part, ns, s);
-    launch_reduce_rows(part, ns, (int64_t)cout * cin * taps, 1.f, dG + oW, s);
-  };
-  auto bias = [&](int l, const bf16_t* d, int pitch, int C, int64_t ob) {
-    launch_bias_grad(d, hw(l) * nb, pitch, 0, C, part, 256, s);
-    launch_reduce_rows(part, 256, C, 1.f, dG + ob, s);
-  };
-  auto dgrad = [&](int taps, int l, const bf16_t* dp, int cout_fwd, int64_t pT, int kT, int rows, bf16_t* out) {
-    ConvGeo g = geo(l, cout_fwd, rows, rows, 0, 0);
-    launch_conv(taps, false, g, nb, dp, nullptr, PK + pT, kT, nullptr, out, s);
-  };
-  auto eta_bwd = [&](const MConvL& m, const bf16_t* x, int64_t eoff, bf16_t* dxb) {
-    if (!cfg.use_eta) return;
-    const int l = m.level;
-    const int len = eta_bwd_len(m.cin, HID);
-    const int np = 2048;
-    launch_eta_bwd(t->H[l], t->W[l], m.cin, m.cin8, HID, nb, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
-                   W + m.ob1, W + m.oW2, W + m.ob2, x, E + eoff, hw(l) * m.cin8, dxb, part, np, s);
-    launch_reduce_rows(part, np, len, 1.f, dG + m.oW1, s);
-  };
-  // DeepONet contraction, head and trunk
-  launch_don_bwd(N * nb, P, Ab + t->o_B, Ab + t->o_T, W + n->o_gamma, gAy, dscale, G + t->g_B, G + t->g_T, part,
-                 kRedBlocks, s);
-  launch_reduce_rows(part, kRedBlocks, 1, 1.f, dG + n->o_gamma, s);
-  wgrad(1, 0, G + t->g_B, P, P, Ab + t->o_d[0], C0, C0, nullptr, n->o_headW);
-  bias(0, G + t->g_B, P, P, n->o_headb);
-  dgrad(1, 0, G + t->g_B, P, t->pT_head, t->kT_head, C0, G + t->g_d[0]);
-  for (int k = TH; k >= 0; --k) {
-    const int cin8 = k == 0 ? 8 : TWd, cin = k == 0 ? 2 : TWd, cout = k == TH ? P : TWd;
-    bf16_t* dk = k == TH ? G + t->g_T : G + t->g_h[k];
-    if (k < TH) launch_act_bwd(dk, cout, Ab + t->o_h[k], cout, 0, cout, N * nb, 2, s);
-    const bf16_t* xin = k == 0 ? Ab + t->o_t0 : Ab + t->o_h[k - 1];
-    wgrad(1, 0, dk, cout, cout, xin, cin8, cin, nullptr, n->o_tW[k]);
-    bias(0, dk, cout, cout, n->o_tb[k]);
-    if (k > 0) dgrad(1, 0, dk, cout, t->pT_tr[k], t->kT_tr[k], cin8, G + t->g_h[k - 1]);
-  }
-  // decoder, finest level first
-  for (int l = 0; l <= L - 2; ++l) {
-    const MConvL& md = n->dec_d[l];
-    const MConvL& mc = n->dec_c[l];
-    const UpL& u = n->up[l];
-    bf16_t* dD = G + t->g_d[l];
-    launch_act_bwd(dD, ch(l), Ab + t->o_d[l], ch(l), 0, ch(l), hw(l) * nb, 1, s);
-    wgrad(9, l, dD, ch(l), ch(l), Ab + t->o_c[l], md.cin8, md.cin, etap(t->e_d[l]), md.oW);
-    bias(l, dD, ch(l), ch(l), md.ob);
-    dgrad(9, l, dD, ch(l), t->pT_d[l], t->kT_d[l], md.cin8, G + t->g_c[l]);
-    eta_bwd(md, Ab + t->o_c[l], t->e_d[l], G + t->g_c[l]);
-    launch_act_bwd(G + t->g_c[l], ch(l), Ab + t->o_c[l], ch(l), 0, ch(l), hw(l) * nb, 1, s);
-    wgrad(9, l, G + t->g_c[l], ch(l), ch(l), Ab + t->o_cat[l], mc.cin8, mc.cin, etap(t->e_c[l]), mc.oW);
-    bias(l, G + t->g_c[l], ch(l), ch(l), mc.ob);
-    dgrad(9, l, G + t->g_c[l], ch(l), t->pT_c[l], t->kT_c[l], mc.cin8, G + t->g_cat[l]);
-    eta_bwd(mc, Ab + t->o_cat[l], t->e_c[l], G + t->g_cat[l]);
-    launch_copy_ch(G + t->g_cat[l], t->p_cat[l], ch(l), G + t->g_E[l], ch(l), ch(l), hw(l) * nb, 0, s);
-    launch_up_bwd(t->H[l + 1], t->W[l + 1], ch(l), G + t->g_cat[l], t->p_cat[l], hw(l) * t->p_cat[l],
-                  G + t->g_Uc[l], hw(l + 1) * ch(l), nb, s);
-    const bf16_t* src = (l == L - 2) ? Ab + t->o_bot : Ab + t->o_d[l + 1];
-    wgrad(1, l + 1, G + t->g_Uc[l], ch(l), ch(l), src, u.cin, u.cin, nullptr, u.oW);
-    bias(l + 1, G + t->g_Uc[l], ch(l), ch(l), u.ob);
-    bf16_t* dnext = (l == L - 2) ? G + t->g_bot : G + t->g_d[l + 1];
-    dgrad(1, l + 1, G + t->g_Uc[l], ch(l), t->pT_up[l], t->kT_up[l], u.cin, dnext);
-  }
-  // encoder, coarsest level first
-  for (int l = L - 1; l >= 0; --l) {
-    const MConvL& mb = n->enc_b[l];
-    const MConvL& ma = n->enc_a[l];
-    bf16_t* dE = (l == L - 1) ? G + t->g_bot : G + t->g_E[l];
-    if (l == L - 1)
-      launch_act_bwd(dE, ch(l), Ab + t->o_bot, ch(l), 0, ch(l), hw(l) * nb, 1, s);
-    else
-      launch_act_bwd(dE, ch(l), Ab + t->o_cat[l], t->p_cat[l], ch(l), ch(l), hw(l) * nb, 1, s);
-    wgrad(9, l, dE, ch(l), ch(l), Ab + t->o_a[l], mb.cin8, mb.cin, etap(t->e_b[l]), mb.oW);
-    bias(l, dE, ch(l), ch(l), mb.ob);
-    dgrad(9, l, dE, ch(l), t->pT_b[l], t->kT_b[l], mb.cin8, G + t->g_a[l]);
-    eta_bwd(mb, Ab + t->o_a[l], t->e_b[l], G + t->g_a[l]);
-    launch_act_bwd(G + t->g_a[l], ch(l), Ab + t->o_a[l], ch(l), 0, ch(l), hw(l) * nb, 1, s);
-    wgrad(9, l, G + t->g_a[l], ch(l), ch(l), Ab + t->o_in[l], ma.cin8, ma.cin, etap(t->e_a[l]), ma.oW);
-    bias(l, G + t->g_a[l], ch(l), ch(l), ma.ob);
-    if (cfg.use_eta || l > 0) {
-      dgrad(9, l, G + t->g_a[l], ch(l), t->pT_a[l], t->kT_a[l], ma.cin8, G + t->g_in[l]);
-      eta_bwd(ma, Ab + t->o_in[l], t->e_a[l], G + t->g_in[l]);
+    launch_pack_weights(W + n->o_headW, P, C0, C0, 1, t->kF_head, PK + t->pF_head, s);
+    launch_pack_weights_t(W + n->o_headW, P, C0, C0, 1, t->kT_head, PK + t->pT_head, s);
+    for (int k = 0; k <= TH; ++k) {
+      const int cin = k == 0 ? 2 : TWd, cin8 = k == 0 ? 8 : TWd, cout = k == TH ? P : TWd;
+      launch_pack_weights(W + n->o_tW[k], cout, cin, cin8, 1, t->kF_tr[k], PK + t->pF_tr[k], s);
+      launch_pack_weights_t(W + n->o_tW[k], cout, cin, cin8, 1, t->kT_tr[k], PK + t->pT_tr[k], s);
     }
-    if (l > 0)
-      launch_pool_bwd(t->H[l], t->W[l], ch(l - 1), G + t->g_in[l], t->p_in[l], hw(l) * t->p_in[l],
-                      G + t->g_E[l - 1], hw(l - 1) * ch(l - 1), nb, s);
-  }
-  HIPCHK(hipGetLastError());
 
+    // static channels, trunk input and per-sample eta maps
+    for (int l = 0; l < L; ++l) {
+      const float* lvl = t->d_lv + t->lv_off[l];
+      const int coff_in = cfg.use_spacing ? (l == 0 ? 2 : ch(l - 1)) : -1;
+      launch_fill_static_multi(t->H[l], t->W[l], t->p_in[l], coff_in, lvl, t->lv_stride, t->d_masks, l == 0 ? 1 : -1,
+                               Ab + t->o_in[l], hw(l) * t->p_in[l], nb, s);
+      if (l < L - 1 && cfg.use_spacing)
+        launch_fill_static_multi(t->H[l], t->W[l], t->p_cat[l], 2 * ch(l), lvl, t->lv_stride, nullptr, -1,
+                                 Ab + t->o_cat[l], hw(l) * t->p_cat[l], nb, s);
+    }
+    launch_trunk_input(ny, nx, t->d_lv + t->tin_off, t->lv_stride, Ab + t->o_t0, nb, s);
+    auto eta_fwd = [&](const MConvL& m, int64_t off) {
+      const int l = m.level;
+      launch_eta_multi(t->H[l], t->W[l], m.cin, m.cin8, HID, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
+                       W + m.ob1, W + m.oW2, W + m.ob2, E + off, hw(l) * m.cin8, nb, s);
+    };
+    if (cfg.use_eta)
+      for (int l = 0; l < L; ++l) {
+        eta_fwd(n->enc_a[l], t->e_a[l]);
+        eta_fwd(n->enc_b[l], t->e_b[l]);
+        if (l < L - 1) {
+          eta_fwd(n->dec_c[l], t->e_c[l]);
+          eta_fwd(n->dec_d[l], t->e_d[l]);
+        }
+      }
+    auto etap = [&](int64_t off) -> const bf16_t* { return cfg.use_eta ? E + off : nullptr; };
+    auto geo = [&](int l, int cin8, int cout, int y_pitch, int y_off, int act) {
+      ConvGeo g;
+      g.H = t->H[l];
+      g.W = t->W[l];
+      g.cin8 = cin8;
+      g.cout = cout;
+      g.y_pitch = y_pitch;
+      g.y_off = y_off;
+      g.x_bstride = hw(l) * cin8;
+      g.y_bstride = hw(l) * y_pitch;
+      g.e_bstride = hw(l) * cin8;
+      g.act = act;
+      return g;
+    };
+
+    // ---- forward, saving activations ----
+    float* y = t->f32;
+    float* Ay = y + N * nb;
+    float* res = Ay + N * nb;
+    float* gAy = res + N * nb;
+    launch_input_pack(R, N, nb, t->dpart, Ab + t->o_in[0], t->p_in[0], N * t->p_in[0], s);
+    for (int l = 0; l < L; ++l) {
+      if (l > 0)
+        launch_pool2(t->H[l], t->W[l], ch(l - 1), Ab + t->o_cat[l - 1], t->p_cat[l - 1], ch(l - 1),
+                     4 * hw(l) * t->p_cat[l - 1], Ab + t->o_in[l], t->p_in[l], hw(l) * t->p_in[l], nb, s);
+      const MConvL& ma = n->enc_a[l];
+      const MConvL& mb = n->enc_b[l];
+      launch_conv(9, false, geo(l, ma.cin8, ma.cout, ch(l), 0, 1), nb, Ab + t->o_in[l], etap(t->e_a[l]),
+                  n->d_pack + ma.opack, ma.kp, W + ma.ob, Ab + t->o_a[l], s);
+      if (l < L - 1)
+        launch_conv(9, false, geo(l, mb.cin8, mb.cout, t->p_cat[l], ch(l), 1), nb, Ab + t->o_a[l], etap(t->e_b[l]),
+                    n->d_pack + mb.opack, mb.kp, W + mb.ob, Ab + t->o_cat[l], s);
+      else
+        launch_conv(9, false, geo(l, mb.cin8, mb.cout, ch(l), 0, 1), nb, Ab + t->o_a[l], etap(t->e_b[l]),
+                    n->d_pack + mb.opack, mb.kp, W + mb.ob, Ab + t->o_bot, s);
+    }
+    for (int l = L - 2; l >= 0; --l) {
+      const UpL& u = n->up[l];
+      const bf16_t* src = (l == L - 2) ? Ab + t->o_bot : Ab + t->o_d[l + 1];
+      ConvGeo gu = geo(l + 1, u.cin, u.cout, t->p_cat[l], 0, 0);
+      gu.y_bstride = hw(l) * t->p_cat[l];
+      launch_conv(1, true, gu, nb, src, nullptr, n->d_pack + u.opack, u.kp, W + u.ob, Ab + t->o_cat[l], s);
+      const MConvL& mc = n->dec_c[l];
+      const MConvL& md = n->dec_d[l];
+      launch_conv(9, false, geo(l, mc.cin8, mc.cout, ch(l), 0, 1), nb, Ab + t->o_cat[l], etap(t->e_c[l]),
+                  n->d_pack + mc.opack, mc.kp, W + mc.ob, Ab + t->o_c[l], s);
+      launch_conv(9, false, geo(l, md.cin8, md.cout, ch(l), 0, 1), nb, Ab + t->o_c[l], etap(t->e_d[l]),
+                  n->d_pack + md.opack, md.kp, W + md.ob, Ab + t->o_d[l], s);
+    }
+    // head B = Wh D0 + bh and trunk T (BF16 MFMA, tanh hidden layers), then y
+    launch_conv(1, false, geo(0, C0, P, P, 0, 0), nb, Ab + t->o_d[0], nullptr, PK + t->pF_head, t->kF_head,
+                W + n->o_headb, Ab + t->o_B, s);
+    for (int k = 0; k <= TH; ++k) {
+      const int cin8 = k == 0 ? 8 : TWd, cout = k == TH ? P : TWd;
+      const bf16_t* src = k == 0 ? Ab + t->o_t0 : Ab + t->o_h[k - 1];
+      bf16_t* dst = k == TH ? Ab + t->o_T : Ab + t->o_h[k];
+      launch_conv(1, false, geo(0, cin8, cout, cout, 0, k == TH ? 0 : 2), nb, src, nullptr, PK + t->pF_tr[k],
+                  t->kF_tr[k], W + n->o_tb[k], dst, s);
+    }
+    launch_don_fwd(N * nb, P, Ab + t->o_B, Ab + t->o_T, W + n->o_gamma, y, s);
+
+    // ---- loss (Eq. 19): res = R - A y, L = mean(res^2); dL/dy = -2/(nb N) A res ----
+    launch_apply_multi(t->d_coefs, nx, ny, nb, y, Ay, s);
+  
+    launch_loss(N * nb, R, Ay, res, lpart, kRedBlocks, s);
+    launch_sum_parts(lpart, kRedBlocks, 1.0 / ((double)N * nb), lpart + kRedBlocks, s);
+    launch_apply_multi(t->d_coefs, nx, ny, nb, res, gAy, s);
+    const float dscale = (float)(-2.0 / ((double)N * nb));
+
+    // ---- backward ----
+    HIPCHK(hipMemsetAsync(dG, 0, n->np * sizeof(float), s));
+    float* part = t->part;
+    const int64_t cap = t->part_len;
+    auto tiles_of = [&](int l) {
+      return (int64_t)((t->W[l] + 15) / 16) * ((t->H[l] + 7) / 8) * nb;
+    };
+    auto wgrad = [&](int taps, int l, const bf16_t* dp, int dp_pitch, int cout, const bf16_t* x, int cin8, int cin,
+                     const bf16_t* eta, int64_t oW) {
+      WgradGeo g;
+      g.H = t->H[l];
+      g.W = t->W[l];
+      g.nb = nb;
+      g.cin8 = cin8;
+      g.cin = cin;
+      g.cout = cout;
+      g.dp_pitch = dp_pitch;
+      g.x_bstride = hw(l) * cin8;
+      g.dp_bstride = hw(l) * dp_pitch;
+      g.e_bstride = hw(l) * cin8;
+      const int ns = wgrad_splits(cout, cin8, taps, tiles_of(l), cap);
+      launch_wgrad(taps, g, dp, x, eta, part, ns, s);
+      launch_reduce_rows(part, ns, (int64_t)cout * cin * taps, 1.f, dG + oW, s);
+    };
+    auto bias = [&](int l, const bf16_t* d, int pitch, int C, int64_t ob) {
+      launch_bias_grad(d, hw(l) * nb, pitch, 0, C, part, 256, s);
+      launch_reduce_rows(part, 256, C, 1.f, dG + ob, s);
+    };
+    auto dgrad = [&](int taps, int l, const bf16_t* dp, int cout_fwd, int64_t pT, int kT, int rows, bf16_t* out) {
+      ConvGeo g = geo(l, cout_fwd, rows, rows, 0, 0);
+      launch_conv(taps, false, g, nb, dp, nullptr, PK + pT, kT, nullptr, out, s);
+    };
+    auto eta_bwd = [&](const MConvL& m, const bf16_t* x, int64_t eoff, bf16_t* dxb) {
+      if (!cfg.use_eta) return;
+      const int l = m.level;
+      const int len = eta_bwd_len(m.cin, HID);
+      const int np = 2048;
+      launch_eta_bwd(t->H[l], t->W[l], m.cin, m.cin8, HID, nb, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
+                     W + m.ob1, W + m.oW2, W + m.ob2, x, E + eoff, hw(l) * m.cin8, dxb, part, np, s);
+      launch_reduce_rows(part, np, len, 1.f, dG + m.oW1, s);
+    };
+    // DeepONet contraction, head and trunk
+    launch_don_bwd(N * nb, P, Ab + t->o_B, Ab + t->o_T, W + n->o_gamma, gAy, dscale, G + t->g_B, G + t->g_T, part,
+                   kRedBlocks, s);
+    launch_reduce_rows(part, kRedBlocks, 1, 1.f, dG + n->o_gamma, s);
+    wgrad(1, 0, G + t->g_B, P, P, Ab + t->o_d[0], C0, C0, nullptr, n->o_headW);
+    bias(0, G + t->g_B, P, P, n->o_headb);
+    dgrad(1, 0, G + t->g_B, P, t->pT_head, t->kT_head, C0, G + t->g_d[0]);
+    for (int k = TH; k >= 0; --k) {
+      const int cin8 = k == 0 ? 8 : TWd, cin = k == 0 ? 2 : TWd, cout = k == TH ? P : TWd;
+      bf16_t* dk = k == TH ? G + t->g_T : G + t->g_h[k];
+      if (k < TH) launch_act_bwd(dk, cout, Ab + t->o_h[k], cout, 0, cout, N * nb, 2, s);
+      const bf16_t* xin = k == 0 ? Ab + t->o_t0 : Ab + t->o_h[k - 1];
+      wgrad(1, 0, dk, cout, cout, xin, cin8, cin, nullptr, n->o_tW[k]);
+      bias(0, dk, cout, cout, n->o_tb[k]);
+      if (k > 0) dgrad(1, 0, dk, cout, t->pT_tr[k], t->kT_tr[k], cin8, G + t->g_h[k - 1]);
+    }
+    // decoder, finest level first
+    for (int l = 0; l <= L - 2; ++l) {
+      const MConvL& md = n->dec_d[l];
+      const MConvL& mc = n->dec_c[l];
+      const UpL& u = n->up[l];
+      bf16_t* dD = G + t->g_d[l];
+      launch_act_bwd(dD, ch(l), Ab + t->o_d[l], ch(l), 0, ch(l), hw(l) * nb, 1, s);
+      wgrad(9, l, dD, ch(l), ch(l), Ab + t->o_c[l], md.cin8, md.cin, etap(t->e_d[l]), md.oW);
+      bias(l, dD, ch(l), ch(l), md.ob);
+      dgrad(9, l, dD, ch(l), t->pT_d[l], t->kT_d[l], md.cin8, G + t->g_c[l]);
+      eta_bwd(md, Ab + t->o_c[l], t->e_d[l], G + t->g_c[l]);
+      launch_act_bwd(G + t->g_c[l], ch(l), Ab + t->o_c[l], ch(l), 0, ch(l), hw(l) * nb, 1, s);
+      wgrad(9, l, G + t->g_c[l], ch(l), ch(l), Ab + t->o_cat[l], mc.cin8, mc.cin, etap(t->e_c[l]), mc.oW);
+      bias(l, G + t->g_c[l], ch(l), ch(l), mc.ob);
+      dgrad(9, l, G + t->g_c[l], ch(l), t->pT_c[l], t->kT_c[l], mc.cin8, G + t->g_cat[l]);
+      eta_bwd(mc, Ab + t->o_cat[l], t->e_c[l], G + t->g_cat[l]);
+      launch_copy_ch(G + t->g_cat[l], t->p_cat[l], ch(l), G + t->g_E[l], ch(l), ch(l), hw(l) * nb, 0, s);
+      launch_up_bwd(t->H[l + 1], t->W[l + 1], ch(l), G + t->g_cat[l], t->p_cat[l], hw(l) * t->p_cat[l],
+                    G + t->g_Uc[l], hw(l + 1) * ch(l), nb, s);
+      const bf16_t* src = (l == L - 2) ? Ab + t->o_bot : Ab + t->o_d[l + 1];
+      wgrad(1, l + 1, G + t->g_Uc[l], ch(l), ch(l), src, u.cin, u.cin, nullptr, u.oW);
+      bias(l + 1, G + t->g_Uc[l], ch(l), ch(l), u.ob);
+      bf16_t* dnext = (l == L - 2) ? G + t->g_bot : G + t->g_d[l + 1];
+      dgrad(1, l + 1, G + t->g_Uc[l], ch(l), t->pT_up[l], t->kT_up[l], u.cin, dnext);
+    }
+    // encoder, coarsest level first
+    for (int l = L - 1; l >= 0; --l) {
+      const MConvL& mb = n->enc_b[l];
+      const MConvL& ma = n->enc_a[l];
+      bf16_t* dE = (l == L - 1) ? G + t->g_bot : G + t->g_E[l];
+      if (l == L - 1)
+        launch_act_bwd(dE, ch(l), Ab + t->o_bot, ch(l), 0, ch(l), hw(l) * nb, 1, s);
+      else
+        launch_act_bwd(dE, ch(l), Ab + t->o_cat[l], t->p_cat[l], ch(l), ch(l), hw(l) * nb, 1, s);
+      wgrad(9, l, dE, ch(l), ch(l), Ab + t->o_a[l], mb.cin8, mb.cin, etap(t->e_b[l]), mb.oW);
+      bias(l, dE, ch(l), ch(l), mb.ob);
+      dgrad(9, l, dE, ch(l), t->pT_b[l], t->kT_b[l], mb.cin8, G + t->g_a[l]);
+      eta_bwd(mb, Ab + t->o_a[l], t->e_b[l], G + t->g_a[l]);
+      launch_act_bwd(G + t->g_a[l], ch(l), Ab + t->o_a[l], ch(l), 0, ch(l), hw(l) * nb, 1, s);
+      wgrad(9, l, G + t->g_a[l], ch(l), ch(l), Ab + t->o_in[l], ma.cin8, ma.cin, etap(t->e_a[l]), ma.oW);
+      bias(l, G + t->g_a[l], ch(l), ch(l), ma.ob);
+      if (cfg.use_eta || l > 0) {
+        dgrad(9, l, G + t->g_a[l], ch(l), t->pT_a[l], t->kT_a[l], ma.cin8, G + t->g_in[l]);
+        eta_bwd(ma, Ab + t->o_in[l], t->e_a[l], G + t->g_in[l]);
+      }
+      if (l > 0)
+        launch_pool_bwd(t->H[l], t->W[l], ch(l - 1), G + t->g_in[l], t->p_in[l], hw(l) * t->p_in[l],
+                        G + t->g_E[l - 1], hw(l - 1) * ch(l - 1), nb, s);
+    }
+    HIPCHK(hipGetLastError());
+    return PPE_OK;
+  };
+
+  st = fwd_bwd();
+  if (st != PPE_OK) return st;
   double loss = 0.0;
   HIPCHK(hipMemcpyAsync(&loss, lpart + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (opts->sam_rho > 0.f) {
+    // Sharpness-aware step: the gradient is taken again at w + rho g / |g|
+    // (|g| in FP64, fixed order), and Adam updates w with that gradient.
+    if (!t->gpart) t->gpart = (double*)dev_alloc(sizeof(double) * kRedBlocks);
+    if (!t->w_save) t->w_save = (float*)dev_alloc(sizeof(float) * n->np);
+    if (!t->gpart || !t->w_save) return set_error(PPE_ERR_HIP, "allocation of the SAM buffers failed");
+    launch_sumsq(dG, n->np, 1, t->gpart, s);
+    HIPCHK(hipMemcpyAsync(t->w_save, n->d_w, n->np * sizeof(float), hipMemcpyDeviceToDevice, s));
+    launch_sam_perturb(n->np, n->d_w, dG, t->gpart, opts->sam_rho, s);
+    st = net_refresh(n, s);
+    if (st != PPE_OK) return st;
+    st = fwd_bwd();
+    if (st != PPE_OK) return st;
+    HIPCHK(hipMemcpyAsync(n->d_w, t->w_save, n->np * sizeof(float), hipMemcpyDeviceToDevice, s));
+    st = net_refresh(n, s);
+    if (st != PPE_OK) return st;
+  }
   if (grad_out) HIPCHK(hipMemcpyAsync(grad_out, dG, n->np * sizeof(float), hipMemcpyDeviceToHost, s));
   // ---- Adam ----
   if (opts->lr > 0.f) {

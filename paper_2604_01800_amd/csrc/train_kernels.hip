@@ -556,6 +556,18 @@ __global__ __launch_bounds__(256) void k_adam(int64_t n, float* __restrict__ w, 
   w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
 }
 
+// Sharpness-aware perturbation (Foret et al., 2021): w += rho g / |g|, with
+// |g|^2 from the kRedBlocks partials of k_sumsq reduced in the same order by
+// every workgroup; no change when g = 0.
+__global__ __launch_bounds__(256) void k_sam_perturb(int64_t n, float* w, const float* g, const double* gpart,
+                                                     float rho) {
+  __shared__ double lds[kWaves];
+  const double gn = sqrt(reduce_partials(gpart, kRedBlocks, lds));
+  const float scale = gn > 0.0 ? (float)((double)rho / gn) : 0.f;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) w[k] += scale * g[k];
+}
+
 // ---------------------------------------------------------------------------
 static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
@@ -644,6 +656,10 @@ void launch_sum_parts(const double* part, int n, double scale, double* out, hipS
 void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
                  float c1, float c2, const double* gpart, float clip, hipStream_t s) {
   k_adam<<<nblk(n), 256, 0, s>>>(n, w, g, m, v, lr, b1, b2, eps, c1, c2, gpart, clip);
+}
+
+void launch_sam_perturb(int64_t n, float* w, const float* g, const double* gpart, float rho, hipStream_t s) {
+  k_sam_perturb<<<nblk(n), 256, 0, s>>>(n, w, g, gpart, rho);
 }
 
 }  // namespace ppe

@@ -44,6 +44,7 @@ void launch_loss(int64_t n, const float* R, const float* Ay, float* res, double*
 void launch_sum_parts(const double* part, int n, double scale, double* out, hipStream_t s);
 // Adam step; clip > 0 scales the gradient to norm <= clip first, with ||g||^2
 // from the kRedBlocks partials in gpart (launch_sumsq on g).
+void launch_sam_perturb(int64_t n, float* w, const float* g, const double* gpart, float rho, hipStream_t s);
 void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
                  float c1, float c2, const double* gpart, float clip, hipStream_t s);
 

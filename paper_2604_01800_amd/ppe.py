@@ -71,7 +71,7 @@ class ppe_train_opts(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("seed", ctypes.c_uint64), ("step", ctypes.c_int64),
                 ("grf_len_lo", ctypes.c_float), ("grf_len_hi", ctypes.c_float), ("grf_features", ctypes.c_int32),
-                ("clip_norm", ctypes.c_float)]
+                ("clip_norm", ctypes.c_float), ("sam_rho", ctypes.c_float)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/ppe.h
@@ -352,7 +352,7 @@ def ppe_solve_hybrid(prob: Problem, net, f, x, opts=None, stream=None):
 
 
 def ppe_train_opts_default(**kw) -> ppe_train_opts:
-    o = ppe_train_opts(1e-3, 0.9, 0.999, 1e-8, 0, 0, 0.05, 0.5, 512, 0.0)
+    o = ppe_train_opts(1e-3, 0.9, 0.999, 1e-8, 0, 0, 0.05, 0.5, 512, 0.0, 0.0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o

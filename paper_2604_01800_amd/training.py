@@ -42,10 +42,11 @@ def cosine_lr(lr: float, step: int, steps: int) -> float:
 
 
 def train(net, grids, R_dev, steps: int, batch: int, lr: float = 1e-3, log_every: int = 0, problems=None,
-          schedule: str = "constant", clip_norm: float = 0.0):
+          schedule: str = "constant", clip_norm: float = 0.0, sam_rho: float = 0.0):
     """Adam steps over consecutive batches of the pool (learning rate constant
     or cosine-decayed; gradients clipped to clip_norm in L2 norm when it is
-    positive); returns the loss history."""
+    positive; sharpness-aware with radius sam_rho when it is positive);
+    returns the loss history."""
     count = len(grids)
     if count % batch:
         raise ValueError("pool size must be a multiple of the batch")
@@ -57,7 +58,7 @@ def train(net, grids, R_dev, steps: int, batch: int, lr: float = 1e-3, log_every
     for k in range(steps):
         b0 = (k * batch) % count
         lr_k = cosine_lr(lr, k, steps) if schedule == "cosine" else lr
-        opts = ppe.ppe_train_opts_default(lr=lr_k, clip_norm=clip_norm)
+        opts = ppe.ppe_train_opts_default(lr=lr_k, clip_norm=clip_norm, sam_rho=sam_rho)
         loss, _ = ppe.ppe_net_train_step(net, probs[b0:b0 + batch], R_dev[b0:b0 + batch], opts)
         losses.append(loss)
         if log_every and (k + 1) % log_every == 0:
@@ -100,6 +101,7 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--clip", type=float, default=0.0, help="global gradient-norm clip (0: none)")
+    ap.add_argument("--sam", type=float, default=0.0, help="sharpness-aware radius (0: plain Adam)")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", default=None, help="save the trained network here")
     ap.add_argument("--eval-sizes", default="64,128,256")
@@ -109,7 +111,8 @@ def main(argv=None):
     net = ppe.Net(ppe.ppe_net_config_default(), seed=args.seed)
     probs = [ppe.ppe_problem_create(g) for g in grids]
     train(net, grids, torch.from_numpy(R).cuda(), steps=args.steps, batch=args.batch, lr=args.lr,
-          log_every=max(1, args.steps // 20), problems=probs, schedule="cosine", clip_norm=args.clip)
+          log_every=max(1, args.steps // 20), problems=probs, schedule="cosine", clip_norm=args.clip,
+          sam_rho=args.sam)
     if args.out:
         ppe.ppe_net_save(net, args.out)
     for n in (int(v) for v in args.eval_sizes.split(",") if v):

@@ -189,3 +189,41 @@ def test_gradient_clipping(ppe):
     assert np.abs(step - unclipped).max() >= 0.2 * lr  # clipping changed the update
     with pytest.raises(ppe.PPEError):
         ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(clip_norm=-1.0))
+
+
+def test_sam_step(ppe):
+    """sam_rho > 0: the gradient Adam uses is the one at w + rho g / |g|, the
+    weights are restored before the update, and the first Adam step follows
+    that gradient. Reference: the same net set to the perturbed weights
+    (computed on the host from the library's own g) and differentiated with
+    lr = 0; the BF16 packing of nearly equal weights can round differently,
+    hence the cosine and relative bars instead of equality."""
+    cfg = small_cfg()
+    grids, R = batch(32, [(1.6, 1.3), (1.2, 2.2)], seed=9)
+    probs = [ppe.ppe_problem_create(g) for g in grids]
+    Rd = torch.from_numpy(R.astype(np.float32)).cuda()
+    rho = 0.05
+    net = ppe.Net(gpu_cfg(ppe, cfg), seed=5)
+    w0 = ppe.ppe_net_get_params(net)
+    _, g = ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(lr=0.0), want_grad=True)
+    _, gs = ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(lr=0.0, sam_rho=rho), want_grad=True)
+    np.testing.assert_array_equal(ppe.ppe_net_get_params(net), w0)
+    g64 = g.astype(np.float64)
+    wp = (w0.astype(np.float64) + rho * g64 / np.linalg.norm(g64)).astype(np.float32)
+    ref = ppe.Net(gpu_cfg(ppe, cfg), seed=5)
+    ppe.ppe_net_set_params(ref, wp)
+    _, gr = ppe.ppe_net_train_step(ref, probs, Rd, ppe.ppe_train_opts_default(lr=0.0), want_grad=True)
+    a, b = gs.astype(np.float64), gr.astype(np.float64)
+    cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+    assert cos >= 0.999 and np.linalg.norm(a - b) <= 0.03 * np.linalg.norm(b), (cos, np.linalg.norm(a - b) / np.linalg.norm(b))
+    assert not np.array_equal(gs, g)
+    # one Adam step with SAM moves each weight by lr * gs / (|gs| + eps)
+    lr, eps = 1e-3, 1e-8
+    net2 = ppe.Net(gpu_cfg(ppe, cfg), seed=5)
+    _, gs2 = ppe.ppe_net_train_step(net2, probs, Rd, ppe.ppe_train_opts_default(lr=lr, eps=eps, sam_rho=rho),
+                                    want_grad=True)
+    step = ppe.ppe_net_get_params(net2).astype(np.float64) - w0
+    want = -lr * gs2.astype(np.float64) / (np.abs(gs2.astype(np.float64)) + eps)
+    assert np.abs(step - want).max() <= 2e-3 * lr
+    with pytest.raises(ppe.PPEError):
+        ppe.ppe_net_train_step(net2, probs, Rd, ppe.ppe_train_opts_default(sam_rho=-1.0))
