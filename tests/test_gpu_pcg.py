@@ -310,3 +310,23 @@ def test_two_step_iterations_track_single(T, orc, n, beta):
         its[v] = stats[0]["iters_total"]
     one, two = its[ppe.PPE_PCG_SINGLE_REDUCTION], its[ppe.PPE_PCG_TWO_STEP]
     assert abs(two - one) <= 0.02 * one + 2, its
+
+
+@pytest.mark.parametrize("nx,ny,beta", [(2, 2, 0.0), (3, 130, 2.5), (130, 3, 1.0), (57, 5, 1.5), (5, 300, 2.0),
+                                        (113, 57, 1.2)])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["single", "two_phase", "two_step"])
+def test_degenerate_shapes_converge(T, orc, variant, nx, ny, beta):
+    """Thin strips, a 2 x 2 grid and widths around the two-step form's 56-column
+    tile (57, 113) converge to the tolerance on the oracle's FP64 true residual,
+    and the solution matches the direct solve."""
+    from oracle import direct
+    ppe = _ppe()
+    g = inputs.make_grid(nx, ny, beta, beta * 0.6)
+    prob = ppe.ppe_problem_create(g)
+    f = inputs.gaussian_bumps(g, nx + ny).astype(np.float32)
+    b, _ = orc.rhs(g, f)
+    st, stats, x = _solve(T, prob, f, tol=1e-9, variant=variant)
+    assert st == ppe.PPE_OK, stats
+    assert np.linalg.norm(b - orc.apply(g, x[0])) / np.linalg.norm(b) <= 1e-9 * 1.001
+    xs = direct.separable_solve(g, b)
+    assert np.linalg.norm(x[0] - xs) / np.linalg.norm(xs) <= 1e-6
