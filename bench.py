@@ -7,8 +7,10 @@ an elliptical obstacle mask (centre U[0.2, 0.8]^2, semi-axes U[0.05, 0.15],
 angle U[0, pi)), and a Gaussian-random-field source (squared-exponential
 covariance, length 0.05, 512 random Fourier features). Each step solves the
 system from x0 = 0 to relative residual 1e-6 (FP64 true residual) with
-Jacobi-PCG, and, when a network is available (--hybrid), with the hybrid
-PCG + line-search method as well.
+Jacobi-PCG. With --hybrid PATH (a network saved by ppe_net_save), the same
+system is also solved by the hybrid PCG + line-search method, and its
+time-to-tolerance is reported beside the plain solve's in config["hybrid"]
+(the headline value stays the plain solve's).
 
 Prints one JSON line. `roofline` reports the dominant kernel (the launch of
 the PCG form that runs: two-step, two iterations per launch; single-reduction,
@@ -80,6 +82,28 @@ def cpu_baseline(g, f, iters_full, sample_iters):
     }
 
 
+def hybrid_run(ppe, torch, prob, f, x, args):
+    """Hybrid solves (Num_CG = 3, Num_DLSM = 2) of the same system with a saved
+    network, timed like the plain solve (one warm-up, then args.steps, capped at
+    3 since a hybrid solve can take seconds)."""
+    net = ppe.Net(ppe.ppe_net_config_default(), seed=0)
+    ppe.ppe_net_load(net, args.hybrid)
+    o = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, max_iter=args.hybrid_max_iter)
+    ppe.ppe_solve_hybrid(prob, net, f, x, o)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 3))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, stats = ppe.ppe_solve_hybrid(prob, net, f, x, o)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    s0 = stats[0]
+    return {"network": os.path.basename(args.hybrid), "converged": st == ppe.PPE_OK, "ms_per_solve": ms,
+            "solves_per_s": 1e3 / ms, "iters": s0["iters_total"], "iters_dlsm": s0["iters_dlsm"],
+            "dlsm_rejected": s0["dlsm_rejected"], "rel_res_true": s0["rel_res_true"],
+            "max_iter": args.hybrid_max_iter}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +122,9 @@ def main():
     ap.add_argument("--network-forward", type=int, default=0, metavar="K",
                     help="time K forwards of the default DeepONet (random weights) on the workload's grid "
                          "instead (for kernel traces of the network)")
+    ap.add_argument("--hybrid", default=None, metavar="PATH",
+                    help="also time the hybrid solve with the network saved at PATH (default configuration)")
+    ap.add_argument("--hybrid-max-iter", type=int, default=30000)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the phase-kernel timing launches and a 64 MiB calibration copy "
                          "(for hardware-counter runs)")
@@ -229,6 +256,8 @@ def main():
             "algorithmic_bytes": kbytes * N,
         },
     }
+    if args.hybrid:
+        out["config"]["hybrid"] = hybrid_run(ppe, torch, prob, f, x, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, f_np, iters, args.cpu_iters)
     print(json.dumps(out), flush=True)

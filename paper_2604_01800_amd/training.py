@@ -67,8 +67,9 @@ def train(net, grids, R_dev, steps: int, batch: int, lr: float = 1e-3, log_every
     return losses
 
 
-def evaluate(net, n, count=6, seed=12345, tol=1e-6, max_iter=20000):
-    """Hybrid (with net) against plain Jacobi-PCG on held-out n x n systems
+def evaluate(net, n, count=6, seed=12345, tol=1e-6, max_iter=20000, num_cg=3, num_dlsm=2):
+    """Hybrid (with net; num_cg PCG iterations and num_dlsm line-search steps
+    per round, Sec. 2.2) against plain Jacobi-PCG on held-out n x n systems
     (random stretching and ellipse, GRF source); returns one dict per system."""
     import torch
     rng = np.random.default_rng(seed)
@@ -78,10 +79,11 @@ def evaluate(net, n, count=6, seed=12345, tol=1e-6, max_iter=20000):
         prob = ppe.ppe_problem_create(g)
         f = torch.from_numpy(inputs.grf(g, 900 + k).astype(np.float32)[None]).cuda()
         x = torch.zeros((1, n, n), dtype=torch.float64, device="cuda")
-        o = ppe.ppe_solve_opts_default(tol=tol, zero_x0=1, max_iter=max_iter)
+        o = ppe.ppe_solve_opts_default(tol=tol, zero_x0=1, max_iter=max_iter, num_cg=num_cg, num_dlsm=num_dlsm)
         st_p, sp = ppe.ppe_solve_plain(prob, f, x, o)
         st_h, sh = ppe.ppe_solve_hybrid(prob, net, f, x, o)
-        rows.append({"n": n, "system": k, "plain_iters": sp[0]["iters_total"], "plain_ms": sp[0]["ms_device"],
+        rows.append({"n": n, "system": k, "num_cg": num_cg, "num_dlsm": num_dlsm,
+                     "plain_iters": sp[0]["iters_total"], "plain_ms": sp[0]["ms_device"],
                      "hybrid_iters": sh[0]["iters_total"], "hybrid_dlsm": sh[0]["iters_dlsm"],
                      "hybrid_ms": sh[0]["ms_device"], "hybrid_converged": st_h == ppe.PPE_OK})
     return rows
@@ -104,20 +106,37 @@ def main(argv=None):
     ap.add_argument("--sam", type=float, default=0.0, help="sharpness-aware radius (0: plain Adam)")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", default=None, help="save the trained network here")
+    ap.add_argument("--load", default=None, help="load this network instead of training one")
     ap.add_argument("--eval-sizes", default="64,128,256")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also sweep Num_CG and Num_DLSM over 1..5 on held-out n x n systems (Appendix A)")
     args = ap.parse_args(argv)
     ppe.lib()
-    grids, R = make_pool(args.n, args.pool, seed=1)
     net = ppe.Net(ppe.ppe_net_config_default(), seed=args.seed)
-    probs = [ppe.ppe_problem_create(g) for g in grids]
-    train(net, grids, torch.from_numpy(R).cuda(), steps=args.steps, batch=args.batch, lr=args.lr,
-          log_every=max(1, args.steps // 20), problems=probs, schedule="cosine", clip_norm=args.clip,
-          sam_rho=args.sam)
+    if args.load:
+        ppe.ppe_net_load(net, args.load)
+    else:
+        grids, R = make_pool(args.n, args.pool, seed=1)
+        probs = [ppe.ppe_problem_create(g) for g in grids]
+        train(net, grids, torch.from_numpy(R).cuda(), steps=args.steps, batch=args.batch, lr=args.lr,
+              log_every=max(1, args.steps // 20), problems=probs, schedule="cosine", clip_norm=args.clip,
+              sam_rho=args.sam)
     if args.out:
         ppe.ppe_net_save(net, args.out)
     for n in (int(v) for v in args.eval_sizes.split(",") if v):
         for row in evaluate(net, n, count=6 if n == args.n else 3):
             print(json.dumps(row), flush=True)
+    if args.sweep:
+        for num_cg in range(1, 6):
+            for num_dlsm in range(1, 6):
+                rows = evaluate(net, args.n, count=6, num_cg=num_cg, num_dlsm=num_dlsm)
+                print(json.dumps({"sweep": True, "n": args.n, "num_cg": num_cg, "num_dlsm": num_dlsm,
+                                  "plain_iters": [r["plain_iters"] for r in rows],
+                                  "hybrid_iters": [r["hybrid_iters"] for r in rows],
+                                  "hybrid_dlsm": [r["hybrid_dlsm"] for r in rows],
+                                  "plain_ms": [round(r["plain_ms"], 3) for r in rows],
+                                  "hybrid_ms": [round(r["hybrid_ms"], 3) for r in rows],
+                                  "converged": [r["hybrid_converged"] for r in rows]}), flush=True)
 
 
 if __name__ == "__main__":
