@@ -242,6 +242,39 @@ ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* proble
                               const ppe_train_opts* opts, float* loss_out, float* grad_out,
                               hipStream_t s);
 
+/* ---- Lanczos-Ritz training vectors (Sec. 2.3, Eqs. 14-16) ---- */
+typedef struct ppe_ritz ppe_ritz; /* opaque: Lanczos basis (device), tridiagonal and its eigen-decomposition */
+
+/* m Lanczos steps (Eq. 14) on the grid's operator, in FP64 on the device, from
+ * the start vector v0 (device FP64 [ny][nx]; its mean is removed and it is
+ * normalised; the caller keeps ownership). Every step re-orthogonalises
+ * against the constant null vector and all earlier Lanczos vectors (twice),
+ * so the basis stays orthonormal. The tridiagonal T_m is then diagonalised
+ * on the host (implicit symmetric QR, O(m^3)): ascending Ritz values theta
+ * and T_m = U diag(theta) U^T. If the Krylov space is exhausted early, fewer
+ * than m vectors are kept (ppe_ritz_info reports how many). Device memory:
+ * (m + 1) N + m^2 doubles. 1 <= m <= min(8192, N - 1). Synchronises s.
+ * Errors: PPE_ERR_INVALID_ARG (bad m, or a zero or constant v0),
+ * PPE_ERR_NONFINITE, PPE_NOT_CONVERGED (eigen-decomposition), PPE_ERR_HIP. */
+ppe_status ppe_ritz_create(ppe_problem* p, int32_t m, const double* v0, ppe_ritz** out, hipStream_t s);
+/* Kept size m and host copies of alpha [m], beta [m - 1] and theta [m]
+ * (ascending); any pointer may be NULL. */
+ppe_status ppe_ritz_info(const ppe_ritz* r, int32_t* m, double* alpha, double* beta, double* theta);
+/* nb training vectors R^i = Q c^i / |Q c^i|_2 (Eq. 15), Q = V_m U the Ritz
+ * vectors in ascending order, c^i_j = 9 N(0,1) for j <= b m and N(0,1)
+ * otherwise (Eq. 16). Normal draws: Philox4x32-10, key = seed, counter =
+ * (j, i + 2^31, step mod 2^32, step div 2^32), Box-Muller; each Ritz vector
+ * is signed so that its component along v_0 is not negative. R: device FP32
+ * [nb][ny][nx]. 1 <= nb <= 4096, 0 <= b <= 1. Synchronises s. */
+ppe_status ppe_ritz_rhs(const ppe_ritz* r, int32_t nb, uint64_t seed, int64_t step, double b, float* R,
+                        hipStream_t s);
+void ppe_ritz_destroy(ppe_ritz* r);
+/* Host-only: eigenvalues (ascending, theta [n]) and eigenvectors (U [n][n],
+ * row-major, column j = eigenvector j, signed so that U[0][j] >= 0; may be
+ * NULL) of the symmetric tridiagonal matrix with diagonal alpha [n] and
+ * off-diagonal beta [n - 1]. */
+ppe_status ppe_tridiag_eigh(int32_t n, const double* alpha, const double* beta, double* theta, double* U);
+
 /* ---- measurement ---- */
 /* Launch-configuration tuning of the plain solve (per problem and batch
  * size nb). ppe_tune_pcg runs every iteration form x tile height (2, 4, 8,

@@ -99,6 +99,11 @@ SIGNATURES = {
     "ppe_profile_copy": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),
     "ppe_solve_batch": (_i32, [_i32, _vp, _vp, _vp, _vp, _P(ppe_solve_opts), _vp, _vp]),
     "ppe_generate_rhs": (_i32, [_i32, _vp, _P(ppe_train_opts), _vp, _vp]),
+    "ppe_ritz_create": (_i32, [_vp, _i32, _vp, _P(_vp), _vp]),
+    "ppe_ritz_info": (_i32, [_vp, _P(_i32), _vp, _vp, _vp]),
+    "ppe_ritz_rhs": (_i32, [_vp, _i32, _u64, _i64, ctypes.c_double, _vp, _vp]),
+    "ppe_ritz_destroy": (None, [_vp]),
+    "ppe_tridiag_eigh": (_i32, [_i32, _vp, _vp, _vp, _vp]),
     "ppe_tune_pcg": (_i32, [_vp, _i32, _vp, _vp, _i32, _P(ppe_tune_result), _vp]),
     "ppe_set_tuning": (_i32, [_vp, _i32, _i32, _i32]),
     "ppe_get_tuning": (_i32, [_vp, _i32, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
@@ -416,3 +421,51 @@ def ppe_net_train_step(net: Net, probs, R, opts=None, want_grad=False, stream=No
                                     ctypes.byref(opts), ctypes.byref(loss),
                                     grad.ctypes.data if want_grad else None, _stream(stream)))
     return float(loss.value), grad
+
+
+class Ritz:
+    """Owns a ppe_ritz handle: m Lanczos steps on a problem's operator from the
+    device FP64 start vector v0 [ny, nx] (Sec. 2.3, Eq. 14)."""
+
+    def __init__(self, prob: Problem, m: int, v0, stream=None):
+        import torch
+        if v0.numel() != prob.nx * prob.ny:
+            raise ValueError("v0 must hold one value per cell")
+        h = ctypes.c_void_p()
+        _check(lib().ppe_ritz_create(prob.handle, m, _dev(v0, torch.float64, "v0"), ctypes.byref(h),
+                                     _stream(stream)))
+        self.handle = h
+        self.nx, self.ny = prob.nx, prob.ny
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.ppe_ritz_destroy(h)
+            self.handle = None
+
+
+def ppe_ritz_info(r: Ritz):
+    """(alpha [m], beta [m - 1], theta [m] ascending) as numpy arrays."""
+    m = ctypes.c_int32()
+    _check(lib().ppe_ritz_info(r.handle, ctypes.byref(m), None, None, None))
+    a, b, t = np.empty(m.value), np.empty(max(m.value - 1, 0)), np.empty(m.value)
+    _check(lib().ppe_ritz_info(r.handle, None, a.ctypes.data, b.ctypes.data if b.size else None, t.ctypes.data))
+    return a, b, t
+
+
+def ppe_ritz_rhs(r: Ritz, R, seed=0, step=0, b=0.6, stream=None):
+    """Fills the device FP32 tensor R [nb, ny, nx] with training vectors (Eqs. 15-16)."""
+    import torch
+    if R.dim() != 3 or tuple(R.shape[1:]) != (r.ny, r.nx):
+        raise ValueError("R must be [nb, ny, nx] on the Ritz basis's grid")
+    _check(lib().ppe_ritz_rhs(r.handle, R.shape[0], seed, step, b, _dev(R, torch.float32, "R"), _stream(stream)))
+
+
+def ppe_tridiag_eigh(alpha, beta):
+    """Host eigen-decomposition of a symmetric tridiagonal matrix: (theta, U)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    n = a.size
+    t, U = np.empty(n), np.empty((n, n))
+    _check(lib().ppe_tridiag_eigh(n, a.ctypes.data, b.ctypes.data if b.size else None, t.ctypes.data, U.ctypes.data))
+    return t, U

@@ -1,0 +1,151 @@
+"""Lanczos-Ritz training vectors (Sec. 2.3, Eqs. 14-16) on the GPU against the
+FP64 reference in oracle/ritz.py:
+
+* the host tridiagonal eigensolver against numpy's dense eigensolver;
+* the Lanczos coefficients alpha, beta and the Ritz values against the
+  reference run from the same start vector (both FP64 with full
+  re-orthogonalisation; they differ by summation order only: 1e-9);
+* a full run (m = N - 1) reproduces the nonzero spectrum of the dense matrix;
+* training vectors against the reference's for the same seed and step
+  (FP32 output: 1e-6), and at 64^2 with m = 566 (the paper's m / N ratio of
+  about 0.14): unit norm, zero mean, the 81:1 weighting of Eq. 16 seen in
+  the mean Rayleigh quotient, and determinism.
+
+Element-wise comparisons need a run whose Ritz values are well separated:
+symmetric stretching makes wall-localised modes at the top of the spectrum
+nearly degenerate (relative gaps down to 1e-8), and within such a pair the
+Ritz vectors, and every later Lanczos vector, are fixed by rounding, so two
+correct runs part ways. The cases below check their separation first."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import direct
+from oracle import ritz as orz
+from paper_2604_01800_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ppe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_01800_amd import ppe as P
+    P.lib()
+    return P
+
+
+def start_vector(g, seed):
+    return np.random.default_rng(seed).standard_normal((g.ny, g.nx))
+
+
+def dev64(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 150])
+def test_tridiag_eigh_matches_dense(ppe, n):
+    rng = np.random.default_rng(n)
+    a, b = rng.standard_normal(n), rng.standard_normal(n - 1)
+    if n > 5:
+        a[2] = a[3]
+        b[4] = 1e-30  # a split
+    th, U = ppe.ppe_tridiag_eigh(a, b)
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    lam = np.linalg.eigvalsh(T)
+    np.testing.assert_allclose(th, lam, atol=1e-13 * max(1.0, np.abs(lam).max()))
+    np.testing.assert_allclose(U.T @ U, np.eye(n), atol=1e-13)
+    np.testing.assert_allclose(T @ U, U * th, atol=1e-12 * max(1.0, np.abs(lam).max()))
+    assert (U[0] >= 0).all()
+
+
+def test_lanczos_matches_oracle(ppe):
+    g = inputs.with_ellipse(inputs.make_grid(32, 24, 1.8, 1.2), np.random.default_rng(1))
+    prob = ppe.ppe_problem_create(g)
+    v0 = start_vector(g, 2)
+    m = 30
+    r = ppe.Ritz(prob, m, dev64(v0))
+    a, b, th = ppe.ppe_ritz_info(r)
+    V, ao, bo = orz.lanczos(lambda x: oracle.apply(g, x.reshape(g.ny, g.nx)).ravel(), v0, m)
+    tho, _ = orz.ritz(V, ao, bo)
+    scale = np.abs(ao).max()
+    assert np.diff(tho).min() >= 1e-4 * scale and bo.min() >= 1e-3 * scale  # a well-separated run
+    np.testing.assert_allclose(a, ao, atol=1e-9 * scale)
+    np.testing.assert_allclose(b, bo, atol=1e-9 * scale)
+    np.testing.assert_allclose(th, tho, atol=1e-9 * scale)
+
+
+def test_full_run_gives_spectrum(ppe):
+    g = inputs.make_grid(8, 6, 1.5, 0.7)
+    N = g.nx * g.ny
+    prob = ppe.ppe_problem_create(g)
+    r = ppe.Ritz(prob, N - 1, dev64(start_vector(g, 3)))
+    _, _, th = ppe.ppe_ritz_info(r)
+    lam = np.linalg.eigvalsh(direct.kron_matrix(g))
+    assert th.size == N - 1
+    np.testing.assert_allclose(th, lam[1:], atol=1e-9 * lam[-1])
+
+
+def test_training_vectors_match_oracle(ppe):
+    g = inputs.make_grid(24, 20, 2.0, 1.1)
+    prob = ppe.ppe_problem_create(g)
+    v0 = start_vector(g, 4)
+    m, nb, b, seed, step = 16, 5, 0.6, 11, 7
+    r = ppe.Ritz(prob, m, dev64(v0))
+    R = torch.zeros((nb, g.ny, g.nx), dtype=torch.float32, device="cuda")
+    ppe.ppe_ritz_rhs(r, R, seed=seed, step=step, b=b)
+    V, ao, bo = orz.lanczos(lambda x: oracle.apply(g, x.reshape(g.ny, g.nx)).ravel(), v0, m)
+    tho, U = orz.ritz(V, ao, bo)
+    assert np.diff(tho).min() >= 1e-4 * np.abs(ao).max()  # a well-separated run
+    want = orz.training_vectors(V, U, orz.coefficients(m, nb, b, seed, step))
+    got = R.cpu().numpy().reshape(nb, -1).astype(np.float64)
+    assert np.abs(got - want).max() <= 1e-6, np.abs(got - want).max()
+
+
+def test_training_vectors_at_64(ppe):
+    g = inputs.with_ellipse(inputs.make_grid(64, 64, 1.75), np.random.default_rng(5))
+    N = g.nx * g.ny
+    prob = ppe.ppe_problem_create(g)
+    m, b = 566, 0.6
+    r = ppe.Ritz(prob, m, dev64(start_vector(g, 6)))
+    a, bb, th = ppe.ppe_ritz_info(r)
+    assert th.size == m and np.all(np.diff(th) >= 0) and th[0] > 0
+    nb = 64
+    R = torch.zeros((nb, g.ny, g.nx), dtype=torch.float32, device="cuda")
+    ppe.ppe_ritz_rhs(r, R, seed=1, step=0, b=b)
+    X = R.cpu().numpy().reshape(nb, N).astype(np.float64)
+    np.testing.assert_allclose(np.linalg.norm(X, axis=1), 1.0, atol=1e-6)
+    assert np.abs(X.sum(axis=1)).max() <= 1e-4
+    # Eq. 16 weights the Ritz vectors j <= b m by 81 in energy, so the mean
+    # Rayleigh quotient (oracle apply, FP64) is the 81:1 weighted mean of the
+    # library's own Ritz values
+    rq = np.mean([x @ oracle.apply(g, x.reshape(g.ny, g.nx)).ravel() for x in X])
+    w2 = np.where(np.arange(m) <= int(np.floor(b * m)), 81.0, 1.0)
+    want = (w2 * th).sum() / w2.sum()
+    assert abs(rq / want - 1.0) <= 0.15, (rq, want)
+    assert want < 0.6 * th.mean()
+    # deterministic for a seed and step; another step draws anew
+    R2 = torch.zeros_like(R)
+    ppe.ppe_ritz_rhs(r, R2, seed=1, step=0, b=b)
+    assert torch.equal(R, R2)
+    ppe.ppe_ritz_rhs(r, R2, seed=1, step=1, b=b)
+    assert not torch.equal(R, R2)
+
+
+def test_ritz_argument_checks(ppe):
+    g = inputs.make_grid(16, 12, 1.0)
+    prob = ppe.ppe_problem_create(g)
+    v0 = dev64(start_vector(g, 7))
+    for m in (0, 16 * 12):
+        with pytest.raises(ppe.PPEError):
+            ppe.Ritz(prob, m, v0)
+    with pytest.raises(ppe.PPEError):  # a constant start vector has nothing in the range
+        ppe.Ritz(prob, 5, dev64(np.ones((12, 16))))
+    r = ppe.Ritz(prob, 5, v0)
+    R = torch.zeros((2, 12, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(ppe.PPEError):
+        ppe.ppe_ritz_rhs(r, R, b=1.5)
+    with pytest.raises(ValueError):
+        ppe.ppe_ritz_rhs(r, torch.zeros((2, 12, 15), dtype=torch.float32, device="cuda"))
