@@ -36,6 +36,34 @@ def make_pool(n: int, count: int, seed: int = 0, ell_lo: float = 0.05, ell_hi: f
     return grids, np.stack(R)
 
 
+def make_ritz_pool(n: int, count: int, seed: int = 0, grids: int = 16, m: int | None = None, b: float = 0.6):
+    """Pool of Lanczos-Ritz training systems (Sec. 2.3, Eqs. 14-16): `grids`
+    random stretched n x n grids (ellipse masks), a Lanczos basis of m vectors
+    on each (default m = 0.14 N, the paper's m / N), and count / grids
+    vectors drawn on each with weight 9 on the lowest b m Ritz vectors.
+    Returns (grid list of length count, device R [count, n, n] float32)."""
+    import torch
+    if count % grids:
+        raise ValueError("count must be a multiple of grids")
+    rng = np.random.default_rng(seed)
+    m = m or max(8, int(0.14 * n * n))
+    per = count // grids
+    gl, Rs = [], []
+    for k in range(grids):
+        g = inputs.with_ellipse(inputs.random_stretched_grid(n, n, rng), rng)
+        prob = ppe.ppe_problem_create(g)
+        v0 = torch.from_numpy(rng.standard_normal((n, n))).cuda()
+        r = ppe.Ritz(prob, m, v0)
+        R = torch.empty((per, n, n), dtype=torch.float32, device="cuda")
+        ppe.ppe_ritz_rhs(r, R, seed=seed, step=k, b=b)
+        # unit L2 norm (Eq. 15) -> unit RMS, the scale of the other training data
+        Rs.append(R * float(np.sqrt(n * n)))
+        gl += [g] * per
+    R = torch.cat(Rs)
+    order = rng.permutation(count)  # batches mix the grids
+    return [gl[i] for i in order], R[torch.from_numpy(order).cuda()].contiguous()
+
+
 def cosine_lr(lr: float, step: int, steps: int) -> float:
     """Cosine decay of the learning rate from lr to 0 over `steps` (Sec. 2.4)."""
     return 0.5 * lr * (1.0 + math.cos(math.pi * step / steps))
@@ -107,6 +135,8 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", default=None, help="save the trained network here")
     ap.add_argument("--load", default=None, help="load this network instead of training one")
+    ap.add_argument("--data", choices=["grf", "ritz"], default="grf",
+                    help="training systems: Gaussian random fields, or Lanczos-Ritz vectors (Eqs. 14-16)")
     ap.add_argument("--eval-sizes", default="64,128,256")
     ap.add_argument("--sweep", action="store_true",
                     help="also sweep Num_CG and Num_DLSM over 1..5 on held-out n x n systems (Appendix A)")
@@ -116,9 +146,13 @@ def main(argv=None):
     if args.load:
         ppe.ppe_net_load(net, args.load)
     else:
-        grids, R = make_pool(args.n, args.pool, seed=1)
+        if args.data == "ritz":
+            grids, Rd = make_ritz_pool(args.n, args.pool, seed=1)
+        else:
+            grids, R = make_pool(args.n, args.pool, seed=1)
+            Rd = torch.from_numpy(R).cuda()
         probs = [ppe.ppe_problem_create(g) for g in grids]
-        train(net, grids, torch.from_numpy(R).cuda(), steps=args.steps, batch=args.batch, lr=args.lr,
+        train(net, grids, Rd, steps=args.steps, batch=args.batch, lr=args.lr,
               log_every=max(1, args.steps // 20), problems=probs, schedule="cosine", clip_norm=args.clip,
               sam_rho=args.sam)
     if args.out:
