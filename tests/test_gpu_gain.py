@@ -1,6 +1,8 @@
 """What the trained network gains (Sec. 2.2-2.4): a DeepONet trained by the
-library (Eq. 19 loss, Adam with cosine decay, fabricated 64 x 64 systems)
-against the same network untrained, on held-out systems.
+library (Eq. 19 loss, Adam with cosine decay) on the paper's Lanczos-Ritz
+training vectors (Eqs. 14-16: 512 vectors from Lanczos bases of m = 0.14 N
+on 16 random stretched 64 x 64 grids, b = 0.6), against the same network
+untrained and against plain PCG, on held-out systems with GRF sources.
 
 Measured per held-out system:
   * the share of the A-norm error that one line search along NN(r) removes,
@@ -8,15 +10,16 @@ Measured per held-out system:
     (A^+ r from a PCG solve to 1e-10);
   * iterations of the hybrid solve to 1e-6 (3 CG + 2 line-search steps per
     round) with the trained and with the untrained network;
-  * iterations of plain PCG, reported beside them.
-Training here is 12 000 Adam steps (about a minute). The bars are the ones a
-working network must clear on every held-out system: the hybrid solve with
-it converges, and its direction removes at least 2 % of the error and 20x
-the untrained share; over the set, the median share is at least 8 % and the
-hybrid needs at most half the untrained network's iterations (an unconverged
-solve counts as the iteration limit). Whether the hybrid beats plain PCG
-depends on how long the network is trained (after 120 000 steps it does on
-most 64 x 64 systems); the table printed by the test records it."""
+  * iterations of plain PCG.
+Training here is 8 000 Adam steps at lr 5e-4 (under a minute); it is
+deterministic, so the bars below (about half of the margins measured on
+MI355X: shares 0.29-0.77, hybrid/plain iteration ratios 0.36-1.6) hold
+from run to run: the hybrid solve with the trained network converges on
+every system, its direction removes at least 10 % of the error and 100x the
+untrained share, the median share is at least 30 %, the hybrid needs at most
+half the untrained network's iterations (an unconverged solve counts as the
+iteration limit), and on the median system it needs at most 0.8 times the
+iterations of plain PCG. The table printed by the test records the numbers."""
 import numpy as np
 import pytest
 import torch
@@ -52,14 +55,13 @@ def line_search_share(ppe, prob, area, net, r):
 
 def test_trained_network_gain(ppe):
     n = 64
-    grids, R = training.make_pool(n, 256, seed=1)
+    grids, R = training.make_ritz_pool(n, 512, seed=1, grids=16)
     probs = [ppe.ppe_problem_create(g) for g in grids]
     cfg = ppe.ppe_net_config_default()
     trained = ppe.Net(cfg, seed=7)
     untrained = ppe.Net(cfg, seed=7)
-    losses = training.train(trained, grids, torch.from_numpy(R).cuda(), steps=12000, batch=16, lr=1e-3,
-                            problems=probs, schedule="cosine")
-    assert np.mean(losses[-200:]) < 0.75 * np.mean(losses[:50]), (np.mean(losses[:50]), np.mean(losses[-200:]))
+    losses = training.train(trained, grids, R, steps=8000, batch=16, lr=5e-4, problems=probs, schedule="cosine")
+    assert np.mean(losses[-200:]) < 0.25 * np.mean(losses[:50]), (np.mean(losses[:50]), np.mean(losses[-200:]))
 
     rng = np.random.default_rng(12345)
     rows = []
@@ -93,8 +95,9 @@ def test_trained_network_gain(ppe):
               "line-search share trained %(share_trained).4f untrained %(share_untrained).2e" % r)
     for r in rows:
         assert r["trained"] is not None, r
-        assert r["share_trained"] >= 0.02 and r["share_trained"] >= 20 * r["share_untrained"], r
-    assert np.median([r["share_trained"] for r in rows]) >= 0.08, rows
+        assert r["share_trained"] >= 0.1 and r["share_trained"] >= 100 * r["share_untrained"], r
+    assert np.median([r["share_trained"] for r in rows]) >= 0.3, rows
     it_trained = sum(r["trained"] for r in rows)
     it_untrained = sum(max_iter if r["untrained"] is None else r["untrained"] for r in rows)
     assert 2 * it_trained <= it_untrained, (it_trained, it_untrained)
+    assert np.median([r["trained"] / r["plain"] for r in rows]) <= 0.8, rows
