@@ -1,6 +1,8 @@
 // Network kernels: Mesh-Conv implicit-GEMM convolutions on BF16 MFMA, the
 // grid-derived constants of the DeepONet (local weights eta, trunk basis),
 // pooling, input scaling and the DeepONet output (Sec. 2.4, Eqs. 17-18).
+#include <algorithm>
+
 #include "common.hpp"
 #include "net_common.hpp"
 #include "net_kernels.hpp"
@@ -9,21 +11,25 @@ namespace ppe {
 
 // ---------------------------------------------------------------------------
 // Convolution as an implicit GEMM: out[px][co] = sum_k Wp[co][k] * Xbar[px, k]
-// with k running over (tap, input channel). One workgroup computes a 16 x 16
-// pixel tile for TN output channels; wave w owns tile rows 4w .. 4w+3, so each
-// K-step issues (TN/16) x 4 MFMA 16x16x32 BF16 (A = weights, M = output
-// channels; B = staged inputs, N = 16 pixels of one tile row; FP32
-// accumulation) and every operand fragment feeds 4 (or TN/16) of them. Input
-// channels are staged through LDS in chunks of 32 (with the 3x3 halo),
-// multiplied by the Mesh-Conv local weight eta on the way (Eq. 18). The
-// weight fragments are read straight from the packed weights (L2-resident,
-// shared by all workgroups) one K-step ahead, through a buffer resource whose
-// size ends at the last output channel, so channels past cout read as 0. Each
-// lane's eight consecutive K values are one (tap, 8-channel group); the packed
-// weight layout enumerates the groups of a chunk in the same order,
-// zero-filled to a multiple of four groups. TAPS = 9 (3x3, zero padding) or 1
-// (1x1). UP = the output is written to the 2x nearest-upsampled pixels of a
-// finer level.
+// with k running over (tap, input channel). A workgroup owns TN output
+// channels of one sample and a run of consecutive 16 x 16 pixel tiles; wave w
+// computes tile rows 4w .. 4w+3, so each K-step issues (TN/16) x 4 MFMA
+// 16x16x32 BF16 (A = weights, M = output channels; B = staged inputs, N = 16
+// pixels of one tile row; FP32 accumulation) and every operand fragment
+// feeds 4 (or TN/16) of them.
+//
+// The work of a workgroup is a list of items (tile, chunk of 32 input
+// channels). For each item the input chunk with its 3x3 halo, multiplied by
+// the Mesh-Conv local weight eta on the way (Eq. 18), and the chunk's slice
+// of the packed weights are written to LDS; the loads of the next item are
+// issued into registers before the current item's MFMA loop, so HBM and L2
+// latency hide behind it, and the loop itself reads only LDS (fragments one
+// K-step ahead). Each lane's eight consecutive K values are one (tap,
+// 8-channel group); the packed weight layout enumerates the groups of a chunk
+// in the same order, zero-filled to a multiple of four groups. Weight rows
+// past cout read as zero through a buffer resource that ends at the last
+// output channel. TAPS = 9 (3x3, zero padding) or 1 (1x1). UP = the output is
+// written to the 2x nearest-upsampled pixels of a finer level.
 constexpr int kCTH = 16, kCTW = 16;  // pixel tile of the convolution kernel
 
 __device__ __forceinline__ uint4 mul_bf16x8(uint4 v, uint4 e) {
@@ -37,25 +43,141 @@ __device__ __forceinline__ uint4 mul_bf16x8(uint4 v, uint4 e) {
   return make_uint4(o[0], o[1], o[2], o[3]);
 }
 
-__device__ __forceinline__ bf16x8_t load_wfrag(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0);
-  return __builtin_bit_cast(bf16x8_t, v);
+template <int TN, int TAPS>
+struct ConvShape {
+  static constexpr int HALO = TAPS == 9 ? 1 : 0;
+  static constexpr int LW = kCTW + 2 * HALO, LH = kCTH + 2 * HALO;
+  static constexpr int NPIX = LW * LH;
+  static constexpr int CKP = kConvCK + 8;                       // LDS pitch of a staged pixel (bf16)
+  static constexpr int SMAX = (TAPS * (kConvCK / 8) + 3) / 4;   // K-steps of a full chunk
+  static constexpr int WQ = SMAX * 4;                           // 8-value groups of a full weight row
+  static constexpr int WKP = SMAX * 32 + 8;                     // LDS pitch of a staged weight row
+  static constexpr int NU = (NPIX + 63) / 64;                   // staged pixels per thread
+  static constexpr int NW = (TN * WQ + 255) / 256;              // weight groups per thread
+};
+
+// Registers of one item's loads, between issue and the write to LDS.
+template <int TN, int TAPS>
+struct ConvStage {
+  uint4 x[ConvShape<TN, TAPS>::NU], e[ConvShape<TN, TAPS>::NU], w[ConvShape<TN, TAPS>::NW];
+};
+
+// Issues the loads of one item: thread t stages the 8-channel group t % 4 of
+// the halo pixels t / 4, t / 4 + 64, ... and a share of the weight slice.
+// Inputs are read through buffer resources over one sample; halo pixels
+// outside the image get an offset past the end, which reads as zero.
+template <int TN, int TAPS>
+__device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS>& st, const ConvGeo& g, __amdgpu_buffer_rsrc_t xr,
+                                           __amdgpu_buffer_rsrc_t er, bool has_eta, __amdgpu_buffer_rsrc_t wr, int Kp,
+                                           int co0, int py0, int px0, int c0, int ck8, int kbase) {
+  using S = ConvShape<TN, TAPS>;
+  // recomputed per item (cheap) rather than kept live across the MFMA loop
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int c8 = tid & 3;
+  const bool cg_ok = c8 < ck8;
+  const uint32_t cofs = (uint32_t)(c0 + c8 * 8) * 2;
+#pragma unroll
+  for (int i = 0; i < S::NU; ++i) {
+    const int pix = (tid >> 2) + 64 * i;
+    const int ly = pix / S::LW, lx = pix - ly * S::LW;
+    const int gy = py0 + ly - S::HALO, gx = px0 + lx - S::HALO;
+    const bool in = cg_ok && pix < S::NPIX && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W;
+    const uint32_t off = in ? (uint32_t)(gy * g.W + gx) * (uint32_t)(g.cin8 * 2) + cofs : 0x80000000u;
+    st.x[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)off, 0, 0));
+    if (has_eta) st.e[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(er, (int)off, 0, 0));
+  }
+  const int wq = conv_chunk_steps(TAPS, ck8 * 8) * 4;  // 8-value groups per weight row of this chunk
+#pragma unroll
+  for (int i = 0; i < S::NW; ++i) {
+    const int u = tid + 256 * i;
+    const int r = u / S::WQ, q = u - r * S::WQ;
+    const bool ok = r < TN && q < wq;
+    const uint32_t off = ok ? (uint32_t)(((co0 + r) * Kp + kbase + q * 8) * 2) : 0x80000000u;
+    st.w[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wr, (int)off, 0, 0));
+  }
+}
+
+// Writes one item's staged registers to LDS (inputs times eta).
+template <int TN, int TAPS>
+__device__ __forceinline__ void conv_commit(const ConvStage<TN, TAPS>& st, bool has_eta, int ck8, bf16_t* s_x,
+                                            bf16_t* s_w) {
+  using S = ConvShape<TN, TAPS>;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int c8 = tid & 3;
+  if (c8 < ck8) {
+#pragma unroll
+    for (int i = 0; i < S::NU; ++i) {
+      const int pix = (tid >> 2) + 64 * i;
+      if (pix < S::NPIX) *(uint4*)(s_x + pix * S::CKP + c8 * 8) = has_eta ? mul_bf16x8(st.x[i], st.e[i]) : st.x[i];
+    }
+  }
+  const int wq = conv_chunk_steps(TAPS, ck8 * 8) * 4;
+#pragma unroll
+  for (int i = 0; i < S::NW; ++i) {
+    const int u = tid + 256 * i;
+    const int r = u / S::WQ, q = u - r * S::WQ;
+    if (r < TN && q < wq) *(uint4*)(s_w + r * S::WKP + q * 8) = st.w[i];
+  }
+}
+
+// MFMA loop over the K-steps of one staged item. B fragments (staged
+// inputs) are read one step ahead, A fragments (staged weights) just before
+// use.
+template <int TN, int TAPS, int CK8>
+__device__ __forceinline__ void conv_mfma(f32x4_t (&acc)[TN / 16][4], const bf16_t* s_x, const bf16_t* s_w,
+                                          int ck8_rt, int lane, int wv) {
+  using S = ConvShape<TN, TAPS>;
+  constexpr int MT = TN / 16, NT = 4;
+  const int ck8 = CK8 ? CK8 : ck8_rt;
+  const int steps = conv_chunk_steps(TAPS, ck8 * 8);
+  auto bfrags = [&](int st, bf16x8_t* bf) {
+    const int G = st * 4 + (lane >> 4);
+    int tap = G / ck8;
+    const int c8 = G - tap * ck8;
+    if (tap >= TAPS) tap = TAPS - 1;  // zero-weight padding group: any in-bounds input
+    const int dy = TAPS == 9 ? tap / 3 : 0, dx = TAPS == 9 ? tap % 3 : 0;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int pix = (NT * wv + nt + dy) * S::LW + (lane & 15) + dx;
+      bf[nt] = *(const bf16x8_t*)(s_x + pix * S::CKP + c8 * 8);
+    }
+  };
+  const bf16_t* wrow = s_w + (lane & 15) * S::WKP + (lane >> 4) * 8;
+  bf16x8_t bfr[NT];
+  bfrags(0, bfr);
+  for (int st = 0; st < steps; ++st) {
+    bf16x8_t afr[MT], bnx[NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) afr[mt] = *(const bf16x8_t*)(wrow + mt * 16 * S::WKP + st * 32);
+    if (st + 1 < steps) bfrags(st + 1, bnx);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[mt], bfr[nt], acc[mt][nt], 0, 0, 0);
+    if (st + 1 < steps) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) bfr[nt] = bnx[nt];
+    }
+  }
 }
 
 template <int TN, int TAPS, bool UP>
-__global__ __launch_bounds__(256) void k_conv(ConvGeo g, const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv(
+    ConvGeo g, const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta,
                                               const bf16_t* __restrict__ wp, int Kp, const float* __restrict__ bias,
-                                              bf16_t* __restrict__ y) {
-  constexpr int HALO = TAPS == 9 ? 1 : 0;
-  constexpr int LW = kCTW + 2 * HALO, LH = kCTH + 2 * HALO;
-  constexpr int NPIX = LW * LH;
-  constexpr int CKP = kConvCK + 8;  // LDS pixel pitch (bank-conflict padding)
+                                              bf16_t* __restrict__ y, int tiles_per_wg) {
+  using S = ConvShape<TN, TAPS>;
   constexpr int MT = TN / 16, NT = 4;
-  __shared__ __attribute__((aligned(16))) bf16_t s_x[NPIX * CKP];
+  __shared__ __attribute__((aligned(16))) bf16_t s_x[S::NPIX * S::CKP];
+  __shared__ __attribute__((aligned(16))) bf16_t s_w[TN * S::WKP];
 
   const int tiles_x = (g.W + kCTW - 1) / kCTW;
-  const int px0 = (blockIdx.x % tiles_x) * kCTW;
-  const int py0 = (blockIdx.x / tiles_x) * kCTH;
+  const int tiles = tiles_x * ((g.H + kCTH - 1) / kCTH);
+  const int t0 = blockIdx.x * tiles_per_wg;
+  const int nt_wg = min(tiles_per_wg, tiles - t0);
   const int co0 = blockIdx.y * TN;
   const int smp = blockIdx.z;
   x += smp * g.x_bstride;
@@ -64,10 +186,13 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const bf16_t* __restric
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const __amdgpu_buffer_rsrc_t wr =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(wp), (short)0, (int)((int64_t)g.cout * Kp * 2), 0x00020000);
-  // byte offset of this lane's A fragment for output-channel tile mt at K = k
-  auto woff = [&](int mt, int k) -> uint32_t {
-    return (uint32_t)(((co0 + mt * 16 + (lane & 15)) * Kp + k + (lane >> 4) * 8) * 2);
-  };
+  const int in_bytes = (int)((int64_t)g.H * g.W * g.cin8 * 2);  // one sample of the input (and of eta)
+  const __amdgpu_buffer_rsrc_t xr =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(x), (short)0, in_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t er =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(eta ? eta : x), (short)0, in_bytes, 0x00020000);
+  const int nch = (g.cin8 + kConvCK - 1) / kConvCK;
+  const int items = nt_wg * nch;
 
   f32x4_t acc[MT][NT];
 #pragma unroll
@@ -75,93 +200,69 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const bf16_t* __restric
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-  int kbase = 0;
-  for (int c0 = 0; c0 < g.cin8; c0 += kConvCK) {
-    const int ck = min(kConvCK, g.cin8 - c0);
-    const int ck8 = ck / 8;
-    const int steps = conv_chunk_steps(TAPS, ck);
-    bf16x8_t afr[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) afr[mt] = load_wfrag(wr, woff(mt, kbase));
+  ConvStage<TN, TAPS> stg;
+  auto issue = [&](int it) {
+    const int t = t0 + it / nch, c = it - (it / nch) * nch;
+    const int py0 = (t / tiles_x) * kCTH, px0 = (t % tiles_x) * kCTW;
+    conv_issue<TN, TAPS>(stg, g, xr, er, eta != nullptr, wr, Kp, co0, py0, px0, c * kConvCK,
+                         min(kConvCK, g.cin8 - c * kConvCK) / 8, c * S::SMAX * 32);
+  };
+  for (int it = 0; it < items; ++it) {
+    const int t = t0 + it / nch, c = it - (it / nch) * nch;
+    const int c0 = c * kConvCK;
+    const int ck8 = min(kConvCK, g.cin8 - c0) / 8;
+    issue(it);        // in flight while the other waves finish the previous item
+    __syncthreads();  // the previous item's MFMA loop is done with LDS
+    conv_commit<TN, TAPS>(stg, eta != nullptr, ck8, s_x, s_w);
     __syncthreads();
-    for (int u = threadIdx.x; u < NPIX * ck8; u += 256) {
-      const int pix = u / ck8, c8 = u - pix * ck8;
-      const int ly = pix / LW, lx = pix - ly * LW;
-      const int gy = py0 + ly - HALO, gx = px0 + lx - HALO;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (gy >= 0 && gy < g.H && gx >= 0 && gx < g.W) {
-        const size_t off = ((size_t)gy * g.W + gx) * g.cin8 + c0 + c8 * 8;
-        v = *(const uint4*)(x + off);
-        if (eta) v = mul_bf16x8(v, *(const uint4*)(eta + off));
-      }
-      *(uint4*)(s_x + pix * CKP + c8 * 8) = v;
-    }
-    __syncthreads();
-    for (int st = 0; st < steps; ++st) {
-      bf16x8_t anx[MT];
-      if (st + 1 < steps) {
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) anx[mt] = load_wfrag(wr, woff(mt, kbase + (st + 1) * 32));
-      }
-      const int G = st * 4 + (lane >> 4);
-      int tap = G / ck8;
-      const int c8 = G - tap * ck8;
-      if (tap >= TAPS) tap = TAPS - 1;  // zero-weight padding group: any in-bounds input
-      const int dy = TAPS == 9 ? tap / 3 : 0, dx = TAPS == 9 ? tap % 3 : 0;
-      bf16x8_t bfr[NT];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int pix = (NT * wv + nt + dy) * LW + (lane & 15) + dx;
-        bfr[nt] = *(const bf16x8_t*)(s_x + pix * CKP + c8 * 8);
-      }
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[mt], bfr[nt], acc[mt][nt], 0, 0, 0);
-      if (st + 1 < steps) {
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) afr[mt] = anx[mt];
-      }
-    }
-    kbase += steps * 32;
-  }
 
-  // Epilogue: lane holds out[co0 + mt*16 + 4*(lane>>4) + j][pixel (row NT*w+nt, col lane&15)].
+    if (ck8 == kConvCK / 8)
+      conv_mfma<TN, TAPS, kConvCK / 8>(acc, s_x, s_w, ck8, lane, wv);
+    else
+      conv_mfma<TN, TAPS, 0>(acc, s_x, s_w, ck8, lane, wv);
+    if (c + 1 < nch) continue;
+
+    // Epilogue of tile t: lane holds out[co0 + mt*16 + 4*(lane>>4) + j][pixel (row NT*w+nt, col lane&15)].
+    const int py0 = (t / tiles_x) * kCTH, px0 = (t % tiles_x) * kCTW;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    const int co = co0 + mt * 16 + 4 * (lane >> 4);
-    if (co >= g.cout) continue;
-    const float b0 = bias ? bias[co] : 0.f, b1 = bias ? bias[co + 1] : 0.f;
-    const float b2 = bias ? bias[co + 2] : 0.f, b3 = bias ? bias[co + 3] : 0.f;
+    for (int mt = 0; mt < MT; ++mt) {
+      const int co = co0 + mt * 16 + 4 * (lane >> 4);
+      if (co < g.cout) {
+        const float b0 = bias ? bias[co] : 0.f, b1 = bias ? bias[co + 1] : 0.f;
+        const float b2 = bias ? bias[co + 2] : 0.f, b3 = bias ? bias[co + 3] : 0.f;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int py = py0 + NT * wv + nt, px = px0 + (lane & 15);
-      if (py >= g.H || px >= g.W) continue;
-      float v0 = acc[mt][nt][0] + b0, v1 = acc[mt][nt][1] + b1, v2 = acc[mt][nt][2] + b2, v3 = acc[mt][nt][3] + b3;
-      if (g.act == 1) {
-        v0 = fmaxf(v0, 0.f);
-        v1 = fmaxf(v1, 0.f);
-        v2 = fmaxf(v2, 0.f);
-        v3 = fmaxf(v3, 0.f);
-      } else if (g.act == 2) {
-        v0 = tanhf(v0);
-        v1 = tanhf(v1);
-        v2 = tanhf(v2);
-        v3 = tanhf(v3);
+        for (int nt = 0; nt < NT; ++nt) {
+          const int py = py0 + NT * wv + nt, px = px0 + (lane & 15);
+          if (py >= g.H || px >= g.W) continue;
+          float v0 = acc[mt][nt][0] + b0, v1 = acc[mt][nt][1] + b1, v2 = acc[mt][nt][2] + b2,
+                v3 = acc[mt][nt][3] + b3;
+          if (g.act == 1) {
+            v0 = fmaxf(v0, 0.f);
+            v1 = fmaxf(v1, 0.f);
+            v2 = fmaxf(v2, 0.f);
+            v3 = fmaxf(v3, 0.f);
+          } else if (g.act == 2) {
+            v0 = tanhf(v0);
+            v1 = tanhf(v1);
+            v2 = tanhf(v2);
+            v3 = tanhf(v3);
+          }
+          const uint2 packed = make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
+                                          (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+          if (!UP) {
+            *(uint2*)(y + ((size_t)py * g.W + px) * g.y_pitch + g.y_off + co) = packed;
+          } else {
+            const int W2 = 2 * g.W;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+              for (int b = 0; b < 2; ++b)
+                *(uint2*)(y + ((size_t)(2 * py + a) * W2 + 2 * px + b) * g.y_pitch + g.y_off + co) = packed;
+          }
+        }
       }
-      const uint2 packed = make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
-                                      (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
-      if (!UP) {
-        *(uint2*)(y + ((size_t)py * g.W + px) * g.y_pitch + g.y_off + co) = packed;
-      } else {
-        const int W2 = 2 * g.W;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            *(uint2*)(y + ((size_t)(2 * py + a) * W2 + 2 * px + b) * g.y_pitch + g.y_off + co) = packed;
-      }
+      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     }
   }
 }
@@ -391,20 +492,52 @@ __global__ void k_deeponet_out(int64_t npix, int c0, const bf16_t* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // Launchers.
+// Compute units of the current device (256 on MI355X), queried once.
+static int conv_device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+template <int TN, int TAPS, bool UP>
+static void conv_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp, int Kp,
+                    const float* bias, bf16_t* y, hipStream_t s) {
+  const int tiles = ((g.W + kCTW - 1) / kCTW) * ((g.H + kCTH - 1) / kCTH);
+  const int cot = (g.cout + TN - 1) / TN;
+  // resident workgroups per CU (registers and LDS), and runs of tiles that
+  // fill them once
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv<TN, TAPS, UP>, 256, 0) != hipSuccess || n < 1) n = 1;
+    per_cu = n;
+  }
+  const int64_t slots = (int64_t)conv_device_cus() * per_cu;
+  const int64_t wgs = (int64_t)tiles * cot * nb;
+  const int run = (int)std::max<int64_t>(1, (wgs + slots - 1) / slots);
+  const dim3 grid((tiles + run - 1) / run, cot, nb);
+  k_conv<TN, TAPS, UP><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run);
+}
+
 void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
                  int Kp, const float* bias, bf16_t* y, hipStream_t s) {
-  const int tiles = ((g.W + kCTW - 1) / kCTW) * ((g.H + kCTH - 1) / kCTH);
-  const int TN = g.cout >= 64 ? 64 : 32;
-  const dim3 grid(tiles, (g.cout + TN - 1) / TN, nb);
+  const bool wide = g.cout >= 64;
   if (taps == 9) {
-    if (TN == 64) k_conv<64, 9, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
-    else k_conv<32, 9, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
+    if (wide) conv_go<64, 9, false>(g, nb, x, eta, wp, Kp, bias, y, s);
+    else conv_go<32, 9, false>(g, nb, x, eta, wp, Kp, bias, y, s);
   } else if (up) {
-    if (TN == 64) k_conv<64, 1, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
-    else k_conv<32, 1, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
+    if (wide) conv_go<64, 1, true>(g, nb, x, eta, wp, Kp, bias, y, s);
+    else conv_go<32, 1, true>(g, nb, x, eta, wp, Kp, bias, y, s);
   } else {
-    if (TN == 64) k_conv<64, 1, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
-    else k_conv<32, 1, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y);
+    if (wide) conv_go<64, 1, false>(g, nb, x, eta, wp, Kp, bias, y, s);
+    else conv_go<32, 1, false>(g, nb, x, eta, wp, Kp, bias, y, s);
   }
 }
 

@@ -30,6 +30,9 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
   constexpr int NDX = TAPS == 9 ? 3 : 1;
   constexpr int DPP = NP + 8;   // LDS pitch of a transposed dPre row
   constexpr int XPP = TW + 8;   // LDS pitch of a staged input row
+  constexpr int NXU = NDX * 4 * LH * TW;   // staged 8-channel input groups per tile
+  constexpr int NUD = NP * 4 / 256, NUX = (NXU + 255) / 256;  // per thread
+  static_assert(NP * 4 == NUD * 256, "dPre staging assumes whole rounds");
   __shared__ __attribute__((aligned(16))) bf16_t s_dp[32 * DPP];
   __shared__ __attribute__((aligned(16))) bf16_t s_x[NDX * 32 * LH * XPP];
   const int co0 = blockIdx.x * 32, ci0 = blockIdx.y * 32;
@@ -49,15 +52,43 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
     const bf16_t* dps = dp + (int64_t)smp * g.dp_bstride;
     const bf16_t* xs = x + (int64_t)smp * g.x_bstride;
     const bf16_t* es = eta ? eta + (int64_t)smp * g.e_bstride : nullptr;
-    __syncthreads();
-    // dPre tile, transposed to [co][pixel]
-    for (int u = threadIdx.x; u < NP * 4; u += 256) {
+    // every load of the tile is issued before the first one is waited for
+    uint4 vd[NUD], vx[NUX], ve[NUX];
+#pragma unroll
+    for (int i = 0; i < NUD; ++i) {
+      const int u = threadIdx.x + 256 * i;  // NP * 4 = NUD * 256
       const int p = u % NP, cg = u / NP;
       const int py = py0 + p / TW, px = px0 + p % TW;
-      uint4 v = make_uint4(0, 0, 0, 0);
+      vd[i] = make_uint4(0, 0, 0, 0);
       if (py < g.H && px < g.W && co0 + cg * 8 < g.cout)
-        v = *(const uint4*)(dps + ((int64_t)py * g.W + px) * g.dp_pitch + co0 + cg * 8);
-      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+        vd[i] = *(const uint4*)(dps + ((int64_t)py * g.W + px) * g.dp_pitch + co0 + cg * 8);
+    }
+#pragma unroll
+    for (int i = 0; i < NUX; ++i) {
+      const int u = threadIdx.x + 256 * i;
+      vx[i] = make_uint4(0, 0, 0, 0);
+      ve[i] = make_uint4(0, 0, 0, 0);
+      if (u < NXU) {
+        const int col = u % TW;
+        int r2 = u / TW;
+        const int row = r2 % LH;
+        r2 /= LH;
+        const int cg = r2 % 4, dx = r2 / 4;
+        const int gy = py0 + row - HALO, gx = px0 + col + dx - HALO;
+        if (gy >= 0 && gy < g.H && gx >= 0 && gx < g.W && ci0 + cg * 8 < g.cin8) {
+          const int64_t off = ((int64_t)gy * g.W + gx) * g.cin8 + ci0 + cg * 8;
+          vx[i] = *(const uint4*)(xs + off);
+          if (es) ve[i] = *(const uint4*)(es + off);
+        }
+      }
+    }
+    __syncthreads();
+    // dPre tile, transposed to [co][pixel]
+#pragma unroll
+    for (int i = 0; i < NUD; ++i) {
+      const int u = threadIdx.x + 256 * i;
+      const int p = u % NP, cg = u / NP;
+      const uint32_t w4[4] = {vd[i].x, vd[i].y, vd[i].z, vd[i].w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         s_dp[(cg * 8 + 2 * e) * DPP + p] = (bf16_t)(w4[e] & 0xffff);
@@ -65,29 +96,26 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
       }
     }
     // weighted input tile, one copy per column shift dx: s_x[dx][ci][row][col] = Xbar[row - H][col + dx - H]
-    for (int u = threadIdx.x; u < NDX * 4 * LH * TW; u += 256) {
+#pragma unroll
+    for (int i = 0; i < NUX; ++i) {
+      const int u = threadIdx.x + 256 * i;
+      if (u >= NXU) continue;
       const int col = u % TW;
       int r2 = u / TW;
       const int row = r2 % LH;
       r2 /= LH;
       const int cg = r2 % 4, dx = r2 / 4;
-      const int gy = py0 + row - HALO, gx = px0 + col + dx - HALO;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (gy >= 0 && gy < g.H && gx >= 0 && gx < g.W && ci0 + cg * 8 < g.cin8) {
-        const int64_t off = ((int64_t)gy * g.W + gx) * g.cin8 + ci0 + cg * 8;
-        v = *(const uint4*)(xs + off);
-        if (es) {
-          const uint4 e = *(const uint4*)(es + off);
-          const uint32_t a4[4] = {v.x, v.y, v.z, v.w}, b4[4] = {e.x, e.y, e.z, e.w};
-          uint32_t o4[4];
+      uint4 v = vx[i];
+      if (es) {
+        const uint32_t a4[4] = {v.x, v.y, v.z, v.w}, b4[4] = {ve[i].x, ve[i].y, ve[i].z, ve[i].w};
+        uint32_t o4[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float lo = bf2f((bf16_t)(a4[q] & 0xffff)) * bf2f((bf16_t)(b4[q] & 0xffff));
-            const float hi = bf2f((bf16_t)(a4[q] >> 16)) * bf2f((bf16_t)(b4[q] >> 16));
-            o4[q] = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
-          }
-          v = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+        for (int q = 0; q < 4; ++q) {
+          const float lo = bf2f((bf16_t)(a4[q] & 0xffff)) * bf2f((bf16_t)(b4[q] & 0xffff));
+          const float hi = bf2f((bf16_t)(a4[q] >> 16)) * bf2f((bf16_t)(b4[q] >> 16));
+          o4[q] = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
         }
+        v = make_uint4(o4[0], o4[1], o4[2], o4[3]);
       }
       const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
       bf16_t* dst = s_x + ((dx * 32 + cg * 8) * LH + row) * XPP + col;
