@@ -237,7 +237,9 @@ ppe_status ppe_generate_rhs(int32_t nb, ppe_problem* const* problems, const ppe_
  * step, length-scale range, features).
  * loss_out: host, the batch loss before the step. grad_out: host or NULL;
  * when given, receives the FP32 gradient that Adam uses (ppe_net_num_params
- * values; with sam_rho > 0 the one at the perturbed weights). */
+ * values; with sam_rho > 0 the one at the perturbed weights).
+ * Errors: PPE_ERR_INVALID_ARG for nb outside [1, 4096] or nb x nx x ny of
+ * 2^31 cells or more; PPE_ERR_SHAPE for grids of different sizes. */
 ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* problems, const float* R,
                               const ppe_train_opts* opts, float* loss_out, float* grad_out,
                               hipStream_t s);

@@ -238,6 +238,8 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
   const int nx = problems[0]->nx, ny = problems[0]->ny, L = cfg.levels, P = cfg.basis, TWd = cfg.trunk_width;
   const int TH = cfg.trunk_hidden, HID = cfg.phi_hidden, C0 = cfg.base_channels;
   const int64_t N = (int64_t)nx * ny;
+  if (N * nb >= (int64_t)1 << 31)
+    return set_error(PPE_ERR_INVALID_ARG, "nb x cells must stay below 2^31 (got %lld)", (long long)(N * nb));
   ppe_status st = train_state(n, nb, nx, ny);
   if (st != PPE_OK) return st;
   TrainState* t = n->train;

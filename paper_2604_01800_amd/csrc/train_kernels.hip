@@ -30,11 +30,12 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
   constexpr int NDX = TAPS == 9 ? 3 : 1;
   constexpr int DPP = NP + 8;   // LDS pitch of a transposed dPre row
   constexpr int XPP = TW + 8;   // LDS pitch of a staged input row
+  constexpr int CIP = LH * XPP + 8;  // LDS pitch of one input channel's rows (16 lanes in distinct banks)
   constexpr int NXU = NDX * 4 * LH * TW;   // staged 8-channel input groups per tile
   constexpr int NUD = NP * 4 / 256, NUX = (NXU + 255) / 256;  // per thread
   static_assert(NP * 4 == NUD * 256, "dPre staging assumes whole rounds");
   __shared__ __attribute__((aligned(16))) bf16_t s_dp[32 * DPP];
-  __shared__ __attribute__((aligned(16))) bf16_t s_x[NDX * 32 * LH * XPP];
+  __shared__ __attribute__((aligned(16))) bf16_t s_x[NDX * 32 * CIP];
   const int co0 = blockIdx.x * 32, ci0 = blockIdx.y * 32;
   const int split = blockIdx.z, nsplit = gridDim.z;
   const int tiles_x = (g.W + TW - 1) / TW, tiles_y = (g.H + TH - 1) / TH;
@@ -118,11 +119,11 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
         v = make_uint4(o4[0], o4[1], o4[2], o4[3]);
       }
       const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-      bf16_t* dst = s_x + ((dx * 32 + cg * 8) * LH + row) * XPP + col;
+      bf16_t* dst = s_x + (dx * 32 + cg * 8) * CIP + row * XPP + col;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        dst[(2 * e) * LH * XPP] = (bf16_t)(w4[e] & 0xffff);
-        dst[(2 * e + 1) * LH * XPP] = (bf16_t)(w4[e] >> 16);
+        dst[(2 * e) * CIP] = (bf16_t)(w4[e] & 0xffff);
+        dst[(2 * e + 1) * CIP] = (bf16_t)(w4[e] >> 16);
       }
     }
     __syncthreads();
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
       for (int tap = 0; tap < TAPS; ++tap) {
         const int dy = TAPS == 9 ? tap / 3 : 0, dx = TAPS == 9 ? tap % 3 : 0;
         const bf16x8_t bfr =
-            *(const bf16x8_t*)(s_x + ((dx * 32 + nt * 16 + (lane & 15)) * LH + prow + dy) * XPP + pcol);
+            *(const bf16x8_t*)(s_x + (dx * 32 + nt * 16 + (lane & 15)) * CIP + (prow + dy) * XPP + pcol);
         acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr, acc[tap], 0, 0, 0);
       }
     }
@@ -318,11 +319,18 @@ __global__ __launch_bounds__(256) void k_eta_multi(int H, int W, int cin, int ci
 // input) and the layer input X: dX = eta * dXbar (written in place of dXbar)
 // and, through dEta = dXbar * X and eta = exp(-Phi^2), the gradients of Phi's
 // parameters. A workgroup handles 32-pixel batches of a contiguous pixel
-// range; thread t owns channel slot t % ns (ns = min(cin8, 256)) and pixel
-// phase t / ns. At the end the per-thread sums are reduced over the phases in
-// a fixed order and one partial row [W1 (hid*4) | b1 (hid) | W2 (cin*hid) |
-// b2 (cin)] (the layout of these parameters in the flat vector) is written.
+// range. In the channel phase thread t owns channel slot t % ns (ns =
+// min(cin8, 256)) and pixel phase t / ns, and issues the loads of 8 pixels
+// before using them. In the hidden phase thread t < S (S = the largest
+// multiple of hid up to 256) owns hidden unit t % hid and the pixels t / hid,
+// t / hid + S / hid, ..., so it accumulates its unit's W1 and b1 gradients
+// itself. At the end the per-thread sums are reduced in a fixed order and one
+// partial row [W1 (hid*4) | b1 (hid) | W2 (cin*hid) | b2 (cin)] (the layout
+// of these parameters in the flat vector) is written. HC = hid rounded up to
+// a power of two.
 constexpr int kEtaPix = 32;
+constexpr int kEtaGrp = 8;  // pixels whose loads are in flight together
+template <int HC>
 __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8, int hid, int nb,
                                                  const float* __restrict__ lv, int64_t lv_stride,
                                                  const float* __restrict__ W1, const float* __restrict__ b1,
@@ -330,12 +338,14 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
                                                  const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta,
                                                  int64_t e_bs, bf16_t* __restrict__ dxb, float* __restrict__ part) {
   extern __shared__ float sm[];
-  float* s_h = sm;                          // [kEtaPix][32] hidden activations
-  float* s_d = s_h + kEtaPix * 32;          // [kEtaPix][4] distances
-  float* s_dz = s_d + kEtaPix * 4;          // [kEtaPix][32] hidden pre-activation gradients
-  float* s_w2 = s_dz + kEtaPix * 32;        // [hid][cin] (transposed)
-  float* s_dphi = s_w2 + cin * hid;         // [kEtaPix][cin]; reused for the final reduction
+  const int cinp = cin + 1;                 // odd row pitch: rows start in different banks
+  float* s_h = sm;                          // [kEtaPix][HC] hidden activations
+  float* s_d = s_h + kEtaPix * HC;          // [kEtaPix][4] distances
+  float* s_w2 = s_d + kEtaPix * 4;          // [hid][cinp] (transposed)
+  float* s_dphi = s_w2 + cinp * hid;        // [kEtaPix][cinp]; reused for the final reductions
+  __shared__ int s_smp[kEtaPix], s_pix[kEtaPix];  // sample and pixel of each batch pixel
   const int64_t npix = (int64_t)H * W, ntot = npix * nb;
+  const int npix32 = H * W;
   const int64_t per = (ntot + gridDim.x - 1) / gridDim.x;
   const int64_t pbeg = blockIdx.x * per, pend = min(ntot, pbeg + per);
   const int t = threadIdx.x;
@@ -343,32 +353,37 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
   const int phases = 256 / ns;
   const int slot = t % ns, ph = t / ns;
   const bool active = ph < phases;
-  for (int u = t; u < cin * hid; u += 256) s_w2[(u % hid) * cin + u / hid] = W2[u];
-  float aw2[2][32], ab2[2] = {0.f, 0.f}, aw1 = 0.f, b2r[2];
+  const int qstep = 256 / hid, S = qstep * hid;
+  const int my_a = t % hid, my_q = t / hid;  // hidden phase (t < S)
+  for (int u = t; u < cin * hid; u += 256) s_w2[(u % hid) * cinp + u / hid] = W2[u];
+  float aw2[2][HC], ab2[2] = {0.f, 0.f}, b2r[2];
+  float aw1[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // W1 row and b1 of unit my_a
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const int c = slot + ns * k;
     b2r[k] = c < cin ? b2[c] : 0.f;
 #pragma unroll
-    for (int q = 0; q < 32; ++q) aw2[k][q] = 0.f;
+    for (int q = 0; q < HC; ++q) aw2[k][q] = 0.f;
   }
   for (int64_t p0 = pbeg; p0 < pend; p0 += kEtaPix) {
     const int np = (int)min((int64_t)kEtaPix, pend - p0);
     __syncthreads();
     for (int u = t; u < np * hid; u += 256) {
       const int q = u / hid, a = u - q * hid;
-      const int64_t gp = p0 + q;
-      const int smp = (int)(gp / npix);
-      const int64_t p = gp - (int64_t)smp * npix;
-      const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
+      const int gp = (int)(p0 + q);  // the host keeps npix * nb below 2^31
+      const int smp = gp / npix32;
+      const int p = gp - smp * npix32;
+      const int j = p / W, i = p - j * W;
       const float* L = lv + smp * lv_stride;
       const float d0 = L[i], d1 = L[W + i], d2 = L[3 * W + j], d3 = L[3 * W + H + j];
-      s_h[q * 32 + a] = tanhf(b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3);
+      s_h[q * HC + a] = tanhf(b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3);
       if (a == 0) {
         s_d[q * 4] = d0;
         s_d[q * 4 + 1] = d1;
         s_d[q * 4 + 2] = d2;
         s_d[q * 4 + 3] = d3;
+        s_smp[q] = smp;
+        s_pix[q] = p;
       }
     }
     __syncthreads();
@@ -377,66 +392,94 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
       for (int k = 0; k < 2; ++k) {
         const int c = slot + ns * k;
         if (c >= cin8) continue;
-        for (int q = ph; q < np; q += phases) {
-          const int64_t gp = p0 + q;
-          const int smp = (int)(gp / npix);
-          const int64_t p = gp - (int64_t)smp * npix;
-          const int64_t o = gp * cin8 + c;
-          const float g = bf2f(dxb[o]);
-          const float e = bf2f(eta[smp * e_bs + p * cin8 + c]);
-          dxb[o] = f2bf(e * g);
-          if (c >= cin) continue;
-          float phi = b2r[k];
+        for (int qb = ph; qb < np; qb += phases * kEtaGrp) {
+          float gv[kEtaGrp], xv[kEtaGrp], ev[kEtaGrp];
+          int64_t ov[kEtaGrp];
 #pragma unroll
-          for (int a = 0; a < 32; ++a)
-            if (a < hid) phi += s_w2[a * cin + c] * s_h[q * 32 + a];
-          const float ef = expf(-phi * phi);
-          const float dphi = g * bf2f(x[o]) * (-2.f * phi * ef);
-          s_dphi[q * cin + c] = dphi;
-          ab2[k] += dphi;
+          for (int e = 0; e < kEtaGrp; ++e) {
+            const int q = qb + phases * e;
+            gv[e] = xv[e] = ev[e] = 0.f;
+            ov[e] = -1;
+            if (q < np) {
+              ov[e] = (p0 + q) * cin8 + c;
+              gv[e] = bf2f(dxb[ov[e]]);
+              xv[e] = bf2f(x[ov[e]]);
+              ev[e] = bf2f(eta[s_smp[q] * e_bs + (int64_t)s_pix[q] * cin8 + c]);
+            }
+          }
 #pragma unroll
-          for (int a = 0; a < 32; ++a)
-            if (a < hid) aw2[k][a] += dphi * s_h[q * 32 + a];
+          for (int e = 0; e < kEtaGrp; ++e) {
+            const int q = qb + phases * e;
+            if (ov[e] < 0) continue;
+            dxb[ov[e]] = f2bf(ev[e] * gv[e]);
+            if (c >= cin) continue;
+            float phi = b2r[k];
+#pragma unroll
+            for (int a = 0; a < HC; ++a)
+              if (a < hid) phi += s_w2[a * cinp + c] * s_h[q * HC + a];
+            const float ef = expf(-phi * phi);
+            const float dphi = gv[e] * xv[e] * (-2.f * phi * ef);
+            s_dphi[q * cinp + c] = dphi;
+            ab2[k] += dphi;
+#pragma unroll
+            for (int a = 0; a < HC; ++a)
+              if (a < hid) aw2[k][a] += dphi * s_h[q * HC + a];
+          }
         }
       }
     }
     __syncthreads();
-    // dz[q][a] = (sum_c W2[c][a] dphi[q][c]) (1 - h^2), spread over (q, a) pairs
-    for (int u = t; u < np * hid; u += 256) {
-      const int q = u / hid, a = u - q * hid;
-      float dh = 0.f;
-      for (int c = 0; c < cin; ++c) dh += s_w2[a * cin + c] * s_dphi[q * cin + c];
-      const float h = s_h[q * 32 + a];
-      s_dz[q * 32 + a] = dh * (1.f - h * h);
-    }
-    __syncthreads();
-    if (t < hid * 5) {
-      const int a = t / 5, kk = t - a * 5;
-      for (int q = 0; q < np; ++q) aw1 += kk < 4 ? s_dz[q * 32 + a] * s_d[q * 4 + kk] : s_dz[q * 32 + a];
+    // dz[q][a] = (sum_c W2[c][a] dphi[q][c]) (1 - h^2); the unit's W1 / b1 sums
+    if (t < S) {
+      const float* w = s_w2 + my_a * cinp;
+      for (int q = my_q; q < np; q += qstep) {
+        const float* f = s_dphi + q * cinp;
+        float e0 = 0.f, e1 = 0.f, e2 = 0.f, e3 = 0.f;
+        int c = 0;
+        for (; c + 4 <= cin; c += 4) {
+          e0 += w[c] * f[c];
+          e1 += w[c + 1] * f[c + 1];
+          e2 += w[c + 2] * f[c + 2];
+          e3 += w[c + 3] * f[c + 3];
+        }
+        for (; c < cin; ++c) e0 += w[c] * f[c];
+        const float h = s_h[q * HC + my_a];
+        const float dz = ((e0 + e1) + (e2 + e3)) * (1.f - h * h);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) aw1[kk] += dz * s_d[q * 4 + kk];
+        aw1[4] += dz;
+      }
     }
   }
   const int len = hid * 5 + cin * hid + cin;
   float* row = part + (int64_t)blockIdx.x * len;
+  float* red = s_dphi;  // >= 256 * (HC + 1) floats
+  // W1 / b1: the threads of one unit, in order of their pixel offset
+  __syncthreads();
+#pragma unroll
+  for (int kk = 0; kk < 5; ++kk) red[t * 5 + kk] = t < S ? aw1[kk] : 0.f;
+  __syncthreads();
   if (t < hid * 5) {
     const int a = t / 5, kk = t - a * 5;
-    if (kk < 4) row[a * 4 + kk] = aw1;
-    else row[hid * 4 + a] = aw1;
+    float acc = 0.f;
+    for (int q = 0; q < qstep; ++q) acc += red[(q * hid + a) * 5 + kk];
+    if (kk < 4) row[a * 4 + kk] = acc;
+    else row[hid * 4 + a] = acc;
   }
-  // reduce the per-phase sums of each channel (s_dphi holds >= 256 * 33 floats)
-  float* red = s_dphi;
+  // W2 / b2: the per-phase sums of each channel
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     __syncthreads();
 #pragma unroll
-    for (int a = 0; a < 32; ++a)
-      if (a <= hid) red[t * 33 + a] = a < hid ? aw2[k][a] : ab2[k];
+    for (int a = 0; a <= HC; ++a)
+      if (a <= hid) red[t * (HC + 1) + a] = a < hid ? aw2[k][a < HC ? a : 0] : ab2[k];
     __syncthreads();
     for (int u = t; u < ns * (hid + 1); u += 256) {
       const int sl = u / (hid + 1), a = u - sl * (hid + 1);
       const int c = sl + ns * k;
       if (c >= cin) continue;
       float acc = 0.f;
-      for (int q = 0; q < phases; ++q) acc += red[(q * ns + sl) * 33 + a];
+      for (int q = 0; q < phases; ++q) acc += red[(q * ns + sl) * (HC + 1) + a];
       if (a < hid) row[hid * 5 + c * hid + a] = acc;
       else row[hid * 5 + cin * hid + c] = acc;
     }
@@ -647,10 +690,17 @@ int eta_bwd_len(int cin, int hid) { return hid * 5 + cin * hid + cin; }
 void launch_eta_bwd(int H, int W, int cin, int cin8, int hid, int nb, const float* lv, int64_t lv_stride,
                     const float* W1, const float* b1, const float* W2, const float* b2, const bf16_t* x,
                     const bf16_t* eta, int64_t e_bs, bf16_t* dxb, float* part, int nparts, hipStream_t s) {
-  const size_t shm = sizeof(float) * (kEtaPix * 32 + kEtaPix * 4 + kEtaPix * 32 + (size_t)cin * hid +
-                                      std::max<size_t>((size_t)kEtaPix * cin, 256 * 33));
-  k_eta_bwd<<<nparts, 256, shm, s>>>(H, W, cin, cin8, hid, nb, lv, lv_stride, W1, b1, W2, b2, x, eta, e_bs, dxb,
-                                      part);
+  const int hc = hid <= 4 ? 4 : hid <= 8 ? 8 : hid <= 16 ? 16 : 32;
+  const size_t shm = sizeof(float) * (kEtaPix * hc + kEtaPix * 4 + (size_t)(cin + 1) * hid +
+                                      std::max<size_t>((size_t)kEtaPix * (cin + 1), 256 * (size_t)(hc + 1)));
+#define PPE_ETA_BWD(HC)                                                                                         \
+  k_eta_bwd<HC><<<nparts, 256, shm, s>>>(H, W, cin, cin8, hid, nb, lv, lv_stride, W1, b1, W2, b2, x, eta, e_bs, \
+                                         dxb, part)
+  if (hc == 4) PPE_ETA_BWD(4);
+  else if (hc == 8) PPE_ETA_BWD(8);
+  else if (hc == 16) PPE_ETA_BWD(16);
+  else PPE_ETA_BWD(32);
+#undef PPE_ETA_BWD
 }
 
 void launch_fill_static_multi(int H, int W, int pitch, int coff, const float* lv, int64_t lv_stride,
