@@ -122,6 +122,10 @@ def main():
     ap.add_argument("--network-forward", type=int, default=0, metavar="K",
                     help="time K forwards of the default DeepONet (random weights) on the workload's grid "
                          "instead (for kernel traces of the network)")
+    ap.add_argument("--train-step", type=int, default=0, metavar="K",
+                    help="time K training steps (forward, backward, Adam) of the default DeepONet on a pool of "
+                         "--train-batch fabricated n x n systems instead (use with --n 256)")
+    ap.add_argument("--train-batch", type=int, default=64)
     ap.add_argument("--hybrid", default=None, metavar="PATH",
                     help="also time the hybrid solve with the network saved at PATH (default configuration)")
     ap.add_argument("--hybrid-max-iter", type=int, default=30000)
@@ -139,6 +143,21 @@ def main():
 
     ppe.lib()
     torch.cuda.set_device(0)
+    if args.train_step:
+        from paper_2604_01800_amd import training
+        grids, R = training.make_pool(args.n, args.train_batch, seed=3)
+        Rd = torch.from_numpy(R).cuda()
+        probs = [ppe.ppe_problem_create(gg) for gg in grids]
+        net = ppe.Net(ppe.ppe_net_config_default(), seed=1)
+        training.train(net, grids, Rd, steps=3, batch=args.train_batch, lr=1e-4, problems=probs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        training.train(net, grids, Rd, steps=args.train_step, batch=args.train_batch, lr=1e-4, problems=probs)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.train_step * 1e3
+        print(json.dumps({"train_step_ms": ms, "grid": [args.n, args.n], "batch": args.train_batch,
+                          "steps": args.train_step}), flush=True)
+        return
     g, f_np = workload(args.n)
     prob = ppe.ppe_problem_create(g)
     f = torch.from_numpy(f_np[None]).cuda()

@@ -130,7 +130,10 @@ typedef struct {
 /* Network configuration (Sec. 2.4). Defaults (ppe_net_config_default): 4 levels,
  * 32 base channels doubling per level, inputs (scaled residual, mask), 128-term
  * DeepONet basis, trunk 2 -> 128 x 4 -> 128 (tanh), per-layer weight network
- * 4 -> 16 (tanh) -> C_in for the Mesh-Conv local weight (Eq. 17). */
+ * 4 -> 16 (tanh) -> C_in for the Mesh-Conv local weight (Eq. 17).
+ * Limits: levels in [2, 6]; base_channels a multiple of 16; basis and
+ * trunk_width multiples of 8 in [8, 128]; trunk_hidden in [1, 8]; phi_hidden
+ * in [1, 32]. Other values give PPE_ERR_INVALID_ARG. */
 typedef struct {
   int32_t levels, base_channels, basis, trunk_width, trunk_hidden, phi_hidden;
   int32_t use_eta;         /* 1 = Mesh-Conv (Eqs. 17-18), 0 = standard conv ("-Conv" ablation) */

@@ -164,8 +164,9 @@ ppe_status net_refresh(ppe_net* n, hipStream_t s) {
 static ppe_status check_config(const ppe_net_config& c) {
   if (c.levels < 2 || c.levels > 6) return set_error(PPE_ERR_INVALID_ARG, "levels must be in [2, 6]");
   if (c.base_channels < 16 || c.base_channels % 16) return set_error(PPE_ERR_INVALID_ARG, "base_channels: multiple of 16");
-  if (c.basis < 1 || c.basis > 128 || c.trunk_width < 1 || c.trunk_width > 128)
-    return set_error(PPE_ERR_INVALID_ARG, "basis and trunk_width must lie in [1, 128]");
+  // both are channel pitches of activation buffers read in 8-channel (16-byte) groups
+  if (c.basis < 8 || c.basis > 128 || c.basis % 8 || c.trunk_width < 8 || c.trunk_width > 128 || c.trunk_width % 8)
+    return set_error(PPE_ERR_INVALID_ARG, "basis and trunk_width must be multiples of 8 in [8, 128]");
   if (c.trunk_hidden < 1 || c.trunk_hidden > 8) return set_error(PPE_ERR_INVALID_ARG, "trunk_hidden in [1, 8]");
   if (c.phi_hidden < 1 || c.phi_hidden > 32) return set_error(PPE_ERR_INVALID_ARG, "phi_hidden in [1, 32]");
   return PPE_OK;

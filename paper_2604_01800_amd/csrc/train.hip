@@ -203,7 +203,8 @@ static ppe_status train_state(ppe_net* n, int nb, int nx, int ny) {
 }
 
 static int wgrad_splits(int cout, int cin8, int taps, int64_t tiles, int64_t cap) {
-  const int64_t blocks = (int64_t)((cout + 31) / 32) * ((cin8 + 31) / 32);
+  const int tb = taps == 1 ? 128 : 32;  // channel tile of the 1x1 / 3x3 weight-gradient kernels
+  const int64_t blocks = (int64_t)((cout + tb - 1) / tb) * ((cin8 + tb - 1) / tb);
   int64_t ns = std::max<int64_t>(1, 1024 / blocks);
   ns = std::min<int64_t>(ns, tiles);
   ns = std::min<int64_t>(ns, cap / ((int64_t)cout * cin8 * taps));

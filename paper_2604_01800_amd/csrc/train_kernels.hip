@@ -153,6 +153,116 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
   }
 }
 
+// Weight gradient of a 1x1 layer, dW[co][ci] = sum over pixels p of
+// dPre[p][co] * X[p][ci], on MFMA 16x16x32 BF16 with A = dPre^T (M = output
+// channels, K = pixels) and B = X (N = input channels). A workgroup owns a
+// 128 x 128 (co, ci) tile, so every pixel's data is read once per tile; wave
+// w computes the 64 x 64 quarter (w / 2, w % 2) as 4 x 4 MFMA tiles. The
+// pixels are taken in stages of 64 (within one sample), stages z, z + nsplit,
+// ... for split z. Per stage, thread t < 128 loads an 8-pixel x 8-channel
+// block of dPre and thread t >= 128 one of X (coalesced 16-byte loads along
+// the channels), transposes it in registers and writes it to LDS as 16-byte
+// rows [channel][8 pixels]; the next stage's loads are issued before the
+// current stage's MFMA loop. The partial sums are written in the layout
+// [co][ci < cin] of the split's row; k_reduce_rows sums the splits in a
+// fixed order.
+constexpr int kW1T = 128;          // output and input channels per workgroup
+constexpr int kW1P = 64;           // pixels per stage
+constexpr int kW1PP = kW1P + 8;    // LDS pitch (bf16) of a channel row
+
+__device__ __forceinline__ void transpose8x8_bf16(const uint4 (&v)[8], uint4 (&w)[8]) {
+  // v[r] holds channels 0..7 of pixel r; w[e] receives pixels 0..7 of channel e
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    uint32_t o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint4 a4 = v[2 * j], b4 = v[2 * j + 1];
+      const uint32_t a = (e / 2 == 0) ? a4.x : (e / 2 == 1) ? a4.y : (e / 2 == 2) ? a4.z : a4.w;
+      const uint32_t b = (e / 2 == 0) ? b4.x : (e / 2 == 1) ? b4.y : (e / 2 == 2) ? b4.z : b4.w;
+      o[j] = (e & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+    }
+    w[e] = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_wgrad1(WgradGeo g, const bf16_t* __restrict__ dp,
+                                                const bf16_t* __restrict__ x, float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) bf16_t s_dp[kW1T * kW1PP];
+  __shared__ __attribute__((aligned(16))) bf16_t s_x[kW1T * kW1PP];
+  const int co0 = blockIdx.x * kW1T, ci0 = blockIdx.y * kW1T;
+  const int split = blockIdx.z, nsplit = gridDim.z;
+  const int npix = g.H * g.W;
+  const int sps = (npix + kW1P - 1) / kW1P;  // stages per sample
+  const int stages = sps * g.nb;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  // staging role: operand (0 = dPre, 1 = X), channel group and pixel octet
+  const int which = t >> 7, oct = t & 7, cg = (t >> 3) & 15;
+  const int ch = (which ? ci0 : co0) + cg * 8;
+  const bool ch_ok = which ? ch < g.cin8 : ch < g.cout;
+  const int pitch = which ? g.cin8 : g.dp_pitch;
+  const bf16_t* src = which ? x : dp;
+  const int64_t bstride = which ? g.x_bstride : g.dp_bstride;
+  bf16_t* dst = (which ? s_x : s_dp) + (cg * 8) * kW1PP + oct * 8;
+
+  f32x4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  uint4 v[8];
+  auto issue = [&](int st) {
+    const int smp = st / sps, p0 = (st - smp * sps) * kW1P + oct * 8;
+    const bf16_t* b = src + smp * bstride + ch;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      v[r] = make_uint4(0, 0, 0, 0);
+      if (ch_ok && p0 + r < npix) v[r] = *(const uint4*)(b + (int64_t)(p0 + r) * pitch);
+    }
+  };
+  if (split < stages) issue(split);
+  for (int st = split; st < stages; st += nsplit) {
+    __syncthreads();  // the previous stage's MFMA loop is done with LDS
+    {
+      uint4 w[8];
+      transpose8x8_bf16(v, w);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) *(uint4*)(dst + e * kW1PP) = w[e];
+    }
+    __syncthreads();
+    if (st + nsplit < stages) issue(st + nsplit);
+#pragma unroll
+    for (int ks = 0; ks < kW1P / 32; ++ks) {
+      const int k = ks * 32 + (lane >> 4) * 8;
+      bf16x8_t af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = *(const bf16x8_t*)(s_dp + (wm * 64 + i * 16 + (lane & 15)) * kW1PP + k);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = *(const bf16x8_t*)(s_x + (wn * 64 + j * 16 + (lane & 15)) * kW1PP + k);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  // lane holds dW[co0 + 64 wm + 16 i + 4 (lane >> 4) + q][ci0 + 64 wn + 16 j + (lane & 15)]
+  float* ps = part + (int64_t)split * g.cout * g.cin;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int ci = ci0 + wn * 64 + j * 16 + (lane & 15);
+    if (ci >= g.cin) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int co = co0 + wm * 64 + i * 16 + 4 * (lane >> 4) + q;
+        if (co < g.cout) ps[(int64_t)co * g.cin + ci] = acc[i][j][q];
+      }
+  }
+}
+
 // out[k] = scale * sum_b part[b][k] (fixed order, FP64 accumulation). A
 // workgroup handles 32 consecutive k; its 8 thread groups sum the rows
 // g, g + 8, ... and the 8 group sums are added in order.
@@ -644,6 +754,11 @@ static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 void launch_wgrad(int taps, const WgradGeo& g, const bf16_t* dp, const bf16_t* x, const bf16_t* eta, float* part,
                   int nsplit, hipStream_t s) {
+  if (taps == 1 && !eta) {
+    const dim3 grid1((g.cout + kW1T - 1) / kW1T, (g.cin8 + kW1T - 1) / kW1T, nsplit);
+    k_wgrad1<<<grid1, 256, 0, s>>>(g, dp, x, part);
+    return;
+  }
   const dim3 grid((g.cout + 31) / 32, (g.cin8 + 31) / 32, nsplit);
   if (taps == 9) k_wgrad<9><<<grid, 256, 0, s>>>(g, dp, x, eta, part);
   else k_wgrad<1><<<grid, 256, 0, s>>>(g, dp, x, eta, part);

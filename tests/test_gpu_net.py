@@ -93,6 +93,15 @@ def test_forward_rejects_bad_shape(ppe):
     assert ei.value.status == ppe.PPE_ERR_SHAPE
 
 
+@pytest.mark.parametrize("bad", [dict(basis=12), dict(trunk_width=4), dict(basis=136), dict(levels=7),
+                                 dict(base_channels=24), dict(phi_hidden=33)])
+def test_config_limits(ppe, bad):
+    # basis and trunk_width are channel pitches read in 8-channel groups
+    with pytest.raises(ppe.PPEError) as ei:
+        ppe.Net(ppe.ppe_net_config_default(**bad), seed=0)
+    assert ei.value.status == ppe.PPE_ERR_INVALID_ARG
+
+
 def test_zero_residual_gives_bias_only_field(ppe):
     # r = 0 is scaled to 0 (no division by zero); the output is finite.
     cfg = onet.NetConfig(levels=3, base_channels=16)
