@@ -48,11 +48,17 @@ struct ConvShape {
   static constexpr int HALO = TAPS == 9 ? 1 : 0;
   static constexpr int LW = kCTW + 2 * HALO, LH = kCTH + 2 * HALO;
   static constexpr int NPIX = LW * LH;
-  static constexpr int CKP = kConvCK + 8;                       // LDS pitch of a staged pixel (bf16)
-  static constexpr int SMAX = (TAPS * (kConvCK / 8) + 3) / 4;   // K-steps of a full chunk
+  // input channels staged per item: 32 for 3x3 layers, 64 for 1x1 layers (the
+  // packed weight layout is the same: a full 64-channel chunk of a 1x1 layer
+  // is two full 32-channel chunks)
+  static constexpr int CK = TAPS == 9 ? kConvCK : 2 * kConvCK;
+  static constexpr int G8 = CK / 8;                             // 8-channel groups of a staged pixel
+  static constexpr int PPR = 256 / G8;                          // pixels staged per round of 256 threads
+  static constexpr int CKP = CK + 8;                            // LDS pitch of a staged pixel (bf16)
+  static constexpr int SMAX = (TAPS * G8 + 3) / 4;              // K-steps of a full chunk
   static constexpr int WQ = SMAX * 4;                           // 8-value groups of a full weight row
   static constexpr int WKP = SMAX * 32 + 8;                     // LDS pitch of a staged weight row
-  static constexpr int NU = (NPIX + 63) / 64;                   // staged pixels per thread
+  static constexpr int NU = (NPIX + PPR - 1) / PPR;             // staged pixels per thread
   static constexpr int NW = (TN * WQ + 255) / 256;              // weight groups per thread
 };
 
@@ -74,12 +80,12 @@ __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS>& st, const ConvGe
   // recomputed per item (cheap) rather than kept live across the MFMA loop
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
-  const int c8 = tid & 3;
+  const int c8 = tid % S::G8;
   const bool cg_ok = c8 < ck8;
   const uint32_t cofs = (uint32_t)(c0 + c8 * 8) * 2;
 #pragma unroll
   for (int i = 0; i < S::NU; ++i) {
-    const int pix = (tid >> 2) + 64 * i;
+    const int pix = tid / S::G8 + S::PPR * i;
     const int ly = pix / S::LW, lx = pix - ly * S::LW;
     const int gy = py0 + ly - S::HALO, gx = px0 + lx - S::HALO;
     const bool in = cg_ok && pix < S::NPIX && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W;
@@ -105,11 +111,11 @@ __device__ __forceinline__ void conv_commit(const ConvStage<TN, TAPS>& st, bool 
   using S = ConvShape<TN, TAPS>;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
-  const int c8 = tid & 3;
+  const int c8 = tid % S::G8;
   if (c8 < ck8) {
 #pragma unroll
     for (int i = 0; i < S::NU; ++i) {
-      const int pix = (tid >> 2) + 64 * i;
+      const int pix = tid / S::G8 + S::PPR * i;
       if (pix < S::NPIX) *(uint4*)(s_x + pix * S::CKP + c8 * 8) = has_eta ? mul_bf16x8(st.x[i], st.e[i]) : st.x[i];
     }
   }
@@ -191,7 +197,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(x), (short)0, in_bytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t er =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(eta ? eta : x), (short)0, in_bytes, 0x00020000);
-  const int nch = (g.cin8 + kConvCK - 1) / kConvCK;
+  const int nch = (g.cin8 + S::CK - 1) / S::CK;
   const int items = nt_wg * nch;
 
   f32x4_t acc[MT][NT];
@@ -204,20 +210,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   auto issue = [&](int it) {
     const int t = t0 + it / nch, c = it - (it / nch) * nch;
     const int py0 = (t / tiles_x) * kCTH, px0 = (t % tiles_x) * kCTW;
-    conv_issue<TN, TAPS>(stg, g, xr, er, eta != nullptr, wr, Kp, co0, py0, px0, c * kConvCK,
-                         min(kConvCK, g.cin8 - c * kConvCK) / 8, c * S::SMAX * 32);
+    conv_issue<TN, TAPS>(stg, g, xr, er, eta != nullptr, wr, Kp, co0, py0, px0, c * S::CK,
+                         min(S::CK, g.cin8 - c * S::CK) / 8, c * S::SMAX * 32);
   };
   for (int it = 0; it < items; ++it) {
     const int t = t0 + it / nch, c = it - (it / nch) * nch;
-    const int c0 = c * kConvCK;
-    const int ck8 = min(kConvCK, g.cin8 - c0) / 8;
+    const int c0 = c * S::CK;
+    const int ck8 = min(S::CK, g.cin8 - c0) / 8;
     issue(it);        // in flight while the other waves finish the previous item
     __syncthreads();  // the previous item's MFMA loop is done with LDS
     conv_commit<TN, TAPS>(stg, eta != nullptr, ck8, s_x, s_w);
     __syncthreads();
 
-    if (ck8 == kConvCK / 8)
-      conv_mfma<TN, TAPS, kConvCK / 8>(acc, s_x, s_w, ck8, lane, wv);
+    if (ck8 == S::G8)
+      conv_mfma<TN, TAPS, S::G8>(acc, s_x, s_w, ck8, lane, wv);
     else
       conv_mfma<TN, TAPS, 0>(acc, s_x, s_w, ck8, lane, wv);
     if (c + 1 < nch) continue;
