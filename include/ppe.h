@@ -131,9 +131,14 @@ typedef struct {
  * 32 base channels doubling per level, inputs (scaled residual, mask), 128-term
  * DeepONet basis, trunk 2 -> 128 x 4 -> 128 (tanh), per-layer weight network
  * 4 -> 16 (tanh) -> C_in for the Mesh-Conv local weight (Eq. 17).
- * Limits: levels in [2, 6]; base_channels a multiple of 16; basis and
- * trunk_width multiples of 8 in [8, 128]; trunk_hidden in [1, 8]; phi_hidden
- * in [1, 32]. Other values give PPE_ERR_INVALID_ARG. */
+ * Limits: levels in [2, 6]; base_channels a multiple of 8 with
+ * base_channels x 2^(levels-1) <= 1024 (the paper's U-Net, 5 levels from 40
+ * channels, fits); basis and trunk_width multiples of 8 in [8, 128];
+ * trunk_hidden in [1, 8]; phi_hidden in [1, 32]. Other values give
+ * PPE_ERR_INVALID_ARG. Training (ppe_net_train_step) further needs every
+ * Mesh-Conv layer's inputs x phi_hidden to fit the local-weight backward's
+ * LDS (up to about 850 inputs at phi_hidden 16, 200 at phi_hidden 32), else
+ * PPE_ERR_INVALID_ARG. */
 typedef struct {
   int32_t levels, base_channels, basis, trunk_width, trunk_hidden, phi_hidden;
   int32_t use_eta;         /* 1 = Mesh-Conv (Eqs. 17-18), 0 = standard conv ("-Conv" ablation) */

@@ -163,7 +163,9 @@ ppe_status net_refresh(ppe_net* n, hipStream_t s) {
 
 static ppe_status check_config(const ppe_net_config& c) {
   if (c.levels < 2 || c.levels > 6) return set_error(PPE_ERR_INVALID_ARG, "levels must be in [2, 6]");
-  if (c.base_channels < 16 || c.base_channels % 16) return set_error(PPE_ERR_INVALID_ARG, "base_channels: multiple of 16");
+  if (c.base_channels < 8 || c.base_channels % 8) return set_error(PPE_ERR_INVALID_ARG, "base_channels: multiple of 8");
+  if ((int64_t)c.base_channels << (c.levels - 1) > 1024)
+    return set_error(PPE_ERR_INVALID_ARG, "base_channels x 2^(levels-1) must not exceed 1024");
   // both are channel pitches of activation buffers read in 8-channel (16-byte) groups
   if (c.basis < 8 || c.basis > 128 || c.basis % 8 || c.trunk_width < 8 || c.trunk_width > 128 || c.trunk_width % 8)
     return set_error(PPE_ERR_INVALID_ARG, "basis and trunk_width must be multiples of 8 in [8, 128]");

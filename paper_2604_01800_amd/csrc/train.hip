@@ -238,6 +238,15 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
   const ppe_net_config& cfg = n->cfg;
   const int nx = problems[0]->nx, ny = problems[0]->ny, L = cfg.levels, P = cfg.basis, TWd = cfg.trunk_width;
   const int TH = cfg.trunk_hidden, HID = cfg.phi_hidden, C0 = cfg.base_channels;
+  if (cfg.use_eta) {
+    auto fits = [&](const MConvL& m) { return m.cin == 0 || eta_bwd_fits(m.cin, m.cin8, HID); };
+    for (int l = 0; l < L; ++l) {
+      const bool ok = fits(n->enc_a[l]) && fits(n->enc_b[l]) && (l > L - 2 || (fits(n->dec_c[l]) && fits(n->dec_d[l])));
+      if (!ok)
+        return set_error(PPE_ERR_INVALID_ARG,
+                         "level %d is too wide for the training kernels (inputs x phi_hidden must fit the LDS)", l);
+    }
+  }
   const int64_t N = (int64_t)nx * ny;
   if (N * nb >= (int64_t)1 << 31)
     return set_error(PPE_ERR_INVALID_ARG, "nb x cells must stay below 2^31 (got %lld)", (long long)(N * nb));
@@ -447,7 +456,8 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
       if (!cfg.use_eta) return;
       const int l = m.level;
       const int len = eta_bwd_len(m.cin, HID);
-      const int np = 2048;
+      // partial rows: up to 2048, as many as the partials buffer holds
+      const int np = (int)std::min<int64_t>(2048, cap / len);
       launch_eta_bwd(t->H[l], t->W[l], m.cin, m.cin8, HID, nb, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
                      W + m.ob1, W + m.oW2, W + m.ob2, x, E + eoff, hw(l) * m.cin8, dxb, part, np, s);
       launch_reduce_rows(part, np, len, 1.f, dG + m.oW1, s);

@@ -429,30 +429,32 @@ __global__ __launch_bounds__(256) void k_eta_multi(int H, int W, int cin, int ci
 // input) and the layer input X: dX = eta * dXbar (written in place of dXbar)
 // and, through dEta = dXbar * X and eta = exp(-Phi^2), the gradients of Phi's
 // parameters. A workgroup handles 32-pixel batches of a contiguous pixel
-// range. In the channel phase thread t owns channel slot t % ns (ns =
-// min(cin8, 256)) and pixel phase t / ns, and issues the loads of 8 pixels
-// before using them. In the hidden phase thread t < S (S = the largest
+// range (npb <= 32 pixels per batch, as many as the LDS holds for this
+// layer's width). In the channel phase thread t owns the channel slots t % ns + k ns
+// (ns = min(cin8, 256), k < KS) and pixel phase t / ns, and issues the loads
+// of 8 pixels before using them. In the hidden phase thread t < S (S = the largest
 // multiple of hid up to 256) owns hidden unit t % hid and the pixels t / hid,
 // t / hid + S / hid, ..., so it accumulates its unit's W1 and b1 gradients
 // itself. At the end the per-thread sums are reduced in a fixed order and one
 // partial row [W1 (hid*4) | b1 (hid) | W2 (cin*hid) | b2 (cin)] (the layout
 // of these parameters in the flat vector) is written. HC = hid rounded up to
-// a power of two.
+// a power of two; KS >= cin8 / 256 channel slots per thread.
 constexpr int kEtaPix = 32;
 constexpr int kEtaGrp = 8;  // pixels whose loads are in flight together
-template <int HC>
+template <int HC, int KS>
 __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8, int hid, int nb,
                                                  const float* __restrict__ lv, int64_t lv_stride,
                                                  const float* __restrict__ W1, const float* __restrict__ b1,
                                                  const float* __restrict__ W2, const float* __restrict__ b2,
                                                  const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta,
-                                                 int64_t e_bs, bf16_t* __restrict__ dxb, float* __restrict__ part) {
+                                                 int64_t e_bs, bf16_t* __restrict__ dxb, float* __restrict__ part,
+                                                 int npb) {
   extern __shared__ float sm[];
   const int cinp = cin + 1;                 // odd row pitch: rows start in different banks
   float* s_h = sm;                          // [kEtaPix][HC] hidden activations
   float* s_d = s_h + kEtaPix * HC;          // [kEtaPix][4] distances
   float* s_w2 = s_d + kEtaPix * 4;          // [hid][cinp] (transposed)
-  float* s_dphi = s_w2 + cinp * hid;        // [kEtaPix][cinp]; reused for the final reductions
+  float* s_dphi = s_w2 + cinp * hid;        // [npb][cinp]; reused for the final reductions
   __shared__ int s_smp[kEtaPix], s_pix[kEtaPix];  // sample and pixel of each batch pixel
   const int64_t npix = (int64_t)H * W, ntot = npix * nb;
   const int npix32 = H * W;
@@ -466,17 +468,18 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
   const int qstep = 256 / hid, S = qstep * hid;
   const int my_a = t % hid, my_q = t / hid;  // hidden phase (t < S)
   for (int u = t; u < cin * hid; u += 256) s_w2[(u % hid) * cinp + u / hid] = W2[u];
-  float aw2[2][HC], ab2[2] = {0.f, 0.f}, b2r[2];
+  float aw2[KS][HC], ab2[KS], b2r[KS];
   float aw1[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // W1 row and b1 of unit my_a
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < KS; ++k) {
     const int c = slot + ns * k;
+    ab2[k] = 0.f;
     b2r[k] = c < cin ? b2[c] : 0.f;
 #pragma unroll
     for (int q = 0; q < HC; ++q) aw2[k][q] = 0.f;
   }
-  for (int64_t p0 = pbeg; p0 < pend; p0 += kEtaPix) {
-    const int np = (int)min((int64_t)kEtaPix, pend - p0);
+  for (int64_t p0 = pbeg; p0 < pend; p0 += npb) {
+    const int np = (int)min((int64_t)npb, pend - p0);
     __syncthreads();
     for (int u = t; u < np * hid; u += 256) {
       const int q = u / hid, a = u - q * hid;
@@ -499,7 +502,7 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
     __syncthreads();
     if (active) {
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < KS; ++k) {
         const int c = slot + ns * k;
         if (c >= cin8) continue;
         for (int qb = ph; qb < np; qb += phases * kEtaGrp) {
@@ -578,7 +581,7 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
   }
   // W2 / b2: the per-phase sums of each channel
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < KS; ++k) {
     __syncthreads();
 #pragma unroll
     for (int a = 0; a <= HC; ++a)
@@ -802,19 +805,45 @@ void launch_eta_multi(int H, int W, int cin, int cin8, int hid, const float* lv,
 
 int eta_bwd_len(int cin, int hid) { return hid * 5 + cin * hid + cin; }
 
+// LDS of one workgroup of k_eta_bwd, in floats, apart from the dphi rows.
+static int64_t eta_bwd_fixed(int cin, int hid, int hc) { return (int64_t)kEtaPix * hc + kEtaPix * 4 + (int64_t)(cin + 1) * hid; }
+
+// LDS available to one workgroup's dynamic allocation: the default 64 KiB
+// limit less 1 KiB for the kernel's static arrays.
+static int64_t lds_per_block() { return 63 * 1024; }
+
+static int eta_bwd_hc(int hid) { return hid <= 4 ? 4 : hid <= 8 ? 8 : hid <= 16 ? 16 : 32; }
+
+// Pixels per batch that fit the LDS (0: the layer is too wide).
+static int eta_bwd_npb(int cin, int hid) {
+  const int hc = eta_bwd_hc(hid);
+  const int64_t room = lds_per_block() / (int64_t)sizeof(float) - eta_bwd_fixed(cin, hid, hc);
+  if (room < 256 * (int64_t)(hc + 1)) return 0;  // the final reductions need this much
+  return (int)std::min<int64_t>(kEtaPix, room / (cin + 1));
+}
+
+bool eta_bwd_fits(int cin, int cin8, int hid) { return cin8 <= 1024 && eta_bwd_npb(cin, hid) >= 1; }
+
 void launch_eta_bwd(int H, int W, int cin, int cin8, int hid, int nb, const float* lv, int64_t lv_stride,
                     const float* W1, const float* b1, const float* W2, const float* b2, const bf16_t* x,
                     const bf16_t* eta, int64_t e_bs, bf16_t* dxb, float* part, int nparts, hipStream_t s) {
-  const int hc = hid <= 4 ? 4 : hid <= 8 ? 8 : hid <= 16 ? 16 : 32;
-  const size_t shm = sizeof(float) * (kEtaPix * hc + kEtaPix * 4 + (size_t)(cin + 1) * hid +
-                                      std::max<size_t>((size_t)kEtaPix * (cin + 1), 256 * (size_t)(hc + 1)));
-#define PPE_ETA_BWD(HC)                                                                                         \
-  k_eta_bwd<HC><<<nparts, 256, shm, s>>>(H, W, cin, cin8, hid, nb, lv, lv_stride, W1, b1, W2, b2, x, eta, e_bs, \
-                                         dxb, part)
-  if (hc == 4) PPE_ETA_BWD(4);
-  else if (hc == 8) PPE_ETA_BWD(8);
-  else if (hc == 16) PPE_ETA_BWD(16);
-  else PPE_ETA_BWD(32);
+  const int hc = eta_bwd_hc(hid);
+  const int npb = eta_bwd_npb(cin, hid);  // >= 1: the caller checked eta_bwd_fits
+  const size_t shm = sizeof(float) * (eta_bwd_fixed(cin, hid, hc) +
+                                      std::max<int64_t>((int64_t)npb * (cin + 1), 256 * (int64_t)(hc + 1)));
+#define PPE_ETA_BWD(HC, KS)                                                                                    \
+  k_eta_bwd<HC, KS><<<nparts, 256, shm, s>>>(H, W, cin, cin8, hid, nb, lv, lv_stride, W1, b1, W2, b2, x, eta, \
+                                             e_bs, dxb, part, npb)
+#define PPE_ETA_BWD_HC(KS)                  \
+  if (hc == 4) PPE_ETA_BWD(4, KS);          \
+  else if (hc == 8) PPE_ETA_BWD(8, KS);     \
+  else if (hc == 16) PPE_ETA_BWD(16, KS);   \
+  else PPE_ETA_BWD(32, KS)
+  // channel slots per thread: cin8 <= 256 needs one, <= 512 two, <= 1024 four
+  if (cin8 <= 256) { PPE_ETA_BWD_HC(1); }
+  else if (cin8 <= 512) { PPE_ETA_BWD_HC(2); }
+  else { PPE_ETA_BWD_HC(4); }
+#undef PPE_ETA_BWD_HC
 #undef PPE_ETA_BWD
 }
 

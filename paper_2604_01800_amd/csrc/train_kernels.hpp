@@ -30,6 +30,9 @@ void launch_eta_multi(int H, int W, int cin, int cin8, int hid, const float* lv,
                       const float* b1, const float* W2, const float* b2, bf16_t* eta, int64_t e_bs, int nb,
                       hipStream_t s);
 int eta_bwd_len(int cin, int hid);
+// Whether the local-weight backward handles a layer of cin inputs (pitch cin8)
+// and hid hidden units: cin8 <= 1024 and its LDS rows fit the device.
+bool eta_bwd_fits(int cin, int cin8, int hid);
 void launch_eta_bwd(int H, int W, int cin, int cin8, int hid, int nb, const float* lv, int64_t lv_stride,
                     const float* W1, const float* b1, const float* W2, const float* b2, const bf16_t* x,
                     const bf16_t* eta, int64_t e_bs, bf16_t* dxb, float* part, int nparts, hipStream_t s);

@@ -66,9 +66,15 @@ def oracle_grads(cfg, p, grids, R):
                          for k, v in q.items()}
 
 
-@pytest.mark.parametrize("use_eta,use_spacing", [(1, 1), (0, 1), (1, 0)])
-def test_gradients_match_oracle(ppe, use_eta, use_spacing):
-    cfg = small_cfg()
+def paper_width_cfg():
+    # the paper's U-Net size (5 levels from 40 channels: layers of up to 642
+    # inputs, several channel slots per thread in the local-weight backward)
+    return onet.NetConfig(levels=5, base_channels=40, basis=16, trunk_width=16, trunk_hidden=2, phi_hidden=16)
+
+
+@pytest.mark.parametrize("use_eta,use_spacing,wide", [(1, 1, 0), (0, 1, 0), (1, 0, 0), (1, 1, 1)])
+def test_gradients_match_oracle(ppe, use_eta, use_spacing, wide):
+    cfg = paper_width_cfg() if wide else small_cfg()
     cfg.use_eta, cfg.use_spacing = use_eta, use_spacing
     p = onet.round_bf16_params(cfg, onet.init_params(cfg, np.random.default_rng(3), phi_scale=1.0))
     net = ppe.Net(gpu_cfg(ppe, cfg), seed=0)
