@@ -132,6 +132,10 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--clip", type=float, default=0.0, help="global gradient-norm clip (0: none)")
     ap.add_argument("--sam", type=float, default=0.0, help="sharpness-aware radius (0: plain Adam)")
+    ap.add_argument("--levels", type=int, default=0, help="U-Net levels (0: the library default, 4)")
+    ap.add_argument("--base-channels", type=int, default=0,
+                    help="channels of the finest level, doubling per level (0: the library default, 32); "
+                         "the paper's network is --levels 5 --base-channels 40")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", default=None, help="save the trained network here")
     ap.add_argument("--load", default=None, help="load this network instead of training one")
@@ -142,7 +146,12 @@ def main(argv=None):
                     help="also sweep Num_CG and Num_DLSM over 1..5 on held-out n x n systems (Appendix A)")
     args = ap.parse_args(argv)
     ppe.lib()
-    net = ppe.Net(ppe.ppe_net_config_default(), seed=args.seed)
+    kw = {}
+    if args.levels:
+        kw["levels"] = args.levels
+    if args.base_channels:
+        kw["base_channels"] = args.base_channels
+    net = ppe.Net(ppe.ppe_net_config_default(**kw), seed=args.seed)
     if args.load:
         ppe.ppe_net_load(net, args.load)
     else:
