@@ -445,8 +445,8 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
       launch_reduce_rows(part, ns, (int64_t)cout * cin * taps, 1.f, dG + oW, s);
     };
     auto bias = [&](int l, const bf16_t* d, int pitch, int C, int64_t ob) {
-      launch_bias_grad(d, hw(l) * nb, pitch, 0, C, part, 256, s);
-      launch_reduce_rows(part, 256, C, 1.f, dG + ob, s);
+      launch_bias_grad(d, hw(l) * nb, pitch, 0, C, part, 1024, s);
+      launch_reduce_rows(part, 1024, C, 1.f, dG + ob, s);
     };
     auto dgrad = [&](int taps, int l, const bf16_t* dp, int cout_fwd, int64_t pT, int kT, int rows, bf16_t* out) {
       ConvGeo g = geo(l, cout_fwd, rows, rows, 0, 0);

@@ -295,13 +295,23 @@ __global__ __launch_bounds__(256) void k_bias_grad(const bf16_t* __restrict__ d,
   const int c8 = t % c8n, g = t / c8n;
   float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (g < G) {
-    for (int64_t p = (int64_t)blockIdx.x * G + g; p < npix; p += (int64_t)gridDim.x * G) {
-      const uint4 v = *(const uint4*)(d + p * pitch + off + c8 * 8);
-      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+    // four pixels' loads in flight per thread
+    const int64_t step = (int64_t)gridDim.x * G;
+    for (int64_t p = (int64_t)blockIdx.x * G + g; p < npix; p += 4 * step) {
+      uint4 v[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        acc[2 * e] += bf2f((bf16_t)(w4[e] & 0xffff));
-        acc[2 * e + 1] += bf2f((bf16_t)(w4[e] >> 16));
+      for (int u = 0; u < 4; ++u) {
+        const int64_t pu = p + u * step;
+        v[u] = pu < npix ? *(const uint4*)(d + pu * pitch + off + c8 * 8) : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t w4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc[2 * e] += bf2f((bf16_t)(w4[e] & 0xffff));
+          acc[2 * e + 1] += bf2f((bf16_t)(w4[e] >> 16));
+        }
       }
     }
   }
@@ -393,35 +403,45 @@ __global__ void k_pool_bwd(int Hc, int Wc, int C, const bf16_t* __restrict__ dpo
 // level arrays of sample s start at lv + s * lv_stride. A workgroup computes
 // the hidden layer of Phi for 32 pixels, then writes eta[p][c] with the
 // channel index fastest across threads.
+constexpr int kEtaMPix = 128;  // pixels per workgroup of k_eta_multi
 __global__ __launch_bounds__(256) void k_eta_multi(int H, int W, int cin, int cin8, int hid,
                                                    const float* __restrict__ lv, int64_t lv_stride,
                                                    const float* __restrict__ W1, const float* __restrict__ b1,
                                                    const float* __restrict__ W2, const float* __restrict__ b2,
                                                    bf16_t* __restrict__ eta, int64_t e_bs) {
+  // Phi's output layer in LDS, transposed ([hid][cin] then b2) so that lanes
+  // of consecutive channels read consecutive words; kEtaMPix pixels per
+  // workgroup in batches of 32
+  extern __shared__ float s_w2[];
   __shared__ float s_h[32][33];
+  float* s_b2 = s_w2 + hid * cin;
+  for (int u = threadIdx.x; u < cin * hid; u += 256) s_w2[(u % hid) * cin + u / hid] = W2[u];
+  for (int u = threadIdx.x; u < cin; u += 256) s_b2[u] = b2[u];
   const int64_t npix = (int64_t)H * W;
-  const int64_t p0 = (int64_t)blockIdx.x * 32;
   const float* L = lv + blockIdx.y * lv_stride;
-  for (int u = threadIdx.x; u < 32 * hid; u += 256) {
-    const int q = u / hid, a = u - q * hid;
-    const int64_t p = min(p0 + q, npix - 1);
-    const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
-    const float d0 = L[i], d1 = L[W + i], d2 = L[3 * W + j], d3 = L[3 * W + H + j];
-    s_h[q][a] = tanhf(b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3);
-  }
-  __syncthreads();
   bf16_t* out = eta + blockIdx.y * e_bs;
-  for (int u = threadIdx.x; u < 32 * cin8; u += 256) {
-    const int q = u / cin8, c = u - q * cin8;
-    const int64_t p = p0 + q;
-    if (p >= npix) continue;
-    float e = 0.f;
-    if (c < cin) {
-      float phi = b2[c];
-      for (int a = 0; a < hid; ++a) phi += W2[c * hid + a] * s_h[q][a];
-      e = expf(-phi * phi);
+  for (int64_t p0 = (int64_t)blockIdx.x * kEtaMPix; p0 < min(npix, (int64_t)(blockIdx.x + 1) * kEtaMPix); p0 += 32) {
+    __syncthreads();
+    for (int u = threadIdx.x; u < 32 * hid; u += 256) {
+      const int q = u / hid, a = u - q * hid;
+      const int64_t p = min(p0 + q, npix - 1);
+      const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
+      const float d0 = L[i], d1 = L[W + i], d2 = L[3 * W + j], d3 = L[3 * W + H + j];
+      s_h[q][a] = tanhf(b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3);
     }
-    out[p * cin8 + c] = f2bf(e);
+    __syncthreads();
+    for (int u = threadIdx.x; u < 32 * cin8; u += 256) {
+      const int q = u / cin8, c = u - q * cin8;
+      const int64_t p = p0 + q;
+      if (p >= npix) continue;
+      float e = 0.f;
+      if (c < cin) {
+        float phi = s_b2[c];
+        for (int a = 0; a < hid; ++a) phi += s_w2[a * cin + c] * s_h[q][a];
+        e = expf(-phi * phi);
+      }
+      out[p * cin8 + c] = f2bf(e);
+    }
   }
 }
 
@@ -799,8 +819,9 @@ void launch_pool_bwd(int Hc, int Wc, int C, const bf16_t* dpool, int ppitch, int
 void launch_eta_multi(int H, int W, int cin, int cin8, int hid, const float* lv, int64_t lv_stride, const float* W1,
                       const float* b1, const float* W2, const float* b2, bf16_t* eta, int64_t e_bs, int nb,
                       hipStream_t s) {
-  k_eta_multi<<<dim3((unsigned)(((int64_t)H * W + 31) / 32), nb), 256, 0, s>>>(H, W, cin, cin8, hid, lv, lv_stride,
-                                                                                W1, b1, W2, b2, eta, e_bs);
+  const size_t shm = sizeof(float) * ((size_t)hid * cin + cin);
+  k_eta_multi<<<dim3((unsigned)(((int64_t)H * W + kEtaMPix - 1) / kEtaMPix), nb), 256, shm, s>>>(
+      H, W, cin, cin8, hid, lv, lv_stride, W1, b1, W2, b2, eta, e_bs);
 }
 
 int eta_bwd_len(int cin, int hid) { return hid * 5 + cin * hid + cin; }
