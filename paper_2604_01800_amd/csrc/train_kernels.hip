@@ -488,7 +488,10 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
   const int qstep = 256 / hid, S = qstep * hid;
   const int my_a = t % hid, my_q = t / hid;  // hidden phase (t < S)
   for (int u = t; u < cin * hid; u += 256) s_w2[(u % hid) * cinp + u / hid] = W2[u];
-  float aw2[KS][HC], ab2[KS], b2r[KS];
+  // the thread's own channels' row of Phi's output layer in registers when it
+  // is small enough (else read from LDS)
+  constexpr bool W2REG = KS * HC <= 32;
+  float aw2[KS][HC], ab2[KS], b2r[KS], w2r[W2REG ? KS : 1][W2REG ? HC : 1];
   float aw1[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // W1 row and b1 of unit my_a
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
@@ -496,7 +499,10 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
     ab2[k] = 0.f;
     b2r[k] = c < cin ? b2[c] : 0.f;
 #pragma unroll
-    for (int q = 0; q < HC; ++q) aw2[k][q] = 0.f;
+    for (int q = 0; q < HC; ++q) {
+      aw2[k][q] = 0.f;
+      if (W2REG) w2r[W2REG ? k : 0][W2REG ? q : 0] = (c < cin && q < hid) ? W2[c * hid + q] : 0.f;
+    }
   }
   for (int64_t p0 = pbeg; p0 < pend; p0 += npb) {
     const int np = (int)min((int64_t)npb, pend - p0);
@@ -549,7 +555,8 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
             float phi = b2r[k];
 #pragma unroll
             for (int a = 0; a < HC; ++a)
-              if (a < hid) phi += s_w2[a * cinp + c] * s_h[q * HC + a];
+              if (a < hid)
+                phi += (W2REG ? w2r[W2REG ? k : 0][W2REG ? a : 0] : s_w2[a * cinp + c]) * s_h[q * HC + a];
             const float ef = expf(-phi * phi);
             const float dphi = gv[e] * xv[e] * (-2.f * phi * ef);
             s_dphi[q * cinp + c] = dphi;
