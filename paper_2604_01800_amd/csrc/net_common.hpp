@@ -27,6 +27,16 @@ __host__ __device__ __forceinline__ float bf2f(bf16_t h) {
   return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
 
+// exp and tanh where the result is stored in BF16 or feeds a network
+// gradient: the hardware exponential and reciprocal, relative error about
+// 1e-6 (absolute for tanh near 0), far below BF16's 2^-8 step. tanh uses the
+// identity tanh x = sign(x) (1 - e^{-2|x|}) / (1 + e^{-2|x|}).
+__device__ __forceinline__ float exp_nn(float x) { return __expf(x); }
+__device__ __forceinline__ float tanh_nn(float x) {
+  const float t = __expf(-2.f * fabsf(x));
+  return copysignf((1.f - t) * __builtin_amdgcn_rcpf(1.f + t), x);
+}
+
 constexpr int kConvTH = 8;   // conv pixel tile: 8 rows x 16 columns
 constexpr int kConvTW = 16;
 constexpr int kConvCK = 32;  // input channels staged per LDS chunk

@@ -248,10 +248,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             v2 = fmaxf(v2, 0.f);
             v3 = fmaxf(v3, 0.f);
           } else if (g.act == 2) {
-            v0 = tanhf(v0);
-            v1 = tanhf(v1);
-            v2 = tanhf(v2);
-            v3 = tanhf(v3);
+            v0 = tanh_nn(v0);
+            v1 = tanh_nn(v1);
+            v2 = tanh_nn(v2);
+            v3 = tanh_nn(v3);
           }
           const uint2 packed = make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
                                           (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
@@ -270,6 +270,120 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     }
+  }
+}
+
+// A 1x1 layer of at most 128 output and 128 input channels as a skinny GEMM,
+// y[p][co] = act(bias[co] + sum_k W[co][k] x[p][k]). The workgroup stages the
+// layer's packed weights in LDS once (A fragments: M = output channels, K =
+// input channels); each wavefront then streams 16-pixel tiles, loading the B
+// fragments (8 consecutive input channels of one pixel per lane) straight
+// from memory two tiles ahead, and computes all output channels of a tile.
+// Every input byte is read once. MT = output-channel tiles of 16 (cout <=
+// 16 MT); K-steps = Kp / 32 <= 4.
+constexpr int kC1KS = 4;                  // K-steps at most (Kp <= 128)
+constexpr int kC1WP = kC1KS * 32 + 8;     // LDS pitch of a weight row (bf16)
+template <int MT>
+__global__ __launch_bounds__(256) void k_conv1x1(ConvGeo g, const bf16_t* __restrict__ x,
+                                                 const bf16_t* __restrict__ wp, int Kp,
+                                                 const float* __restrict__ bias, bf16_t* __restrict__ y) {
+  __shared__ __attribute__((aligned(16))) bf16_t s_w[MT * 16 * kC1WP];
+  constexpr int OP = MT * 16 + 8;  // LDS pitch (bf16) of a staged output pixel
+  __shared__ __attribute__((aligned(16))) bf16_t s_o[4][16 * OP];  // per wavefront
+  const int nks = Kp / 32;
+  const int lane = threadIdx.x & 63;
+  const int smp = blockIdx.y;
+  x += smp * g.x_bstride;
+  y += smp * g.y_bstride;
+  const int npix = g.H * g.W;
+  // weights: rows past cout read as zero
+  const __amdgpu_buffer_rsrc_t wr =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(wp), (short)0, (int)((int64_t)g.cout * Kp * 2), 0x00020000);
+  for (int u = threadIdx.x; u < MT * 16 * (Kp / 8); u += 256) {
+    const int r = u / (Kp / 8), q = u - r * (Kp / 8);
+    *(uint4*)(s_w + r * kC1WP + q * 8) =
+        __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wr, (int)((r * Kp + q * 8) * 2), 0, 0));
+  }
+  __syncthreads();
+  const __amdgpu_buffer_rsrc_t xr =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(x), (short)0, (int)((int64_t)npix * g.cin8 * 2), 0x00020000);
+  const int tiles = (npix + 15) / 16;
+  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6), nwv = gridDim.x * 4;
+  // B fragments of tile t: channels ks*32 + (lane>>4)*8 of pixel 16t + (lane&15)
+  auto bload = [&](int t, bf16x8_t* bf) {
+    const int px = t * 16 + (lane & 15);
+#pragma unroll
+    for (int ks = 0; ks < kC1KS; ++ks) {
+      const int k = ks * 32 + (lane >> 4) * 8;
+      const uint32_t o = (ks < nks && px < npix && k < g.cin8) ? (uint32_t)(px * g.cin8 + k) * 2u : 0x80000000u;
+      bf[ks] = __builtin_bit_cast(bf16x8_t, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)o, 0, 0));
+    }
+  };
+  const bf16_t* arow = s_w + (lane & 15) * kC1WP + (lane >> 4) * 8;
+  float bv[MT][4];  // this lane's output channels' biases
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int co = mt * 16 + 4 * (lane >> 4) + j;
+      bv[mt][j] = (bias && co < g.cout) ? bias[co] : 0.f;
+    }
+  auto tile = [&](int t, const bf16x8_t* bf) {
+    f32x4_t acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kC1KS; ++ks) {
+      if (ks >= nks) break;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const bf16x8_t af = *(const bf16x8_t*)(arow + mt * 16 * kC1WP + ks * 32);
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[ks], acc[mt], 0, 0, 0);
+      }
+    }
+    // the tile's outputs through the wavefront's LDS rows, then stored as
+    // 16-byte pieces that cover whole pixel rows
+    bf16_t* so = s_o[threadIdx.x >> 6];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int co = mt * 16 + 4 * (lane >> 4);
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[j] = acc[mt][j] + bv[mt][j];
+        if (g.act == 1) v[j] = fmaxf(v[j], 0.f);
+        else if (g.act == 2) v[j] = tanh_nn(v[j]);
+      }
+      *(uint2*)(so + (lane & 15) * OP + co) = make_uint2((uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                                                         (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16));
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int c8n = g.cout / 8;  // 8-channel groups per pixel
+#pragma unroll
+    for (int e0 = 0; e0 < 16 * MT * 2; e0 += 64) {
+      const int e = e0 + lane, q = e / (MT * 2), c8 = e - q * (MT * 2);
+      const int px = t * 16 + q;
+      if (c8 < c8n && px < npix)
+        *(uint4*)(y + (size_t)px * g.y_pitch + g.y_off + c8 * 8) = *(const uint4*)(so + q * OP + c8 * 8);
+    }
+    __builtin_amdgcn_wave_barrier();
+  };
+  // two tiles in flight: the loads of tile t + 2 nwv are issued as soon as
+  // tile t's fragments are consumed
+  bf16x8_t b0[kC1KS], b1[kC1KS];
+  int t = wv;
+  if (t < tiles) bload(t, b0);
+  if (t + nwv < tiles) bload(t + nwv, b1);
+  while (t < tiles) {
+    tile(t, b0);
+    if (t + 2 * nwv < tiles) bload(t + 2 * nwv, b0);
+    t += nwv;
+    if (t >= tiles) break;
+    tile(t, b1);
+    if (t + 2 * nwv < tiles) bload(t + 2 * nwv, b1);
+    t += nwv;
   }
 }
 
@@ -324,7 +438,7 @@ __global__ void k_eta(int H, int W, int cin, int cin8, int hid, const float* __r
   for (int a = 0; a < hid; ++a) {
     float s = b1[a];
     for (int q = 0; q < 4; ++q) s += W1[a * 4 + q] * d[q];
-    h[a] = tanhf(s);
+    h[a] = tanh_nn(s);
   }
   bf16_t* out = eta + p * cin8;
   for (int c = 0; c < cin8; ++c) {
@@ -332,7 +446,7 @@ __global__ void k_eta(int H, int W, int cin, int cin8, int hid, const float* __r
     if (c < cin) {
       float phi = b2[c];
       for (int a = 0; a < hid; ++a) phi += W2[c * hid + a] * h[a];
-      e = expf(-phi * phi);
+      e = exp_nn(-phi * phi);
     }
     out[c] = f2bf(e);
   }
@@ -532,8 +646,31 @@ static void conv_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta
   k_conv<TN, TAPS, UP><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run);
 }
 
+template <int MT>
+static void conv1x1_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* wp, int Kp, const float* bias,
+                       bf16_t* y, hipStream_t s) {
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv1x1<MT>, 256, 0) != hipSuccess || n < 1) n = 1;
+    per_cu = n;
+  }
+  const int tiles = (g.H * g.W + 15) / 16;
+  const int64_t want = (int64_t)conv_device_cus() * per_cu;
+  const int per_smp = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, want / nb));
+  k_conv1x1<MT><<<dim3(per_smp, nb), 256, 0, s>>>(g, x, wp, Kp, bias, y);
+}
+
 void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
                  int Kp, const float* bias, bf16_t* y, hipStream_t s) {
+  if (taps == 1 && !up && !eta && g.cout <= 128 && Kp <= 128 && g.y_pitch % 8 == 0 && g.y_off % 8 == 0) {
+    // small 1x1 layers: the skinny GEMM, one round of resident workgroups
+    // over all samples
+    if (g.cout <= 32) conv1x1_go<2>(g, nb, x, wp, Kp, bias, y, s);
+    else if (g.cout <= 64) conv1x1_go<4>(g, nb, x, wp, Kp, bias, y, s);
+    else conv1x1_go<8>(g, nb, x, wp, Kp, bias, y, s);
+    return;
+  }
   const bool wide = g.cout >= 64;
   if (taps == 9) {
     if (wide) conv_go<64, 9, false>(g, nb, x, eta, wp, Kp, bias, y, s);

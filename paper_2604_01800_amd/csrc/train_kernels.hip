@@ -427,7 +427,7 @@ __global__ __launch_bounds__(256) void k_eta_multi(int H, int W, int cin, int ci
       const int64_t p = min(p0 + q, npix - 1);
       const int j = (int)(p / W), i = (int)(p - (int64_t)j * W);
       const float d0 = L[i], d1 = L[W + i], d2 = L[3 * W + j], d3 = L[3 * W + H + j];
-      s_h[q][a] = tanhf(b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3);
+      s_h[q][a] = tanh_nn(b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3);
     }
     __syncthreads();
     for (int u = threadIdx.x; u < 32 * cin8; u += 256) {
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(256) void k_eta_multi(int H, int W, int cin, int ci
       if (c < cin) {
         float phi = s_b2[c];
         for (int a = 0; a < hid; ++a) phi += s_w2[a * cin + c] * s_h[q][a];
-        e = expf(-phi * phi);
+        e = exp_nn(-phi * phi);
       }
       out[p * cin8 + c] = f2bf(e);
     }
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
       const int j = p / W, i = p - j * W;
       const float* L = lv + smp * lv_stride;
       const float d0 = L[i], d1 = L[W + i], d2 = L[3 * W + j], d3 = L[3 * W + H + j];
-      s_h[q * HC + a] = tanhf(b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3);
+      s_h[q * HC + a] = tanh_nn(b1[a] + W1[a * 4] * d0 + W1[a * 4 + 1] * d1 + W1[a * 4 + 2] * d2 + W1[a * 4 + 3] * d3);
       if (a == 0) {
         s_d[q * 4] = d0;
         s_d[q * 4 + 1] = d1;
@@ -557,7 +557,7 @@ __global__ __launch_bounds__(256) void k_eta_bwd(int H, int W, int cin, int cin8
             for (int a = 0; a < HC; ++a)
               if (a < hid)
                 phi += (W2REG ? w2r[W2REG ? k : 0][W2REG ? a : 0] : s_w2[a * cinp + c]) * s_h[q * HC + a];
-            const float ef = expf(-phi * phi);
+            const float ef = exp_nn(-phi * phi);
             const float dphi = gv[e] * xv[e] * (-2.f * phi * ef);
             s_dphi[q * cinp + c] = dphi;
             ab2[k] += dphi;
