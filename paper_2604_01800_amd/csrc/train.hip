@@ -464,8 +464,8 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
     };
     // DeepONet contraction, head and trunk
     launch_don_bwd(N * nb, P, Ab + t->o_B, Ab + t->o_T, W + n->o_gamma, gAy, dscale, G + t->g_B, G + t->g_T, part,
-                   kRedBlocks, s);
-    launch_reduce_rows(part, kRedBlocks, 1, 1.f, dG + n->o_gamma, s);
+                   2048, s);
+    launch_reduce_rows(part, 2048, 1, 1.f, dG + n->o_gamma, s);
     wgrad(1, 0, G + t->g_B, P, P, Ab + t->o_d[0], C0, C0, nullptr, n->o_headW);
     bias(0, G + t->g_B, P, P, n->o_headb);
     dgrad(1, 0, G + t->g_B, P, t->pT_head, t->kT_head, C0, G + t->g_d[0]);

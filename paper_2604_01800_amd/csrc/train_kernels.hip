@@ -704,19 +704,37 @@ __global__ __launch_bounds__(256) void k_don_bwd(int64_t n, int P, const bf16_t*
                                                  bf16_t* __restrict__ dT, float* __restrict__ part) {
   __shared__ double lds[kWaves];
   const int l = threadIdx.x & 15;
+  const float gam = gamma[0];
   double acc = 0.0;
-  for (int64_t p = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4); p < n; p += (int64_t)gridDim.x * 16) {
-    const float dy = scale * g[p];
-    const float gd = gamma[0] * dy;
-    float s = 0.f;
-    for (int k = l * 8; k < P; k += 128) {
-      const uint4 b = *(const uint4*)(B + p * P + k), t = *(const uint4*)(T + p * P + k);
-      s += dot8(b, t);
-      *(uint4*)(dB + p * P + k) = scale8(t, gd);
-      *(uint4*)(dT + p * P + k) = scale8(b, gd);
+  // four pixels per pass, their loads issued together; 16 lanes per pixel,
+  // lane l holding basis terms 8l .. 8l+7 (P <= 128: at most one group)
+  const int k = l * 8;
+  const bool kin = k < P;
+  const int64_t step = (int64_t)gridDim.x * 16;
+  for (int64_t p0 = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4); p0 < n; p0 += 4 * step) {
+    uint4 b[4], t[4];
+    float dy[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t p = p0 + u * step;
+      const bool ok = p < n && kin;
+      b[u] = ok ? *(const uint4*)(B + p * P + k) : make_uint4(0, 0, 0, 0);
+      t[u] = ok ? *(const uint4*)(T + p * P + k) : make_uint4(0, 0, 0, 0);
+      dy[u] = p < n ? scale * g[p] : 0.f;
     }
-    const float tot = sum16(s);  // all 16 lanes of the pixel take part
-    if (l == 0) acc += (double)dy * (double)tot;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t p = p0 + u * step;
+      const float tot = sum16(dot8(b[u], t[u]));  // all 16 lanes of the pixel take part
+      if (p < n) {
+        const float gd = gam * dy[u];
+        if (kin) {
+          *(uint4*)(dB + p * P + k) = scale8(t[u], gd);
+          *(uint4*)(dT + p * P + k) = scale8(b[u], gd);
+        }
+        if (l == 0) acc += (double)dy[u] * (double)tot;
+      }
+    }
   }
   acc = block_sum(acc, lds);
   if (threadIdx.x == 0) part[blockIdx.x] = (float)acc;
