@@ -21,6 +21,22 @@ namespace ppe {
 // accumulates 8 x 16 pixel tiles z, z + nsplit, ... of all samples and writes
 // its partial sums in the master layout [co][ci < cin][tap]; k_reduce_rows
 // sums the splits in a fixed order.
+__device__ __forceinline__ void transpose8x8_bf16(const uint4 (&v)[8], uint4 (&w)[8]) {
+  // v[r] holds channels 0..7 of pixel r; w[e] receives pixels 0..7 of channel e
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    uint32_t o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint4 a4 = v[2 * j], b4 = v[2 * j + 1];
+      const uint32_t a = (e / 2 == 0) ? a4.x : (e / 2 == 1) ? a4.y : (e / 2 == 2) ? a4.z : a4.w;
+      const uint32_t b = (e / 2 == 0) ? b4.x : (e / 2 == 1) ? b4.y : (e / 2 == 2) ? b4.z : b4.w;
+      o[j] = (e & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+    }
+    w[e] = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
 template <int TAPS>
 __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restrict__ dp, const bf16_t* __restrict__ x,
                                                const bf16_t* __restrict__ eta, float* __restrict__ part) {
@@ -31,9 +47,12 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
   constexpr int DPP = NP + 8;   // LDS pitch of a transposed dPre row
   constexpr int XPP = TW + 8;   // LDS pitch of a staged input row
   constexpr int CIP = LH * XPP + 8;  // LDS pitch of one input channel's rows (16 lanes in distinct banks)
-  constexpr int NXU = NDX * 4 * LH * TW;   // staged 8-channel input groups per tile
-  constexpr int NUD = NP * 4 / 256, NUX = (NXU + 255) / 256;  // per thread
-  static_assert(NP * 4 == NUD * 256, "dPre staging assumes whole rounds");
+  // staging units of 8 pixels x 8 channels, each loaded with 16-byte loads,
+  // transposed in registers and written as 16-byte LDS rows: dPre (4 channel
+  // groups x 16 pixel octets), then the weighted input (NDX column shifts x 4
+  // channel groups x LH rows x 2 column octets)
+  constexpr int NUD = 4 * (NP / 8), NUXS = NDX * 4 * LH * (TW / 8);
+  constexpr int NUS = NUD + NUXS, RND = (NUS + 255) / 256;
   __shared__ __attribute__((aligned(16))) bf16_t s_dp[32 * DPP];
   __shared__ __attribute__((aligned(16))) bf16_t s_x[NDX * 32 * CIP];
   const int co0 = blockIdx.x * 32, ci0 = blockIdx.y * 32;
@@ -53,77 +72,65 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
     const bf16_t* dps = dp + (int64_t)smp * g.dp_bstride;
     const bf16_t* xs = x + (int64_t)smp * g.x_bstride;
     const bf16_t* es = eta ? eta + (int64_t)smp * g.e_bstride : nullptr;
-    // every load of the tile is issued before the first one is waited for
-    uint4 vd[NUD], vx[NUX], ve[NUX];
+    __syncthreads();  // the previous tile's MFMA loop is done with LDS
 #pragma unroll
-    for (int i = 0; i < NUD; ++i) {
-      const int u = threadIdx.x + 256 * i;  // NP * 4 = NUD * 256
-      const int p = u % NP, cg = u / NP;
-      const int py = py0 + p / TW, px = px0 + p % TW;
-      vd[i] = make_uint4(0, 0, 0, 0);
-      if (py < g.H && px < g.W && co0 + cg * 8 < g.cout)
-        vd[i] = *(const uint4*)(dps + ((int64_t)py * g.W + px) * g.dp_pitch + co0 + cg * 8);
-    }
+    for (int rd = 0; rd < RND; ++rd) {
+      const int u = threadIdx.x + 256 * rd;
+      if (u >= NUS) continue;
+      uint4 v[8], w[8];
+      if (u < NUD) {
+        // dPre: channel group cg of pixels 8 oct .. 8 oct + 7 (one tile row)
+        const int cg = u & 3, oct = u >> 2;
+        const int py = py0 + (oct * 8) / TW, pxb = px0 + (oct * 8) % TW;
+        const bool ok = py < g.H && co0 + cg * 8 < g.cout;
 #pragma unroll
-    for (int i = 0; i < NUX; ++i) {
-      const int u = threadIdx.x + 256 * i;
-      vx[i] = make_uint4(0, 0, 0, 0);
-      ve[i] = make_uint4(0, 0, 0, 0);
-      if (u < NXU) {
-        const int col = u % TW;
-        int r2 = u / TW;
+        for (int r = 0; r < 8; ++r) {
+          v[r] = make_uint4(0, 0, 0, 0);
+          if (ok && pxb + r < g.W)
+            v[r] = *(const uint4*)(dps + ((int64_t)py * g.W + pxb + r) * g.dp_pitch + co0 + cg * 8);
+        }
+        transpose8x8_bf16(v, w);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) *(uint4*)(s_dp + (cg * 8 + e) * DPP + oct * 8) = w[e];
+      } else {
+        // weighted input, column shift dx: s_x[dx][ci][row][col] = Xbar[row - H][col + dx - H]
+        const int q = u - NUD;
+        const int oct = q & 1;
+        int r2 = q >> 1;
         const int row = r2 % LH;
         r2 /= LH;
         const int cg = r2 % 4, dx = r2 / 4;
-        const int gy = py0 + row - HALO, gx = px0 + col + dx - HALO;
-        if (gy >= 0 && gy < g.H && gx >= 0 && gx < g.W && ci0 + cg * 8 < g.cin8) {
-          const int64_t off = ((int64_t)gy * g.W + gx) * g.cin8 + ci0 + cg * 8;
-          vx[i] = *(const uint4*)(xs + off);
-          if (es) ve[i] = *(const uint4*)(es + off);
+        const int gy = py0 + row - HALO, gxb = px0 + oct * 8 + dx - HALO;
+        const bool ok = gy >= 0 && gy < g.H && ci0 + cg * 8 < g.cin8;
+        uint4 ev[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          v[r] = make_uint4(0, 0, 0, 0);
+          ev[r] = make_uint4(0, 0, 0, 0);
+          const int gx = gxb + r;
+          if (ok && gx >= 0 && gx < g.W) {
+            const int64_t off = ((int64_t)gy * g.W + gx) * g.cin8 + ci0 + cg * 8;
+            v[r] = *(const uint4*)(xs + off);
+            if (es) ev[r] = *(const uint4*)(es + off);
+          }
         }
-      }
-    }
-    __syncthreads();
-    // dPre tile, transposed to [co][pixel]
+        if (es) {
 #pragma unroll
-    for (int i = 0; i < NUD; ++i) {
-      const int u = threadIdx.x + 256 * i;
-      const int p = u % NP, cg = u / NP;
-      const uint32_t w4[4] = {vd[i].x, vd[i].y, vd[i].z, vd[i].w};
+          for (int r = 0; r < 8; ++r) {
+            const uint32_t a4[4] = {v[r].x, v[r].y, v[r].z, v[r].w}, b4[4] = {ev[r].x, ev[r].y, ev[r].z, ev[r].w};
+            uint32_t o4[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        s_dp[(cg * 8 + 2 * e) * DPP + p] = (bf16_t)(w4[e] & 0xffff);
-        s_dp[(cg * 8 + 2 * e + 1) * DPP + p] = (bf16_t)(w4[e] >> 16);
-      }
-    }
-    // weighted input tile, one copy per column shift dx: s_x[dx][ci][row][col] = Xbar[row - H][col + dx - H]
-#pragma unroll
-    for (int i = 0; i < NUX; ++i) {
-      const int u = threadIdx.x + 256 * i;
-      if (u >= NXU) continue;
-      const int col = u % TW;
-      int r2 = u / TW;
-      const int row = r2 % LH;
-      r2 /= LH;
-      const int cg = r2 % 4, dx = r2 / 4;
-      uint4 v = vx[i];
-      if (es) {
-        const uint32_t a4[4] = {v.x, v.y, v.z, v.w}, b4[4] = {ve[i].x, ve[i].y, ve[i].z, ve[i].w};
-        uint32_t o4[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float lo = bf2f((bf16_t)(a4[q] & 0xffff)) * bf2f((bf16_t)(b4[q] & 0xffff));
-          const float hi = bf2f((bf16_t)(a4[q] >> 16)) * bf2f((bf16_t)(b4[q] >> 16));
-          o4[q] = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+            for (int k = 0; k < 4; ++k) {
+              const float lo = bf2f((bf16_t)(a4[k] & 0xffff)) * bf2f((bf16_t)(b4[k] & 0xffff));
+              const float hi = bf2f((bf16_t)(a4[k] >> 16)) * bf2f((bf16_t)(b4[k] >> 16));
+              o4[k] = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+            }
+            v[r] = make_uint4(o4[0], o4[1], o4[2], o4[3]);
+          }
         }
-        v = make_uint4(o4[0], o4[1], o4[2], o4[3]);
-      }
-      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-      bf16_t* dst = s_x + (dx * 32 + cg * 8) * CIP + row * XPP + col;
+        transpose8x8_bf16(v, w);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        dst[(2 * e) * CIP] = (bf16_t)(w4[e] & 0xffff);
-        dst[(2 * e + 1) * CIP] = (bf16_t)(w4[e] >> 16);
+        for (int e = 0; e < 8; ++e) *(uint4*)(s_x + (dx * 32 + cg * 8 + e) * CIP + row * XPP + oct * 8) = w[e];
       }
     }
     __syncthreads();
@@ -169,22 +176,6 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
 constexpr int kW1T = 128;          // output and input channels per workgroup
 constexpr int kW1P = 64;           // pixels per stage
 constexpr int kW1PP = kW1P + 8;    // LDS pitch (bf16) of a channel row
-
-__device__ __forceinline__ void transpose8x8_bf16(const uint4 (&v)[8], uint4 (&w)[8]) {
-  // v[r] holds channels 0..7 of pixel r; w[e] receives pixels 0..7 of channel e
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    uint32_t o[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint4 a4 = v[2 * j], b4 = v[2 * j + 1];
-      const uint32_t a = (e / 2 == 0) ? a4.x : (e / 2 == 1) ? a4.y : (e / 2 == 2) ? a4.z : a4.w;
-      const uint32_t b = (e / 2 == 0) ? b4.x : (e / 2 == 1) ? b4.y : (e / 2 == 2) ? b4.z : b4.w;
-      o[j] = (e & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
-    }
-    w[e] = make_uint4(o[0], o[1], o[2], o[3]);
-  }
-}
 
 __global__ __launch_bounds__(256) void k_wgrad1(WgradGeo g, const bf16_t* __restrict__ dp,
                                                 const bf16_t* __restrict__ x, float* __restrict__ part) {
