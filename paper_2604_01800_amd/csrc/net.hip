@@ -289,7 +289,7 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
       c->d_eta = (bf16_t*)dev_alloc(eo * sizeof(bf16_t));
       if (!c->d_eta) return set_error(PPE_ERR_HIP, "allocation of eta maps failed");
     }
-    c->fold_pitch = cfg.base_channels + 1;
+    c->fold_pitch = (cfg.base_channels + 1 + 3) & ~3;  // C0 weights and the constant term, padded to 4 floats
     c->d_fold = (float*)dev_alloc((size_t)p->nx * p->ny * c->fold_pitch * sizeof(float));
     if (!c->d_fold) return set_error(PPE_ERR_HIP, "allocation of the trunk basis failed");
     // activation buffers for nb samples

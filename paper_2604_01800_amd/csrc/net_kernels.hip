@@ -589,25 +589,30 @@ __global__ void k_pool2(int Ho, int Wo, int C, const bf16_t* __restrict__ in, in
 }
 
 // DeepONet output y = gamma * (D0 . fold[p][0:C0] + fold[p][C0]) in FP32.
+// Eight lanes per pixel, lane l taking channels 4l + 32k, so that a pixel's
+// D0 and fold rows are read contiguously (fold rows are padded to a multiple
+// of 4 floats); the eight partial sums are added with lane shuffles.
 __global__ void k_deeponet_out(int64_t npix, int c0, const bf16_t* __restrict__ d0, int64_t d_bs,
                                const float* __restrict__ fold, int fold_pitch, const float* __restrict__ gamma,
                                float* __restrict__ y) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
+  const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int l = threadIdx.x & 7;
   const int smp = blockIdx.y;
-  const bf16_t* d = d0 + smp * d_bs + p * c0;
-  const float* f = fold + p * fold_pitch;
-  float s = f[c0];
-  for (int c = 0; c < c0; c += 8) {
-    const uint4 v = *(const uint4*)(d + c);
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      s += bf2f((bf16_t)(w[q] & 0xffff)) * f[c + 2 * q];
-      s += bf2f((bf16_t)(w[q] >> 16)) * f[c + 2 * q + 1];
+  float s = 0.f;
+  if (p < npix) {
+    const bf16_t* d = d0 + smp * d_bs + p * c0;
+    const float* f = fold + p * fold_pitch;
+    for (int c = 4 * l; c < c0; c += 32) {
+      const uint2 v = *(const uint2*)(d + c);
+      const float4 w = *(const float4*)(f + c);
+      s += bf2f((bf16_t)(v.x & 0xffff)) * w.x + bf2f((bf16_t)(v.x >> 16)) * w.y +
+           bf2f((bf16_t)(v.y & 0xffff)) * w.z + bf2f((bf16_t)(v.y >> 16)) * w.w;
     }
   }
-  y[smp * npix + p] = gamma[0] * s;
+  s += __shfl_xor(s, 4, 8);
+  s += __shfl_xor(s, 2, 8);
+  s += __shfl_xor(s, 1, 8);
+  if (p < npix && l == 0) y[smp * npix + p] = gamma[0] * (s + fold[p * fold_pitch + c0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -733,7 +738,7 @@ void launch_pool2(int Ho, int Wo, int C, const bf16_t* in, int pin, int cin_off,
 
 void launch_deeponet_out(int64_t npix, int c0, const bf16_t* d0, int64_t d_bs, const float* fold, int fold_pitch,
                          const float* gamma, float* y, int nb, hipStream_t s) {
-  k_deeponet_out<<<dim3((unsigned)((npix + 255) / 256), nb), 256, 0, s>>>(npix, c0, d0, d_bs, fold, fold_pitch, gamma,
+  k_deeponet_out<<<dim3((unsigned)((npix * 8 + 255) / 256), nb), 256, 0, s>>>(npix, c0, d0, d_bs, fold, fold_pitch, gamma,
                                                                            y);
 }
 
