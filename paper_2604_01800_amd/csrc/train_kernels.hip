@@ -262,9 +262,20 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ p
   __shared__ double red[8][32];
   const int kk = threadIdx.x & 31, g = threadIdx.x >> 5;
   const int64_t k = (int64_t)blockIdx.x * 32 + kk;
-  double s = 0.0;
-  if (k < len)
-    for (int b = g; b < nparts; b += 8) s += part[(int64_t)b * len + k];
+  // rows g, g + 8, ... in four interleaved partial sums (their loads in
+  // flight together), added in a fixed order
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (k < len) {
+    int b = g;
+    for (; b + 24 < nparts; b += 32) {
+      s0 += part[(int64_t)b * len + k];
+      s1 += part[(int64_t)(b + 8) * len + k];
+      s2 += part[(int64_t)(b + 16) * len + k];
+      s3 += part[(int64_t)(b + 24) * len + k];
+    }
+    for (; b < nparts; b += 8) s0 += part[(int64_t)b * len + k];
+  }
+  const double s = (s0 + s1) + (s2 + s3);
   red[g][kk] = s;
   __syncthreads();
   if (g == 0 && k < len) {
