@@ -53,6 +53,13 @@ constexpr int kH2 = 4;                  // halo depth of a launch (cells)
 constexpr int kOwn2 = kWave - 2 * kH2;  // columns owned by a wavefront
 constexpr int kPre = 16;                // partials per thread loaded ahead (P2 <= 256 in one go)
 
+// The CG pipeline's stores write through the L2 (coherence bits sc0 sc1):
+// r, p and x_c reach memory while the launch runs, instead of in the L2
+// write-back at the kernel boundary that the next launch waits for.
+__device__ __forceinline__ void bstore_wt(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 17);
+}
+
 // Sums of solve s (of nbs solves sharing a.part2) written by launch parity par.
 __device__ __forceinline__ double* sums2_of(const PcgArgs& a, int par, int s, int nbs) {
   return a.part2 + ((size_t)par * nbs + s) * kSums2 * a.P2;
@@ -387,9 +394,9 @@ __device__ __forceinline__ void pcg2_body(const PcgArgs& a, int s, int nbs, int 
         }
         if (q >= kH2 && q < kH2 + R) {
           const uint32_t o = at(own4, row4(j0 - kH2 + q));
-          bstore(rso, o, r2);
-          bstore(pso, o, pk1[q]);
-          bstore(xsr, o, xcv[q - kH2] + falf * pk[q] + falf1 * pk1[q]);
+          bstore_wt(rso, o, r2);
+          bstore_wt(pso, o, pk1[q]);
+          bstore_wt(xsr, o, xcv[q - kH2] + falf * pk[q] + falf1 * pk1[q]);
           const double dr = r2, dz = z2[q], ds = s1, dp = pk1[q], dv = v1[q];
           acc[0] += own ? dr * dz : 0.0;
           acc[2] += own ? dz * ds : 0.0;
