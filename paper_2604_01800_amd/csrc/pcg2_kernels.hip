@@ -60,6 +60,35 @@ __device__ __forceinline__ void bstore_wt(__amdgpu_buffer_rsrc_t r, uint32_t off
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 17);
 }
 
+// Workgroup sums of N values per thread, stored by one thread per sum into
+// part[m][blk] ([N][P]), written through the L2 like the vectors (every
+// workgroup of the next launch reads them first). The values go through LDS
+// (lds: N * kBlock doubles): thread 16m + c adds threads c, c + 16, ...,
+// c + 240 of sum m, and the 16-lane row adds those. Fixed order; needs
+// 16 N <= kBlock.
+template <int N>
+__device__ __forceinline__ void store_sums16(const double (&v)[N], double* lds, double* __restrict__ part, int P,
+                                             int blk) {
+  static_assert(16 * N <= kBlock, "one 16-lane row per sum");
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int m = 0; m < N; ++m) lds[m * kBlock + t] = v[m];
+  __syncthreads();
+  if (t < 16 * N) {
+    const int m = t >> 4, c = t & 15;
+    const double* l = lds + m * kBlock + c;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 16; ++k) s += l[16 * k];
+    s = row_sum16(s);
+    if (c == 0) {
+      const auto pr = make_rsrc(part, (uint64_t)N * P * 8);
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, s), pr, (int)(((uint32_t)m * P + blk) * 8), 0, 17);
+    }
+  }
+}
+
 // Sums of solve s (of nbs solves sharing a.part2) written by launch parity par.
 __device__ __forceinline__ double* sums2_of(const PcgArgs& a, int par, int s, int nbs) {
   return a.part2 + ((size_t)par * nbs + s) * kSums2 * a.P2;

@@ -384,29 +384,6 @@ __device__ __forceinline__ void sums16_finish(const double* __restrict__ part, i
   for (int m = 0; m < N; ++m) out[m] = lds[m];
 }
 
-// Workgroup sums of N values per thread, stored by one thread per sum into
-// part[m][blk] ([N][P]). The values go through LDS (lds: N * kBlock doubles):
-// thread 16m + c adds threads c, c + 16, ..., c + 240 of sum m, and the
-// 16-lane row adds those. Fixed order; needs 16 N <= kBlock.
-template <int N>
-__device__ __forceinline__ void store_sums16(const double (&v)[N], double* lds, double* __restrict__ part, int P,
-                                             int blk) {
-  static_assert(16 * N <= kBlock, "one 16-lane row per sum");
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int m = 0; m < N; ++m) lds[m * kBlock + t] = v[m];
-  __syncthreads();
-  if (t < 16 * N) {
-    const int m = t >> 4, c = t & 15;
-    const double* l = lds + m * kBlock + c;
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < kBlock / 16; ++k) s += l[16 * k];
-    s = row_sum16(s);
-    if (c == 0) part[(size_t)m * P + blk] = s;
-  }
-}
-
 template <typename T>
 __device__ __forceinline__ T diag_of(T hyj, T gs, T gn, T hx, T gw, T ge) {
   return hyj * (gw + ge) + hx * (gs + gn);
