@@ -104,6 +104,32 @@ def hybrid_run(ppe, torch, prob, f, x, args):
             "max_iter": args.hybrid_max_iter}
 
 
+def sequence_run(ppe, torch, g, prob, x, opts, form, rows, args):
+    """Consecutive solves of a travelling source on one grid (the shape of the
+    paper's 20 000-step PPE timings): plain PCG from x0 = 0 and warm-started,
+    and the hybrid solve likewise when a network is given. Prints one JSON line."""
+    from paper_2604_01800_amd import inputs, sequence
+    fs = torch.from_numpy(inputs.travelling_grf(g, 0, args.sequence, shift=args.seq_shift)).cuda()
+    runs = {"pcg_x0_zero": (None, False), "pcg_warm": (None, True)}
+    if args.hybrid:
+        net = ppe.Net(ppe.ppe_net_config_default(), seed=0)
+        ppe.ppe_net_load(net, args.hybrid)
+        runs.update({"hybrid_x0_zero": (net, False), "hybrid_warm": (net, True)})
+    out = {}
+    for name, (net, warm) in runs.items():
+        o = ppe.ppe_solve_opts_default(tol=args.tol, variant=opts.variant, rows_per_wave=opts.rows_per_wave,
+                                       max_iter=args.hybrid_max_iter if net is not None else opts.max_iter)
+        x.zero_()
+        sequence.run(ppe, prob, fs[:1], x, o, net=net, warm=False)  # warm-up (graphs, workspaces)
+        x.zero_()
+        ms, stats, status = sequence.run(ppe, prob, fs, x, o, net=net, warm=warm)
+        out[name] = sequence.summary(ms, stats, status, ppe.PPE_OK)
+    print(json.dumps({"sequence": out, "grid": [g.nx, g.ny], "shift_per_step": args.seq_shift,
+                      "tol": args.tol, "pcg_form": form, "rows_per_wave": rows,
+                      "workload": "travelling GRF source (l = 0.05) on the headline grid, one solve per step"}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +155,11 @@ def main():
     ap.add_argument("--hybrid", default=None, metavar="PATH",
                     help="also time the hybrid solve with the network saved at PATH (default configuration)")
     ap.add_argument("--hybrid-max-iter", type=int, default=30000)
+    ap.add_argument("--sequence", type=int, default=0, metavar="T",
+                    help="time T consecutive solves on the workload's grid instead, the source travelling "
+                         "--seq-shift domain lengths per step (step 0 is the headline source), from x0 = 0 "
+                         "and warm-started from the previous step; with --hybrid also the hybrid solve")
+    ap.add_argument("--seq-shift", type=float, default=0.001)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the phase-kernel timing launches and a 64 MiB calibration copy "
                          "(for hardware-counter runs)")
@@ -193,6 +224,10 @@ def main():
     opts = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, variant=variant, rows_per_wave=rows)
     form = {ppe.PPE_PCG_SINGLE_REDUCTION: "single", ppe.PPE_PCG_TWO_PHASE: "two_phase",
             ppe.PPE_PCG_TWO_STEP: "two_step"}[variant]
+
+    if args.sequence:
+        sequence_run(ppe, torch, g, prob, x, opts, form, rows, args)
+        return
 
     if args.kernels_only:
         ms_a, ms_b = ppe.ppe_profile_pcg(prob, f, x, opts, reps=args.profile_reps)

@@ -142,3 +142,22 @@ def bf16_round(x: np.ndarray) -> np.ndarray:
     u = a.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
     return u.astype(np.uint32).view(np.float32).reshape(a.shape)
+
+
+def travelling_grf(g: Grid, seed: int, steps: int, shift: float = 0.001,
+                   direction=(0.95, 0.31), ell: float = 0.05, J: int = 512) -> np.ndarray:
+    """Source sequence for consecutive solves on one grid, [steps, ny, nx] float32.
+
+    The grf(g, seed) pattern carried along a unit `direction` by `shift` domain
+    lengths per step, as a pressure source does in a flow that advects it
+    between time steps: step t is the same feature sum with every phase phi
+    moved to phi - t * shift * (w . direction), i.e. the step-0 field read at
+    (x, y) - t * shift * direction. Step 0 equals grf(g, seed)."""
+    w, phi, a = grf_features(np.random.default_rng(seed), ell, J)
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    k = w @ d
+    out = np.empty((steps, g.ny, g.nx), dtype=np.float32)
+    for t in range(steps):
+        out[t] = grf_eval(g.xc, g.yc, (w, phi - t * shift * k, a))
+    return out
