@@ -184,6 +184,7 @@ void net_cache_free(NetCache* c) {
   dev_free(c->d_fold);
   dev_free(c->d_act);
   dev_free(c->d_part);
+  dev_free(c->d_kpart);
   delete c;
 }
 
@@ -317,7 +318,10 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
     c->act_elems = ao;
     c->d_act = (bf16_t*)dev_alloc(ao * sizeof(bf16_t));
     c->d_part = (double*)dev_alloc((size_t)kRedBlocks * nb * sizeof(double));
-    if (!c->d_act || !c->d_part) return set_error(PPE_ERR_HIP, "allocation of network activations failed");
+    c->kpart_elems = conv_kpart_elems();
+    c->d_kpart = (float*)dev_alloc((size_t)c->kpart_elems * sizeof(float));
+    if (!c->d_act || !c->d_part || !c->d_kpart)
+      return set_error(PPE_ERR_HIP, "allocation of network activations failed");
     HIPCHK(hipMemsetAsync(c->d_act, 0, ao * sizeof(bf16_t), s));
     // static channels: widths (and the mask at level 0)
     for (int l = 0; l < L; ++l) {
@@ -411,13 +415,13 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
     const MConvL& ma = n->enc_a[l];
     const MConvL& mb = n->enc_b[l];
     launch_conv(9, false, geo(c, l, ma.cin8, ma.cout, ch(l), 0, 1), nb, A + c->o_in[l], eta(c->eta_a[l]),
-                n->d_pack + ma.opack, ma.kp, n->d_w + ma.ob, A + c->o_a[l], s);
+                n->d_pack + ma.opack, ma.kp, n->d_w + ma.ob, A + c->o_a[l], s, c->d_kpart, c->kpart_elems);
     if (l < L - 1) {
       launch_conv(9, false, geo(c, l, mb.cin8, mb.cout, c->p_cat[l], ch(l), 1), nb, A + c->o_a[l], eta(c->eta_b[l]),
-                  n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob, A + c->o_cat[l], s);
+                  n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob, A + c->o_cat[l], s, c->d_kpart, c->kpart_elems);
     } else {
       launch_conv(9, false, geo(c, l, mb.cin8, mb.cout, ch(l), 0, 1), nb, A + c->o_a[l], eta(c->eta_b[l]),
-                  n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob, A + c->o_bot, s);
+                  n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob, A + c->o_bot, s, c->d_kpart, c->kpart_elems);
     }
   }
   for (int l = L - 2; l >= 0; --l) {
@@ -426,13 +430,13 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
     ConvGeo gu = geo(c, l + 1, u.cin, u.cout, c->p_cat[l], 0, 1);
     gu.y_bstride = (int64_t)c->H[l] * c->W[l] * c->p_cat[l];
     gu.act = 0;
-    launch_conv(1, true, gu, nb, src, nullptr, n->d_pack + u.opack, u.kp, n->d_w + u.ob, A + c->o_cat[l], s);
+    launch_conv(1, true, gu, nb, src, nullptr, n->d_pack + u.opack, u.kp, n->d_w + u.ob, A + c->o_cat[l], s, c->d_kpart, c->kpart_elems);
     const MConvL& mc = n->dec_c[l];
     const MConvL& md = n->dec_d[l];
     launch_conv(9, false, geo(c, l, mc.cin8, mc.cout, ch(l), 0, 1), nb, A + c->o_cat[l], eta(c->eta_c[l]),
-                n->d_pack + mc.opack, mc.kp, n->d_w + mc.ob, A + c->o_c[l], s);
+                n->d_pack + mc.opack, mc.kp, n->d_w + mc.ob, A + c->o_c[l], s, c->d_kpart, c->kpart_elems);
     launch_conv(9, false, geo(c, l, md.cin8, md.cout, ch(l), 0, 1), nb, A + c->o_c[l], eta(c->eta_d[l]),
-                n->d_pack + md.opack, md.kp, n->d_w + md.ob, A + c->o_d[l], s);
+                n->d_pack + md.opack, md.kp, n->d_w + md.ob, A + c->o_d[l], s, c->d_kpart, c->kpart_elems);
   }
   launch_deeponet_out(N, cfg.base_channels, A + c->o_d[0], N * cfg.base_channels, c->d_fold, c->fold_pitch,
                       n->d_w + n->o_gamma, y, nb, s);

@@ -60,6 +60,8 @@ struct NetCache {
   int64_t o_in[kMaxLevels] = {}, o_a[kMaxLevels] = {}, o_cat[kMaxLevels] = {}, o_c[kMaxLevels] = {},
           o_d[kMaxLevels] = {}, o_bot = 0;
   double* d_part = nullptr;
+  float* d_kpart = nullptr;  // partial sums of convolutions with a split K loop
+  int64_t kpart_elems = 0;
 };
 
 void net_cache_free(NetCache* c);

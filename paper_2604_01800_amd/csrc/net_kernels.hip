@@ -174,7 +174,8 @@ template <int TN, int TAPS, bool UP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv(
     ConvGeo g, const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta,
                                               const bf16_t* __restrict__ wp, int Kp, const float* __restrict__ bias,
-                                              bf16_t* __restrict__ y, int tiles_per_wg) {
+                                              bf16_t* __restrict__ y, int tiles_per_wg,
+                                              float* __restrict__ kpart, int ksplit) {
   using S = ConvShape<TN, TAPS>;
   constexpr int MT = TN / 16, NT = 4;
   __shared__ __attribute__((aligned(16))) bf16_t s_x[S::NPIX * S::CKP];
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int t0 = blockIdx.x * tiles_per_wg;
   const int nt_wg = min(tiles_per_wg, tiles - t0);
   const int co0 = blockIdx.y * TN;
-  const int smp = blockIdx.z;
+  const int smp = blockIdx.z / ksplit, ksp = blockIdx.z - smp * ksplit;
   x += smp * g.x_bstride;
   y += smp * g.y_bstride;
   if (eta) eta += smp * g.e_bstride;
@@ -197,7 +198,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(x), (short)0, in_bytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t er =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(eta ? eta : x), (short)0, in_bytes, 0x00020000);
-  const int nch = (g.cin8 + S::CK - 1) / S::CK;
+  // input-channel chunks of this workgroup: all of them, or its share when
+  // the K loop is split over ksplit workgroups
+  const int nch_all = (g.cin8 + S::CK - 1) / S::CK;
+  const int cps = (nch_all + ksplit - 1) / ksplit;
+  const int c_lo = ksp * cps;
+  const int nch = min(cps, nch_all - c_lo);
   const int items = nt_wg * nch;
 
   f32x4_t acc[MT][NT];
@@ -208,13 +214,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
   ConvStage<TN, TAPS> stg;
   auto issue = [&](int it) {
-    const int t = t0 + it / nch, c = it - (it / nch) * nch;
+    const int t = t0 + it / nch, c = c_lo + it - (it / nch) * nch;
     const int py0 = (t / tiles_x) * kCTH, px0 = (t % tiles_x) * kCTW;
     conv_issue<TN, TAPS>(stg, g, xr, er, eta != nullptr, wr, Kp, co0, py0, px0, c * S::CK,
                          min(S::CK, g.cin8 - c * S::CK) / 8, c * S::SMAX * 32);
   };
   for (int it = 0; it < items; ++it) {
-    const int t = t0 + it / nch, c = it - (it / nch) * nch;
+    const int t = t0 + it / nch, c = c_lo + it - (it / nch) * nch;
     const int c0 = c * S::CK;
     const int ck8 = min(S::CK, g.cin8 - c0) / 8;
     issue(it);        // in flight while the other waves finish the previous item
@@ -226,10 +232,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       conv_mfma<TN, TAPS, S::G8>(acc, s_x, s_w, ck8, lane, wv);
     else
       conv_mfma<TN, TAPS, 0>(acc, s_x, s_w, ck8, lane, wv);
-    if (c + 1 < nch) continue;
+    if (c + 1 < c_lo + nch) continue;
 
     // Epilogue of tile t: lane holds out[co0 + mt*16 + 4*(lane>>4) + j][pixel (row NT*w+nt, col lane&15)].
     const int py0 = (t / tiles_x) * kCTH, px0 = (t % tiles_x) * kCTW;
+    if (ksplit > 1) {
+      // partial sums of this share of K, [ksplit][sample][pixel][gridDim.y * TN] FP32
+      const int cp = gridDim.y * TN;
+      const int nbs = gridDim.z / ksplit;  // samples
+      float* pp = kpart + ((int64_t)ksp * nbs + smp) * g.H * g.W * cp;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int co = co0 + mt * 16 + 4 * (lane >> 4);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int py = py0 + NT * wv + nt, px = px0 + (lane & 15);
+          if (co < g.cout && py < g.H && px < g.W)
+            *(f32x4_t*)(pp + ((int64_t)py * g.W + px) * cp + co) = acc[mt][nt];
+          acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int co = co0 + mt * 16 + 4 * (lane >> 4);
@@ -270,6 +294,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     }
+  }
+}
+
+// Sum of the K-split partials of a convolution, in a fixed order, then bias,
+// activation and the BF16 store of the unsplit epilogue (UP: to the 2 x 2
+// finer pixels). One thread per (pixel, 4 output channels); cp = channel pitch
+// of the partials.
+template <bool UP>
+__global__ __launch_bounds__(256) void k_conv_ksum(ConvGeo g, int nb, int ksplit, int cp,
+                                                   const float* __restrict__ kpart, const float* __restrict__ bias,
+                                                   bf16_t* __restrict__ y) {
+  const int q4 = g.cout / 4;
+  const int64_t hw = (int64_t)g.H * g.W;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int smp = blockIdx.y;
+  if (i >= hw * q4) return;
+  const int64_t p = i / q4;
+  const int co = (int)(i - p * q4) * 4;
+  const int64_t kstride = (int64_t)nb * hw * cp;
+  const float* src = kpart + ((int64_t)smp * hw + p) * cp + co;
+  f32x4_t a = *(const f32x4_t*)src;
+  for (int k = 1; k < ksplit; ++k) {
+    const f32x4_t b = *(const f32x4_t*)(src + k * kstride);
+    a[0] += b[0];
+    a[1] += b[1];
+    a[2] += b[2];
+    a[3] += b[3];
+  }
+  float v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float t = a[j] + (bias ? bias[co + j] : 0.f);
+    if (g.act == 1) t = fmaxf(t, 0.f);
+    else if (g.act == 2) t = tanh_nn(t);
+    v[j] = t;
+  }
+  const uint2 packed = make_uint2((uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                                  (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16));
+  y += smp * g.y_bstride;
+  const int py = (int)(p / g.W), px = (int)(p - (int64_t)py * g.W);
+  if (!UP) {
+    *(uint2*)(y + p * g.y_pitch + g.y_off + co) = packed;
+  } else {
+    const int W2 = 2 * g.W;
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+      for (int b2 = 0; b2 < 2; ++b2)
+        *(uint2*)(y + ((size_t)(2 * py + a2) * W2 + 2 * px + b2) * g.y_pitch + g.y_off + co) = packed;
   }
 }
 
@@ -631,9 +704,14 @@ static int conv_device_cus() {
   return cus;
 }
 
+// Room for the partial sums of any split layer: a layer splits only with
+// tiles * cot * nb < cus workgroups, into ks <= ceil(cus / (tiles * cot * nb))
+// shares, so ks * nb * pixels * channel pitch < 2 * cus * 256 * 64.
+int64_t conv_kpart_elems() { return (int64_t)2 * conv_device_cus() * kCTH * kCTW * 64; }
+
 template <int TN, int TAPS, bool UP>
 static void conv_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp, int Kp,
-                    const float* bias, bf16_t* y, hipStream_t s) {
+                    const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems) {
   const int tiles = ((g.W + kCTW - 1) / kCTW) * ((g.H + kCTH - 1) / kCTH);
   const int cot = (g.cout + TN - 1) / TN;
   // resident workgroups per CU (registers and LDS), and runs of tiles that
@@ -644,11 +722,27 @@ static void conv_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv<TN, TAPS, UP>, 256, 0) != hipSuccess || n < 1) n = 1;
     per_cu = n;
   }
-  const int64_t slots = (int64_t)conv_device_cus() * per_cu;
+  const int cus = conv_device_cus();
+  const int64_t slots = (int64_t)cus * per_cu;
   const int64_t wgs = (int64_t)tiles * cot * nb;
   const int run = (int)std::max<int64_t>(1, (wgs + slots - 1) / slots);
-  const dim3 grid((tiles + run - 1) / run, cot, nb);
-  k_conv<TN, TAPS, UP><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run);
+  // Layers with fewer workgroups than compute units (the coarse levels of
+  // small grids) split their chunks of input channels over up to
+  // ceil(cus / wgs) workgroups, when the caller gave room for the partials.
+  const int nch = (g.cin8 + ConvShape<TN, TAPS>::CK - 1) / ConvShape<TN, TAPS>::CK;
+  int ks = 1;
+  if (kpart && wgs < cus && nch > 1 && g.cout % 4 == 0) {
+    ks = (int)std::min<int64_t>(nch, (cus + wgs - 1) / wgs);
+    const int cps = (nch + ks - 1) / ks;
+    ks = (nch + cps - 1) / cps;  // no empty shares
+    if ((int64_t)ks * nb * g.H * g.W * cot * TN > kpart_elems) ks = 1;
+  }
+  const dim3 grid((tiles + run - 1) / run, cot, nb * ks);
+  k_conv<TN, TAPS, UP><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks);
+  if (ks > 1) {
+    const int64_t n = (int64_t)g.H * g.W * (g.cout / 4);
+    k_conv_ksum<UP><<<dim3((unsigned)((n + 255) / 256), nb), 256, 0, s>>>(g, nb, ks, cot * TN, kpart, bias, y);
+  }
 }
 
 template <int MT>
@@ -667,7 +761,7 @@ static void conv1x1_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* 
 }
 
 void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
-                 int Kp, const float* bias, bf16_t* y, hipStream_t s) {
+                 int Kp, const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems) {
   if (taps == 1 && !up && !eta && g.cout <= 128 && Kp <= 128 && g.y_pitch % 8 == 0 && g.y_off % 8 == 0) {
     // small 1x1 layers: the skinny GEMM, one round of resident workgroups
     // over all samples
@@ -678,14 +772,14 @@ void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, c
   }
   const bool wide = g.cout >= 64;
   if (taps == 9) {
-    if (wide) conv_go<64, 9, false>(g, nb, x, eta, wp, Kp, bias, y, s);
-    else conv_go<32, 9, false>(g, nb, x, eta, wp, Kp, bias, y, s);
+    if (wide) conv_go<64, 9, false>(g, nb, x, eta, wp, Kp, bias, y, s, kpart, kpart_elems);
+    else conv_go<32, 9, false>(g, nb, x, eta, wp, Kp, bias, y, s, kpart, kpart_elems);
   } else if (up) {
-    if (wide) conv_go<64, 1, true>(g, nb, x, eta, wp, Kp, bias, y, s);
-    else conv_go<32, 1, true>(g, nb, x, eta, wp, Kp, bias, y, s);
+    if (wide) conv_go<64, 1, true>(g, nb, x, eta, wp, Kp, bias, y, s, kpart, kpart_elems);
+    else conv_go<32, 1, true>(g, nb, x, eta, wp, Kp, bias, y, s, kpart, kpart_elems);
   } else {
-    if (wide) conv_go<64, 1, false>(g, nb, x, eta, wp, Kp, bias, y, s);
-    else conv_go<32, 1, false>(g, nb, x, eta, wp, Kp, bias, y, s);
+    if (wide) conv_go<64, 1, false>(g, nb, x, eta, wp, Kp, bias, y, s, kpart, kpart_elems);
+    else conv_go<32, 1, false>(g, nb, x, eta, wp, Kp, bias, y, s, kpart, kpart_elems);
   }
 }
 

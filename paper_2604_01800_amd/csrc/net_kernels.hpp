@@ -13,8 +13,13 @@ struct TrunkDesc {
   int64_t oWh, obh;      // branch head (folded into the basis)
 };
 
+// Floats of partial-sum room that lets every small layer split its K loop.
+int64_t conv_kpart_elems();
+// kpart (optional, kpart_elems floats): room for FP32 partial sums, which lets
+// layers with fewer workgroups than compute units split their K loop.
 void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
-                 int Kp, const float* bias, bf16_t* y, hipStream_t s);
+                 int Kp, const float* bias, bf16_t* y, hipStream_t s, float* kpart = nullptr,
+                 int64_t kpart_elems = 0);
 void launch_pack_weights(const float* w, int cout, int cin, int cin8, int taps, int Kp, bf16_t* out, hipStream_t s);
 // Input-gradient operator: rows = input channels (padded), K over cout_fwd.
 void launch_pack_weights_t(const float* w, int cout_fwd, int cin_fwd, int rows, int taps, int Kp, bf16_t* out,
