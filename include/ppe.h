@@ -191,9 +191,14 @@ ppe_status ppe_solve_plain(ppe_problem* p, int32_t nb, const float* f, double* x
  * problems: host array of n distinct problems; f: host array of n device
  * FP32 sources [ny_i][nx_i]; x: host array of n device FP64 solutions
  * (in: initial guess, out: zero-mean solution); stats: host [n] or NULL,
- * with ms_device the solve's own time to its convergence decision. net must
- * be NULL (hybrid batches over mixed sizes are not built:
- * PPE_ERR_UNSUPPORTED). Statuses as for ppe_solve_plain. */
+ * with ms_device the solve's own time to its convergence decision.
+ * net: NULL for the plain solves above. Otherwise each system gets the hybrid
+ * solve of ppe_solve_hybrid (Sec. 2.2, with opts->direction, num_cg and
+ * num_dlsm checked as there; the network must fit every grid when the
+ * direction is PPE_DIR_NET). The solves' rounds advance in lock step on
+ * stream s, one replay of every undecided solve per step, and each solve is
+ * bit-identical to the same ppe_solve_hybrid call alone. The network is only
+ * read. Statuses as for ppe_solve_plain. */
 ppe_status ppe_solve_batch(int32_t n, ppe_problem* const* problems, const ppe_net* net, const float* const* f,
                            double* const* x, const ppe_solve_opts* opts, ppe_solve_stats* stats, hipStream_t s);
 

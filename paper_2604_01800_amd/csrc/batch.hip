@@ -12,6 +12,7 @@
 #include <cstring>
 
 #include "api_internal.hpp"
+#include "net_internal.hpp"
 
 namespace ppe {
 
@@ -126,7 +127,6 @@ extern "C" ppe_status ppe_solve_batch(int32_t n, ppe_problem* const* problems, c
   if (n == 0) return PPE_OK;
   if (n > 4096) return set_error(PPE_ERR_INVALID_ARG, "n > 4096");
   if (!problems || !f || !x) return set_error(PPE_ERR_INVALID_ARG, "problems, f or x is NULL");
-  if (net) return set_error(PPE_ERR_UNSUPPORTED, "hybrid solves of a mixed-size batch are not built");
   ppe_solve_opts o;
   ppe_solve_opts_default(&o);
   if (opts) o = *opts;
@@ -140,6 +140,23 @@ extern "C" ppe_status ppe_solve_batch(int32_t n, ppe_problem* const* problems, c
     for (int k = 0; k < i; ++k)
       if (problems[k] == problems[i]) return set_error(PPE_ERR_INVALID_ARG, "problem %d appears twice", i);
     cells += (int64_t)problems[i]->nx * problems[i]->ny;
+  }
+  if (net) {
+    // hybrid rounds (the two-phase CG form, as in ppe_solve_hybrid)
+    if (o.num_cg < 0 || o.num_dlsm < 0 || o.num_cg + o.num_dlsm < 1 || o.num_cg > 64 || o.num_dlsm > 64)
+      return set_error(PPE_ERR_INVALID_ARG, "num_cg, num_dlsm must lie in [0, 64] with a positive sum");
+    if (o.direction < PPE_DIR_NET || o.direction > PPE_DIR_ONES)
+      return set_error(PPE_ERR_INVALID_ARG, "unknown direction %d", o.direction);
+    if (o.direction == PPE_DIR_NET)
+      for (int i = 0; i < n; ++i) {
+        ppe_status st = check_net_grid(problems[i], net);
+        if (st != PPE_OK) {
+          const std::string msg = ppe_last_error();
+          return set_error(st, "solve %d: %s", i, msg.c_str());
+        }
+      }
+    // the forward reads the network's parameters and writes only per-problem buffers
+    return solve_hybrid_batch_impl(n, problems, const_cast<ppe_net*>(net), f, x, o, stats, s);
   }
   if (o.variant == PPE_PCG_TWO_PHASE)
     return set_error(PPE_ERR_UNSUPPORTED, "the mixed-size batch runs the two-step or single-reduction form");

@@ -6,8 +6,10 @@
 // convergence is judged.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <vector>
 
 #include "api_internal.hpp"
 #include "net_internal.hpp"
@@ -47,9 +49,25 @@ static ppe_status enqueue_rounds(ppe_problem* p, ppe_net* net, const PcgArgs& a,
   return PPE_OK;
 }
 
-ppe_status solve_hybrid_impl(ppe_problem* p, ppe_net* net, int32_t nb, const float* f, double* x,
-                             const ppe_solve_opts& o, ppe_solve_stats* stats, hipStream_t s) {
-  const auto t0 = std::chrono::steady_clock::now();
+// One hybrid solve (of nb right-hand sides on one problem) in progress: its
+// arguments and the graph of one replay unit.
+struct HybridRun {
+  ppe_problem* p = nullptr;
+  int nb = 0;
+  PcgArgs a{};
+  hipGraphExec_t exec = nullptr;
+  int per = 1;               // rounds per replay unit
+  int64_t max_units = 0;
+  bool done = false;         // every solve of the run has reached a decision
+  bool pending = false;      // a unit's flags are in flight
+};
+
+// Setup of a run on stream s: workspace, network constants, call arguments,
+// the first true residual, and the capture of one replay unit.
+static ppe_status hybrid_begin(HybridRun& h, ppe_problem* p, ppe_net* net, int32_t nb, const float* f, double* x,
+                               const ppe_solve_opts& o, hipStream_t s) {
+  h.p = p;
+  h.nb = nb;
   ppe_status st = ensure_ws(p, nb);
   if (st != PPE_OK) return st;
   if (o.direction == PPE_DIR_NET) {
@@ -57,56 +75,133 @@ ppe_status solve_hybrid_impl(ppe_problem* p, ppe_net* net, int32_t nb, const flo
     if (st != PPE_OK) return st;
   }
   const int R = rows_of(p, nb, o);
-  const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  h.a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
   // The reliable update closing every round replaces the delta trigger.
   launch_set_call(p->ws.call, f, x, o.max_iter, 0.0, s);
-  launch_pcg_setup(a, nb, s);
+  launch_pcg_setup(h.a, nb, s);
   HIPCHK(hipGetLastError());
   // Rounds per replayed unit: the parity must return to 0 at its end.
-  const int per = ((o.num_cg + 1) % 2) ? 2 : 1;
-  SolveWs& w = p->ws;
-  hipGraphExec_t exec = nullptr;
+  h.per = ((o.num_cg + 1) % 2) ? 2 : 1;
   if (o.use_graph) {
     if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-    st = enqueue_rounds(p, net, a, nb, o, per, p->cap_stream);
+    st = enqueue_rounds(p, net, h.a, nb, o, h.per, p->cap_stream);
     hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
     if (st != PPE_OK) {
       if (graph) (void)hipGraphDestroy(graph);
       return st;
     }
     if (e != hipSuccess) return set_error(PPE_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&h.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return set_error(PPE_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
-  }
-  const int iters_per_unit = per * (o.num_cg + o.num_dlsm);
-  const int64_t max_units = (int64_t)o.max_iter / (iters_per_unit > 0 ? iters_per_unit : 1) + 3;
-  for (int64_t c = 0; c < max_units; ++c) {
-    if (exec) {
-      HIPCHK(hipGraphLaunch(exec, s));
-    } else {
-      st = enqueue_rounds(p, net, a, nb, o, per, s);
-      if (st != PPE_OK) return st;
-    }
-    HIPCHK(hipMemcpyAsync(w.h_flags + (c & 1) * nb, w.flags, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipEventRecord(w.ev[c & 1], s));
-    if (c >= 1) {
-      HIPCHK(hipEventSynchronize(w.ev[(c - 1) & 1]));
-      const int32_t* fl = w.h_flags + ((c - 1) & 1) * nb;
-      bool all = true;
-      for (int i = 0; i < nb; ++i) all = all && fl[i] != DONE_NO;
-      if (all) break;
+    if (e != hipSuccess) {
+      h.exec = nullptr;
+      return set_error(PPE_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
     }
   }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  launch_pcg_finish(a, nb, s);
+  const int iters_per_unit = h.per * (o.num_cg + o.num_dlsm);
+  h.max_units = (int64_t)o.max_iter / (iters_per_unit > 0 ? iters_per_unit : 1) + 3;
+  return PPE_OK;
+}
+
+// Enqueues unit c of a run, then the copy of its done flags to the host and
+// an event behind them (double-buffered by the parity of c).
+static ppe_status hybrid_unit(HybridRun& h, ppe_net* net, const ppe_solve_opts& o, int64_t c, hipStream_t s) {
+  SolveWs& w = h.p->ws;
+  if (h.exec) {
+    HIPCHK(hipGraphLaunch(h.exec, s));
+  } else {
+    ppe_status st = enqueue_rounds(h.p, net, h.a, h.nb, o, h.per, s);
+    if (st != PPE_OK) return st;
+  }
+  HIPCHK(hipMemcpyAsync(w.h_flags + (c & 1) * h.nb, w.flags, sizeof(int32_t) * h.nb, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(w.ev[c & 1], s));
+  h.pending = true;
+  return PPE_OK;
+}
+
+// Waits for the flags of unit c and records whether every solve has decided.
+static ppe_status hybrid_check(HybridRun& h, int64_t c) {
+  SolveWs& w = h.p->ws;
+  HIPCHK(hipEventSynchronize(w.ev[c & 1]));
+  const int32_t* fl = w.h_flags + (c & 1) * h.nb;
+  bool all = true;
+  for (int i = 0; i < h.nb; ++i) all = all && fl[i] != DONE_NO;
+  h.done = all;
+  return PPE_OK;
+}
+
+static void hybrid_release(HybridRun& h) {
+  if (h.exec) (void)hipGraphExecDestroy(h.exec);
+  h.exec = nullptr;
+}
+
+ppe_status solve_hybrid_impl(ppe_problem* p, ppe_net* net, int32_t nb, const float* f, double* x,
+                             const ppe_solve_opts& o, ppe_solve_stats* stats, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  HybridRun h;
+  ppe_status st = hybrid_begin(h, p, net, nb, f, x, o, s);
+  if (st != PPE_OK) {
+    hybrid_release(h);
+    return st;
+  }
+  for (int64_t c = 0; c < h.max_units && st == PPE_OK; ++c) {
+    st = hybrid_unit(h, net, o, c, s);
+    if (st == PPE_OK && c >= 1) st = hybrid_check(h, c - 1);
+    if (h.done) break;
+  }
+  hybrid_release(h);
+  if (st != PPE_OK) return st;
+  launch_pcg_finish(h.a, nb, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   const double ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return fill_stats(p, nb, stats, ms, s, true);
+}
+
+// Hybrid solves of a mixed-size batch: one run per problem, advanced in lock
+// step on one stream. Each unit of a round enqueues the next replay of every
+// run that has not yet decided, so the runs' rounds interleave; a run leaves
+// the rotation once its flags show that its solve has decided.
+ppe_status solve_hybrid_batch_impl(int32_t n, ppe_problem* const* problems, ppe_net* net, const float* const* f,
+                                   double* const* x, const ppe_solve_opts& o, ppe_solve_stats* stats,
+                                   hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<HybridRun> runs(n);
+  ppe_status st = PPE_OK;
+  for (int i = 0; i < n && st == PPE_OK; ++i) st = hybrid_begin(runs[i], problems[i], net, 1, f[i], x[i], o, s);
+  int64_t max_units = 0;
+  for (const HybridRun& h : runs) max_units = std::max(max_units, h.max_units);
+  for (int64_t c = 0; c < max_units && st == PPE_OK; ++c) {
+    bool any = false;
+    for (HybridRun& h : runs) {
+      if (h.done || c >= h.max_units) continue;
+      st = hybrid_unit(h, net, o, c, s);
+      if (st != PPE_OK) break;
+      any = true;
+    }
+    if (st != PPE_OK || !any) break;
+    if (c >= 1)
+      for (HybridRun& h : runs)
+        if (!h.done && c - 1 < h.max_units && st == PPE_OK) st = hybrid_check(h, c - 1);
+  }
+  for (HybridRun& h : runs) hybrid_release(h);
+  if (st != PPE_OK) return st;
+  for (const HybridRun& h : runs) launch_pcg_finish(h.a, 1, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  ppe_status worst = PPE_OK;
+  for (int i = 0; i < n; ++i) {
+    st = fill_stats(problems[i], 1, stats ? stats + i : nullptr, ms, s, true);
+    if (st == PPE_ERR_NONFINITE) worst = st;
+    else if (st == PPE_NOT_CONVERGED && worst == PPE_OK) worst = st;
+    else if (st < 0 && st != PPE_ERR_NONFINITE) return st;
+  }
+  if (worst == PPE_ERR_NONFINITE) set_error(worst, "non-finite value in a source field or iteration");
+  return worst;
 }
 
 }  // namespace ppe

@@ -69,6 +69,11 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s);
 ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float* y, hipStream_t s);
 ppe_status net_refresh(ppe_net* n, hipStream_t s);
 ppe_status check_net_grid(const ppe_problem* p, const ppe_net* n);
+// Hybrid solves of a mixed-size batch (one solve per problem, problems
+// distinct), advanced round by round in lock step on stream s.
+ppe_status solve_hybrid_batch_impl(int32_t n, ppe_problem* const* problems, ppe_net* net, const float* const* f,
+                                   double* const* x, const ppe_solve_opts& o, ppe_solve_stats* stats,
+                                   hipStream_t s);
 void net_train_free(ppe_net* n);
 void grid_block(const ppe_problem* p, int L, std::vector<float>& lv, int64_t* lv_off, int64_t* tin_off);
 

@@ -363,9 +363,10 @@ def ppe_train_opts_default(**kw) -> ppe_train_opts:
     return o
 
 
-def ppe_solve_batch(probs, fs, xs, opts=None, stream=None):
-    """Plain solves of one right-hand side on each of len(probs) grids of any
-    sizes, batched per iteration. fs[i]: device float32 [ny_i, nx_i] (or
+def ppe_solve_batch(probs, fs, xs, opts=None, stream=None, net=None):
+    """Solves of one right-hand side on each of len(probs) grids of any sizes:
+    plain PCG batched per iteration, or with a network the hybrid solve, its
+    rounds advanced in lock step. fs[i]: device float32 [ny_i, nx_i] (or
     [1, ny_i, nx_i]); xs[i]: device float64 of the same shape. Returns
     (status, list of stats dicts)."""
     import torch
@@ -381,7 +382,8 @@ def ppe_solve_batch(probs, fs, xs, opts=None, stream=None):
     xarr = (ctypes.c_void_p * n)(*[_dev(x, torch.float64, "x") for x in xs])
     opts = opts or ppe_solve_opts_default()
     stats = (ppe_solve_stats * n)()
-    st = lib().ppe_solve_batch(n, ctypes.cast(parr, ctypes.c_void_p), None, ctypes.cast(farr, ctypes.c_void_p),
+    st = lib().ppe_solve_batch(n, ctypes.cast(parr, ctypes.c_void_p), net.handle if net is not None else None,
+                               ctypes.cast(farr, ctypes.c_void_p),
                                ctypes.cast(xarr, ctypes.c_void_p), ctypes.byref(opts),
                                ctypes.cast(stats, ctypes.c_void_p), _stream(stream))
     _check(st, allow=(PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))

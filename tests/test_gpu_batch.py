@@ -3,9 +3,8 @@ work list of all grids) against single solves and the oracle: every solve of
 the batch is bit-identical to the same solve alone (same iteration form and
 tile height: identical arithmetic and reduction order), reaches the tolerance
 on the FP64 true residual the oracle recomputes, and keeps its own status and
-timing."""
-import ctypes
-
+timing. With a network the batch runs hybrid solves, each bit-identical to
+the same hybrid solve alone."""
 import numpy as np
 import pytest
 import torch
@@ -114,12 +113,65 @@ def test_batch_argument_checks(ppe):
         ppe.ppe_solve_batch([p], [f[:16]], [x])
     with pytest.raises(ppe.PPEError):  # the two-phase form is not batched over mixed sizes
         ppe.ppe_solve_batch([p], [f], [x], ppe.ppe_solve_opts_default(variant=ppe.PPE_PCG_TWO_PHASE))
-    # a network is rejected before anything runs
-    arr = (ctypes.c_void_p * 1)(p.handle.value)
-    fa = (ctypes.c_void_p * 1)(f.data_ptr())
-    xa = (ctypes.c_void_p * 1)(x.data_ptr())
-    st = ppe.lib().ppe_solve_batch(1, ctypes.cast(arr, ctypes.c_void_p), ctypes.c_void_p(8),
-                                   ctypes.cast(fa, ctypes.c_void_p), ctypes.cast(xa, ctypes.c_void_p), None, None,
-                                   None)
-    assert st == ppe.PPE_ERR_UNSUPPORTED
     assert ppe.lib().ppe_solve_batch(0, None, None, None, None, None, None, None) == ppe.PPE_OK
+
+
+# Hybrid solves of a mixed-size batch: the rounds of every solve advance in
+# lock step, and each solve is bit-identical to the same hybrid solve alone
+# (same kernels, arguments and order on its own buffers).
+HYB_SHAPES = [(64, 64), (128, 72), (40, 96), (32, 32)]  # multiples of 8 for the 4-level network
+
+
+def _single_hybrid(ppe, p, net, f, **kw):
+    fd = torch.from_numpy(f[None]).cuda()
+    xd = torch.zeros((1,) + f.shape, dtype=torch.float64, device="cuda")
+    st, s = ppe.ppe_solve_hybrid(p, net, fd, xd, ppe.ppe_solve_opts_default(**kw))
+    return st, s[0], xd[0].cpu().numpy()
+
+
+@pytest.mark.parametrize("direction,tol,max_iter", [(2, 1e-6, 20000), (0, 0.0, 23), (0, 0.0, 40)],
+                         ids=["jacobi_to_tol", "net_23_iters", "net_40_iters"])
+def test_hybrid_mixed_batch_equals_single_solves(ppe, direction, tol, max_iter):
+    sys_ = systems(HYB_SHAPES, seed=4)
+    net = ppe.Net(ppe.ppe_net_config_default(), seed=3)
+    probs = [ppe.ppe_problem_create(g) for g, _ in sys_]
+    fs = [torch.from_numpy(f).cuda() for _, f in sys_]
+    xs = [torch.zeros(f.shape, dtype=torch.float64, device="cuda") for _, f in sys_]
+    kw = dict(tol=tol, max_iter=max_iter, direction=direction)
+    st, stats = ppe.ppe_solve_batch(probs, fs, xs, ppe.ppe_solve_opts_default(**kw), net=net)
+    assert st == (ppe.PPE_OK if tol > 0 else ppe.PPE_NOT_CONVERGED)
+    for (g, f), x, s, p in zip(sys_, xs, stats, probs):
+        st1, s1, x1 = _single_hybrid(ppe, p, net, f, **kw)
+        np.testing.assert_array_equal(x.cpu().numpy(), x1)
+        for k in ("status", "iters_total", "iters_cg", "iters_dlsm", "dlsm_rejected", "reliable_updates"):
+            assert s[k] == s1[k], (k, s, s1)
+        if tol > 0:
+            assert s["status"] == ppe.PPE_OK
+            assert true_res(g, f, x.cpu().numpy()) <= tol * 1.001
+        else:
+            assert s["iters_total"] == max_iter and s["iters_dlsm"] > 0
+
+
+def test_hybrid_batch_statuses_and_checks(ppe):
+    sys_ = systems(HYB_SHAPES[:3], seed=6)
+    net = ppe.Net(ppe.ppe_net_config_default(), seed=3)
+    probs = [ppe.ppe_problem_create(g) for g, _ in sys_]
+    fs = [torch.from_numpy(f).cuda() for _, f in sys_]
+    fs[1][3, 5] = float("nan")
+    xs = [torch.zeros(f.shape, dtype=torch.float64, device="cuda") for _, f in sys_]
+    o = ppe.ppe_solve_opts_default(tol=1e-6, max_iter=20000, direction=ppe.PPE_DIR_JACOBI)
+    st, stats = ppe.ppe_solve_batch(probs, fs, xs, o, net=net)
+    assert st == ppe.PPE_ERR_NONFINITE
+    assert [s["status"] for s in stats] == [ppe.PPE_OK, ppe.PPE_ERR_NONFINITE, ppe.PPE_OK]
+    for (g, f), x, s in zip(sys_, xs, stats):
+        if s["status"] == ppe.PPE_OK:
+            assert true_res(g, f, x.cpu().numpy()) <= 1e-6 * 1.001
+    # a grid the 4-level network cannot pool is rejected when the network is used
+    g36 = inputs.make_grid(36, 36, 1.5)
+    p36 = ppe.ppe_problem_create(g36)
+    f36 = torch.zeros((36, 36), dtype=torch.float32, device="cuda")
+    x36 = torch.zeros((36, 36), dtype=torch.float64, device="cuda")
+    with pytest.raises(ppe.PPEError):
+        ppe.ppe_solve_batch([probs[0], p36], [fs[0], f36], [xs[0], x36], ppe.ppe_solve_opts_default(), net=net)
+    with pytest.raises(ppe.PPEError):  # the same problem twice
+        ppe.ppe_solve_batch([probs[0], probs[0]], [fs[0], fs[0]], [xs[0], xs[0].clone()], o, net=net)
