@@ -242,6 +242,23 @@ ppe_status ppe_net_forward(ppe_net* n, ppe_problem* p, int32_t nb, const float* 
 ppe_status ppe_generate_rhs(int32_t nb, ppe_problem* const* problems, const ppe_train_opts* opts, float* R,
                             hipStream_t s);
 
+/* Grid of fabricated training system `sample` at training step `step` (the
+ * per-sample stretch and obstacle of the generator; Table 1's range of
+ * stretching, an immersed obstacle as in Sec. 3). With the Philox4x32-10
+ * stream of ppe_generate_rhs (key = seed, counter = (d, sample, step mod 2^32,
+ * step div 2^32)) and u(x) = ((x >> 8) + 1/2) 2^-24, draw d = 0xFFFFFF00 gives
+ * beta_x = 1 + 1.5 u0, beta_y = 1 + 1.5 u1 and the ellipse centre
+ * (0.25 + 0.5 u2, 0.25 + 0.5 u3); draw d + 1 gives its semi-axes
+ * 0.05 + 0.1 u0, 0.05 + 0.1 u1 and angle pi u2. Axes: faces
+ * (1 + tanh(beta (2 i / n - 1)) / tanh beta) / 2, centres at face midpoints.
+ * A cell is solid when its centre lies in the closed ellipse.
+ * xc, hx: host [nx]; yc, hy: host [ny]; mask: host [ny*nx] or NULL;
+ * params: host [7] or NULL (beta_x, beta_y, centre x, y, semi-axes a, b,
+ * angle). Runs on the host; no device work. Errors: PPE_ERR_INVALID_ARG for
+ * nx or ny < 2, more than 2^28 cells, sample < 0 or a NULL axis array. */
+ppe_status ppe_generate_grid(int32_t nx, int32_t ny, uint64_t seed, uint64_t step, int32_t sample, double* xc,
+                             double* yc, double* hx, double* hy, uint8_t* mask, double* params);
+
 /* One Adam step on nb fabricated systems with the residual loss of Eq. 19,
  * Loss = mean over cells of (R - A NN(R))^2, averaged over the batch.
  * problems: host array of nb grids of one size (each sample has its own grid);

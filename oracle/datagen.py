@@ -88,6 +88,41 @@ def grf_field(xc, yc, wx, wy, phi):
     return np.sqrt(2.0 / J) * np.cos(arg).sum(axis=0)
 
 
+GRID_DRAW = 0xFFFFFF00  # counter index of the first grid draw, past the field draws
+
+
+def grid(nx, ny, seed, step, sample):
+    """Grid of fabricated system `sample` at `step`: a tanh-stretched tensor
+    grid (stretch factors in [1, 2.5], the range of Table 1's grids) and an
+    elliptic obstacle (the immersed bodies of Sec. 3).
+      draw GRID_DRAW:     beta_x = 1 + 1.5 u0, beta_y = 1 + 1.5 u1,
+                          centre (0.25 + 0.5 u2, 0.25 + 0.5 u3);
+      draw GRID_DRAW + 1: semi-axes 0.05 + 0.1 u0, 0.05 + 0.1 u1, angle pi u2;
+      faces (1 + tanh(beta (2 i / n - 1)) / tanh beta) / 2, centres at face
+      midpoints; a cell is solid when its centre lies in the closed ellipse.
+    Returns (xc, yc, hx, hy, mask [ny, nx] uint8, (beta_x, beta_y, cx, cy, a, b, theta))."""
+    key = (seed & MASK, (seed >> 32) & MASK)
+    d0 = philox4x32_10((GRID_DRAW, sample, step & MASK, (step >> 32) & MASK), key)
+    d1 = philox4x32_10((GRID_DRAW + 1, sample, step & MASK, (step >> 32) & MASK), key)
+    u0, u1 = to_unit(np.array(d0)), to_unit(np.array(d1))
+    bx, by = 1.0 + 1.5 * u0[0], 1.0 + 1.5 * u0[1]
+    cx, cy = 0.25 + 0.5 * u0[2], 0.25 + 0.5 * u0[3]
+    a, b, th = 0.05 + 0.1 * u1[0], 0.05 + 0.1 * u1[1], np.pi * u1[2]
+
+    def axis(n, beta):
+        f = 0.5 * (1.0 + np.tanh(beta * (2.0 * np.arange(n + 1) / n - 1.0)) / np.tanh(beta))
+        f[0], f[-1] = 0.0, 1.0
+        return 0.5 * (f[1:] + f[:-1]), np.diff(f)
+
+    xc, hx = axis(nx, bx)
+    yc, hy = axis(ny, by)
+    dx, dy = xc[None, :] - cx, yc[:, None] - cy
+    p = (dx * np.cos(th) + dy * np.sin(th)) / a
+    q = (dy * np.cos(th) - dx * np.sin(th)) / b
+    mask = (p * p + q * q <= 1.0).astype(np.uint8)
+    return xc, yc, hx, hy, mask, (bx, by, cx, cy, a, b, th)
+
+
 def generate(grids, seed, step, J=512, len_lo=0.05, len_hi=0.5):
     """R [nb, ny, nx] for sample s on grids[s] (FP64)."""
     out = []

@@ -206,6 +206,71 @@ ppe_status generate_rhs(GenWs& w, int nb, ppe_problem* const* probs, const ppe_t
 
 using namespace ppe;
 
+// Grid of a fabricated training system, drawn on the host (2 Philox blocks
+// and O(nx + ny + nx ny) arithmetic: no kernel launch pays for itself). The
+// draws use counter indices past those of the source fields.
+namespace {
+constexpr uint32_t kGridDraw = 0xFFFFFF00u;
+
+uint4 philox_host(uint4 c, uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+double unit01_host(uint32_t x) { return ((double)(x >> 8) + 0.5) * 0x1p-24; }
+
+// tanh-stretched axis of n cells on [0, 1]: faces, then centres and widths
+void tanh_axis(int n, double beta, double* c, double* h) {
+  const double tb = std::tanh(beta);
+  double f0 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double f1 = i + 1 == n ? 1.0 : 0.5 * (1.0 + std::tanh(beta * (2.0 * (i + 1) / n - 1.0)) / tb);
+    c[i] = 0.5 * (f0 + f1);
+    h[i] = f1 - f0;
+    f0 = f1;
+  }
+}
+}  // namespace
+
+extern "C" ppe_status ppe_generate_grid(int32_t nx, int32_t ny, uint64_t seed, uint64_t step, int32_t sample,
+                                        double* xc, double* yc, double* hx, double* hy, uint8_t* mask,
+                                        double* params) {
+  if (nx < 2 || ny < 2 || (int64_t)nx * ny > ((int64_t)1 << 28))
+    return set_error(PPE_ERR_INVALID_ARG, "grid %d x %d outside [2, 2^28 cells]", nx, ny);
+  if (sample < 0) return set_error(PPE_ERR_INVALID_ARG, "sample < 0");
+  if (!xc || !yc || !hx || !hy) return set_error(PPE_ERR_INVALID_ARG, "xc, yc, hx or hy is NULL");
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  auto draw = [&](uint32_t d) {
+    return philox_host(make_uint4(d, (uint32_t)sample, (uint32_t)step, (uint32_t)(step >> 32)), k0, k1);
+  };
+  const uint4 a = draw(kGridDraw), b = draw(kGridDraw + 1);
+  const double bx = 1.0 + 1.5 * unit01_host(a.x), by = 1.0 + 1.5 * unit01_host(a.y);
+  const double cx = 0.25 + 0.5 * unit01_host(a.z), cy = 0.25 + 0.5 * unit01_host(a.w);
+  const double ea = 0.05 + 0.1 * unit01_host(b.x), eb = 0.05 + 0.1 * unit01_host(b.y);
+  const double th = M_PI * unit01_host(b.z);
+  tanh_axis(nx, bx, xc, hx);
+  tanh_axis(ny, by, yc, hy);
+  if (mask) {
+    const double ct = std::cos(th), st = std::sin(th);
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const double dx = xc[i] - cx, dy = yc[j] - cy;
+        const double u = (dx * ct + dy * st) / ea, v = (dy * ct - dx * st) / eb;
+        mask[(int64_t)j * nx + i] = u * u + v * v <= 1.0;
+      }
+  }
+  if (params) {
+    const double pv[7] = {bx, by, cx, cy, ea, eb, th};
+    for (int k = 0; k < 7; ++k) params[k] = pv[k];
+  }
+  return PPE_OK;
+}
+
 extern "C" ppe_status ppe_generate_rhs(int32_t nb, ppe_problem* const* problems, const ppe_train_opts* opts, float* R,
                                        hipStream_t s) {
   if (nb < 0 || (nb > 0 && (!problems || !R)) || !opts) return set_error(PPE_ERR_INVALID_ARG, "bad arguments");

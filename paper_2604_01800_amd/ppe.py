@@ -99,6 +99,7 @@ SIGNATURES = {
     "ppe_profile_copy": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),
     "ppe_solve_batch": (_i32, [_i32, _vp, _vp, _vp, _vp, _P(ppe_solve_opts), _vp, _vp]),
     "ppe_generate_rhs": (_i32, [_i32, _vp, _P(ppe_train_opts), _vp, _vp]),
+    "ppe_generate_grid": (_i32, [_i32, _i32, _u64, _u64, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ppe_ritz_create": (_i32, [_vp, _i32, _vp, _P(_vp), _vp]),
     "ppe_ritz_info": (_i32, [_vp, _P(_i32), _vp, _vp, _vp]),
     "ppe_ritz_rhs": (_i32, [_vp, _i32, _u64, _i64, ctypes.c_double, _vp, _vp]),
@@ -388,6 +389,20 @@ def ppe_solve_batch(probs, fs, xs, opts=None, stream=None, net=None):
                                ctypes.cast(stats, ctypes.c_void_p), _stream(stream))
     _check(st, allow=(PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))
     return st, [s.as_dict() for s in stats]
+
+
+def ppe_generate_grid(nx, ny, seed, step, sample, mask=True):
+    """Grid of fabricated training system `sample` at step `step` (drawn by the
+    library on the host); returns an inputs.Grid with its draws recorded."""
+    import numpy as np
+    from . import inputs
+    xc, yc, hx, hy = np.empty(nx), np.empty(ny), np.empty(nx), np.empty(ny)
+    m = np.empty((ny, nx), dtype=np.uint8) if mask else None
+    par = np.empty(7)
+    _check(lib().ppe_generate_grid(nx, ny, seed, step, sample, xc.ctypes.data, yc.ctypes.data, hx.ctypes.data,
+                                   hy.ctypes.data, m.ctypes.data if mask else None, par.ctypes.data))
+    return inputs.Grid(nx, ny, xc, yc, hx, hy, m, float(par[0]), float(par[1]),
+                       tuple(float(v) for v in par[2:]) if mask else None)
 
 
 def ppe_generate_rhs(probs, opts, R, stream=None):

@@ -36,6 +36,12 @@ def make_pool(n: int, count: int, seed: int = 0, ell_lo: float = 0.05, ell_hi: f
     return grids, np.stack(R)
 
 
+def generated_grids(n: int, count: int, seed: int = 0, step: int = 0):
+    """count n x n grids drawn by the library's generator (ppe_generate_grid):
+    tanh stretch factors in [1, 2.5] and an elliptic obstacle per sample."""
+    return [ppe.ppe_generate_grid(n, n, seed, step, k) for k in range(count)]
+
+
 def make_ritz_pool(n: int, count: int, seed: int = 0, grids: int = 16, m: int | None = None, b: float = 0.6):
     """Pool of Lanczos-Ritz training systems (Sec. 2.3, Eqs. 14-16): `grids`
     random stretched n x n grids (ellipse masks), a Lanczos basis of m vectors
@@ -70,11 +76,12 @@ def cosine_lr(lr: float, step: int, steps: int) -> float:
 
 
 def train(net, grids, R_dev, steps: int, batch: int, lr: float = 1e-3, log_every: int = 0, problems=None,
-          schedule: str = "constant", clip_norm: float = 0.0, sam_rho: float = 0.0):
+          schedule: str = "constant", clip_norm: float = 0.0, sam_rho: float = 0.0, data_seed: int = 0):
     """Adam steps over consecutive batches of the pool (learning rate constant
     or cosine-decayed; gradients clipped to clip_norm in L2 norm when it is
     positive; sharpness-aware with radius sam_rho when it is positive);
-    returns the loss history."""
+    returns the loss history. With R_dev None the sources of step k are drawn
+    on the device by the library's generator (seed data_seed, step k)."""
     count = len(grids)
     if count % batch:
         raise ValueError("pool size must be a multiple of the batch")
@@ -86,8 +93,10 @@ def train(net, grids, R_dev, steps: int, batch: int, lr: float = 1e-3, log_every
     for k in range(steps):
         b0 = (k * batch) % count
         lr_k = cosine_lr(lr, k, steps) if schedule == "cosine" else lr
-        opts = ppe.ppe_train_opts_default(lr=lr_k, clip_norm=clip_norm, sam_rho=sam_rho)
-        loss, _ = ppe.ppe_net_train_step(net, probs[b0:b0 + batch], R_dev[b0:b0 + batch], opts)
+        opts = ppe.ppe_train_opts_default(lr=lr_k, clip_norm=clip_norm, sam_rho=sam_rho, seed=data_seed, step=k)
+        # R_dev None: the library draws every batch's sources on the device
+        R_k = None if R_dev is None else R_dev[b0:b0 + batch]
+        loss, _ = ppe.ppe_net_train_step(net, probs[b0:b0 + batch], R_k, opts)
         losses.append(loss)
         if log_every and (k + 1) % log_every == 0:
             print(f"train step {k + 1}/{steps} loss {np.mean(losses[-log_every:]):.4e} "
@@ -139,8 +148,9 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", default=None, help="save the trained network here")
     ap.add_argument("--load", default=None, help="load this network instead of training one")
-    ap.add_argument("--data", choices=["grf", "ritz"], default="grf",
-                    help="training systems: Gaussian random fields, or Lanczos-Ritz vectors (Eqs. 14-16)")
+    ap.add_argument("--data", choices=["grf", "ritz", "generated"], default="grf",
+                    help="training systems: Gaussian random fields, Lanczos-Ritz vectors (Eqs. 14-16), or "
+                         "grids from the library's generator with sources drawn on the device at every step")
     ap.add_argument("--eval-sizes", default="64,128,256")
     ap.add_argument("--sweep", action="store_true",
                     help="also sweep Num_CG and Num_DLSM over 1..5 on held-out n x n systems (Appendix A)")
@@ -157,6 +167,8 @@ def main(argv=None):
     else:
         if args.data == "ritz":
             grids, Rd = make_ritz_pool(args.n, args.pool, seed=1)
+        elif args.data == "generated":
+            grids, Rd = generated_grids(args.n, args.pool, seed=1), None
         else:
             grids, R = make_pool(args.n, args.pool, seed=1)
             Rd = torch.from_numpy(R).cuda()

@@ -4,6 +4,7 @@ library (Salmon et al., SC 2011), the uniform map's moments, and the random
 Fourier-feature field's covariance against exp(-d^2 / (2 l^2)) within three
 standard errors (Rahimi & Recht, 2007)."""
 import numpy as np
+import pytest
 
 from oracle import datagen
 from paper_2604_01800_amd import inputs
@@ -67,3 +68,47 @@ def test_generated_batch_properties():
     assert np.array_equal(R, datagen.generate(grids, seed=5, step=2, J=64))
     other = datagen.generate(grids, seed=5, step=3, J=64)
     assert np.abs(other - R).max() > 0.1
+
+
+# ---- grids of fabricated systems ----
+
+def test_grid_reference_properties():
+    """The oracle's grid draw against what the definition fixes: the tanh axis
+    is odd about the centre (x_i + x_(n-i) = 1), spans [0, 1], and its width
+    ratio tends to cosh^2(beta) (dx/dxi = beta sech^2(beta (2 xi - 1)) / tanh beta,
+    smallest at the walls); the draws stay in their ranges and fill them; the
+    solid cells cover the ellipse area pi a b."""
+    betas, areas = [], []
+    for sample in range(64):
+        xc, yc, hx, hy, mask, (bx, by, cx, cy, a, b, th) = datagen.grid(512, 384, 11, 5, sample)
+        assert 1.0 <= bx <= 2.5 and 1.0 <= by <= 2.5 and 0.25 <= cx <= 0.75 and 0.05 <= a <= 0.15
+        assert 0.0 <= th <= np.pi
+        np.testing.assert_allclose(hx.sum(), 1.0, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(hx + hx[::-1], 2 * hx, rtol=1e-9)  # mirror symmetric widths
+        np.testing.assert_allclose(xc + xc[::-1], 1.0, rtol=0, atol=1e-13)
+        assert np.all(np.diff(xc) > 0) and np.all(np.diff(yc) > 0)
+        assert abs(hx.max() / hx.min() / np.cosh(bx) ** 2 - 1) < 0.02
+        cell_area = np.outer(hy, hx)
+        areas.append((cell_area[mask == 1].sum(), np.pi * a * b))
+        betas += [bx, by]
+    for got, want in areas:
+        assert abs(got / want - 1) < 0.05, (got, want)
+    assert 1.6 < np.mean(betas) < 1.9 and min(betas) < 1.15 and max(betas) > 2.35
+
+
+def test_library_grid_matches_reference():
+    """The library's host-side grid draw (C-ABI) against the oracle: same
+    stretch and obstacle draws, axes to rounding, and the same solid cells
+    except where a centre lies within rounding of the ellipse boundary."""
+    from paper_2604_01800_amd import ppe
+    for (nx, ny, seed, step, sample) in [(64, 48, 7, 3, 2), (257, 130, 2 ** 40 + 5, 2 ** 33 + 1, 9), (2, 2, 0, 0, 0)]:
+        g = ppe.ppe_generate_grid(nx, ny, seed, step, sample)
+        xc, yc, hx, hy, mask, par = datagen.grid(nx, ny, seed, step, sample)
+        np.testing.assert_allclose([g.beta_x, g.beta_y, *g.ellipse], par, rtol=1e-15, atol=0)
+        for a, b in ((g.xc, xc), (g.yc, yc), (g.hx, hx), (g.hy, hy)):
+            np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-16)
+        assert np.count_nonzero(g.mask != mask) <= 1
+    with pytest.raises(ppe.PPEError):
+        ppe.ppe_generate_grid(1, 8, 0, 0, 0)
+    with pytest.raises(ppe.PPEError):
+        ppe.ppe_generate_grid(8, 8, 0, 0, -1)
