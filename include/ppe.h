@@ -161,8 +161,11 @@ typedef struct {
                                    w + sam_rho g / |g| (two forward/backward passes; default 0) */
 } ppe_train_opts;
 
-/* ---- problem (Sec. 8 a1: per-grid setup, built once and reused, as the paper
- *      reuses its matrix and preconditioner across time steps) ---- */
+/* ---- problem: per-grid setup, built once and reused. The coefficient
+ *      matrix of the PPE stays constant over a simulation, so its
+ *      preconditioner is built at the first time step and reused in all
+ *      later ones (Sec. 2.5, technical details); a problem handle holds the
+ *      grid's operator coefficients and workspaces in the same way. ---- */
 ppe_status ppe_problem_create(const ppe_grid_desc* grid, ppe_problem** out);
 void ppe_problem_destroy(ppe_problem* p);
 void ppe_solve_opts_default(ppe_solve_opts* o);

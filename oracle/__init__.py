@@ -9,7 +9,13 @@ no code with the GPU library. Everything here is FP64 and single-threaded:
   hybrid CG / line-search controller of Sec. 2.2 with a pluggable error provider.
 * ``direct``: two independent direct solves used to pin the iterative ones.
 * ``net``: the DeepONet branch/trunk network and Mesh-Conv layers (Sec. 2.4)
-  in plain PyTorch CPU float64.
+  in plain PyTorch CPU float64, the Eq. 19 loss, its autograd gradient, the
+  sharpness-aware gradient and its own BF16 rounding of parameters.
+* ``datagen`` and ``ritz``: the training-data generators (random-field
+  sources, per-sample grids, and the Lanczos-Ritz vectors of Eqs. 14-16).
+
+The package imports nothing from the GPU library's package; the tests feed
+both sides from the seeded input module only.
 """
 from __future__ import annotations
 

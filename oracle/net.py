@@ -280,9 +280,28 @@ def init_params(cfg: NetConfig, rng: np.random.Generator, phi_scale=0.5):
     return p
 
 
+def bf16_round(x) -> np.ndarray:
+    """Nearest bfloat16 value of each float32 value (ties to the even
+    significand), returned as float32.
+
+    A bfloat16 keeps the sign, the 8 exponent bits and the top 7 fraction bits
+    of a float32, i.e. the upper 16 bits of its encoding. The value is rounded
+    on the discarded lower 16 bits: above half of the upper half's unit in the
+    last place it rounds away from zero, below it truncates, and at exactly
+    half it goes to the neighbour whose last kept bit is 0. Carries ripple into
+    the exponent as in any rounding of a binary encoding."""
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    bits = a.view(np.uint32)
+    upper = bits >> np.uint32(16)
+    lower = bits & np.uint32(0xFFFF)
+    half = np.uint32(0x8000)
+    up = (lower > half) | ((lower == half) & ((upper & np.uint32(1)) == 1))
+    upper = upper + up.astype(np.uint32)
+    return (upper << np.uint32(16)).astype(np.uint32).view(np.float32).reshape(a.shape)
+
+
 def round_bf16_params(cfg: NetConfig, p):
     """Copy of p with the BF16-consumed matrices rounded to BF16 values."""
-    from paper_2604_01800_amd.inputs import bf16_round
     q = {}
     for name, t in p.items():
         if name in bf16_params(cfg):
@@ -303,3 +322,28 @@ def residual_loss(p, cfg, grids, R, masks=None, apply=None):
         res = torch.as_tensor(R[s], dtype=torch.float64) - apply(g, y)
         total = total + (res * res).mean()
     return total / len(grids)
+
+
+def loss_and_grad(p, cfg, grids, R, masks=None, apply=None):
+    """Eq. 19 loss and its gradient (autograd) at the parameters p."""
+    q = {k: v.detach().clone().requires_grad_(True) for k, v in p.items()}
+    loss = residual_loss(q, cfg, grids, R, masks=masks, apply=apply)
+    loss.backward()
+    return float(loss.detach()), {k: (v.grad.detach().clone() if v.grad is not None else torch.zeros_like(v))
+                         for k, v in q.items()}
+
+
+def sam_gradient(p, cfg, grids, R, rho, masks=None, apply=None, bf16=True):
+    """Gradient of a sharpness-aware minimisation step (Foret et al., ICLR
+    2021), which Sec. 2.4 combines with Adam: with g the gradient of the loss
+    at w, the optimiser is handed the gradient at w + rho g / |g|_2, the norm
+    taken over all parameters together; the update itself is applied to w.
+    With bf16, the perturbed matrices the network consumes in BF16 are
+    rounded as the unperturbed ones are."""
+    _, g = loss_and_grad(p, cfg, grids, R, masks, apply)
+    norm = math.sqrt(sum(float((t * t).sum()) for t in g.values()))
+    scale = rho / norm if norm > 0 else 0.0
+    w = {k: p[k].detach() + scale * g[k] for k in p}
+    if bf16:
+        w = round_bf16_params(cfg, w)
+    return loss_and_grad(w, cfg, grids, R, masks, apply)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <chrono>
 #include <cmath>
@@ -465,7 +466,9 @@ ppe_status ppe_problem_create(const ppe_grid_desc* g, ppe_problem** out) {
       return set_error(PPE_ERR_INVALID_ARG, "yc/hy invalid at j=%d", j);
     if (j > 0 && !(g->yc[j] > g->yc[j - 1])) return set_error(PPE_ERR_INVALID_ARG, "yc not increasing at %d", j);
   }
+  static std::atomic<uint64_t> next_uid{1};
   ppe_problem* p = new ppe_problem();
+  p->uid = next_uid.fetch_add(1);
   p->nx = nx;
   p->ny = ny;
   p->xc.assign(g->xc, g->xc + nx);

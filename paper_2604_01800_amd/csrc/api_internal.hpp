@@ -45,6 +45,10 @@ void net_cache_free(NetCache* c);
 
 struct ppe_problem {
   int nx = 0, ny = 0;
+  // Identity of this handle for caches keyed on problems: unique over the
+  // process lifetime, unlike the handle's address, which the allocator reuses
+  // after ppe_problem_destroy.
+  uint64_t uid = 0;
   // Tuned PCG launch configuration per batch size: {nb, variant, rows_per_wave}.
   std::vector<std::array<int, 3>> tuned;
   std::vector<double> xc, yc, hx, hy;

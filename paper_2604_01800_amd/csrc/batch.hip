@@ -24,7 +24,7 @@ namespace ppe {
   } while (0)
 
 struct BatchWs {
-  std::vector<const ppe_problem*> key;  // problems the work list was built for
+  std::vector<uint64_t> key;  // uids of the problems the work list was built for
   int form = 0, R = 0, chunk = 0, jacobi = -1, n = 0, nblocks = 0;
   PcgArgs* d_descs = nullptr;
   uint32_t* d_work = nullptr;
@@ -50,7 +50,8 @@ static void batch_free(BatchWs& w) {
 // (Re)builds the work list and buffers when the problem list, the form or
 // the tile height changes.
 static ppe_status batch_prepare(BatchWs& w, int n, ppe_problem* const* probs, int form, int R) {
-  const std::vector<const ppe_problem*> key(probs, probs + n);
+  std::vector<uint64_t> key(n);
+  for (int i = 0; i < n; ++i) key[i] = probs[i]->uid;
   if (w.d_descs && w.key == key && w.form == form && w.R == R) return PPE_OK;
   batch_free(w);
   std::vector<uint32_t> work;

@@ -136,14 +136,6 @@ def grf(g: Grid, seed: int, ell: float = 0.05, J: int = 512) -> np.ndarray:
     return grf_eval(g.xc, g.yc, grf_features(np.random.default_rng(seed), ell, J))
 
 
-def bf16_round(x: np.ndarray) -> np.ndarray:
-    """Round float values to the nearest bfloat16 (ties to even), as float32."""
-    a = np.ascontiguousarray(x, dtype=np.float32)
-    u = a.view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
-    return u.astype(np.uint32).view(np.float32).reshape(a.shape)
-
-
 def travelling_grf(g: Grid, seed: int, steps: int, shift: float = 0.001,
                    direction=(0.95, 0.31), ell: float = 0.05, J: int = 512) -> np.ndarray:
     """Source sequence for consecutive solves on one grid, [steps, ny, nx] float32.

@@ -175,3 +175,19 @@ def test_hybrid_batch_statuses_and_checks(ppe):
         ppe.ppe_solve_batch([probs[0], p36], [fs[0], f36], [xs[0], x36], ppe.ppe_solve_opts_default(), net=net)
     with pytest.raises(ppe.PPEError):  # the same problem twice
         ppe.ppe_solve_batch([probs[0], probs[0]], [fs[0], fs[0]], [xs[0], xs[0].clone()], o, net=net)
+
+
+def test_batch_after_destroyed_problems_of_other_sizes(ppe):
+    """Batches on freshly created problems after the previous batch's problems
+    were destroyed: the allocator may hand the new handles the old addresses
+    (in the same order), yet the work list must follow the new grids. Each
+    solve is judged on the oracle's true residual."""
+    import gc
+    for shapes in ([(64, 64), (96, 40)], [(200, 130), (150, 210)], [(40, 24), (33, 47)]):
+        sys_ = systems(shapes, seed=7)
+        st, stats, xs, probs = run_batch(ppe, sys_, tol=1e-7)
+        assert st == ppe.PPE_OK
+        for (g, f), x in zip(sys_, xs):
+            assert true_res(g, f, x) <= 1e-7 * 1.001
+        del probs
+        gc.collect()

@@ -198,34 +198,48 @@ def test_gradient_clipping(ppe):
 
 
 def test_sam_step(ppe):
-    """sam_rho > 0: the gradient Adam uses is the one at w + rho g / |g|, the
-    weights are restored before the update, and the first Adam step follows
-    that gradient. Reference: the same net set to the perturbed weights
-    (computed on the host from the library's own g) and differentiated with
-    lr = 0; the BF16 packing of nearly equal weights can round differently,
-    hence the cosine and relative bars instead of equality."""
+    """sam_rho > 0: the gradient Adam uses is the one at w + rho g / |g|
+    (sharpness-aware minimisation, which Sec. 2.4 pairs with Adam), compared
+    with the oracle's SAM gradient (oracle.net.sam_gradient: FP64 autograd at
+    the perturbed weights, the perturbed BF16 operands rounded as the GPU's
+    are). At rho = 0.05 the perturbation turns the FP64 gradient by a wide
+    angle (cosine about 0.74 against the unperturbed one, relative change
+    about 1.7 on this batch), so the bars below separate a SAM step from a
+    plain one. The GPU perturbs along its own BF16 gradient (whole-vector
+    error up to 10 %), which the perturbed gradient inherits, hence looser
+    bars than the plain-gradient test's. The weights are restored before the
+    update, and the first Adam step follows the SAM gradient."""
     cfg = small_cfg()
     grids, R = batch(32, [(1.6, 1.3), (1.2, 2.2)], seed=9)
     probs = [ppe.ppe_problem_create(g) for g in grids]
     Rd = torch.from_numpy(R.astype(np.float32)).cuda()
     rho = 0.05
+    p = onet.round_bf16_params(cfg, onet.init_params(cfg, np.random.default_rng(3), phi_scale=1.0))
     net = ppe.Net(gpu_cfg(ppe, cfg), seed=5)
+    ppe.ppe_net_set_params(net, onet.flatten(cfg, p))
     w0 = ppe.ppe_net_get_params(net)
-    _, g = ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(lr=0.0), want_grad=True)
     _, gs = ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(lr=0.0, sam_rho=rho), want_grad=True)
     np.testing.assert_array_equal(ppe.ppe_net_get_params(net), w0)
-    g64 = g.astype(np.float64)
-    wp = (w0.astype(np.float64) + rho * g64 / np.linalg.norm(g64)).astype(np.float32)
-    ref = ppe.Net(gpu_cfg(ppe, cfg), seed=5)
-    ppe.ppe_net_set_params(ref, wp)
-    _, gr = ppe.ppe_net_train_step(ref, probs, Rd, ppe.ppe_train_opts_default(lr=0.0), want_grad=True)
-    a, b = gs.astype(np.float64), gr.astype(np.float64)
-    cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
-    assert cos >= 0.999 and np.linalg.norm(a - b) <= 0.03 * np.linalg.norm(b), (cos, np.linalg.norm(a - b) / np.linalg.norm(b))
-    assert not np.array_equal(gs, g)
+    mats = {id(g): torch.from_numpy(direct.kron_matrix(g)) for g in grids}
+    app = lambda g, y: (mats[id(g)] @ y.reshape(-1)).reshape(y.shape)
+    masks = [g.mask for g in grids]
+    _, g_or = onet.loss_and_grad(p, cfg, grids, R, masks, app)
+    _, gs_or = onet.sam_gradient(p, cfg, grids, R, rho, masks, app)
+    a = gs.astype(np.float64)
+    b = onet.flatten(cfg, gs_or)
+    c = onet.flatten(cfg, g_or)
+    cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+    rel = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    cos_plain = float(c @ b / (np.linalg.norm(c) * np.linalg.norm(b)))
+    rel_plain = float(np.linalg.norm(c - b) / np.linalg.norm(b))
+    print("SAM gradient vs oracle: cos %.5f rel %.3e; oracle plain vs SAM: cos %.4f rel %.3f"
+          % (cos, rel, cos_plain, rel_plain))
+    assert cos_plain <= 0.9 and rel_plain >= 0.5  # the bars below discriminate
+    assert cos >= 0.98 and rel <= 0.25, (cos, rel)
     # one Adam step with SAM moves each weight by lr * gs / (|gs| + eps)
     lr, eps = 1e-3, 1e-8
     net2 = ppe.Net(gpu_cfg(ppe, cfg), seed=5)
+    ppe.ppe_net_set_params(net2, onet.flatten(cfg, p))
     _, gs2 = ppe.ppe_net_train_step(net2, probs, Rd, ppe.ppe_train_opts_default(lr=lr, eps=eps, sam_rho=rho),
                                     want_grad=True)
     step = ppe.ppe_net_get_params(net2).astype(np.float64) - w0

@@ -170,3 +170,48 @@ def test_fd_gradients_of_residual_loss():
             assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * abs(float(loss.detach()))), (name, idx, fd, an)
             checked += 1
     assert checked >= 20
+
+
+def test_bf16_round_known_values_and_ties():
+    """The oracle's BF16 rounding: exact values stay, halfway cases go to the
+    even neighbour, anything past halfway rounds away from zero, carries
+    reach the exponent; and it agrees with torch's float32 -> bfloat16
+    conversion (round to nearest even) on random values of every magnitude."""
+    u = 2.0 ** -7  # spacing of bfloat16 values in [1, 2)
+    cases = [(1.0, 1.0), (1.0 + u, 1.0 + u), (1.0 + u / 2, 1.0), (1.0 + 3 * u / 2, 1.0 + 2 * u),
+             (1.0 + u / 2 + 2.0 ** -20, 1.0 + u), (1.0 + u / 2 - 2.0 ** -20, 1.0),
+             (-(1.0 + 3 * u / 2), -(1.0 + 2 * u)), (2.0 - u / 2, 2.0), (0.0, 0.0), (-0.0, -0.0),
+             (3.0 * 2.0 ** -130, 3.0 * 2.0 ** -130)]
+    x = np.array([c[0] for c in cases], dtype=np.float32)
+    want = np.array([c[1] for c in cases], dtype=np.float32)
+    got = onet.bf16_round(x)
+    np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
+    rng = np.random.default_rng(0)
+    v = (rng.standard_normal(200000) * np.exp(rng.uniform(-60, 60, 200000))).astype(np.float32)
+    ref = torch.from_numpy(v).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(onet.bf16_round(v).view(np.uint32), ref.view(np.uint32))
+
+
+def test_sam_gradient_definition():
+    """The oracle's SAM gradient equals the plain gradient taken at the
+    explicitly perturbed parameters w + rho g / |g| (whole-vector norm), and
+    reduces to the plain gradient at rho = 0."""
+    cfg = small_cfg()
+    g = inputs.make_grid(16, 16, 1.4)
+    R = inputs.grf(g, 3, ell=0.2, J=64)[None]
+    R = R - R.mean()
+    from oracle import direct
+    A = torch.from_numpy(direct.kron_matrix(g))
+    app = lambda grid, y: (A @ y.reshape(-1)).reshape(y.shape)
+    p = onet.init_params(cfg, np.random.default_rng(2))
+    l0, g0 = onet.loss_and_grad(p, cfg, [g], R, apply=app)
+    ls, gs = onet.sam_gradient(p, cfg, [g], R, 0.0, apply=app, bf16=False)
+    assert ls == l0 and all(torch.equal(gs[k], g0[k]) for k in g0)
+    flat = onet.flatten(cfg, g0)
+    rho = 0.03
+    w = onet.unflatten(cfg, onet.flatten(cfg, p) + rho * flat / np.linalg.norm(flat))
+    lw, gw = onet.loss_and_grad(w, cfg, [g], R, apply=app)
+    ls, gs = onet.sam_gradient(p, cfg, [g], R, rho, apply=app, bf16=False)
+    assert abs(ls - lw) <= 1e-12 * lw
+    np.testing.assert_allclose(onet.flatten(cfg, gs), onet.flatten(cfg, gw), rtol=1e-10, atol=1e-12)
+    assert ls > l0  # the step along +g/|g| climbs the loss

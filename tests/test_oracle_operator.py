@@ -103,3 +103,54 @@ def test_manufactured_operator_consistency(orc):
         lhs = orc.apply(g, P)[interior]
         rhs = (np.outer(g.hy, g.hx) * 2 * np.pi ** 2 * P)[interior]
         assert np.abs(lhs - rhs).max() <= tol * np.abs(rhs).max()
+
+
+def _manufactured_pcg_error(orc, n, beta):
+    """Max error of the oracle's own pipeline, rhs() then pcg(), against the
+    manufactured p = cos(pi x) cos(pi y) of -lap p = 2 pi^2 p (pointwise f)."""
+    g = inputs.make_grid(n, n, beta, 0.8 * beta)
+    P = np.outer(np.cos(np.pi * g.yc), np.cos(np.pi * g.xc))
+    b, removed = orc.rhs(g, 2 * np.pi ** 2 * P)
+    x, st, _ = orc.pcg(g, b, tol=1e-13, max_iter=20000)
+    assert st.converged
+    e = (x - x.mean()) - (P - P.mean())
+    return np.abs(e).max(), removed
+
+
+def test_rhs_through_pcg_converges_at_second_order(orc):
+    """Pins rhs() (b = cell area x f, then the plain mean removed) by what it
+    must produce: solved by the oracle's PCG, it reaches the manufactured
+    solution at second order on stretched grids. A wrong area factor (one
+    width only, a squared width, a missing projection) breaks the order or the
+    convergence to P. The removed mean is the discrete integral of f over the
+    unit square divided by N, which vanishes for this f up to O(h^2)."""
+    ns = [32, 64, 128]
+    out = [_manufactured_pcg_error(orc, n, 1.5) for n in ns]
+    errs = [e for e, _ in out]
+    orders = [np.log2(errs[k] / errs[k + 1]) for k in range(len(ns) - 1)]
+    assert all(1.85 <= o <= 2.15 for o in orders), (errs, orders)
+    for n, (_, removed) in zip(ns, out):
+        assert abs(removed) * n * n <= 5.0 / n ** 2, (n, removed)
+
+
+def test_rhs_projection_makes_the_system_consistent(orc):
+    """A source with a constant offset c has no Neumann solution unless b is
+    projected onto the range of A (zero sum). After rhs() the oracle's PCG
+    converges on it; the removed plain mean equals c times the domain area
+    (1) over N plus the vanishing mean of the rest, and the solution differs
+    from the unshifted one only through c (cell area - mean area)."""
+    n = 48
+    g = inputs.make_grid(n, n, 1.5, 1.1)
+    P = np.outer(np.cos(np.pi * g.yc), np.cos(np.pi * g.xc))
+    f0 = (2 * np.pi ** 2 * P).astype(np.float32)
+    b0, m0 = orc.rhs(g, f0)
+    b1, m1 = orc.rhs(g, f0 + np.float32(3.0))
+    # f crosses the boundary in FP32: |fl(f0 + 3) - (f0 + 3)| <= 2^-24 * 23 per cell
+    assert abs((m1 - m0) - 3.0 / (n * n)) <= 2e-6 / (n * n)
+    x1, st, _ = orc.pcg(g, b1, tol=1e-11, max_iter=20000)
+    assert st.converged and st.res_final <= 1e-11 * np.linalg.norm(b1)
+    area = np.outer(g.hy, g.hx)
+    want = b0 + 3.0 * (area - area.mean())
+    np.testing.assert_allclose(b1, want, rtol=0, atol=2e-6 * area.max())
+    # without the projection the sum of b would be 3 (the domain area times c)
+    assert abs(b1.sum()) <= 1e-12 * np.abs(b1).sum()
