@@ -7,18 +7,25 @@ an elliptical obstacle mask (centre U[0.2, 0.8]^2, semi-axes U[0.05, 0.15],
 angle U[0, pi)), and a Gaussian-random-field source (squared-exponential
 covariance, length 0.05, 512 random Fourier features). Each step solves the
 system from x0 = 0 to relative residual 1e-6 (FP64 true residual) with
-Jacobi-PCG. With --hybrid PATH (a network saved by ppe_net_save), the same
-system is also solved by the hybrid PCG + line-search method, and its
-time-to-tolerance is reported beside the plain solve's in config["hybrid"]
-(the headline value stays the plain solve's).
+Jacobi-PCG; `value` is that plain solve's rate.
 
-Prints one JSON line. `roofline` reports the dominant kernel (the launch of
-the PCG form that runs: two-step, two iterations per launch; single-reduction,
-one iteration per launch; or phase A of the two-phase form) with its
-algorithmic bytes per launch
-divided by its average launch duration (HIP events attached to the launches). `cpu_baseline` times the FP64 oracle on a
-bounded sample (a fixed number of PCG iterations on the same system, scaled to
-the iteration count of a full solve).
+Beside it the line always carries the hybrid half of the comparison
+(config["hybrid"]): the same system solved by the hybrid PCG + line-search
+method of Sec. 2.2 (Num_CG = 3, Num_DLSM = 2) with the network saved at
+--hybrid PATH, or, without one, with the default network at its seeded
+random initialisation (the control), each run capped at --hybrid-max-iter
+iterations and reported as converged or not.
+
+`roofline` reports the dominant kernel (the launch of the PCG form that
+runs) on the algorithmic basis of 32 bytes per cell and PCG iteration (the
+two-phase iteration's reads and writes of HBM-resident FP32 vectors), times
+the iterations one launch makes, over its average launch duration (HIP
+events attached to the launches); the kernel's own bytes per launch are
+given beside it. config["hbm_resident_batch"] repeats the solve for 32
+right-hand sides on the same grid, whose 1.1 GB of state cannot stay in the
+256 MB last-level cache. `cpu_baseline` times the FP64 oracle on a bounded
+sample (a fixed number of PCG iterations on the same system, scaled to the
+iteration count of a full solve).
 """
 from __future__ import annotations
 
@@ -32,10 +39,12 @@ import numpy as np
 
 METRIC = "PPE solves/sec to rel-res 1e-6, hybrid vs plain PCG, 1024² grid; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-BYTES_PCG1 = 24     # per cell: reads r, p, x_c; writes r, p, x_c (FP32)
-BYTES_PCG2 = 24     # per cell and launch of two iterations: the same six FP32 vectors
-BYTES_PHASE_A = 20  # per cell: reads r, p_old, x_c; writes p, x_c (FP32)
-BYTES_PHASE_B = 12  # per cell: reads p, r; writes r (FP32)
+BYTES_ITER = 32     # algorithmic basis per cell and PCG iteration (two-phase reads and writes)
+BYTES_PCG1 = 24     # own bytes per cell: reads r, p, x_c; writes r, p, x_c (FP32)
+BYTES_PCG2 = 24     # own bytes per cell and launch of two iterations: the same six FP32 vectors
+BYTES_PHASE_A = 20  # own bytes per cell: reads r, p_old, x_c; writes p, x_c (FP32)
+BYTES_PHASE_B = 12  # own bytes per cell: reads p, r; writes r (FP32)
+HBM_BATCH = 32      # right-hand sides of the HBM-resident batch
 
 
 def workload(n=1024, beta=1.75, seed=0):
@@ -63,6 +72,16 @@ def measured_traffic(kernel, record):
         return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, f, iters_full, sample_iters):
     """Single-threaded FP64 oracle PCG: time `sample_iters` iterations, scale."""
     import oracle
@@ -79,29 +98,78 @@ def cpu_baseline(g, f, iters_full, sample_iters):
         "sample": f"{sample_iters} FP64 Jacobi-PCG iterations of the C oracle on the same {g.nx}x{g.ny} "
                   f"system ({dt:.1f} s, {per_iter * 1e3:.2f} ms/iteration), scaled to the {iters_full} "
                   f"iterations of a full solve to 1e-6",
+        "cpu_model": cpu_model(),
+        "host_threads_visible": os.cpu_count(),
     }
 
 
 def hybrid_run(ppe, torch, prob, f, x, args):
-    """Hybrid solves (Num_CG = 3, Num_DLSM = 2) of the same system with a saved
-    network, timed like the plain solve (one warm-up, then args.steps, capped at
-    3 since a hybrid solve can take seconds)."""
+    """Hybrid solves (Num_CG = 3, Num_DLSM = 2) of the same system, timed like
+    the plain solve (one warm-up, then args.steps, capped at 2 since a hybrid
+    solve can take seconds). The network is the one saved at args.hybrid, or
+    the default network at its seeded random initialisation."""
     net = ppe.Net(ppe.ppe_net_config_default(), seed=0)
-    ppe.ppe_net_load(net, args.hybrid)
+    if args.hybrid:
+        ppe.ppe_net_load(net, args.hybrid)
+        name = os.path.basename(args.hybrid)
+    else:
+        name = "default network (4 levels, 32-256 channels), seeded random initialisation (control)"
     o = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, max_iter=args.hybrid_max_iter)
     ppe.ppe_solve_hybrid(prob, net, f, x, o)
     torch.cuda.synchronize()
-    steps = max(1, min(args.steps, 3))
+    steps = max(1, min(args.steps, 2))
     t0 = time.perf_counter()
     for _ in range(steps):
         st, stats = ppe.ppe_solve_hybrid(prob, net, f, x, o)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
     s0 = stats[0]
-    return {"network": os.path.basename(args.hybrid), "converged": st == ppe.PPE_OK, "ms_per_solve": ms,
-            "solves_per_s": 1e3 / ms, "iters": s0["iters_total"], "iters_dlsm": s0["iters_dlsm"],
-            "dlsm_rejected": s0["dlsm_rejected"], "rel_res_true": s0["rel_res_true"],
-            "max_iter": args.hybrid_max_iter}
+    out = {"network": name, "converged": st == ppe.PPE_OK,
+           "status": "converged" if st == ppe.PPE_OK else f"not converged within {args.hybrid_max_iter} iterations",
+           "ms_per_solve": ms, "solves_per_s": 1e3 / ms if st == ppe.PPE_OK else 0.0,
+           "iters": s0["iters_total"], "iters_cg": s0["iters_cg"], "iters_dlsm": s0["iters_dlsm"],
+           "dlsm_rejected": s0["dlsm_rejected"], "rel_res_true": s0["rel_res_true"],
+           "max_iter": args.hybrid_max_iter, "num_cg": 3, "num_dlsm": 2}
+    for k in ("ms_pcg", "ms_net", "ms_dlsm"):
+        if k in s0:
+            out[k] = s0[k]
+    return out
+
+
+def hbm_batch_run(ppe, torch, g, prob, args):
+    """Plain solve of HBM_BATCH right-hand sides on the headline grid (state
+    well beyond the last-level cache) and the average launch time of its PCG
+    kernel; bandwidth on the 32 B/cell/iteration basis and on the kernel's
+    own bytes."""
+    from paper_2604_01800_amd import inputs
+    nb = HBM_BATCH
+    f = torch.from_numpy(np.stack([inputs.grf(g, 1000 + k).astype(np.float32) for k in range(nb)])).cuda()
+    x = torch.zeros((nb, g.ny, g.nx), dtype=torch.float64, device="cuda")
+    o = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1)
+    variant, rows = ppe.ppe_get_tuning(prob, nb)
+    ppe.ppe_solve_plain(prob, f, x, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, stats = ppe.ppe_solve_plain(prob, f, x, o)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    po = ppe.ppe_solve_opts_default(tol=args.tol, variant=variant, rows_per_wave=rows)
+    ms_a, ms_b = ppe.ppe_profile_pcg(prob, f, torch.zeros_like(x), po, reps=max(20, args.profile_reps // 4))
+    N = g.nx * g.ny * nb
+    per_launch = 2 if variant == ppe.PPE_PCG_TWO_STEP else 1
+    own = {ppe.PPE_PCG_TWO_STEP: BYTES_PCG2, ppe.PPE_PCG_SINGLE_REDUCTION: BYTES_PCG1}.get(variant, BYTES_ITER)
+    t_launch = (ms_a + ms_b) * 1e-3
+    alg = BYTES_ITER * per_launch * N / t_launch / 1e9
+    own_gbs = own * N / t_launch / 1e9
+    del f, x
+    torch.cuda.empty_cache()
+    return {"nb": nb, "grid": [g.nx, g.ny], "state_GB": N * 32 / 1e9,
+            "converged": st == ppe.PPE_OK, "ms_per_batch_solve": ms, "solves_per_s": nb * 1e3 / ms,
+            "iters_max": max(s["iters_total"] for s in stats), "iters_min": min(s["iters_total"] for s in stats),
+            "pcg_form": {1: "single", 2: "two_phase", 3: "two_step"}[variant], "rows_per_wave": rows,
+            "kernel_ms": ms_a + ms_b, "iters_per_launch": per_launch,
+            "GBps_32B_basis": alg, "frac_32B_basis": alg / HBM_PEAK_GBS,
+            "own_bytes_per_cell_launch": own, "GBps_own_bytes": own_gbs, "frac_own_bytes": own_gbs / HBM_PEAK_GBS}
 
 
 def sequence_run(ppe, torch, g, prob, x, opts, form, rows, args):
@@ -153,8 +221,10 @@ def main():
                          "--train-batch fabricated n x n systems instead (use with --n 256)")
     ap.add_argument("--train-batch", type=int, default=64)
     ap.add_argument("--hybrid", default=None, metavar="PATH",
-                    help="also time the hybrid solve with the network saved at PATH (default configuration)")
-    ap.add_argument("--hybrid-max-iter", type=int, default=30000)
+                    help="network for the hybrid leg, saved by ppe_net_save (default configuration); without it "
+                         "the hybrid leg runs the default network at its seeded random initialisation")
+    ap.add_argument("--hybrid-max-iter", type=int, default=3000)
+    ap.add_argument("--no-hbm-batch", action="store_true", help="skip the HBM-resident batch leg")
     ap.add_argument("--sequence", type=int, default=0, metavar="T",
                     help="time T consecutive solves on the workload's grid instead, the source travelling "
                          "--seq-shift domain lengths per step (step 0 is the headline source), from x0 = 0 "
@@ -259,18 +329,19 @@ def main():
     N = g.nx * g.ny
     iters = s0["iters_total"]
     if form == "two_step":
-        kname, kbytes, record = "k_pcg2 (two PCG iterations per launch)", BYTES_PCG2, "pcg2_1024_plain.counters.json"
-        tkey = "k_pcg2"
+        kname, own, per_launch = "k_pcg2 (two PCG iterations per launch)", BYTES_PCG2, 2
+        record, tkey, t_launch = "pcg2_1024_plain.counters.json", "k_pcg2", ms_a
     elif form == "single":
-        kname, kbytes, record = "k_pcg1 (single-reduction PCG iteration)", BYTES_PCG1, "pcg1_1024_plain.counters.json"
-        tkey = "k_pcg1"
+        kname, own, per_launch = "k_pcg1 (single-reduction PCG iteration)", BYTES_PCG1, 1
+        record, tkey, t_launch = "pcg1_1024_plain.counters.json", "k_pcg1", ms_a
     else:
-        kname, kbytes, record = "k_pcg_a (PCG phase A)", BYTES_PHASE_A, "pcg_phases_1024_plain.counters.json"
-        tkey = "k_pcg_a"
-    ach = kbytes * N / (ms_a * 1e-3) / 1e9
-    # Whole-solve rate in the bytes a one-reduction iteration must move (24 B
-    # per cell and iteration), whatever form ran: comparable across forms.
-    pcg_gbs = BYTES_PCG1 * N * iters / (ms_per_step * 1e-3) / 1e9
+        kname, own, per_launch = "k_pcg_a + k_pcg_b (the two phases of one PCG iteration)", BYTES_ITER, 1
+        record, tkey, t_launch = "pcg_phases_1024_plain.counters.json", "k_pcg_a", ms_a + ms_b
+    alg_bytes = BYTES_ITER * per_launch * N
+    ach = alg_bytes / (t_launch * 1e-3) / 1e9
+    own_gbs = own * N / (t_launch * 1e-3) / 1e9
+    # Whole-solve rate on the same 32 B/cell/iteration basis.
+    pcg_gbs = BYTES_ITER * N * iters / (ms_per_step * 1e-3) / 1e9
 
     out = {
         "metric": METRIC,
@@ -296,7 +367,7 @@ def main():
             "reliable_updates": s0["reliable_updates"],
             "rel_res_true": s0["rel_res_true"],
             "precision": "FP32 vectors, FP64 reductions and solution accumulator",
-            "effective_pcg_GBps": pcg_gbs,
+            "effective_pcg_GBps_32B_basis": pcg_gbs,
             "kernel_ms": [ms_a, ms_b],
         },
         "roofline": {
@@ -307,11 +378,17 @@ def main():
             "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS,
             "traffic": measured_traffic(tkey, record),
-            "algorithmic_bytes": kbytes * N,
+            "basis": f"{BYTES_ITER} B/cell per PCG iteration x {per_launch} iteration(s) per launch x {N} cells",
+            "algorithmic_bytes": alg_bytes,
+            "kernel_ms": t_launch,
+            "own_bytes": own * N,
+            "own_GBps": own_gbs,
+            "own_frac": own_gbs / HBM_PEAK_GBS,
         },
     }
-    if args.hybrid:
-        out["config"]["hybrid"] = hybrid_run(ppe, torch, prob, f, x, args)
+    out["config"]["hybrid"] = hybrid_run(ppe, torch, prob, f, x, args)
+    if not args.no_hbm_batch:
+        out["config"]["hbm_resident_batch"] = hbm_batch_run(ppe, torch, g, prob, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, f_np, iters, args.cpu_iters)
     print(json.dumps(out), flush=True)
