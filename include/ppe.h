@@ -350,6 +350,34 @@ ppe_status ppe_profile_pcg(ppe_problem* p, int32_t nb, const float* f, double* x
 ppe_status ppe_profile_copy(const void* src, void* dst, int64_t bytes, int32_t reps, double* ms_out,
                             hipStream_t s);
 
+/* ---- allocation-free plain solve ----
+ * For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the Jacobi-PCG / CG solve of ppe_solve_plain for ONE right-hand side, with
+ * its solver state (six FP32 vectors, FP64 partial sums, iteration state) in
+ * a fixed device array of PPE_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on every device it runs on until the process ends. The call makes no
+ * device or pinned-host allocation and frees nothing: it launches the solve's
+ * kernels eagerly on stream s (no HIP graph) and polls convergence with
+ * synchronous device-to-host copies into host stack memory. The kernels and
+ * their order are those of ppe_solve_plain with the same iteration form and
+ * tile height, so the result is bit-identical to that call's.
+ * p, opts, stats: as for ppe_solve_plain with nb = 1 (the problem's
+ * workspace is not touched). f: device FP32 [ny][nx]; x: device FP64
+ * [ny][nx], in = initial guess (unless opts->zero_x0), out = zero-mean
+ * solution.
+ * The grid's state must fit the array: ppe_noalloc_scratch_bytes(p) bytes,
+ * about 24 bytes per cell plus the partial sums (a 1024 x 1024 grid needs
+ * 26 MB). A larger grid gives PPE_ERR_INVALID_ARG before anything is
+ * launched. All calls on one device share its array, which keeps the last
+ * call's contents (each call clears what must start at zero): the library
+ * serialises calls within a process with a lock, and a caller must not
+ * overlap a call with another use of the same device's array. */
+#define PPE_NOALLOC_SCRATCH_BYTES (32 * 1024 * 1024)
+int64_t ppe_noalloc_scratch_bytes(const ppe_problem* p); /* -1 for NULL */
+ppe_status ppe_solve_plain_noalloc(const ppe_problem* p, const float* f, double* x, const ppe_solve_opts* opts,
+                                   ppe_solve_stats* stats, hipStream_t s);
+
 const char* ppe_last_error(void);
 
 #ifdef __cplusplus

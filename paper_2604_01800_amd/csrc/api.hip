@@ -66,9 +66,7 @@ ppe_status ensure_ws(ppe_problem* p, int nb) {
   if (w.nb >= nb && w.vec) return PPE_OK;
   free_ws(w);
   const int64_t N = (int64_t)p->nx * p->ny;
-  const dim3 g = stencil_grid(p->coef, 2, 1);  // the smallest tile height has the most workgroups
-  w.Pmax = (int)(g.x * g.y);
-  w.P2max = (int)stencil_grid2(p->coef, 2, 1).x;
+  ws_extent(p, &w.Pmax, &w.P2max);
   w.vec = (float*)dev_alloc(sizeof(float) * 6 * N * nb);
   w.part = (double*)dev_alloc(sizeof(double) * (16 * (size_t)w.Pmax + 22 * (size_t)w.P2max) * nb);
   w.st = (SolveState*)dev_alloc(sizeof(SolveState) * nb);
@@ -93,8 +91,8 @@ ppe_status ensure_ws(ppe_problem* p, int nb) {
   return PPE_OK;
 }
 
-PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int tol_kind, int zero_x0) {
-  SolveWs& w = p->ws;
+PcgArgs make_pcg_args_at(const ppe_problem* p, const WsView& w, int nb, int R, int jacobi, double tol, int tol_kind,
+                         int zero_x0) {
   PcgArgs a{};
   a.c = p->coef;
   const dim3 g = stencil_grid(p->coef, R, 1);
@@ -122,6 +120,18 @@ PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int
   a.jacobi = jacobi;
   a.zero_x0 = zero_x0;
   return a;
+}
+
+void ws_extent(const ppe_problem* p, int* Pmax, int* P2max) {
+  const dim3 g = stencil_grid(p->coef, 2, 1);  // the smallest tile height has the most workgroups
+  *Pmax = (int)(g.x * g.y);
+  *P2max = (int)stencil_grid2(p->coef, 2, 1).x;
+}
+
+PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int tol_kind, int zero_x0) {
+  SolveWs& w = p->ws;
+  const WsView v{w.vec, w.part, w.Pmax, w.st, w.flags, w.call};
+  return make_pcg_args_at(p, v, nb, R, jacobi, tol, tol_kind, zero_x0);
 }
 
 int default_rows(const ppe_problem* p, int nb) {
@@ -215,7 +225,7 @@ int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o) {
 // One chunk of `chunk` launches with alternating parity: pairs of phase
 // launches (two-phase form) or single launches (single-reduction and
 // two-step forms).
-static void launch_chunk(const PcgArgs& a, int nb, int chunk, int form, hipStream_t s) {
+void launch_chunk(const PcgArgs& a, int nb, int chunk, int form, hipStream_t s) {
   for (int k = 0; k < chunk; ++k) {
     if (form == PPE_PCG_SINGLE_REDUCTION) launch_pcg1_step(a, nb, k & 1, s);
     else if (form == PPE_PCG_TWO_STEP) launch_pcg2_step(a, nb, k & 1, s);
@@ -299,6 +309,27 @@ double wall_clock_khz() {
   return khz;
 }
 
+void stats_from_state(const SolveState& S, ppe_status st, double ms, bool hybrid, ppe_solve_stats* out) {
+  ppe_solve_stats& o = *out;
+  memset(&o, 0, sizeof o);
+  o.status = st;
+  o.iters_total = S.it_final;
+  o.iters_cg = S.itcg_final;
+  o.iters_dlsm = hybrid ? S.n_dlsm : 0;
+  o.dlsm_rejected = hybrid ? S.n_rej : 0;
+  o.reliable_updates = S.nru_final;
+  o.abs_res_true = std::sqrt(S.rr_final);
+  o.bnorm = std::sqrt(S.bnorm2);
+  o.rel_res_true = S.bnorm2 > 0 ? std::sqrt(S.rr_final / S.bnorm2) : o.abs_res_true;
+  o.rhs_mean_removed = S.bmean;
+  o.ms_total = ms;
+  o.ms_device = (double)(S.t_done - S.t_start) / wall_clock_khz();
+}
+
+ppe_status state_status(const SolveState& S) {
+  return S.done == DONE_CONV ? PPE_OK : S.done == DONE_NONFINITE ? PPE_ERR_NONFINITE : PPE_NOT_CONVERGED;
+}
+
 ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s, bool hybrid) {
   SolveWs& w = p->ws;
   HIPCHK(hipMemcpyAsync(w.h_state, w.st, sizeof(SolveState) * nb, hipMemcpyDeviceToHost, s));
@@ -306,27 +337,10 @@ ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms,
   ppe_status worst = PPE_OK;
   for (int i = 0; i < nb; ++i) {
     const SolveState& S = w.h_state[i];
-    ppe_status st = S.done == DONE_CONV ? PPE_OK
-                    : S.done == DONE_NONFINITE ? PPE_ERR_NONFINITE
-                                               : PPE_NOT_CONVERGED;
+    const ppe_status st = state_status(S);
     if (st == PPE_ERR_NONFINITE) worst = st;
     else if (st == PPE_NOT_CONVERGED && worst == PPE_OK) worst = st;
-    if (stats) {
-      ppe_solve_stats& o = stats[i];
-      memset(&o, 0, sizeof o);
-      o.status = st;
-      o.iters_total = S.it_final;
-      o.iters_cg = S.itcg_final;
-      o.iters_dlsm = hybrid ? S.n_dlsm : 0;
-      o.dlsm_rejected = hybrid ? S.n_rej : 0;
-      o.reliable_updates = S.nru_final;
-      o.abs_res_true = std::sqrt(S.rr_final);
-      o.bnorm = std::sqrt(S.bnorm2);
-      o.rel_res_true = S.bnorm2 > 0 ? std::sqrt(S.rr_final / S.bnorm2) : o.abs_res_true;
-      o.rhs_mean_removed = S.bmean;
-      o.ms_total = ms;
-      o.ms_device = (double)(S.t_done - S.t_start) / wall_clock_khz();
-    }
+    if (stats) stats_from_state(S, st, ms, hybrid, stats + i);
   }
   if (worst == PPE_ERR_NONFINITE) set_error(worst, "non-finite value in a source field or iteration");
   return worst;
@@ -352,7 +366,7 @@ ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, con
   return PPE_OK;
 }
 
-static void launch_setup(const PcgArgs& a, int nb, int form, hipStream_t s) {
+void launch_setup(const PcgArgs& a, int nb, int form, hipStream_t s) {
   if (form == PPE_PCG_SINGLE_REDUCTION) launch_pcg1_setup(a, nb, s);
   else if (form == PPE_PCG_TWO_STEP) launch_pcg2_setup(a, nb, s);
   else launch_pcg_setup(a, nb, s);

@@ -70,7 +70,25 @@ void dev_free(void* p);
 ppe_status problem_upload(ppe_problem* p);
 void problem_release(ppe_problem* p);
 ppe_status ensure_ws(ppe_problem* p, int nb);
+// Device buffers a solve of nb systems runs in: the problem's own workspace
+// (make_pcg_args) or a caller's view of equal layout (make_pcg_args_at).
+struct WsView {
+  float* vec;        // [6][nb][N]
+  double* part;      // [16][nb][Pmax], then [22][nb][P2max]
+  int Pmax;
+  SolveState* st;    // [nb]
+  int32_t* flags;    // [nb]
+  CallArgs* call;
+};
+// Workgroup counts the partial-sum arrays of a problem are sized for.
+void ws_extent(const ppe_problem* p, int* Pmax, int* P2max);
+PcgArgs make_pcg_args_at(const ppe_problem* p, const WsView& w, int nb, int R, int jacobi, double tol, int tol_kind,
+                         int zero_x0);
 PcgArgs make_pcg_args(ppe_problem* p, int nb, int R, int jacobi, double tol, int tol_kind, int zero_x0);
+void launch_setup(const PcgArgs& a, int nb, int form, hipStream_t s);
+void launch_chunk(const PcgArgs& a, int nb, int chunk, int form, hipStream_t s);
+void stats_from_state(const SolveState& S, ppe_status st, double ms, bool hybrid, ppe_solve_stats* out);
+ppe_status state_status(const SolveState& S);
 int rows_of(const ppe_problem* p, int nb, const ppe_solve_opts& o);
 ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s,
                           int form);

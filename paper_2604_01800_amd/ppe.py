@@ -108,6 +108,8 @@ SIGNATURES = {
     "ppe_tune_pcg": (_i32, [_vp, _i32, _vp, _vp, _i32, _P(ppe_tune_result), _vp]),
     "ppe_set_tuning": (_i32, [_vp, _i32, _i32, _i32]),
     "ppe_get_tuning": (_i32, [_vp, _i32, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+    "ppe_noalloc_scratch_bytes": (_i64, [_vp]),
+    "ppe_solve_plain_noalloc": (_i32, [_vp, _vp, _vp, _P(ppe_solve_opts), _vp, _vp]),
     "ppe_last_error": (ctypes.c_char_p, []),
 }
 
@@ -231,6 +233,28 @@ def ppe_solve_plain(prob: Problem, f, x, opts=None, stream=None):
                                ctypes.byref(opts), ctypes.cast(stats, ctypes.c_void_p), _stream(stream))
     _check(st, (PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))
     return st, [stats[i].as_dict() for i in range(nb)]
+
+
+def ppe_solve_plain_noalloc(prob: Problem, f, x, opts=None, stream=None):
+    """Allocation-free plain solve of one right-hand side (f: device float32
+    [ny, nx] or [1, ny, nx]; x: device float64 of the same shape). Returns
+    (status, stats dict)."""
+    import torch
+    if _nb(f, prob) != 1 or _nb(x, prob) != 1:
+        raise ValueError("the allocation-free solve takes one right-hand side")
+    opts = opts or ppe_solve_opts_default()
+    stats = ppe_solve_stats()
+    st = lib().ppe_solve_plain_noalloc(prob.handle, _dev(f, torch.float32, "f"), _dev(x, torch.float64, "x"),
+                                       ctypes.byref(opts), ctypes.byref(stats), _stream(stream))
+    _check(st, (PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))
+    return st, stats.as_dict()
+
+
+def ppe_noalloc_scratch_bytes(prob: Problem) -> int:
+    return int(lib().ppe_noalloc_scratch_bytes(prob.handle))
+
+
+PPE_NOALLOC_SCRATCH_BYTES = 32 * 1024 * 1024
 
 
 def ppe_profile_pcg(prob: Problem, f, x, opts=None, reps=50, stream=None):

@@ -75,3 +75,10 @@ def test_struct_layout_matches_c(tmp_path):
     subprocess.run(["gcc", "-std=c99", "-D__HIP_PLATFORM_AMD__", *inc, "-o", str(exe), str(src)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     assert got == expect
+
+
+def test_noalloc_scratch_size_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+PPE_NOALLOC_SCRATCH_BYTES\s+\(([^)]*)\)", text)
+    assert m, "PPE_NOALLOC_SCRATCH_BYTES not defined"
+    assert eval(m.group(1), {}, {}) == ppe.PPE_NOALLOC_SCRATCH_BYTES
