@@ -11,6 +11,9 @@ no code with the GPU library. Everything here is FP64 and single-threaded:
 * ``net``: the DeepONet branch/trunk network and Mesh-Conv layers (Sec. 2.4)
   in plain PyTorch CPU float64, the Eq. 19 loss, its autograd gradient, the
   sharpness-aware gradient and its own BF16 rounding of parameters.
+* ``mg``: the multigrid V-cycle preconditioner (the paper's MGPCG-4 CG-type,
+  Sec. 2.5), geometric on the tensor grid, for ``pcg``/``hybrid`` with
+  ``precond = 2``.
 * ``datagen`` and ``ritz``: the training-data generators (random-field
   sources, per-sample grids, and the Lanczos-Ritz vectors of Eqs. 14-16).
 
@@ -73,6 +76,9 @@ def lib():
         _lib.orc_hybrid.argtypes = [ctypes.POINTER(_Grid), vp, vp, ctypes.c_int, d, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, PROVIDER, vp,
                                     ctypes.POINTER(Stats), vp, i32]
+        _lib.orc_hybrid_pc.argtypes = [ctypes.POINTER(_Grid), vp, vp, ctypes.c_int, d, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, PROVIDER, vp, PROVIDER, vp,
+                                       ctypes.POINTER(Stats), vp, i32]
         _lib.orc_pcg.argtypes = [ctypes.POINTER(_Grid), vp, vp, ctypes.c_int, d, ctypes.c_int,
                                  ctypes.c_int, ctypes.POINTER(Stats), vp, i32]
         _lib.orc_remove_mean.argtypes = [i64, vp]
@@ -134,10 +140,25 @@ def remove_mean(x):
     return x
 
 
+def _callback(n, fn, err):
+    def _cb(ctx, rp, ep):
+        try:
+            r = np.ctypeslib.as_array(rp, shape=(n.n,)).reshape(n.ny, n.nx).copy()
+            e = np.asarray(fn(r), dtype=np.float64).reshape(-1)
+            np.ctypeslib.as_array(ep, shape=(n.n,))[:] = e
+            return 0
+        except Exception as ex:  # reported after the call returns
+            err.append(ex)
+            return 1
+    return _cb
+
+
 def hybrid(g, b, provider=None, *, x0=None, precond=1, tol=1e-6, tol_kind=0,
-           max_iter=10000, num_cg=3, num_dlsm=2, history=False):
+           max_iter=10000, num_cg=3, num_dlsm=2, history=False, pc=None):
     """Hybrid solve of Sec. 2.2; ``provider(r) -> e`` maps a residual field
-    [ny, nx] to an error direction (None = plain PCG). Returns (x, stats, hist)."""
+    [ny, nx] to an error direction (None = plain PCG). ``pc(r) -> z`` is a
+    preconditioner operator (precond = 2, e.g. ``oracle.mg.Hierarchy.apply``).
+    Returns (x, stats, hist)."""
     g = _og(g)
     b = _f64(b).reshape(g.ny, g.nx)
     x = np.zeros_like(b) if x0 is None else _f64(x0).reshape(g.ny, g.nx).copy()
@@ -146,21 +167,13 @@ def hybrid(g, b, provider=None, *, x0=None, precond=1, tol=1e-6, tol_kind=0,
     hp = hist.ctypes.data if history else None
     cap = max_iter + 1 if history else 0
     err = []
-
-    def _cb(ctx, rp, ep):
-        try:
-            r = np.ctypeslib.as_array(rp, shape=(g.n,)).reshape(g.ny, g.nx).copy()
-            e = np.asarray(provider(r), dtype=np.float64).reshape(-1)
-            np.ctypeslib.as_array(ep, shape=(g.n,))[:] = e
-            return 0
-        except Exception as ex:  # reported after the call returns
-            err.append(ex)
-            return 1
-
-    cb = PROVIDER(_cb) if provider is not None else PROVIDER()
-    lib().orc_hybrid(ctypes.byref(g.c), b.ctypes.data, x.ctypes.data, precond, tol, tol_kind,
-                     max_iter, num_cg, num_dlsm if provider is not None else 0, cb, None,
-                     ctypes.byref(st), hp, cap)
+    if precond == 2 and pc is None:
+        raise ValueError("precond = 2 needs a preconditioner operator pc")
+    cb = PROVIDER(_callback(g, provider, err)) if provider is not None else PROVIDER()
+    pcb = PROVIDER(_callback(g, pc, err)) if pc is not None else PROVIDER()
+    lib().orc_hybrid_pc(ctypes.byref(g.c), b.ctypes.data, x.ctypes.data, precond, tol, tol_kind,
+                        max_iter, num_cg, num_dlsm if provider is not None else 0, cb, None, pcb, None,
+                        ctypes.byref(st), hp, cap)
     if err and not isinstance(err[0], FloatingPointError):
         raise err[0]
     if history:
@@ -168,7 +181,8 @@ def hybrid(g, b, provider=None, *, x0=None, precond=1, tol=1e-6, tol_kind=0,
     return x, st, hist
 
 
-def pcg(g, b, *, x0=None, precond=1, tol=1e-6, tol_kind=0, max_iter=10000, history=False):
-    """Textbook (Jacobi-)PCG; tol <= 0 runs exactly max_iter iterations."""
+def pcg(g, b, *, x0=None, precond=1, tol=1e-6, tol_kind=0, max_iter=10000, history=False, pc=None):
+    """Textbook PCG (Saad Alg. 9.1) with no, Jacobi or a supplied (pc)
+    preconditioner; tol <= 0 runs exactly max_iter iterations."""
     return hybrid(g, b, None, x0=x0, precond=precond, tol=tol, tol_kind=tol_kind,
-                  max_iter=max_iter, history=history)
+                  max_iter=max_iter, history=history, pc=pc)

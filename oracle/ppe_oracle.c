@@ -107,18 +107,29 @@ static void record(double* hist, int32_t cap, int32_t k, double v) {
   if (hist && k < cap) hist[k] = v;
 }
 
+/* z = M^-1 r for the preconditioner in use: diagonal (dinv) or a supplied
+ * operator (pc). Returns nonzero when the supplied operator fails. */
+static int precond_apply(int64_t n, const double* dinv, orc_provider pc, void* pc_ctx, const double* r,
+                         double* z) {
+  if (pc) return pc(pc_ctx, r, z);
+  for (int64_t m = 0; m < n; ++m) z[m] = dinv[m] * r[m];
+  return 0;
+}
+
 /*
  * Hybrid solve (Sec. 2.2). num_dlsm = 0 (or provider = NULL) gives plain PCG
- * with no restarts. precond: 0 = none (vanilla CG), 1 = Jacobi.
+ * with no restarts. precond: 0 = none (vanilla CG), 1 = Jacobi, 2 = the
+ * supplied symmetric positive (semi-)definite operator pc (z = pc(r), e.g. a
+ * multigrid V-cycle).
  * tol_kind: 0 = stop when ||r|| <= tol ||b||, 1 = stop when ||r|| <= tol.
  * tol <= 0 runs exactly max_iter iterations. x holds x0 on entry.
  * hist[0] = initial residual norm, hist[k] = norm after iteration k.
  * Returns 0 when converged, 1 otherwise.
  */
-int orc_hybrid(const orc_grid* g, const double* b, double* x, int precond,
-               double tol, int tol_kind, int max_iter, int num_cg, int num_dlsm,
-               orc_provider prov, void* ctx, orc_stats* st, double* hist,
-               int32_t hist_cap) {
+int orc_hybrid_pc(const orc_grid* g, const double* b, double* x, int precond,
+                  double tol, int tol_kind, int max_iter, int num_cg, int num_dlsm,
+                  orc_provider prov, void* ctx, orc_provider pc, void* pc_ctx,
+                  orc_stats* st, double* hist, int32_t hist_cap) {
   const int64_t n = (int64_t)g->nx * g->ny;
   double* r = (double*)malloc(sizeof(double) * n);
   double* z = (double*)malloc(sizeof(double) * n);
@@ -130,7 +141,9 @@ int orc_hybrid(const orc_grid* g, const double* b, double* x, int precond,
   memset(&s, 0, sizeof(s));
 
   orc_diag(g, dinv);
-  for (int64_t k = 0; k < n; ++k) dinv[k] = precond ? 1.0 / dinv[k] : 1.0;
+  for (int64_t k = 0; k < n; ++k) dinv[k] = precond == 1 ? 1.0 / dinv[k] : 1.0;
+  if (precond != 2) pc = NULL;
+  int pc_failed = 0;
 
   orc_apply(g, x, q);
   for (int64_t k = 0; k < n; ++k) r[k] = b[k] - q[k];
@@ -145,7 +158,7 @@ int orc_hybrid(const orc_grid* g, const double* b, double* x, int precond,
 
   while (!done && k < max_iter) {
     /* CG block, restarted from the current residual. */
-    for (int64_t m = 0; m < n; ++m) z[m] = dinv[m] * r[m];
+    if (precond_apply(n, dinv, pc, pc_ctx, r, z)) { pc_failed = 1; break; }
     memcpy(p, z, sizeof(double) * n);
     double rho = orc_dot(n, r, z);
     for (int c = 0; c < num_cg && !done && k < max_iter; ++c) {
@@ -165,13 +178,13 @@ int orc_hybrid(const orc_grid* g, const double* b, double* x, int precond,
       rnorm = sqrt(orc_dot(n, r, r));
       record(hist, hist_cap, k, rnorm);
       if (rnorm <= thr) { done = 1; break; }
-      for (int64_t m = 0; m < n; ++m) z[m] = dinv[m] * r[m];
+      if (precond_apply(n, dinv, pc, pc_ctx, r, z)) { pc_failed = 1; break; }
       const double rho_new = orc_dot(n, r, z);
       const double beta = rho_new / rho;
       rho = rho_new;
       for (int64_t m = 0; m < n; ++m) p[m] = z[m] + beta * p[m];
     }
-    if (!hybrid) break;
+    if (!hybrid || pc_failed) break;
     /* Line-search block along the supplied error directions (Eqs. 12-13). */
     for (int d = 0; d < num_dlsm && !done && k < max_iter; ++d) {
       int bad = prov(ctx, r, e) != 0;
@@ -206,6 +219,14 @@ int orc_hybrid(const orc_grid* g, const double* b, double* x, int precond,
   if (st) *st = s;
   free(r); free(z); free(p); free(q); free(dinv); free(e);
   return done ? 0 : 1;
+}
+
+int orc_hybrid(const orc_grid* g, const double* b, double* x, int precond,
+               double tol, int tol_kind, int max_iter, int num_cg, int num_dlsm,
+               orc_provider prov, void* ctx, orc_stats* st, double* hist,
+               int32_t hist_cap) {
+  return orc_hybrid_pc(g, b, x, precond, tol, tol_kind, max_iter, num_cg, num_dlsm, prov, ctx, NULL, NULL,
+                       st, hist, hist_cap);
 }
 
 /* Plain PCG: the hybrid with no line-search block. */
