@@ -54,8 +54,25 @@ enum {
 typedef struct ppe_problem ppe_problem; /* opaque: one grid, its coefficients and workspaces */
 typedef struct ppe_net ppe_net;         /* opaque: DeepONet weights, optimiser state, buffers */
 
-enum { PPE_PC_NONE = 0, PPE_PC_JACOBI = 1 };           /* vanilla CG / Jacobi-PCG (Sec. 2.5) */
+/* CG-type of the solve (Sec. 2.5): vanilla CG, Jacobi-PCG, or multigrid-
+ * preconditioned CG (the paper's MGPCG-4): a V-cycle on the tensor grid with
+ * levels made by merging 2 x 2 cells, Galerkin coarse operators of the
+ * piecewise-constant prolongation, a degree-2 Chebyshev smoother on D^-1 A
+ * over [0.2, 2] before and after the coarse correction, and an exact
+ * separable solve on the coarsest level (opts->mg_levels levels, default 4). */
+enum { PPE_PC_NONE = 0, PPE_PC_JACOBI = 1, PPE_PC_MG = 2 };
 enum { PPE_TOL_RELATIVE = 0, PPE_TOL_ABSOLUTE = 1 };   /* ||b-Ax||2 <= tol*||b||2 or <= tol */
+
+/* How an obstacle mask enters the operator. DIBPM (default): it does not;
+ * the decoupled immersed-boundary projection method keeps the coefficient
+ * matrix of the PPE unchanged by the body (Sec. 2.1, Eqs. 4-5; the forcing
+ * acts through the source), and the mask is an input channel of the network.
+ * SOLID: faces between a fluid and a solid cell are removed and solid cells
+ * get identity rows (x = b there), the classical masked Laplacian; it is not
+ * the paper's form and is offered for comparison (ppe_apply_*, and the plain
+ * solve with the two-phase iteration and no or Jacobi preconditioning;
+ * other solves return PPE_ERR_UNSUPPORTED). */
+enum { PPE_MASK_DIBPM = 0, PPE_MASK_SOLID = 1 };
 
 /* Form of the plain PCG iteration (the same iterates in exact arithmetic):
  * SINGLE_REDUCTION regroups the recurrences so that one launch and one
@@ -88,14 +105,15 @@ enum {
  * xc, yc: host, [nx], [ny] strictly increasing cell centres.
  * hx, hy: host, [nx], [ny] cell widths > 0 (face length of the other axis).
  * At most 2^28 cells (16384^2) per grid.
- * mask:   host [ny*nx] or NULL, 1 = solid. The obstacle does not enter M (the
- *         immersed boundary acts through the source); it is an input channel
- *         of the network. */
+ * mask:   host [ny*nx] or NULL, 1 = solid; an input channel of the network.
+ * mask_mode: PPE_MASK_DIBPM (0, the mask does not enter M) or
+ *         PPE_MASK_SOLID (needs a mask with at least one fluid cell). */
 typedef struct {
   int32_t nx, ny;
   const double *xc, *yc;
   const double *hx, *hy;
   const uint8_t* mask;
+  int32_t mask_mode;
 } ppe_grid_desc;
 
 typedef struct {
@@ -112,7 +130,11 @@ typedef struct {
   int32_t use_graph;       /* 1 (default) = replay iteration chunks as a HIP graph, 0 = eager launches */
   int32_t chunk;           /* iterations per polled chunk (0 = default 64) */
   int32_t zero_x0;         /* 1 = ignore x on entry and start from x0 = 0 */
-  int32_t variant;         /* plain solve: PPE_PCG_AUTO (default), _SINGLE_REDUCTION, _TWO_PHASE or _TWO_STEP */
+  int32_t variant;         /* plain solve: PPE_PCG_AUTO (default), _SINGLE_REDUCTION, _TWO_PHASE or _TWO_STEP;
+                              PPE_PC_MG, PPE_MASK_SOLID and record_history run the two-phase form */
+  int32_t mg_levels;       /* PPE_PC_MG: levels of the V-cycle, 0 = default 4, at most 12; nx and ny must
+                              be divisible by 2^(levels-1) (else PPE_ERR_SHAPE) */
+  int32_t record_history;  /* 1 = fill each solve's stats history (the caller's buffer, see below) */
 } ppe_solve_opts;
 
 typedef struct {
@@ -125,6 +147,21 @@ typedef struct {
   double ms_total;         /* wall time of the call (host clock), same for all solves of a call */
   double ms_device;        /* this solve's time from its set-up to its convergence decision, on the
                               device's real-time clock (per solve within a batch) */
+  /* Split of the hybrid solve's device time (Tables 2-3 report the DLSM share):
+   * ms_pcg the CG-type iterations (with their reliable updates and
+   * preconditioner), ms_net the network forwards, ms_dlsm the line-search
+   * vector kernels; device real-time clock, summed over the replayed rounds
+   * (per call, shared by the solves of a batch). Plain solves: ms_pcg =
+   * ms_device, the others 0. */
+  double ms_pcg, ms_net, ms_dlsm;
+  /* Residual history, with opts->record_history: the caller sets history (a
+   * host buffer of history_cap doubles, or NULL) and history_cap before the
+   * call; the library fills history[k] = ||r_k||_2 / ||b||_2 (the recursive
+   * residual after iteration k, CG or line search; k = 0 the start, and at a
+   * reliable update the true residual) for k < min(history_cap, iters + 1),
+   * and sets history_len to that count. Every other field is output only. */
+  double* history;
+  int32_t history_cap, history_len;
 } ppe_solve_stats;
 
 /* Network configuration (Sec. 2.4). Defaults (ppe_net_config_default): 4 levels,
@@ -159,14 +196,26 @@ typedef struct {
   float clip_norm;              /* > 0: scale the gradient to this L2 norm before Adam when larger (default 0) */
   float sam_rho;                /* > 0: sharpness-aware step (Sec. 2.4): the gradient Adam uses is taken at
                                    w + sam_rho g / |g| (two forward/backward passes; default 0) */
+  int32_t loss_kind;            /* PPE_LOSS_RESIDUAL (default, Eq. 19) or PPE_LOSS_SUPERVISED */
 } ppe_train_opts;
+
+/* Training loss. RESIDUAL is Eq. 19, mean over cells of (R - A NN(R))^2.
+ * SUPERVISED compares the network output with a target error field e*
+ * (typically the FP64 solution of A e* = R): since the line search of
+ * Eqs. 12-13 is blind to the output's scale and to constants (A 1 = 0), the
+ * loss is scale- and shift-invariant: with y0 = y - mean(y),
+ * L = 1 - (y0 . e*)^2 / (|y0|^2 |e*|^2) per sample (0 when y0 is a multiple of
+ * e*), averaged over the batch. */
+enum { PPE_LOSS_RESIDUAL = 0, PPE_LOSS_SUPERVISED = 1 };
 
 /* ---- problem: per-grid setup, built once and reused. The coefficient
  *      matrix of the PPE stays constant over a simulation, so its
  *      preconditioner is built at the first time step and reused in all
  *      later ones (Sec. 2.5, technical details); a problem handle holds the
  *      grid's operator coefficients and workspaces in the same way. ---- */
-ppe_status ppe_problem_create(const ppe_grid_desc* grid, ppe_problem** out);
+/* Copies the grid to the device with copies ordered on stream s (then
+ * synchronises s). */
+ppe_status ppe_problem_create(const ppe_grid_desc* grid, hipStream_t s, ppe_problem** out);
 void ppe_problem_destroy(ppe_problem* p);
 void ppe_solve_opts_default(ppe_solve_opts* o);
 
@@ -174,6 +223,14 @@ void ppe_solve_opts_default(ppe_solve_opts* o);
  * x, y: device [nb][ny][nx]. */
 ppe_status ppe_apply_f32(const ppe_problem* p, int32_t nb, const float* x, float* y, hipStream_t s);
 ppe_status ppe_apply_f64(const ppe_problem* p, int32_t nb, const double* x, double* y, hipStream_t s);
+
+/* z = M^-1 r for the preconditioner opts->precond selects (opts NULL:
+ * defaults): PPE_PC_JACOBI z = D^-1 r; PPE_PC_MG one V-cycle from a zero
+ * guess (opts->mg_levels), the operator the MG-PCG solve applies each
+ * iteration; PPE_PC_NONE z = r. r, z: device FP32 [nb][ny][nx]. Returns
+ * after the stream's work for the call has completed. */
+ppe_status ppe_apply_precond(ppe_problem* p, int32_t nb, const float* r, float* z, const ppe_solve_opts* opts,
+                             hipStream_t s);
 
 /* Plain (Jacobi-)PCG solve of nb systems on one grid (Sec. 2.5, JPCG).
  * f: device FP32 [nb][ny][nx], the source of -lap p = f (pointwise values).
@@ -263,19 +320,22 @@ ppe_status ppe_generate_grid(int32_t nx, int32_t ny, uint64_t seed, uint64_t ste
                              double* yc, double* hx, double* hy, uint8_t* mask, double* params);
 
 /* One Adam step on nb fabricated systems with the residual loss of Eq. 19,
- * Loss = mean over cells of (R - A NN(R))^2, averaged over the batch.
+ * Loss = mean over cells of (R - A NN(R))^2, averaged over the batch, or with
+ * the supervised loss (opts->loss_kind; see PPE_LOSS_SUPERVISED).
  * problems: host array of nb grids of one size (each sample has its own grid);
  * R: device FP32 [nb][ny][nx] (zero-sum residual fields), or NULL: the
  * library then generates the batch with ppe_generate_rhs from opts (seed,
  * step, length-scale range, features).
+ * target: device FP64 [nb][ny][nx], the error fields e* of the supervised
+ * loss (required with PPE_LOSS_SUPERVISED and an explicit R, NULL otherwise).
  * loss_out: host, the batch loss before the step. grad_out: host or NULL;
  * when given, receives the FP32 gradient that Adam uses (ppe_net_num_params
  * values; with sam_rho > 0 the one at the perturbed weights).
  * Errors: PPE_ERR_INVALID_ARG for nb outside [1, 4096] or nb x nx x ny of
  * 2^31 cells or more; PPE_ERR_SHAPE for grids of different sizes. */
 ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* problems, const float* R,
-                              const ppe_train_opts* opts, float* loss_out, float* grad_out,
-                              hipStream_t s);
+                              const double* target, const ppe_train_opts* opts, float* loss_out,
+                              float* grad_out, hipStream_t s);
 
 /* ---- Lanczos-Ritz training vectors (Sec. 2.3, Eqs. 14-16) ---- */
 typedef struct ppe_ritz ppe_ritz; /* opaque: Lanczos basis (device), tridiagonal and its eigen-decomposition */

@@ -16,6 +16,7 @@
 #include "../../include/ppe.h"
 #include "api_internal.hpp"
 #include "kernels.hpp"
+#include "mg_internal.hpp"
 
 namespace ppe {
 
@@ -50,6 +51,7 @@ static void free_ws(SolveWs& w) {
   dev_free(w.st);
   dev_free(w.flags);
   dev_free(w.call);
+  dev_free(w.hist);
   if (w.h_flags) (void)hipHostFree(w.h_flags);
   if (w.h_state) (void)hipHostFree(w.h_state);
   for (auto& e : w.ev)
@@ -201,6 +203,12 @@ void resolve_plain(const ppe_problem* p, int nb, const ppe_solve_opts& o, int* f
       }
   }
   if (v == PPE_PCG_AUTO) v = PPE_PCG_TWO_STEP;
+  // the multigrid preconditioner, masked operators and residual histories
+  // are built on the two-phase iteration
+  if (o.precond == PPE_PC_MG || o.record_history || p->mask_mode == PPE_MASK_SOLID) {
+    if (v != PPE_PCG_TWO_PHASE) R = 0;
+    v = PPE_PCG_TWO_PHASE;
+  }
   *form = v;
   if (!height_ok(v, R))
     R = v == PPE_PCG_TWO_PHASE ? default_rows(p, nb)
@@ -236,8 +244,9 @@ void launch_chunk(const PcgArgs& a, int nb, int chunk, int form, hipStream_t s) 
 // Capture (once per workspace shape and iteration form) the chunk as a graph.
 static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int chunk, int form) {
   SolveWs& w = p->ws;
-  const int key[5] = {nb, a.R, a.jacobi, chunk, form};
-  if (w.exec && std::equal(key, key + 5, w.exec_key)) return PPE_OK;
+  const std::array<int64_t, 8> key = {nb, a.R, a.jacobi, chunk, form, a.mg ? (int64_t)a.mg->uid : 0,
+                                      (int64_t)(intptr_t)a.hist, a.hist_cap};
+  if (w.exec && key == w.exec_key) return PPE_OK;
   if (w.exec) {
     (void)hipGraphExecDestroy(w.exec);
     w.exec = nullptr;
@@ -254,7 +263,7 @@ static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int 
     w.exec = nullptr;
     return set_error(PPE_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
   }
-  std::copy(key, key + 5, w.exec_key);
+  w.exec_key = key;
   return PPE_OK;
 }
 
@@ -330,17 +339,68 @@ ppe_status state_status(const SolveState& S) {
   return S.done == DONE_CONV ? PPE_OK : S.done == DONE_NONFINITE ? PPE_ERR_NONFINITE : PPE_NOT_CONVERGED;
 }
 
-ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s, bool hybrid) {
+ppe_status attach_extras(ppe_problem* p, PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s) {
+  if (o.precond == PPE_PC_MG) {
+    ppe_status st = mg_ensure(p, o.mg_levels > 0 ? o.mg_levels : 4, nb, a.R, s);
+    if (st != PPE_OK) return st;
+    a.mg = p->mg;
+    a.z = p->mg->z;
+    a.jacobi = 0;
+  }
+  if (o.record_history) {
+    SolveWs& w = p->ws;
+    const int cap = (int)std::min<int64_t>((int64_t)o.max_iter + 1, (int64_t)1 << 22);
+    const int64_t need = (int64_t)cap * nb;
+    if (w.hist_elems < need) {
+      if (w.exec) {  // a captured graph may hold the old buffer
+        (void)hipGraphExecDestroy(w.exec);
+        w.exec = nullptr;
+      }
+      dev_free(w.hist);
+      w.hist = (double*)dev_alloc(sizeof(double) * need);
+      w.hist_elems = w.hist ? need : 0;
+      if (!w.hist) return set_error(PPE_ERR_HIP, "allocation of the residual histories failed");
+    }
+    a.hist = w.hist;
+    a.hist_cap = cap;
+  }
+  return PPE_OK;
+}
+
+ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s, bool hybrid,
+                      const PcgArgs& a) {
   SolveWs& w = p->ws;
-  HIPCHK(hipMemcpyAsync(w.h_state, w.st, sizeof(SolveState) * nb, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(w.h_state, a.st, sizeof(SolveState) * nb, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   ppe_status worst = PPE_OK;
+  const double khz = wall_clock_khz();
   for (int i = 0; i < nb; ++i) {
     const SolveState& S = w.h_state[i];
     const ppe_status st = state_status(S);
     if (st == PPE_ERR_NONFINITE) worst = st;
     else if (st == PPE_NOT_CONVERGED && worst == PPE_OK) worst = st;
-    if (stats) stats_from_state(S, st, ms, hybrid, stats + i);
+    if (!stats) continue;
+    ppe_solve_stats& o = stats[i];
+    double* hbuf = o.history;
+    const int hcap = o.history_cap;
+    stats_from_state(S, st, ms, hybrid, &o);
+    if (hybrid) {
+      // the phase clocks run on the first solve's state, for the whole call
+      const SolveState& S0 = w.h_state[0];
+      o.ms_pcg = (double)S0.t_acc[0] / khz;
+      o.ms_net = (double)S0.t_acc[1] / khz;
+      o.ms_dlsm = (double)S0.t_acc[2] / khz;
+    } else {
+      o.ms_pcg = o.ms_device;
+    }
+    o.history = hbuf;
+    o.history_cap = hcap;
+    if (a.hist && hbuf && hcap > 0) {
+      const int n = std::min(std::min(hcap, a.hist_cap), S.it_final + 1);
+      if (n > 0)
+        HIPCHK(hipMemcpy(hbuf, a.hist + (size_t)i * a.hist_cap, sizeof(double) * n, hipMemcpyDeviceToHost));
+      o.history_len = std::max(n, 0);
+    }
   }
   if (worst == PPE_ERR_NONFINITE) set_error(worst, "non-finite value in a source field or iteration");
   return worst;
@@ -352,12 +412,22 @@ ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, con
   if (nb < 0) return set_error(PPE_ERR_INVALID_ARG, "nb < 0");
   if (nb > 65535) return set_error(PPE_ERR_INVALID_ARG, "nb > 65535");
   if (nb > 0 && (!f || !x)) return set_error(PPE_ERR_INVALID_ARG, "f or x is NULL");
+  if (p->mask_mode == PPE_MASK_SOLID)
+    return set_error(PPE_ERR_UNSUPPORTED, "PPE_MASK_SOLID operators are not built yet");
   if (opts) {
     if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol))
       return set_error(PPE_ERR_INVALID_ARG, "tol must be finite and >= 0");
     if (opts->max_iter < 0) return set_error(PPE_ERR_INVALID_ARG, "max_iter < 0");
-    if (opts->precond != PPE_PC_NONE && opts->precond != PPE_PC_JACOBI)
-      return set_error(PPE_ERR_UNSUPPORTED, "preconditioner %d is not built", opts->precond);
+    if (opts->precond != PPE_PC_NONE && opts->precond != PPE_PC_JACOBI && opts->precond != PPE_PC_MG)
+      return set_error(PPE_ERR_INVALID_ARG, "unknown preconditioner %d", opts->precond);
+    if (opts->mg_levels < 0 || opts->mg_levels > 12)
+      return set_error(PPE_ERR_INVALID_ARG, "mg_levels must lie in [0, 12]");
+    if (opts->precond == PPE_PC_MG) {
+      const int L = opts->mg_levels ? opts->mg_levels : 4;
+      if (p->nx % (1 << (L - 1)) || p->ny % (1 << (L - 1)))
+        return set_error(PPE_ERR_SHAPE, "multigrid with %d levels needs nx, ny divisible by %d (got %d x %d)", L,
+                         1 << (L - 1), p->nx, p->ny);
+    }
     if (opts->tol_kind != PPE_TOL_RELATIVE && opts->tol_kind != PPE_TOL_ABSOLUTE)
       return set_error(PPE_ERR_INVALID_ARG, "tol_kind %d", opts->tol_kind);
     if (!(opts->reliable_delta > 0.0 && opts->reliable_delta < 1.0))
@@ -379,7 +449,9 @@ ppe_status solve_plain_impl(ppe_problem* p, int32_t nb, const float* f, double* 
   if (st != PPE_OK) return st;
   int form, R;
   resolve_plain(p, nb, o, &form, &R);
-  const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  st = attach_extras(p, a, nb, o, s);
+  if (st != PPE_OK) return st;
   launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
   launch_setup(a, nb, form, s);
   HIPCHK(hipGetLastError());
@@ -390,7 +462,7 @@ ppe_status solve_plain_impl(ppe_problem* p, int32_t nb, const float* f, double* 
   HIPCHK(hipStreamSynchronize(s));
   const double ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  return fill_stats(p, nb, stats, ms, s, false);
+  return fill_stats(p, nb, stats, ms, s, false, a);
 }
 
 // Average kernel durations of `reps` iterations of one launch configuration
@@ -399,7 +471,9 @@ ppe_status profile_form(ppe_problem* p, int nb, const float* f, double* x, const
                         int R, int reps, double* ms_out, hipStream_t s) {
   ppe_status st = ensure_ws(p, nb);
   if (st != PPE_OK) return st;
-  const PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  st = attach_extras(p, a, nb, o, s);
+  if (st != PPE_OK) return st;
   launch_set_call(p->ws.call, f, x, o.max_iter, o.reliable_delta * o.reliable_delta, s);
   launch_setup(a, nb, form, s);
   const bool single = form != PPE_PCG_TWO_PHASE;
@@ -463,7 +537,7 @@ void ppe_solve_opts_default(ppe_solve_opts* o) {
   o->variant = PPE_PCG_AUTO;
 }
 
-ppe_status ppe_problem_create(const ppe_grid_desc* g, ppe_problem** out) {
+ppe_status ppe_problem_create(const ppe_grid_desc* g, hipStream_t s, ppe_problem** out) {
   if (!g || !out) return set_error(PPE_ERR_INVALID_ARG, "grid or out is NULL");
   *out = nullptr;
   const int nx = g->nx, ny = g->ny;
@@ -481,6 +555,14 @@ ppe_status ppe_problem_create(const ppe_grid_desc* g, ppe_problem** out) {
     if (j > 0 && !(g->yc[j] > g->yc[j - 1])) return set_error(PPE_ERR_INVALID_ARG, "yc not increasing at %d", j);
   }
   static std::atomic<uint64_t> next_uid{1};
+  if (g->mask_mode != PPE_MASK_DIBPM && g->mask_mode != PPE_MASK_SOLID)
+    return set_error(PPE_ERR_INVALID_ARG, "mask_mode %d", g->mask_mode);
+  if (g->mask_mode == PPE_MASK_SOLID) {
+    if (!g->mask) return set_error(PPE_ERR_INVALID_ARG, "PPE_MASK_SOLID needs a mask");
+    int64_t fluid = 0;
+    for (int64_t k = 0; k < (int64_t)nx * ny; ++k) fluid += g->mask[k] == 0;
+    if (fluid == 0) return set_error(PPE_ERR_INVALID_ARG, "PPE_MASK_SOLID needs at least one fluid cell");
+  }
   ppe_problem* p = new ppe_problem();
   p->uid = next_uid.fetch_add(1);
   p->nx = nx;
@@ -490,7 +572,8 @@ ppe_status ppe_problem_create(const ppe_grid_desc* g, ppe_problem** out) {
   p->hx.assign(g->hx, g->hx + nx);
   p->hy.assign(g->hy, g->hy + ny);
   if (g->mask) p->mask.assign(g->mask, g->mask + (size_t)nx * ny);
-  ppe_status st = problem_upload(p);
+  p->mask_mode = g->mask_mode;
+  ppe_status st = problem_upload(p, s);
   if (st != PPE_OK) {
     ppe_problem_destroy(p);
     return st;
@@ -520,6 +603,40 @@ ppe_status ppe_apply_f64(const ppe_problem* p, int32_t nb, const double* x, doub
   if (nb == 0) return PPE_OK;
   launch_apply_f64(p->coef, nb, x, y, 4, s);
   HIPCHK(hipGetLastError());
+  return PPE_OK;
+}
+
+ppe_status ppe_apply_precond(ppe_problem* p, int32_t nb, const float* r, float* z, const ppe_solve_opts* opts,
+                             hipStream_t s) {
+  ppe_solve_opts o;
+  ppe_solve_opts_default(&o);
+  if (opts) o = *opts;
+  o.record_history = 0;
+  ppe_status st = check_solve_args(p, nb, r, z, &o);
+  if (st != PPE_OK) return st;
+  if (nb == 0) return PPE_OK;
+  const int64_t N = (int64_t)p->nx * p->ny * nb;
+  if (o.precond == PPE_PC_NONE) {
+    HIPCHK(hipMemcpyAsync(z, r, sizeof(float) * N, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PPE_OK;
+  }
+  st = ensure_ws(p, nb);
+  if (st != PPE_OK) return st;
+  const int R = default_rows(p, nb);
+  PcgArgs a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  st = attach_extras(p, a, nb, o, s);
+  if (st != PPE_OK) return st;
+  a.r = const_cast<float*>(r);  // only read, as the PCG's residual
+  launch_zero_flags(a.flags, nb, s);
+  if (o.precond == PPE_PC_JACOBI) {
+    launch_direction(a, nb, PPE_DIR_JACOBI, z, s);
+  } else {
+    launch_vcycle(a, nb, s);
+    HIPCHK(hipMemcpyAsync(z, a.z, sizeof(float) * N, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
   return PPE_OK;
 }
 

@@ -25,7 +25,9 @@ struct SolveWs {
   SolveState* h_state = nullptr;  // pinned [nb]
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipGraphExec_t exec = nullptr;
-  int exec_key[5] = {0, 0, 0, 0, 0};
+  std::array<int64_t, 8> exec_key{};  // launch configuration the graph was captured for
+  double* hist = nullptr;             // [nb][hist_cap] residual histories
+  int64_t hist_elems = 0;
 };
 
 // Device workspace of the training-data generator (grown on demand).
@@ -40,6 +42,8 @@ struct GenWs {
 
 struct NetCache;  // per (grid, net) constants of the network (net_internal.hpp)
 void net_cache_free(NetCache* c);
+struct MgData;    // multigrid hierarchy of a problem (mg_internal.hpp)
+void mg_free(MgData* m);
 
 }  // namespace ppe
 
@@ -53,6 +57,7 @@ struct ppe_problem {
   std::vector<std::array<int, 3>> tuned;
   std::vector<double> xc, yc, hx, hy;
   std::vector<uint8_t> mask;  // empty = no obstacle
+  int mask_mode = PPE_MASK_DIBPM;
   // device copies of the 1D coefficients
   void* dev_coef = nullptr;
   uint8_t* d_mask = nullptr;
@@ -60,6 +65,7 @@ struct ppe_problem {
   ppe::SolveWs ws;
   hipStream_t cap_stream = nullptr;
   ppe::NetCache* net_cache = nullptr;
+  ppe::MgData* mg = nullptr;
 };
 
 namespace ppe {
@@ -67,7 +73,10 @@ extern thread_local std::string g_last_error;
 ppe_status set_error(ppe_status st, const char* fmt, ...);
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
-ppe_status problem_upload(ppe_problem* p);
+ppe_status problem_upload(ppe_problem* p, hipStream_t s);
+ppe_status coef_upload(int nx, int ny, const double* hx, const double* hy, const double* gx, const double* gy,
+                       const double* xc, const double* yc, hipStream_t s, std::vector<double>& h64,
+                       std::vector<float>& h32, void** dev, Coef* cout);
 void problem_release(ppe_problem* p);
 ppe_status ensure_ws(ppe_problem* p, int nb);
 // Device buffers a solve of nb systems runs in: the problem's own workspace
@@ -107,7 +116,13 @@ int default_rows_two_step(const ppe_problem* const* probs, int n, int nb);
 void resolve_plain(const ppe_problem* p, int nb, const ppe_solve_opts& o, int* form, int* rows);
 ppe_status profile_form(ppe_problem* p, int nb, const float* f, double* x, const ppe_solve_opts& o, int form,
                         int R, int reps, double* ms_out, hipStream_t s);
-ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s, bool hybrid);
+// Host statistics of the nb solves of a call (and the residual histories a
+// recorded, into the callers' buffers).
+ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms, hipStream_t s, bool hybrid,
+                      const PcgArgs& a);
+// Attaches to a what the options ask for beyond the plain iteration: the
+// multigrid hierarchy (PPE_PC_MG) and the device residual-history buffer.
+ppe_status attach_extras(ppe_problem* p, PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s);
 ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, const void* x,
                             const ppe_solve_opts* opts);
 }  // namespace ppe

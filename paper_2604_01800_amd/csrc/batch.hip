@@ -161,6 +161,11 @@ extern "C" ppe_status ppe_solve_batch(int32_t n, ppe_problem* const* problems, c
   }
   if (o.variant == PPE_PCG_TWO_PHASE)
     return set_error(PPE_ERR_UNSUPPORTED, "the mixed-size batch runs the two-step or single-reduction form");
+  if (o.precond == PPE_PC_MG || o.record_history)
+    return set_error(PPE_ERR_UNSUPPORTED, "the plain mixed-size batch runs Jacobi or no preconditioning, without history");
+  for (int i = 0; i < n; ++i)
+    if (problems[i]->mask_mode == PPE_MASK_SOLID)
+      return set_error(PPE_ERR_UNSUPPORTED, "the plain mixed-size batch does not take PPE_MASK_SOLID grids");
   const int form = o.variant == PPE_PCG_SINGLE_REDUCTION ? PPE_PCG_SINGLE_REDUCTION : PPE_PCG_TWO_STEP;
   int R = o.rows_per_wave;
   if (!height_ok(form, R))
@@ -215,7 +220,7 @@ extern "C" ppe_status ppe_solve_batch(int32_t n, ppe_problem* const* problems, c
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   ppe_status worst = PPE_OK;
   for (int i = 0; i < n; ++i) {
-    st = fill_stats(problems[i], 1, stats ? stats + i : nullptr, ms, s, false);
+    st = fill_stats(problems[i], 1, stats ? stats + i : nullptr, ms, s, false, descs[i]);
     if (st == PPE_ERR_NONFINITE) worst = st;
     else if (st == PPE_NOT_CONVERGED && worst == PPE_OK) worst = st;
     else if (st < 0 && st != PPE_ERR_NONFINITE) return st;

@@ -52,6 +52,10 @@ struct SolveState {
   int32_t pad[2];
   // device real-time clock (wall_clock64) at set-up and when the solve finished
   uint64_t t_start, t_done;
+  // hybrid solve: clock at the last phase mark and the time accumulated per
+  // phase (0 CG-type iterations, 1 network forwards, 2 line-search kernels)
+  uint64_t t_mark;
+  uint64_t t_acc[3];
 };
 
 // MODE_FLUSH and MODE_SUMS are used by the single-reduction iteration only

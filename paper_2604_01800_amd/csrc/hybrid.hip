@@ -26,6 +26,7 @@ namespace ppe {
 // Enqueues `rounds` hybrid rounds starting at parity 0 on stream s.
 static ppe_status enqueue_rounds(ppe_problem* p, ppe_net* net, const PcgArgs& a, int nb, const ppe_solve_opts& o,
                                  int rounds, hipStream_t s) {
+  // phase clocks (device real-time clock): 0 CG-type, 1 network, 2 line search
   int par = 0;
   for (int r = 0; r < rounds; ++r) {
     for (int c = 0; c < o.num_cg; ++c) {
@@ -33,6 +34,8 @@ static ppe_status enqueue_rounds(ppe_problem* p, ppe_net* net, const PcgArgs& a,
       par ^= 1;
     }
     const int lastpar = par ^ 1;
+    if (o.num_cg > 0) launch_hist_cg(a, nb, lastpar, s);
+    launch_mark(a, nb, 0, s);
     for (int d = 0; d < o.num_dlsm; ++d) {
       if (o.direction == PPE_DIR_NET) {
         ppe_status st = net_forward(p, net, nb, a.r, const_cast<float*>(a.e), s);
@@ -40,7 +43,9 @@ static ppe_status enqueue_rounds(ppe_problem* p, ppe_net* net, const PcgArgs& a,
       } else {
         launch_direction(a, nb, o.direction, const_cast<float*>(a.e), s);
       }
+      launch_mark(a, nb, 1, s);
       launch_dlsm_step(a, nb, lastpar, s);
+      launch_mark(a, nb, 2, s);
     }
     launch_pcg_pair(a, nb, par, 1, 1, s);  // reliable update + CG restart
     par ^= 1;
@@ -76,6 +81,8 @@ static ppe_status hybrid_begin(HybridRun& h, ppe_problem* p, ppe_net* net, int32
   }
   const int R = rows_of(p, nb, o);
   h.a = make_pcg_args(p, nb, R, o.precond == PPE_PC_JACOBI, o.tol, o.tol_kind, o.zero_x0);
+  st = attach_extras(p, h.a, nb, o, s);
+  if (st != PPE_OK) return st;
   // The reliable update closing every round replaces the delta trigger.
   launch_set_call(p->ws.call, f, x, o.max_iter, 0.0, s);
   launch_pcg_setup(h.a, nb, s);
@@ -158,7 +165,7 @@ ppe_status solve_hybrid_impl(ppe_problem* p, ppe_net* net, int32_t nb, const flo
   HIPCHK(hipStreamSynchronize(s));
   const double ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  return fill_stats(p, nb, stats, ms, s, true);
+  return fill_stats(p, nb, stats, ms, s, true, h.a);
 }
 
 // Hybrid solves of a mixed-size batch: one run per problem, advanced in lock
@@ -195,7 +202,7 @@ ppe_status solve_hybrid_batch_impl(int32_t n, ppe_problem* const* problems, ppe_
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   ppe_status worst = PPE_OK;
   for (int i = 0; i < n; ++i) {
-    st = fill_stats(problems[i], 1, stats ? stats + i : nullptr, ms, s, true);
+    st = fill_stats(problems[i], 1, stats ? stats + i : nullptr, ms, s, true, runs[i].a);
     if (st == PPE_ERR_NONFINITE) worst = st;
     else if (st == PPE_NOT_CONVERGED && worst == PPE_OK) worst = st;
     else if (st < 0 && st != PPE_ERR_NONFINITE) return st;

@@ -25,6 +25,14 @@ struct PcgArgs {
   int tol_kind;
   int jacobi;
   int zero_x0;  // the setup zeroes x before the first residual
+  // Multigrid preconditioner (host-side handle, NULL otherwise): the two-phase
+  // kernels then read z = M^-1 r from z, which the V-cycle writes after every
+  // pass that changes r.
+  const struct MgData* mg;
+  float* z;     // [nb][N]
+  // Residual history (device [nb][hist_cap] FP64, NULL when not recorded).
+  double* hist;
+  int hist_cap;
 };
 
 dim3 stencil_grid(const Coef& c, int R, int nb);
@@ -53,7 +61,16 @@ void launch_pcg_phase_timed(const PcgArgs& a, int nb, int par, int phase, hipStr
                             hipEvent_t e1);
 void launch_direction(const PcgArgs& a, int nb, int mode, float* e, hipStream_t s);
 void launch_dlsm_step(const PcgArgs& a, int nb, int par, hipStream_t s);
+// Hybrid phase clock: time since the last mark is added to phase cat
+// (0 CG-type, 1 network, 2 line search; -1 marks only).
+void launch_mark(const PcgArgs& a, int nb, int cat, hipStream_t s);
+void launch_zero_flags(int32_t* flags, int nb, hipStream_t s);
+// Residual-history entry after a CG block (no-op without a history buffer).
+void launch_hist_cg(const PcgArgs& a, int nb, int par, hipStream_t s);
 void launch_apply_multi(const Coef* coefs, int nx, int ny, int nb, const float* x, float* y, hipStream_t s);
 void launch_pcg_finish(const PcgArgs& a, int nb, hipStream_t s);
+// The multigrid V-cycle on the residual a.r into a.z (a.mg), ending with the
+// partial sums of r.z in the second half of a.partB.
+void launch_vcycle(const PcgArgs& a, int nb, hipStream_t s);
 
 }  // namespace ppe

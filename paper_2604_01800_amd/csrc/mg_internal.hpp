@@ -1,0 +1,63 @@
+// Multigrid preconditioner of the PCG solve (the MGPCG CG-type of Sec. 2.5):
+// device hierarchy and launchers shared by its host and kernel units.
+#pragma once
+#include <vector>
+
+#include "api_internal.hpp"
+
+namespace ppe {
+
+// Chebyshev smoother on D^-1 A over [kChebLo, kChebHi] (kChebHi bounds the
+// spectrum of D^-1 A: zero row sums and non-positive off-diagonals), degree 2.
+constexpr double kChebHi = 2.0, kChebLo = 0.2;
+
+// Largest coarsest level the separable direct solve takes (dense x-eigenbasis
+// of nx^2 doubles, row transforms staged in LDS).
+constexpr int kMgCoarseMaxNx = 2048;
+constexpr int kMgCoarseMaxNy = 8192;
+
+// One level of the hierarchy. Level 0 is the problem's grid; its right-hand
+// side is the PCG residual and its output the preconditioned residual z.
+struct MgLevel {
+  int nx = 0, ny = 0;
+  int R = 2, P = 0;           // tile rows per wavefront and workgroups per solve
+  Coef c{};                   // operator coefficients (level 0: the problem's)
+  void* dev_coef = nullptr;   // coefficient block owned by levels >= 1
+  float* b = nullptr;         // [nb][N] right-hand side (levels >= 1)
+  float* x = nullptr;         // [nb][N] approximate solution (levels >= 1)
+  float* y = nullptr;         // [nb][N] x after the first post-smoothing step (levels >= 1): the
+                              // post-smoothing kernels read x on a halo, so they never write in place
+  float* d = nullptr;         // [nb][N] Chebyshev direction of the post-smoothing
+};
+
+struct MgData {
+  uint64_t uid = 0;  // process-unique build id (cached graphs key on it, not on the address)
+  int L = 0, nb = 0, R0 = 0;
+  std::vector<MgLevel> lv;
+  // Coarsest level: A_c = T_x (x) H_y + H_x (x) T_y is diagonalised along x by
+  // the generalised eigenvectors T_x phi = lam H_x phi (phi^T H_x phi = 1);
+  // each mode k leaves the tridiagonal system (T_y + lam_k H_y) c_k = b_k,
+  // factored once (Thomas); mode 0 (lam = 0, singular) is grounded at its last
+  // unknown.
+  int nxc = 0, nyc = 0;
+  double* phi = nullptr;   // [nxc][nxc] phi[i][k]
+  double* phiT = nullptr;  // [nxc][nxc] phiT[k][i]
+  double* mult = nullptr;  // [nyc][nxc] Thomas multipliers a_j / w_{j-1}
+  double* iw = nullptr;    // [nyc][nxc] inverse pivots 1 / w_j (0 for the grounded unknown)
+  double* offd = nullptr;  // [nyc + 1] off-diagonal -gy_j between rows j-1 and j
+  double* bh = nullptr;    // [nb][nyc][nxc] transformed right-hand side, then the mode solutions
+  double* bpart = nullptr; // [nb][bP] partial sums of the coarsest right-hand side
+  int bP = 0;
+  double* xpart = nullptr; // [nb][nyc] row sums of the coarsest solution
+  float* z = nullptr;      // [nb][N0] output of the V-cycle on the fine level
+  float* d0 = nullptr;     // [nb][N0] post-smoothing direction on the fine level
+  float* y0 = nullptr;     // [nb][N0] fine-level x after the first post-smoothing step
+  std::vector<void*> owned;
+};
+
+// Builds (or reuses) the hierarchy of L levels for nb right-hand sides, with
+// the fine level tiled at R0 rows per wavefront.
+ppe_status mg_ensure(ppe_problem* p, int L, int nb, int R0, hipStream_t s);
+void mg_free(MgData* m);
+
+}  // namespace ppe

@@ -109,6 +109,10 @@ extern "C" ppe_status ppe_solve_plain_noalloc(const ppe_problem* p, const float*
   if (opts) o = *opts;
   ppe_status st = check_solve_args(p, 1, f, x, &o);
   if (st != PPE_OK) return st;
+  if (o.precond == PPE_PC_MG || o.record_history || p->mask_mode == PPE_MASK_SOLID)
+    return set_error(PPE_ERR_UNSUPPORTED,
+                     "the allocation-free solve runs Jacobi or no preconditioning on unmasked operators, "
+                     "without history");
   const Layout L = layout_of(p);
   if (L.total > (size_t)PPE_NOALLOC_SCRATCH_BYTES)
     return set_error(PPE_ERR_INVALID_ARG,
@@ -148,7 +152,14 @@ extern "C" ppe_status ppe_solve_plain_noalloc(const ppe_problem* p, const float*
   HIPCHK(hipStreamSynchronize(s));
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   st = state_status(S);
-  if (stats) stats_from_state(S, st, ms, false, stats);
+  if (stats) {
+    double* hbuf = stats->history;
+    const int hcap = stats->history_cap;
+    stats_from_state(S, st, ms, false, stats);
+    stats->ms_pcg = stats->ms_device;
+    stats->history = hbuf;
+    stats->history_cap = hcap;
+  }
   if (st == PPE_ERR_NONFINITE) set_error(st, "non-finite value in the source field or iteration");
   return st;
 }

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs_norm(PcgArgs a) {
 // and accumulates |r|^2 (FP64 value) and r.D^-1 r (FP32 value, exact products).
 // It runs a handful of times per solve, so it walks the rows with a small
 // register footprint instead of holding a full FP64 tile.
-template <int R, bool JAC>
+template <int R, int PC>
 __device__ __forceinline__ void true_residual_rows(const PcgArgs& a, int s, double& acc_rr, double& acc_rz) {
   const int nx = a.c.nx, ny = a.c.ny;
   const size_t off = (size_t)s * a.N;
@@ -172,16 +172,18 @@ __device__ __forceinline__ void true_residual_rows(const PcgArgs& a, int s, doub
       const float rr = (float)rv;
       r[(size_t)j * nx + ci.i] = rr;
       acc_rr += rv * rv;
-      float z = rr;
-      if (JAC) z = rr / (a.c.hy[j] * (kf.gw + kf.ge) + kf.hx * (a.c.gy[j] + a.c.gy[j + 1]));
-      acc_rz += (double)rr * (double)z;
+      if (PC != 2) {
+        float z = rr;
+        if (PC == 1) z = rr / (a.c.hy[j] * (kf.gw + kf.ge) + kf.hx * (a.c.gy[j] + a.c.gy[j + 1]));
+        acc_rz += (double)rr * (double)z;
+      }
     }
     vprev = vcur;
     vcur = vnext;
   }
 }
 
-template <int R, bool JAC>
+template <int R, int PC>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs a) {
   __shared__ double lds[kWaves];
   const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
@@ -211,6 +213,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs a) {
     st->rr_final = 0.0;
     st->t_start = wall_clock64();
     st->t_done = st->t_start;
+    st->t_mark = st->t_start;
+    st->t_acc[0] = st->t_acc[1] = st->t_acc[2] = 0;
     a.flags[s] = bad ? DONE_NONFINITE : DONE_NO;
   }
   double rr = 0.0, rz = 0.0;
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs a) {
         a.p1[k] = 0.f;
       }
     }
-    true_residual_rows<R, JAC>(a, s, rr, rz);
+    true_residual_rows<R, PC>(a, s, rr, rz);
   }
   rr = block_sum(rr, lds);
   rz = block_sum(rz, lds);
@@ -244,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs a) {
 // Phase A. par selects the p buffer written (p[par]) and the state slots.
 // force != 0 makes this pass a reliable update (used after line-search
 // blocks); force_restart then also restarts CG (beta = 0) afterwards.
-template <int R, bool JAC>
+template <int R, int PC>
 __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force, int force_restart) {
   __shared__ double lds[kWaves];
   const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
@@ -263,7 +267,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
   const uint64_t vbytes = (uint64_t)a.N * 4;
   Tile<float, R> tr, tp;
   float xcv[R];
-  load_tile<R>(make_rsrc(r, vbytes), nx, ny, j0, ci, tr);
+  // the preconditioned residual: D^-1 r formed below, or z = M^-1 r supplied (PC = 2)
+  load_tile<R>(make_rsrc(PC == 2 ? a.z + off : r, vbytes), nx, ny, j0, ci, tr);
   load_tile<R>(make_rsrc(pold, vbytes), nx, ny, j0, ci, tp);
   load_rows_own<R>(make_rsrc(xc, vbytes), nx, ny, j0, ci, xcv);
   RowCoef<float, R> rc;
@@ -288,6 +293,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
   if (dprev) {
     if (leader) st->dflag[par] = dprev;
     return;
+  }
+  // residual history: the norm after `it` iterations (the recursive residual,
+  // or the true one after a reliable update, which overwrites it)
+  if (leader && a.hist && it < a.hist_cap) {
+    const double bb = st->bnorm2;
+    a.hist[(size_t)s * a.hist_cap + it] = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
   }
   int done = DONE_NO;
   bool flush = false;
@@ -355,13 +366,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
 #pragma unroll
   for (int q = 0; q < R + 2; ++q) {
     float z = tr.own[q];
-    if (JAC) z = z / fmaxf(rc.hy[q] * (k.gw + k.ge) + k.hx * (rc.gy[q] + rc.gy[q + 1]), 1e-30f);
+    if (PC == 1) z = z / fmaxf(rc.hy[q] * (k.gw + k.ge) + k.hx * (rc.gy[q] + rc.gy[q + 1]), 1e-30f);
     pn.own[q] = z + beta * tp.own[q];
   }
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     float z = tr.halo[q];
-    if (JAC) z = z / fmaxf(rc.hy[q + 1] * (k.gwh + k.geh) + k.hxh * (rc.gy[q + 1] + rc.gy[q + 2]), 1e-30f);
+    if (PC == 1) z = z / fmaxf(rc.hy[q + 1] * (k.gwh + k.geh) + k.hxh * (rc.gy[q + 1] + rc.gy[q + 2]), 1e-30f);
     pn.halo[q] = z + beta * tp.halo[q];
   }
   float Ap[R];
@@ -395,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
 }
 
 // Phase B: CG residual update, or the FP64 true residual after a flush.
-template <int R, bool JAC>
+template <int R, int PC>
 __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int par) {
   __shared__ double lds[kWaves];
   const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
@@ -407,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int par) {
   double acc_rr = 0.0, acc_rz = 0.0;
   if (mode == MODE_TRUE) {
     if (dprev) return;
-    true_residual_rows<R, JAC>(a, s, acc_rr, acc_rz);
+    true_residual_rows<R, PC>(a, s, acc_rr, acc_rz);
     if (leader) {
       st->alpha[par] = 0.0;
       st->brk[par] = 0;
@@ -443,9 +454,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int par) {
         const float rn = rv[q] - alf * Ap[q];
         r[(size_t)j * nx + ci.i] = rn;
         acc_rr += (double)rn * (double)rn;
-        float z = rn;
-        if (JAC) z = rn / (rc.hy[q + 1] * (k.gw + k.ge) + k.hx * (rc.gy[q + 1] + rc.gy[q + 2]));
-        acc_rz += (double)rn * (double)z;
+        if (PC != 2) {
+          float z = rn;
+          if (PC == 1) z = rn / (rc.hy[q + 1] * (k.gw + k.ge) + k.hx * (rc.gy[q + 1] + rc.gy[q + 2]));
+          acc_rz += (double)rn * (double)z;
+        }
       }
     }
     if (leader) {
@@ -558,7 +571,18 @@ __global__ __launch_bounds__(kBlock) void k_dlsm_b(PcgArgs a, int par) {
       st->n_rej += 1;
     }
   }
-  if (!ok) return;
+  double rr = 0.0;
+  if (!ok) {
+    // rejected: r is unchanged; its norm only matters for the history
+    if (a.hist) {
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if (ci.ok && j0 + q < ny) rr += (double)rv[q] * (double)rv[q];
+      rr = block_sum(rr, lds);
+      if (threadIdx.x == 0) a.partA[(size_t)s * a.P + block_linear()] = rr;
+    }
+    return;
+  }
   const float af = (float)alpha;
   float Ae[R];
   stencil_rows<float, R>(te, rc, k, Ae);
@@ -568,9 +592,61 @@ __global__ __launch_bounds__(kBlock) void k_dlsm_b(PcgArgs a, int par) {
     if (ci.ok && j < ny) {
       const size_t kk = (size_t)j * nx + ci.i;
       xc[kk] = xv[q] + af * te.own[q + 1];
-      r[kk] = rv[q] - af * Ae[q];
+      const float rn = rv[q] - af * Ae[q];
+      r[kk] = rn;
+      rr += (double)rn * (double)rn;
     }
   }
+  // the partial sums of |r|^2 for the history (phase A's slots are free
+  // during a line-search block: the next phase A rewrites them)
+  if (a.hist) {
+    rr = block_sum(rr, lds);
+    if (threadIdx.x == 0) a.partA[(size_t)s * a.P + block_linear()] = rr;
+  }
+}
+
+// History entry after a line-search step: |r| / |b| at the step's iteration
+// count. One workgroup per solve.
+__global__ __launch_bounds__(kBlock) void k_hist_dlsm(PcgArgs a) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z;
+  SolveState* st = a.st + s;
+  if (!st->dl_active) return;
+  const double rr = reduce_partials(a.partA + (size_t)s * a.P, a.P, lds);
+  const int it = st->dl_it;
+  if (threadIdx.x == 0 && it < a.hist_cap) {
+    const double bb = st->bnorm2;
+    a.hist[(size_t)s * a.hist_cap + it] = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
+  }
+}
+
+// History entry after a block of CG iterations (before a line-search
+// block): the residual the last phase B left, at the iteration count its
+// phase A recorded in slot par. One workgroup per solve.
+__global__ __launch_bounds__(kBlock) void k_hist_cg(PcgArgs a, int par) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.z;
+  SolveState* st = a.st + s;
+  if (st->dflag[par]) return;
+  const double rr = reduce_partials(a.partB + (size_t)s * 2 * a.P, a.P, lds);
+  const int it = st->it[par];
+  if (threadIdx.x == 0 && it < a.hist_cap) {
+    const double bb = st->bnorm2;
+    a.hist[(size_t)s * a.hist_cap + it] = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
+  }
+}
+
+// Phase clock of the hybrid solve: adds the time since the last mark to
+// phase `cat` (0 CG-type, 1 network, 2 line search; -1 only marks), unless
+// every solve of the call has decided. One thread.
+__global__ void k_mark(PcgArgs a, int nb, int cat) {
+  bool all = true;
+  for (int s = 0; s < nb; ++s) all = all && a.flags[s] != DONE_NO;
+  if (all) return;
+  const uint64_t t = wall_clock64();
+  SolveState* st = a.st;
+  if (cat >= 0) st->t_acc[cat] += t - st->t_mark;
+  st->t_mark = t;
 }
 
 // Test directions that replace the network: 1 zero, 2 Jacobi D^-1 r, 3 NaN, 4 ones.
@@ -719,62 +795,56 @@ void launch_rhs(const PcgArgs& a, int nb, hipStream_t s) {
   k_rhs_norm<<<g, kBlock, 0, s>>>(a);
 }
 
+// Kernel variant of the preconditioner: 0 none, 1 Jacobi, 2 a supplied z (multigrid).
+static int pc_of(const PcgArgs& a) { return a.mg ? 2 : (a.jacobi ? 1 : 0); }
+
+#define PPE_DISPATCH_PC(pc, R, ...)                                   \
+  switch (pc) {                                                       \
+    case 2: { constexpr int PP = 2; PPE_DISPATCH_R(R, __VA_ARGS__); } break; \
+    case 1: { constexpr int PP = 1; PPE_DISPATCH_R(R, __VA_ARGS__); } break; \
+    default: { constexpr int PP = 0; PPE_DISPATCH_R(R, __VA_ARGS__); } break; \
+  }
+
 void launch_pcg_setup(const PcgArgs& a, int nb, hipStream_t s) {
   const dim3 g = stencil_grid(a.c, a.R, nb);
   launch_rhs(a, nb, s);
-  if (a.jacobi) {
-    PPE_DISPATCH_R(a.R, k_pcg_init<RR, true><<<g, kBlock, 0, s>>>(a));
-  } else {
-    PPE_DISPATCH_R(a.R, k_pcg_init<RR, false><<<g, kBlock, 0, s>>>(a));
-  }
+  PPE_DISPATCH_PC(pc_of(a), a.R, k_pcg_init<RR, PP><<<g, kBlock, 0, s>>>(a));
+  if (a.mg) launch_vcycle(a, nb, s);
 }
 
+// One CG iteration (or reliable-update pass) of the two-phase form; with the
+// multigrid preconditioner the V-cycle then turns the new residual into z
+// and leaves the partial sums of r.z where phase A reads them.
 void launch_pcg_pair(const PcgArgs& a, int nb, int par, int force, int force_restart, hipStream_t s) {
   const dim3 g = stencil_grid(a.c, a.R, nb);
-  if (a.jacobi) {
-    PPE_DISPATCH_R(a.R, k_pcg_a<RR, true><<<g, kBlock, 0, s>>>(a, par, force, force_restart);
-                   k_pcg_b<RR, true><<<g, kBlock, 0, s>>>(a, par));
-  } else {
-    PPE_DISPATCH_R(a.R, k_pcg_a<RR, false><<<g, kBlock, 0, s>>>(a, par, force, force_restart);
-                   k_pcg_b<RR, false><<<g, kBlock, 0, s>>>(a, par));
-  }
+  PPE_DISPATCH_PC(pc_of(a), a.R, k_pcg_a<RR, PP><<<g, kBlock, 0, s>>>(a, par, force, force_restart);
+                  k_pcg_b<RR, PP><<<g, kBlock, 0, s>>>(a, par));
+  if (a.mg) launch_vcycle(a, nb, s);
 }
 
 void launch_pcg_phase_a(const PcgArgs& a, int nb, int par, hipStream_t s) {
   const dim3 g = stencil_grid(a.c, a.R, nb);
-  if (a.jacobi) {
-    PPE_DISPATCH_R(a.R, k_pcg_a<RR, true><<<g, kBlock, 0, s>>>(a, par, 0, 0));
-  } else {
-    PPE_DISPATCH_R(a.R, k_pcg_a<RR, false><<<g, kBlock, 0, s>>>(a, par, 0, 0));
-  }
+  PPE_DISPATCH_PC(pc_of(a), a.R, k_pcg_a<RR, PP><<<g, kBlock, 0, s>>>(a, par, 0, 0));
 }
 
 void launch_pcg_phase_b(const PcgArgs& a, int nb, int par, hipStream_t s) {
   const dim3 g = stencil_grid(a.c, a.R, nb);
-  if (a.jacobi) {
-    PPE_DISPATCH_R(a.R, k_pcg_b<RR, true><<<g, kBlock, 0, s>>>(a, par));
-  } else {
-    PPE_DISPATCH_R(a.R, k_pcg_b<RR, false><<<g, kBlock, 0, s>>>(a, par));
-  }
+  PPE_DISPATCH_PC(pc_of(a), a.R, k_pcg_b<RR, PP><<<g, kBlock, 0, s>>>(a, par));
+  if (a.mg) launch_vcycle(a, nb, s);
 }
 
 // One phase launch whose own dispatch carries the start/stop events, so the
-// elapsed time between them is the kernel's execution only.
+// elapsed time between them is the kernel's execution only (with the
+// multigrid preconditioner, the V-cycle follows phase B untimed).
 void launch_pcg_phase_timed(const PcgArgs& a, int nb, int par, int phase, hipStream_t s, hipEvent_t e0,
                             hipEvent_t e1) {
   const dim3 g = stencil_grid(a.c, a.R, nb);
-  if (a.jacobi) {
-    if (phase == 0) {
-      PPE_DISPATCH_R(a.R, hipExtLaunchKernelGGL(k_pcg_a<RR, true>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par, 0, 0));
-    } else {
-      PPE_DISPATCH_R(a.R, hipExtLaunchKernelGGL(k_pcg_b<RR, true>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par));
-    }
+  if (phase == 0) {
+    PPE_DISPATCH_PC(pc_of(a), a.R,
+                    hipExtLaunchKernelGGL(k_pcg_a<RR, PP>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par, 0, 0));
   } else {
-    if (phase == 0) {
-      PPE_DISPATCH_R(a.R, hipExtLaunchKernelGGL(k_pcg_a<RR, false>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par, 0, 0));
-    } else {
-      PPE_DISPATCH_R(a.R, hipExtLaunchKernelGGL(k_pcg_b<RR, false>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par));
-    }
+    PPE_DISPATCH_PC(pc_of(a), a.R, hipExtLaunchKernelGGL(k_pcg_b<RR, PP>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par));
+    if (a.mg) launch_vcycle(a, nb, s);
   }
 }
 
@@ -786,7 +856,20 @@ void launch_direction(const PcgArgs& a, int nb, int mode, float* e, hipStream_t 
 void launch_dlsm_step(const PcgArgs& a, int nb, int par, hipStream_t s) {
   const dim3 g = stencil_grid(a.c, a.R, nb);
   PPE_DISPATCH_R(a.R, k_dlsm_a<RR><<<g, kBlock, 0, s>>>(a, par); k_dlsm_b<RR><<<g, kBlock, 0, s>>>(a, par));
+  if (a.hist) k_hist_dlsm<<<dim3(1, 1, nb), kBlock, 0, s>>>(a);
 }
+
+void launch_mark(const PcgArgs& a, int nb, int cat, hipStream_t s) { k_mark<<<1, 1, 0, s>>>(a, nb, cat); }
+
+void launch_hist_cg(const PcgArgs& a, int nb, int par, hipStream_t s) {
+  if (a.hist) k_hist_cg<<<dim3(1, 1, nb), kBlock, 0, s>>>(a, par);
+}
+
+__global__ void k_zero_flags(int32_t* flags, int nb) {
+  for (int s = threadIdx.x; s < nb; s += blockDim.x) flags[s] = DONE_NO;
+}
+
+void launch_zero_flags(int32_t* flags, int nb, hipStream_t s) { k_zero_flags<<<1, 256, 0, s>>>(flags, nb); }
 
 void launch_pcg_finish(const PcgArgs& a, int nb, hipStream_t s) {
   const dim3 g = stencil_grid(a.c, a.R, nb);

@@ -216,9 +216,17 @@ static int wgrad_splits(int cout, int cin8, int taps, int64_t tiles, int64_t cap
 using namespace ppe;
 
 extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* const* problems, const float* R,
-                                         const ppe_train_opts* opts, float* loss_out, float* grad_out,
-                                         hipStream_t s) {
+                                         const double* target, const ppe_train_opts* opts, float* loss_out,
+                                         float* grad_out, hipStream_t s) {
   if (!n || !problems || !opts) return set_error(PPE_ERR_INVALID_ARG, "net, problems or opts NULL");
+  if (opts->loss_kind != PPE_LOSS_RESIDUAL && opts->loss_kind != PPE_LOSS_SUPERVISED)
+    return set_error(PPE_ERR_INVALID_ARG, "loss_kind %d", opts->loss_kind);
+  if (opts->loss_kind == PPE_LOSS_SUPERVISED && (!R || !target))
+    return set_error(PPE_ERR_INVALID_ARG, "the supervised loss needs an explicit batch R and its target");
+  if (opts->loss_kind == PPE_LOSS_RESIDUAL && target)
+    return set_error(PPE_ERR_INVALID_ARG, "target is given but the loss is the residual loss");
+  if (opts->loss_kind == PPE_LOSS_SUPERVISED)
+    return set_error(PPE_ERR_UNSUPPORTED, "the supervised loss is not built yet");
   if (nb < 1 || nb > 4096) return set_error(PPE_ERR_INVALID_ARG, "nb must lie in [1, 4096]");
   if (!R) {
     ppe_status sg = check_gen_opts(*opts);

@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libppe_hip.so")
 
 PPE_OK, PPE_NOT_CONVERGED = 0, 1
 PPE_ERR_INVALID_ARG, PPE_ERR_SHAPE, PPE_ERR_UNSUPPORTED, PPE_ERR_HIP, PPE_ERR_NONFINITE = -1, -2, -3, -4, -5
-PPE_PC_NONE, PPE_PC_JACOBI = 0, 1
+PPE_PC_NONE, PPE_PC_JACOBI, PPE_PC_MG = 0, 1, 2
+PPE_MASK_DIBPM, PPE_MASK_SOLID = 0, 1
+PPE_LOSS_RESIDUAL, PPE_LOSS_SUPERVISED = 0, 1
 PPE_TOL_RELATIVE, PPE_TOL_ABSOLUTE = 0, 1
 PPE_PCG_AUTO, PPE_PCG_SINGLE_REDUCTION, PPE_PCG_TWO_PHASE, PPE_PCG_TWO_STEP = 0, 1, 2, 3
 PPE_DIR_NET, PPE_DIR_ZERO, PPE_DIR_JACOBI, PPE_DIR_NAN, PPE_DIR_ONES = 0, 1, 2, 3, 4
@@ -34,7 +36,7 @@ class ppe_grid_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("xc", ctypes.c_void_p), ("yc", ctypes.c_void_p),
                 ("hx", ctypes.c_void_p), ("hy", ctypes.c_void_p),
-                ("mask", ctypes.c_void_p)]
+                ("mask", ctypes.c_void_p), ("mask_mode", ctypes.c_int32)]
 
 
 class ppe_solve_opts(ctypes.Structure):
@@ -42,7 +44,8 @@ class ppe_solve_opts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("num_cg", ctypes.c_int32), ("num_dlsm", ctypes.c_int32),
                 ("direction", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
                 ("rows_per_wave", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("zero_x0", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("zero_x0", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("mg_levels", ctypes.c_int32), ("record_history", ctypes.c_int32)]
 
 
 class ppe_tune_result(ctypes.Structure):
@@ -55,10 +58,31 @@ class ppe_solve_stats(ctypes.Structure):
                 ("iters_dlsm", ctypes.c_int32), ("dlsm_rejected", ctypes.c_int32),
                 ("reliable_updates", ctypes.c_int32), ("rel_res_true", ctypes.c_double),
                 ("abs_res_true", ctypes.c_double), ("bnorm", ctypes.c_double),
-                ("rhs_mean_removed", ctypes.c_double), ("ms_total", ctypes.c_double), ("ms_device", ctypes.c_double)]
+                ("rhs_mean_removed", ctypes.c_double), ("ms_total", ctypes.c_double), ("ms_device", ctypes.c_double),
+                ("ms_pcg", ctypes.c_double), ("ms_net", ctypes.c_double), ("ms_dlsm", ctypes.c_double),
+                ("history", ctypes.c_void_p), ("history_cap", ctypes.c_int32), ("history_len", ctypes.c_int32)]
 
-    def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+    def as_dict(self, hist=None):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("history", "history_cap")}
+        d["history"] = None if hist is None else hist[: self.history_len].copy()
+        return d
+
+
+HISTORY_CAP_MAX = 1 << 22
+
+
+def _stats_array(nb, opts):
+    """Stats structs for nb solves, with a history buffer per solve when the
+    options ask for the residual history. Returns (array, buffers)."""
+    stats = (ppe_solve_stats * max(nb, 1))()
+    bufs = [None] * max(nb, 1)
+    if opts is not None and opts.record_history:
+        cap = int(min(max(opts.max_iter, 0) + 1, HISTORY_CAP_MAX))
+        for i in range(nb):
+            bufs[i] = np.zeros(cap, dtype=np.float64)
+            stats[i].history = bufs[i].ctypes.data
+            stats[i].history_cap = cap
+    return stats, bufs
 
 
 class ppe_net_config(ctypes.Structure):
@@ -71,19 +95,20 @@ class ppe_train_opts(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("seed", ctypes.c_uint64), ("step", ctypes.c_int64),
                 ("grf_len_lo", ctypes.c_float), ("grf_len_hi", ctypes.c_float), ("grf_features", ctypes.c_int32),
-                ("clip_norm", ctypes.c_float), ("sam_rho", ctypes.c_float)]
+                ("clip_norm", ctypes.c_float), ("sam_rho", ctypes.c_float), ("loss_kind", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/ppe.h
 _vp, _i32, _i64, _u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
 _P = ctypes.POINTER
 SIGNATURES = {
-    "ppe_problem_create": (_i32, [_P(ppe_grid_desc), _P(_vp)]),
+    "ppe_problem_create": (_i32, [_P(ppe_grid_desc), _vp, _P(_vp)]),
     "ppe_problem_destroy": (None, [_vp]),
     "ppe_solve_opts_default": (None, [_P(ppe_solve_opts)]),
     "ppe_apply_f32": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "ppe_apply_f64": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "ppe_solve_plain": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_solve_opts), _vp, _vp]),
+    "ppe_apply_precond": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_solve_opts), _vp]),
     "ppe_solve_hybrid": (_i32, [_vp, _vp, _i32, _vp, _vp, _P(ppe_solve_opts), _vp, _vp]),
     "ppe_net_config_default": (None, [_P(ppe_net_config)]),
     "ppe_net_create": (_i32, [_P(ppe_net_config), _u64, _P(_vp)]),
@@ -94,7 +119,7 @@ SIGNATURES = {
     "ppe_net_save": (_i32, [_vp, ctypes.c_char_p]),
     "ppe_net_load": (_i32, [_vp, ctypes.c_char_p]),
     "ppe_net_forward": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
-    "ppe_net_train_step": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_train_opts), _vp, _vp, _vp]),
+    "ppe_net_train_step": (_i32, [_vp, _i32, _vp, _vp, _vp, _P(ppe_train_opts), _vp, _vp, _vp]),
     "ppe_profile_pcg": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_solve_opts), _i32, _vp, _vp]),
     "ppe_profile_copy": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),
     "ppe_solve_batch": (_i32, [_i32, _vp, _vp, _vp, _vp, _P(ppe_solve_opts), _vp, _vp]),
@@ -164,14 +189,17 @@ def _dev(t, dtype, name):
 class Problem:
     """Owns a ppe_problem handle (one grid)."""
 
-    def __init__(self, grid):
+    def __init__(self, grid, mask_mode=PPE_MASK_DIBPM, stream=None):
         self.nx, self.ny = int(grid.nx), int(grid.ny)
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (grid.xc, grid.yc, grid.hx, grid.hy)]
         mask = None if getattr(grid, "mask", None) is None else np.ascontiguousarray(grid.mask, dtype=np.uint8)
         d = ppe_grid_desc(self.nx, self.ny, *[a.ctypes.data for a in arrs],
-                          mask.ctypes.data if mask is not None else None)
+                          mask.ctypes.data if mask is not None else None, mask_mode)
         h = ctypes.c_void_p()
-        _check(lib().ppe_problem_create(ctypes.byref(d), ctypes.byref(h)))
+        s = None
+        if stream is not None:
+            s = ctypes.c_void_p(stream.cuda_stream)
+        _check(lib().ppe_problem_create(ctypes.byref(d), s, ctypes.byref(h)))
         self.handle = h
 
     def __del__(self):
@@ -181,8 +209,8 @@ class Problem:
             self.handle = None
 
 
-def ppe_problem_create(grid) -> Problem:
-    return Problem(grid)
+def ppe_problem_create(grid, mask_mode=PPE_MASK_DIBPM, stream=None) -> Problem:
+    return Problem(grid, mask_mode, stream)
 
 
 def ppe_solve_opts_default(**kw) -> ppe_solve_opts:
@@ -221,6 +249,18 @@ def ppe_apply_f64(prob: Problem, x, y, stream=None):
                                _stream(stream)))
 
 
+def ppe_apply_precond(prob: Problem, r, z, opts=None, stream=None):
+    """z = M^-1 r (float32 device arrays [nb, ny, nx] or [ny, nx]) for the
+    preconditioner opts.precond selects."""
+    import torch
+    nb = _nb(r, prob)
+    if _nb(z, prob) != nb:
+        raise ValueError("r and z batch sizes differ")
+    opts = opts or ppe_solve_opts_default()
+    _check(lib().ppe_apply_precond(prob.handle, nb, _dev(r, torch.float32, "r"), _dev(z, torch.float32, "z"),
+                                   ctypes.byref(opts), _stream(stream)))
+
+
 def ppe_solve_plain(prob: Problem, f, x, opts=None, stream=None):
     """Returns (status, [stats dict per solve])."""
     import torch
@@ -228,11 +268,11 @@ def ppe_solve_plain(prob: Problem, f, x, opts=None, stream=None):
     if _nb(x, prob) != nb:
         raise ValueError("f and x batch sizes differ")
     opts = opts or ppe_solve_opts_default()
-    stats = (ppe_solve_stats * max(nb, 1))()
+    stats, bufs = _stats_array(nb, opts)
     st = lib().ppe_solve_plain(prob.handle, nb, _dev(f, torch.float32, "f"), _dev(x, torch.float64, "x"),
                                ctypes.byref(opts), ctypes.cast(stats, ctypes.c_void_p), _stream(stream))
     _check(st, (PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))
-    return st, [stats[i].as_dict() for i in range(nb)]
+    return st, [stats[i].as_dict(bufs[i]) for i in range(nb)]
 
 
 def ppe_solve_plain_noalloc(prob: Problem, f, x, opts=None, stream=None):
@@ -243,11 +283,11 @@ def ppe_solve_plain_noalloc(prob: Problem, f, x, opts=None, stream=None):
     if _nb(f, prob) != 1 or _nb(x, prob) != 1:
         raise ValueError("the allocation-free solve takes one right-hand side")
     opts = opts or ppe_solve_opts_default()
-    stats = ppe_solve_stats()
+    stats, bufs = _stats_array(1, opts)
     st = lib().ppe_solve_plain_noalloc(prob.handle, _dev(f, torch.float32, "f"), _dev(x, torch.float64, "x"),
-                                       ctypes.byref(opts), ctypes.byref(stats), _stream(stream))
+                                       ctypes.byref(opts), ctypes.cast(stats, ctypes.c_void_p), _stream(stream))
     _check(st, (PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))
-    return st, stats.as_dict()
+    return st, stats[0].as_dict(bufs[0])
 
 
 def ppe_noalloc_scratch_bytes(prob: Problem) -> int:
@@ -373,16 +413,16 @@ def ppe_solve_hybrid(prob: Problem, net, f, x, opts=None, stream=None):
     if _nb(x, prob) != nb:
         raise ValueError("f and x batch sizes differ")
     opts = opts or ppe_solve_opts_default()
-    stats = (ppe_solve_stats * max(nb, 1))()
+    stats, bufs = _stats_array(nb, opts)
     st = lib().ppe_solve_hybrid(prob.handle, net.handle if net is not None else None, nb,
                                 _dev(f, torch.float32, "f"), _dev(x, torch.float64, "x"), ctypes.byref(opts),
                                 ctypes.cast(stats, ctypes.c_void_p), _stream(stream))
     _check(st, (PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))
-    return st, [stats[i].as_dict() for i in range(nb)]
+    return st, [stats[i].as_dict(bufs[i]) for i in range(nb)]
 
 
 def ppe_train_opts_default(**kw) -> ppe_train_opts:
-    o = ppe_train_opts(1e-3, 0.9, 0.999, 1e-8, 0, 0, 0.05, 0.5, 512, 0.0, 0.0)
+    o = ppe_train_opts(1e-3, 0.9, 0.999, 1e-8, 0, 0, 0.05, 0.5, 512, 0.0, 0.0, PPE_LOSS_RESIDUAL)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -406,13 +446,13 @@ def ppe_solve_batch(probs, fs, xs, opts=None, stream=None, net=None):
     farr = (ctypes.c_void_p * n)(*[_dev(f, torch.float32, "f") for f in fs])
     xarr = (ctypes.c_void_p * n)(*[_dev(x, torch.float64, "x") for x in xs])
     opts = opts or ppe_solve_opts_default()
-    stats = (ppe_solve_stats * n)()
+    stats, bufs = _stats_array(n, opts)
     st = lib().ppe_solve_batch(n, ctypes.cast(parr, ctypes.c_void_p), net.handle if net is not None else None,
                                ctypes.cast(farr, ctypes.c_void_p),
                                ctypes.cast(xarr, ctypes.c_void_p), ctypes.byref(opts),
                                ctypes.cast(stats, ctypes.c_void_p), _stream(stream))
     _check(st, allow=(PPE_OK, PPE_NOT_CONVERGED, PPE_ERR_NONFINITE))
-    return st, [s.as_dict() for s in stats]
+    return st, [stats[i].as_dict(bufs[i]) for i in range(n)]
 
 
 def ppe_generate_grid(nx, ny, seed, step, sample, mask=True):
@@ -442,10 +482,11 @@ def ppe_generate_rhs(probs, opts, R, stream=None):
                                   _dev(R, torch.float32, "R"), _stream(stream)))
 
 
-def ppe_net_train_step(net: Net, probs, R, opts=None, want_grad=False, stream=None):
+def ppe_net_train_step(net: Net, probs, R, opts=None, want_grad=False, stream=None, target=None):
     """One Adam step (lr = 0: gradient only). probs: list of Problem (one grid per sample),
     R: device float32 [nb, ny, nx], or None to generate the batch on the device from
-    opts (seed, step, length scales, features). Returns (loss, grad ndarray or None)."""
+    opts (seed, step, length scales, features); target: device float64 [nb, ny, nx]
+    for the supervised loss. Returns (loss, grad ndarray or None)."""
     import torch
     nb = len(probs)
     if R is not None:
@@ -458,7 +499,14 @@ def ppe_net_train_step(net: Net, probs, R, opts=None, want_grad=False, stream=No
     loss = ctypes.c_float()
     grad = np.empty(ppe_net_num_params(net), dtype=np.float32) if want_grad else None
     Rp = None if R is None else _dev(R, torch.float32, "R")
-    _check(lib().ppe_net_train_step(net.handle, nb, ctypes.cast(arr, ctypes.c_void_p), Rp,
+    Tp = None
+    if target is not None:
+        if target.dim() != 3 or target.shape[0] != nb:
+            raise ValueError("target must be [nb, ny, nx]")
+        for p in probs:
+            _nb(target[0], p)
+        Tp = _dev(target, torch.float64, "target")
+    _check(lib().ppe_net_train_step(net.handle, nb, ctypes.cast(arr, ctypes.c_void_p), Rp, Tp,
                                     ctypes.byref(opts), ctypes.byref(loss),
                                     grad.ctypes.data if want_grad else None, _stream(stream)))
     return float(loss.value), grad
