@@ -14,7 +14,10 @@ Beside it the line always carries the hybrid half of the comparison
 method of Sec. 2.2 (Num_CG = 3, Num_DLSM = 2) with the network saved at
 --hybrid PATH, or, without one, with the default network at its seeded
 random initialisation (the control), each run capped at --hybrid-max-iter
-iterations and reported as converged or not.
+iterations and reported as converged or not, with the device time split
+into CG-type, network and line-search parts. config["mgpcg"] and
+config["hybrid_mgpcg"] repeat both with the multigrid-preconditioned CG
+(the paper's strongest CG-type, MGPCG-4).
 
 `roofline` reports the dominant kernel (the launch of the PCG form that
 runs) on the algorithmic basis of 32 bytes per cell and PCG iteration (the
@@ -129,10 +132,49 @@ def hybrid_run(ppe, torch, prob, f, x, args):
            "ms_per_solve": ms, "solves_per_s": 1e3 / ms if st == ppe.PPE_OK else 0.0,
            "iters": s0["iters_total"], "iters_cg": s0["iters_cg"], "iters_dlsm": s0["iters_dlsm"],
            "dlsm_rejected": s0["dlsm_rejected"], "rel_res_true": s0["rel_res_true"],
-           "max_iter": args.hybrid_max_iter, "num_cg": 3, "num_dlsm": 2}
-    for k in ("ms_pcg", "ms_net", "ms_dlsm"):
-        if k in s0:
-            out[k] = s0[k]
+           "max_iter": args.hybrid_max_iter, "num_cg": 3, "num_dlsm": 2,
+           "ms_pcg": s0["ms_pcg"], "ms_net": s0["ms_net"], "ms_dlsm": s0["ms_dlsm"]}
+    return out
+
+
+def mg_run(ppe, torch, prob, f, x, args):
+    """Multigrid-preconditioned CG (the paper's MGPCG-4 CG-type) on the same
+    system, and the hybrid over it (the network of the hybrid leg), timed
+    like the plain solve."""
+    out = {}
+    o = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, precond=ppe.PPE_PC_MG, mg_levels=4,
+                                   reliable_delta=args.mg_delta)
+    ppe.ppe_solve_plain(prob, f, x, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, stats = ppe.ppe_solve_plain(prob, f, x, o)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    s0 = stats[0]
+    out["mgpcg"] = {"converged": st == ppe.PPE_OK, "ms_per_solve": ms, "solves_per_s": 1e3 / ms,
+                    "iters": s0["iters_total"], "reliable_updates": s0["reliable_updates"],
+                    "rel_res_true": s0["rel_res_true"], "levels": 4, "reliable_delta": args.mg_delta,
+                    "smoother": "Chebyshev degree 2 on D^-1 A over [0.2, 2], pre and post",
+                    "coarsest": "exact separable FP64 solve (128 x 128)"}
+    net = ppe.Net(ppe.ppe_net_config_default(), seed=0)
+    if args.hybrid:
+        ppe.ppe_net_load(net, args.hybrid)
+    oh = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, precond=ppe.PPE_PC_MG, mg_levels=4,
+                                    reliable_delta=args.mg_delta, max_iter=args.mg_hybrid_max_iter)
+    ppe.ppe_solve_hybrid(prob, net, f, x, oh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, stats = ppe.ppe_solve_hybrid(prob, net, f, x, oh)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    s0 = stats[0]
+    out["hybrid_mgpcg"] = {"network": os.path.basename(args.hybrid) if args.hybrid else "seeded random init (control)",
+                           "converged": st == ppe.PPE_OK, "ms_per_solve": ms,
+                           "solves_per_s": 1e3 / ms if st == ppe.PPE_OK else 0.0,
+                           "iters": s0["iters_total"], "iters_cg": s0["iters_cg"], "iters_dlsm": s0["iters_dlsm"],
+                           "rel_res_true": s0["rel_res_true"], "max_iter": args.mg_hybrid_max_iter,
+                           "ms_pcg": s0["ms_pcg"], "ms_net": s0["ms_net"], "ms_dlsm": s0["ms_dlsm"]}
     return out
 
 
@@ -225,6 +267,9 @@ def main():
                          "the hybrid leg runs the default network at its seeded random initialisation")
     ap.add_argument("--hybrid-max-iter", type=int, default=3000)
     ap.add_argument("--no-hbm-batch", action="store_true", help="skip the HBM-resident batch leg")
+    ap.add_argument("--mg-delta", type=float, default=0.1,
+                    help="reliable-update threshold of the multigrid legs")
+    ap.add_argument("--mg-hybrid-max-iter", type=int, default=500)
     ap.add_argument("--sequence", type=int, default=0, metavar="T",
                     help="time T consecutive solves on the workload's grid instead, the source travelling "
                          "--seq-shift domain lengths per step (step 0 is the headline source), from x0 = 0 "
@@ -387,6 +432,7 @@ def main():
         },
     }
     out["config"]["hybrid"] = hybrid_run(ppe, torch, prob, f, x, args)
+    out["config"].update(mg_run(ppe, torch, prob, f, x, args))
     if not args.no_hbm_batch:
         out["config"]["hbm_resident_batch"] = hbm_batch_run(ppe, torch, g, prob, args)
     if not args.no_cpu_baseline:

@@ -273,7 +273,10 @@ static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int 
 ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s,
                           int form) {
   SolveWs& w = p->ws;
-  int chunk = o.chunk > 0 ? o.chunk : 64;
+  // Iterations per polled chunk: multigrid converges in tens of iterations,
+  // Jacobi-PCG in thousands; a chunk may run past convergence by up to two
+  // chunks of early-exit launches.
+  int chunk = o.chunk > 0 ? o.chunk : (a.mg ? 8 : 64);
   chunk += chunk & 1;
   if (o.use_graph) {
     ppe_status st = get_chunk_graph(p, a, nb, chunk, form);

@@ -128,55 +128,54 @@ ppe_status mg_ensure(ppe_problem* p, int L, int nb, int R0, hipStream_t s) {
   const int nxc = (int)hx.size(), nyc = (int)hy.size();
   m->nxc = nxc;
   m->nyc = nyc;
-  // T_x phi = lam H_x phi through the symmetric S = H^-1/2 T_x H^-1/2.
-  std::vector<double> sd(nxc), so(nxc > 1 ? nxc - 1 : 0), lam(nxc), U((size_t)nxc * nxc);
-  for (int i = 0; i < nxc; ++i) sd[i] = (gx[i] + gx[i + 1]) / hx[i];
-  for (int i = 0; i + 1 < nxc; ++i) so[i] = -gx[i + 1] / std::sqrt(hx[i] * hx[i + 1]);
-  ppe_status est = ppe_tridiag_eigh(nxc, sd.data(), so.data(), lam.data(), U.data());
+  // Generalised eigenvectors of one axis, T v = lam H v with v^T H v = 1,
+  // through the symmetric S = H^-1/2 T H^-1/2 (tridiagonal); ascending, so
+  // mode 0 is the constant (lam = 0).
+  auto axis_eig = [&](const std::vector<double>& h, const std::vector<double>& g, std::vector<double>& lam,
+                      std::vector<double>& V) -> ppe_status {
+    const int n = (int)h.size();
+    std::vector<double> sd(n), so(n > 1 ? n - 1 : 0), U((size_t)n * n);
+    lam.resize(n);
+    for (int i = 0; i < n; ++i) sd[i] = (g[i] + g[i + 1]) / h[i];
+    for (int i = 0; i + 1 < n; ++i) so[i] = -g[i + 1] / std::sqrt(h[i] * h[i + 1]);
+    ppe_status st = ppe_tridiag_eigh(n, sd.data(), so.data(), lam.data(), U.data());
+    if (st != PPE_OK) return st;
+    V.resize((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) V[(size_t)i * n + k] = U[(size_t)i * n + k] / std::sqrt(h[i]);
+    lam[0] = 0.0;  // the constant mode
+    return PPE_OK;
+  };
+  std::vector<double> lam, mu, phi, psi;
+  ppe_status est = axis_eig(hx, gx, lam, phi);
+  if (est == PPE_OK) est = axis_eig(hy, gy, mu, psi);
   if (est != PPE_OK) {
     mg_free(m);
     return est;
   }
-  std::vector<double> phi((size_t)nxc * nxc), phiT((size_t)nxc * nxc);
+  std::vector<double> phiT((size_t)nxc * nxc), psiT((size_t)nyc * nyc), dinv((size_t)nyc * nxc);
   for (int i = 0; i < nxc; ++i)
-    for (int k = 0; k < nxc; ++k) {
-      const double v = U[(size_t)i * nxc + k] / std::sqrt(hx[i]);
-      phi[(size_t)i * nxc + k] = v;
-      phiT[(size_t)k * nxc + i] = v;
-    }
-  lam[0] = 0.0;  // the constant mode (the null space along x)
-  // Thomas factors of T_y + lam_k H_y per mode; mode 0 is singular (the
-  // constant along y) and grounded at its last unknown.
-  std::vector<double> offd(nyc + 1, 0.0), mult((size_t)nyc * nxc, 0.0), iw((size_t)nyc * nxc, 0.0);
-  for (int j = 1; j < nyc; ++j) offd[j] = -gy[j];
-  for (int k = 0; k < nxc; ++k) {
-    double w = lam[k] * hy[0] + gy[0] + gy[1];
-    iw[k] = 1.0 / w;
-    for (int j = 1; j < nyc; ++j) {
-      const double mu = offd[j] / w;
-      mult[(size_t)j * nxc + k] = mu;
-      w = lam[k] * hy[j] + gy[j] + gy[j + 1] - mu * offd[j];
-      iw[(size_t)j * nxc + k] = 1.0 / w;
-    }
-    if (k == 0) iw[(size_t)(nyc - 1) * nxc] = 0.0;
-  }
-  if (nyc == 1) iw[0] = 0.0;  // a single row: mode 0 is the null space itself
+    for (int k = 0; k < nxc; ++k) phiT[(size_t)k * nxc + i] = phi[(size_t)i * nxc + k];
+  for (int j = 0; j < nyc; ++j)
+    for (int k = 0; k < nyc; ++k) psiT[(size_t)k * nyc + j] = psi[(size_t)j * nyc + k];
+  for (int j = 0; j < nyc; ++j)
+    for (int k = 0; k < nxc; ++k) dinv[(size_t)j * nxc + k] = (j == 0 && k == 0) ? 0.0 : 1.0 / (lam[k] + mu[j]);
   m->phi = alloc_n<double>(m, phi.size());
   m->phiT = alloc_n<double>(m, phiT.size());
-  m->mult = alloc_n<double>(m, mult.size());
-  m->iw = alloc_n<double>(m, iw.size());
-  m->offd = alloc_n<double>(m, offd.size());
+  m->psi = alloc_n<double>(m, psi.size());
+  m->psiT = alloc_n<double>(m, psiT.size());
+  m->dinv = alloc_n<double>(m, dinv.size());
   m->bh = alloc_n<double>(m, (size_t)nxc * nyc * nb);
   m->bP = L >= 2 ? m->lv[L - 2].P : 1;
   m->bpart = alloc_n<double>(m, (size_t)m->bP * nb);
   m->xpart = alloc_n<double>(m, (size_t)nyc * nb);
-  if (!m->phi || !m->phiT || !m->mult || !m->iw || !m->offd || !m->bh || !m->bpart || !m->xpart)
+  if (!m->phi || !m->phiT || !m->psi || !m->psiT || !m->dinv || !m->bh || !m->bpart || !m->xpart)
     return fail("coarsest-level buffers");
   hipError_t e = hipMemcpyAsync(m->phi, phi.data(), phi.size() * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(m->phiT, phiT.data(), phiT.size() * 8, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(m->mult, mult.data(), mult.size() * 8, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(m->iw, iw.data(), iw.size() * 8, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(m->offd, offd.data(), offd.size() * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->psi, psi.data(), psi.size() * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->psiT, psiT.data(), psiT.size() * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->dinv, dinv.data(), dinv.size() * 8, hipMemcpyHostToDevice, s);
   // the staging vectors above and the levels' upload arrays go out of scope
   const hipError_t es = hipStreamSynchronize(s);
   if (e != hipSuccess || es != hipSuccess) return fail("upload");

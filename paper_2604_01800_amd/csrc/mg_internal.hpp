@@ -14,7 +14,7 @@ constexpr double kChebHi = 2.0, kChebLo = 0.2;
 // Largest coarsest level the separable direct solve takes (dense x-eigenbasis
 // of nx^2 doubles, row transforms staged in LDS).
 constexpr int kMgCoarseMaxNx = 2048;
-constexpr int kMgCoarseMaxNy = 8192;
+constexpr int kMgCoarseMaxNy = 2048;
 
 // One level of the hierarchy. Level 0 is the problem's grid; its right-hand
 // side is the PCG residual and its output the preconditioned residual z.
@@ -34,17 +34,18 @@ struct MgData {
   uint64_t uid = 0;  // process-unique build id (cached graphs key on it, not on the address)
   int L = 0, nb = 0, R0 = 0;
   std::vector<MgLevel> lv;
-  // Coarsest level: A_c = T_x (x) H_y + H_x (x) T_y is diagonalised along x by
-  // the generalised eigenvectors T_x phi = lam H_x phi (phi^T H_x phi = 1);
-  // each mode k leaves the tridiagonal system (T_y + lam_k H_y) c_k = b_k,
-  // factored once (Thomas); mode 0 (lam = 0, singular) is grounded at its last
-  // unknown.
+  // Coarsest level: A_c = T_x (x) H_y + H_x (x) T_y is diagonalised by the
+  // generalised eigenvectors of both axes, T_x phi = lam H_x phi
+  // (phi^T H_x phi = 1) and T_y psi = mu H_y psi (psi^T H_y psi = 1):
+  // (Phi (x) Psi)^T A_c (Phi (x) Psi) = Lam (x) I + I (x) Mu, so
+  // A_c^+ b = (Phi (x) Psi) diag(1 / (lam_k + mu_j)) (Phi (x) Psi)^T b with the
+  // constant mode (k = j = 0) dropped.
   int nxc = 0, nyc = 0;
   double* phi = nullptr;   // [nxc][nxc] phi[i][k]
   double* phiT = nullptr;  // [nxc][nxc] phiT[k][i]
-  double* mult = nullptr;  // [nyc][nxc] Thomas multipliers a_j / w_{j-1}
-  double* iw = nullptr;    // [nyc][nxc] inverse pivots 1 / w_j (0 for the grounded unknown)
-  double* offd = nullptr;  // [nyc + 1] off-diagonal -gy_j between rows j-1 and j
+  double* psi = nullptr;   // [nyc][nyc] psi[j'][j]
+  double* psiT = nullptr;  // [nyc][nyc] psiT[j][j'] = psi[j'][j]
+  double* dinv = nullptr;  // [nyc][nxc] 1 / (lam_k + mu_j), 0 for the constant mode
   double* bh = nullptr;    // [nb][nyc][nxc] transformed right-hand side, then the mode solutions
   double* bpart = nullptr; // [nb][bP] partial sums of the coarsest right-hand side
   int bP = 0;

@@ -20,8 +20,8 @@
 // post step, second post step. A kernel that reads a vector on a halo never
 // writes that vector (other workgroups may still be reading it): x2 and x5
 // live in x, x4 in y. The coarsest level is solved exactly by the
-// separable direct method (x-eigenbasis transform, one tridiagonal solve per
-// mode, back-transform) in FP64, with the right-hand side's mean removed
+// separable direct method (transforms to the eigenbases of both axes, a
+// diagonal scaling, and back) in FP64, with the right-hand side's mean removed
 // before and the solution's mean after, i.e. the minimum-norm solution.
 //
 // Vectors are FP32; every kernel returns at once for a solve whose done flag
@@ -293,9 +293,9 @@ struct CoarseArgs {
   float* x;              // [nb][Nc]
   const double* phi;     // [nxc][nxc]
   const double* phiT;    // [nxc][nxc]
-  const double* mult;    // [nyc][nxc]
-  const double* iw;      // [nyc][nxc]
-  const double* offd;    // [nyc + 1]
+  const double* psi;     // [nyc][nyc]
+  const double* psiT;    // [nyc][nyc]
+  const double* dinv;    // [nyc][nxc]
   double* bh;            // [nb][nyc][nxc]
   const double* bpart;   // [nb][bP] or NULL
   int bP;
@@ -324,25 +324,30 @@ __global__ __launch_bounds__(kBlock) void k_mg_cfwd(CoarseArgs a) {
   }
 }
 
-// One tridiagonal solve per mode k (one thread each), in place in bh:
-// forward elimination with the stored multipliers, back substitution with
-// the inverse pivots.
-__global__ __launch_bounds__(kBlock) void k_mg_ctri(CoarseArgs a) {
-  const int s = blockIdx.z;
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (a.flags[s] != DONE_NO || k >= a.nxc) return;
-  double* c = a.bh + (size_t)s * a.Nc + k;
+// Column k of the transformed right-hand side: forward transform along y
+// (bh[j][k] <- sum_j' psi[j'][j] bh[j'][k]), division by lam_k + mu_j, and the
+// inverse transform along y (bh[j][k] <- sum_j' psi[j][j'] c[j'][k]); one
+// workgroup per column, in place (no other workgroup touches the column).
+__global__ __launch_bounds__(kBlock) void k_mg_ccol(CoarseArgs a) {
+  extern __shared__ double col[];  // [2][nyc]
+  const int s = blockIdx.z, k = blockIdx.x;
+  if (a.flags[s] != DONE_NO) return;
   const int n = a.nyc, m = a.nxc;
-  double y = c[0];
-  for (int j = 1; j < n; ++j) {
-    y = c[(size_t)j * m] - a.mult[(size_t)j * m + k] * y;
-    c[(size_t)j * m] = y;
+  double* c = a.bh + (size_t)s * a.Nc + k;
+  double* t = col;
+  double* u = col + n;
+  for (int j = threadIdx.x; j < n; j += kBlock) t[j] = c[(size_t)j * m];
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += kBlock) {
+    double acc = 0.0;
+    for (int q = 0; q < n; ++q) acc += a.psi[(size_t)q * n + j] * t[q];
+    u[j] = acc * a.dinv[(size_t)j * m + k];
   }
-  double v = y * a.iw[(size_t)(n - 1) * m + k];
-  c[(size_t)(n - 1) * m] = v;
-  for (int j = n - 2; j >= 0; --j) {
-    v = (c[(size_t)j * m] - a.offd[j + 1] * v) * a.iw[(size_t)j * m + k];
-    c[(size_t)j * m] = v;
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += kBlock) {
+    double acc = 0.0;
+    for (int q = 0; q < n; ++q) acc += a.psiT[(size_t)q * n + j] * u[q];
+    c[(size_t)j * m] = acc;
   }
 }
 
@@ -425,9 +430,9 @@ void launch_vcycle(const PcgArgs& pa, int nb, hipStream_t s) {
     ca.x = L == 1 ? m.z : c.x;
     ca.phi = m.phi;
     ca.phiT = m.phiT;
-    ca.mult = m.mult;
-    ca.iw = m.iw;
-    ca.offd = m.offd;
+    ca.psi = m.psi;
+    ca.psiT = m.psiT;
+    ca.dinv = m.dinv;
     ca.bh = m.bh;
     ca.bpart = L == 1 ? nullptr : m.bpart;
     ca.bP = m.bP;
@@ -435,7 +440,7 @@ void launch_vcycle(const PcgArgs& pa, int nb, hipStream_t s) {
     ca.flags = pa.flags;
     const size_t shm = sizeof(double) * m.nxc;
     k_mg_cfwd<<<dim3(m.nyc, 1, nb), kBlock, shm, s>>>(ca);
-    k_mg_ctri<<<dim3((m.nxc + kBlock - 1) / kBlock, 1, nb), kBlock, 0, s>>>(ca);
+    k_mg_ccol<<<dim3(m.nxc, 1, nb), kBlock, sizeof(double) * 2 * m.nyc, s>>>(ca);
     k_mg_cbwd<<<dim3(m.nyc, 1, nb), kBlock, shm, s>>>(ca);
   }
   if (L == 1) {
