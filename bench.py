@@ -291,9 +291,7 @@ def main():
     torch.cuda.set_device(0)
     if args.train_step:
         from paper_2604_01800_amd import training
-        grids, R = training.make_pool(args.n, args.train_batch, seed=3)
-        Rd = torch.from_numpy(R).cuda()
-        probs = [ppe.ppe_problem_create(gg) for gg in grids]
+        grids, probs, Rd = training.make_pool(args.n, args.train_batch, seed=3)
         net = ppe.Net(ppe.ppe_net_config_default(), seed=1)
         training.train(net, grids, Rd, steps=3, batch=args.train_batch, lr=1e-4, problems=probs)
         torch.cuda.synchronize()

@@ -355,14 +355,15 @@ ppe_status ppe_ritz_create(ppe_problem* p, int32_t m, const double* v0, ppe_ritz
 /* Kept size m and host copies of alpha [m], beta [m - 1] and theta [m]
  * (ascending); any pointer may be NULL. */
 ppe_status ppe_ritz_info(const ppe_ritz* r, int32_t* m, double* alpha, double* beta, double* theta);
-/* nb training vectors R^i = Q c^i / |Q c^i|_2 (Eq. 15), Q = V_m U the Ritz
+/* nb training vectors R^i = scale Q c^i / |Q c^i|_2 (Eq. 15 for scale = 1;
+ * scale = sqrt(N) gives unit RMS, the scale of the random-field data), Q = V_m U the Ritz
  * vectors in ascending order, c^i_j = 9 N(0,1) for j <= b m and N(0,1)
  * otherwise (Eq. 16). Normal draws: Philox4x32-10, key = seed, counter =
  * (j, i + 2^31, step mod 2^32, step div 2^32), Box-Muller; each Ritz vector
  * is signed so that its component along v_0 is not negative. R: device FP32
  * [nb][ny][nx]. 1 <= nb <= 4096, 0 <= b <= 1. Synchronises s. */
-ppe_status ppe_ritz_rhs(const ppe_ritz* r, int32_t nb, uint64_t seed, int64_t step, double b, float* R,
-                        hipStream_t s);
+ppe_status ppe_ritz_rhs(const ppe_ritz* r, int32_t nb, uint64_t seed, int64_t step, double b, double scale,
+                        float* R, hipStream_t s);
 void ppe_ritz_destroy(ppe_ritz* r);
 /* Host-only: eigenvalues (ascending, theta [n]) and eigenvectors (U [n][n],
  * row-major, column j = eigenvector j, signed so that U[0][j] >= 0; may be

@@ -150,11 +150,12 @@ __global__ __launch_bounds__(kRB) void k_sumsq64_batch(const double* __restrict_
 }
 
 __global__ __launch_bounds__(kRB) void k_normalise(const double* __restrict__ r, int64_t N,
-                                                  const double* __restrict__ part, float* __restrict__ R) {
+                                                  const double* __restrict__ part, double scale,
+                                                  float* __restrict__ R) {
   __shared__ double lds[kRB / kWave];
   const int s = blockIdx.y;
   const double nrm = sqrt(reduce_partials(part + (size_t)s * kNormBlocks, kNormBlocks, lds));
-  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  const double inv = nrm > 0.0 ? scale / nrm : 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kRB + threadIdx.x; i < N; i += (int64_t)gridDim.x * kRB)
     R[(size_t)s * N + i] = (float)(r[(size_t)s * N + i] * inv);
 }
@@ -383,9 +384,10 @@ extern "C" ppe_status ppe_ritz_info(const ppe_ritz* r, int32_t* m, double* alpha
   return PPE_OK;
 }
 
-extern "C" ppe_status ppe_ritz_rhs(const ppe_ritz* r, int32_t nb, uint64_t seed, int64_t step, double b, float* R,
-                                   hipStream_t s) {
+extern "C" ppe_status ppe_ritz_rhs(const ppe_ritz* r, int32_t nb, uint64_t seed, int64_t step, double b,
+                                   double scale, float* R, hipStream_t s) {
   if (!r || !R) return set_error(PPE_ERR_INVALID_ARG, "ritz or R is NULL");
+  if (!(scale > 0.0) || !std::isfinite(scale)) return set_error(PPE_ERR_INVALID_ARG, "scale must be finite and > 0");
   if (nb < 1 || nb > 4096) return set_error(PPE_ERR_INVALID_ARG, "nb must lie in [1, 4096]");
   if (!(b >= 0.0 && b <= 1.0)) return set_error(PPE_ERR_INVALID_ARG, "b must lie in [0, 1]");
   const int m = r->m;
@@ -411,7 +413,7 @@ extern "C" ppe_status ppe_ritz_rhs(const ppe_ritz* r, int32_t nb, uint64_t seed,
   k_u_times_c<<<dim3(m, nb), kRB, 0, s>>>(r->d_U, m, d_c, d_y);
   k_v_times_y<<<dim3(blocks_for(N), nb), kRB, 0, s>>>(r->d_V, m, N, d_y, d_r);
   k_sumsq64_batch<<<dim3(kNormBlocks, nb), kRB, 0, s>>>(d_r, N, d_part);
-  k_normalise<<<dim3(kNormBlocks, nb), kRB, 0, s>>>(d_r, N, d_part, R);
+  k_normalise<<<dim3(kNormBlocks, nb), kRB, 0, s>>>(d_r, N, d_part, scale, R);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();

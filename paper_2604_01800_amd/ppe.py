@@ -127,7 +127,7 @@ SIGNATURES = {
     "ppe_generate_grid": (_i32, [_i32, _i32, _u64, _u64, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ppe_ritz_create": (_i32, [_vp, _i32, _vp, _P(_vp), _vp]),
     "ppe_ritz_info": (_i32, [_vp, _P(_i32), _vp, _vp, _vp]),
-    "ppe_ritz_rhs": (_i32, [_vp, _i32, _u64, _i64, ctypes.c_double, _vp, _vp]),
+    "ppe_ritz_rhs": (_i32, [_vp, _i32, _u64, _i64, ctypes.c_double, ctypes.c_double, _vp, _vp]),
     "ppe_ritz_destroy": (None, [_vp]),
     "ppe_tridiag_eigh": (_i32, [_i32, _vp, _vp, _vp, _vp]),
     "ppe_tune_pcg": (_i32, [_vp, _i32, _vp, _vp, _i32, _P(ppe_tune_result), _vp]),
@@ -542,12 +542,14 @@ def ppe_ritz_info(r: Ritz):
     return a, b, t
 
 
-def ppe_ritz_rhs(r: Ritz, R, seed=0, step=0, b=0.6, stream=None):
-    """Fills the device FP32 tensor R [nb, ny, nx] with training vectors (Eqs. 15-16)."""
+def ppe_ritz_rhs(r: Ritz, R, seed=0, step=0, b=0.6, scale=1.0, stream=None):
+    """Fills the device FP32 tensor R [nb, ny, nx] with training vectors
+    (Eqs. 15-16) of L2 norm `scale`."""
     import torch
     if R.dim() != 3 or tuple(R.shape[1:]) != (r.ny, r.nx):
         raise ValueError("R must be [nb, ny, nx] on the Ritz basis's grid")
-    _check(lib().ppe_ritz_rhs(r.handle, R.shape[0], seed, step, b, _dev(R, torch.float32, "R"), _stream(stream)))
+    _check(lib().ppe_ritz_rhs(r.handle, R.shape[0], seed, step, b, scale, _dev(R, torch.float32, "R"),
+                              _stream(stream)))
 
 
 def ppe_tridiag_eigh(alpha, beta):

@@ -22,18 +22,18 @@ from . import inputs, ppe
 
 
 def make_pool(n: int, count: int, seed: int = 0, ell_lo: float = 0.05, ell_hi: float = 0.5):
-    """Returns (grids, R [count, n, n] float32)."""
+    """count random stretched n x n grids (ellipse masks) with their sources
+    drawn on the device by the library's generator (ppe_generate_rhs: random
+    fields of log-uniform length scale in [ell_lo, ell_hi], times the cell
+    area, zero mean, unit RMS). Returns (grids, problems, device R [count, n, n])."""
+    import torch
     rng = np.random.default_rng(seed)
-    grids, R = [], []
-    for k in range(count):
-        g = inputs.with_ellipse(inputs.random_stretched_grid(n, n, rng), rng)
-        ell = float(np.exp(rng.uniform(np.log(ell_lo), np.log(ell_hi))))
-        r = inputs.grf(g, int(rng.integers(1 << 31)), ell=ell) * np.outer(g.hy, g.hx)
-        r -= r.mean()
-        r /= np.sqrt(np.mean(r * r))
-        grids.append(g)
-        R.append(r.astype(np.float32))
-    return grids, np.stack(R)
+    grids = [inputs.with_ellipse(inputs.random_stretched_grid(n, n, rng), rng) for _ in range(count)]
+    probs = [ppe.ppe_problem_create(g) for g in grids]
+    R = torch.empty((count, n, n), dtype=torch.float32, device="cuda")
+    ppe.ppe_generate_rhs(probs, ppe.ppe_train_opts_default(seed=seed, step=0, grf_len_lo=ell_lo, grf_len_hi=ell_hi),
+                         R)
+    return grids, probs, R
 
 
 def generated_grids(n: int, count: int, seed: int = 0, step: int = 0):
@@ -54,20 +54,21 @@ def make_ritz_pool(n: int, count: int, seed: int = 0, grids: int = 16, m: int | 
     rng = np.random.default_rng(seed)
     m = m or max(8, int(0.14 * n * n))
     per = count // grids
-    gl, Rs = [], []
+    R = torch.empty((count, n, n), dtype=torch.float32, device="cuda")
+    gl = [None] * count
+    # slot i * grids + k holds vector i of grid k, so consecutive batches mix
+    # the grids; the vectors have unit RMS (L2 norm sqrt(N) instead of the 1
+    # of Eq. 15), the scale of the other training data
     for k in range(grids):
         g = inputs.with_ellipse(inputs.random_stretched_grid(n, n, rng), rng)
         prob = ppe.ppe_problem_create(g)
         v0 = torch.from_numpy(rng.standard_normal((n, n))).cuda()
         r = ppe.Ritz(prob, m, v0)
-        R = torch.empty((per, n, n), dtype=torch.float32, device="cuda")
-        ppe.ppe_ritz_rhs(r, R, seed=seed, step=k, b=b)
-        # unit L2 norm (Eq. 15) -> unit RMS, the scale of the other training data
-        Rs.append(R * float(np.sqrt(n * n)))
-        gl += [g] * per
-    R = torch.cat(Rs)
-    order = rng.permutation(count)  # batches mix the grids
-    return [gl[i] for i in order], R[torch.from_numpy(order).cuda()].contiguous()
+        for i in range(per):
+            slot = i * grids + k
+            ppe.ppe_ritz_rhs(r, R[slot:slot + 1], seed=seed, step=k * per + i, b=b, scale=float(np.sqrt(n * n)))
+            gl[slot] = g
+    return gl, R
 
 
 def cosine_lr(lr: float, step: int, steps: int) -> float:
@@ -170,8 +171,7 @@ def main(argv=None):
         elif args.data == "generated":
             grids, Rd = generated_grids(args.n, args.pool, seed=1), None
         else:
-            grids, R = make_pool(args.n, args.pool, seed=1)
-            Rd = torch.from_numpy(R).cuda()
+            grids, _, Rd = make_pool(args.n, args.pool, seed=1)
         probs = [ppe.ppe_problem_create(g) for g in grids]
         train(net, grids, Rd, steps=args.steps, batch=args.batch, lr=args.lr,
               log_every=max(1, args.steps // 20), problems=probs, schedule="cosine", clip_norm=args.clip,

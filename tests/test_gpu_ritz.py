@@ -102,6 +102,13 @@ def test_training_vectors_match_oracle(ppe):
     want = orz.training_vectors(V, U, orz.coefficients(m, nb, b, seed, step))
     got = R.cpu().numpy().reshape(nb, -1).astype(np.float64)
     assert np.abs(got - want).max() <= 1e-6, np.abs(got - want).max()
+    # scale: the same vectors with L2 norm `scale` (unit RMS for sqrt(N))
+    scale = float(np.sqrt(g.nx * g.ny))
+    ppe.ppe_ritz_rhs(r, R, seed=seed, step=step, b=b, scale=scale)
+    got = R.cpu().numpy().reshape(nb, -1).astype(np.float64)
+    assert np.abs(got - scale * want).max() <= 1e-6 * scale
+    with pytest.raises(ppe.PPEError):
+        ppe.ppe_ritz_rhs(r, R, scale=0.0)
 
 
 def test_training_vectors_at_64(ppe):
