@@ -347,3 +347,23 @@ def sam_gradient(p, cfg, grids, R, rho, masks=None, apply=None, bf16=True):
     if bf16:
         w = round_bf16_params(cfg, w)
     return loss_and_grad(w, cfg, grids, R, masks, apply)
+
+
+def supervised_loss_of(y, e):
+    """Scale- and shift-invariant misfit of an output y against a target e
+    (both [ny, nx]): 1 - (y0 . e0)^2 / (|y0|^2 |e0|^2) with y0, e0 the fields
+    minus their means. The line search of Eqs. 12-13 is blind to the output's
+    scale and to constants (A 1 = 0), so only the direction matters."""
+    y0 = y - y.mean()
+    e0 = e - e.mean()
+    return 1.0 - (y0 * e0).sum() ** 2 / ((y0 * y0).sum() * (e0 * e0).sum())
+
+
+def supervised_loss(p, cfg, grids, R, targets, masks=None):
+    """Batch mean of supervised_loss_of(NN(R_s), e_s) (the FP64 target e_s,
+    typically the solution of A e_s = R_s)."""
+    total = 0.0
+    for s, g in enumerate(grids):
+        y = forward(p, cfg, g, R[s:s + 1], None if masks is None else masks[s])[0]
+        total = total + supervised_loss_of(y, torch.as_tensor(targets[s], dtype=torch.float64))
+    return total / len(grids)

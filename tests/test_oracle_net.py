@@ -215,3 +215,56 @@ def test_sam_gradient_definition():
     assert abs(ls - lw) <= 1e-12 * lw
     np.testing.assert_allclose(onet.flatten(cfg, gs), onet.flatten(cfg, gw), rtol=1e-10, atol=1e-12)
     assert ls > l0  # the step along +g/|g| climbs the loss
+
+
+def test_supervised_loss_invariances():
+    """The supervised misfit is 0 for any y = c e + d (c != 0), 1 for a y
+    orthogonal to the centred target, lies in [0, 1], and is unchanged by
+    scaling or shifting either field."""
+    rng = np.random.default_rng(3)
+    e = torch.from_numpy(rng.standard_normal((12, 10)))
+    y = torch.from_numpy(rng.standard_normal((12, 10)))
+    f = onet.supervised_loss_of
+    assert abs(float(f(-2.5 * e + 7.0, e))) <= 1e-14
+    e0 = e - e.mean()
+    y0 = y - y.mean()
+    orth = y0 - (y0 * e0).sum() / (e0 * e0).sum() * e0
+    assert abs(float(f(orth, e)) - 1.0) <= 1e-14
+    v = float(f(y, e))
+    assert 0.0 < v < 1.0
+    for c, d in [(3.0, 0.0), (-0.1, 5.0), (1e4, -2.0)]:
+        assert abs(float(f(c * y + d, e)) - v) <= 1e-12
+        assert abs(float(f(y, c * e + d)) - v) <= 1e-12
+
+
+def test_fd_gradients_of_supervised_loss():
+    cfg = small_cfg()
+    n = 16
+    rng = np.random.default_rng(8)
+    grids = [inputs.make_grid(n, n, b) for b in (1.3, 2.0)]
+    R = np.stack([inputs.grf(gr, 20 + i, ell=0.2, J=64) for i, gr in enumerate(grids)])
+    R -= R.mean(axis=(1, 2), keepdims=True)
+    T = rng.standard_normal(R.shape)
+    p = onet.init_params(cfg, rng)
+    for t in p.values():
+        t.requires_grad_(True)
+    loss = onet.supervised_loss(p, cfg, grids, R, T)
+    loss.backward()
+    checked = 0
+    for name in ["enc0.a.W", "dec0.d.W", "head.W", "trunk1.W", "gamma", "enc1.b.phi.W1", "up0.b"]:
+        t = p[name]
+        flat = t.detach().reshape(-1)
+        for idx in rng.choice(flat.numel(), size=min(3, flat.numel()), replace=False):
+            v0 = float(flat[idx])
+            h = 1e-6 * max(1.0, abs(v0))
+            vals = []
+            for sgn in (+1, -1):
+                with torch.no_grad():
+                    q = {k: v.detach().clone() for k, v in p.items()}
+                    q[name].reshape(-1)[idx] = v0 + sgn * h
+                    vals.append(float(onet.supervised_loss(q, cfg, grids, R, T)))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = float(t.grad.reshape(-1)[idx])
+            assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * abs(float(loss.detach()))), (name, idx, fd, an)
+            checked += 1
+    assert checked >= 15
