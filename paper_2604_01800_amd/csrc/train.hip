@@ -60,7 +60,11 @@ struct TrainState {
   float* d_R = nullptr;  // [nb][N]
   double* gpart = nullptr;  // [kRedBlocks] partial sums of the squared gradient (clipping, SAM)
   float* w_save = nullptr;  // [np] weights kept during a sharpness-aware step
+  double* sup = nullptr;    // supervised loss: [nb][5][kSupParts] partial sums, then [nb] sample losses
+  int sup_nb = 0;
 };
+
+constexpr int kSupParts = 64;
 
 static int pad8(int c) { return (c + 7) / 8 * 8; }
 
@@ -74,6 +78,7 @@ void net_train_free(ppe_net* n) {
   dev_free(t->d_R);
   dev_free(t->gpart);
   dev_free(t->w_save);
+  dev_free(t->sup);
   dev_free(t->act);
   dev_free(t->grad);
   dev_free(t->eta);
@@ -225,8 +230,6 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
     return set_error(PPE_ERR_INVALID_ARG, "the supervised loss needs an explicit batch R and its target");
   if (opts->loss_kind == PPE_LOSS_RESIDUAL && target)
     return set_error(PPE_ERR_INVALID_ARG, "target is given but the loss is the residual loss");
-  if (opts->loss_kind == PPE_LOSS_SUPERVISED)
-    return set_error(PPE_ERR_UNSUPPORTED, "the supervised loss is not built yet");
   if (nb < 1 || nb > 4096) return set_error(PPE_ERR_INVALID_ARG, "nb must lie in [1, 4096]");
   if (!R) {
     ppe_status sg = check_gen_opts(*opts);
@@ -261,6 +264,13 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
   ppe_status st = train_state(n, nb, nx, ny);
   if (st != PPE_OK) return st;
   TrainState* t = n->train;
+  const bool supervised = opts->loss_kind == PPE_LOSS_SUPERVISED;
+  if (supervised && t->sup_nb < nb) {
+    dev_free(t->sup);
+    t->sup = (double*)dev_alloc(sizeof(double) * ((size_t)nb * 5 * kSupParts + nb));
+    t->sup_nb = t->sup ? nb : 0;
+    if (!t->sup) return set_error(PPE_ERR_HIP, "allocation of the supervised-loss sums failed");
+  }
   if (!R) {
     if (!t->d_R) t->d_R = (float*)dev_alloc(sizeof(float) * N * nb);
     if (!t->d_R) return set_error(PPE_ERR_HIP, "allocation of the generated batch failed");
@@ -420,13 +430,19 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
     }
     launch_don_fwd(N * nb, P, Ab + t->o_B, Ab + t->o_T, W + n->o_gamma, y, s);
 
-    // ---- loss (Eq. 19): res = R - A y, L = mean(res^2); dL/dy = -2/(nb N) A res ----
-    launch_apply_multi(t->d_coefs, nx, ny, nb, y, Ay, s);
-  
-    launch_loss(N * nb, R, Ay, res, lpart, kRedBlocks, s);
-    launch_sum_parts(lpart, kRedBlocks, 1.0 / ((double)N * nb), lpart + kRedBlocks, s);
-    launch_apply_multi(t->d_coefs, nx, ny, nb, res, gAy, s);
-    const float dscale = (float)(-2.0 / ((double)N * nb));
+    float dscale = 1.f;
+    if (supervised) {
+      // ---- supervised loss: dL/dy straight into gAy ----
+      launch_sup_loss(N, nb, y, target, t->sup, kSupParts, gAy, t->sup + (size_t)nb * 5 * kSupParts, s);
+      launch_sum_parts(t->sup + (size_t)nb * 5 * kSupParts, nb, 1.0 / nb, lpart + kRedBlocks, s);
+    } else {
+      // ---- loss (Eq. 19): res = R - A y, L = mean(res^2); dL/dy = -2/(nb N) A res ----
+      launch_apply_multi(t->d_coefs, nx, ny, nb, y, Ay, s);
+      launch_loss(N * nb, R, Ay, res, lpart, kRedBlocks, s);
+      launch_sum_parts(lpart, kRedBlocks, 1.0 / ((double)N * nb), lpart + kRedBlocks, s);
+      launch_apply_multi(t->d_coefs, nx, ny, nb, res, gAy, s);
+      dscale = (float)(-2.0 / ((double)N * nb));
+    }
 
     // ---- backward ----
     HIPCHK(hipMemsetAsync(dG, 0, n->np * sizeof(float), s));

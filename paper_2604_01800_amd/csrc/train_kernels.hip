@@ -756,6 +756,58 @@ __global__ __launch_bounds__(256) void k_loss(int64_t n, const float* __restrict
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// Supervised loss pieces, per sample s (blockIdx.y): partial sums of y, e,
+// y^2, y e and e^2 ([nb][5][gridDim.x]).
+__global__ __launch_bounds__(256) void k_sup_sums(int64_t N, const float* __restrict__ y,
+                                                  const double* __restrict__ e, double* __restrict__ part) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.y;
+  const float* ys = y + (size_t)s * N;
+  const double* es = e + (size_t)s * N;
+  double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (int64_t)gridDim.x * 256) {
+    const double yv = ys[p], ev = es[p];
+    a[0] += yv;
+    a[1] += ev;
+    a[2] += yv * yv;
+    a[3] += yv * ev;
+    a[4] += ev * ev;
+  }
+  for (int m = 0; m < 5; ++m) {
+    const double v = block_sum(a[m], lds);
+    if (threadIdx.x == 0) part[((size_t)s * 5 + m) * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// Supervised loss L_s = 1 - a^2 / (b c) with a = y0.e0, b = |y0|^2, c = |e0|^2
+// (centred fields) and its gradient, averaged over the nb samples:
+// dL/dy = 2 a / (b c nb) (a/b y0 - e0) (zero mean, so the centring needs no
+// further projection). A constant y (b = 0) or target (c = 0) gives L = 1
+// and no gradient. Every workgroup reduces the partials in the same order.
+__global__ __launch_bounds__(256) void k_sup_grad(int64_t N, int nb, const float* __restrict__ y,
+                                                  const double* __restrict__ e, const double* __restrict__ part,
+                                                  int nparts, float* __restrict__ dy, double* __restrict__ lsamp) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.y;
+  double S[5];
+  for (int m = 0; m < 5; ++m) S[m] = reduce_partials(part + ((size_t)s * 5 + m) * nparts, nparts, lds);
+  const double n = (double)N;
+  const double my = S[0] / n, me = S[1] / n;
+  const double a = S[3] - n * my * me;
+  const double b = S[2] - n * my * my;
+  const double c = S[4] - n * me * me;
+  const bool ok = b > 0.0 && c > 0.0 && isfinite(a);
+  const double L = ok ? 1.0 - a * a / (b * c) : 1.0;
+  const double g = ok ? 2.0 * a / (b * c * (double)nb) : 0.0;
+  const double ab = ok ? a / b : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) lsamp[s] = L;
+  const float* ys = y + (size_t)s * N;
+  const double* es = e + (size_t)s * N;
+  float* ds = dy + (size_t)s * N;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (int64_t)gridDim.x * 256)
+    ds[p] = (float)(g * (ab * ((double)ys[p] - my) - (es[p] - me)));
+}
+
 __global__ void k_sum_parts(const double* __restrict__ part, int n, double scale, double* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double s = 0.0;
@@ -917,6 +969,12 @@ void launch_don_bwd(int64_t n, int P, const bf16_t* B, const bf16_t* T, const fl
 
 void launch_loss(int64_t n, const float* R, const float* Ay, float* res, double* part, int nparts, hipStream_t s) {
   k_loss<<<nparts, 256, 0, s>>>(n, R, Ay, res, part);
+}
+
+void launch_sup_loss(int64_t N, int nb, const float* y, const double* e, double* part, int nparts, float* dy,
+                     double* lsamp, hipStream_t s) {
+  k_sup_sums<<<dim3(nparts, nb), 256, 0, s>>>(N, y, e, part);
+  k_sup_grad<<<dim3(nparts, nb), 256, 0, s>>>(N, nb, y, e, part, nparts, dy, lsamp);
 }
 
 void launch_sum_parts(const double* part, int n, double scale, double* out, hipStream_t s) {

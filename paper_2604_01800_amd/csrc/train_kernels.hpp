@@ -45,6 +45,11 @@ void launch_don_bwd(int64_t n, int P, const bf16_t* B, const bf16_t* T, const fl
                     float scale, bf16_t* dB, bf16_t* dT, float* part, int nparts, hipStream_t s);
 void launch_loss(int64_t n, const float* R, const float* Ay, float* res, double* part, int nparts, hipStream_t s);
 void launch_sum_parts(const double* part, int n, double scale, double* out, hipStream_t s);
+// Supervised loss (scale- and shift-invariant misfit of y against the FP64
+// targets e): per-sample losses into lsamp [nb] and dL/dy (batch mean) into
+// dy; part holds [nb][5][nparts] partial sums.
+void launch_sup_loss(int64_t N, int nb, const float* y, const double* e, double* part, int nparts, float* dy,
+                     double* lsamp, hipStream_t s);
 // Adam step; clip > 0 scales the gradient to norm <= clip first, with ||g||^2
 // from the kRedBlocks partials in gpart (launch_sumsq on g).
 void launch_sam_perturb(int64_t n, float* w, const float* g, const double* gpart, float rho, hipStream_t s);

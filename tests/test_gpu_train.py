@@ -266,3 +266,61 @@ def test_training_on_generated_data(ppe):
     losses = runs[0]
     assert np.all(np.isfinite(losses))
     assert np.mean(losses[-20:]) < 0.8 * np.mean(losses[:5]), (np.mean(losses[:5]), np.mean(losses[-20:]))
+
+
+def test_supervised_loss_gradients_match_oracle(ppe):
+    """loss_kind = SUPERVISED with FP64 targets (the min-norm solutions of
+    A e = R): the loss and every parameter tensor's gradient against the
+    oracle's autograd of oracle.net.supervised_loss, to the same bars as the
+    residual loss; a few Adam steps lower the loss; and the argument checks."""
+    cfg = small_cfg()
+    p = onet.round_bf16_params(cfg, onet.init_params(cfg, np.random.default_rng(3), phi_scale=1.0))
+    net = ppe.Net(gpu_cfg(ppe, cfg), seed=0)
+    ppe.ppe_net_set_params(net, onet.flatten(cfg, p))
+    grids, R = batch(32, [(1.2, 2.0), (2.4, 1.1)], seed=5)
+    T = np.stack([direct.separable_solve(g, R[s]) for s, g in enumerate(grids)])
+    probs = [ppe.ppe_problem_create(g) for g in grids]
+    Rd = torch.from_numpy(R.astype(np.float32)).cuda()
+    Td = torch.from_numpy(T).cuda()
+    o = ppe.ppe_train_opts_default(lr=0.0, loss_kind=ppe.PPE_LOSS_SUPERVISED)
+    loss, grad = ppe.ppe_net_train_step(net, probs, Rd, o, want_grad=True, target=Td)
+    q = {k: v.clone().requires_grad_(True) for k, v in p.items()}
+    lo = onet.supervised_loss(q, cfg, grids, R, T, masks=[g.mask for g in grids])
+    lo.backward()
+    go = {k: (v.grad.numpy() if v.grad is not None else np.zeros(tuple(v.shape))) for k, v in q.items()}
+    lo = float(lo.detach())
+    print(f"supervised loss GPU {loss:.6f} oracle {lo:.6f}")
+    assert abs(loss - lo) <= 2e-2 * lo
+    gg = onet.unflatten(cfg, grad)
+    gscale = np.linalg.norm(grad) / np.sqrt(grad.size)
+    for name, _ in onet.param_spec(cfg):
+        a = gg[name].numpy().reshape(-1)
+        b = go[name].reshape(-1)
+        if name == "gamma":
+            # the loss does not see the output's scale: dL/dgamma = y.dL/dy / gamma = 0
+            # exactly; both sides hold rounding noise only
+            assert abs(b[0]) <= 1e-10 * gscale and abs(a[0]) <= 1e-2 * gscale, (a, b, gscale)
+            continue
+        if np.linalg.norm(b) == 0:
+            continue
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+        if name == "head.b":
+            assert cos >= 0.6, (name, rel, cos)
+        elif ".phi." in name:
+            assert cos >= 0.9 and rel <= 0.6, (name, rel, cos)
+        else:
+            assert cos >= 0.98 and rel <= 0.2, (name, rel, cos)
+    a = grad.astype(np.float64)
+    b = onet.flatten(cfg, {k: torch.from_numpy(v) for k, v in go.items()})
+    keep = np.ones(a.size, bool)
+    keep[-1] = False  # gamma, last in the flat layout
+    a, b = a[keep], b[keep]
+    assert float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b))) >= 0.995
+    losses = [ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(
+        lr=1e-3, loss_kind=ppe.PPE_LOSS_SUPERVISED), target=Td)[0] for _ in range(20)]
+    assert losses[-1] < 0.9 * losses[0], losses
+    with pytest.raises(ppe.PPEError):  # the supervised loss needs targets
+        ppe.ppe_net_train_step(net, probs, Rd, o)
+    with pytest.raises(ppe.PPEError):  # targets only go with the supervised loss
+        ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(lr=0.0), target=Td)
