@@ -46,7 +46,8 @@ def build(force: bool = False) -> str:
 class _Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("xc", ctypes.c_void_p), ("yc", ctypes.c_void_p),
-                ("hx", ctypes.c_void_p), ("hy", ctypes.c_void_p)]
+                ("hx", ctypes.c_void_p), ("hy", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p), ("mask_mode", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -90,13 +91,21 @@ def _f64(a):
 
 
 class OGrid:
-    """Keeps the FP64 coordinate arrays alive for the C structure."""
+    """Keeps the FP64 coordinate arrays (and the mask) alive for the C
+    structure. solid = True takes the grid's mask into the operator (the
+    solid-mask mode); by default the mask does not enter it."""
 
-    def __init__(self, g):
+    def __init__(self, g, solid=False):
         self.nx, self.ny = int(g.nx), int(g.ny)
         self.xc, self.yc, self.hx, self.hy = _f64(g.xc), _f64(g.yc), _f64(g.hx), _f64(g.hy)
+        self.mask = None
+        if solid:
+            if getattr(g, "mask", None) is None:
+                raise ValueError("the solid-mask mode needs a mask")
+            self.mask = np.ascontiguousarray(g.mask, dtype=np.uint8).reshape(self.ny, self.nx)
         self.c = _Grid(self.nx, self.ny, self.xc.ctypes.data, self.yc.ctypes.data,
-                       self.hx.ctypes.data, self.hy.ctypes.data)
+                       self.hx.ctypes.data, self.hy.ctypes.data,
+                       self.mask.ctypes.data if solid else None, 1 if solid else 0)
 
     @property
     def n(self):
@@ -132,6 +141,15 @@ def rhs(g, f):
     b = np.empty((g.ny, g.nx))
     m = lib().orc_rhs(ctypes.byref(g.c), f32.ctypes.data, b.ctypes.data)
     return b, m
+
+
+def remove_fluid_mean(g, x):
+    """Solid-mask mode's minimum-norm normalisation: subtract the mean over
+    the fluid cells from the fluid cells (solid cells unchanged)."""
+    x = _f64(x).reshape(int(g.ny), int(g.nx)).copy()
+    fl = np.asarray(g.mask).reshape(x.shape) == 0
+    x[fl] -= x[fl].mean()
+    return x
 
 
 def remove_mean(x):

@@ -15,6 +15,13 @@
  * its null space. The source of -lap p = f becomes b = (cell area) * f, and b
  * is projected onto range(A) by removing its plain mean.
  *
+ * Solid-mask mode (mask_mode 1, an option beside the paper's form, in which
+ * the obstacle does not enter the matrix): only faces between two fluid cells
+ * (mask 0) carry weight, and a solid cell's row is the identity, (A x)_c = x_c.
+ * The null space is then the fluid indicator (for a connected fluid region);
+ * b = (cell area) f minus its mean over the fluid cells, on fluid cells, and
+ * 0 on solid cells.
+ *
  * Jacobi-PCG follows the textbook preconditioned CG (Saad, Iterative Methods
  * for Sparse Linear Systems, Alg. 9.1) with D = diag(A). The hybrid solve
  * follows Sec. 2.2: consecutive blocks of at most Num_CG-type CG iterations and
@@ -31,7 +38,14 @@
 typedef struct {
   int32_t nx, ny;
   const double *xc, *yc, *hx, *hy;
+  const uint8_t* mask;  /* [ny][nx], 1 = solid; used in mask_mode 1 only */
+  int32_t mask_mode;    /* 0: the mask does not enter A; 1: solid cells are cut out */
 } orc_grid;
+
+/* 1 when cell (i, j) takes part in the operator as a fluid cell. */
+static int fluid(const orc_grid* g, int i, int j) {
+  return g->mask_mode != 1 || g->mask[(size_t)j * g->nx + i] == 0;
+}
 
 /* Weight of the face between cells (i,j) and (i+1,j): face length hy[j] over
  * centre distance xc[i+1]-xc[i]. */
@@ -49,11 +63,15 @@ void orc_apply(const orc_grid* g, const double* x, double* y) {
   for (int j = 0; j < ny; ++j) {
     for (int i = 0; i < nx; ++i) {
       const double xcen = x[(size_t)j * nx + i];
+      if (!fluid(g, i, j)) {
+        y[(size_t)j * nx + i] = xcen;
+        continue;
+      }
       double s = 0.0;
-      if (i > 0) s += wface_x(g, i - 1, j) * (xcen - x[(size_t)j * nx + i - 1]);
-      if (i < nx - 1) s += wface_x(g, i, j) * (xcen - x[(size_t)j * nx + i + 1]);
-      if (j > 0) s += wface_y(g, i, j - 1) * (xcen - x[(size_t)(j - 1) * nx + i]);
-      if (j < ny - 1) s += wface_y(g, i, j) * (xcen - x[(size_t)(j + 1) * nx + i]);
+      if (i > 0 && fluid(g, i - 1, j)) s += wface_x(g, i - 1, j) * (xcen - x[(size_t)j * nx + i - 1]);
+      if (i < nx - 1 && fluid(g, i + 1, j)) s += wface_x(g, i, j) * (xcen - x[(size_t)j * nx + i + 1]);
+      if (j > 0 && fluid(g, i, j - 1)) s += wface_y(g, i, j - 1) * (xcen - x[(size_t)(j - 1) * nx + i]);
+      if (j < ny - 1 && fluid(g, i, j + 1)) s += wface_y(g, i, j) * (xcen - x[(size_t)(j + 1) * nx + i]);
       y[(size_t)j * nx + i] = s;
     }
   }
@@ -64,11 +82,15 @@ void orc_diag(const orc_grid* g, double* d) {
   const int nx = g->nx, ny = g->ny;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
+      if (!fluid(g, i, j)) {
+        d[(size_t)j * nx + i] = 1.0;
+        continue;
+      }
       double s = 0.0;
-      if (i > 0) s += wface_x(g, i - 1, j);
-      if (i < nx - 1) s += wface_x(g, i, j);
-      if (j > 0) s += wface_y(g, i, j - 1);
-      if (j < ny - 1) s += wface_y(g, i, j);
+      if (i > 0 && fluid(g, i - 1, j)) s += wface_x(g, i - 1, j);
+      if (i < nx - 1 && fluid(g, i + 1, j)) s += wface_x(g, i, j);
+      if (j > 0 && fluid(g, i, j - 1)) s += wface_y(g, i, j - 1);
+      if (j < ny - 1 && fluid(g, i, j + 1)) s += wface_y(g, i, j);
       d[(size_t)j * nx + i] = s;
     }
 }
@@ -79,19 +101,27 @@ double orc_dot(int64_t n, const double* a, const double* b) {
   return s;
 }
 
-/* b = (cell area) f, then b -= mean(b). Returns the removed mean. */
+/* b = (cell area) f, then b -= mean(b) (solid-mask mode: over and on the
+ * fluid cells only, b = 0 on solid cells). Returns the removed mean. */
 double orc_rhs(const orc_grid* g, const float* f, double* b) {
   const int nx = g->nx, ny = g->ny;
-  const int64_t n = (int64_t)nx * ny;
   double sum = 0.0;
+  int64_t count = 0;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const double v = g->hx[i] * g->hy[j] * (double)f[(size_t)j * nx + i];
       b[(size_t)j * nx + i] = v;
-      sum += v;
+      if (fluid(g, i, j)) {
+        sum += v;
+        ++count;
+      }
     }
-  const double mean = sum / (double)n;
-  for (int64_t k = 0; k < n; ++k) b[k] -= mean;
+  const double mean = sum / (double)count;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double* bv = &b[(size_t)j * nx + i];
+      *bv = fluid(g, i, j) ? *bv - mean : 0.0;
+    }
   return mean;
 }
 
