@@ -415,14 +415,14 @@ ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, con
   if (nb < 0) return set_error(PPE_ERR_INVALID_ARG, "nb < 0");
   if (nb > 65535) return set_error(PPE_ERR_INVALID_ARG, "nb > 65535");
   if (nb > 0 && (!f || !x)) return set_error(PPE_ERR_INVALID_ARG, "f or x is NULL");
-  if (p->mask_mode == PPE_MASK_SOLID)
-    return set_error(PPE_ERR_UNSUPPORTED, "PPE_MASK_SOLID operators are not built yet");
   if (opts) {
     if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol))
       return set_error(PPE_ERR_INVALID_ARG, "tol must be finite and >= 0");
     if (opts->max_iter < 0) return set_error(PPE_ERR_INVALID_ARG, "max_iter < 0");
     if (opts->precond != PPE_PC_NONE && opts->precond != PPE_PC_JACOBI && opts->precond != PPE_PC_MG)
       return set_error(PPE_ERR_INVALID_ARG, "unknown preconditioner %d", opts->precond);
+    if (p->mask_mode == PPE_MASK_SOLID && opts->precond == PPE_PC_MG)
+      return set_error(PPE_ERR_UNSUPPORTED, "the multigrid preconditioner does not take PPE_MASK_SOLID grids");
     if (opts->mg_levels < 0 || opts->mg_levels > 12)
       return set_error(PPE_ERR_INVALID_ARG, "mg_levels must lie in [0, 12]");
     if (opts->precond == PPE_PC_MG) {
@@ -436,6 +436,12 @@ ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, con
     if (!(opts->reliable_delta > 0.0 && opts->reliable_delta < 1.0))
       return set_error(PPE_ERR_INVALID_ARG, "reliable_delta must lie in (0, 1)");
   }
+  return PPE_OK;
+}
+
+ppe_status reject_solid(const ppe_problem* p, const char* what) {
+  if (p && p->mask_mode == PPE_MASK_SOLID)
+    return set_error(PPE_ERR_UNSUPPORTED, "%s does not take PPE_MASK_SOLID grids", what);
   return PPE_OK;
 }
 
@@ -616,6 +622,7 @@ ppe_status ppe_apply_precond(ppe_problem* p, int32_t nb, const float* r, float* 
   if (opts) o = *opts;
   o.record_history = 0;
   ppe_status st = check_solve_args(p, nb, r, z, &o);
+  if (st == PPE_OK) st = reject_solid(p, "ppe_apply_precond");
   if (st != PPE_OK) return st;
   if (nb == 0) return PPE_OK;
   const int64_t N = (int64_t)p->nx * p->ny * nb;
@@ -660,6 +667,7 @@ ppe_status ppe_profile_pcg(ppe_problem* p, int32_t nb, const float* f, double* x
   ppe_solve_opts_default(&o);
   if (opts) o = *opts;
   ppe_status st = check_solve_args(p, nb, f, x, &o);
+  if (st == PPE_OK) st = reject_solid(p, "ppe_profile_pcg");
   if (st != PPE_OK) return st;
   if (nb < 1 || reps < 1 || !ms_out) return set_error(PPE_ERR_INVALID_ARG, "nb, reps >= 1 and ms_out required");
   int form, R;
@@ -672,6 +680,7 @@ ppe_status ppe_tune_pcg(ppe_problem* p, int32_t nb, const float* f, double* x, i
   ppe_solve_opts o;
   ppe_solve_opts_default(&o);
   ppe_status st = check_solve_args(p, nb, f, x, &o);
+  if (st == PPE_OK) st = reject_solid(p, "ppe_tune_pcg");
   if (st != PPE_OK) return st;
   if (nb < 1 || reps < 2) return set_error(PPE_ERR_INVALID_ARG, "nb >= 1 and reps >= 2 required");
   // Candidates run the real iteration on (f, x) without a stopping test.

@@ -61,6 +61,7 @@ struct ppe_problem {
   // device copies of the 1D coefficients
   void* dev_coef = nullptr;
   uint8_t* d_mask = nullptr;
+  float* d_solid = nullptr;  // solid-mask mode: fluid flags, then the inverse diagonal
   ppe::Coef coef{};
   ppe::SolveWs ws;
   hipStream_t cap_stream = nullptr;
@@ -125,4 +126,7 @@ ppe_status fill_stats(ppe_problem* p, int nb, ppe_solve_stats* stats, double ms,
 ppe_status attach_extras(ppe_problem* p, PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s);
 ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, const void* x,
                             const ppe_solve_opts* opts);
+// PPE_ERR_UNSUPPORTED for a solid-mask problem (entry points whose kernels
+// carry only the immersed-boundary operator).
+ppe_status reject_solid(const ppe_problem* p, const char* what);
 }  // namespace ppe

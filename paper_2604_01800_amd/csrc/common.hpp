@@ -22,6 +22,13 @@ struct Coef {
   const float *hx, *hy, *gx, *gy;          // [nx], [ny], [nx+1], [ny+1]
   const double *hx64, *hy64, *gx64, *gy64; // same in FP64
   const double *xc64, *yc64;               // cell centres [nx], [ny] (not padded)
+  // Solid-mask operator (NULL otherwise): only faces between two fluid cells
+  // carry weight and solid cells have identity rows. fl is the fluid
+  // indicator (1 fluid, 0 solid), dinv the inverse of that operator's
+  // diagonal (1 on solid cells), both [ny][nx]; nfluid counts the fluid cells.
+  const float* fl;
+  const float* dinv;
+  int64_t nfluid;
 };
 
 // Per-solve iteration state. Fields with a [2] index are written by the

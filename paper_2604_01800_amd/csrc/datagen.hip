@@ -278,6 +278,7 @@ extern "C" ppe_status ppe_generate_rhs(int32_t nb, ppe_problem* const* problems,
   if (nb > 65535) return set_error(PPE_ERR_INVALID_ARG, "nb > 65535");
   for (int i = 0; i < nb; ++i) {
     if (!problems[i]) return set_error(PPE_ERR_INVALID_ARG, "problems[%d] is NULL", i);
+    if (problems[i]->mask_mode == PPE_MASK_SOLID) return reject_solid(problems[i], "ppe_generate_rhs");
     if (problems[i]->nx != problems[0]->nx || problems[i]->ny != problems[0]->ny)
       return set_error(PPE_ERR_SHAPE, "all grids of a batch must have one size");
   }

@@ -221,6 +221,7 @@ extern "C" ppe_status ppe_solve_hybrid(ppe_problem* p, ppe_net* net, int32_t nb,
   ppe_solve_opts_default(&o);
   if (opts) o = *opts;
   ppe_status st = check_solve_args(p, nb, f, x, &o);
+  if (st == PPE_OK) st = reject_solid(p, "ppe_solve_hybrid");
   if (st != PPE_OK) return st;
   if (o.num_cg < 0 || o.num_dlsm < 0 || o.num_cg + o.num_dlsm < 1 || o.num_cg > 64 || o.num_dlsm > 64)
     return set_error(PPE_ERR_INVALID_ARG, "num_cg, num_dlsm must lie in [0, 64] with a positive sum");

@@ -36,7 +36,7 @@ namespace ppe {
 
 // ---------------------------------------------------------------------------
 // y = A x for a batch (parity checks and the line-search step).
-template <typename T, int R>
+template <typename T, int R, bool M>
 __global__ __launch_bounds__(kBlock) void k_apply(Coef c, const T* __restrict__ x, T* __restrict__ y) {
   const int nx = c.nx, ny = c.ny;
   const size_t off = (size_t)blockIdx.z * nx * ny;
@@ -53,6 +53,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(Coef c, const T* __restrict__ 
   if (j0 >= ny) return;
   T vprev = (j0 > 0 && cc.ok) ? x[(size_t)(j0 - 1) * nx + cc.i] : T(0);
   T vcur = cc.ok ? x[(size_t)j0 * nx + cc.i] : T(0);
+  // solid-mask operator: fluid flags of the same cells (0 off the grid)
+  auto flag = [&](bool ok, int j, int i) { return (M && ok) ? (T)c.fl[(size_t)j * nx + i] : T(0); };
+  T mprev = flag(j0 > 0 && cc.ok, j0 - 1, cc.i);
+  T mcur = flag(cc.ok, j0, cc.i);
   for (int q = 0; q < R; ++q) {
     const int j = j0 + q;
     if (j >= ny) break;
@@ -60,7 +64,20 @@ __global__ __launch_bounds__(kBlock) void k_apply(Coef c, const T* __restrict__ 
     const T vh = cc.hok ? x[(size_t)j * nx + cc.ih] : T(0);
     T ve, vw;
     east_west(vcur, vh, ve, vw);
-    const T v = stencil5(vcur, ve, vw, vnext, vprev, hy[j], gy[j], gy[j + 1], cc.hx, cc.gw, cc.ge);
+    T v;
+    if (M) {
+      const T mnext = flag(j + 1 < ny && cc.ok, j + 1, cc.i);
+      const T mh = flag(cc.hok, j, cc.ih);
+      T me, mw;
+      east_west(mcur, mh, me, mw);
+      const T sum = hy[j] * (cc.ge * me * (vcur - ve) + cc.gw * mw * (vcur - vw)) +
+                    cc.hx * (gy[j + 1] * mnext * (vcur - vnext) + gy[j] * mprev * (vcur - vprev));
+      v = mcur * sum + (T(1) - mcur) * vcur;
+      mprev = mcur;
+      mcur = mnext;
+    } else {
+      v = stencil5(vcur, ve, vw, vnext, vprev, hy[j], gy[j], gy[j + 1], cc.hx, cc.gw, cc.ge);
+    }
     if (cc.ok) y[(size_t)j * nx + cc.i] = v;
     vprev = vcur;
     vcur = vnext;
@@ -85,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs_sum(PcgArgs a) {
       if (j >= ny) break;
       const float v = f[(size_t)j * nx + i];
       if (!isfinite(v)) bad += 1.0;
-      else sum += hxi * a.c.hy64[j] * (double)v;
+      else if (!a.c.fl || a.c.fl[(size_t)j * nx + i] != 0.f) sum += hxi * a.c.hy64[j] * (double)v;
     }
   }
   sum = block_sum(sum, lds);
@@ -104,7 +121,8 @@ __global__ __launch_bounds__(kBlock) void k_rhs_norm(PcgArgs a) {
   const double* pb = a.partB + (size_t)s * 2 * a.P;
   const double sum = reduce_partials(pb, a.P, lds);
   const double bad = reduce_partials(pb + a.P, a.P, lds);
-  const double mean = sum / (double)a.N;
+  // the mean over the cells of the operator (the fluid cells with a solid mask)
+  const double mean = sum / (double)(a.c.fl ? a.c.nfluid : a.N);
   SolveState* st = a.st + s;
   if (is_first_block()) {
     st->bmean = mean;
@@ -120,7 +138,9 @@ __global__ __launch_bounds__(kBlock) void k_rhs_norm(PcgArgs a) {
     for (int q = 0; q < a.R; ++q) {
       const int j = j0 + q;
       if (j >= ny) break;
-      const double b = hxi * a.c.hy64[j] * (double)f[(size_t)j * nx + i] - mean;
+      const double b = (a.c.fl && a.c.fl[(size_t)j * nx + i] == 0.f)
+                           ? 0.0
+                           : hxi * a.c.hy64[j] * (double)f[(size_t)j * nx + i] - mean;
       bb += b * b;
     }
   }
@@ -140,8 +160,18 @@ __global__ __launch_bounds__(kBlock) void k_rhs_norm(PcgArgs a) {
 // and accumulates |r|^2 (FP64 value) and r.D^-1 r (FP32 value, exact products).
 // It runs a handful of times per solve, so it walks the rows with a small
 // register footprint instead of holding a full FP64 tile.
+// Preconditioner variants of the two-phase kernels: PC 0 none, 1 Jacobi,
+// 2 a supplied z (multigrid); 3 and 4 are 0 and 1 on the solid-mask operator.
+template <int PC>
+struct PcKind {
+  static constexpr bool mask = PC >= 3;
+  static constexpr int base = PC >= 3 ? PC - 3 : PC;
+};
+
 template <int R, int PC>
 __device__ __forceinline__ void true_residual_rows(const PcgArgs& a, int s, double& acc_rr, double& acc_rz) {
+  constexpr bool M = PcKind<PC>::mask;
+  constexpr int PB = PcKind<PC>::base;
   const int nx = a.c.nx, ny = a.c.ny;
   const size_t off = (size_t)s * a.N;
   const double* __restrict__ x = a.call->x + off;
@@ -156,6 +186,9 @@ __device__ __forceinline__ void true_residual_rows(const PcgArgs& a, int s, doub
   const double bmean = a.st[s].bmean;
   double vprev = (ci.ok && j0 > 0) ? x[(size_t)(j0 - 1) * nx + ci.i] : 0.0;
   double vcur = ci.ok ? x[(size_t)j0 * nx + ci.i] : 0.0;
+  auto flag = [&](bool ok, int j, int i) { return (M && ok) ? (double)a.c.fl[(size_t)j * nx + i] : 0.0; };
+  double mprev = flag(ci.ok && j0 > 0, j0 - 1, ci.i);
+  double mcur = flag(ci.ok, j0, ci.i);
 #pragma unroll 1
   for (int q = 0; q < R; ++q) {
     const int j = j0 + q;
@@ -166,15 +199,32 @@ __device__ __forceinline__ void true_residual_rows(const PcgArgs& a, int s, doub
     double ve, vw;
     east_west(vcur, vh, ve, vw);
     const double hyj = a.c.hy64[j];
-    const double Ax = stencil5(vcur, ve, vw, vnext, vprev, hyj, a.c.gy64[j], a.c.gy64[j + 1], k.hx, k.gw, k.ge);
+    double Ax, bv;
+    if (M) {
+      const double mnext = flag(ci.ok && j + 1 < ny, j + 1, ci.i);
+      const double mh = flag(ci.hok, j, ci.ih);
+      double me, mw;
+      east_west(mcur, mh, me, mw);
+      const double sum = hyj * (k.ge * me * (vcur - ve) + k.gw * mw * (vcur - vw)) +
+                         k.hx * (a.c.gy64[j + 1] * mnext * (vcur - vnext) + a.c.gy64[j] * mprev * (vcur - vprev));
+      Ax = mcur * sum + (1.0 - mcur) * vcur;
+      bv = mcur * (k.hx * hyj * (double)fv - bmean);
+      mprev = mcur;
+      mcur = mnext;
+    } else {
+      Ax = stencil5(vcur, ve, vw, vnext, vprev, hyj, a.c.gy64[j], a.c.gy64[j + 1], k.hx, k.gw, k.ge);
+      bv = k.hx * hyj * (double)fv - bmean;
+    }
     if (ci.ok) {
-      const double rv = (k.hx * hyj * (double)fv - bmean) - Ax;
+      const double rv = bv - Ax;
       const float rr = (float)rv;
       r[(size_t)j * nx + ci.i] = rr;
       acc_rr += rv * rv;
-      if (PC != 2) {
+      if (PB != 2) {
         float z = rr;
-        if (PC == 1) z = rr / (a.c.hy[j] * (kf.gw + kf.ge) + kf.hx * (a.c.gy[j] + a.c.gy[j + 1]));
+        if (PB == 1)
+          z = M ? rr * a.c.dinv[(size_t)j * nx + ci.i]
+                : rr / (a.c.hy[j] * (kf.gw + kf.ge) + kf.hx * (a.c.gy[j] + a.c.gy[j + 1]));
         acc_rz += (double)rr * (double)z;
       }
     }
@@ -250,6 +300,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(PcgArgs a) {
 // blocks); force_restart then also restarts CG (beta = 0) afterwards.
 template <int R, int PC>
 __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force, int force_restart) {
+  constexpr bool M = PcKind<PC>::mask;
+  constexpr int PB = PcKind<PC>::base;
   __shared__ double lds[kWaves];
   const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
   SolveState* st = a.st + s;
@@ -268,8 +320,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
   Tile<float, R> tr, tp;
   float xcv[R];
   // the preconditioned residual: D^-1 r formed below, or z = M^-1 r supplied (PC = 2)
-  load_tile<R>(make_rsrc(PC == 2 ? a.z + off : r, vbytes), nx, ny, j0, ci, tr);
+  load_tile<R>(make_rsrc(PB == 2 ? a.z + off : r, vbytes), nx, ny, j0, ci, tr);
   load_tile<R>(make_rsrc(pold, vbytes), nx, ny, j0, ci, tp);
+  // solid-mask operator: fluid flags and the inverse diagonal on the tile
+  Tile<float, R> tm, td;
+  if (M) {
+    load_tile<R>(make_rsrc(a.c.fl, vbytes), nx, ny, j0, ci, tm);
+    if (PB == 1) load_tile<R>(make_rsrc(a.c.dinv, vbytes), nx, ny, j0, ci, td);
+  }
   load_rows_own<R>(make_rsrc(xc, vbytes), nx, ny, j0, ci, xcv);
   RowCoef<float, R> rc;
   load_rows<float, R>(a.c.hy, a.c.gy, j0, rc);
@@ -366,17 +424,24 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
 #pragma unroll
   for (int q = 0; q < R + 2; ++q) {
     float z = tr.own[q];
-    if (PC == 1) z = z / fmaxf(rc.hy[q] * (k.gw + k.ge) + k.hx * (rc.gy[q] + rc.gy[q + 1]), 1e-30f);
+    if (PB == 1) {
+      if (M) z = z * td.own[q];
+      else z = z / fmaxf(rc.hy[q] * (k.gw + k.ge) + k.hx * (rc.gy[q] + rc.gy[q + 1]), 1e-30f);
+    }
     pn.own[q] = z + beta * tp.own[q];
   }
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     float z = tr.halo[q];
-    if (PC == 1) z = z / fmaxf(rc.hy[q + 1] * (k.gwh + k.geh) + k.hxh * (rc.gy[q + 1] + rc.gy[q + 2]), 1e-30f);
+    if (PB == 1) {
+      if (M) z = z * td.halo[q];
+      else z = z / fmaxf(rc.hy[q + 1] * (k.gwh + k.geh) + k.hxh * (rc.gy[q + 1] + rc.gy[q + 2]), 1e-30f);
+    }
     pn.halo[q] = z + beta * tp.halo[q];
   }
   float Ap[R];
-  stencil_rows<float, R>(pn, rc, k, Ap);
+  if (M) stencil_rows_masked<R>(pn, tm, rc, k, Ap);
+  else stencil_rows<float, R>(pn, rc, k, Ap);
   double acc = 0.0;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -408,6 +473,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs a, int par, int force,
 // Phase B: CG residual update, or the FP64 true residual after a flush.
 template <int R, int PC>
 __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int par) {
+  constexpr bool M = PcKind<PC>::mask;
+  constexpr int PB = PcKind<PC>::base;
   __shared__ double lds[kWaves];
   const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
   SolveState* st = a.st + s;
@@ -431,10 +498,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int par) {
     const ColIdx ci = col_idx(nx, tl);
     const int j0 = tl.j0;
     const uint64_t vbytes = (uint64_t)a.N * 4;
-    Tile<float, R> tp;
-    float rv[R];
+    Tile<float, R> tp, tm;
+    float rv[R], dv[R];
     load_tile<R>(make_rsrc(p, vbytes), nx, ny, j0, ci, tp);
     load_rows_own<R>(make_rsrc(r, vbytes), nx, ny, j0, ci, rv);
+    if (M) {
+      load_tile<R>(make_rsrc(a.c.fl, vbytes), nx, ny, j0, ci, tm);
+      if (PB == 1) load_rows_own<R>(make_rsrc(a.c.dinv, vbytes), nx, ny, j0, ci, dv);
+    }
     RowCoef<float, R> rc;
     load_rows<float, R>(a.c.hy, a.c.gy, j0, rc);
     const ColCoef<float> k = load_cols<float>(a.c.hx, a.c.gx, ci);
@@ -446,7 +517,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int par) {
     if (brk) al = 0.0;
     const float alf = (float)al;
     float Ap[R];
-    stencil_rows<float, R>(tp, rc, k, Ap);
+    if (M) stencil_rows_masked<R>(tp, tm, rc, k, Ap);
+    else stencil_rows<float, R>(tp, rc, k, Ap);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int j = j0 + q;
@@ -454,9 +526,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs a, int par) {
         const float rn = rv[q] - alf * Ap[q];
         r[(size_t)j * nx + ci.i] = rn;
         acc_rr += (double)rn * (double)rn;
-        if (PC != 2) {
+        if (PB != 2) {
           float z = rn;
-          if (PC == 1) z = rn / (rc.hy[q + 1] * (k.gw + k.ge) + k.hx * (rc.gy[q + 1] + rc.gy[q + 2]));
+          if (PB == 1) z = M ? rn * dv[q] : rn / (rc.hy[q + 1] * (k.gw + k.ge) + k.hx * (rc.gy[q + 1] + rc.gy[q + 2]));
           acc_rz += (double)rn * (double)z;
         }
       }
@@ -714,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void k_x_sum(PcgArgs a) {
     for (int q = 0; q < a.R; ++q) {
       const int j = j0 + q;
       if (j >= ny) break;
-      sum += x[(size_t)j * nx + i];
+      if (!a.c.fl || a.c.fl[(size_t)j * nx + i] != 0.f) sum += x[(size_t)j * nx + i];
     }
   sum = block_sum(sum, lds);
   if (threadIdx.x == 0) a.partA[(size_t)s * a.P + block_linear()] = sum;
@@ -723,7 +795,9 @@ __global__ __launch_bounds__(kBlock) void k_x_sum(PcgArgs a) {
 __global__ __launch_bounds__(kBlock) void k_x_shift(PcgArgs a) {
   __shared__ double lds[kWaves];
   const int s = blockIdx.z, nx = a.c.nx, ny = a.c.ny;
-  const double mean = reduce_partials(a.partA + (size_t)s * a.P, a.P, lds) / (double)a.N;
+  // the minimum-norm solution: zero mean over the operator's cells (the
+  // fluid cells with a solid mask, whose solid cells keep their values)
+  const double mean = reduce_partials(a.partA + (size_t)s * a.P, a.P, lds) / (double)(a.c.fl ? a.c.nfluid : a.N);
   if (is_first_block()) a.st[s].xmean = mean;
   double* x = a.call->x + (size_t)s * a.N;
   const TileXY tl = tile_xy(nx, ny, a.R);
@@ -733,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_x_shift(PcgArgs a) {
     for (int q = 0; q < a.R; ++q) {
       const int j = j0 + q;
       if (j >= ny) break;
-      x[(size_t)j * nx + i] -= mean;
+      if (!a.c.fl || a.c.fl[(size_t)j * nx + i] != 0.f) x[(size_t)j * nx + i] -= mean;
     }
 }
 
@@ -778,10 +852,18 @@ static dim3 grid_of(const Coef& c, int nb) {
   }
 
 void launch_apply_f32(const Coef& c, int nb, const float* x, float* y, int R, hipStream_t s) {
-  PPE_DISPATCH_R(R, k_apply<float, RR><<<grid_of<RR>(c, nb), kBlock, 0, s>>>(c, x, y));
+  if (c.fl) {
+    PPE_DISPATCH_R(R, k_apply<float, RR, true><<<grid_of<RR>(c, nb), kBlock, 0, s>>>(c, x, y));
+  } else {
+    PPE_DISPATCH_R(R, k_apply<float, RR, false><<<grid_of<RR>(c, nb), kBlock, 0, s>>>(c, x, y));
+  }
 }
 void launch_apply_f64(const Coef& c, int nb, const double* x, double* y, int R, hipStream_t s) {
-  PPE_DISPATCH_R(R, k_apply<double, RR><<<grid_of<RR>(c, nb), kBlock, 0, s>>>(c, x, y));
+  if (c.fl) {
+    PPE_DISPATCH_R(R, k_apply<double, RR, true><<<grid_of<RR>(c, nb), kBlock, 0, s>>>(c, x, y));
+  } else {
+    PPE_DISPATCH_R(R, k_apply<double, RR, false><<<grid_of<RR>(c, nb), kBlock, 0, s>>>(c, x, y));
+  }
 }
 
 void launch_set_call(CallArgs* c, const float* f, double* x, int max_iter, double delta2,
@@ -795,11 +877,17 @@ void launch_rhs(const PcgArgs& a, int nb, hipStream_t s) {
   k_rhs_norm<<<g, kBlock, 0, s>>>(a);
 }
 
-// Kernel variant of the preconditioner: 0 none, 1 Jacobi, 2 a supplied z (multigrid).
-static int pc_of(const PcgArgs& a) { return a.mg ? 2 : (a.jacobi ? 1 : 0); }
+// Kernel variant (PcKind): 0 none, 1 Jacobi, 2 a supplied z (multigrid);
+// 3, 4: none, Jacobi on the solid-mask operator.
+static int pc_of(const PcgArgs& a) {
+  if (a.mg) return 2;
+  return (a.c.fl ? 3 : 0) + (a.jacobi ? 1 : 0);
+}
 
 #define PPE_DISPATCH_PC(pc, R, ...)                                   \
   switch (pc) {                                                       \
+    case 4: { constexpr int PP = 4; PPE_DISPATCH_R(R, __VA_ARGS__); } break; \
+    case 3: { constexpr int PP = 3; PPE_DISPATCH_R(R, __VA_ARGS__); } break; \
     case 2: { constexpr int PP = 2; PPE_DISPATCH_R(R, __VA_ARGS__); } break; \
     case 1: { constexpr int PP = 1; PPE_DISPATCH_R(R, __VA_ARGS__); } break; \
     default: { constexpr int PP = 0; PPE_DISPATCH_R(R, __VA_ARGS__); } break; \

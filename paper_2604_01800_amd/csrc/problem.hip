@@ -75,7 +75,40 @@ ppe_status problem_upload(ppe_problem* p, hipStream_t s) {
                               p->yc.data(), s, h64, h32, &p->dev_coef, &p->coef);
   if (up != PPE_OK) return up;
   ppe_status st = PPE_OK;
-  if (!p->mask.empty()) {
+  std::vector<float> fl, dinv;
+  if (p->mask_mode == PPE_MASK_SOLID) {
+    // fluid flags and the inverse diagonal of the solid-mask operator (FP64, rounded once)
+    const size_t N = (size_t)nx * ny;
+    fl.resize(N);
+    dinv.resize(N);
+    int64_t nf = 0;
+    auto isf = [&](int i, int j) { return p->mask[(size_t)j * nx + i] == 0; };
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const size_t c = (size_t)j * nx + i;
+        fl[c] = isf(i, j) ? 1.f : 0.f;
+        if (!isf(i, j)) {
+          dinv[c] = 1.f;
+          continue;
+        }
+        ++nf;
+        double d = 0.0;
+        if (i > 0 && isf(i - 1, j)) d += p->hy[j] * gx[i];
+        if (i + 1 < nx && isf(i + 1, j)) d += p->hy[j] * gx[i + 1];
+        if (j > 0 && isf(i, j - 1)) d += p->hx[i] * gy[j];
+        if (j + 1 < ny && isf(i, j + 1)) d += p->hx[i] * gy[j + 1];
+        dinv[c] = d > 0.0 ? (float)(1.0 / d) : 0.f;  // an isolated fluid cell has no equation
+      }
+    p->d_solid = (float*)dev_alloc(sizeof(float) * 2 * N);
+    if (!p->d_solid) st = set_error(PPE_ERR_HIP, "device allocation of the solid-mask arrays failed");
+    else if (hipMemcpyAsync(p->d_solid, fl.data(), sizeof(float) * N, hipMemcpyHostToDevice, s) != hipSuccess ||
+             hipMemcpyAsync(p->d_solid + N, dinv.data(), sizeof(float) * N, hipMemcpyHostToDevice, s) != hipSuccess)
+      st = set_error(PPE_ERR_HIP, "upload of the solid-mask arrays failed");
+    p->coef.fl = p->d_solid;
+    p->coef.dinv = p->d_solid + N;
+    p->coef.nfluid = nf;
+  }
+  if (st == PPE_OK && !p->mask.empty()) {
     p->d_mask = (uint8_t*)dev_alloc(p->mask.size());
     if (!p->d_mask) st = set_error(PPE_ERR_HIP, "device allocation of the mask failed");
     else if (hipMemcpyAsync(p->d_mask, p->mask.data(), p->mask.size(), hipMemcpyHostToDevice, s) != hipSuccess)
@@ -96,6 +129,8 @@ void problem_release(ppe_problem* p) {
   p->dev_coef = nullptr;
   dev_free(p->d_mask);
   p->d_mask = nullptr;
+  dev_free(p->d_solid);
+  p->d_solid = nullptr;
 }
 
 }  // namespace ppe

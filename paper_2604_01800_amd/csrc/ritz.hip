@@ -270,6 +270,7 @@ extern "C" void ppe_ritz_destroy(ppe_ritz* r) {
 extern "C" ppe_status ppe_ritz_create(ppe_problem* p, int32_t m, const double* v0, ppe_ritz** out, hipStream_t s) {
   if (!p || !v0 || !out) return set_error(PPE_ERR_INVALID_ARG, "problem, v0 or out is NULL");
   *out = nullptr;
+  if (p->mask_mode == PPE_MASK_SOLID) return reject_solid(p, "ppe_ritz_create");
   const int64_t N = (int64_t)p->nx * p->ny;
   if (m < 1 || m > 8192 || m >= N) return set_error(PPE_ERR_INVALID_ARG, "m must lie in [1, min(8192, N - 1)]");
   ppe_ritz* r = new ppe_ritz();

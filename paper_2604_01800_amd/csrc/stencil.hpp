@@ -231,6 +231,26 @@ __device__ __forceinline__ void stencil_rows(const Tile<T, R>& v, const RowCoef<
   }
 }
 
+// The solid-mask operator on the R rows of the tile: face terms weighted by
+// the neighbour's fluid flag, the sum by the own cell's, and x itself on solid
+// cells. m holds the fluid flags (0 or 1) in the tile's layout.
+template <int R>
+__device__ __forceinline__ void stencil_rows_masked(const Tile<float, R>& v, const Tile<float, R>& m,
+                                                    const RowCoef<float, R>& rc, const ColCoef<float>& k,
+                                                    float (&out)[R]) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const float vc = v.own[q + 1], mc = m.own[q + 1];
+    float ve, vw, me, mw;
+    east_west(vc, v.halo[q], ve, vw);
+    east_west(mc, m.halo[q], me, mw);
+    const float s = rc.hy[q + 1] * (k.ge * me * (vc - ve) + k.gw * mw * (vc - vw)) +
+                    k.hx * (rc.gy[q + 2] * m.own[q + 2] * (vc - v.own[q + 2]) +
+                            rc.gy[q + 1] * m.own[q] * (vc - v.own[q]));
+    out[q] = mc * s + (1.f - mc) * vc;
+  }
+}
+
 // FP64 sum over a wavefront on DPP lane moves (no LDS traffic): within each
 // row of 16 lanes, quad xor 1, quad xor 2, half-row mirror and row mirror
 // leave the row sum in every lane of the row (each step adds commuted equal

@@ -231,6 +231,8 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
   if (opts->loss_kind == PPE_LOSS_RESIDUAL && target)
     return set_error(PPE_ERR_INVALID_ARG, "target is given but the loss is the residual loss");
   if (nb < 1 || nb > 4096) return set_error(PPE_ERR_INVALID_ARG, "nb must lie in [1, 4096]");
+  for (int i = 0; i < nb; ++i)
+    if (problems[i] && problems[i]->mask_mode == PPE_MASK_SOLID) return reject_solid(problems[i], "ppe_net_train_step");
   if (!R) {
     ppe_status sg = check_gen_opts(*opts);
     if (sg != PPE_OK) return sg;
