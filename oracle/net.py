@@ -359,6 +359,27 @@ def supervised_loss_of(y, e):
     return 1.0 - (y0 * e0).sum() ** 2 / ((y0 * y0).sum() * (e0 * e0).sum())
 
 
+def anorm_loss_of(y, R, e, Ay):
+    """One minus the share of the A-norm error that one exact line search
+    along y removes (the DLSM step of Eqs. 12-13 with residual R and error
+    e = A^+ R): 1 - (R . y)^2 / ((y . A y)(R . e)). Ay is A y. Invariant to
+    the scale of y and to constants in it (A 1 = 0 and R . 1 = 0). This loss
+    is an option beside Eq. 19: it weights the misfit by A once, where the
+    residual loss weights it by A^2."""
+    return 1.0 - (R * y).sum() ** 2 / ((y * Ay).sum() * (R * e).sum())
+
+
+def anorm_loss(p, cfg, grids, R, targets, masks=None, apply=None):
+    """Batch mean of anorm_loss_of(NN(R_s), R_s, e_s, A NN(R_s)) with the FP64
+    target e_s (the solution of A e_s = R_s); apply(grid, y) -> A y."""
+    total = 0.0
+    for s, g in enumerate(grids):
+        y = forward(p, cfg, g, R[s:s + 1], None if masks is None else masks[s])[0]
+        Rs = torch.as_tensor(R[s], dtype=torch.float64)
+        total = total + anorm_loss_of(y, Rs, torch.as_tensor(targets[s], dtype=torch.float64), apply(g, y))
+    return total / len(grids)
+
+
 def supervised_loss(p, cfg, grids, R, targets, masks=None):
     """Batch mean of supervised_loss_of(NN(R_s), e_s) (the FP64 target e_s,
     typically the solution of A e_s = R_s)."""

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 from paper_2604_01800_amd import inputs
+from oracle import direct
 from oracle import net as onet
 
 
@@ -268,3 +269,85 @@ def test_fd_gradients_of_supervised_loss():
             assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * abs(float(loss.detach()))), (name, idx, fd, an)
             checked += 1
     assert checked >= 15
+
+
+def test_anorm_loss_is_the_line_search_share(orc):
+    """The A-norm loss equals |e - alpha y|_A^2 / |e|_A^2 after the exact
+    line search alpha = (R . y) / (y . A y) along y (Eqs. 12-13), computed
+    here from the error directly; it is 0 for y = c e + d and 1 for a y
+    A-orthogonal to e."""
+    g = inputs.make_grid(14, 11, 1.7, 1.2)
+    rng = np.random.default_rng(12)
+    e = rng.standard_normal((11, 14))
+    e -= e.mean()
+    R = orc.apply(g, e)
+    y = rng.standard_normal((11, 14))
+    A = lambda v: orc.apply(g, v)
+    alpha = (R * y).sum() / (y * A(y)).sum()
+    d = e - alpha * y
+    want = (d * A(d)).sum() / (e * A(e)).sum()
+    t = lambda a: torch.from_numpy(np.asarray(a, dtype=np.float64))
+    got = float(onet.anorm_loss_of(t(y), t(R), t(e), t(A(y))))
+    assert abs(got - want) <= 1e-13
+    assert 0.0 < got < 1.0
+    for c, dd in [(-2.5, 0.0), (0.3, 4.0)]:
+        yy = c * e + dd
+        assert abs(float(onet.anorm_loss_of(t(yy), t(R), t(e), t(A(yy))))) <= 1e-13
+    # a direction A-orthogonal to e removes nothing
+    z = y - (y * A(e)).sum() / (e * A(e)).sum() * e
+    assert abs(float(onet.anorm_loss_of(t(z), t(R), t(e), t(A(z)))) - 1.0) <= 1e-13
+
+
+def test_anorm_loss_on_two_eigenmodes(orc):
+    """Uniform grid: with e = v1 + v2 (cosine eigenvectors of A with
+    eigenvalues l1, l2) and y = v1 the loss is l2|v2|^2 / (l1|v1|^2 + l2|v2|^2)."""
+    n = 12
+    g = inputs.make_grid(n, n, 0.0)
+    h = 1.0 / n
+    xc = (np.arange(n) + 0.5) * h
+    v1 = np.outer(np.ones(n), np.cos(np.pi * xc))
+    v2 = np.outer(np.cos(3 * np.pi * xc), np.cos(2 * np.pi * xc))
+    lam = lambda kx, ky: (2 - 2 * np.cos(np.pi * kx * h)) / h ** 2 * h * h + (2 - 2 * np.cos(np.pi * ky * h)) / h ** 2 * h * h
+    l1, l2 = lam(1, 0), lam(2, 3)
+    np.testing.assert_allclose(orc.apply(g, v1), l1 * v1, atol=1e-12)
+    np.testing.assert_allclose(orc.apply(g, v2), l2 * v2, atol=1e-12)
+    e = v1 + v2
+    R = orc.apply(g, e)
+    t = lambda a: torch.from_numpy(np.asarray(a, dtype=np.float64))
+    got = float(onet.anorm_loss_of(t(v1), t(R), t(e), t(orc.apply(g, v1))))
+    n1, n2 = (v1 * v1).sum(), (v2 * v2).sum()
+    assert abs(got - l2 * n2 / (l1 * n1 + l2 * n2)) <= 1e-12
+
+
+def test_fd_gradients_of_anorm_loss(orc):
+    cfg = small_cfg()
+    n = 16
+    rng = np.random.default_rng(9)
+    grids = [inputs.make_grid(n, n, b) for b in (1.3, 2.0)]
+    E = rng.standard_normal((2, n, n))
+    R = np.stack([orc.apply(gr, E[i]) for i, gr in enumerate(grids)])
+    mats = {id(gr): torch.from_numpy(direct.kron_matrix(gr)) for gr in grids}
+    app = lambda gr, y: (mats[id(gr)] @ y.reshape(-1)).reshape(y.shape)
+    p = onet.init_params(cfg, rng)
+    for t in p.values():
+        t.requires_grad_(True)
+    loss = onet.anorm_loss(p, cfg, grids, R, E, apply=app)
+    loss.backward()
+    checked = 0
+    for name in ["enc0.a.W", "dec0.d.W", "head.W", "trunk1.W", "enc1.b.phi.W1", "up0.b"]:
+        t = p[name]
+        flat = t.detach().reshape(-1)
+        for idx in rng.choice(flat.numel(), size=min(3, flat.numel()), replace=False):
+            v0 = float(flat[idx])
+            h = 1e-6 * max(1.0, abs(v0))
+            vals = []
+            for sgn in (+1, -1):
+                with torch.no_grad():
+                    q = {k: v.detach().clone() for k, v in p.items()}
+                    q[name].reshape(-1)[idx] = v0 + sgn * h
+                    vals.append(float(onet.anorm_loss(q, cfg, grids, R, E, apply=app)))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = float(t.grad.reshape(-1)[idx])
+            assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * abs(float(loss.detach()))), (name, idx, fd, an)
+            checked += 1
+    assert checked >= 12
