@@ -196,7 +196,7 @@ typedef struct {
   float clip_norm;              /* > 0: scale the gradient to this L2 norm before Adam when larger (default 0) */
   float sam_rho;                /* > 0: sharpness-aware step (Sec. 2.4): the gradient Adam uses is taken at
                                    w + sam_rho g / |g| (two forward/backward passes; default 0) */
-  int32_t loss_kind;            /* PPE_LOSS_RESIDUAL (default, Eq. 19) or PPE_LOSS_SUPERVISED */
+  int32_t loss_kind;            /* PPE_LOSS_RESIDUAL (default, Eq. 19), PPE_LOSS_SUPERVISED or PPE_LOSS_ANORM */
 } ppe_train_opts;
 
 /* Training loss. RESIDUAL is Eq. 19, mean over cells of (R - A NN(R))^2.
@@ -205,8 +205,15 @@ typedef struct {
  * Eqs. 12-13 is blind to the output's scale and to constants (A 1 = 0), the
  * loss is scale- and shift-invariant: with y0 = y - mean(y),
  * L = 1 - (y0 . e*)^2 / (|y0|^2 |e*|^2) per sample (0 when y0 is a multiple of
- * e*), averaged over the batch. */
-enum { PPE_LOSS_RESIDUAL = 0, PPE_LOSS_SUPERVISED = 1 };
+ * e*), averaged over the batch.
+ * ANORM is one minus the share of the A-norm error that one exact line
+ * search along the output removes (the DLSM step of Eqs. 12-13 with e* the
+ * error): L = 1 - (R . y)^2 / ((y . A y)(R . e*)) per sample, averaged over
+ * the batch; scale- and shift-invariant like SUPERVISED, but the misfit is
+ * weighted by A once (Eq. 19 weights it by A^2, SUPERVISED not at all). A
+ * sample with y . A y <= 0 or R . e* <= 0 counts 1 with no gradient. Both
+ * SUPERVISED and ANORM are options beside the paper's Eq. 19. */
+enum { PPE_LOSS_RESIDUAL = 0, PPE_LOSS_SUPERVISED = 1, PPE_LOSS_ANORM = 2 };
 
 /* ---- problem: per-grid setup, built once and reused. The coefficient
  *      matrix of the PPE stays constant over a simulation, so its
@@ -223,6 +230,13 @@ void ppe_solve_opts_default(ppe_solve_opts* o);
  * x, y: device [nb][ny][nx]. */
 ppe_status ppe_apply_f32(const ppe_problem* p, int32_t nb, const float* x, float* y, hipStream_t s);
 ppe_status ppe_apply_f64(const ppe_problem* p, int32_t nb, const double* x, double* y, hipStream_t s);
+
+/* f = b / (cell area), elementwise in FP64 rounded to FP32: the source
+ * whose right-hand side (Eq. 10, b = cell area x f) is b, so that a caller
+ * holding right-hand sides (the training vectors of Eqs. 15-16, for one)
+ * can solve A x = b with ppe_solve_plain. b, f: device FP32 [nb][ny][nx];
+ * may alias. Enqueued on s; does not synchronise. */
+ppe_status ppe_rhs_to_source(const ppe_problem* p, int32_t nb, const float* b, float* f, hipStream_t s);
 
 /* z = M^-1 r for the preconditioner opts->precond selects (opts NULL:
  * defaults): PPE_PC_JACOBI z = D^-1 r; PPE_PC_MG one V-cycle from a zero
@@ -321,13 +335,13 @@ ppe_status ppe_generate_grid(int32_t nx, int32_t ny, uint64_t seed, uint64_t ste
 
 /* One Adam step on nb fabricated systems with the residual loss of Eq. 19,
  * Loss = mean over cells of (R - A NN(R))^2, averaged over the batch, or with
- * the supervised loss (opts->loss_kind; see PPE_LOSS_SUPERVISED).
+ * the supervised or A-norm loss (opts->loss_kind; see PPE_LOSS_SUPERVISED).
  * problems: host array of nb grids of one size (each sample has its own grid);
  * R: device FP32 [nb][ny][nx] (zero-sum residual fields), or NULL: the
  * library then generates the batch with ppe_generate_rhs from opts (seed,
  * step, length-scale range, features).
  * target: device FP64 [nb][ny][nx], the error fields e* of the supervised
- * loss (required with PPE_LOSS_SUPERVISED and an explicit R, NULL otherwise).
+ * and A-norm losses (required with those and an explicit R, NULL otherwise).
  * loss_out: host, the batch loss before the step. grad_out: host or NULL;
  * when given, receives the FP32 gradient that Adam uses (ppe_net_num_params
  * values; with sam_rho > 0 the one at the perturbed weights).

@@ -615,6 +615,14 @@ ppe_status ppe_apply_f64(const ppe_problem* p, int32_t nb, const double* x, doub
   return PPE_OK;
 }
 
+ppe_status ppe_rhs_to_source(const ppe_problem* p, int32_t nb, const float* b, float* f, hipStream_t s) {
+  if (!p || nb < 0 || (nb > 0 && (!b || !f))) return set_error(PPE_ERR_INVALID_ARG, "bad arguments");
+  if (nb == 0) return PPE_OK;
+  launch_rhs_to_source(p->coef, nb, b, f, s);
+  HIPCHK(hipGetLastError());
+  return PPE_OK;
+}
+
 ppe_status ppe_apply_precond(ppe_problem* p, int32_t nb, const float* r, float* z, const ppe_solve_opts* opts,
                              hipStream_t s) {
   ppe_solve_opts o;

@@ -851,6 +851,20 @@ static dim3 grid_of(const Coef& c, int nb) {
     default: { constexpr int RR = 16; __VA_ARGS__; } break; \
   }
 
+// f = b / (cell area), one thread per cell.
+__global__ __launch_bounds__(256) void k_rhs_to_source(Coef c, int64_t n, const float* b, float* f) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  const int64_t cell = q % ((int64_t)c.nx * c.ny);
+  const int j = (int)(cell / c.nx), i = (int)(cell - (int64_t)j * c.nx);
+  f[q] = (float)((double)b[q] / (c.hx64[i] * c.hy64[j]));
+}
+
+void launch_rhs_to_source(const Coef& c, int nb, const float* b, float* f, hipStream_t s) {
+  const int64_t n = (int64_t)c.nx * c.ny * nb;
+  k_rhs_to_source<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(c, n, b, f);
+}
+
 void launch_apply_f32(const Coef& c, int nb, const float* x, float* y, int R, hipStream_t s) {
   if (c.fl) {
     PPE_DISPATCH_R(R, k_apply<float, RR, true><<<grid_of<RR>(c, nb), kBlock, 0, s>>>(c, x, y));

@@ -224,10 +224,11 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
                                          const double* target, const ppe_train_opts* opts, float* loss_out,
                                          float* grad_out, hipStream_t s) {
   if (!n || !problems || !opts) return set_error(PPE_ERR_INVALID_ARG, "net, problems or opts NULL");
-  if (opts->loss_kind != PPE_LOSS_RESIDUAL && opts->loss_kind != PPE_LOSS_SUPERVISED)
+  if (opts->loss_kind != PPE_LOSS_RESIDUAL && opts->loss_kind != PPE_LOSS_SUPERVISED &&
+      opts->loss_kind != PPE_LOSS_ANORM)
     return set_error(PPE_ERR_INVALID_ARG, "loss_kind %d", opts->loss_kind);
-  if (opts->loss_kind == PPE_LOSS_SUPERVISED && (!R || !target))
-    return set_error(PPE_ERR_INVALID_ARG, "the supervised loss needs an explicit batch R and its target");
+  if (opts->loss_kind != PPE_LOSS_RESIDUAL && (!R || !target))
+    return set_error(PPE_ERR_INVALID_ARG, "the supervised and A-norm losses need an explicit batch R and its target");
   if (opts->loss_kind == PPE_LOSS_RESIDUAL && target)
     return set_error(PPE_ERR_INVALID_ARG, "target is given but the loss is the residual loss");
   if (nb < 1 || nb > 4096) return set_error(PPE_ERR_INVALID_ARG, "nb must lie in [1, 4096]");
@@ -267,7 +268,8 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
   if (st != PPE_OK) return st;
   TrainState* t = n->train;
   const bool supervised = opts->loss_kind == PPE_LOSS_SUPERVISED;
-  if (supervised && t->sup_nb < nb) {
+  const bool anorm = opts->loss_kind == PPE_LOSS_ANORM;
+  if ((supervised || anorm) && t->sup_nb < nb) {
     dev_free(t->sup);
     t->sup = (double*)dev_alloc(sizeof(double) * ((size_t)nb * 5 * kSupParts + nb));
     t->sup_nb = t->sup ? nb : 0;
@@ -436,6 +438,11 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
     if (supervised) {
       // ---- supervised loss: dL/dy straight into gAy ----
       launch_sup_loss(N, nb, y, target, t->sup, kSupParts, gAy, t->sup + (size_t)nb * 5 * kSupParts, s);
+      launch_sum_parts(t->sup + (size_t)nb * 5 * kSupParts, nb, 1.0 / nb, lpart + kRedBlocks, s);
+    } else if (anorm) {
+      // ---- A-norm loss: dL/dy = c_R R + c_A A y per sample, into gAy ----
+      launch_apply_multi(t->d_coefs, nx, ny, nb, y, Ay, s);
+      launch_anorm_loss(N, nb, y, Ay, R, target, t->sup, kSupParts, gAy, t->sup + (size_t)nb * 5 * kSupParts, s);
       launch_sum_parts(t->sup + (size_t)nb * 5 * kSupParts, nb, 1.0 / nb, lpart + kRedBlocks, s);
     } else {
       // ---- loss (Eq. 19): res = R - A y, L = mean(res^2); dL/dy = -2/(nb N) A res ----

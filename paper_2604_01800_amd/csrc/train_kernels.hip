@@ -808,6 +808,48 @@ __global__ __launch_bounds__(256) void k_sup_grad(int64_t N, int nb, const float
     ds[p] = (float)(g * (ab * ((double)ys[p] - my) - (es[p] - me)));
 }
 
+// Per-sample partial sums of the A-norm loss: R.y, y.Ay, R.e (FP64).
+__global__ __launch_bounds__(256) void k_anorm_sums(int64_t N, const float* __restrict__ y,
+                                                    const float* __restrict__ Ay, const float* __restrict__ R,
+                                                    const double* __restrict__ e, double* __restrict__ part) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.y;
+  const size_t o = (size_t)s * N;
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (int64_t)gridDim.x * 256) {
+    const double yv = y[o + p], rv = R[o + p];
+    a[0] += rv * yv;
+    a[1] += yv * (double)Ay[o + p];
+    a[2] += rv * e[o + p];
+  }
+  for (int m = 0; m < 3; ++m) {
+    const double v = block_sum(a[m], lds);
+    if (threadIdx.x == 0) part[((size_t)s * 3 + m) * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// A-norm loss L_s = 1 - a^2 / (b c) with a = R.y, b = y.Ay, c = R.e, and its
+// gradient averaged over the nb samples (A symmetric):
+// dL/dy = (2 a / (b c nb)) (a/b A y - R). b <= 0 or c <= 0 gives L = 1 and no
+// gradient. Every workgroup reduces the partials in the same order.
+__global__ __launch_bounds__(256) void k_anorm_grad(int64_t N, int nb, const float* __restrict__ Ay,
+                                                    const float* __restrict__ R, const double* __restrict__ part,
+                                                    int nparts, float* __restrict__ dy, double* __restrict__ lsamp) {
+  __shared__ double lds[kWaves];
+  const int s = blockIdx.y;
+  double S[3];
+  for (int m = 0; m < 3; ++m) S[m] = reduce_partials(part + ((size_t)s * 3 + m) * nparts, nparts, lds);
+  const double a = S[0], b = S[1], c = S[2];
+  const bool ok = b > 0.0 && c > 0.0 && isfinite(a);
+  const double L = ok ? 1.0 - a * a / (b * c) : 1.0;
+  const double g = ok ? 2.0 * a / (b * c * (double)nb) : 0.0;
+  const double ab = ok ? a / b : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) lsamp[s] = L;
+  const size_t o = (size_t)s * N;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (int64_t)gridDim.x * 256)
+    dy[o + p] = (float)(g * (ab * (double)Ay[o + p] - (double)R[o + p]));
+}
+
 __global__ void k_sum_parts(const double* __restrict__ part, int n, double scale, double* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double s = 0.0;
@@ -975,6 +1017,12 @@ void launch_sup_loss(int64_t N, int nb, const float* y, const double* e, double*
                      double* lsamp, hipStream_t s) {
   k_sup_sums<<<dim3(nparts, nb), 256, 0, s>>>(N, y, e, part);
   k_sup_grad<<<dim3(nparts, nb), 256, 0, s>>>(N, nb, y, e, part, nparts, dy, lsamp);
+}
+
+void launch_anorm_loss(int64_t N, int nb, const float* y, const float* Ay, const float* R, const double* e,
+                       double* part, int nparts, float* dy, double* lsamp, hipStream_t s) {
+  k_anorm_sums<<<dim3(nparts, nb), 256, 0, s>>>(N, y, Ay, R, e, part);
+  k_anorm_grad<<<dim3(nparts, nb), 256, 0, s>>>(N, nb, Ay, R, part, nparts, dy, lsamp);
 }
 
 void launch_sum_parts(const double* part, int n, double scale, double* out, hipStream_t s) {

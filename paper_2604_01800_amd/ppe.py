@@ -20,7 +20,7 @@ PPE_OK, PPE_NOT_CONVERGED = 0, 1
 PPE_ERR_INVALID_ARG, PPE_ERR_SHAPE, PPE_ERR_UNSUPPORTED, PPE_ERR_HIP, PPE_ERR_NONFINITE = -1, -2, -3, -4, -5
 PPE_PC_NONE, PPE_PC_JACOBI, PPE_PC_MG = 0, 1, 2
 PPE_MASK_DIBPM, PPE_MASK_SOLID = 0, 1
-PPE_LOSS_RESIDUAL, PPE_LOSS_SUPERVISED = 0, 1
+PPE_LOSS_RESIDUAL, PPE_LOSS_SUPERVISED, PPE_LOSS_ANORM = 0, 1, 2
 PPE_TOL_RELATIVE, PPE_TOL_ABSOLUTE = 0, 1
 PPE_PCG_AUTO, PPE_PCG_SINGLE_REDUCTION, PPE_PCG_TWO_PHASE, PPE_PCG_TWO_STEP = 0, 1, 2, 3
 PPE_DIR_NET, PPE_DIR_ZERO, PPE_DIR_JACOBI, PPE_DIR_NAN, PPE_DIR_ONES = 0, 1, 2, 3, 4
@@ -107,6 +107,7 @@ SIGNATURES = {
     "ppe_solve_opts_default": (None, [_P(ppe_solve_opts)]),
     "ppe_apply_f32": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "ppe_apply_f64": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "ppe_rhs_to_source": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "ppe_solve_plain": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_solve_opts), _vp, _vp]),
     "ppe_apply_precond": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_solve_opts), _vp]),
     "ppe_solve_hybrid": (_i32, [_vp, _vp, _i32, _vp, _vp, _P(ppe_solve_opts), _vp, _vp]),
@@ -247,6 +248,16 @@ def ppe_apply_f64(prob: Problem, x, y, stream=None):
     nb = _nb(x, prob)
     _check(lib().ppe_apply_f64(prob.handle, nb, _dev(x, torch.float64, "x"), _dev(y, torch.float64, "y"),
                                _stream(stream)))
+
+
+def ppe_rhs_to_source(prob: Problem, b, f, stream=None):
+    """f = b / (cell area) (float32 device arrays [nb, ny, nx] or [ny, nx]):
+    the source whose right-hand side is b. Enqueued, not synchronised."""
+    import torch
+    nb = _nb(b, prob)
+    _nb(f, prob)
+    _check(lib().ppe_rhs_to_source(prob.handle, nb, _dev(b, torch.float32, "b"), _dev(f, torch.float32, "f"),
+                                   _stream(stream)))
 
 
 def ppe_apply_precond(prob: Problem, r, z, opts=None, stream=None):

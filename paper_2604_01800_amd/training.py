@@ -7,9 +7,11 @@ stretched grids (tanh factors U[1, 2.5] per axis, an elliptical obstacle
 mask each) whose right-hand sides are Gaussian random fields with the length
 scale drawn log-uniformly in [0.05, 0.5] (longer scales weight the low end
 of the spectrum), multiplied by the cell areas, projected to zero mean and
-scaled to unit RMS. Training cycles through the pool in consecutive batches
-and calls ppe_net_train_step (the residual loss of Eq. 19, Adam), with a
-constant or cosine-decayed learning rate.
+scaled to unit RMS, or the Lanczos-Ritz vectors of Eqs. 14-16. Training
+cycles through the pool in consecutive batches and calls ppe_net_train_step
+(the residual loss of Eq. 19, or the supervised loss against the pool's FP64
+solutions; Adam, optionally SAM), with a constant or cosine-decayed learning
+rate.
 """
 from __future__ import annotations
 
@@ -71,18 +73,43 @@ def make_ritz_pool(n: int, count: int, seed: int = 0, grids: int = 16, m: int | 
     return gl, R
 
 
+def make_targets(probs, R, tol: float = 1e-10):
+    """FP64 solutions e_s of A e_s = R_s (the targets of the supervised loss):
+    each right-hand side turned into its source by the library
+    (ppe_rhs_to_source) and solved with multigrid PCG where the grid allows
+    it, else Jacobi-PCG. Returns a device float64 tensor shaped like R."""
+    import torch
+    n = R.shape[0]
+    E = torch.zeros(R.shape, dtype=torch.float64, device="cuda")
+    f = torch.empty_like(R[0:1])
+    for k in range(n):
+        p = probs[k]
+        ppe.ppe_rhs_to_source(p, R[k:k + 1], f)
+        mg = p.nx % 8 == 0 and p.ny % 8 == 0
+        o = ppe.ppe_solve_opts_default(tol=tol, zero_x0=1, max_iter=200000,
+                                       precond=ppe.PPE_PC_MG if mg else ppe.PPE_PC_JACOBI)
+        st, _ = ppe.ppe_solve_plain(p, f, E[k:k + 1], o)
+        if st != ppe.PPE_OK:
+            raise RuntimeError(f"target solve {k} did not converge")
+    return E
+
+
 def cosine_lr(lr: float, step: int, steps: int) -> float:
     """Cosine decay of the learning rate from lr to 0 over `steps` (Sec. 2.4)."""
     return 0.5 * lr * (1.0 + math.cos(math.pi * step / steps))
 
 
 def train(net, grids, R_dev, steps: int, batch: int, lr: float = 1e-3, log_every: int = 0, problems=None,
-          schedule: str = "constant", clip_norm: float = 0.0, sam_rho: float = 0.0, data_seed: int = 0):
+          schedule: str = "constant", clip_norm: float = 0.0, sam_rho: float = 0.0, data_seed: int = 0,
+          targets=None, loss_kind: int = ppe.PPE_LOSS_SUPERVISED):
     """Adam steps over consecutive batches of the pool (learning rate constant
     or cosine-decayed; gradients clipped to clip_norm in L2 norm when it is
     positive; sharpness-aware with radius sam_rho when it is positive);
     returns the loss history. With R_dev None the sources of step k are drawn
-    on the device by the library's generator (seed data_seed, step k)."""
+    on the device by the library's generator (seed data_seed, step k). With
+    targets (FP64 solutions of the pool's systems, make_targets) the loss is
+    loss_kind against them (supervised or A-norm), else the residual loss of
+    Eq. 19."""
     count = len(grids)
     if count % batch:
         raise ValueError("pool size must be a multiple of the batch")
@@ -94,10 +121,12 @@ def train(net, grids, R_dev, steps: int, batch: int, lr: float = 1e-3, log_every
     for k in range(steps):
         b0 = (k * batch) % count
         lr_k = cosine_lr(lr, k, steps) if schedule == "cosine" else lr
-        opts = ppe.ppe_train_opts_default(lr=lr_k, clip_norm=clip_norm, sam_rho=sam_rho, seed=data_seed, step=k)
+        opts = ppe.ppe_train_opts_default(lr=lr_k, clip_norm=clip_norm, sam_rho=sam_rho, seed=data_seed, step=k,
+                                          loss_kind=ppe.PPE_LOSS_RESIDUAL if targets is None else loss_kind)
         # R_dev None: the library draws every batch's sources on the device
         R_k = None if R_dev is None else R_dev[b0:b0 + batch]
-        loss, _ = ppe.ppe_net_train_step(net, probs[b0:b0 + batch], R_k, opts)
+        T_k = None if targets is None else targets[b0:b0 + batch]
+        loss, _ = ppe.ppe_net_train_step(net, probs[b0:b0 + batch], R_k, opts, target=T_k)
         losses.append(loss)
         if log_every and (k + 1) % log_every == 0:
             print(f"train step {k + 1}/{steps} loss {np.mean(losses[-log_every:]):.4e} "
@@ -152,6 +181,9 @@ def main(argv=None):
     ap.add_argument("--data", choices=["grf", "ritz", "generated"], default="grf",
                     help="training systems: Gaussian random fields, Lanczos-Ritz vectors (Eqs. 14-16), or "
                          "grids from the library's generator with sources drawn on the device at every step")
+    ap.add_argument("--loss", choices=["residual", "supervised", "anorm"], default="residual",
+                    help="the residual loss of Eq. 19, or the supervised or A-norm (line-search share) loss "
+                         "against FP64 solutions of the pool")
     ap.add_argument("--eval-sizes", default="64,128,256")
     ap.add_argument("--sweep", action="store_true",
                     help="also sweep Num_CG and Num_DLSM over 1..5 on held-out n x n systems (Appendix A)")
@@ -173,9 +205,15 @@ def main(argv=None):
         else:
             grids, _, Rd = make_pool(args.n, args.pool, seed=1)
         probs = [ppe.ppe_problem_create(g) for g in grids]
+        targets = None
+        if args.loss != "residual":
+            if Rd is None:
+                raise SystemExit(f"--loss {args.loss} needs a fixed pool (--data grf or ritz)")
+            targets = make_targets(probs, Rd)
         train(net, grids, Rd, steps=args.steps, batch=args.batch, lr=args.lr,
               log_every=max(1, args.steps // 20), problems=probs, schedule="cosine", clip_norm=args.clip,
-              sam_rho=args.sam)
+              sam_rho=args.sam, targets=targets,
+              loss_kind=ppe.PPE_LOSS_ANORM if args.loss == "anorm" else ppe.PPE_LOSS_SUPERVISED)
     if args.out:
         ppe.ppe_net_save(net, args.out)
     for n in (int(v) for v in args.eval_sizes.split(",") if v):

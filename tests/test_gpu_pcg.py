@@ -330,3 +330,30 @@ def test_degenerate_shapes_converge(T, orc, variant, nx, ny, beta):
     assert np.linalg.norm(b - orc.apply(g, x[0])) / np.linalg.norm(b) <= 1e-9 * 1.001
     xs = direct.separable_solve(g, b)
     assert np.linalg.norm(x[0] - xs) / np.linalg.norm(xs) <= 1e-6
+
+
+def test_rhs_to_source_round_trip(T, orc):
+    """ppe_rhs_to_source gives the source whose right-hand side (cell area x
+    f, Eq. 10) is b: the oracle's right-hand side of it returns b to FP32
+    rounding, and a solve of it solves A x = b."""
+    ppe = _ppe()
+    g = inputs.make_grid(70, 45, 2.0, 1.4)
+    prob = ppe.ppe_problem_create(g)
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal((2, 45, 70))
+    b -= b.mean(axis=(1, 2), keepdims=True)
+    b32 = b.astype(np.float32)
+    f = T.empty((2, 45, 70), dtype=T.float32, device="cuda")
+    ppe.ppe_rhs_to_source(prob, _dev(T, b32, T.float32), f)
+    T.cuda.synchronize()
+    fh = f.cpu().numpy()
+    area = np.outer(np.asarray(g.hy), np.asarray(g.hx))
+    np.testing.assert_array_equal(fh, (b32.astype(np.float64) / area).astype(np.float32))
+    for s in range(2):
+        bo, _ = orc.rhs(g, fh[s])
+        assert np.abs(bo - b32[s]).max() <= 1e-6 * np.abs(b32[s]).max()
+    st, stats, x = _solve(T, prob, fh, tol=1e-9)
+    assert st == ppe.PPE_OK
+    for s in range(2):
+        bo, _ = orc.rhs(g, fh[s])
+        assert np.linalg.norm(bo - orc.apply(g, x[s])) <= 1.001e-9 * np.linalg.norm(bo)

@@ -268,11 +268,13 @@ def test_training_on_generated_data(ppe):
     assert np.mean(losses[-20:]) < 0.8 * np.mean(losses[:5]), (np.mean(losses[:5]), np.mean(losses[-20:]))
 
 
-def test_supervised_loss_gradients_match_oracle(ppe):
-    """loss_kind = SUPERVISED with FP64 targets (the min-norm solutions of
-    A e = R): the loss and every parameter tensor's gradient against the
-    oracle's autograd of oracle.net.supervised_loss, to the same bars as the
-    residual loss; a few Adam steps lower the loss; and the argument checks."""
+@pytest.mark.parametrize("kind", ["supervised", "anorm"])
+def test_supervised_loss_gradients_match_oracle(ppe, kind):
+    """loss_kind = SUPERVISED or ANORM with FP64 targets (the min-norm
+    solutions of A e = R): the loss and every parameter tensor's gradient
+    against the oracle's autograd of oracle.net.supervised_loss or
+    oracle.net.anorm_loss, to the same bars as the residual loss; a few Adam
+    steps lower the loss; and the argument checks."""
     cfg = small_cfg()
     p = onet.round_bf16_params(cfg, onet.init_params(cfg, np.random.default_rng(3), phi_scale=1.0))
     net = ppe.Net(gpu_cfg(ppe, cfg), seed=0)
@@ -282,14 +284,21 @@ def test_supervised_loss_gradients_match_oracle(ppe):
     probs = [ppe.ppe_problem_create(g) for g in grids]
     Rd = torch.from_numpy(R.astype(np.float32)).cuda()
     Td = torch.from_numpy(T).cuda()
-    o = ppe.ppe_train_opts_default(lr=0.0, loss_kind=ppe.PPE_LOSS_SUPERVISED)
+    lk = ppe.PPE_LOSS_SUPERVISED if kind == "supervised" else ppe.PPE_LOSS_ANORM
+    o = ppe.ppe_train_opts_default(lr=0.0, loss_kind=lk)
     loss, grad = ppe.ppe_net_train_step(net, probs, Rd, o, want_grad=True, target=Td)
     q = {k: v.clone().requires_grad_(True) for k, v in p.items()}
-    lo = onet.supervised_loss(q, cfg, grids, R, T, masks=[g.mask for g in grids])
+    masks = [g.mask for g in grids]
+    if kind == "supervised":
+        lo = onet.supervised_loss(q, cfg, grids, R, T, masks=masks)
+    else:
+        mats = {id(g): torch.from_numpy(direct.kron_matrix(g)) for g in grids}
+        app = lambda g, y: (mats[id(g)] @ y.reshape(-1)).reshape(y.shape)
+        lo = onet.anorm_loss(q, cfg, grids, R, T, masks=masks, apply=app)
     lo.backward()
     go = {k: (v.grad.numpy() if v.grad is not None else np.zeros(tuple(v.shape))) for k, v in q.items()}
     lo = float(lo.detach())
-    print(f"supervised loss GPU {loss:.6f} oracle {lo:.6f}")
+    print(f"{kind} loss GPU {loss:.6f} oracle {lo:.6f}")
     assert abs(loss - lo) <= 2e-2 * lo
     gg = onet.unflatten(cfg, grad)
     gscale = np.linalg.norm(grad) / np.sqrt(grad.size)
@@ -318,9 +327,9 @@ def test_supervised_loss_gradients_match_oracle(ppe):
     a, b = a[keep], b[keep]
     assert float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b))) >= 0.995
     losses = [ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(
-        lr=1e-3, loss_kind=ppe.PPE_LOSS_SUPERVISED), target=Td)[0] for _ in range(20)]
+        lr=1e-3, loss_kind=lk), target=Td)[0] for _ in range(20)]
     assert losses[-1] < 0.9 * losses[0], losses
-    with pytest.raises(ppe.PPEError):  # the supervised loss needs targets
+    with pytest.raises(ppe.PPEError):  # the loss needs targets
         ppe.ppe_net_train_step(net, probs, Rd, o)
     with pytest.raises(ppe.PPEError):  # targets only go with the supervised loss
         ppe.ppe_net_train_step(net, probs, Rd, ppe.ppe_train_opts_default(lr=0.0), target=Td)
