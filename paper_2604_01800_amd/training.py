@@ -181,6 +181,9 @@ def main(argv=None):
     ap.add_argument("--data", choices=["grf", "ritz", "generated"], default="grf",
                     help="training systems: Gaussian random fields, Lanczos-Ritz vectors (Eqs. 14-16), or "
                          "grids from the library's generator with sources drawn on the device at every step")
+    ap.add_argument("--ritz-m", type=int, default=0,
+                    help="Lanczos steps per grid of the Ritz pool (0: the paper's ratio, 0.14 N)")
+    ap.add_argument("--ritz-grids", type=int, default=16, help="grids of the Ritz pool")
     ap.add_argument("--loss", choices=["residual", "supervised", "anorm"], default="residual",
                     help="the residual loss of Eq. 19, or the supervised or A-norm (line-search share) loss "
                          "against FP64 solutions of the pool")
@@ -199,7 +202,7 @@ def main(argv=None):
         ppe.ppe_net_load(net, args.load)
     else:
         if args.data == "ritz":
-            grids, Rd = make_ritz_pool(args.n, args.pool, seed=1)
+            grids, Rd = make_ritz_pool(args.n, args.pool, seed=1, grids=args.ritz_grids, m=args.ritz_m or None)
         elif args.data == "generated":
             grids, Rd = generated_grids(args.n, args.pool, seed=1), None
         else:
