@@ -8,10 +8,12 @@ choices below are this implementation's reading, stated once here):
 
 * Mesh-Conv layer (Eqs. 17-18): per pixel, the distance vector Delta holds the
   distances to the four orthogonal neighbours (left, right, down, up) at the
-  layer's resolution; a small network Phi (4 -> hidden, tanh -> C_in) maps it
-  to one value per input channel; the local weight is eta = exp(-Phi^2); the
-  layer computes conv3x3(eta * X) + bias (zero padding). With use_eta = 0 the
-  layer is a standard convolution (the paper's "-Conv" variant).
+  layer's resolution; a small network Phi (4 -> hidden, tanh -> K) maps it to
+  the local weight eta = exp(-Phi^2); the layer computes conv3x3(eta * X) +
+  bias (zero padding). use_eta = 2: K = 1, one weight per node multiplying
+  the whole feature vector, as Eqs. 17-18 are written; use_eta = 1: K = C_in,
+  one weight per input channel (a generalisation); use_eta = 0: a standard
+  convolution (the paper's "-Conv" variant).
 * Multi-level distance maps: the cell-centre coordinates are average-pooled
   level by level (pairs of centres), distances are taken between pooled
   centres, the exterior distance at a boundary pixel equals its interior
@@ -32,8 +34,8 @@ choices below are this implementation's reading, stated once here):
 The flat parameter vector lists, in order: for each encoder level l = 0..L-1
 the layers (a, b); for each decoder level l = L-2..0 the 1x1 up-conv then the
 layers (c, d); the head; the trunk layers; gamma. A Mesh-Conv layer holds
-W [Cout, Cin, 3, 3], b [Cout], phi.W1 [H, 4], phi.b1 [H], phi.W2 [Cin, H],
-phi.b2 [Cin]. A 1x1 conv holds W [Cout, Cin], b [Cout]. A trunk layer holds
+W [Cout, Cin, 3, 3], b [Cout], phi.W1 [H, 4], phi.b1 [H], phi.W2 [K, H],
+phi.b2 [K] (K = 1 with use_eta = 2, else Cin). A 1x1 conv holds W [Cout, Cin], b [Cout]. A trunk layer holds
 W [out, in], b [out].
 """
 from __future__ import annotations
@@ -62,24 +64,25 @@ class NetConfig:
         return self.base_channels << l
 
 
-def _mconv_spec(name, cin, cout, H):
+def _mconv_spec(name, cin, cout, H, per_node=False):
+    k = 1 if per_node else cin
     return [(f"{name}.W", (cout, cin, 3, 3)), (f"{name}.b", (cout,)),
             (f"{name}.phi.W1", (H, 4)), (f"{name}.phi.b1", (H,)),
-            (f"{name}.phi.W2", (cin, H)), (f"{name}.phi.b2", (cin,))]
+            (f"{name}.phi.W2", (k, H)), (f"{name}.phi.b2", (k,))]
 
 
 def param_spec(cfg: NetConfig):
     """Ordered (name, shape) list of the flat parameter vector."""
-    L, H, sp = cfg.levels, cfg.phi_hidden, 2 * cfg.use_spacing
+    L, H, sp, pn = cfg.levels, cfg.phi_hidden, 2 * cfg.use_spacing, cfg.use_eta == 2
     spec = []
     for l in range(L):
         cin = (cfg.in_channels if l == 0 else cfg.ch(l - 1)) + sp
-        spec += _mconv_spec(f"enc{l}.a", cin, cfg.ch(l), H)
-        spec += _mconv_spec(f"enc{l}.b", cfg.ch(l), cfg.ch(l), H)
+        spec += _mconv_spec(f"enc{l}.a", cin, cfg.ch(l), H, pn)
+        spec += _mconv_spec(f"enc{l}.b", cfg.ch(l), cfg.ch(l), H, pn)
     for l in range(L - 2, -1, -1):
         spec += [(f"up{l}.W", (cfg.ch(l), cfg.ch(l + 1))), (f"up{l}.b", (cfg.ch(l),))]
-        spec += _mconv_spec(f"dec{l}.c", 2 * cfg.ch(l) + sp, cfg.ch(l), H)
-        spec += _mconv_spec(f"dec{l}.d", cfg.ch(l), cfg.ch(l), H)
+        spec += _mconv_spec(f"dec{l}.c", 2 * cfg.ch(l) + sp, cfg.ch(l), H, pn)
+        spec += _mconv_spec(f"dec{l}.d", cfg.ch(l), cfg.ch(l), H, pn)
     spec += [("head.W", (cfg.basis, cfg.ch(0))), ("head.b", (cfg.basis,))]
     w, nin = cfg.trunk_width, 2
     for k in range(cfg.trunk_hidden):
@@ -172,7 +175,8 @@ def trunk_input(grid):
 # Layers.
 
 def eta_map(p, name, delta, use_eta):
-    """Local weight of Eq. 17 per input channel: [Cin, H, W]."""
+    """Local weight of Eq. 17: [K, H, W] (K = 1 per node, or one per input
+    channel), broadcast over the channels when K = 1."""
     cin = p[f"{name}.phi.W2"].shape[0]
     if not use_eta:
         return torch.ones((cin,) + tuple(delta.shape[1:]), dtype=torch.float64)

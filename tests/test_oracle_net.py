@@ -24,18 +24,22 @@ def test_param_count_default():
     assert 1.7e6 < n < 2.1e6, n
 
 
-def test_mconv_matches_explicit_loops():
+@pytest.mark.parametrize("per_node", [False, True])
+def test_mconv_matches_explicit_loops(per_node):
+    """Eqs. 17-18 written out: one local weight per node (use_eta = 2) or one
+    per input channel (use_eta = 1)."""
     rng = np.random.default_rng(0)
     cin, cout, H, W, Hd = 3, 2, 5, 6, 3
+    k = 1 if per_node else cin
     p = {"m.W": torch.from_numpy(rng.standard_normal((cout, cin, 3, 3))),
          "m.b": torch.from_numpy(rng.standard_normal(cout)),
          "m.phi.W1": torch.from_numpy(rng.standard_normal((Hd, 4))),
          "m.phi.b1": torch.from_numpy(rng.standard_normal(Hd)),
-         "m.phi.W2": torch.from_numpy(rng.standard_normal((cin, Hd))),
-         "m.phi.b2": torch.from_numpy(rng.standard_normal(cin))}
+         "m.phi.W2": torch.from_numpy(rng.standard_normal((k, Hd))),
+         "m.phi.b2": torch.from_numpy(rng.standard_normal(k))}
     X = rng.standard_normal((1, cin, H, W))
     delta = rng.uniform(0.2, 2.0, size=(4, H, W))
-    Y = onet.mconv(p, "m", torch.from_numpy(X), torch.from_numpy(delta), 1).numpy()
+    Y = onet.mconv(p, "m", torch.from_numpy(X), torch.from_numpy(delta), 2 if per_node else 1).numpy()
     W1, b1, W2, b2 = (p[k].numpy() for k in ("m.phi.W1", "m.phi.b1", "m.phi.W2", "m.phi.b2"))
     Wc, bc = p["m.W"].numpy(), p["m.b"].numpy()
     ref = np.zeros((1, cout, H, W))
@@ -50,7 +54,8 @@ def test_mconv_matches_explicit_loops():
                             continue
                         h = [math.tanh(sum(W1[a, k] * delta[k, yy, xx] for k in range(4)) + b1[a]) for a in range(Hd)]
                         for ci in range(cin):
-                            phi = sum(W2[ci, a] * h[a] for a in range(Hd)) + b2[ci]
+                            kk = 0 if per_node else ci
+                            phi = sum(W2[kk, a] * h[a] for a in range(Hd)) + b2[kk]
                             acc += Wc[co, ci, ky, kx] * math.exp(-phi * phi) * X[0, ci, yy, xx]
                 ref[0, co, y, x] = acc
     np.testing.assert_allclose(Y, ref, rtol=1e-12, atol=1e-12)
@@ -351,3 +356,66 @@ def test_fd_gradients_of_anorm_loss(orc):
             assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * abs(float(loss.detach()))), (name, idx, fd, an)
             checked += 1
     assert checked >= 12
+
+
+def test_per_node_weight_is_the_per_channel_form_with_equal_rows():
+    """use_eta = 2 (one local weight per node) gives the forward of use_eta = 1
+    whose Phi output rows are all equal to the single row, and its Phi output
+    gradient is the sum of the per-channel rows' gradients."""
+    cfg2 = small_cfg(use_eta=2)
+    cfg1 = small_cfg(use_eta=1)
+    rng = np.random.default_rng(21)
+    p2 = onet.init_params(cfg2, rng, phi_scale=1.0)
+    p1 = {}
+    for name, shape in onet.param_spec(cfg1):
+        t = p2[name]
+        p1[name] = t.expand(shape).clone() if (".phi.W2" in name or ".phi.b2" in name) else t.clone()
+    g = inputs.make_grid(16, 12, 1.7, 1.2)
+    g.mask = np.zeros((12, 16), np.uint8)
+    R = inputs.grf(g, 3, ell=0.2, J=64)[None]
+    for t in list(p1.values()) + list(p2.values()):
+        t.requires_grad_(True)
+    y1 = onet.forward(p1, cfg1, g, R, g.mask)
+    y2 = onet.forward(p2, cfg2, g, R, g.mask)
+    np.testing.assert_allclose(y1.detach().numpy(), y2.detach().numpy(), rtol=1e-13, atol=1e-13)
+    w = torch.from_numpy(np.random.default_rng(5).standard_normal(y1.shape))
+    (y1 * w).sum().backward()
+    (y2 * w).sum().backward()
+    for name in ("enc0.a.phi.W2", "dec1.c.phi.b2", "enc2.b.phi.W2"):
+        np.testing.assert_allclose(p1[name].grad.sum(0).numpy(), p2[name].grad[0].numpy(), rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(p1["enc1.a.phi.W1"].grad.numpy(), p2["enc1.a.phi.W1"].grad.numpy(), rtol=1e-11,
+                               atol=1e-13)
+
+
+def test_fd_gradients_per_node_weights():
+    cfg = small_cfg(use_eta=2)
+    n = 16
+    rng = np.random.default_rng(17)
+    grids = [inputs.make_grid(n, n, b) for b in (1.4, 1.9)]
+    R = np.stack([inputs.grf(gr, 30 + i, ell=0.2, J=64) for i, gr in enumerate(grids)])
+    R -= R.mean(axis=(1, 2), keepdims=True)
+    p = onet.init_params(cfg, rng, phi_scale=1.0)
+    for t in p.values():
+        t.requires_grad_(True)
+    applies = {id(gr): _apply_torch(gr) for gr in grids}
+    app = lambda grid, y: applies[id(grid)](grid, y)
+    loss = onet.residual_loss(p, cfg, grids, R, apply=app)
+    loss.backward()
+    checked = 0
+    for name in ["enc0.a.phi.W2", "enc1.b.phi.b2", "dec0.c.phi.W1", "dec1.d.phi.W2", "enc0.b.W"]:
+        t = p[name]
+        flat = t.detach().reshape(-1)
+        for idx in rng.choice(flat.numel(), size=min(3, flat.numel()), replace=False):
+            v0 = float(flat[idx])
+            h = 1e-6 * max(1.0, abs(v0))
+            vals = []
+            for sgn in (+1, -1):
+                with torch.no_grad():
+                    q = {k: v.detach().clone() for k, v in p.items()}
+                    q[name].reshape(-1)[idx] = v0 + sgn * h
+                    vals.append(float(onet.residual_loss(q, cfg, grids, R, apply=app)))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = float(t.grad.reshape(-1)[idx])
+            assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * abs(float(loss.detach()))), (name, idx, fd, an)
+            checked += 1
+    assert checked >= 10
