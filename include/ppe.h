@@ -167,7 +167,7 @@ typedef struct {
 /* Network configuration (Sec. 2.4). Defaults (ppe_net_config_default): 4 levels,
  * 32 base channels doubling per level, inputs (scaled residual, mask), 128-term
  * DeepONet basis, trunk 2 -> 128 x 4 -> 128 (tanh), per-layer weight network
- * 4 -> 16 (tanh) -> C_in for the Mesh-Conv local weight (Eq. 17).
+ * 4 -> 16 (tanh) -> 1 for the Mesh-Conv local weight of each node (Eq. 17).
  * Limits: levels in [2, 6]; base_channels a multiple of 8 with
  * base_channels x 2^(levels-1) <= 1024 (the paper's U-Net, 5 levels from 40
  * channels, fits); basis and trunk_width multiples of 8 in [8, 128];
@@ -178,7 +178,10 @@ typedef struct {
  * PPE_ERR_INVALID_ARG. */
 typedef struct {
   int32_t levels, base_channels, basis, trunk_width, trunk_hidden, phi_hidden;
-  int32_t use_eta;         /* 1 = Mesh-Conv (Eqs. 17-18), 0 = standard conv ("-Conv" ablation) */
+  int32_t use_eta;         /* Mesh-Conv local weight (Eqs. 17-18): 2 = one weight per node multiplying the
+                              whole feature vector, as the equations are written (default); 1 = one
+                              weight per input channel (Phi with C_in outputs); 0 = standard conv
+                              (the "-Conv" ablation) */
   int32_t use_spacing;     /* 1 = concatenate the normalised widths (hx, hy) at each level */
 } ppe_net_config;
 

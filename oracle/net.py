@@ -57,7 +57,7 @@ class NetConfig:
     trunk_width: int = 128
     trunk_hidden: int = 4
     phi_hidden: int = 16
-    use_eta: int = 1
+    use_eta: int = 2
     use_spacing: int = 1
 
     def ch(self, l):

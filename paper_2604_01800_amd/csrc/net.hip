@@ -28,7 +28,7 @@ static void build_layout(ppe_net* n) {
   const ppe_net_config& c = n->cfg;
   const int L = c.levels, H = c.phi_hidden, sp = 2 * c.use_spacing;
   auto ch = [&](int l) { return c.base_channels << l; };
-  int64_t o = 0, op = 0;
+  int64_t o = 0, op = 0, oe = 0;
   auto mconv = [&](int level, int cin, int cout) {
     MConvL m;
     m.level = level;
@@ -43,10 +43,13 @@ static void build_layout(ppe_net* n) {
     o += (int64_t)H * 4;
     m.ob1 = o;
     o += H;
+    m.phik = c.use_eta == 2 ? 1 : cin;
+    m.oexp = oe;
+    if (c.use_eta == 2) oe += (int64_t)cin * H + cin;
     m.oW2 = o;
-    o += (int64_t)cin * H;
+    o += (int64_t)m.phik * H;
     m.ob2 = o;
-    o += cin;
+    o += m.phik;
     m.kp = conv_packed_k(9, m.cin8);
     m.opack = op;
     op += (int64_t)cout * m.kp;
@@ -96,6 +99,7 @@ static void build_layout(ppe_net* n) {
   o += 1;
   n->np = o;
   n->npack = op;
+  n->nexp = oe;
 }
 
 // splitmix64 + Box-Muller: the library's own seeded initialisation.
@@ -121,7 +125,7 @@ static void init_params(ppe_net* n, uint64_t seed, std::vector<float>& w) {
   auto mconv = [&](const MConvL& m) {
     fill(m.oW, (int64_t)m.cout * m.cin * 9, std::sqrt(2.0 / (9.0 * m.cin)));
     fill(m.oW1, (int64_t)H * 4, 0.5);
-    fill(m.oW2, (int64_t)m.cin * H, 0.1 / std::sqrt((double)H));
+    fill(m.oW2, (int64_t)m.phik * H, 0.1 / std::sqrt((double)H));
   };
   for (auto& m : n->enc_a) mconv(m);
   for (auto& m : n->enc_b) mconv(m);
@@ -171,6 +175,7 @@ static ppe_status check_config(const ppe_net_config& c) {
     return set_error(PPE_ERR_INVALID_ARG, "basis and trunk_width must be multiples of 8 in [8, 128]");
   if (c.trunk_hidden < 1 || c.trunk_hidden > 8) return set_error(PPE_ERR_INVALID_ARG, "trunk_hidden in [1, 8]");
   if (c.phi_hidden < 1 || c.phi_hidden > 32) return set_error(PPE_ERR_INVALID_ARG, "phi_hidden in [1, 32]");
+  if (c.use_eta < 0 || c.use_eta > 2) return set_error(PPE_ERR_INVALID_ARG, "use_eta in {0, 1, 2}");
   return PPE_OK;
 }
 
@@ -275,7 +280,8 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
     int64_t eo = 0;
     auto eta_slot = [&](const MConvL& m) {
       const int64_t o = eo;
-      eo += (int64_t)c->H[m.level] * c->W[m.level] * m.cin8;
+      eo += (int64_t)c->H[m.level] * c->W[m.level] * (cfg.use_eta == 2 ? 1 : m.cin8);
+      eo = (eo + 63) / 64 * 64;
       return o;
     };
     for (int l = 0; l < L; ++l) {
@@ -346,8 +352,10 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
       const int l = m.level;
       const float* b = c->d_lv + c->lv_off[l];
       const int W = c->W[l], H = c->H[l];
-      launch_eta(H, W, m.cin, m.cin8, cfg.phi_hidden, b, b + W, b + 3 * W, b + 3 * W + H, n->d_w + m.oW1,
-                 n->d_w + m.ob1, n->d_w + m.oW2, n->d_w + m.ob2, c->d_eta + off, s);
+      // one weight per pixel: the same kernel with one output channel
+      const int k = m.phik, k8 = cfg.use_eta == 2 ? 1 : m.cin8;
+      launch_eta(H, W, k, k8, cfg.phi_hidden, b, b + W, b + 3 * W, b + 3 * W + H, n->d_w + m.oW1, n->d_w + m.ob1,
+                 n->d_w + m.oW2, n->d_w + m.ob2, c->d_eta + off, s);
     };
     for (int l = 0; l < L; ++l) {
       eta(n->enc_a[l], c->eta_a[l]);
@@ -386,7 +394,8 @@ static ConvGeo geo(const NetCache* c, int l, int cin8, int cout, int y_pitch, in
   g.y_off = y_off;
   g.x_bstride = (int64_t)g.H * g.W * cin8;
   g.y_bstride = (int64_t)g.H * g.W * y_pitch;
-  g.e_bstride = nb_eta_shared ? 0 : (int64_t)g.H * g.W * cin8;
+  g.eta_node = c->use_eta == 2;
+  g.e_bstride = nb_eta_shared ? 0 : (int64_t)g.H * g.W * (g.eta_node ? 1 : cin8);
   g.act = 1;
   return g;
 }
@@ -466,7 +475,7 @@ void ppe_net_config_default(ppe_net_config* c) {
   c->trunk_width = 128;
   c->trunk_hidden = 4;
   c->phi_hidden = 16;
-  c->use_eta = 1;
+  c->use_eta = 2;
   c->use_spacing = 1;
 }
 

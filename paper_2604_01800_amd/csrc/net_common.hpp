@@ -52,6 +52,7 @@ struct ConvGeo {
   int64_t y_bstride; // elements between samples of the output
   int64_t e_bstride; // elements between samples of eta (0 = shared by the batch)
   int act;          // epilogue activation: 0 none, 1 ReLU, 2 tanh
+  int eta_node;     // 1: eta holds one weight per pixel ([H][W]), else one per input channel (pitch cin8)
 };
 
 // Number of 32-wide MFMA K-steps of an input-channel chunk of ck channels

@@ -43,6 +43,19 @@ __device__ __forceinline__ uint4 mul_bf16x8(uint4 v, uint4 e) {
   return make_uint4(o[0], o[1], o[2], o[3]);
 }
 
+// Eight BF16 values times one BF16 weight (one local weight per node).
+__device__ __forceinline__ uint4 mul_bf16x8_s(uint4 v, uint32_t e16) {
+  const float e = bf2f((bf16_t)(e16 & 0xffff));
+  uint32_t a[4] = {v.x, v.y, v.z, v.w}, o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float lo = bf2f((bf16_t)(a[q] & 0xffff)) * e;
+    const float hi = bf2f((bf16_t)(a[q] >> 16)) * e;
+    o[q] = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+  }
+  return make_uint4(o[0], o[1], o[2], o[3]);
+}
+
 template <int TN, int TAPS>
 struct ConvShape {
   static constexpr int HALO = TAPS == 9 ? 1 : 0;
@@ -91,7 +104,15 @@ __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS>& st, const ConvGe
     const bool in = cg_ok && pix < S::NPIX && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W;
     const uint32_t off = in ? (uint32_t)(gy * g.W + gx) * (uint32_t)(g.cin8 * 2) + cofs : 0x80000000u;
     st.x[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)off, 0, 0));
-    if (has_eta) st.e[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(er, (int)off, 0, 0));
+    if (has_eta) {
+      if (g.eta_node) {
+        // one weight per pixel: two bytes at the pixel's index
+        const uint32_t eo = in ? (uint32_t)(gy * g.W + gx) * 2u : 0x80000000u;
+        st.e[i].x = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(er, (int)eo, 0, 0);
+      } else {
+        st.e[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(er, (int)off, 0, 0));
+      }
+    }
   }
   const int wq = conv_chunk_steps(TAPS, ck8 * 8) * 4;  // 8-value groups per weight row of this chunk
 #pragma unroll
@@ -106,8 +127,8 @@ __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS>& st, const ConvGe
 
 // Writes one item's staged registers to LDS (inputs times eta).
 template <int TN, int TAPS>
-__device__ __forceinline__ void conv_commit(const ConvStage<TN, TAPS>& st, bool has_eta, int ck8, bf16_t* s_x,
-                                            bf16_t* s_w) {
+__device__ __forceinline__ void conv_commit(const ConvStage<TN, TAPS>& st, bool has_eta, bool eta_node, int ck8,
+                                            bf16_t* s_x, bf16_t* s_w) {
   using S = ConvShape<TN, TAPS>;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
@@ -116,7 +137,9 @@ __device__ __forceinline__ void conv_commit(const ConvStage<TN, TAPS>& st, bool 
 #pragma unroll
     for (int i = 0; i < S::NU; ++i) {
       const int pix = tid / S::G8 + S::PPR * i;
-      if (pix < S::NPIX) *(uint4*)(s_x + pix * S::CKP + c8 * 8) = has_eta ? mul_bf16x8(st.x[i], st.e[i]) : st.x[i];
+      if (pix < S::NPIX)
+        *(uint4*)(s_x + pix * S::CKP + c8 * 8) =
+            !has_eta ? st.x[i] : eta_node ? mul_bf16x8_s(st.x[i], st.e[i].x) : mul_bf16x8(st.x[i], st.e[i]);
     }
   }
   const int wq = conv_chunk_steps(TAPS, ck8 * 8) * 4;
@@ -196,8 +219,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int in_bytes = (int)((int64_t)g.H * g.W * g.cin8 * 2);  // one sample of the input (and of eta)
   const __amdgpu_buffer_rsrc_t xr =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(x), (short)0, in_bytes, 0x00020000);
+  const int eta_bytes = g.eta_node ? (int)((int64_t)g.H * g.W * 2) : in_bytes;
   const __amdgpu_buffer_rsrc_t er =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(eta ? eta : x), (short)0, in_bytes, 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(eta ? eta : x), (short)0, eta_bytes, 0x00020000);
   // input-channel chunks of this workgroup: all of them, or its share when
   // the K loop is split over ksplit workgroups
   const int nch_all = (g.cin8 + S::CK - 1) / S::CK;
@@ -225,7 +249,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int ck8 = min(S::CK, g.cin8 - c0) / 8;
     issue(it);        // in flight while the other waves finish the previous item
     __syncthreads();  // the previous item's MFMA loop is done with LDS
-    conv_commit<TN, TAPS>(stg, eta != nullptr, ck8, s_x, s_w);
+    conv_commit<TN, TAPS>(stg, eta != nullptr, g.eta_node != 0, ck8, s_x, s_w);
     __syncthreads();
 
     if (ck8 == S::G8)

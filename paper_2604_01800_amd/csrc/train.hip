@@ -62,6 +62,12 @@ struct TrainState {
   float* w_save = nullptr;  // [np] weights kept during a sharpness-aware step
   double* sup = nullptr;    // supervised loss: [nb][5][kSupParts] partial sums, then [nb] sample losses
   int sup_nb = 0;
+  // One local weight per node: each Mesh-Conv layer's Phi output row and bias
+  // replicated to one row per input channel (the per-channel form with equal
+  // rows), so the per-channel kernels run unchanged; the per-channel gradient
+  // rows of a layer are reduced into phig and summed back into the single row.
+  float* phix = nullptr;
+  float* phig = nullptr;
 };
 
 constexpr int kSupParts = 64;
@@ -78,6 +84,8 @@ void net_train_free(ppe_net* n) {
   dev_free(t->d_R);
   dev_free(t->gpart);
   dev_free(t->w_save);
+  dev_free(t->phix);
+  dev_free(t->phig);
   dev_free(t->sup);
   dev_free(t->act);
   dev_free(t->grad);
@@ -199,6 +207,15 @@ static ppe_status train_state(ppe_net* n, int nb, int nx, int ny) {
   t->dpart = (double*)dev_alloc(((size_t)kRedBlocks * (nb + 1) + 8) * sizeof(double));
   t->d_coefs = (Coef*)dev_alloc(nb * sizeof(Coef));
   t->d_masks = (const uint8_t**)dev_alloc(nb * sizeof(void*));
+  if (cfg.use_eta == 2) {
+    int64_t gmax = 0;
+    for (const auto* v : {&n->enc_a, &n->enc_b, &n->dec_c, &n->dec_d})
+      for (const MConvL& m : *v)
+        if (m.cin) gmax = std::max<int64_t>(gmax, eta_bwd_len(m.cin, cfg.phi_hidden));
+    t->phix = (float*)dev_alloc(std::max<int64_t>(n->nexp, 1) * sizeof(float));
+    t->phig = (float*)dev_alloc(std::max<int64_t>(gmax, 1) * sizeof(float));
+    if (!t->phix || !t->phig) return set_error(PPE_ERR_HIP, "allocation of the per-node weight expansion failed");
+  }
   if (!t->act || !t->grad || (cfg.use_eta && !t->eta) || !t->packs || !t->f32 || !t->part || !t->dpart ||
       !t->d_coefs || !t->d_masks)
     return set_error(PPE_ERR_HIP, "allocation of the training workspace failed");
@@ -323,7 +340,25 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
   double* lpart = t->dpart + (size_t)kRedBlocks * nb;
   // One forward and backward pass at the current weights: the loss sum in
   // lpart[kRedBlocks] and the gradient in dG.
+  const bool per_node = cfg.use_eta == 2;
+  auto each_mconv = [&](auto&& fn) {
+    for (int l = 0; l < L; ++l) {
+      fn(n->enc_a[l]);
+      fn(n->enc_b[l]);
+      if (l < L - 1) {
+        fn(n->dec_c[l]);
+        fn(n->dec_d[l]);
+      }
+    }
+  };
+  // Phi's output row and bias of a layer as the per-channel kernels read them
+  auto phi_w2 = [&](const MConvL& m) -> const float* { return per_node ? t->phix + m.oexp : W + m.oW2; };
+  auto phi_b2 = [&](const MConvL& m) -> const float* {
+    return per_node ? t->phix + m.oexp + (int64_t)m.cin * HID : W + m.ob2;
+  };
   auto fwd_bwd = [&]() -> ppe_status {
+    if (per_node)
+      each_mconv([&](const MConvL& m) { launch_phi_expand(W + m.oW2, W + m.ob2, m.cin, HID, t->phix + m.oexp, s); });
     // packed weights of this step (transposed operators and the head / trunk forward)
     for (int l = 0; l < L; ++l) {
       const MConvL& a = n->enc_a[l];
@@ -361,7 +396,7 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
     auto eta_fwd = [&](const MConvL& m, int64_t off) {
       const int l = m.level;
       launch_eta_multi(t->H[l], t->W[l], m.cin, m.cin8, HID, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
-                       W + m.ob1, W + m.oW2, W + m.ob2, E + off, hw(l) * m.cin8, nb, s);
+                       W + m.ob1, phi_w2(m), phi_b2(m), E + off, hw(l) * m.cin8, nb, s);
     };
     if (cfg.use_eta)
       for (int l = 0; l < L; ++l) {
@@ -385,6 +420,7 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
       g.y_bstride = hw(l) * y_pitch;
       g.e_bstride = hw(l) * cin8;
       g.act = act;
+      g.eta_node = 0;  // training keeps per-channel maps (per-node weights are expanded)
       return g;
     };
 
@@ -492,8 +528,14 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
       // partial rows: up to 2048, as many as the partials buffer holds
       const int np = (int)std::min<int64_t>(2048, cap / len);
       launch_eta_bwd(t->H[l], t->W[l], m.cin, m.cin8, HID, nb, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
-                     W + m.ob1, W + m.oW2, W + m.ob2, x, E + eoff, hw(l) * m.cin8, dxb, part, np, s);
-      launch_reduce_rows(part, np, len, 1.f, dG + m.oW1, s);
+                     W + m.ob1, phi_w2(m), phi_b2(m), x, E + eoff, hw(l) * m.cin8, dxb, part, np, s);
+      if (per_node) {
+        // the per-channel rows' gradient, summed back into the layer's single row
+        launch_reduce_rows(part, np, len, 1.f, t->phig, s);
+        launch_phi_collapse(t->phig, m.cin, HID, dG + m.oW1, s);
+      } else {
+        launch_reduce_rows(part, np, len, 1.f, dG + m.oW1, s);
+      }
     };
     // DeepONet contraction, head and trunk
     launch_don_bwd(N * nb, P, Ab + t->o_B, Ab + t->o_T, W + n->o_gamma, gAy, dscale, G + t->g_B, G + t->g_T, part,

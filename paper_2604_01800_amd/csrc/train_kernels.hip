@@ -1025,6 +1025,44 @@ void launch_anorm_loss(int64_t N, int nb, const float* y, const float* Ay, const
   k_anorm_grad<<<dim3(nparts, nb), 256, 0, s>>>(N, nb, Ay, R, part, nparts, dy, lsamp);
 }
 
+// One local weight per node, run through the per-channel kernels: Phi's
+// output row w2 [hid] and bias b2 replicated to cin rows (expansion), and the
+// per-channel gradient row [W1 (4 hid) | b1 (hid) | W2 (cin x hid) | b2 (cin)]
+// reduced to the per-node layout [W1 | b1 | W2 (hid) | b2 (1)] (collapse),
+// each channel sum in channel order.
+__global__ void k_phi_expand(const float* __restrict__ w2, const float* __restrict__ b2, int cin, int hid,
+                             float* __restrict__ out) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u < cin * hid) out[u] = w2[u % hid];
+  else if (u < cin * hid + cin) out[u] = b2[0];
+}
+
+__global__ void k_phi_collapse(const float* __restrict__ g, int cin, int hid, float* __restrict__ out) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u < 5 * hid) {
+    out[u] = g[u];
+  } else if (u < 6 * hid) {
+    const int a = u - 5 * hid;
+    float acc = 0.f;
+    for (int c = 0; c < cin; ++c) acc += g[5 * hid + c * hid + a];
+    out[u] = acc;
+  } else if (u == 6 * hid) {
+    float acc = 0.f;
+    for (int c = 0; c < cin; ++c) acc += g[5 * hid + cin * hid + c];
+    out[u] = acc;
+  }
+}
+
+void launch_phi_expand(const float* w2, const float* b2, int cin, int hid, float* out, hipStream_t s) {
+  const int n = cin * hid + cin;
+  k_phi_expand<<<(n + 255) / 256, 256, 0, s>>>(w2, b2, cin, hid, out);
+}
+
+void launch_phi_collapse(const float* g, int cin, int hid, float* out, hipStream_t s) {
+  const int n = 6 * hid + 1;
+  k_phi_collapse<<<(n + 255) / 256, 256, 0, s>>>(g, cin, hid, out);
+}
+
 void launch_sum_parts(const double* part, int n, double scale, double* out, hipStream_t s) {
   k_sum_parts<<<1, 64, 0, s>>>(part, n, scale, out);
 }

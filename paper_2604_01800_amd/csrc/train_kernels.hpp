@@ -48,6 +48,8 @@ void launch_sum_parts(const double* part, int n, double scale, double* out, hipS
 // Supervised loss (scale- and shift-invariant misfit of y against the FP64
 // targets e): per-sample losses into lsamp [nb] and dL/dy (batch mean) into
 // dy; part holds [nb][5][nparts] partial sums.
+void launch_phi_expand(const float* w2, const float* b2, int cin, int hid, float* out, hipStream_t s);
+void launch_phi_collapse(const float* g, int cin, int hid, float* out, hipStream_t s);
 void launch_anorm_loss(int64_t N, int nb, const float* y, const float* Ay, const float* R, const double* e,
                        double* part, int nparts, float* dy, double* lsamp, hipStream_t s);
 void launch_sup_loss(int64_t N, int nb, const float* y, const double* e, double* part, int nparts, float* dy,

@@ -47,6 +47,10 @@ CASES = [
     # the paper's U-Net size: 5 levels from 40 channels (40 ... 640)
     (64, 48, 1.6, 1.2, 5, 40, 1, 1, 1),
     (40, 24, 1.3, 1.8, 3, 24, 1, 1, 2),
+    # one local weight per node (Eqs. 17-18 as written)
+    (64, 64, 1.5, 1.5, 4, 32, 2, 1, 1),
+    (80, 48, 2.5, 1.0, 4, 32, 2, 1, 2),
+    (64, 48, 1.6, 1.2, 5, 40, 2, 1, 1),
 ]
 
 
@@ -97,7 +101,8 @@ def test_forward_rejects_bad_shape(ppe):
 
 
 @pytest.mark.parametrize("bad", [dict(basis=12), dict(trunk_width=4), dict(basis=136), dict(levels=7),
-                                 dict(base_channels=12), dict(levels=6, base_channels=64), dict(phi_hidden=33)])
+                                 dict(base_channels=12), dict(levels=6, base_channels=64), dict(phi_hidden=33),
+                                 dict(use_eta=3)])
 def test_config_limits(ppe, bad):
     # basis and trunk_width are channel pitches read in 8-channel groups
     with pytest.raises(ppe.PPEError) as ei:

@@ -63,8 +63,9 @@ def loop_distance(c, i, side, scale):
 
 
 def loop_mconv(P, name, X, geo, use_eta):
-    """conv3x3(eta * X) + b with eta = exp(-Phi(Delta)^2) per input channel,
-    evaluated at the input pixel; zero padding. X: [Cin][H][W] lists."""
+    """conv3x3(eta * X) + b with eta = exp(-Phi(Delta)^2) evaluated at the
+    input pixel, one value per node (use_eta = 2) or per input channel
+    (use_eta = 1); zero padding. X: [Cin][H][W] lists."""
     cx, cy, sx, sy = geo
     W3, b = P[f"{name}.W"], P[f"{name}.b"]
     W1, b1, W2, b2 = P[f"{name}.phi.W1"], P[f"{name}.phi.b1"], P[f"{name}.phi.W2"], P[f"{name}.phi.b2"]
@@ -78,7 +79,8 @@ def loop_mconv(P, name, X, geo, use_eta):
                          loop_distance(cy, j, -1, sy), loop_distance(cy, j, +1, sy)]
                 hid = [math.tanh(sum(W1[a][k] * delta[k] for k in range(4)) + b1[a]) for a in range(len(b1))]
                 for c in range(cin):
-                    phi = sum(W2[c][a] * hid[a] for a in range(len(b1))) + b2[c]
+                    k = 0 if use_eta == 2 else c
+                    phi = sum(W2[k][a] * hid[a] for a in range(len(b1))) + b2[k]
                     eta[c][j][i] = math.exp(-phi * phi)
     out = [[[0.0] * W for _ in range(H)] for _ in range(cout)]
     for o in range(cout):
@@ -163,7 +165,7 @@ def loop_forward(P, cfg, g, r, mask):
 
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("use_eta,use_spacing", [(1, 1), (0, 1), (1, 0)])
+@pytest.mark.parametrize("use_eta,use_spacing", [(2, 1), (1, 1), (0, 1), (2, 0)])
 def test_forward_matches_explicit_loops(use_eta, use_spacing):
     cfg = tiny_cfg(use_eta=use_eta, use_spacing=use_spacing)
     g = tiny_grid()
@@ -185,10 +187,12 @@ def test_three_level_forward_matches_explicit_loops():
     np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
-def test_planted_wiring_mistakes_are_caught(monkeypatch):
+@pytest.mark.parametrize("use_eta", [2, 1])
+def test_planted_wiring_mistakes_are_caught(monkeypatch, use_eta):
     """Each planted mistake in the oracle moves its output away from the
-    explicit loops by far more than rounding."""
-    cfg = tiny_cfg()
+    explicit loops by far more than rounding (the loops agree with the
+    oracle to 1e-12; every mistake moves it by more than 1e-5)."""
+    cfg = tiny_cfg(use_eta=use_eta)
     g = tiny_grid()
     p = onet.init_params(cfg, np.random.default_rng(5), phi_scale=1.0)
     r = np.random.default_rng(6).standard_normal((g.ny, g.nx))
@@ -203,7 +207,7 @@ def test_planted_wiring_mistakes_are_caught(monkeypatch):
 
     # 1. trunk basis transposed: (y, x) fed where (x, y) belongs
     monkeypatch.setattr(onet, "trunk_input", lambda grid: real_trunk_input(grid).flip(1))
-    assert rel_err() > 1e-3
+    assert rel_err() > 1e-5
     monkeypatch.setattr(onet, "trunk_input", real_trunk_input)
 
     # 2. decoder concatenation in the order [skip, upsampled, widths]
@@ -213,7 +217,7 @@ def test_planted_wiring_mistakes_are_caught(monkeypatch):
         return real_cat(parts, dim=dim)
 
     monkeypatch.setattr(onet.torch, "cat", swapped_cat)
-    assert rel_err() > 1e-3
+    assert rel_err() > 1e-5
     monkeypatch.setattr(onet.torch, "cat", real_cat)
 
     # 3. distance maps of the two axes exchanged (left/right <-> down/up)
@@ -221,6 +225,6 @@ def test_planted_wiring_mistakes_are_caught(monkeypatch):
         return [(d[[2, 3, 0, 1]].contiguous(), w) for d, w in real_features(grid, c)]
 
     monkeypatch.setattr(onet, "grid_features", swapped_axes)
-    assert rel_err() > 1e-3
+    assert rel_err() > 1e-5
     monkeypatch.setattr(onet, "grid_features", real_features)
     assert rel_err() <= 1e-12
