@@ -14,6 +14,8 @@ no code with the GPU library. Everything here is FP64 and single-threaded:
 * ``mg``: the multigrid V-cycle preconditioner (the paper's MGPCG-4 CG-type,
   Sec. 2.5), geometric on the tensor grid, for ``pcg``/``hybrid`` with
   ``precond = 2``.
+* ``ic``: the incomplete-Cholesky preconditioner IC(0) in red-black
+  ordering (the paper's ICPCG CG-type, Sec. 2.5), for ``precond = 2``.
 * ``datagen`` and ``ritz``: the training-data generators (random-field
   sources, per-sample grids, and the Lanczos-Ritz vectors of Eqs. 14-16).
 
