@@ -17,7 +17,9 @@ random initialisation (the control), each run capped at --hybrid-max-iter
 iterations and reported as converged or not, with the device time split
 into CG-type, network and line-search parts. config["mgpcg"] and
 config["hybrid_mgpcg"] repeat both with the multigrid-preconditioned CG
-(the paper's strongest CG-type, MGPCG-4).
+(the paper's strongest CG-type, MGPCG-4), and config["icpcg"] and
+config["hybrid_icpcg"] with incomplete-Cholesky PCG (IC(0) in red-black
+ordering, the paper's main comparison CG-type).
 
 `roofline` reports the dominant kernel (the launch of the PCG form that
 runs) on the algorithmic basis of 32 bytes per cell and PCG iteration (the
@@ -172,6 +174,45 @@ def mg_run(ppe, torch, prob, f, x, args):
     out["hybrid_mgpcg"] = {"network": os.path.basename(args.hybrid) if args.hybrid else "seeded random init (control)",
                            "converged": st == ppe.PPE_OK, "ms_per_solve": ms,
                            "solves_per_s": 1e3 / ms if st == ppe.PPE_OK else 0.0,
+                           "iters": s0["iters_total"], "iters_cg": s0["iters_cg"], "iters_dlsm": s0["iters_dlsm"],
+                           "rel_res_true": s0["rel_res_true"], "max_iter": args.mg_hybrid_max_iter,
+                           "ms_pcg": s0["ms_pcg"], "ms_net": s0["ms_net"], "ms_dlsm": s0["ms_dlsm"]}
+    return out
+
+
+def ic_run(ppe, torch, prob, f, x, args):
+    """Incomplete-Cholesky PCG (IC(0) in red-black ordering, the paper's
+    ICPCG CG-type) on the same system, and the hybrid over it (the network of
+    the hybrid leg), timed like the plain solve."""
+    out = {}
+    o = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, precond=ppe.PPE_PC_IC, max_iter=20000)
+    ppe.ppe_solve_plain(prob, f, x, o)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 3))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, stats = ppe.ppe_solve_plain(prob, f, x, o)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    s0 = stats[0]
+    out["icpcg"] = {"converged": st == ppe.PPE_OK, "ms_per_solve": ms, "solves_per_s": 1e3 / ms,
+                    "iters": s0["iters_total"], "reliable_updates": s0["reliable_updates"],
+                    "rel_res_true": s0["rel_res_true"],
+                    "preconditioner": "IC(0) in red-black ordering (two passes over independent cells)"}
+    net = ppe.Net(ppe.ppe_net_config_default(), seed=0)
+    if args.hybrid:
+        ppe.ppe_net_load(net, args.hybrid)
+    oh = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, precond=ppe.PPE_PC_IC, max_iter=args.mg_hybrid_max_iter)
+    t0 = time.perf_counter()
+    st, stats = ppe.ppe_solve_hybrid(prob, net, f, x, oh)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    s0 = stats[0]
+    out["hybrid_icpcg"] = {"network": os.path.basename(args.hybrid) if args.hybrid else "seeded random init (control)",
+                           "converged": st == ppe.PPE_OK,
+                           "status": "converged" if st == ppe.PPE_OK
+                           else f"not converged within {args.mg_hybrid_max_iter} iterations",
+                           "ms_per_solve": ms, "solves_per_s": 1e3 / ms if st == ppe.PPE_OK else 0.0,
                            "iters": s0["iters_total"], "iters_cg": s0["iters_cg"], "iters_dlsm": s0["iters_dlsm"],
                            "rel_res_true": s0["rel_res_true"], "max_iter": args.mg_hybrid_max_iter,
                            "ms_pcg": s0["ms_pcg"], "ms_net": s0["ms_net"], "ms_dlsm": s0["ms_dlsm"]}
@@ -431,6 +472,7 @@ def main():
     }
     out["config"]["hybrid"] = hybrid_run(ppe, torch, prob, f, x, args)
     out["config"].update(mg_run(ppe, torch, prob, f, x, args))
+    out["config"].update(ic_run(ppe, torch, prob, f, x, args))
     if not args.no_hbm_batch:
         out["config"]["hbm_resident_batch"] = hbm_batch_run(ppe, torch, g, prob, args)
     if not args.no_cpu_baseline:

@@ -54,13 +54,16 @@ enum {
 typedef struct ppe_problem ppe_problem; /* opaque: one grid, its coefficients and workspaces */
 typedef struct ppe_net ppe_net;         /* opaque: DeepONet weights, optimiser state, buffers */
 
-/* CG-type of the solve (Sec. 2.5): vanilla CG, Jacobi-PCG, or multigrid-
+/* CG-type of the solve (Sec. 2.5): vanilla CG, Jacobi-PCG, multigrid-
  * preconditioned CG (the paper's MGPCG-4): a V-cycle on the tensor grid with
  * levels made by merging 2 x 2 cells, Galerkin coarse operators of the
  * piecewise-constant prolongation, a degree-2 Chebyshev smoother on D^-1 A
  * over [0.2, 2] before and after the coarse correction, and an exact
- * separable solve on the coarsest level (opts->mg_levels levels, default 4). */
-enum { PPE_PC_NONE = 0, PPE_PC_JACOBI = 1, PPE_PC_MG = 2 };
+ * separable solve on the coarsest level (opts->mg_levels levels, default 4);
+ * or incomplete-Cholesky PCG (the paper's ICPCG): IC(0) of the operator in
+ * red-black (checkerboard) ordering, whose two triangular solves are two
+ * passes over independent cells (nx and ny at least 2, else PPE_ERR_SHAPE). */
+enum { PPE_PC_NONE = 0, PPE_PC_JACOBI = 1, PPE_PC_MG = 2, PPE_PC_IC = 3 };
 enum { PPE_TOL_RELATIVE = 0, PPE_TOL_ABSOLUTE = 1 };   /* ||b-Ax||2 <= tol*||b||2 or <= tol */
 
 /* How an obstacle mask enters the operator. DIBPM (default): it does not;
@@ -131,7 +134,8 @@ typedef struct {
   int32_t chunk;           /* iterations per polled chunk (0 = default 64) */
   int32_t zero_x0;         /* 1 = ignore x on entry and start from x0 = 0 */
   int32_t variant;         /* plain solve: PPE_PCG_AUTO (default), _SINGLE_REDUCTION, _TWO_PHASE or _TWO_STEP;
-                              PPE_PC_MG, PPE_MASK_SOLID and record_history run the two-phase form */
+                              PPE_PC_MG, PPE_PC_IC, PPE_MASK_SOLID and record_history run the
+                              two-phase form */
   int32_t mg_levels;       /* PPE_PC_MG: levels of the V-cycle, 0 = default 4, at most 12; nx and ny must
                               be divisible by 2^(levels-1) (else PPE_ERR_SHAPE) */
   int32_t record_history;  /* 1 = fill each solve's stats history (the caller's buffer, see below) */
@@ -244,7 +248,8 @@ ppe_status ppe_rhs_to_source(const ppe_problem* p, int32_t nb, const float* b, f
 /* z = M^-1 r for the preconditioner opts->precond selects (opts NULL:
  * defaults): PPE_PC_JACOBI z = D^-1 r; PPE_PC_MG one V-cycle from a zero
  * guess (opts->mg_levels), the operator the MG-PCG solve applies each
- * iteration; PPE_PC_NONE z = r. r, z: device FP32 [nb][ny][nx]. Returns
+ * iteration; PPE_PC_IC the two triangular solves of red-black IC(0);
+ * PPE_PC_NONE z = r. r, z: device FP32 [nb][ny][nx]. Returns
  * after the stream's work for the call has completed. */
 ppe_status ppe_apply_precond(ppe_problem* p, int32_t nb, const float* r, float* z, const ppe_solve_opts* opts,
                              hipStream_t s);

@@ -205,7 +205,7 @@ void resolve_plain(const ppe_problem* p, int nb, const ppe_solve_opts& o, int* f
   if (v == PPE_PCG_AUTO) v = PPE_PCG_TWO_STEP;
   // the multigrid preconditioner, masked operators and residual histories
   // are built on the two-phase iteration
-  if (o.precond == PPE_PC_MG || o.record_history || p->mask_mode == PPE_MASK_SOLID) {
+  if (o.precond == PPE_PC_MG || o.precond == PPE_PC_IC || o.record_history || p->mask_mode == PPE_MASK_SOLID) {
     if (v != PPE_PCG_TWO_PHASE) R = 0;
     v = PPE_PCG_TWO_PHASE;
   }
@@ -244,8 +244,8 @@ void launch_chunk(const PcgArgs& a, int nb, int chunk, int form, hipStream_t s) 
 // Capture (once per workspace shape and iteration form) the chunk as a graph.
 static ppe_status get_chunk_graph(ppe_problem* p, const PcgArgs& a, int nb, int chunk, int form) {
   SolveWs& w = p->ws;
-  const std::array<int64_t, 8> key = {nb, a.R, a.jacobi, chunk, form, a.mg ? (int64_t)a.mg->uid : 0,
-                                      (int64_t)(intptr_t)a.hist, a.hist_cap};
+  const std::array<int64_t, 8> key = {nb, a.R, a.jacobi + (a.icq ? 2 : 0), chunk, form,
+                                      a.mg ? (int64_t)a.mg->uid : 0, (int64_t)(intptr_t)a.hist, a.hist_cap};
   if (w.exec && key == w.exec_key) return PPE_OK;
   if (w.exec) {
     (void)hipGraphExecDestroy(w.exec);
@@ -276,7 +276,7 @@ ppe_status run_pcg_chunks(ppe_problem* p, const PcgArgs& a, int nb, const ppe_so
   // Iterations per polled chunk: multigrid converges in tens of iterations,
   // Jacobi-PCG in thousands; a chunk may run past convergence by up to two
   // chunks of early-exit launches.
-  int chunk = o.chunk > 0 ? o.chunk : (a.mg ? 8 : 64);
+  int chunk = o.chunk > 0 ? o.chunk : (a.mg ? 8 : a.icq ? 32 : 64);
   chunk += chunk & 1;
   if (o.use_graph) {
     ppe_status st = get_chunk_graph(p, a, nb, chunk, form);
@@ -342,7 +342,58 @@ ppe_status state_status(const SolveState& S) {
   return S.done == DONE_CONV ? PPE_OK : S.done == DONE_NONFINITE ? PPE_ERR_NONFINITE : PPE_NOT_CONVERGED;
 }
 
+// The red-black IC(0) diagonals of a problem (FP64 on the host, rounded
+// once): q = 1/D on red cells, 1/S_b on black cells with
+// S_b = D_b - sum over the red neighbours r of w_br^2 / D_r; and its output
+// buffer for nb right-hand sides.
+static ppe_status ic_ensure(ppe_problem* p, int nb, hipStream_t s) {
+  const int nx = p->nx, ny = p->ny;
+  const int64_t N = (int64_t)nx * ny;
+  if (!p->d_icq) {
+    std::vector<double> gx(nx + 1, 0.0), gy(ny + 1, 0.0);
+    for (int k = 1; k < nx; ++k) gx[k] = 1.0 / (p->xc[k] - p->xc[k - 1]);
+    for (int k = 1; k < ny; ++k) gy[k] = 1.0 / (p->yc[k] - p->yc[k - 1]);
+    auto D = [&](int i, int j) { return p->hy[j] * (gx[i] + gx[i + 1]) + p->hx[i] * (gy[j] + gy[j + 1]); };
+    std::vector<float> q((size_t)N);
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double d = D(i, j);
+        if ((i + j) % 2) {  // black: the four red neighbours (face weight 0 at a wall)
+          if (i > 0) d -= std::pow(p->hy[j] * gx[i], 2) / D(i - 1, j);
+          if (i + 1 < nx) d -= std::pow(p->hy[j] * gx[i + 1], 2) / D(i + 1, j);
+          if (j > 0) d -= std::pow(p->hx[i] * gy[j], 2) / D(i, j - 1);
+          if (j + 1 < ny) d -= std::pow(p->hx[i] * gy[j + 1], 2) / D(i, j + 1);
+        }
+        if (!(d > 0.0)) return set_error(PPE_ERR_SHAPE, "IC(0) breaks down at cell (%d, %d)", i, j);
+        q[(size_t)j * nx + i] = (float)(1.0 / d);
+      }
+    float* dq = (float*)dev_alloc(sizeof(float) * N);
+    if (!dq) return set_error(PPE_ERR_HIP, "allocation of the IC(0) diagonals failed");
+    const hipError_t e = hipMemcpyAsync(dq, q.data(), sizeof(float) * N, hipMemcpyHostToDevice, s);
+    const hipError_t es = hipStreamSynchronize(s);  // q goes out of scope
+    if (e != hipSuccess || es != hipSuccess) {
+      dev_free(dq);
+      return set_error(PPE_ERR_HIP, "upload of the IC(0) diagonals failed");
+    }
+    p->d_icq = dq;
+  }
+  if (p->ic_nb < nb) {
+    dev_free(p->d_icz);
+    p->d_icz = (float*)dev_alloc(sizeof(float) * N * nb);
+    p->ic_nb = p->d_icz ? nb : 0;
+    if (!p->d_icz) return set_error(PPE_ERR_HIP, "allocation of the IC(0) output failed");
+  }
+  return PPE_OK;
+}
+
 ppe_status attach_extras(ppe_problem* p, PcgArgs& a, int nb, const ppe_solve_opts& o, hipStream_t s) {
+  if (o.precond == PPE_PC_IC) {
+    ppe_status st = ic_ensure(p, nb, s);
+    if (st != PPE_OK) return st;
+    a.icq = p->d_icq;
+    a.z = p->d_icz;
+    a.jacobi = 0;
+  }
   if (o.precond == PPE_PC_MG) {
     ppe_status st = mg_ensure(p, o.mg_levels > 0 ? o.mg_levels : 4, nb, a.R, s);
     if (st != PPE_OK) return st;
@@ -419,10 +470,14 @@ ppe_status check_solve_args(const ppe_problem* p, int32_t nb, const void* f, con
     if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol))
       return set_error(PPE_ERR_INVALID_ARG, "tol must be finite and >= 0");
     if (opts->max_iter < 0) return set_error(PPE_ERR_INVALID_ARG, "max_iter < 0");
-    if (opts->precond != PPE_PC_NONE && opts->precond != PPE_PC_JACOBI && opts->precond != PPE_PC_MG)
+    if (opts->precond != PPE_PC_NONE && opts->precond != PPE_PC_JACOBI && opts->precond != PPE_PC_MG &&
+        opts->precond != PPE_PC_IC)
       return set_error(PPE_ERR_INVALID_ARG, "unknown preconditioner %d", opts->precond);
-    if (p->mask_mode == PPE_MASK_SOLID && opts->precond == PPE_PC_MG)
-      return set_error(PPE_ERR_UNSUPPORTED, "the multigrid preconditioner does not take PPE_MASK_SOLID grids");
+    if (p->mask_mode == PPE_MASK_SOLID && (opts->precond == PPE_PC_MG || opts->precond == PPE_PC_IC))
+      return set_error(PPE_ERR_UNSUPPORTED, "the multigrid and IC preconditioners do not take PPE_MASK_SOLID grids");
+    if (opts->precond == PPE_PC_IC && (p->nx < 2 || p->ny < 2))
+      return set_error(PPE_ERR_SHAPE, "the IC(0) preconditioner needs nx and ny of at least 2 (got %d x %d)", p->nx,
+                       p->ny);
     if (opts->mg_levels < 0 || opts->mg_levels > 12)
       return set_error(PPE_ERR_INVALID_ARG, "mg_levels must lie in [0, 12]");
     if (opts->precond == PPE_PC_MG) {
@@ -650,7 +705,8 @@ ppe_status ppe_apply_precond(ppe_problem* p, int32_t nb, const float* r, float* 
   if (o.precond == PPE_PC_JACOBI) {
     launch_direction(a, nb, PPE_DIR_JACOBI, z, s);
   } else {
-    launch_vcycle(a, nb, s);
+    if (o.precond == PPE_PC_MG) launch_vcycle(a, nb, s);
+    else launch_ic(a, nb, s);
     HIPCHK(hipMemcpyAsync(z, a.z, sizeof(float) * N, hipMemcpyDeviceToDevice, s));
   }
   HIPCHK(hipGetLastError());

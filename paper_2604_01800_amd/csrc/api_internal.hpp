@@ -67,6 +67,11 @@ struct ppe_problem {
   hipStream_t cap_stream = nullptr;
   ppe::NetCache* net_cache = nullptr;
   ppe::MgData* mg = nullptr;
+  // incomplete-Cholesky preconditioner: 1/D on red cells, 1/S on black cells,
+  // and its output z for up to ic_nb right-hand sides
+  float* d_icq = nullptr;
+  float* d_icz = nullptr;
+  int ic_nb = 0;
 };
 
 namespace ppe {

@@ -161,7 +161,7 @@ extern "C" ppe_status ppe_solve_batch(int32_t n, ppe_problem* const* problems, c
   }
   if (o.variant == PPE_PCG_TWO_PHASE)
     return set_error(PPE_ERR_UNSUPPORTED, "the mixed-size batch runs the two-step or single-reduction form");
-  if (o.precond == PPE_PC_MG || o.record_history)
+  if (o.precond == PPE_PC_MG || o.precond == PPE_PC_IC || o.record_history)
     return set_error(PPE_ERR_UNSUPPORTED, "the plain mixed-size batch runs Jacobi or no preconditioning, without history");
   for (int i = 0; i < n; ++i)
     if (problems[i]->mask_mode == PPE_MASK_SOLID)

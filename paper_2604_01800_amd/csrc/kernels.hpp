@@ -30,6 +30,9 @@ struct PcgArgs {
   // pass that changes r.
   const struct MgData* mg;
   float* z;     // [nb][N]
+  // Incomplete-Cholesky preconditioner (red-black IC(0)): 1/D on red cells
+  // and 1/S on black cells [ny][nx], NULL otherwise; z as for multigrid.
+  const float* icq;
   // Residual history (device [nb][hist_cap] FP64, NULL when not recorded).
   double* hist;
   int hist_cap;
@@ -40,6 +43,7 @@ dim3 stencil_grid2(const Coef& c, int R, int nb);
 void launch_apply_f32(const Coef& c, int nb, const float* x, float* y, int R, hipStream_t s);
 void launch_apply_f64(const Coef& c, int nb, const double* x, double* y, int R, hipStream_t s);
 void launch_rhs_to_source(const Coef& c, int nb, const float* b, float* f, hipStream_t s);
+void launch_ic(const PcgArgs& a, int nb, hipStream_t s);
 void launch_set_call(CallArgs* c, const float* f, double* x, int max_iter, double delta2, hipStream_t s);
 void launch_rhs(const PcgArgs& a, int nb, hipStream_t s);
 void launch_pcg_setup(const PcgArgs& a, int nb, hipStream_t s);

@@ -109,7 +109,7 @@ extern "C" ppe_status ppe_solve_plain_noalloc(const ppe_problem* p, const float*
   if (opts) o = *opts;
   ppe_status st = check_solve_args(p, 1, f, x, &o);
   if (st != PPE_OK) return st;
-  if (o.precond == PPE_PC_MG || o.record_history || p->mask_mode == PPE_MASK_SOLID)
+  if (o.precond == PPE_PC_MG || o.precond == PPE_PC_IC || o.record_history || p->mask_mode == PPE_MASK_SOLID)
     return set_error(PPE_ERR_UNSUPPORTED,
                      "the allocation-free solve runs Jacobi or no preconditioning on unmasked operators, "
                      "without history");

@@ -894,7 +894,7 @@ void launch_rhs(const PcgArgs& a, int nb, hipStream_t s) {
 // Kernel variant (PcKind): 0 none, 1 Jacobi, 2 a supplied z (multigrid);
 // 3, 4: none, Jacobi on the solid-mask operator.
 static int pc_of(const PcgArgs& a) {
-  if (a.mg) return 2;
+  if (a.mg || a.icq) return 2;
   return (a.c.fl ? 3 : 0) + (a.jacobi ? 1 : 0);
 }
 
@@ -907,11 +907,18 @@ static int pc_of(const PcgArgs& a) {
     default: { constexpr int PP = 0; PPE_DISPATCH_R(R, __VA_ARGS__); } break; \
   }
 
+// z = M^-1 r for the preconditioners applied by their own kernels after
+// every pass that changes r (multigrid V-cycle, red-black IC(0)).
+static void launch_pc(const PcgArgs& a, int nb, hipStream_t s) {
+  if (a.mg) launch_vcycle(a, nb, s);
+  else if (a.icq) launch_ic(a, nb, s);
+}
+
 void launch_pcg_setup(const PcgArgs& a, int nb, hipStream_t s) {
   const dim3 g = stencil_grid(a.c, a.R, nb);
   launch_rhs(a, nb, s);
   PPE_DISPATCH_PC(pc_of(a), a.R, k_pcg_init<RR, PP><<<g, kBlock, 0, s>>>(a));
-  if (a.mg) launch_vcycle(a, nb, s);
+  launch_pc(a, nb, s);
 }
 
 // One CG iteration (or reliable-update pass) of the two-phase form; with the
@@ -921,7 +928,7 @@ void launch_pcg_pair(const PcgArgs& a, int nb, int par, int force, int force_res
   const dim3 g = stencil_grid(a.c, a.R, nb);
   PPE_DISPATCH_PC(pc_of(a), a.R, k_pcg_a<RR, PP><<<g, kBlock, 0, s>>>(a, par, force, force_restart);
                   k_pcg_b<RR, PP><<<g, kBlock, 0, s>>>(a, par));
-  if (a.mg) launch_vcycle(a, nb, s);
+  launch_pc(a, nb, s);
 }
 
 void launch_pcg_phase_a(const PcgArgs& a, int nb, int par, hipStream_t s) {
@@ -932,7 +939,7 @@ void launch_pcg_phase_a(const PcgArgs& a, int nb, int par, hipStream_t s) {
 void launch_pcg_phase_b(const PcgArgs& a, int nb, int par, hipStream_t s) {
   const dim3 g = stencil_grid(a.c, a.R, nb);
   PPE_DISPATCH_PC(pc_of(a), a.R, k_pcg_b<RR, PP><<<g, kBlock, 0, s>>>(a, par));
-  if (a.mg) launch_vcycle(a, nb, s);
+  launch_pc(a, nb, s);
 }
 
 // One phase launch whose own dispatch carries the start/stop events, so the
@@ -946,7 +953,7 @@ void launch_pcg_phase_timed(const PcgArgs& a, int nb, int par, int phase, hipStr
                     hipExtLaunchKernelGGL(k_pcg_a<RR, PP>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par, 0, 0));
   } else {
     PPE_DISPATCH_PC(pc_of(a), a.R, hipExtLaunchKernelGGL(k_pcg_b<RR, PP>, g, dim3(kBlock), 0, s, e0, e1, 0, a, par));
-    if (a.mg) launch_vcycle(a, nb, s);
+    launch_pc(a, nb, s);
   }
 }
 

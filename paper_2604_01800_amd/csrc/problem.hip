@@ -131,6 +131,10 @@ void problem_release(ppe_problem* p) {
   p->d_mask = nullptr;
   dev_free(p->d_solid);
   p->d_solid = nullptr;
+  dev_free(p->d_icq);
+  dev_free(p->d_icz);
+  p->d_icq = p->d_icz = nullptr;
+  p->ic_nb = 0;
 }
 
 }  // namespace ppe

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libppe_hip.so")
 
 PPE_OK, PPE_NOT_CONVERGED = 0, 1
 PPE_ERR_INVALID_ARG, PPE_ERR_SHAPE, PPE_ERR_UNSUPPORTED, PPE_ERR_HIP, PPE_ERR_NONFINITE = -1, -2, -3, -4, -5
-PPE_PC_NONE, PPE_PC_JACOBI, PPE_PC_MG = 0, 1, 2
+PPE_PC_NONE, PPE_PC_JACOBI, PPE_PC_MG, PPE_PC_IC = 0, 1, 2, 3
 PPE_MASK_DIBPM, PPE_MASK_SOLID = 0, 1
 PPE_LOSS_RESIDUAL, PPE_LOSS_SUPERVISED, PPE_LOSS_ANORM = 0, 1, 2
 PPE_TOL_RELATIVE, PPE_TOL_ABSOLUTE = 0, 1
