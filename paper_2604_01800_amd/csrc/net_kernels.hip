@@ -21,10 +21,12 @@ namespace ppe {
 // The work of a workgroup is a list of items (tile, chunk of 32 input
 // channels). For each item the input chunk with its 3x3 halo, multiplied by
 // the Mesh-Conv local weight eta on the way (Eq. 18), and the chunk's slice
-// of the packed weights are written to LDS; the loads of the next item are
-// issued into registers before the current item's MFMA loop, so HBM and L2
-// latency hide behind it, and the loop itself reads only LDS (fragments one
-// K-step ahead). Each lane's eight consecutive K values are one (tap,
+// of the packed weights are written to LDS (a workgroup with one chunk
+// stages its weight slice once); an item's loads are issued before the
+// barrier that waits for the other waves' MFMA loops of the item before, and
+// the loop itself reads only LDS (fragments one K-step ahead). On tiles whose
+// halo lies inside the image every load address is a per-thread offset fixed
+// for the launch plus a scalar base. Each lane's eight consecutive K values are one (tap,
 // 8-channel group); the packed weight layout enumerates the groups of a chunk
 // in the same order, zero-filled to a multiple of four groups. Weight rows
 // past cout read as zero through a buffer resource that ends at the last
@@ -32,29 +34,34 @@ namespace ppe {
 // written to the 2x nearest-upsampled pixels of a finer level.
 constexpr int kCTH = 16, kCTW = 16;  // pixel tile of the convolution kernel
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// Two BF16 values (one word) times one factor each, back to BF16 by one
+// packed round-to-nearest-even conversion.
+__device__ __forceinline__ uint32_t mul_bf16x2(uint32_t v, float lo, float hi) {
+  const float a = __builtin_bit_cast(float, v << 16) * lo;
+  const float b = __builtin_bit_cast(float, v & 0xffff0000u) * hi;
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
+}
+
+// Eight BF16 values times eight BF16 weights (one local weight per input channel).
 __device__ __forceinline__ uint4 mul_bf16x8(uint4 v, uint4 e) {
-  uint32_t a[4] = {v.x, v.y, v.z, v.w}, b[4] = {e.x, e.y, e.z, e.w}, o[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const float lo = bf2f((bf16_t)(a[q] & 0xffff)) * bf2f((bf16_t)(b[q] & 0xffff));
-    const float hi = bf2f((bf16_t)(a[q] >> 16)) * bf2f((bf16_t)(b[q] >> 16));
-    o[q] = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
-  }
-  return make_uint4(o[0], o[1], o[2], o[3]);
+  auto lo = [](uint32_t w) { return __builtin_bit_cast(float, w << 16); };
+  auto hi = [](uint32_t w) { return __builtin_bit_cast(float, w & 0xffff0000u); };
+  return make_uint4(mul_bf16x2(v.x, lo(e.x), hi(e.x)), mul_bf16x2(v.y, lo(e.y), hi(e.y)),
+                    mul_bf16x2(v.z, lo(e.z), hi(e.z)), mul_bf16x2(v.w, lo(e.w), hi(e.w)));
 }
 
 // Eight BF16 values times one BF16 weight (one local weight per node).
 __device__ __forceinline__ uint4 mul_bf16x8_s(uint4 v, uint32_t e16) {
-  const float e = bf2f((bf16_t)(e16 & 0xffff));
-  uint32_t a[4] = {v.x, v.y, v.z, v.w}, o[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const float lo = bf2f((bf16_t)(a[q] & 0xffff)) * e;
-    const float hi = bf2f((bf16_t)(a[q] >> 16)) * e;
-    o[q] = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
-  }
-  return make_uint4(o[0], o[1], o[2], o[3]);
+  const float e = __builtin_bit_cast(float, e16 << 16);
+  return make_uint4(mul_bf16x2(v.x, e, e), mul_bf16x2(v.y, e, e), mul_bf16x2(v.z, e, e), mul_bf16x2(v.w, e, e));
 }
+
+// Local-weight forms of a convolution: none, one per input channel (a map
+// laid out as the input), one per node (a [H][W] map).
+enum { kEtaNone = 0, kEtaChannel = 1, kEtaNode = 2 };
 
 template <int TN, int TAPS>
 struct ConvShape {
@@ -76,44 +83,57 @@ struct ConvShape {
 };
 
 // Registers of one item's loads, between issue and the write to LDS.
-template <int TN, int TAPS>
+template <int TN, int TAPS, int ETA>
 struct ConvStage {
-  uint4 x[ConvShape<TN, TAPS>::NU], e[ConvShape<TN, TAPS>::NU], w[ConvShape<TN, TAPS>::NW];
+  static constexpr int NU = ConvShape<TN, TAPS>::NU;
+  uint4 x[NU], w[ConvShape<TN, TAPS>::NW];
+  uint4 e[ETA == kEtaChannel ? NU : 1];
+  uint32_t e1[ETA == kEtaNode ? NU : 1];
 };
 
-// Issues the loads of one item: thread t stages the 8-channel group t % 4 of
-// the halo pixels t / 4, t / 4 + 64, ... and a share of the weight slice.
-// Inputs are read through buffer resources over one sample; halo pixels
-// outside the image get an offset past the end, which reads as zero.
+// This thread's staged pixels, fixed for the launch: pixel i sits at (ly, lx)
+// of the halo tile; xo[i] is its 8-channel group's byte offset from the halo
+// tile's first pixel in the input, eo[i] its byte offset in a per-node map
+// (both out of range for the slots past the halo tile).
 template <int TN, int TAPS>
-__device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS>& st, const ConvGeo& g, __amdgpu_buffer_rsrc_t xr,
-                                           __amdgpu_buffer_rsrc_t er, bool has_eta, __amdgpu_buffer_rsrc_t wr, int Kp,
-                                           int co0, int py0, int px0, int c0, int ck8, int kbase) {
+struct ConvLane {
+  static constexpr int NU = ConvShape<TN, TAPS>::NU;
+  uint32_t xo[NU], eo[NU];
+};
+
+// Kept in registers for the launch where they fit (32 output channels per
+// workgroup); recomputed per item (about six VALU operations a pixel) where
+// the 64-channel kernel has no registers to spare.
+template <int TN>
+constexpr bool kKeepLane = TN == 32;
+
+template <int TN, int TAPS>
+__device__ __forceinline__ ConvLane<TN, TAPS> conv_lane(const ConvGeo& g) {
   using S = ConvShape<TN, TAPS>;
-  // recomputed per item (cheap) rather than kept live across the MFMA loop
+  ConvLane<TN, TAPS> ln;
   int tid = threadIdx.x;
-  asm volatile("" : "+v"(tid));
+  asm volatile("" : "+v"(tid));  // not hoisted out of the item loop where recomputed
   const int c8 = tid % S::G8;
-  const bool cg_ok = c8 < ck8;
-  const uint32_t cofs = (uint32_t)(c0 + c8 * 8) * 2;
 #pragma unroll
   for (int i = 0; i < S::NU; ++i) {
     const int pix = tid / S::G8 + S::PPR * i;
     const int ly = pix / S::LW, lx = pix - ly * S::LW;
-    const int gy = py0 + ly - S::HALO, gx = px0 + lx - S::HALO;
-    const bool in = cg_ok && pix < S::NPIX && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W;
-    const uint32_t off = in ? (uint32_t)(gy * g.W + gx) * (uint32_t)(g.cin8 * 2) + cofs : 0x80000000u;
-    st.x[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)off, 0, 0));
-    if (has_eta) {
-      if (g.eta_node) {
-        // one weight per pixel: two bytes at the pixel's index
-        const uint32_t eo = in ? (uint32_t)(gy * g.W + gx) * 2u : 0x80000000u;
-        st.e[i].x = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(er, (int)eo, 0, 0);
-      } else {
-        st.e[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(er, (int)off, 0, 0));
-      }
-    }
+    const uint32_t rel = (uint32_t)(ly * g.W + lx);
+    const bool ok = pix < S::NPIX;
+    ln.xo[i] = ok ? rel * (uint32_t)(g.cin8 * 2) + (uint32_t)c8 * 16u : 0x80000000u;
+    ln.eo[i] = ok ? rel * 2u : 0x80000000u;
   }
+  return ln;
+}
+
+// Loads of a chunk's weight slice (weight rows past cout read as zero),
+// and their write to LDS.
+template <int TN, int TAPS>
+__device__ __forceinline__ void conv_issue_w(uint4* w, __amdgpu_buffer_rsrc_t wr, int Kp,
+                                             int co0, int ck8, int kbase) {
+  using S = ConvShape<TN, TAPS>;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   const int wq = conv_chunk_steps(TAPS, ck8 * 8) * 4;  // 8-value groups per weight row of this chunk
 #pragma unroll
   for (int i = 0; i < S::NW; ++i) {
@@ -121,14 +141,79 @@ __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS>& st, const ConvGe
     const int r = u / S::WQ, q = u - r * S::WQ;
     const bool ok = r < TN && q < wq;
     const uint32_t off = ok ? (uint32_t)(((co0 + r) * Kp + kbase + q * 8) * 2) : 0x80000000u;
-    st.w[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wr, (int)off, 0, 0));
+    w[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(wr, (int)off, 0, 0));
   }
 }
 
-// Writes one item's staged registers to LDS (inputs times eta).
 template <int TN, int TAPS>
-__device__ __forceinline__ void conv_commit(const ConvStage<TN, TAPS>& st, bool has_eta, bool eta_node, int ck8,
-                                            bf16_t* s_x, bf16_t* s_w) {
+__device__ __forceinline__ void conv_commit_w(const uint4* w, int ck8, bf16_t* s_w) {
+  using S = ConvShape<TN, TAPS>;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int wq = conv_chunk_steps(TAPS, ck8 * 8) * 4;
+#pragma unroll
+  for (int i = 0; i < S::NW; ++i) {
+    const int u = tid + 256 * i;
+    const int r = u / S::WQ, q = u - r * S::WQ;
+    if (r < TN && q < wq) *(uint4*)(s_w + r * S::WKP + q * 8) = w[i];
+  }
+}
+
+// Issues the loads of one item: thread t stages the 8-channel group t % G8 of
+// the halo pixels t / G8, t / G8 + PPR, ... and a share of the weight slice
+// (unless the slice is already in LDS). Inputs are read through buffer
+// resources over one sample. On a tile whose halo lies inside the image and
+// a full chunk, every offset is this thread's fixed one plus a scalar base;
+// otherwise halo pixels outside the image (and channel groups past the
+// chunk) get an offset past the end, which reads as zero.
+template <int TN, int TAPS, int ETA>
+__device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS, ETA>& st, const ConvLane<TN, TAPS>& ln,
+                                           const ConvGeo& g, __amdgpu_buffer_rsrc_t xr, __amdgpu_buffer_rsrc_t er,
+                                           __amdgpu_buffer_rsrc_t wr, int Kp, int co0, int py0, int px0, int c0,
+                                           int ck8, int kbase, bool fast, bool wload) {
+  using S = ConvShape<TN, TAPS>;
+  if (fast) {
+    const ConvLane<TN, TAPS> lf = kKeepLane<TN> ? ln : conv_lane<TN, TAPS>(g);
+    const int pbase = (py0 - S::HALO) * g.W + (px0 - S::HALO);  // first halo pixel (>= 0 here)
+    const int xb = (pbase * g.cin8 + c0) * 2;
+#pragma unroll
+    for (int i = 0; i < S::NU; ++i) {
+      st.x[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)lf.xo[i], xb, 0));
+      if constexpr (ETA == kEtaChannel)
+        st.e[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(er, (int)lf.xo[i], xb, 0));
+      if constexpr (ETA == kEtaNode)
+        st.e1[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(er, (int)lf.eo[i], pbase * 2, 0);
+    }
+  } else {
+    // recomputed per item (cheap next to the fast path's share) rather than kept live
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int c8 = tid % S::G8;
+    const bool cg_ok = c8 < ck8;
+    const uint32_t cofs = (uint32_t)(c0 + c8 * 8) * 2;
+#pragma unroll
+    for (int i = 0; i < S::NU; ++i) {
+      const int pix = tid / S::G8 + S::PPR * i;
+      const int ly = pix / S::LW, lx = pix - ly * S::LW;
+      const int gy = py0 + ly - S::HALO, gx = px0 + lx - S::HALO;
+      const bool in = cg_ok && pix < S::NPIX && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W;
+      const uint32_t off = in ? (uint32_t)(gy * g.W + gx) * (uint32_t)(g.cin8 * 2) + cofs : 0x80000000u;
+      st.x[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)off, 0, 0));
+      if constexpr (ETA == kEtaChannel)
+        st.e[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(er, (int)off, 0, 0));
+      if constexpr (ETA == kEtaNode) {
+        const uint32_t eo = in ? (uint32_t)(gy * g.W + gx) * 2u : 0x80000000u;
+        st.e1[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(er, (int)eo, 0, 0);
+      }
+    }
+  }
+  if (wload) conv_issue_w<TN, TAPS>(st.w, wr, Kp, co0, ck8, kbase);
+}
+
+// Writes one item's staged registers to LDS (inputs times eta).
+template <int TN, int TAPS, int ETA>
+__device__ __forceinline__ void conv_commit(const ConvStage<TN, TAPS, ETA>& st, int ck8, bool wload, bf16_t* s_x,
+                                            bf16_t* s_w) {
   using S = ConvShape<TN, TAPS>;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
@@ -137,18 +222,15 @@ __device__ __forceinline__ void conv_commit(const ConvStage<TN, TAPS>& st, bool 
 #pragma unroll
     for (int i = 0; i < S::NU; ++i) {
       const int pix = tid / S::G8 + S::PPR * i;
-      if (pix < S::NPIX)
-        *(uint4*)(s_x + pix * S::CKP + c8 * 8) =
-            !has_eta ? st.x[i] : eta_node ? mul_bf16x8_s(st.x[i], st.e[i].x) : mul_bf16x8(st.x[i], st.e[i]);
+      if (pix < S::NPIX) {
+        uint4 v = st.x[i];
+        if constexpr (ETA == kEtaChannel) v = mul_bf16x8(v, st.e[i]);
+        if constexpr (ETA == kEtaNode) v = mul_bf16x8_s(v, st.e1[i]);
+        *(uint4*)(s_x + pix * S::CKP + c8 * 8) = v;
+      }
     }
   }
-  const int wq = conv_chunk_steps(TAPS, ck8 * 8) * 4;
-#pragma unroll
-  for (int i = 0; i < S::NW; ++i) {
-    const int u = tid + 256 * i;
-    const int r = u / S::WQ, q = u - r * S::WQ;
-    if (r < TN && q < wq) *(uint4*)(s_w + r * S::WKP + q * 8) = st.w[i];
-  }
+  if (wload) conv_commit_w<TN, TAPS>(st.w, ck8, s_w);
 }
 
 // MFMA loop over the K-steps of one staged item. B fragments (staged
@@ -193,16 +275,17 @@ __device__ __forceinline__ void conv_mfma(f32x4_t (&acc)[TN / 16][4], const bf16
   }
 }
 
-template <int TN, int TAPS, bool UP>
+// WSTAT: the workgroup has one input-channel chunk, so its weight slice is
+// staged once, before its first tile.
+template <int TN, int TAPS, bool UP, int ETA, bool WSTAT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv(
-    ConvGeo g, const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta,
-                                              const bf16_t* __restrict__ wp, int Kp, const float* __restrict__ bias,
-                                              bf16_t* __restrict__ y, int tiles_per_wg,
-                                              float* __restrict__ kpart, int ksplit) {
+    ConvGeo g, const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta, const bf16_t* __restrict__ wp, int Kp,
+    const float* __restrict__ bias, bf16_t* __restrict__ y, int tiles_per_wg, float* __restrict__ kpart, int ksplit) {
   using S = ConvShape<TN, TAPS>;
   constexpr int MT = TN / 16, NT = 4;
   __shared__ __attribute__((aligned(16))) bf16_t s_x[S::NPIX * S::CKP];
   __shared__ __attribute__((aligned(16))) bf16_t s_w[TN * S::WKP];
+  __shared__ __attribute__((aligned(16))) float s_b[TN];
 
   const int tiles_x = (g.W + kCTW - 1) / kCTW;
   const int tiles = tiles_x * ((g.H + kCTH - 1) / kCTH);
@@ -212,16 +295,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int smp = blockIdx.z / ksplit, ksp = blockIdx.z - smp * ksplit;
   x += smp * g.x_bstride;
   y += smp * g.y_bstride;
-  if (eta) eta += smp * g.e_bstride;
+  if (ETA != kEtaNone) eta += smp * g.e_bstride;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the output channels' biases (0 past cout), read by the epilogue after
+  // the first item's barriers
+  if (threadIdx.x < TN) s_b[threadIdx.x] = (bias && co0 + (int)threadIdx.x < g.cout) ? bias[co0 + threadIdx.x] : 0.f;
   const __amdgpu_buffer_rsrc_t wr =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(wp), (short)0, (int)((int64_t)g.cout * Kp * 2), 0x00020000);
   const int in_bytes = (int)((int64_t)g.H * g.W * g.cin8 * 2);  // one sample of the input (and of eta)
   const __amdgpu_buffer_rsrc_t xr =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(x), (short)0, in_bytes, 0x00020000);
-  const int eta_bytes = g.eta_node ? (int)((int64_t)g.H * g.W * 2) : in_bytes;
-  const __amdgpu_buffer_rsrc_t er =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(eta ? eta : x), (short)0, eta_bytes, 0x00020000);
+  const int eta_bytes = ETA == kEtaNode ? (int)((int64_t)g.H * g.W * 2) : in_bytes;
+  const __amdgpu_buffer_rsrc_t er = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<bf16_t*>(ETA != kEtaNone ? eta : x), (short)0, eta_bytes, 0x00020000);
+  const int HO = UP ? 2 * g.H : g.H, WO = UP ? 2 * g.W : g.W;
+  const __amdgpu_buffer_rsrc_t yr =
+      __builtin_amdgcn_make_buffer_rsrc(y, (short)0, (int)((int64_t)HO * WO * g.y_pitch * 2), 0x00020000);
+  ConvLane<TN, TAPS> ln;
+  if constexpr (kKeepLane<TN>) ln = conv_lane<TN, TAPS>(g);
   // input-channel chunks of this workgroup: all of them, or its share when
   // the K loop is split over ksplit workgroups
   const int nch_all = (g.cin8 + S::CK - 1) / S::CK;
@@ -236,20 +327,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-  ConvStage<TN, TAPS> stg;
-  auto issue = [&](int it) {
-    const int t = t0 + it / nch, c = c_lo + it - (it / nch) * nch;
-    const int py0 = (t / tiles_x) * kCTH, px0 = (t % tiles_x) * kCTW;
-    conv_issue<TN, TAPS>(stg, g, xr, er, eta != nullptr, wr, Kp, co0, py0, px0, c * S::CK,
-                         min(S::CK, g.cin8 - c * S::CK) / 8, c * S::SMAX * 32);
-  };
-  for (int it = 0; it < items; ++it) {
+  if constexpr (WSTAT) {
+    // the one chunk's weight slice, before the first item (whose barriers
+    // order it before the first MFMA loop)
+    const int ck8 = min(S::CK, g.cin8 - c_lo * S::CK) / 8;
+    uint4 w[S::NW];
+    conv_issue_w<TN, TAPS>(w, wr, Kp, co0, ck8, c_lo * S::SMAX * 32);
+    conv_commit_w<TN, TAPS>(w, ck8, s_w);
+  }
+  constexpr bool wload = !WSTAT;
+  // the loads of item it
+  auto issue = [&](ConvStage<TN, TAPS, ETA>& st, int it) {
     const int t = t0 + it / nch, c = c_lo + it - (it / nch) * nch;
     const int c0 = c * S::CK;
     const int ck8 = min(S::CK, g.cin8 - c0) / 8;
-    issue(it);        // in flight while the other waves finish the previous item
+    const int py0 = (t / tiles_x) * kCTH, px0 = (t % tiles_x) * kCTW;
+    const bool fast = ck8 == S::G8 && py0 >= S::HALO && px0 >= S::HALO && py0 + kCTH + S::HALO <= g.H &&
+                      px0 + kCTW + S::HALO <= g.W;
+    conv_issue<TN, TAPS, ETA>(st, ln, g, xr, er, wr, Kp, co0, py0, px0, c0, ck8, c * S::SMAX * 32, fast, wload);
+  };
+  for (int it = 0; it < items; ++it) {
+    const int t = t0 + it / nch, c = c_lo + it - (it / nch) * nch;
+    const int ck8 = min(S::CK, g.cin8 - c * S::CK) / 8;
+    const int py0 = (t / tiles_x) * kCTH, px0 = (t % tiles_x) * kCTW;
+    // in flight while the other waves finish the previous item (declared here:
+    // nothing of it is live from one item to the next). Issuing the next
+    // item's loads before the current MFMA loop instead costs the 32-channel
+    // kernel a resident workgroup per CU and was slower.
+    ConvStage<TN, TAPS, ETA> stg;
+    issue(stg, it);
     __syncthreads();  // the previous item's MFMA loop is done with LDS
-    conv_commit<TN, TAPS>(stg, eta != nullptr, g.eta_node != 0, ck8, s_x, s_w);
+    conv_commit<TN, TAPS, ETA>(stg, ck8, wload, s_x, s_w);
     __syncthreads();
 
     if (ck8 == S::G8)
@@ -259,7 +367,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (c + 1 < c_lo + nch) continue;
 
     // Epilogue of tile t: lane holds out[co0 + mt*16 + 4*(lane>>4) + j][pixel (row NT*w+nt, col lane&15)].
-    const int py0 = (t / tiles_x) * kCTH, px0 = (t % tiles_x) * kCTW;
     if (ksplit > 1) {
       // partial sums of this share of K, [ksplit][sample][pixel][gridDim.y * TN] FP32
       const int cp = gridDim.y * TN;
@@ -278,40 +385,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       }
       continue;
     }
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      const int co = co0 + mt * 16 + 4 * (lane >> 4);
+      const int col = mt * 16 + 4 * (lane >> 4);  // first of this lane's 4 channels within the workgroup's TN
+      const int co = co0 + col;
       if (co < g.cout) {
-        const float b0 = bias ? bias[co] : 0.f, b1 = bias ? bias[co + 1] : 0.f;
-        const float b2 = bias ? bias[co + 2] : 0.f, b3 = bias ? bias[co + 3] : 0.f;
+        const f32x4_t b = *(const f32x4_t*)(s_b + col);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           const int py = py0 + NT * wv + nt, px = px0 + (lane & 15);
           if (py >= g.H || px >= g.W) continue;
-          float v0 = acc[mt][nt][0] + b0, v1 = acc[mt][nt][1] + b1, v2 = acc[mt][nt][2] + b2,
-                v3 = acc[mt][nt][3] + b3;
+          float v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = acc[mt][nt][j] + b[j];
           if (g.act == 1) {
-            v0 = fmaxf(v0, 0.f);
-            v1 = fmaxf(v1, 0.f);
-            v2 = fmaxf(v2, 0.f);
-            v3 = fmaxf(v3, 0.f);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = __builtin_amdgcn_fmed3f(v[j], 0.f, __builtin_inff());
           } else if (g.act == 2) {
-            v0 = tanh_nn(v0);
-            v1 = tanh_nn(v1);
-            v2 = tanh_nn(v2);
-            v3 = tanh_nn(v3);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = tanh_nn(v[j]);
           }
-          const uint2 packed = make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
-                                          (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+          const u32x2 packed = {__builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){v[0], v[1]}, bf16x2_t)),
+                                __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){v[2], v[3]}, bf16x2_t))};
           if (!UP) {
-            *(uint2*)(y + ((size_t)py * g.W + px) * g.y_pitch + g.y_off + co) = packed;
+            const uint32_t o = (uint32_t)(((py * WO + px) * g.y_pitch + g.y_off + co) * 2);
+            __builtin_amdgcn_raw_buffer_store_b64(packed, yr, (int)o, 0, 0);
           } else {
-            const int W2 = 2 * g.W;
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-              for (int b = 0; b < 2; ++b)
-                *(uint2*)(y + ((size_t)(2 * py + a) * W2 + 2 * px + b) * g.y_pitch + g.y_off + co) = packed;
+              for (int bb = 0; bb < 2; ++bb) {
+                const uint32_t o = (uint32_t)((((2 * py + a) * WO + 2 * px + bb) * g.y_pitch + g.y_off + co) * 2);
+                __builtin_amdgcn_raw_buffer_store_b64(packed, yr, (int)o, 0, 0);
+              }
           }
         }
       }
@@ -733,23 +840,28 @@ static int conv_device_cus() {
 // shares, so ks * nb * pixels * channel pitch < 2 * cus * 256 * 64.
 int64_t conv_kpart_elems() { return (int64_t)2 * conv_device_cus() * kCTH * kCTW * 64; }
 
-template <int TN, int TAPS, bool UP>
-static void conv_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp, int Kp,
-                    const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems) {
-  const int tiles = ((g.W + kCTW - 1) / kCTW) * ((g.H + kCTH - 1) / kCTH);
-  const int cot = (g.cout + TN - 1) / TN;
-  // resident workgroups per CU (registers and LDS), and runs of tiles that
-  // fill them once
+// Resident workgroups per CU of a convolution kernel (registers and LDS),
+// queried once per instantiation.
+template <int TN, int TAPS, bool UP, int ETA, bool WSTAT>
+static int conv_per_cu() {
   static int per_cu = 0;
   if (per_cu == 0) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv<TN, TAPS, UP>, 256, 0) != hipSuccess || n < 1) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv<TN, TAPS, UP, ETA, WSTAT>, 256, 0) != hipSuccess ||
+        n < 1)
+      n = 1;
     per_cu = n;
   }
+  return per_cu;
+}
+
+template <int TN, int TAPS, bool UP, int ETA>
+static void conv_go_eta(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp, int Kp,
+                        const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems) {
+  const int tiles = ((g.W + kCTW - 1) / kCTW) * ((g.H + kCTH - 1) / kCTH);
+  const int cot = (g.cout + TN - 1) / TN;
   const int cus = conv_device_cus();
-  const int64_t slots = (int64_t)cus * per_cu;
   const int64_t wgs = (int64_t)tiles * cot * nb;
-  const int run = (int)std::max<int64_t>(1, (wgs + slots - 1) / slots);
   // Layers with fewer workgroups than compute units (the coarse levels of
   // small grids) split their chunks of input channels over up to
   // ceil(cus / wgs) workgroups, when the caller gave room for the partials.
@@ -761,12 +873,32 @@ static void conv_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta
     ks = (nch + cps - 1) / cps;  // no empty shares
     if ((int64_t)ks * nb * g.H * g.W * cot * TN > kpart_elems) ks = 1;
   }
+  // one chunk per workgroup: the weight slice is staged once
+  const bool wstat = (nch + ks - 1) / ks == 1;
+  // runs of tiles that fill the resident workgroups once
+  const int per_cu = wstat ? conv_per_cu<TN, TAPS, UP, ETA, true>() : conv_per_cu<TN, TAPS, UP, ETA, false>();
+  const int64_t slots = (int64_t)cus * per_cu;
+  const int run = (int)std::max<int64_t>(1, (wgs + slots - 1) / slots);
   const dim3 grid((tiles + run - 1) / run, cot, nb * ks);
-  k_conv<TN, TAPS, UP><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks);
+  if (wstat)
+    k_conv<TN, TAPS, UP, ETA, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks);
+  else
+    k_conv<TN, TAPS, UP, ETA, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks);
   if (ks > 1) {
     const int64_t n = (int64_t)g.H * g.W * (g.cout / 4);
     k_conv_ksum<UP><<<dim3((unsigned)((n + 255) / 256), nb), 256, 0, s>>>(g, nb, ks, cot * TN, kpart, bias, y);
   }
+}
+
+template <int TN, int TAPS, bool UP>
+static void conv_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp, int Kp,
+                    const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems) {
+  if (!eta)
+    conv_go_eta<TN, TAPS, UP, kEtaNone>(g, nb, x, eta, wp, Kp, bias, y, s, kpart, kpart_elems);
+  else if (g.eta_node)
+    conv_go_eta<TN, TAPS, UP, kEtaNode>(g, nb, x, eta, wp, Kp, bias, y, s, kpart, kpart_elems);
+  else
+    conv_go_eta<TN, TAPS, UP, kEtaChannel>(g, nb, x, eta, wp, Kp, bias, y, s, kpart, kpart_elems);
 }
 
 template <int MT>
