@@ -14,6 +14,7 @@
 namespace ppe {
 
 static int pad8(int c) { return (c + 7) / 8 * 8; }
+static int pad_to(int c, int q) { return (c + q - 1) / q * q; }
 
 #define HIPCHK(call)                                                                 \
   do {                                                                               \
@@ -276,20 +277,30 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
     c->d_lv = (float*)dev_alloc(lv.size() * sizeof(float));
     if (!c->d_lv) return set_error(PPE_ERR_HIP, "allocation of level arrays failed");
     HIPCHK(hipMemcpy(c->d_lv, lv.data(), lv.size() * sizeof(float), hipMemcpyHostToDevice));
-    // eta maps, one per Mesh-Conv layer (shared by the batch)
+    // Channel pitches of the buffers that concatenate pooled or upsampled
+    // features with the static channels: rounded up to 32 channels (64
+    // bytes), so that the features of a pixel that one kernel writes and
+    // another reads start on a 64-byte boundary. The level-0 input keeps its
+    // 8 channels.
+    for (int l = 0; l < L; ++l) {
+      c->p_in[l] = l == 0 ? n->enc_a[l].cin8 : pad_to(n->enc_a[l].cin8, 32);
+      if (l < L - 1) c->p_cat[l] = pad_to(n->dec_c[l].cin8, 32);
+    }
+    // eta maps, one per Mesh-Conv layer (shared by the batch); per-channel
+    // maps are laid out as the layer's input (its pitch)
     int64_t eo = 0;
-    auto eta_slot = [&](const MConvL& m) {
+    auto eta_slot = [&](const MConvL& m, int pitch) {
       const int64_t o = eo;
-      eo += (int64_t)c->H[m.level] * c->W[m.level] * (cfg.use_eta == 2 ? 1 : m.cin8);
+      eo += (int64_t)c->H[m.level] * c->W[m.level] * (cfg.use_eta == 2 ? 1 : pitch);
       eo = (eo + 63) / 64 * 64;
       return o;
     };
     for (int l = 0; l < L; ++l) {
-      c->eta_a[l] = eta_slot(n->enc_a[l]);
-      c->eta_b[l] = eta_slot(n->enc_b[l]);
+      c->eta_a[l] = eta_slot(n->enc_a[l], c->p_in[l]);
+      c->eta_b[l] = eta_slot(n->enc_b[l], n->enc_b[l].cin8);
       if (l < L - 1) {
-        c->eta_c[l] = eta_slot(n->dec_c[l]);
-        c->eta_d[l] = eta_slot(n->dec_d[l]);
+        c->eta_c[l] = eta_slot(n->dec_c[l], c->p_cat[l]);
+        c->eta_d[l] = eta_slot(n->dec_d[l], n->dec_d[l].cin8);
       }
     }
     if (cfg.use_eta) {
@@ -309,11 +320,9 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
     };
     for (int l = 0; l < L; ++l) {
       const int ch = cfg.base_channels << l;
-      c->p_in[l] = n->enc_a[l].cin8;
       c->o_in[l] = act(l, c->p_in[l]);
       c->o_a[l] = act(l, ch);
       if (l < L - 1) {
-        c->p_cat[l] = n->dec_c[l].cin8;
         c->o_cat[l] = act(l, c->p_cat[l]);
         c->o_c[l] = act(l, ch);
         c->o_d[l] = act(l, ch);
@@ -348,21 +357,21 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
   }
   // weight-dependent constants: eta maps and the folded trunk basis
   if (cfg.use_eta) {
-    auto eta = [&](const MConvL& m, int64_t off) {
+    auto eta = [&](const MConvL& m, int64_t off, int pitch) {
       const int l = m.level;
       const float* b = c->d_lv + c->lv_off[l];
       const int W = c->W[l], H = c->H[l];
       // one weight per pixel: the same kernel with one output channel
-      const int k = m.phik, k8 = cfg.use_eta == 2 ? 1 : m.cin8;
+      const int k = m.phik, k8 = cfg.use_eta == 2 ? 1 : pitch;
       launch_eta(H, W, k, k8, cfg.phi_hidden, b, b + W, b + 3 * W, b + 3 * W + H, n->d_w + m.oW1, n->d_w + m.ob1,
                  n->d_w + m.oW2, n->d_w + m.ob2, c->d_eta + off, s);
     };
     for (int l = 0; l < L; ++l) {
-      eta(n->enc_a[l], c->eta_a[l]);
-      eta(n->enc_b[l], c->eta_b[l]);
+      eta(n->enc_a[l], c->eta_a[l], c->p_in[l]);
+      eta(n->enc_b[l], c->eta_b[l], n->enc_b[l].cin8);
       if (l < L - 1) {
-        eta(n->dec_c[l], c->eta_c[l]);
-        eta(n->dec_d[l], c->eta_d[l]);
+        eta(n->dec_c[l], c->eta_c[l], c->p_cat[l]);
+        eta(n->dec_d[l], c->eta_d[l], n->dec_d[l].cin8);
       }
     }
   }
@@ -384,18 +393,20 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
   return PPE_OK;
 }
 
-static ConvGeo geo(const NetCache* c, int l, int cin8, int cout, int y_pitch, int y_off, int nb_eta_shared) {
+static ConvGeo geo(const NetCache* c, int l, int cin8, int cout, int y_pitch, int y_off, int nb_eta_shared,
+                   int x_pitch = 0) {
   ConvGeo g;
   g.H = c->H[l];
   g.W = c->W[l];
   g.cin8 = cin8;
+  g.x_pitch = x_pitch ? x_pitch : cin8;
   g.cout = cout;
   g.y_pitch = y_pitch;
   g.y_off = y_off;
-  g.x_bstride = (int64_t)g.H * g.W * cin8;
+  g.x_bstride = (int64_t)g.H * g.W * g.x_pitch;
   g.y_bstride = (int64_t)g.H * g.W * y_pitch;
   g.eta_node = c->use_eta == 2;
-  g.e_bstride = nb_eta_shared ? 0 : (int64_t)g.H * g.W * (g.eta_node ? 1 : cin8);
+  g.e_bstride = nb_eta_shared ? 0 : (int64_t)g.H * g.W * (g.eta_node ? 1 : g.x_pitch);
   g.act = 1;
   return g;
 }
@@ -423,7 +434,7 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
     }
     const MConvL& ma = n->enc_a[l];
     const MConvL& mb = n->enc_b[l];
-    launch_conv(9, false, geo(c, l, ma.cin8, ma.cout, ch(l), 0, 1), nb, A + c->o_in[l], eta(c->eta_a[l]),
+    launch_conv(9, false, geo(c, l, ma.cin8, ma.cout, ch(l), 0, 1, c->p_in[l]), nb, A + c->o_in[l], eta(c->eta_a[l]),
                 n->d_pack + ma.opack, ma.kp, n->d_w + ma.ob, A + c->o_a[l], s, c->d_kpart, c->kpart_elems);
     if (l < L - 1) {
       launch_conv(9, false, geo(c, l, mb.cin8, mb.cout, c->p_cat[l], ch(l), 1), nb, A + c->o_a[l], eta(c->eta_b[l]),
@@ -442,7 +453,7 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
     launch_conv(1, true, gu, nb, src, nullptr, n->d_pack + u.opack, u.kp, n->d_w + u.ob, A + c->o_cat[l], s, c->d_kpart, c->kpart_elems);
     const MConvL& mc = n->dec_c[l];
     const MConvL& md = n->dec_d[l];
-    launch_conv(9, false, geo(c, l, mc.cin8, mc.cout, ch(l), 0, 1), nb, A + c->o_cat[l], eta(c->eta_c[l]),
+    launch_conv(9, false, geo(c, l, mc.cin8, mc.cout, ch(l), 0, 1, c->p_cat[l]), nb, A + c->o_cat[l], eta(c->eta_c[l]),
                 n->d_pack + mc.opack, mc.kp, n->d_w + mc.ob, A + c->o_c[l], s, c->d_kpart, c->kpart_elems);
     launch_conv(9, false, geo(c, l, md.cin8, md.cout, ch(l), 0, 1), nb, A + c->o_c[l], eta(c->eta_d[l]),
                 n->d_pack + md.opack, md.kp, n->d_w + md.ob, A + c->o_d[l], s, c->d_kpart, c->kpart_elems);

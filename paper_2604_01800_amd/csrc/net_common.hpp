@@ -44,7 +44,8 @@ constexpr int kConvCK = 32;  // input channels staged per LDS chunk
 // Geometry of one MConv / conv layer as the kernels see it.
 struct ConvGeo {
   int H, W;          // pixels of the layer's level
-  int cin8;          // input channels read (multiple of 8) = input pitch
+  int cin8;          // input channels read (multiple of 8)
+  int x_pitch;       // channels per pixel of the input buffer (>= cin8)
   int cout;          // output channels
   int y_pitch;       // output buffer pitch (channels per pixel)
   int y_off;         // first output channel in that buffer

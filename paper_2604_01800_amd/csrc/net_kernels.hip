@@ -120,7 +120,7 @@ __device__ __forceinline__ ConvLane<TN, TAPS> conv_lane(const ConvGeo& g) {
     const int ly = pix / S::LW, lx = pix - ly * S::LW;
     const uint32_t rel = (uint32_t)(ly * g.W + lx);
     const bool ok = pix < S::NPIX;
-    ln.xo[i] = ok ? rel * (uint32_t)(g.cin8 * 2) + (uint32_t)c8 * 16u : 0x80000000u;
+    ln.xo[i] = ok ? rel * (uint32_t)(g.x_pitch * 2) + (uint32_t)c8 * 16u : 0x80000000u;
     ln.eo[i] = ok ? rel * 2u : 0x80000000u;
   }
   return ln;
@@ -175,7 +175,7 @@ __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS, ETA>& st, const C
   if (fast) {
     const ConvLane<TN, TAPS> lf = kKeepLane<TN> ? ln : conv_lane<TN, TAPS>(g);
     const int pbase = (py0 - S::HALO) * g.W + (px0 - S::HALO);  // first halo pixel (>= 0 here)
-    const int xb = (pbase * g.cin8 + c0) * 2;
+    const int xb = (pbase * g.x_pitch + c0) * 2;
 #pragma unroll
     for (int i = 0; i < S::NU; ++i) {
       st.x[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)lf.xo[i], xb, 0));
@@ -197,7 +197,7 @@ __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS, ETA>& st, const C
       const int ly = pix / S::LW, lx = pix - ly * S::LW;
       const int gy = py0 + ly - S::HALO, gx = px0 + lx - S::HALO;
       const bool in = cg_ok && pix < S::NPIX && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W;
-      const uint32_t off = in ? (uint32_t)(gy * g.W + gx) * (uint32_t)(g.cin8 * 2) + cofs : 0x80000000u;
+      const uint32_t off = in ? (uint32_t)(gy * g.W + gx) * (uint32_t)(g.x_pitch * 2) + cofs : 0x80000000u;
       st.x[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)off, 0, 0));
       if constexpr (ETA == kEtaChannel)
         st.e[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(er, (int)off, 0, 0));
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   if (threadIdx.x < TN) s_b[threadIdx.x] = (bias && co0 + (int)threadIdx.x < g.cout) ? bias[co0 + threadIdx.x] : 0.f;
   const __amdgpu_buffer_rsrc_t wr =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(wp), (short)0, (int)((int64_t)g.cout * Kp * 2), 0x00020000);
-  const int in_bytes = (int)((int64_t)g.H * g.W * g.cin8 * 2);  // one sample of the input (and of eta)
+  const int in_bytes = (int)((int64_t)g.H * g.W * g.x_pitch * 2);  // one sample of the input (and of eta)
   const __amdgpu_buffer_rsrc_t xr =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(x), (short)0, in_bytes, 0x00020000);
   const int eta_bytes = ETA == kEtaNode ? (int)((int64_t)g.H * g.W * 2) : in_bytes;
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void k_conv1x1(ConvGeo g, const bf16_t* __rest
   }
   __syncthreads();
   const __amdgpu_buffer_rsrc_t xr =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(x), (short)0, (int)((int64_t)npix * g.cin8 * 2), 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(x), (short)0, (int)((int64_t)npix * g.x_pitch * 2), 0x00020000);
   const int tiles = (npix + 15) / 16;
   const int wv = blockIdx.x * 4 + (threadIdx.x >> 6), nwv = gridDim.x * 4;
   // B fragments of tile t: channels ks*32 + (lane>>4)*8 of pixel 16t + (lane&15)
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(256) void k_conv1x1(ConvGeo g, const bf16_t* __rest
 #pragma unroll
     for (int ks = 0; ks < kC1KS; ++ks) {
       const int k = ks * 32 + (lane >> 4) * 8;
-      const uint32_t o = (ks < nks && px < npix && k < g.cin8) ? (uint32_t)(px * g.cin8 + k) * 2u : 0x80000000u;
+      const uint32_t o = (ks < nks && px < npix && k < g.cin8) ? (uint32_t)(px * g.x_pitch + k) * 2u : 0x80000000u;
       bf[ks] = __builtin_bit_cast(bf16x8_t, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)o, 0, 0));
     }
   };

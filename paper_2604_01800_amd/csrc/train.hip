@@ -413,6 +413,7 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
       g.H = t->H[l];
       g.W = t->W[l];
       g.cin8 = cin8;
+      g.x_pitch = cin8;
       g.cout = cout;
       g.y_pitch = y_pitch;
       g.y_off = y_off;

@@ -44,12 +44,14 @@ def generated_grids(n: int, count: int, seed: int = 0, step: int = 0):
     return [ppe.ppe_generate_grid(n, n, seed, step, k) for k in range(count)]
 
 
-def make_ritz_pool(n: int, count: int, seed: int = 0, grids: int = 16, m: int | None = None, b: float = 0.6):
+def make_ritz_pool(n: int, count: int, seed: int = 0, grids: int = 16, m: int | None = None, b: float = 0.6,
+                   log: bool = False):
     """Pool of Lanczos-Ritz training systems (Sec. 2.3, Eqs. 14-16): `grids`
     random stretched n x n grids (ellipse masks), a Lanczos basis of m vectors
     on each (default m = 0.14 N, the paper's m / N), and count / grids
-    vectors drawn on each with weight 9 on the lowest b m Ritz vectors.
-    Returns (grid list of length count, device R [count, n, n] float32)."""
+    vectors drawn on each with weight 9 on the lowest b m Ritz vectors
+    (log: one progress line per grid). Returns (grid list of length count,
+    device R [count, n, n] float32)."""
     import torch
     if count % grids:
         raise ValueError("count must be a multiple of grids")
@@ -58,6 +60,7 @@ def make_ritz_pool(n: int, count: int, seed: int = 0, grids: int = 16, m: int | 
     per = count // grids
     R = torch.empty((count, n, n), dtype=torch.float32, device="cuda")
     gl = [None] * count
+    t0 = time.perf_counter()
     # slot i * grids + k holds vector i of grid k, so consecutive batches mix
     # the grids; the vectors have unit RMS (L2 norm sqrt(N) instead of the 1
     # of Eq. 15), the scale of the other training data
@@ -70,6 +73,8 @@ def make_ritz_pool(n: int, count: int, seed: int = 0, grids: int = 16, m: int | 
             slot = i * grids + k
             ppe.ppe_ritz_rhs(r, R[slot:slot + 1], seed=seed, step=k * per + i, b=b, scale=float(np.sqrt(n * n)))
             gl[slot] = g
+        if log:
+            print(f"ritz pool: grid {k + 1}/{grids} ({m} Lanczos steps, {time.perf_counter() - t0:.1f} s)", flush=True)
     return gl, R
 
 
@@ -202,7 +207,8 @@ def main(argv=None):
         ppe.ppe_net_load(net, args.load)
     else:
         if args.data == "ritz":
-            grids, Rd = make_ritz_pool(args.n, args.pool, seed=1, grids=args.ritz_grids, m=args.ritz_m or None)
+            grids, Rd = make_ritz_pool(args.n, args.pool, seed=1, grids=args.ritz_grids, m=args.ritz_m or None,
+                                       log=True)
         elif args.data == "generated":
             grids, Rd = generated_grids(args.n, args.pool, seed=1), None
         else:
