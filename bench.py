@@ -15,7 +15,11 @@ method of Sec. 2.2 (Num_CG = 3, Num_DLSM = 2) with the network saved at
 --hybrid PATH, or, without one, with the default network at its seeded
 random initialisation (the control), each run capped at --hybrid-max-iter
 iterations and reported as converged or not, with the device time split
-into CG-type, network and line-search parts. config["mgpcg"] and
+into CG-type, network and line-search parts. config["hybrid_trained"]
+repeats it with a network the run trains itself (the default network,
+trained at 64^2 on Lanczos-Ritz vectors, about a minute), and compares
+hybrid with plain PCG on held-out 64^2 systems, where that network was
+trained. config["mgpcg"] and
 config["hybrid_mgpcg"] repeat both with the multigrid-preconditioned CG
 (the paper's strongest CG-type, MGPCG-4), and config["icpcg"] and
 config["hybrid_icpcg"] with incomplete-Cholesky PCG (IC(0) in red-black
@@ -108,17 +112,19 @@ def cpu_baseline(g, f, iters_full, sample_iters):
     }
 
 
-def hybrid_run(ppe, torch, prob, f, x, args):
+def hybrid_run(ppe, torch, prob, f, x, args, net=None, name=None):
     """Hybrid solves (Num_CG = 3, Num_DLSM = 2) of the same system, timed like
     the plain solve (one warm-up, then args.steps, capped at 2 since a hybrid
-    solve can take seconds). The network is the one saved at args.hybrid, or
-    the default network at its seeded random initialisation."""
-    net = ppe.Net(ppe.ppe_net_config_default(), seed=0)
-    if args.hybrid:
-        ppe.ppe_net_load(net, args.hybrid)
-        name = os.path.basename(args.hybrid)
-    else:
-        name = "default network (4 levels, 32-256 channels), seeded random initialisation (control)"
+    solve can take seconds). The network is `net` (described by `name`), else
+    the one saved at args.hybrid, else the default network at its seeded
+    random initialisation."""
+    if net is None:
+        net = ppe.Net(ppe.ppe_net_config_default(), seed=0)
+        if args.hybrid:
+            ppe.ppe_net_load(net, args.hybrid)
+            name = os.path.basename(args.hybrid)
+        else:
+            name = "default network (4 levels, 32-256 channels), seeded random initialisation (control)"
     o = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, max_iter=args.hybrid_max_iter)
     ppe.ppe_solve_hybrid(prob, net, f, x, o)
     torch.cuda.synchronize()
@@ -136,6 +142,46 @@ def hybrid_run(ppe, torch, prob, f, x, args):
            "dlsm_rejected": s0["dlsm_rejected"], "rel_res_true": s0["rel_res_true"],
            "max_iter": args.hybrid_max_iter, "num_cg": 3, "num_dlsm": 2,
            "ms_pcg": s0["ms_pcg"], "ms_net": s0["ms_net"], "ms_dlsm": s0["ms_dlsm"]}
+    return out
+
+
+def trained_run(ppe, torch, prob, f, x, args):
+    """The hybrid half with a network trained here: the default network
+    trained by the library at 64^2 (Eq. 19 loss, Adam with cosine decay from
+    5e-4, batch 16, args.train_steps steps) on Lanczos-Ritz training vectors
+    (Eqs. 14-16: 512 vectors from Lanczos bases of m = 0.14 N on 16 random
+    stretched grids, b = 0.6). Reported: the hybrid solve of the benchmark
+    system with it (timed like the plain solve), and hybrid against plain
+    Jacobi-PCG on six held-out 64^2 systems (random stretching and ellipse,
+    GRF sources), iterations and device ms each."""
+    from paper_2604_01800_amd import training
+    t0 = time.perf_counter()
+    n = 64
+    grids, R = training.make_ritz_pool(n, 512, seed=1, grids=16)
+    probs = [ppe.ppe_problem_create(g) for g in grids]
+    net = ppe.Net(ppe.ppe_net_config_default(), seed=7)
+    losses = training.train(net, grids, R, steps=args.train_steps, batch=16, lr=5e-4, problems=probs,
+                            schedule="cosine")
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    recipe = (f"default network trained here at 64^2: {args.train_steps} Adam steps (Eq. 19 loss, cosine decay from "
+              f"5e-4, batch 16) on 512 Lanczos-Ritz vectors from 16 grids")
+    out = {"training": {"recipe": recipe, "seconds": round(train_s, 1),
+                        "loss_first_50": float(np.mean(losses[:50])), "loss_last_200": float(np.mean(losses[-200:]))},
+           "benchmark_system": hybrid_run(ppe, torch, prob, f, x, args, net=net, name=recipe)}
+    rows = training.evaluate(net, n, count=6, max_iter=args.hybrid_max_iter)
+    ratio = [r["hybrid_iters"] / r["plain_iters"] for r in rows]
+    out["held_out_64"] = {
+        "systems": len(rows),
+        "plain_iters": [r["plain_iters"] for r in rows],
+        "hybrid_iters": [r["hybrid_iters"] for r in rows],
+        "hybrid_dlsm": [r["hybrid_dlsm"] for r in rows],
+        "hybrid_converged": [r["hybrid_converged"] for r in rows],
+        "plain_ms": [round(r["plain_ms"], 3) for r in rows],
+        "hybrid_ms": [round(r["hybrid_ms"], 3) for r in rows],
+        "median_iter_ratio_hybrid_over_plain": float(np.median(ratio)),
+        "median_ms_ratio_hybrid_over_plain": float(np.median([r["hybrid_ms"] / r["plain_ms"] for r in rows])),
+    }
     return out
 
 
@@ -307,6 +353,8 @@ def main():
                     help="network for the hybrid leg, saved by ppe_net_save (default configuration); without it "
                          "the hybrid leg runs the default network at its seeded random initialisation")
     ap.add_argument("--hybrid-max-iter", type=int, default=3000)
+    ap.add_argument("--train-steps", type=int, default=12000,
+                    help="Adam steps of the network trained for config['hybrid_trained'] (0: skip that leg)")
     ap.add_argument("--no-hbm-batch", action="store_true", help="skip the HBM-resident batch leg")
     ap.add_argument("--mg-delta", type=float, default=0.1,
                     help="reliable-update threshold of the multigrid legs")
@@ -471,6 +519,8 @@ def main():
         },
     }
     out["config"]["hybrid"] = hybrid_run(ppe, torch, prob, f, x, args)
+    if args.train_steps > 0 and not args.hybrid:
+        out["config"]["hybrid_trained"] = trained_run(ppe, torch, prob, f, x, args)
     out["config"].update(mg_run(ppe, torch, prob, f, x, args))
     out["config"].update(ic_run(ppe, torch, prob, f, x, args))
     if not args.no_hbm_batch:
