@@ -14,7 +14,6 @@
 namespace ppe {
 
 static int pad8(int c) { return (c + 7) / 8 * 8; }
-static int pad_to(int c, int q) { return (c + q - 1) / q * q; }
 
 #define HIPCHK(call)                                                                 \
   do {                                                                               \
@@ -277,30 +276,32 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
     c->d_lv = (float*)dev_alloc(lv.size() * sizeof(float));
     if (!c->d_lv) return set_error(PPE_ERR_HIP, "allocation of level arrays failed");
     HIPCHK(hipMemcpy(c->d_lv, lv.data(), lv.size() * sizeof(float), hipMemcpyHostToDevice));
-    // Channel pitches of the buffers that concatenate pooled or upsampled
-    // features with the static channels: rounded up to 32 channels (64
-    // bytes), so that the features of a pixel that one kernel writes and
-    // another reads start on a 64-byte boundary. The level-0 input keeps its
-    // 8 channels.
+    // Channel pitches: the level inputs past level 0 hold only the pooled
+    // features and the decoder concatenations only the upsampled and skip
+    // features; the two static channels (widths) of each level live in a
+    // buffer of their own (pitch 8), the convolutions' second input source.
+    // So every kernel that writes features into these buffers writes whole
+    // channel groups of pixel records that start on 64-byte boundaries (for
+    // base channels a multiple of 32), and the readers read no padding.
     for (int l = 0; l < L; ++l) {
-      c->p_in[l] = l == 0 ? n->enc_a[l].cin8 : pad_to(n->enc_a[l].cin8, 32);
-      if (l < L - 1) c->p_cat[l] = pad_to(n->dec_c[l].cin8, 32);
+      c->p_in[l] = l == 0 ? n->enc_a[l].cin8 : (cfg.base_channels << (l - 1));
+      if (l < L - 1) c->p_cat[l] = 2 * (cfg.base_channels << l);
     }
     // eta maps, one per Mesh-Conv layer (shared by the batch); per-channel
-    // maps are laid out as the layer's input (its pitch)
+    // maps have the layer's cin8 channels per pixel
     int64_t eo = 0;
-    auto eta_slot = [&](const MConvL& m, int pitch) {
+    auto eta_slot = [&](const MConvL& m) {
       const int64_t o = eo;
-      eo += (int64_t)c->H[m.level] * c->W[m.level] * (cfg.use_eta == 2 ? 1 : pitch);
+      eo += (int64_t)c->H[m.level] * c->W[m.level] * (cfg.use_eta == 2 ? 1 : m.cin8);
       eo = (eo + 63) / 64 * 64;
       return o;
     };
     for (int l = 0; l < L; ++l) {
-      c->eta_a[l] = eta_slot(n->enc_a[l], c->p_in[l]);
-      c->eta_b[l] = eta_slot(n->enc_b[l], n->enc_b[l].cin8);
+      c->eta_a[l] = eta_slot(n->enc_a[l]);
+      c->eta_b[l] = eta_slot(n->enc_b[l]);
       if (l < L - 1) {
-        c->eta_c[l] = eta_slot(n->dec_c[l], c->p_cat[l]);
-        c->eta_d[l] = eta_slot(n->dec_d[l], n->dec_d[l].cin8);
+        c->eta_c[l] = eta_slot(n->dec_c[l]);
+        c->eta_d[l] = eta_slot(n->dec_d[l]);
       }
     }
     if (cfg.use_eta) {
@@ -329,6 +330,11 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
       } else {
         c->o_bot = act(l, ch);
       }
+      if (cfg.use_spacing) {  // one copy for the batch
+        c->o_st[l] = ao;
+        ao += (int64_t)c->H[l] * c->W[l] * 8;
+        ao = (ao + 127) / 128 * 128;
+      }
     }
     c->act_elems = ao;
     c->d_act = (bf16_t*)dev_alloc(ao * sizeof(bf16_t));
@@ -338,40 +344,38 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
     if (!c->d_act || !c->d_part || !c->d_kpart)
       return set_error(PPE_ERR_HIP, "allocation of network activations failed");
     HIPCHK(hipMemsetAsync(c->d_act, 0, ao * sizeof(bf16_t), s));
-    // static channels: widths (and the mask at level 0)
+    // static channels: widths (and the mask at level 0, in the level-0
+    // input; the widths of every level also in the level's static buffer)
     for (int l = 0; l < L; ++l) {
-      const int ch = cfg.base_channels << l;
       const float* hxn = c->d_lv + c->lv_off[l] + 2 * c->W[l];
       const float* hyn = c->d_lv + c->lv_off[l] + 3 * c->W[l] + 2 * c->H[l];
-      const int coff_in = cfg.use_spacing ? (l == 0 ? 2 : (cfg.base_channels << (l - 1))) : -1;
-      const int64_t bs_in = (int64_t)c->H[l] * c->W[l] * c->p_in[l];
-      launch_fill_static(c->H[l], c->W[l], c->p_in[l], coff_in, hxn, hyn, p->d_mask, l == 0 ? 1 : -1,
-                         c->d_act + c->o_in[l], bs_in, nb, s);
-      if (l < L - 1 && cfg.use_spacing) {
-        const int64_t bs_cat = (int64_t)c->H[l] * c->W[l] * c->p_cat[l];
-        launch_fill_static(c->H[l], c->W[l], c->p_cat[l], 2 * ch, hxn, hyn, nullptr, -1, c->d_act + c->o_cat[l],
-                           bs_cat, nb, s);
+      if (l == 0) {
+        const int64_t bs_in = (int64_t)c->H[0] * c->W[0] * c->p_in[0];
+        launch_fill_static(c->H[0], c->W[0], c->p_in[0], cfg.use_spacing ? 2 : -1, hxn, hyn, p->d_mask, 1,
+                           c->d_act + c->o_in[0], bs_in, nb, s);
       }
+      if (cfg.use_spacing)
+        launch_fill_static(c->H[l], c->W[l], 8, 0, hxn, hyn, nullptr, -1, c->d_act + c->o_st[l], 0, 1, s);
     }
     HIPCHK(hipGetLastError());
   }
   // weight-dependent constants: eta maps and the folded trunk basis
   if (cfg.use_eta) {
-    auto eta = [&](const MConvL& m, int64_t off, int pitch) {
+    auto eta = [&](const MConvL& m, int64_t off) {
       const int l = m.level;
       const float* b = c->d_lv + c->lv_off[l];
       const int W = c->W[l], H = c->H[l];
       // one weight per pixel: the same kernel with one output channel
-      const int k = m.phik, k8 = cfg.use_eta == 2 ? 1 : pitch;
+      const int k = m.phik, k8 = cfg.use_eta == 2 ? 1 : m.cin8;
       launch_eta(H, W, k, k8, cfg.phi_hidden, b, b + W, b + 3 * W, b + 3 * W + H, n->d_w + m.oW1, n->d_w + m.ob1,
                  n->d_w + m.oW2, n->d_w + m.ob2, c->d_eta + off, s);
     };
     for (int l = 0; l < L; ++l) {
-      eta(n->enc_a[l], c->eta_a[l], c->p_in[l]);
-      eta(n->enc_b[l], c->eta_b[l], n->enc_b[l].cin8);
+      eta(n->enc_a[l], c->eta_a[l]);
+      eta(n->enc_b[l], c->eta_b[l]);
       if (l < L - 1) {
-        eta(n->dec_c[l], c->eta_c[l], c->p_cat[l]);
-        eta(n->dec_d[l], c->eta_d[l], n->dec_d[l].cin8);
+        eta(n->dec_c[l], c->eta_c[l]);
+        eta(n->dec_d[l], c->eta_d[l]);
       }
     }
   }
@@ -400,14 +404,30 @@ static ConvGeo geo(const NetCache* c, int l, int cin8, int cout, int y_pitch, in
   g.W = c->W[l];
   g.cin8 = cin8;
   g.x_pitch = x_pitch ? x_pitch : cin8;
+  g.c1 = cin8;
+  g.x1_pitch = 0;
+  g.x1 = nullptr;
+  g.x1_bstride = 0;
   g.cout = cout;
   g.y_pitch = y_pitch;
   g.y_off = y_off;
   g.x_bstride = (int64_t)g.H * g.W * g.x_pitch;
   g.y_bstride = (int64_t)g.H * g.W * y_pitch;
   g.eta_node = c->use_eta == 2;
-  g.e_bstride = nb_eta_shared ? 0 : (int64_t)g.H * g.W * (g.eta_node ? 1 : g.x_pitch);
+  g.e_bstride = nb_eta_shared ? 0 : (int64_t)g.H * g.W * (g.eta_node ? 1 : cin8);
   g.act = 1;
+  return g;
+}
+
+// A convolution whose input channels past the feature buffer's pitch are
+// the level's static channels (the second input source, shared by the batch).
+static ConvGeo with_static(const NetCache* c, ConvGeo g, int l, const bf16_t* A) {
+  if (g.x_pitch < g.cin8) {
+    g.c1 = g.x_pitch;
+    g.x1 = A + c->o_st[l];
+    g.x1_pitch = 8;
+    g.x1_bstride = 0;
+  }
   return g;
 }
 
@@ -434,8 +454,9 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
     }
     const MConvL& ma = n->enc_a[l];
     const MConvL& mb = n->enc_b[l];
-    launch_conv(9, false, geo(c, l, ma.cin8, ma.cout, ch(l), 0, 1, c->p_in[l]), nb, A + c->o_in[l], eta(c->eta_a[l]),
-                n->d_pack + ma.opack, ma.kp, n->d_w + ma.ob, A + c->o_a[l], s, c->d_kpart, c->kpart_elems);
+    launch_conv(9, false, with_static(c, geo(c, l, ma.cin8, ma.cout, ch(l), 0, 1, c->p_in[l]), l, A), nb,
+                A + c->o_in[l], eta(c->eta_a[l]), n->d_pack + ma.opack, ma.kp, n->d_w + ma.ob, A + c->o_a[l], s,
+                c->d_kpart, c->kpart_elems);
     if (l < L - 1) {
       launch_conv(9, false, geo(c, l, mb.cin8, mb.cout, c->p_cat[l], ch(l), 1), nb, A + c->o_a[l], eta(c->eta_b[l]),
                   n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob, A + c->o_cat[l], s, c->d_kpart, c->kpart_elems);
@@ -453,8 +474,9 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
     launch_conv(1, true, gu, nb, src, nullptr, n->d_pack + u.opack, u.kp, n->d_w + u.ob, A + c->o_cat[l], s, c->d_kpart, c->kpart_elems);
     const MConvL& mc = n->dec_c[l];
     const MConvL& md = n->dec_d[l];
-    launch_conv(9, false, geo(c, l, mc.cin8, mc.cout, ch(l), 0, 1, c->p_cat[l]), nb, A + c->o_cat[l], eta(c->eta_c[l]),
-                n->d_pack + mc.opack, mc.kp, n->d_w + mc.ob, A + c->o_c[l], s, c->d_kpart, c->kpart_elems);
+    launch_conv(9, false, with_static(c, geo(c, l, mc.cin8, mc.cout, ch(l), 0, 1, c->p_cat[l]), l, A), nb,
+                A + c->o_cat[l], eta(c->eta_c[l]), n->d_pack + mc.opack, mc.kp, n->d_w + mc.ob, A + c->o_c[l], s,
+                c->d_kpart, c->kpart_elems);
     launch_conv(9, false, geo(c, l, md.cin8, md.cout, ch(l), 0, 1), nb, A + c->o_c[l], eta(c->eta_d[l]),
                 n->d_pack + md.opack, md.kp, n->d_w + md.ob, A + c->o_d[l], s, c->d_kpart, c->kpart_elems);
   }

@@ -45,7 +45,11 @@ constexpr int kConvCK = 32;  // input channels staged per LDS chunk
 struct ConvGeo {
   int H, W;          // pixels of the layer's level
   int cin8;          // input channels read (multiple of 8)
-  int x_pitch;       // channels per pixel of the input buffer (>= cin8)
+  int x_pitch;       // channels per pixel of the input buffer
+  int c1;            // input channels [0, c1) come from the input buffer, [c1, cin8) from x1
+  int x1_pitch;      // channels per pixel of x1
+  const bf16_t* x1;    // second input buffer (channels c1 .. cin8-1), or null when c1 = cin8
+  int64_t x1_bstride;  // elements between samples of x1 (0 = shared by the batch)
   int cout;          // output channels
   int y_pitch;       // output buffer pitch (channels per pixel)
   int y_off;         // first output channel in that buffer

@@ -162,15 +162,17 @@ __device__ __forceinline__ void conv_commit_w(const uint4* w, int ck8, bf16_t* s
 // Issues the loads of one item: thread t stages the 8-channel group t % G8 of
 // the halo pixels t / G8, t / G8 + PPR, ... and a share of the weight slice
 // (unless the slice is already in LDS). Inputs are read through buffer
-// resources over one sample. On a tile whose halo lies inside the image and
-// a full chunk, every offset is this thread's fixed one plus a scalar base;
-// otherwise halo pixels outside the image (and channel groups past the
-// chunk) get an offset past the end, which reads as zero.
+// resources over one sample: input channels below g.c1 from the input
+// buffer (xr), the others from the second source (x1r). On a tile whose halo
+// lies inside the image and a full chunk of the input buffer, every offset is
+// this thread's fixed one plus a scalar base; otherwise halo pixels outside
+// the image (and channel groups past the chunk or in the other source) get
+// an offset past the end, which reads as zero.
 template <int TN, int TAPS, int ETA>
 __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS, ETA>& st, const ConvLane<TN, TAPS>& ln,
-                                           const ConvGeo& g, __amdgpu_buffer_rsrc_t xr, __amdgpu_buffer_rsrc_t er,
-                                           __amdgpu_buffer_rsrc_t wr, int Kp, int co0, int py0, int px0, int c0,
-                                           int ck8, int kbase, bool fast, bool wload) {
+                                           const ConvGeo& g, __amdgpu_buffer_rsrc_t xr, __amdgpu_buffer_rsrc_t x1r,
+                                           __amdgpu_buffer_rsrc_t er, __amdgpu_buffer_rsrc_t wr, int Kp, int co0,
+                                           int py0, int px0, int c0, int ck8, int kbase, bool fast, bool wload) {
   using S = ConvShape<TN, TAPS>;
   if (fast) {
     const ConvLane<TN, TAPS> lf = kKeepLane<TN> ? ln : conv_lane<TN, TAPS>(g);
@@ -179,7 +181,7 @@ __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS, ETA>& st, const C
 #pragma unroll
     for (int i = 0; i < S::NU; ++i) {
       st.x[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)lf.xo[i], xb, 0));
-      if constexpr (ETA == kEtaChannel)
+      if constexpr (ETA == kEtaChannel)  // (the fast path runs only when the map's pitch is the input's)
         st.e[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(er, (int)lf.xo[i], xb, 0));
       if constexpr (ETA == kEtaNode)
         st.e1[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(er, (int)lf.eo[i], pbase * 2, 0);
@@ -189,20 +191,36 @@ __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS, ETA>& st, const C
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int c8 = tid % S::G8;
+    const int cg = c0 + c8 * 8;  // this thread's first input channel
     const bool cg_ok = c8 < ck8;
-    const uint32_t cofs = (uint32_t)(c0 + c8 * 8) * 2;
+    const bool src1 = cg >= g.c1;
+    // sources the chunk touches (uniform)
+    const bool any0 = c0 < g.c1, any1 = c0 + ck8 * 8 > g.c1;
 #pragma unroll
     for (int i = 0; i < S::NU; ++i) {
       const int pix = tid / S::G8 + S::PPR * i;
       const int ly = pix / S::LW, lx = pix - ly * S::LW;
       const int gy = py0 + ly - S::HALO, gx = px0 + lx - S::HALO;
       const bool in = cg_ok && pix < S::NPIX && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W;
-      const uint32_t off = in ? (uint32_t)(gy * g.W + gx) * (uint32_t)(g.x_pitch * 2) + cofs : 0x80000000u;
-      st.x[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)off, 0, 0));
-      if constexpr (ETA == kEtaChannel)
-        st.e[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(er, (int)off, 0, 0));
+      const uint32_t pi = (uint32_t)(gy * g.W + gx);
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (any0) {
+        const uint32_t off = in && !src1 ? pi * (uint32_t)(g.x_pitch * 2) + (uint32_t)cg * 2u : 0x80000000u;
+        v = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)off, 0, 0));
+      }
+      if (any1) {
+        const uint32_t off =
+            in && src1 ? pi * (uint32_t)(g.x1_pitch * 2) + (uint32_t)(cg - g.c1) * 2u : 0x80000000u;
+        const uint4 w = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(x1r, (int)off, 0, 0));
+        v = make_uint4(v.x | w.x, v.y | w.y, v.z | w.z, v.w | w.w);
+      }
+      st.x[i] = v;
+      if constexpr (ETA == kEtaChannel) {  // the map is laid out with pitch cin8
+        const uint32_t eo = in ? pi * (uint32_t)(g.cin8 * 2) + (uint32_t)cg * 2u : 0x80000000u;
+        st.e[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(er, (int)eo, 0, 0));
+      }
       if constexpr (ETA == kEtaNode) {
-        const uint32_t eo = in ? (uint32_t)(gy * g.W + gx) * 2u : 0x80000000u;
+        const uint32_t eo = in ? pi * 2u : 0x80000000u;
         st.e1[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(er, (int)eo, 0, 0);
       }
     }
@@ -302,10 +320,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   if (threadIdx.x < TN) s_b[threadIdx.x] = (bias && co0 + (int)threadIdx.x < g.cout) ? bias[co0 + threadIdx.x] : 0.f;
   const __amdgpu_buffer_rsrc_t wr =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(wp), (short)0, (int)((int64_t)g.cout * Kp * 2), 0x00020000);
-  const int in_bytes = (int)((int64_t)g.H * g.W * g.x_pitch * 2);  // one sample of the input (and of eta)
+  const int in_bytes = (int)((int64_t)g.H * g.W * g.x_pitch * 2);  // one sample of the input
   const __amdgpu_buffer_rsrc_t xr =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16_t*>(x), (short)0, in_bytes, 0x00020000);
-  const int eta_bytes = ETA == kEtaNode ? (int)((int64_t)g.H * g.W * 2) : in_bytes;
+  const __amdgpu_buffer_rsrc_t x1r = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<bf16_t*>(g.x1 ? g.x1 + smp * g.x1_bstride : x), (short)0,
+      g.x1 ? (int)((int64_t)g.H * g.W * g.x1_pitch * 2) : 0, 0x00020000);
+  const int eta_bytes = (int)((int64_t)g.H * g.W * (ETA == kEtaNode ? 1 : g.cin8) * 2);
   const __amdgpu_buffer_rsrc_t er = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<bf16_t*>(ETA != kEtaNone ? eta : x), (short)0, eta_bytes, 0x00020000);
   const int HO = UP ? 2 * g.H : g.H, WO = UP ? 2 * g.W : g.W;
@@ -342,9 +363,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int c0 = c * S::CK;
     const int ck8 = min(S::CK, g.cin8 - c0) / 8;
     const int py0 = (t / tiles_x) * kCTH, px0 = (t % tiles_x) * kCTW;
-    const bool fast = ck8 == S::G8 && py0 >= S::HALO && px0 >= S::HALO && py0 + kCTH + S::HALO <= g.H &&
-                      px0 + kCTW + S::HALO <= g.W;
-    conv_issue<TN, TAPS, ETA>(st, ln, g, xr, er, wr, Kp, co0, py0, px0, c0, ck8, c * S::SMAX * 32, fast, wload);
+    const bool fast = ck8 == S::G8 && c0 + S::CK <= g.c1 && (ETA != kEtaChannel || g.x_pitch == g.cin8) &&
+                      py0 >= S::HALO && px0 >= S::HALO && py0 + kCTH + S::HALO <= g.H && px0 + kCTW + S::HALO <= g.W;
+    conv_issue<TN, TAPS, ETA>(st, ln, g, xr, x1r, er, wr, Kp, co0, py0, px0, c0, ck8, c * S::SMAX * 32, fast,
+                              wload);
   };
   for (int it = 0; it < items; ++it) {
     const int t = t0 + it / nch, c = c_lo + it - (it / nch) * nch;
@@ -918,7 +940,7 @@ static void conv1x1_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* 
 
 void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
                  int Kp, const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems) {
-  if (taps == 1 && !up && !eta && g.cout <= 128 && Kp <= 128 && g.y_pitch % 8 == 0 && g.y_off % 8 == 0) {
+  if (taps == 1 && !up && !eta && !g.x1 && g.cout <= 128 && Kp <= 128 && g.y_pitch % 8 == 0 && g.y_off % 8 == 0) {
     // small 1x1 layers: the skinny GEMM, one round of resident workgroups
     // over all samples
     if (g.cout <= 32) conv1x1_go<2>(g, nb, x, wp, Kp, bias, y, s);

@@ -414,6 +414,10 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
       g.W = t->W[l];
       g.cin8 = cin8;
       g.x_pitch = cin8;
+      g.c1 = cin8;
+      g.x1_pitch = 0;
+      g.x1 = nullptr;
+      g.x1_bstride = 0;
       g.cout = cout;
       g.y_pitch = y_pitch;
       g.y_off = y_off;
