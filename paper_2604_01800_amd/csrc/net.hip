@@ -28,7 +28,7 @@ static void build_layout(ppe_net* n) {
   const ppe_net_config& c = n->cfg;
   const int L = c.levels, H = c.phi_hidden, sp = 2 * c.use_spacing;
   auto ch = [&](int l) { return c.base_channels << l; };
-  int64_t o = 0, op = 0, oe = 0;
+  int64_t o = 0, op = 0;
   auto mconv = [&](int level, int cin, int cout) {
     MConvL m;
     m.level = level;
@@ -44,8 +44,6 @@ static void build_layout(ppe_net* n) {
     m.ob1 = o;
     o += H;
     m.phik = c.use_eta == 2 ? 1 : cin;
-    m.oexp = oe;
-    if (c.use_eta == 2) oe += (int64_t)cin * H + cin;
     m.oW2 = o;
     o += (int64_t)m.phik * H;
     m.ob2 = o;
@@ -99,7 +97,6 @@ static void build_layout(ppe_net* n) {
   o += 1;
   n->np = o;
   n->npack = op;
-  n->nexp = oe;
 }
 
 // splitmix64 + Box-Muller: the library's own seeded initialisation.

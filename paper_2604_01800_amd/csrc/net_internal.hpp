@@ -13,7 +13,6 @@ namespace ppe {
 struct MConvL {
   int level = 0, cin = 0, cout = 0, cin8 = 0, kp = 0;
   int phik = 0;  // outputs of the local-weight network Phi: 1 per node, or cin
-  int64_t oexp = 0;  // per node: offset of the per-channel expansion (cin x H, then cin) used in training
   int64_t oW = 0, ob = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, opack = 0;
 };
 
@@ -32,7 +31,6 @@ struct ppe_net {
   uint64_t uid = 0;       // unique id (per-grid caches key on it)
   uint64_t version = 0;   // bumped whenever the weights change
   int64_t np = 0, npack = 0, step = 0;
-  int64_t nexp = 0;  // per-node local weights: length of the training expansion of all layers' Phi rows
   std::vector<ppe::MConvL> enc_a, enc_b, dec_c, dec_d;
   std::vector<ppe::UpL> up;
   int64_t o_headW = 0, o_headb = 0, o_gamma = 0;

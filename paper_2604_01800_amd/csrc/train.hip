@@ -62,12 +62,6 @@ struct TrainState {
   float* w_save = nullptr;  // [np] weights kept during a sharpness-aware step
   double* sup = nullptr;    // supervised loss: [nb][5][kSupParts] partial sums, then [nb] sample losses
   int sup_nb = 0;
-  // One local weight per node: each Mesh-Conv layer's Phi output row and bias
-  // replicated to one row per input channel (the per-channel form with equal
-  // rows), so the per-channel kernels run unchanged; the per-channel gradient
-  // rows of a layer are reduced into phig and summed back into the single row.
-  float* phix = nullptr;
-  float* phig = nullptr;
 };
 
 constexpr int kSupParts = 64;
@@ -84,8 +78,6 @@ void net_train_free(ppe_net* n) {
   dev_free(t->d_R);
   dev_free(t->gpart);
   dev_free(t->w_save);
-  dev_free(t->phix);
-  dev_free(t->phig);
   dev_free(t->sup);
   dev_free(t->act);
   dev_free(t->grad);
@@ -142,12 +134,13 @@ static ppe_status train_state(ppe_net* n, int nb, int nx, int ny) {
       t->o_bot = A(ao, l, ch(l));
       t->g_bot = A(go, l, ch(l));
     }
-    if (cfg.use_eta) {
-      t->e_a[l] = A(eo, l, n->enc_a[l].cin8);
-      t->e_b[l] = A(eo, l, n->enc_b[l].cin8);
+    if (cfg.use_eta) {  // per-sample maps: one weight per pixel, or one per input channel
+      auto ep = [&](const MConvL& m) { return cfg.use_eta == 2 ? 1 : m.cin8; };
+      t->e_a[l] = A(eo, l, ep(n->enc_a[l]));
+      t->e_b[l] = A(eo, l, ep(n->enc_b[l]));
       if (l < L - 1) {
-        t->e_c[l] = A(eo, l, n->dec_c[l].cin8);
-        t->e_d[l] = A(eo, l, n->dec_d[l].cin8);
+        t->e_c[l] = A(eo, l, ep(n->dec_c[l]));
+        t->e_d[l] = A(eo, l, ep(n->dec_d[l]));
       }
     }
   }
@@ -207,15 +200,6 @@ static ppe_status train_state(ppe_net* n, int nb, int nx, int ny) {
   t->dpart = (double*)dev_alloc(((size_t)kRedBlocks * (nb + 1) + 8) * sizeof(double));
   t->d_coefs = (Coef*)dev_alloc(nb * sizeof(Coef));
   t->d_masks = (const uint8_t**)dev_alloc(nb * sizeof(void*));
-  if (cfg.use_eta == 2) {
-    int64_t gmax = 0;
-    for (const auto* v : {&n->enc_a, &n->enc_b, &n->dec_c, &n->dec_d})
-      for (const MConvL& m : *v)
-        if (m.cin) gmax = std::max<int64_t>(gmax, eta_bwd_len(m.cin, cfg.phi_hidden));
-    t->phix = (float*)dev_alloc(std::max<int64_t>(n->nexp, 1) * sizeof(float));
-    t->phig = (float*)dev_alloc(std::max<int64_t>(gmax, 1) * sizeof(float));
-    if (!t->phix || !t->phig) return set_error(PPE_ERR_HIP, "allocation of the per-node weight expansion failed");
-  }
   if (!t->act || !t->grad || (cfg.use_eta && !t->eta) || !t->packs || !t->f32 || !t->part || !t->dpart ||
       !t->d_coefs || !t->d_masks)
     return set_error(PPE_ERR_HIP, "allocation of the training workspace failed");
@@ -269,7 +253,7 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
   const ppe_net_config& cfg = n->cfg;
   const int nx = problems[0]->nx, ny = problems[0]->ny, L = cfg.levels, P = cfg.basis, TWd = cfg.trunk_width;
   const int TH = cfg.trunk_hidden, HID = cfg.phi_hidden, C0 = cfg.base_channels;
-  if (cfg.use_eta) {
+  if (cfg.use_eta == 1) {
     auto fits = [&](const MConvL& m) { return m.cin == 0 || eta_bwd_fits(m.cin, m.cin8, HID); };
     for (int l = 0; l < L; ++l) {
       const bool ok = fits(n->enc_a[l]) && fits(n->enc_b[l]) && (l > L - 2 || (fits(n->dec_c[l]) && fits(n->dec_d[l])));
@@ -341,24 +325,7 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
   // One forward and backward pass at the current weights: the loss sum in
   // lpart[kRedBlocks] and the gradient in dG.
   const bool per_node = cfg.use_eta == 2;
-  auto each_mconv = [&](auto&& fn) {
-    for (int l = 0; l < L; ++l) {
-      fn(n->enc_a[l]);
-      fn(n->enc_b[l]);
-      if (l < L - 1) {
-        fn(n->dec_c[l]);
-        fn(n->dec_d[l]);
-      }
-    }
-  };
-  // Phi's output row and bias of a layer as the per-channel kernels read them
-  auto phi_w2 = [&](const MConvL& m) -> const float* { return per_node ? t->phix + m.oexp : W + m.oW2; };
-  auto phi_b2 = [&](const MConvL& m) -> const float* {
-    return per_node ? t->phix + m.oexp + (int64_t)m.cin * HID : W + m.ob2;
-  };
   auto fwd_bwd = [&]() -> ppe_status {
-    if (per_node)
-      each_mconv([&](const MConvL& m) { launch_phi_expand(W + m.oW2, W + m.ob2, m.cin, HID, t->phix + m.oexp, s); });
     // packed weights of this step (transposed operators and the head / trunk forward)
     for (int l = 0; l < L; ++l) {
       const MConvL& a = n->enc_a[l];
@@ -395,8 +362,10 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
     launch_trunk_input(ny, nx, t->d_lv + t->tin_off, t->lv_stride, Ab + t->o_t0, nb, s);
     auto eta_fwd = [&](const MConvL& m, int64_t off) {
       const int l = m.level;
-      launch_eta_multi(t->H[l], t->W[l], m.cin, m.cin8, HID, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
-                       W + m.ob1, phi_w2(m), phi_b2(m), E + off, hw(l) * m.cin8, nb, s);
+      // one weight per node: the same kernel with Phi's single output
+      const int k = per_node ? 1 : m.cin, k8 = per_node ? 1 : m.cin8;
+      launch_eta_multi(t->H[l], t->W[l], k, k8, HID, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1, W + m.ob1,
+                       W + m.oW2, W + m.ob2, E + off, hw(l) * k8, nb, s);
     };
     if (cfg.use_eta)
       for (int l = 0; l < L; ++l) {
@@ -423,9 +392,9 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
       g.y_off = y_off;
       g.x_bstride = hw(l) * cin8;
       g.y_bstride = hw(l) * y_pitch;
-      g.e_bstride = hw(l) * cin8;
+      g.e_bstride = hw(l) * (per_node ? 1 : cin8);
       g.act = act;
-      g.eta_node = 0;  // training keeps per-channel maps (per-node weights are expanded)
+      g.eta_node = per_node;
       return g;
     };
 
@@ -513,7 +482,8 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
       g.dp_pitch = dp_pitch;
       g.x_bstride = hw(l) * cin8;
       g.dp_bstride = hw(l) * dp_pitch;
-      g.e_bstride = hw(l) * cin8;
+      g.e_bstride = hw(l) * (per_node ? 1 : cin8);
+      g.eta_node = per_node;
       const int ns = wgrad_splits(cout, cin8, taps, tiles_of(l), cap);
       launch_wgrad(taps, g, dp, x, eta, part, ns, s);
       launch_reduce_rows(part, ns, (int64_t)cout * cin * taps, 1.f, dG + oW, s);
@@ -529,18 +499,18 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
     auto eta_bwd = [&](const MConvL& m, const bf16_t* x, int64_t eoff, bf16_t* dxb) {
       if (!cfg.use_eta) return;
       const int l = m.level;
-      const int len = eta_bwd_len(m.cin, HID);
+      const int len = per_node ? eta_bwd_node_len(HID) : eta_bwd_len(m.cin, HID);
       // partial rows: up to 2048, as many as the partials buffer holds
-      const int np = (int)std::min<int64_t>(2048, cap / len);
-      launch_eta_bwd(t->H[l], t->W[l], m.cin, m.cin8, HID, nb, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
-                     W + m.ob1, phi_w2(m), phi_b2(m), x, E + eoff, hw(l) * m.cin8, dxb, part, np, s);
+      int np = (int)std::min<int64_t>(2048, cap / len);
       if (per_node) {
-        // the per-channel rows' gradient, summed back into the layer's single row
-        launch_reduce_rows(part, np, len, 1.f, t->phig, s);
-        launch_phi_collapse(t->phig, m.cin, HID, dG + m.oW1, s);
+        np = (int)std::min<int64_t>(np, (hw(l) * nb + 255) / 256);
+        launch_eta_bwd_node(t->H[l], t->W[l], m.cin8, HID, nb, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
+                            W + m.ob1, W + m.oW2, W + m.ob2, x, E + eoff, dxb, part, np, s);
       } else {
-        launch_reduce_rows(part, np, len, 1.f, dG + m.oW1, s);
+        launch_eta_bwd(t->H[l], t->W[l], m.cin, m.cin8, HID, nb, t->d_lv + t->lv_off[l], t->lv_stride, W + m.oW1,
+                       W + m.ob1, W + m.oW2, W + m.ob2, x, E + eoff, hw(l) * m.cin8, dxb, part, np, s);
       }
+      launch_reduce_rows(part, np, len, 1.f, dG + m.oW1, s);
     };
     // DeepONet contraction, head and trunk
     launch_don_bwd(N * nb, P, Ab + t->o_B, Ab + t->o_T, W + n->o_gamma, gAy, dscale, G + t->g_B, G + t->g_T, part,

@@ -109,9 +109,17 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradGeo g, const bf16_t* __restr
           ev[r] = make_uint4(0, 0, 0, 0);
           const int gx = gxb + r;
           if (ok && gx >= 0 && gx < g.W) {
-            const int64_t off = ((int64_t)gy * g.W + gx) * g.cin8 + ci0 + cg * 8;
+            const int64_t pix = (int64_t)gy * g.W + gx;
+            const int64_t off = pix * g.cin8 + ci0 + cg * 8;
             v[r] = *(const uint4*)(xs + off);
-            if (es) ev[r] = *(const uint4*)(es + off);
+            if (es) {
+              if (g.eta_node) {  // one weight for the pixel's eight channels
+                const uint32_t e2 = (uint32_t)es[pix] * 0x10001u;
+                ev[r] = make_uint4(e2, e2, e2, e2);
+              } else {
+                ev[r] = *(const uint4*)(es + off);
+              }
+            }
           }
         }
         if (es) {
@@ -1025,42 +1033,107 @@ void launch_anorm_loss(int64_t N, int nb, const float* y, const float* Ay, const
   k_anorm_grad<<<dim3(nparts, nb), 256, 0, s>>>(N, nb, Ay, R, part, nparts, dy, lsamp);
 }
 
-// One local weight per node, run through the per-channel kernels: Phi's
-// output row w2 [hid] and bias b2 replicated to cin rows (expansion), and the
-// per-channel gradient row [W1 (4 hid) | b1 (hid) | W2 (cin x hid) | b2 (cin)]
-// reduced to the per-node layout [W1 | b1 | W2 (hid) | b2 (1)] (collapse),
-// each channel sum in channel order.
-__global__ void k_phi_expand(const float* __restrict__ w2, const float* __restrict__ b2, int cin, int hid,
-                             float* __restrict__ out) {
-  const int u = blockIdx.x * 256 + threadIdx.x;
-  if (u < cin * hid) out[u] = w2[u % hid];
-  else if (u < cin * hid + cin) out[u] = b2[0];
-}
-
-__global__ void k_phi_collapse(const float* __restrict__ g, int cin, int hid, float* __restrict__ out) {
-  const int u = blockIdx.x * 256 + threadIdx.x;
-  if (u < 5 * hid) {
-    out[u] = g[u];
-  } else if (u < 6 * hid) {
-    const int a = u - 5 * hid;
-    float acc = 0.f;
-    for (int c = 0; c < cin; ++c) acc += g[5 * hid + c * hid + a];
-    out[u] = acc;
-  } else if (u == 6 * hid) {
-    float acc = 0.f;
-    for (int c = 0; c < cin; ++c) acc += g[5 * hid + cin * hid + c];
-    out[u] = acc;
+// Mesh-Conv local-weight backward with one local weight per node (Eqs.
+// 17-18 as written: Phi has one output). Given dXbar (gradient of the
+// weighted input) and the layer input X: dX = eta * dXbar (in place of
+// dXbar), dEta[p] = sum_c dXbar[p][c] X[p][c], and through eta = exp(-Phi^2),
+// Phi = W2 . tanh(W1 d + b1) + b2 (d the node's four distances), the
+// gradients of Phi's parameters. One thread per pixel of the batch
+// (grid-stride). Each thread sums its pixels' parameter gradients; a wave
+// adds its lanes by a butterfly and the workgroup its waves in order, into
+// one partial row [W1 (hid*4) | b1 (hid) | W2 (hid) | b2] (the layout of
+// these parameters in the flat vector). HC = hid rounded up to a power of two.
+template <int HC>
+__global__ __launch_bounds__(256) void k_eta_bwd_node(int H, int W, int cin8, int hid, int nb,
+                                                      const float* __restrict__ lv, int64_t lv_stride,
+                                                      const float* __restrict__ W1, const float* __restrict__ b1,
+                                                      const float* __restrict__ W2, const float* __restrict__ b2,
+                                                      const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta,
+                                                      bf16_t* __restrict__ dxb, float* __restrict__ part) {
+  constexpr int NV = HC * 6 + 1;  // accumulated values: W1 (4 HC), b1, W2, b2
+  __shared__ float s_w[kWaves][NV];
+  float acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.f;
+  const int64_t npix = (int64_t)H * W, ntot = npix * nb;
+  for (int64_t gp = (int64_t)blockIdx.x * 256 + threadIdx.x; gp < ntot; gp += (int64_t)gridDim.x * 256) {
+    const int smp = (int)(gp / npix);
+    const int p = (int)(gp - smp * npix);
+    const int j = p / W, i = p - j * W;
+    const float* L = lv + smp * lv_stride;
+    const float d[4] = {L[i], L[W + i], L[3 * W + j], L[3 * W + H + j]};
+    // dEta and dX over the pixel's channels (eta: one value per pixel of each sample)
+    const float e = bf2f(eta[gp]);
+    const uint4* xr = (const uint4*)(x + gp * cin8);
+    uint4* gr = (uint4*)(dxb + gp * cin8);
+    float se = 0.f;
+    for (int c8 = 0; c8 < cin8 / 8; ++c8) {
+      const uint4 gv = gr[c8], xv = xr[c8];
+      const uint32_t ga[4] = {gv.x, gv.y, gv.z, gv.w}, xa[4] = {xv.x, xv.y, xv.z, xv.w};
+      uint32_t o[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float g0 = bf2f((bf16_t)(ga[k] & 0xffff)), g1 = bf2f((bf16_t)(ga[k] >> 16));
+        se += g0 * bf2f((bf16_t)(xa[k] & 0xffff)) + g1 * bf2f((bf16_t)(xa[k] >> 16));
+        o[k] = (uint32_t)f2bf(e * g0) | ((uint32_t)f2bf(e * g1) << 16);
+      }
+      gr[c8] = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+    // Phi and its parameters' gradients at this node
+    float h[HC];
+    float phi = b2[0];
+#pragma unroll
+    for (int a = 0; a < HC; ++a) {
+      h[a] = 0.f;
+      if (a < hid) {
+        h[a] = tanh_nn(b1[a] + W1[a * 4] * d[0] + W1[a * 4 + 1] * d[1] + W1[a * 4 + 2] * d[2] + W1[a * 4 + 3] * d[3]);
+        phi += W2[a] * h[a];
+      }
+    }
+    const float dphi = se * (-2.f * phi * exp_nn(-phi * phi));
+#pragma unroll
+    for (int a = 0; a < HC; ++a) {
+      if (a >= hid) continue;
+      const float dz = dphi * W2[a] * (1.f - h[a] * h[a]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[a * 4 + k] += dz * d[k];
+      acc[HC * 4 + a] += dz;
+      acc[HC * 5 + a] += dphi * h[a];
+    }
+    acc[HC * 6] += dphi;
+  }
+  // lanes of a wave (butterfly), then the waves in order
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    float v = acc[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) s_w[wv][k] = v;
+  }
+  __syncthreads();
+  const int len = hid * 6 + 1;
+  float* row = part + (int64_t)blockIdx.x * len;
+  for (int u = threadIdx.x; u < len; u += 256) {
+    // u: W1 (a * 4 + k) | b1 (a) | W2 (a) | b2
+    const int k = u < hid * 4 ? u : u < hid * 5 ? HC * 4 + (u - hid * 4) : u < hid * 6 ? HC * 5 + (u - hid * 5) : HC * 6;
+    float t = 0.f;
+    for (int w = 0; w < kWaves; ++w) t += s_w[w][k];
+    row[u] = t;
   }
 }
 
-void launch_phi_expand(const float* w2, const float* b2, int cin, int hid, float* out, hipStream_t s) {
-  const int n = cin * hid + cin;
-  k_phi_expand<<<(n + 255) / 256, 256, 0, s>>>(w2, b2, cin, hid, out);
-}
+int eta_bwd_node_len(int hid) { return hid * 6 + 1; }
 
-void launch_phi_collapse(const float* g, int cin, int hid, float* out, hipStream_t s) {
-  const int n = 6 * hid + 1;
-  k_phi_collapse<<<(n + 255) / 256, 256, 0, s>>>(g, cin, hid, out);
+void launch_eta_bwd_node(int H, int W, int cin8, int hid, int nb, const float* lv, int64_t lv_stride,
+                         const float* W1, const float* b1, const float* W2, const float* b2, const bf16_t* x,
+                         const bf16_t* eta, bf16_t* dxb, float* part, int nparts, hipStream_t s) {
+  if (hid <= 8)
+    k_eta_bwd_node<8><<<nparts, 256, 0, s>>>(H, W, cin8, hid, nb, lv, lv_stride, W1, b1, W2, b2, x, eta, dxb, part);
+  else if (hid <= 16)
+    k_eta_bwd_node<16><<<nparts, 256, 0, s>>>(H, W, cin8, hid, nb, lv, lv_stride, W1, b1, W2, b2, x, eta, dxb, part);
+  else
+    k_eta_bwd_node<32><<<nparts, 256, 0, s>>>(H, W, cin8, hid, nb, lv, lv_stride, W1, b1, W2, b2, x, eta, dxb, part);
 }
 
 void launch_sum_parts(const double* part, int n, double scale, double* out, hipStream_t s) {

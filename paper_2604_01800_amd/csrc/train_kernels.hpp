@@ -11,6 +11,7 @@ struct WgradGeo {
   int cout;           // output channels
   int dp_pitch;       // pitch of the output gradient
   int64_t x_bstride, dp_bstride, e_bstride;  // per-sample strides (e_bstride unused without eta)
+  int eta_node;       // 1: eta holds one weight per pixel ([H][W] per sample), else one per input channel
 };
 
 void launch_wgrad(int taps, const WgradGeo& g, const bf16_t* dp, const bf16_t* x, const bf16_t* eta, float* part,
@@ -48,8 +49,10 @@ void launch_sum_parts(const double* part, int n, double scale, double* out, hipS
 // Supervised loss (scale- and shift-invariant misfit of y against the FP64
 // targets e): per-sample losses into lsamp [nb] and dL/dy (batch mean) into
 // dy; part holds [nb][5][nparts] partial sums.
-void launch_phi_expand(const float* w2, const float* b2, int cin, int hid, float* out, hipStream_t s);
-void launch_phi_collapse(const float* g, int cin, int hid, float* out, hipStream_t s);
+int eta_bwd_node_len(int hid);
+void launch_eta_bwd_node(int H, int W, int cin8, int hid, int nb, const float* lv, int64_t lv_stride,
+                         const float* W1, const float* b1, const float* W2, const float* b2, const bf16_t* x,
+                         const bf16_t* eta, bf16_t* dxb, float* part, int nparts, hipStream_t s);
 void launch_anorm_loss(int64_t N, int nb, const float* y, const float* Ay, const float* R, const double* e,
                        double* part, int nparts, float* dy, double* lsamp, hipStream_t s);
 void launch_sup_loss(int64_t N, int nb, const float* y, const double* e, double* part, int nparts, float* dy,
