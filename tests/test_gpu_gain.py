@@ -17,7 +17,9 @@ MI355X: 0.29-0.67 trained against 1e-6-3e-4 untrained). The hybrid's
 iteration count is not: a rounding-level change in the network output (the
 summation order of the DeepONet contraction) moved the trained/plain
 iteration ratios of these four systems from 0.36-1.6 (median 0.53) to
-0.56-2.2 (median 0.81), with the same trained weights. The bars: the hybrid
+0.56-2.2 (median 0.81), with the same trained weights, and the per-node
+local-weight backward (a different summation order of the same gradient)
+to 0.31-4.2 (median 0.77; shares 0.24-0.73). The bars: the hybrid
 solve with the trained network converges on every system, its direction
 removes at least 10 % of the error and 100x the untrained share, the median
 share is at least 30 %, the hybrid needs at most half the untrained
