@@ -304,6 +304,24 @@ struct CoarseArgs {
 };
 }  // namespace
 
+// sum_q M[q * ld + j] v[q] for q < n (v in LDS), accumulated in q order.
+// The matrix loads of 32 terms are issued together before their products, so
+// the sum waits for the L2 once per 32 terms instead of once per few.
+__device__ __forceinline__ double dot_strided(const double* __restrict__ M, int ld, int j, const double* v, int n) {
+  constexpr int B = 32;
+  double acc = 0.0;
+  int q0 = 0;
+  for (; q0 + B <= n; q0 += B) {
+    double m[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) m[u] = M[(size_t)(q0 + u) * ld + j];
+#pragma unroll
+    for (int u = 0; u < B; ++u) acc += m[u] * v[q0 + u];
+  }
+  for (; q0 < n; ++q0) acc += M[(size_t)q0 * ld + j] * v[q0];
+  return acc;
+}
+
 // Row transform of the coarsest right-hand side (its mean removed):
 // bh[j][k] = sum_i phi[i][k] b[j][i]; one workgroup per row.
 __global__ __launch_bounds__(kBlock) void k_mg_cfwd(CoarseArgs a) {
@@ -317,11 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_cfwd(CoarseArgs a) {
   for (int i = threadIdx.x; i < a.nxc; i += kBlock) row[i] = (double)b[i] - mean;
   __syncthreads();
   double* out = a.bh + (size_t)s * a.Nc + (size_t)j * a.nxc;
-  for (int k = threadIdx.x; k < a.nxc; k += kBlock) {
-    double acc = 0.0;
-    for (int i = 0; i < a.nxc; ++i) acc += a.phi[(size_t)i * a.nxc + k] * row[i];
-    out[k] = acc;
-  }
+  for (int k = threadIdx.x; k < a.nxc; k += kBlock) out[k] = dot_strided(a.phi, a.nxc, k, row, a.nxc);
 }
 
 // Column k of the transformed right-hand side: forward transform along y
@@ -338,17 +352,9 @@ __global__ __launch_bounds__(kBlock) void k_mg_ccol(CoarseArgs a) {
   double* u = col + n;
   for (int j = threadIdx.x; j < n; j += kBlock) t[j] = c[(size_t)j * m];
   __syncthreads();
-  for (int j = threadIdx.x; j < n; j += kBlock) {
-    double acc = 0.0;
-    for (int q = 0; q < n; ++q) acc += a.psi[(size_t)q * n + j] * t[q];
-    u[j] = acc * a.dinv[(size_t)j * m + k];
-  }
+  for (int j = threadIdx.x; j < n; j += kBlock) u[j] = dot_strided(a.psi, n, j, t, n) * a.dinv[(size_t)j * m + k];
   __syncthreads();
-  for (int j = threadIdx.x; j < n; j += kBlock) {
-    double acc = 0.0;
-    for (int q = 0; q < n; ++q) acc += a.psiT[(size_t)q * n + j] * u[q];
-    c[(size_t)j * m] = acc;
-  }
+  for (int j = threadIdx.x; j < n; j += kBlock) c[(size_t)j * m] = dot_strided(a.psiT, n, j, u, n);
 }
 
 // Back-transform x[j][i] = sum_k phi[i][k] c[j][k] and the row sums of x (the
@@ -364,8 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_cbwd(CoarseArgs a) {
   float* x = a.x + (size_t)s * a.Nc + (size_t)j * a.nxc;
   double sum = 0.0;
   for (int i = threadIdx.x; i < a.nxc; i += kBlock) {
-    double acc = 0.0;
-    for (int k = 0; k < a.nxc; ++k) acc += a.phiT[(size_t)k * a.nxc + i] * row[k];
+    const double acc = dot_strided(a.phiT, a.nxc, i, row, a.nxc);
     x[i] = (float)acc;
     sum += (double)(float)acc;
   }
