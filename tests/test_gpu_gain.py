@@ -11,21 +11,20 @@ Measured per held-out system:
   * iterations of the hybrid solve to 1e-6 (3 CG + 2 line-search steps per
     round) with the trained and with the untrained network;
   * iterations of plain PCG.
-Training here is 8 000 Adam steps at lr 5e-4 (under a minute) and is
-deterministic. The line-search shares are the robust signal (measured on
-MI355X: 0.29-0.67 trained against 1e-6-3e-4 untrained). The hybrid's
-iteration count is not: a rounding-level change in the network output (the
-summation order of the DeepONet contraction) moved the trained/plain
-iteration ratios of these four systems from 0.36-1.6 (median 0.53) to
-0.56-2.2 (median 0.81), with the same trained weights, and the per-node
-local-weight backward (a different summation order of the same gradient)
-to 0.31-4.2 (median 0.77; shares 0.24-0.73). The bars: the hybrid
-solve with the trained network converges on every system, its direction
-removes at least 10 % of the error and 100x the untrained share, the median
-share is at least 30 %, the hybrid needs at most half the untrained
-network's iterations (an unconverged solve counts as the iteration limit),
-and on the median system it needs no more iterations than plain PCG. The
-table printed by the test records the numbers."""
+Training here is 12 000 Adam steps at lr 5e-4 (under a minute) and is
+deterministic; six held-out systems. The line-search shares are the robust
+signal (measured on MI355X: 0.27-0.81 trained against 1e-7-3e-3 untrained).
+The hybrid's iteration count moves more: a rounding-level change in the
+network output once moved the trained/plain ratios of the first four of
+these systems from a median of 0.53 to 0.81, with the same weights, and the
+median over four systems after 8 000 steps was 0.77. With 12 000 steps the
+six ratios measured 0.23-2.1, median 0.40, which the bar of 0.7 leaves room
+for. The bars: the hybrid solve with the trained network converges on every
+system, its direction removes at least 10 % of the error and 100x the
+untrained share, the median share is at least 30 %, the hybrid needs at most
+half the untrained network's iterations (an unconverged solve counts as the
+iteration limit), and on the median system it needs at most 0.7 times plain
+PCG's iterations. The table printed by the test records the numbers."""
 import numpy as np
 import pytest
 import torch
@@ -66,13 +65,13 @@ def test_trained_network_gain(ppe):
     cfg = ppe.ppe_net_config_default()
     trained = ppe.Net(cfg, seed=7)
     untrained = ppe.Net(cfg, seed=7)
-    losses = training.train(trained, grids, R, steps=8000, batch=16, lr=5e-4, problems=probs, schedule="cosine")
+    losses = training.train(trained, grids, R, steps=12000, batch=16, lr=5e-4, problems=probs, schedule="cosine")
     assert np.mean(losses[-200:]) < 0.25 * np.mean(losses[:50]), (np.mean(losses[:50]), np.mean(losses[-200:]))
 
     rng = np.random.default_rng(12345)
     rows = []
     max_iter = 20000
-    for k in range(4):
+    for k in range(6):
         g = inputs.with_ellipse(inputs.random_stretched_grid(n, n, rng), rng)
         prob = ppe.ppe_problem_create(g)
         area = torch.from_numpy(np.outer(g.hy, g.hx)[None]).cuda()
@@ -106,4 +105,4 @@ def test_trained_network_gain(ppe):
     it_trained = sum(r["trained"] for r in rows)
     it_untrained = sum(max_iter if r["untrained"] is None else r["untrained"] for r in rows)
     assert 2 * it_trained <= it_untrained, (it_trained, it_untrained)
-    assert np.median([r["trained"] / r["plain"] for r in rows]) <= 1.0, rows
+    assert np.median([r["trained"] / r["plain"] for r in rows]) <= 0.7, rows
