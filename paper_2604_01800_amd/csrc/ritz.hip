@@ -165,14 +165,22 @@ static unsigned blocks_for(int64_t n) { return (unsigned)((n + kRB - 1) / kRB); 
 // ---------------------------------------------------------------------------
 // Host: eigen-decomposition of a symmetric tridiagonal matrix by implicit QR
 // steps with Wilkinson shifts (Golub and Van Loan, Sec. 8.3). a: diagonal
-// (n), b: off-diagonal (n - 1); both are overwritten. Z (n x n, row-major)
-// receives the eigenvectors as columns; the eigenvalues are returned in a.
-// Each step chases a bulge down the unreduced block [p, q] with Givens
-// rotations G acting on coordinates k, k+1 (G_kk = G_k+1,k+1 = c,
-// G_k,k+1 = s, G_k+1,k = -s), T <- G^T T G, Z <- Z G.
-static bool tridiag_qr(int n, std::vector<double>& a, std::vector<double>& b, std::vector<double>& Z) {
-  Z.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+// (n), b: off-diagonal (n - 1); both are overwritten and the eigenvalues are
+// returned in a (in the order the iteration leaves them). Each step chases a
+// bulge down the unreduced block [p, q] with Givens rotations G acting on
+// coordinates k, k+1 (G_kk = G_k+1,k+1 = c, G_k,k+1 = s, G_k+1,k = -s),
+// T <- G^T T G; the eigenvector matrix is Z = G_1 G_2 ... (Z <- Z G for
+// each rotation in turn). The rotations are recorded, one sweep (QR step)
+// at a time: sweeps[t] = {first rotation, p, q}, rotation r acting on
+// coordinates p + (r - first), p + (r - first) + 1.
+struct QrSweeps {
+  std::vector<int64_t> first;
+  std::vector<int> p, q;
+  std::vector<double> c, s;
+};
+
+static bool tridiag_qr(int n, std::vector<double>& a, std::vector<double>& b, QrSweeps& sw) {
+  sw = QrSweeps{};
   const double eps = 2.220446049250313e-16;
   auto small = [&](int k) { return std::fabs(b[k]) <= eps * (std::fabs(a[k]) + std::fabs(a[k + 1])); };
   int q = n - 1;
@@ -187,6 +195,9 @@ static bool tridiag_qr(int n, std::vector<double>& a, std::vector<double>& b, st
     while (p > 0 && !small(p - 1)) --p;
     if (p > 0) b[p - 1] = 0.0;
     if (++steps > 60LL * n + 100) return false;
+    sw.first.push_back((int64_t)sw.c.size());
+    sw.p.push_back(p);
+    sw.q.push_back(q);
     // Wilkinson shift from the trailing 2 x 2 block of [p, q]
     const double d = 0.5 * (a[q - 1] - a[q]);
     const double bq = b[q - 1];
@@ -206,6 +217,31 @@ static bool tridiag_qr(int n, std::vector<double>& a, std::vector<double>& b, st
         b[k + 1] = c * g;
         x = b[k];
       }
+      sw.c.push_back(c);
+      sw.s.push_back(s);
+    }
+  }
+  return true;
+}
+
+// Ascending order of the eigenvalues in a (a stable sort of the indices).
+static std::vector<int> ascending(const std::vector<double>& a) {
+  std::vector<int> ord(a.size());
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int i, int j) { return a[i] < a[j]; });
+  return ord;
+}
+
+// Z <- Z G for every recorded rotation, on the host (Z row-major n x n,
+// starting from the identity), then the columns in ascending order of the
+// eigenvalues and each signed so that its first component (for T_m, the
+// component along the start vector v_0) is not negative.
+static void eigvecs_host(int n, const std::vector<double>& a, const QrSweeps& sw, std::vector<double>& U) {
+  std::vector<double> Z((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+  for (size_t t = 0; t < sw.first.size(); ++t)
+    for (int k = sw.p[t]; k < sw.q[t]; ++k) {
+      const double c = sw.c[sw.first[t] + (k - sw.p[t])], s = sw.s[sw.first[t] + (k - sw.p[t])];
       for (int i = 0; i < n; ++i) {
         double* zi = &Z[(size_t)i * n];
         const double u = zi[k], v = zi[k + 1];
@@ -213,24 +249,126 @@ static bool tridiag_qr(int n, std::vector<double>& a, std::vector<double>& b, st
         zi[k + 1] = s * u + c * v;
       }
     }
-  }
-  // ascending order
-  std::vector<int> ord(n);
-  std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(), [&](int i, int j) { return a[i] < a[j]; });
-  std::vector<double> a2(n), Z2((size_t)n * n);
+  const std::vector<int> ord = ascending(a);
+  U.assign((size_t)n * n, 0.0);
   for (int j = 0; j < n; ++j) {
-    a2[j] = a[ord[j]];
-    for (int i = 0; i < n; ++i) Z2[(size_t)i * n + j] = Z[(size_t)i * n + ord[j]];
+    const double sg = Z[ord[j]] < 0.0 ? -1.0 : 1.0;
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + j] = sg * Z[(size_t)i * n + ord[j]];
   }
-  // Sign convention: the first component of each eigenvector (for T_m, the
-  // component along the start vector v_0) is not negative.
-  for (int j = 0; j < n; ++j)
-    if (Z2[j] < 0.0)
-      for (int i = 0; i < n; ++i) Z2[(size_t)i * n + j] = -Z2[(size_t)i * n + j];
-  a.swap(a2);
-  Z.swap(Z2);
-  return true;
+}
+
+// The same on the device. Zc is column-major (Zc[k][i] = component i of
+// column k), so one thread per component i reads and writes coalesced rows.
+// A thread walks the sweeps in order; within a sweep the coordinates rise by
+// one per rotation, so the column just rotated into position k + 1 is kept
+// in a register for the next rotation, and the next kRotAhead columns are
+// loaded before they are used (none of them has been written in this sweep).
+constexpr int kRotAhead = 16;
+__global__ __launch_bounds__(kRB) void k_apply_sweeps(double* __restrict__ Zc, int n, int nsweeps,
+                                                     const int* __restrict__ sp, const int* __restrict__ sq,
+                                                     const int64_t* __restrict__ sfirst,
+                                                     const double* __restrict__ rc, const double* __restrict__ rs) {
+  const int i = blockIdx.x * kRB + threadIdx.x;
+  if (i >= n) return;
+  for (int t = 0; t < nsweeps; ++t) {
+    const int p = sp[t], q = sq[t];
+    const double* c = rc + sfirst[t];
+    const double* s = rs + sfirst[t];
+    double u = Zc[(size_t)p * n + i];
+    for (int k0 = p; k0 < q; k0 += kRotAhead) {
+      double v[kRotAhead];
+#pragma unroll
+      for (int r = 0; r < kRotAhead; ++r) v[r] = (k0 + r < q) ? Zc[(size_t)(k0 + r + 1) * n + i] : 0.0;
+#pragma unroll
+      for (int r = 0; r < kRotAhead; ++r) {
+        const int k = k0 + r;
+        if (k >= q) break;
+        const double cc = c[k - p], ss = s[k - p];
+        Zc[(size_t)k * n + i] = cc * u - ss * v[r];
+        u = ss * u + cc * v[r];
+      }
+    }
+    Zc[(size_t)q * n + i] = u;
+  }
+}
+
+// U[i][j] = sign_j Zc[ord[j]][i] (row-major U, the layout the Ritz kernels read).
+__global__ __launch_bounds__(kRB) void k_order_eigvecs(const double* __restrict__ Zc, int n,
+                                                      const int* __restrict__ ord, const double* __restrict__ sign,
+                                                      double* __restrict__ U) {
+  const int64_t t = (int64_t)blockIdx.x * kRB + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t % n);
+  U[t] = sign[j] * Zc[(size_t)ord[j] * n + i];
+}
+
+// Eigenvectors of the recorded sweeps on the device, into d_U (n x n,
+// row-major), sweeps uploaded in chunks of at most kChunk rotations.
+static ppe_status eigvecs_device(int n, const std::vector<double>& a, const QrSweeps& sw, double* d_U,
+                                 hipStream_t st) {
+  constexpr int64_t kChunk = (int64_t)1 << 22;
+  const int64_t nrot = (int64_t)sw.c.size();
+  const int64_t nsw = (int64_t)sw.first.size();
+  double* Zc = (double*)dev_alloc(sizeof(double) * (size_t)n * n);
+  double *d_c = (double*)dev_alloc(sizeof(double) * (size_t)std::min<int64_t>(std::max<int64_t>(nrot, 1), kChunk + n));
+  double *d_s = (double*)dev_alloc(sizeof(double) * (size_t)std::min<int64_t>(std::max<int64_t>(nrot, 1), kChunk + n));
+  int* d_p = (int*)dev_alloc(sizeof(int) * (size_t)std::max<int64_t>(nsw, 1));
+  int* d_q = (int*)dev_alloc(sizeof(int) * (size_t)std::max<int64_t>(nsw, 1));
+  int64_t* d_f = (int64_t*)dev_alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(nsw, 1));
+  int* d_ord = (int*)dev_alloc(sizeof(int) * n);
+  double* d_sg = (double*)dev_alloc(sizeof(double) * n);
+  auto done = [&](ppe_status st_) {
+    dev_free(Zc); dev_free(d_c); dev_free(d_s); dev_free(d_p); dev_free(d_q); dev_free(d_f); dev_free(d_ord);
+    dev_free(d_sg);
+    return st_;
+  };
+  if (!Zc || !d_c || !d_s || !d_p || !d_q || !d_f || !d_ord || !d_sg)
+    return done(set_error(PPE_ERR_HIP, "allocation for the Ritz eigenvectors failed"));
+  // identity
+  {
+    std::vector<double> I((size_t)n * n, 0.0);
+    for (int k = 0; k < n; ++k) I[(size_t)k * n + k] = 1.0;
+    if (hipMemcpyAsync(Zc, I.data(), sizeof(double) * (size_t)n * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return done(set_error(PPE_ERR_HIP, "upload for the Ritz eigenvectors failed"));
+  }
+  std::vector<int64_t> rel(nsw);
+  int64_t t0 = 0;
+  while (t0 < nsw) {
+    // sweeps t0 .. t1-1, at most kChunk rotations (a sweep has at most n - 1)
+    int64_t t1 = t0;
+    const int64_t r0 = sw.first[t0];
+    while (t1 < nsw && (t1 == t0 || (t1 + 1 < nsw ? sw.first[t1 + 1] : nrot) - r0 <= kChunk)) ++t1;
+    const int64_t r1 = t1 < nsw ? sw.first[t1] : nrot;
+    for (int64_t t = t0; t < t1; ++t) rel[t] = sw.first[t] - r0;
+    const size_t nr = (size_t)(r1 - r0), ns = (size_t)(t1 - t0);
+    if (hipMemcpyAsync(d_c, sw.c.data() + r0, sizeof(double) * nr, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d_s, sw.s.data() + r0, sizeof(double) * nr, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d_p, sw.p.data() + t0, sizeof(int) * ns, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d_q, sw.q.data() + t0, sizeof(int) * ns, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d_f, rel.data() + t0, sizeof(int64_t) * ns, hipMemcpyHostToDevice, st) != hipSuccess)
+      return done(set_error(PPE_ERR_HIP, "upload of the QR rotations failed"));
+    k_apply_sweeps<<<blocks_for(n), kRB, 0, st>>>(Zc, n, (int)ns, d_p, d_q, d_f, d_c, d_s);
+    // the host arrays of the next chunk overwrite these buffers
+    if (hipStreamSynchronize(st) != hipSuccess) return done(set_error(PPE_ERR_HIP, "applying the QR rotations failed"));
+    t0 = t1;
+  }
+  // order and signs: the first component of column k is Zc[k][0]
+  std::vector<double> first(n);
+  if (hipMemcpy2DAsync(first.data(), sizeof(double), Zc, sizeof(double) * (size_t)n, sizeof(double), n,
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return done(set_error(PPE_ERR_HIP, "download of the eigenvector signs failed"));
+  const std::vector<int> ord = ascending(a);
+  std::vector<double> sg(n);
+  for (int j = 0; j < n; ++j) sg[j] = first[ord[j]] < 0.0 ? -1.0 : 1.0;
+  if (hipMemcpyAsync(d_ord, ord.data(), sizeof(int) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(d_sg, sg.data(), sizeof(double) * n, hipMemcpyHostToDevice, st) != hipSuccess)
+    return done(set_error(PPE_ERR_HIP, "upload of the eigenvector order failed"));
+  k_order_eigvecs<<<blocks_for((int64_t)n * n), kRB, 0, st>>>(Zc, n, d_ord, d_sg, d_U);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+    return done(set_error(PPE_ERR_HIP, "ordering the Ritz eigenvectors failed"));
+  return done(PPE_OK);
 }
 
 }  // namespace ppe
@@ -244,8 +382,11 @@ extern "C" ppe_status ppe_tridiag_eigh(int32_t n, const double* alpha, const dou
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(a[i]) || (i + 1 < n && !std::isfinite(b[i])))
       return set_error(PPE_ERR_NONFINITE, "non-finite tridiagonal entry");
-  if (!tridiag_qr(n, a, b, Z)) return set_error(PPE_NOT_CONVERGED, "tridiagonal QR did not converge");
-  std::copy(a.begin(), a.end(), theta);
+  QrSweeps sw;
+  if (!tridiag_qr(n, a, b, sw)) return set_error(PPE_NOT_CONVERGED, "tridiagonal QR did not converge");
+  eigvecs_host(n, a, sw, Z);
+  const std::vector<int> ord = ascending(a);
+  for (int j = 0; j < n; ++j) theta[j] = a[ord[j]];
   if (U) std::copy(Z.begin(), Z.end(), U);
   return PPE_OK;
 }
@@ -359,19 +500,25 @@ extern "C" ppe_status ppe_ritz_create(ppe_problem* p, int32_t m, const double* v
   r->m = mk;
   r->alpha.assign(ab.begin(), ab.begin() + mk);
   r->beta.assign(ab.begin() + m, ab.begin() + m + (mk - 1));
-  std::vector<double> a = r->alpha, b = r->beta, Z;
-  if (!tridiag_qr(mk, a, b, Z)) {
+  std::vector<double> a = r->alpha, b = r->beta;
+  QrSweeps sw;
+  if (!tridiag_qr(mk, a, b, sw)) {
     ppe_ritz_destroy(r);
     return set_error(PPE_NOT_CONVERGED, "tridiagonal QR did not converge");
   }
-  r->theta = a;
+  const std::vector<int> ord = ascending(a);
+  r->theta.resize(mk);
+  for (int j = 0; j < mk; ++j) r->theta[j] = a[ord[j]];
   r->d_U = (double*)dev_alloc(sizeof(double) * (size_t)mk * mk);
   if (!r->d_U) {
     ppe_ritz_destroy(r);
     return set_error(PPE_ERR_HIP, "allocation of the Ritz eigenvectors failed");
   }
-  HIPCHK_R(hipMemcpyAsync(r->d_U, Z.data(), sizeof(double) * (size_t)mk * mk, hipMemcpyHostToDevice, s));
-  HIPCHK_R(hipStreamSynchronize(s));
+  const ppe_status est = eigvecs_device(mk, a, sw, r->d_U, s);
+  if (est != PPE_OK) {
+    ppe_ritz_destroy(r);
+    return est;
+  }
   *out = r;
   return PPE_OK;
 }
