@@ -278,9 +278,13 @@ ppe_status ppe_solve_plain(ppe_problem* p, int32_t nb, const float* f, double* x
  * solve of ppe_solve_hybrid (Sec. 2.2, with opts->direction, num_cg and
  * num_dlsm checked as there; the network must fit every grid when the
  * direction is PPE_DIR_NET). The solves' rounds advance in lock step on
- * stream s, one replay of every undecided solve per step, and each solve is
- * bit-identical to the same ppe_solve_hybrid call alone. The network is only
- * read. Statuses as for ppe_solve_plain. */
+ * stream s, and each solve is bit-identical to the same ppe_solve_hybrid
+ * call alone. With PPE_DIR_NET every line-search step runs the network on
+ * all undecided solves as one grouped launch per layer (the forward of
+ * ppe_net_forward_batch), and the phase times of each solve (ms_pcg, ms_net,
+ * ms_dlsm) are those of the whole lock-step batch; other directions replay
+ * each undecided solve's round in turn. The network is only read. Statuses
+ * as for ppe_solve_plain. */
 ppe_status ppe_solve_batch(int32_t n, ppe_problem* const* problems, const ppe_net* net, const float* const* f,
                            double* const* x, const ppe_solve_opts* opts, ppe_solve_stats* stats, hipStream_t s);
 
@@ -310,6 +314,20 @@ ppe_status ppe_net_load(ppe_net* n, const char* path);
  * r: device FP32 [nb][ny][nx]; y: device FP32 [nb][ny][nx]. */
 ppe_status ppe_net_forward(ppe_net* n, ppe_problem* p, int32_t nb, const float* r, float* y,
                            hipStream_t s);
+
+/* The forward on one residual field of each of count grids of any sizes
+ * (Sec. 2.4), every layer as one grouped launch over the grids: each grid's
+ * tiles are work items of the same launch, so small grids share the chip
+ * with large ones instead of running one launch sequence each. y[i] is
+ * bit-identical to ppe_net_forward on problems[i] alone.
+ * problems: host array of count distinct problems (each fitting the
+ * network, else PPE_ERR_SHAPE); r, y: host arrays of count device FP32
+ * pointers [ny_i][nx_i]. Builds the launch tables, enqueues on stream s and
+ * returns after the forwards have finished (the tables are then freed).
+ * Errors: PPE_ERR_INVALID_ARG for a NULL argument, count < 0 or a repeated
+ * problem; PPE_ERR_HIP. count = 0 is a no-op. */
+ppe_status ppe_net_forward_batch(ppe_net* n, int32_t count, ppe_problem* const* problems, const float* const* r,
+                                 float* const* y, hipStream_t s);
 
 /* Fabricated right-hand sides on the device (stand-in for the Lanczos-Ritz
  * vectors of Eqs. 14-16): for sample s of the batch, a Gaussian random field

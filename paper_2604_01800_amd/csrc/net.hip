@@ -428,11 +428,48 @@ static ConvGeo with_static(const NetCache* c, ConvGeo g, int l, const bf16_t* A)
   return g;
 }
 
-// y = NN(r) for nb residual fields of one grid (device FP32 in and out).
-ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float* y, hipStream_t s) {
-  ppe_status st = net_cache_ensure(p, n, nb, s);
-  if (st != PPE_OK) return st;
-  NetCache* c = p->net_cache;
+// One launch of the forward on one grid: what the launch over nb samples of
+// the grid, or a grouped launch over grids, needs.
+struct FwdOp {
+  enum Kind { PACK, POOL, CONV, OUT } kind = PACK;
+  // PACK: channel 0 of the level-0 input from r (pitch, bstride)
+  const float* r = nullptr;
+  int64_t n = 0;
+  double* part = nullptr;
+  bf16_t* xin = nullptr;
+  int pitch = 0;
+  int64_t bstride = 0;
+  // POOL: Ho x Wo pixels of C channels
+  int Ho = 0, Wo = 0, C = 0, pin = 0, cin_off = 0, pout = 0;
+  const bf16_t* in = nullptr;
+  bf16_t* out = nullptr;
+  int64_t in_bs = 0, out_bs = 0;
+  // CONV
+  int taps = 9;
+  bool up = false;
+  ConvGeo g{};
+  const bf16_t* x = nullptr;
+  const bf16_t* eta = nullptr;
+  const bf16_t* wp = nullptr;
+  int Kp = 0;
+  const float* bias = nullptr;
+  bf16_t* y = nullptr;
+  float* kpart = nullptr;
+  int64_t kpart_elems = 0;
+  // OUT
+  int c0 = 0, fold_pitch = 0;
+  const bf16_t* d0 = nullptr;
+  int64_t d_bs = 0;
+  const float* fold = nullptr;
+  const float* gamma = nullptr;
+  float* yout = nullptr;
+};
+
+// The forward's launches for the grid of cache c, in order: input scaling,
+// per encoder level (pooling,) two Mesh-Convs, per decoder level the 1x1
+// up-convolution and two Mesh-Convs, then the DeepONet output.
+static void forward_ops(const ppe_problem* p, const ppe_net* n, const NetCache* c, const float* r, float* y,
+                        std::vector<FwdOp>& ops) {
   const ppe_net_config& cfg = n->cfg;
   const int L = cfg.levels;
   const int64_t N = (int64_t)p->nx * p->ny;
@@ -440,27 +477,61 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
   const bf16_t* E = c->d_eta;
   auto ch = [&](int l) { return cfg.base_channels << l; };
   auto eta = [&](int64_t off) -> const bf16_t* { return cfg.use_eta ? E + off : nullptr; };
-  launch_input_pack(r, N, nb, c->d_part, A + c->o_in[0], c->p_in[0], N * c->p_in[0], s);
+  ops.clear();
+  FwdOp pk;
+  pk.kind = FwdOp::PACK;
+  pk.r = r;
+  pk.n = N;
+  pk.part = c->d_part;
+  pk.xin = A + c->o_in[0];
+  pk.pitch = c->p_in[0];
+  pk.bstride = N * c->p_in[0];
+  ops.push_back(pk);
+  auto conv = [&](int taps, bool up, const ConvGeo& g, const bf16_t* x, const bf16_t* e, const bf16_t* wp, int Kp,
+                  const float* bias, bf16_t* yo) {
+    FwdOp o;
+    o.kind = FwdOp::CONV;
+    o.taps = taps;
+    o.up = up;
+    o.g = g;
+    o.x = x;
+    o.eta = e;
+    o.wp = wp;
+    o.Kp = Kp;
+    o.bias = bias;
+    o.y = yo;
+    o.kpart = c->d_kpart;
+    o.kpart_elems = c->kpart_elems;
+    ops.push_back(o);
+  };
   for (int l = 0; l < L; ++l) {
     const int64_t hw = (int64_t)c->H[l] * c->W[l];
     if (l > 0) {
       // E_{l-1} lives in the decoder concat buffer of level l-1 at channel C_{l-1}
-      const int pc = c->p_cat[l - 1];
-      launch_pool2(c->H[l], c->W[l], ch(l - 1), A + c->o_cat[l - 1], pc, ch(l - 1), 4 * hw * pc, A + c->o_in[l],
-                   c->p_in[l], hw * c->p_in[l], nb, s);
+      FwdOp o;
+      o.kind = FwdOp::POOL;
+      o.Ho = c->H[l];
+      o.Wo = c->W[l];
+      o.C = ch(l - 1);
+      o.in = A + c->o_cat[l - 1];
+      o.pin = c->p_cat[l - 1];
+      o.cin_off = ch(l - 1);
+      o.in_bs = 4 * hw * o.pin;
+      o.out = A + c->o_in[l];
+      o.pout = c->p_in[l];
+      o.out_bs = hw * c->p_in[l];
+      ops.push_back(o);
     }
     const MConvL& ma = n->enc_a[l];
     const MConvL& mb = n->enc_b[l];
-    launch_conv(9, false, with_static(c, geo(c, l, ma.cin8, ma.cout, ch(l), 0, 1, c->p_in[l]), l, A), nb,
-                A + c->o_in[l], eta(c->eta_a[l]), n->d_pack + ma.opack, ma.kp, n->d_w + ma.ob, A + c->o_a[l], s,
-                c->d_kpart, c->kpart_elems);
-    if (l < L - 1) {
-      launch_conv(9, false, geo(c, l, mb.cin8, mb.cout, c->p_cat[l], ch(l), 1), nb, A + c->o_a[l], eta(c->eta_b[l]),
-                  n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob, A + c->o_cat[l], s, c->d_kpart, c->kpart_elems);
-    } else {
-      launch_conv(9, false, geo(c, l, mb.cin8, mb.cout, ch(l), 0, 1), nb, A + c->o_a[l], eta(c->eta_b[l]),
-                  n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob, A + c->o_bot, s, c->d_kpart, c->kpart_elems);
-    }
+    conv(9, false, with_static(c, geo(c, l, ma.cin8, ma.cout, ch(l), 0, 1, c->p_in[l]), l, A), A + c->o_in[l],
+         eta(c->eta_a[l]), n->d_pack + ma.opack, ma.kp, n->d_w + ma.ob, A + c->o_a[l]);
+    if (l < L - 1)
+      conv(9, false, geo(c, l, mb.cin8, mb.cout, c->p_cat[l], ch(l), 1), A + c->o_a[l], eta(c->eta_b[l]),
+           n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob, A + c->o_cat[l]);
+    else
+      conv(9, false, geo(c, l, mb.cin8, mb.cout, ch(l), 0, 1), A + c->o_a[l], eta(c->eta_b[l]), n->d_pack + mb.opack,
+           mb.kp, n->d_w + mb.ob, A + c->o_bot);
   }
   for (int l = L - 2; l >= 0; --l) {
     const UpL& u = n->up[l];
@@ -468,17 +539,161 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
     ConvGeo gu = geo(c, l + 1, u.cin, u.cout, c->p_cat[l], 0, 1);
     gu.y_bstride = (int64_t)c->H[l] * c->W[l] * c->p_cat[l];
     gu.act = 0;
-    launch_conv(1, true, gu, nb, src, nullptr, n->d_pack + u.opack, u.kp, n->d_w + u.ob, A + c->o_cat[l], s, c->d_kpart, c->kpart_elems);
+    conv(1, true, gu, src, nullptr, n->d_pack + u.opack, u.kp, n->d_w + u.ob, A + c->o_cat[l]);
     const MConvL& mc = n->dec_c[l];
     const MConvL& md = n->dec_d[l];
-    launch_conv(9, false, with_static(c, geo(c, l, mc.cin8, mc.cout, ch(l), 0, 1, c->p_cat[l]), l, A), nb,
-                A + c->o_cat[l], eta(c->eta_c[l]), n->d_pack + mc.opack, mc.kp, n->d_w + mc.ob, A + c->o_c[l], s,
-                c->d_kpart, c->kpart_elems);
-    launch_conv(9, false, geo(c, l, md.cin8, md.cout, ch(l), 0, 1), nb, A + c->o_c[l], eta(c->eta_d[l]),
-                n->d_pack + md.opack, md.kp, n->d_w + md.ob, A + c->o_d[l], s, c->d_kpart, c->kpart_elems);
+    conv(9, false, with_static(c, geo(c, l, mc.cin8, mc.cout, ch(l), 0, 1, c->p_cat[l]), l, A), A + c->o_cat[l],
+         eta(c->eta_c[l]), n->d_pack + mc.opack, mc.kp, n->d_w + mc.ob, A + c->o_c[l]);
+    conv(9, false, geo(c, l, md.cin8, md.cout, ch(l), 0, 1), A + c->o_c[l], eta(c->eta_d[l]), n->d_pack + md.opack,
+         md.kp, n->d_w + md.ob, A + c->o_d[l]);
   }
-  launch_deeponet_out(N, cfg.base_channels, A + c->o_d[0], N * cfg.base_channels, c->d_fold, c->fold_pitch,
-                      n->d_w + n->o_gamma, y, nb, s);
+  FwdOp o;
+  o.kind = FwdOp::OUT;
+  o.n = N;
+  o.c0 = cfg.base_channels;
+  o.d0 = A + c->o_d[0];
+  o.d_bs = N * cfg.base_channels;
+  o.fold = c->d_fold;
+  o.fold_pitch = c->fold_pitch;
+  o.gamma = n->d_w + n->o_gamma;
+  o.yout = y;
+  ops.push_back(o);
+}
+
+// y = NN(r) for nb residual fields of one grid (device FP32 in and out).
+ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float* y, hipStream_t s) {
+  ppe_status st = net_cache_ensure(p, n, nb, s);
+  if (st != PPE_OK) return st;
+  std::vector<FwdOp> ops;
+  forward_ops(p, n, p->net_cache, r, y, ops);
+  for (const FwdOp& o : ops) {
+    switch (o.kind) {
+      case FwdOp::PACK: launch_input_pack(o.r, o.n, nb, o.part, o.xin, o.pitch, o.bstride, s); break;
+      case FwdOp::POOL:
+        launch_pool2(o.Ho, o.Wo, o.C, o.in, o.pin, o.cin_off, o.in_bs, o.out, o.pout, o.out_bs, nb, s);
+        break;
+      case FwdOp::CONV:
+        launch_conv(o.taps, o.up, o.g, nb, o.x, o.eta, o.wp, o.Kp, o.bias, o.y, s, o.kpart, o.kpart_elems);
+        break;
+      case FwdOp::OUT: launch_deeponet_out(o.n, o.c0, o.d0, o.d_bs, o.fold, o.fold_pitch, o.gamma, o.yout, nb, s); break;
+    }
+  }
+  HIPCHK(hipGetLastError());
+  return PPE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Grouped forward over several grids (one residual field each): the same
+// launches as net_forward on each grid, each layer as one launch over all
+// grids. The member tables of every layer live in one device block.
+
+void net_group_free(NetGroup& G) {
+  if (G.d_tab) (void)hipFree(G.d_tab);
+  G = NetGroup{};
+}
+
+ppe_status net_group_build(int n, ppe_problem* const* probs, ppe_net* net, const float* const* r, float* const* y,
+                           const int32_t* const* skip, hipStream_t s, NetGroup& G) {
+  net_group_free(G);
+  if (n < 1) return set_error(PPE_ERR_INVALID_ARG, "empty group");
+  std::vector<std::vector<FwdOp>> ops(n);
+  for (int i = 0; i < n; ++i) {
+    ppe_status st = net_cache_ensure(probs[i], net, 1, s);
+    if (st != PPE_OK) return st;
+    forward_ops(probs[i], net, probs[i]->net_cache, r[i], y[i], ops[i]);
+    if (ops[i].size() != ops[0].size()) return set_error(PPE_ERR_UNSUPPORTED, "group members with different layers");
+  }
+  const size_t nops = ops[0].size();
+  std::vector<char> blob;
+  auto append = [&](const void* src, size_t bytes) {
+    const size_t o = (blob.size() + 255) / 256 * 256;
+    blob.resize(o + bytes);
+    std::memcpy(blob.data() + o, src, bytes);
+    return (int64_t)o;
+  };
+  G.n = n;
+  G.ops.resize(nops);
+  for (size_t k = 0; k < nops; ++k) {
+    const FwdOp& o0 = ops[0][k];
+    GroupOp& q = G.ops[k];
+    q.kind = o0.kind;
+    switch (o0.kind) {
+      case FwdOp::PACK: {
+        std::vector<PackMember> m(n);
+        for (int i = 0; i < n; ++i) {
+          const FwdOp& o = ops[i][k];
+          m[i] = PackMember{o.r, o.n, o.part, o.xin, skip ? skip[i] : nullptr};
+        }
+        q.a = o0.pitch;
+        q.off = append(m.data(), m.size() * sizeof(PackMember));
+        break;
+      }
+      case FwdOp::POOL: {
+        std::vector<PoolMember> m(n);
+        for (int i = 0; i < n; ++i) {
+          const FwdOp& o = ops[i][k];
+          m[i] = PoolMember{o.Ho, o.Wo, o.in, o.out, skip ? skip[i] : nullptr};
+          q.maxn = std::max<int64_t>(q.maxn, (int64_t)o.Ho * o.Wo);
+        }
+        q.a = o0.C;
+        q.b = o0.pin;
+        q.c = o0.cin_off;
+        q.d = o0.pout;
+        q.off = append(m.data(), m.size() * sizeof(PoolMember));
+        break;
+      }
+      case FwdOp::CONV: {
+        std::vector<ConvMember> m(n);
+        for (int i = 0; i < n; ++i) {
+          const FwdOp& o = ops[i][k];
+          m[i] = ConvMember{};
+          m[i].g = o.g;
+          m[i].x = o.x;
+          m[i].eta = o.eta;
+          m[i].y = o.y;
+          m[i].kpart = o.kpart;
+          m[i].skip = skip ? skip[i] : nullptr;
+        }
+        if (!plan_conv_group(o0.taps, o0.up, m, o0.kpart_elems, q.conv))
+          return set_error(PPE_ERR_UNSUPPORTED, "layer %zu has no grouped form", k);
+        q.wp = o0.wp;
+        q.Kp = o0.Kp;
+        q.bias = o0.bias;
+        q.off = append(m.data(), m.size() * sizeof(ConvMember));
+        break;
+      }
+      case FwdOp::OUT: {
+        std::vector<OutMember> m(n);
+        for (int i = 0; i < n; ++i) {
+          const FwdOp& o = ops[i][k];
+          m[i] = OutMember{o.n, o.d0, o.fold, o.yout, skip ? skip[i] : nullptr};
+          q.maxn = std::max<int64_t>(q.maxn, o.n);
+        }
+        q.a = o0.c0;
+        q.b = o0.fold_pitch;
+        q.gamma = o0.gamma;
+        q.off = append(m.data(), m.size() * sizeof(OutMember));
+        break;
+      }
+    }
+  }
+  G.d_tab = (char*)dev_alloc(blob.size());
+  if (!G.d_tab) return set_error(PPE_ERR_HIP, "allocation of the group tables failed");
+  G.h_tab = std::move(blob);
+  HIPCHK(hipMemcpyAsync(G.d_tab, G.h_tab.data(), G.h_tab.size(), hipMemcpyHostToDevice, s));
+  return PPE_OK;
+}
+
+ppe_status net_group_forward(const NetGroup& G, hipStream_t s) {
+  for (const GroupOp& q : G.ops) {
+    const void* t = G.d_tab + q.off;
+    switch (q.kind) {
+      case FwdOp::PACK: launch_input_pack_group((const PackMember*)t, G.n, q.a, s); break;
+      case FwdOp::POOL: launch_pool2_group((const PoolMember*)t, G.n, q.maxn, q.a, q.b, q.c, q.d, s); break;
+      case FwdOp::CONV: launch_conv_group(q.conv, (const ConvMember*)t, q.wp, q.Kp, q.bias, s); break;
+      case FwdOp::OUT: launch_deeponet_out_group((const OutMember*)t, G.n, q.maxn, q.a, q.b, q.gamma, s); break;
+    }
+  }
   HIPCHK(hipGetLastError());
   return PPE_OK;
 }
@@ -619,6 +834,28 @@ ppe_status ppe_net_load(ppe_net* n, const char* path) {
   HIPCHK(hipMemcpy(n->d_m, m.data(), np * 4, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(n->d_v, v.data(), np * 4, hipMemcpyHostToDevice));
   n->step = step;
+  return PPE_OK;
+}
+
+ppe_status ppe_net_forward_batch(ppe_net* n, int32_t count, ppe_problem* const* problems, const float* const* r,
+                                 float* const* y, hipStream_t s) {
+  if (!n || count < 0 || (count > 0 && (!problems || !r || !y)))
+    return set_error(PPE_ERR_INVALID_ARG, "NULL argument or negative count");
+  for (int i = 0; i < count; ++i) {
+    if (!problems[i] || !r[i] || !y[i]) return set_error(PPE_ERR_INVALID_ARG, "NULL entry %d", i);
+    for (int j = 0; j < i; ++j)
+      if (problems[j] == problems[i]) return set_error(PPE_ERR_INVALID_ARG, "problem %d repeated", i);
+    const ppe_status st = check_net_grid(problems[i], n);
+    if (st != PPE_OK) return st;
+  }
+  if (count == 0) return PPE_OK;
+  NetGroup G;
+  ppe_status st = net_group_build(count, problems, n, r, y, nullptr, s, G);
+  if (st == PPE_OK) st = net_group_forward(G, s);
+  const hipError_t e = hipStreamSynchronize(s);  // the tables are in use until the launches end
+  net_group_free(G);
+  if (st != PPE_OK) return st;
+  if (e != hipSuccess) return set_error(PPE_ERR_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
   return PPE_OK;
 }
 

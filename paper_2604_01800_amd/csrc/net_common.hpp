@@ -60,6 +60,43 @@ struct ConvGeo {
   int eta_node;     // 1: eta holds one weight per pixel ([H][W]), else one per input channel (pitch cin8)
 };
 
+// Grouped launches: one layer of the forwards of several grids (one sample
+// each) in one launch. Each grid is a member with its own geometry and
+// buffers; `skip` points at the member's solve-decided flag (nonzero: the
+// member's workgroups return at once), or is null.
+struct ConvMember {
+  ConvGeo g;
+  const bf16_t* x;
+  const bf16_t* eta;
+  bf16_t* y;
+  float* kpart;         // room for the member's K-split partial sums
+  const int32_t* skip;
+  int wg0;              // first workgroup of the member along x
+  int nwt;              // workgroups per K share (runs of tiles)
+  int ks;               // K shares: the split the member's own launch uses
+  int pad_;
+};
+struct PackMember {     // input scaling (sum of squares, then the packed input)
+  const float* r;
+  int64_t n;
+  double* part;
+  bf16_t* xin;
+  const int32_t* skip;
+};
+struct PoolMember {     // 2x2 pooling into a level
+  int Ho, Wo;
+  const bf16_t* in;
+  bf16_t* out;
+  const int32_t* skip;
+};
+struct OutMember {      // DeepONet output
+  int64_t npix;
+  const bf16_t* d0;
+  const float* fold;
+  float* y;
+  const int32_t* skip;
+};
+
 // Number of 32-wide MFMA K-steps of an input-channel chunk of ck channels
 // for a kernel with `taps` taps (taps x ck/8 eight-channel groups, rounded up
 // to groups of four).

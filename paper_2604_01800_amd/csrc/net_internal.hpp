@@ -5,6 +5,7 @@
 
 #include "../../include/ppe.h"
 #include "net_common.hpp"
+#include "net_kernels.hpp"
 
 namespace ppe {
 
@@ -68,9 +69,38 @@ struct NetCache {
   int64_t kpart_elems = 0;
 };
 
+// One layer of a grouped forward: its member table (at d_tab + off) and the
+// launch parameters the members share.
+struct GroupOp {
+  int kind = 0;            // input scaling, pooling, convolution, output (the forward's order)
+  int64_t off = 0;
+  int a = 0, b = 0, c = 0, d = 0;  // shared channel counts and pitches
+  int64_t maxn = 0;        // largest member's pixels (pooling, output)
+  ConvGroupLaunch conv{};
+  const bf16_t* wp = nullptr;
+  int Kp = 0;
+  const float* bias = nullptr;
+  const float* gamma = nullptr;
+};
+
+// The forwards of several grids (one field each) as one launch per layer.
+struct NetGroup {
+  int n = 0;
+  std::vector<GroupOp> ops;
+  char* d_tab = nullptr;
+  std::vector<char> h_tab;  // host copy of the tables (source of the upload)
+};
+
 void net_cache_free(NetCache* c);
 ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s);
 ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float* y, hipStream_t s);
+// Builds the group of problems[0..n) (distinct, each with one field r[i] ->
+// y[i]; skip[i] = a flag whose nonzero value makes member i's launches return
+// at once, or skip = null) on stream s; the member tables are uploaded on s.
+ppe_status net_group_build(int n, ppe_problem* const* probs, ppe_net* net, const float* const* r, float* const* y,
+                           const int32_t* const* skip, hipStream_t s, NetGroup& G);
+ppe_status net_group_forward(const NetGroup& G, hipStream_t s);
+void net_group_free(NetGroup& G);
 ppe_status net_refresh(ppe_net* n, hipStream_t s);
 ppe_status check_net_grid(const ppe_problem* p, const ppe_net* n);
 // Hybrid solves of a mixed-size batch (one solve per problem, problems

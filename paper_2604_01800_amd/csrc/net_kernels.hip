@@ -2,6 +2,8 @@
 // grid-derived constants of the DeepONet (local weights eta, trunk basis),
 // pooling, input scaling and the DeepONet output (Sec. 2.4, Eqs. 17-18).
 #include <algorithm>
+#include <type_traits>
+#include <vector>
 
 #include "common.hpp"
 #include "net_common.hpp"
@@ -295,22 +297,56 @@ __device__ __forceinline__ void conv_mfma(f32x4_t (&acc)[TN / 16][4], const bf16
 
 // WSTAT: the workgroup has one input-channel chunk, so its weight slice is
 // staged once, before its first tile.
-template <int TN, int TAPS, bool UP, int ETA, bool WSTAT>
+//
+// GRP: a grouped launch over the forwards of several grids. The geometry,
+// buffers and K split of each grid come from the member table `mem` (nmem
+// entries ordered by their first workgroup along x); a workgroup finds its
+// member, returns at once when the member's solve has decided, and then does
+// exactly the work of the same tile run in the member's own launch.
+template <int TN, int TAPS, bool UP, int ETA, bool WSTAT, bool GRP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv(
     ConvGeo g, const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta, const bf16_t* __restrict__ wp, int Kp,
-    const float* __restrict__ bias, bf16_t* __restrict__ y, int tiles_per_wg, float* __restrict__ kpart, int ksplit) {
+    const float* __restrict__ bias, bf16_t* __restrict__ y, int tiles_per_wg, float* __restrict__ kpart, int ksplit,
+    const ConvMember* __restrict__ mem, int nmem) {
   using S = ConvShape<TN, TAPS>;
   constexpr int MT = TN / 16, NT = 4;
   __shared__ __attribute__((aligned(16))) bf16_t s_x[S::NPIX * S::CKP];
   __shared__ __attribute__((aligned(16))) bf16_t s_w[TN * S::WKP];
   __shared__ __attribute__((aligned(16))) float s_b[TN];
 
+  int t0, smp, ksp, nbs;  // first tile, sample, K share, samples of the launch
+  if constexpr (GRP) {
+    int lo = 0, hi = nmem - 1;  // the last member whose first workgroup is <= blockIdx.x
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (mem[mid].wg0 <= (int)blockIdx.x) lo = mid;
+      else hi = mid - 1;
+    }
+    const ConvMember& M = mem[lo];
+    // a uniform branch (the flag's value taken from the first lane), so that
+    // the member's fields stay in scalar registers
+    if (M.skip && __builtin_amdgcn_readfirstlane(*M.skip) != 0) return;
+    g = M.g;
+    x = M.x;
+    eta = M.eta;
+    y = M.y;
+    kpart = M.kpart;
+    ksplit = M.ks;
+    const int local = (int)blockIdx.x - M.wg0;
+    ksp = local / M.nwt;
+    t0 = (local - ksp * M.nwt) * tiles_per_wg;
+    smp = 0;
+    nbs = 1;
+  } else {
+    t0 = blockIdx.x * tiles_per_wg;
+    smp = blockIdx.z / ksplit;
+    ksp = blockIdx.z - smp * ksplit;
+    nbs = gridDim.z / ksplit;
+  }
   const int tiles_x = (g.W + kCTW - 1) / kCTW;
   const int tiles = tiles_x * ((g.H + kCTH - 1) / kCTH);
-  const int t0 = blockIdx.x * tiles_per_wg;
   const int nt_wg = min(tiles_per_wg, tiles - t0);
   const int co0 = blockIdx.y * TN;
-  const int smp = blockIdx.z / ksplit, ksp = blockIdx.z - smp * ksplit;
   x += smp * g.x_bstride;
   y += smp * g.y_bstride;
   if (ETA != kEtaNone) eta += smp * g.e_bstride;
@@ -392,7 +428,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (ksplit > 1) {
       // partial sums of this share of K, [ksplit][sample][pixel][gridDim.y * TN] FP32
       const int cp = gridDim.y * TN;
-      const int nbs = gridDim.z / ksplit;  // samples
       float* pp = kpart + ((int64_t)ksp * nbs + smp) * g.H * g.W * cp;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
@@ -454,14 +489,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // activation and the BF16 store of the unsplit epilogue (UP: to the 2 x 2
 // finer pixels). One thread per (pixel, 4 output channels); cp = channel pitch
 // of the partials.
-template <bool UP>
+// GRP: blockIdx.y is the member of a grouped launch (members without a split
+// or whose solve has decided return).
+template <bool UP, bool GRP>
 __global__ __launch_bounds__(256) void k_conv_ksum(ConvGeo g, int nb, int ksplit, int cp,
                                                    const float* __restrict__ kpart, const float* __restrict__ bias,
-                                                   bf16_t* __restrict__ y) {
+                                                   bf16_t* __restrict__ y, const ConvMember* __restrict__ mem) {
+  int smp = blockIdx.y;
+  if constexpr (GRP) {
+    const ConvMember& M = mem[blockIdx.y];
+    if (M.ks < 2 || (M.skip && *M.skip != 0)) return;
+    g = M.g;
+    nb = 1;
+    ksplit = M.ks;
+    kpart = M.kpart;
+    y = M.y;
+    smp = 0;
+  }
   const int q4 = g.cout / 4;
   const int64_t hw = (int64_t)g.H * g.W;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int smp = blockIdx.y;
   if (i >= hw * q4) return;
   const int64_t p = i / q4;
   const int co = (int)(i - p * q4) * 4;
@@ -756,25 +803,47 @@ __global__ void k_fill_static(int H, int W, int pitch, int coff, const float* __
 }
 
 // Partial sums of r^2 per workgroup (fixed grid of kRedBlocks per sample).
-__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ r, int64_t n, double* __restrict__ part) {
+template <bool GRP>
+__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ r, int64_t n, double* __restrict__ part,
+                                               const PackMember* __restrict__ mem) {
   __shared__ double lds[kWaves];
-  const float* rs = r + (int64_t)blockIdx.y * n;
+  int smp = blockIdx.y;
+  if constexpr (GRP) {
+    const PackMember& M = mem[blockIdx.y];
+    if (M.skip && *M.skip != 0) return;
+    r = M.r;
+    n = M.n;
+    part = M.part;
+    smp = 0;
+  }
+  const float* rs = r + (int64_t)smp * n;
   double s = 0.0;
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
     const double v = rs[k];
     s += v * v;
   }
   s = block_sum(s, lds);
-  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+  if (threadIdx.x == 0) part[smp * gridDim.x + blockIdx.x] = s;
 }
 
 // Channel 0 of the level-0 input: r * sqrt(N) / ||r|| in BF16 (0 for r = 0).
 // ||r||^2 comes from the kRedBlocks partials of k_sumsq, reduced in the same
 // order by every workgroup.
+template <bool GRP>
 __global__ __launch_bounds__(256) void k_input_pack(const float* __restrict__ r, int64_t n, const double* __restrict__ part,
-                                                    int nparts, bf16_t* __restrict__ xin, int pitch, int64_t bstride) {
+                                                    int nparts, bf16_t* __restrict__ xin, int pitch, int64_t bstride,
+                                                    const PackMember* __restrict__ mem) {
   __shared__ double lds[kWaves];
-  const int smp = blockIdx.y;
+  int smp = blockIdx.y;
+  if constexpr (GRP) {
+    const PackMember& M = mem[blockIdx.y];
+    if (M.skip && *M.skip != 0) return;
+    r = M.r;
+    n = M.n;
+    part = M.part;
+    xin = M.xin;
+    smp = 0;
+  }
   const double rr = reduce_partials(part + (int64_t)smp * nparts, nparts, lds);
   const float scale = rr > 0.0 ? (float)(sqrt((double)n) / sqrt(rr)) : 0.f;
   const float* rs = r + (int64_t)smp * n;
@@ -785,8 +854,19 @@ __global__ __launch_bounds__(256) void k_input_pack(const float* __restrict__ r,
 
 // 2x2 average pooling of C channels (8 per thread) from a buffer of pitch
 // pin at channel offset cin_off into a buffer of pitch pout (channel 0 on).
+template <bool GRP>
 __global__ void k_pool2(int Ho, int Wo, int C, const bf16_t* __restrict__ in, int pin, int cin_off, int64_t in_bs,
-                        bf16_t* __restrict__ out, int pout, int64_t out_bs) {
+                        bf16_t* __restrict__ out, int pout, int64_t out_bs, const PoolMember* __restrict__ mem) {
+  int smp = blockIdx.y;
+  if constexpr (GRP) {
+    const PoolMember& M = mem[blockIdx.y];
+    if (M.skip && *M.skip != 0) return;
+    Ho = M.Ho;
+    Wo = M.Wo;
+    in = M.in;
+    out = M.out;
+    smp = 0;
+  }
   const int c8n = C / 8;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)Ho * Wo * c8n) return;
@@ -794,7 +874,7 @@ __global__ void k_pool2(int Ho, int Wo, int C, const bf16_t* __restrict__ in, in
   const int64_t p = idx / c8n;
   const int yo = (int)(p / Wo), xo = (int)(p - (int64_t)yo * Wo);
   const int Wi = 2 * Wo;
-  const bf16_t* ib = in + blockIdx.y * in_bs + cin_off + c8 * 8;
+  const bf16_t* ib = in + smp * in_bs + cin_off + c8 * 8;
   float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -811,19 +891,29 @@ __global__ void k_pool2(int Ho, int Wo, int C, const bf16_t* __restrict__ in, in
   uint32_t o[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) o[q] = (uint32_t)f2bf(0.25f * s[2 * q]) | ((uint32_t)f2bf(0.25f * s[2 * q + 1]) << 16);
-  *(uint4*)(out + blockIdx.y * out_bs + p * pout + c8 * 8) = make_uint4(o[0], o[1], o[2], o[3]);
+  *(uint4*)(out + smp * out_bs + p * pout + c8 * 8) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // DeepONet output y = gamma * (D0 . fold[p][0:C0] + fold[p][C0]) in FP32.
 // Eight lanes per pixel, lane l taking channels 4l + 32k, so that a pixel's
 // D0 and fold rows are read contiguously (fold rows are padded to a multiple
 // of 4 floats); the eight partial sums are added with lane shuffles.
+template <bool GRP>
 __global__ void k_deeponet_out(int64_t npix, int c0, const bf16_t* __restrict__ d0, int64_t d_bs,
                                const float* __restrict__ fold, int fold_pitch, const float* __restrict__ gamma,
-                               float* __restrict__ y) {
+                               float* __restrict__ y, const OutMember* __restrict__ mem) {
+  int smp = blockIdx.y;
+  if constexpr (GRP) {
+    const OutMember& M = mem[blockIdx.y];
+    if (M.skip && *M.skip != 0) return;
+    npix = M.npix;
+    d0 = M.d0;
+    fold = M.fold;
+    y = M.y;
+    smp = 0;
+  }
   const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const int l = threadIdx.x & 7;
-  const int smp = blockIdx.y;
   float s = 0.f;
   if (p < npix) {
     const bf16_t* d = d0 + smp * d_bs + p * c0;
@@ -864,12 +954,12 @@ int64_t conv_kpart_elems() { return (int64_t)2 * conv_device_cus() * kCTH * kCTW
 
 // Resident workgroups per CU of a convolution kernel (registers and LDS),
 // queried once per instantiation.
-template <int TN, int TAPS, bool UP, int ETA, bool WSTAT>
+template <int TN, int TAPS, bool UP, int ETA, bool WSTAT, bool GRP>
 static int conv_per_cu() {
   static int per_cu = 0;
   if (per_cu == 0) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv<TN, TAPS, UP, ETA, WSTAT>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv<TN, TAPS, UP, ETA, WSTAT, GRP>, 256, 0) != hipSuccess ||
         n < 1)
       n = 1;
     per_cu = n;
@@ -877,39 +967,155 @@ static int conv_per_cu() {
   return per_cu;
 }
 
-template <int TN, int TAPS, bool UP, int ETA>
-static void conv_go_eta(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp, int Kp,
-                        const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems) {
-  const int tiles = ((g.W + kCTW - 1) / kCTW) * ((g.H + kCTH - 1) / kCTH);
+static int conv_tiles(const ConvGeo& g) { return ((g.W + kCTW - 1) / kCTW) * ((g.H + kCTH - 1) / kCTH); }
+
+// K shares of a layer's launch over nb samples. Layers with fewer workgroups
+// than compute units (the coarse levels of small grids) split their chunks of
+// input channels over up to ceil(cus / workgroups) workgroups, when the
+// caller gave room for the partials. A grouped launch applies the same rule
+// to each member alone, so that a member's sums are those of its own launch.
+template <int TN, int TAPS>
+static int conv_ksplit(const ConvGeo& g, int nb, bool have_kpart, int64_t kpart_elems) {
   const int cot = (g.cout + TN - 1) / TN;
   const int cus = conv_device_cus();
-  const int64_t wgs = (int64_t)tiles * cot * nb;
-  // Layers with fewer workgroups than compute units (the coarse levels of
-  // small grids) split their chunks of input channels over up to
-  // ceil(cus / wgs) workgroups, when the caller gave room for the partials.
+  const int64_t wgs = (int64_t)conv_tiles(g) * cot * nb;
   const int nch = (g.cin8 + ConvShape<TN, TAPS>::CK - 1) / ConvShape<TN, TAPS>::CK;
   int ks = 1;
-  if (kpart && wgs < cus && nch > 1 && g.cout % 4 == 0) {
+  if (have_kpart && wgs < cus && nch > 1 && g.cout % 4 == 0) {
     ks = (int)std::min<int64_t>(nch, (cus + wgs - 1) / wgs);
     const int cps = (nch + ks - 1) / ks;
     ks = (nch + cps - 1) / cps;  // no empty shares
     if ((int64_t)ks * nb * g.H * g.W * cot * TN > kpart_elems) ks = 1;
   }
+  return ks;
+}
+
+template <int TN, int TAPS, bool UP, int ETA>
+static void conv_go_eta(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp, int Kp,
+                        const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems) {
+  const int tiles = conv_tiles(g);
+  const int cot = (g.cout + TN - 1) / TN;
+  const int cus = conv_device_cus();
+  const int64_t wgs = (int64_t)tiles * cot * nb;
+  const int nch = (g.cin8 + ConvShape<TN, TAPS>::CK - 1) / ConvShape<TN, TAPS>::CK;
+  const int ks = conv_ksplit<TN, TAPS>(g, nb, kpart != nullptr, kpart_elems);
   // one chunk per workgroup: the weight slice is staged once
   const bool wstat = (nch + ks - 1) / ks == 1;
   // runs of tiles that fill the resident workgroups once
-  const int per_cu = wstat ? conv_per_cu<TN, TAPS, UP, ETA, true>() : conv_per_cu<TN, TAPS, UP, ETA, false>();
+  const int per_cu =
+      wstat ? conv_per_cu<TN, TAPS, UP, ETA, true, false>() : conv_per_cu<TN, TAPS, UP, ETA, false, false>();
   const int64_t slots = (int64_t)cus * per_cu;
   const int run = (int)std::max<int64_t>(1, (wgs + slots - 1) / slots);
   const dim3 grid((tiles + run - 1) / run, cot, nb * ks);
   if (wstat)
-    k_conv<TN, TAPS, UP, ETA, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks);
+    k_conv<TN, TAPS, UP, ETA, true, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks, nullptr, 0);
   else
-    k_conv<TN, TAPS, UP, ETA, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks);
+    k_conv<TN, TAPS, UP, ETA, false, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks, nullptr, 0);
   if (ks > 1) {
     const int64_t n = (int64_t)g.H * g.W * (g.cout / 4);
-    k_conv_ksum<UP><<<dim3((unsigned)((n + 255) / 256), nb), 256, 0, s>>>(g, nb, ks, cot * TN, kpart, bias, y);
+    k_conv_ksum<UP, false><<<dim3((unsigned)((n + 255) / 256), nb), 256, 0, s>>>(g, nb, ks, cot * TN, kpart, bias, y,
+                                                                                 nullptr);
   }
+}
+
+// Grouped convolution: the members' K splits and runs of tiles, one launch
+// shape for all of them (runs of tiles that fill the resident workgroups once
+// over the whole group).
+template <int TN, int TAPS, bool UP, int ETA>
+static void conv_group_plan_t(std::vector<ConvMember>& m, int64_t kpart_elems, ConvGroupLaunch& L) {
+  const ConvGeo& g0 = m[0].g;
+  const int cot = (g0.cout + TN - 1) / TN;
+  const int nch = (g0.cin8 + ConvShape<TN, TAPS>::CK - 1) / ConvShape<TN, TAPS>::CK;
+  int64_t wgs = 0, ksum_n = 0;
+  bool wstat = true, split = false;
+  for (ConvMember& e : m) {
+    e.ks = conv_ksplit<TN, TAPS>(e.g, 1, e.kpart != nullptr, kpart_elems);
+    wgs += (int64_t)conv_tiles(e.g) * cot * e.ks;
+    wstat = wstat && (nch + e.ks - 1) / e.ks == 1;
+    if (e.ks > 1) {
+      split = true;
+      ksum_n = std::max<int64_t>(ksum_n, (int64_t)e.g.H * e.g.W * (e.g.cout / 4));
+    }
+  }
+  const int per_cu =
+      wstat ? conv_per_cu<TN, TAPS, UP, ETA, true, true>() : conv_per_cu<TN, TAPS, UP, ETA, false, true>();
+  const int64_t slots = (int64_t)conv_device_cus() * per_cu;
+  const int run = (int)std::max<int64_t>(1, (wgs + slots - 1) / slots);
+  int64_t wg = 0;
+  for (ConvMember& e : m) {
+    e.nwt = (conv_tiles(e.g) + run - 1) / run;
+    e.wg0 = (int)wg;
+    wg += (int64_t)e.nwt * e.ks;
+  }
+  L.tn = TN;
+  L.wstat = wstat;
+  L.run = run;
+  L.gx = (int)wg;
+  L.cot = cot;
+  L.nmem = (int)m.size();
+  L.split = split;
+  L.ksum_gx = (int)((ksum_n + 255) / 256);
+}
+
+template <int TN, int TAPS, bool UP, int ETA>
+static void conv_group_launch_t(const ConvGroupLaunch& L, const ConvMember* dm, const bf16_t* wp, int Kp,
+                                const float* bias, hipStream_t s) {
+  const ConvGeo g0{};
+  const dim3 grid(L.gx, L.cot, 1);
+  if (L.wstat)
+    k_conv<TN, TAPS, UP, ETA, true, true><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr, L.run,
+                                                               nullptr, 1, dm, L.nmem);
+  else
+    k_conv<TN, TAPS, UP, ETA, false, true><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr, L.run,
+                                                                nullptr, 1, dm, L.nmem);
+  if (L.split)
+    k_conv_ksum<UP, true><<<dim3(L.ksum_gx, L.nmem), 256, 0, s>>>(g0, 1, 1, L.cot * TN, nullptr, bias, nullptr, dm);
+}
+
+// The instantiations a grouped forward uses: 3x3 layers with any local
+// weight, and 1x1 up-convolutions without one.
+template <class F>
+static bool conv_group_dispatch(int taps, bool up, int eta, bool wide, F&& f) {
+  using std::integral_constant;
+  auto by_eta = [&](auto tn, auto tp, auto upc) {
+    if (eta == kEtaNone) f(tn, tp, upc, integral_constant<int, kEtaNone>{});
+    else if (eta == kEtaNode) f(tn, tp, upc, integral_constant<int, kEtaNode>{});
+    else f(tn, tp, upc, integral_constant<int, kEtaChannel>{});
+  };
+  if (taps == 9 && !up) {
+    if (wide) by_eta(integral_constant<int, 64>{}, integral_constant<int, 9>{}, integral_constant<bool, false>{});
+    else by_eta(integral_constant<int, 32>{}, integral_constant<int, 9>{}, integral_constant<bool, false>{});
+    return true;
+  }
+  if (taps == 1 && up && eta == kEtaNone) {
+    const auto none = integral_constant<int, kEtaNone>{};
+    if (wide) f(integral_constant<int, 64>{}, integral_constant<int, 1>{}, integral_constant<bool, true>{}, none);
+    else f(integral_constant<int, 32>{}, integral_constant<int, 1>{}, integral_constant<bool, true>{}, none);
+    return true;
+  }
+  return false;
+}
+
+static int conv_eta_mode(const ConvMember& e) { return !e.eta ? kEtaNone : e.g.eta_node ? kEtaNode : kEtaChannel; }
+
+bool plan_conv_group(int taps, bool up, std::vector<ConvMember>& m, int64_t kpart_elems, ConvGroupLaunch& L) {
+  if (m.empty()) return false;
+  L = ConvGroupLaunch{};
+  L.taps = taps;
+  L.up = up;
+  L.eta = conv_eta_mode(m[0]);
+  return conv_group_dispatch(taps, up, L.eta, m[0].g.cout >= 64, [&](auto tn, auto tp, auto upc, auto et) {
+    conv_group_plan_t<decltype(tn)::value, decltype(tp)::value, decltype(upc)::value, decltype(et)::value>(
+        m, kpart_elems, L);
+  });
+}
+
+void launch_conv_group(const ConvGroupLaunch& L, const ConvMember* d_mem, const bf16_t* wp, int Kp,
+                       const float* bias, hipStream_t s) {
+  conv_group_dispatch(L.taps, L.up, L.eta, L.tn == 64, [&](auto tn, auto tp, auto upc, auto et) {
+    conv_group_launch_t<decltype(tn)::value, decltype(tp)::value, decltype(upc)::value, decltype(et)::value>(
+        L, d_mem, wp, Kp, bias, s);
+  });
 }
 
 template <int TN, int TAPS, bool UP>
@@ -993,25 +1199,44 @@ void launch_fill_static(int H, int W, int pitch, int coff, const float* hxn, con
 }
 
 void launch_sumsq(const float* r, int64_t n, int nb, double* part, hipStream_t s) {
-  k_sumsq<<<dim3(kRedBlocks, nb), 256, 0, s>>>(r, n, part);
+  k_sumsq<false><<<dim3(kRedBlocks, nb), 256, 0, s>>>(r, n, part, nullptr);
 }
 
 void launch_input_pack(const float* r, int64_t n, int nb, double* part, bf16_t* xin, int pitch, int64_t bstride,
                        hipStream_t s) {
-  k_sumsq<<<dim3(kRedBlocks, nb), 256, 0, s>>>(r, n, part);
-  k_input_pack<<<dim3(kRedBlocks, nb), 256, 0, s>>>(r, n, part, kRedBlocks, xin, pitch, bstride);
+  k_sumsq<false><<<dim3(kRedBlocks, nb), 256, 0, s>>>(r, n, part, nullptr);
+  k_input_pack<false><<<dim3(kRedBlocks, nb), 256, 0, s>>>(r, n, part, kRedBlocks, xin, pitch, bstride, nullptr);
 }
 
 void launch_pool2(int Ho, int Wo, int C, const bf16_t* in, int pin, int cin_off, int64_t in_bs, bf16_t* out, int pout,
                   int64_t out_bs, int nb, hipStream_t s) {
   const int64_t n = (int64_t)Ho * Wo * (C / 8);
-  k_pool2<<<dim3((unsigned)((n + 255) / 256), nb), 256, 0, s>>>(Ho, Wo, C, in, pin, cin_off, in_bs, out, pout, out_bs);
+  k_pool2<false><<<dim3((unsigned)((n + 255) / 256), nb), 256, 0, s>>>(Ho, Wo, C, in, pin, cin_off, in_bs, out, pout,
+                                                                       out_bs, nullptr);
+}
+
+void launch_input_pack_group(const PackMember* d_mem, int n, int pitch, hipStream_t s) {
+  k_sumsq<true><<<dim3(kRedBlocks, n), 256, 0, s>>>(nullptr, 0, nullptr, d_mem);
+  k_input_pack<true><<<dim3(kRedBlocks, n), 256, 0, s>>>(nullptr, 0, nullptr, kRedBlocks, nullptr, pitch, 0, d_mem);
+}
+
+void launch_pool2_group(const PoolMember* d_mem, int n, int64_t max_out_pix, int C, int pin, int cin_off, int pout,
+                        hipStream_t s) {
+  const int64_t m = max_out_pix * (C / 8);
+  k_pool2<true><<<dim3((unsigned)((m + 255) / 256), n), 256, 0, s>>>(0, 0, C, nullptr, pin, cin_off, 0, nullptr, pout,
+                                                                    0, d_mem);
+}
+
+void launch_deeponet_out_group(const OutMember* d_mem, int n, int64_t max_npix, int c0, int fold_pitch,
+                               const float* gamma, hipStream_t s) {
+  k_deeponet_out<true><<<dim3((unsigned)((max_npix * 8 + 255) / 256), n), 256, 0, s>>>(
+      0, c0, nullptr, 0, nullptr, fold_pitch, gamma, nullptr, d_mem);
 }
 
 void launch_deeponet_out(int64_t npix, int c0, const bf16_t* d0, int64_t d_bs, const float* fold, int fold_pitch,
                          const float* gamma, float* y, int nb, hipStream_t s) {
-  k_deeponet_out<<<dim3((unsigned)((npix * 8 + 255) / 256), nb), 256, 0, s>>>(npix, c0, d0, d_bs, fold, fold_pitch, gamma,
-                                                                           y);
+  k_deeponet_out<false><<<dim3((unsigned)((npix * 8 + 255) / 256), nb), 256, 0, s>>>(npix, c0, d0, d_bs, fold,
+                                                                                  fold_pitch, gamma, y, nullptr);
 }
 
 }  // namespace ppe

@@ -1,5 +1,7 @@
 // Host-side declarations of the network kernel launchers.
 #pragma once
+#include <vector>
+
 #include "net_common.hpp"
 
 namespace ppe {
@@ -20,6 +22,23 @@ int64_t conv_kpart_elems();
 void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
                  int Kp, const float* bias, bf16_t* y, hipStream_t s, float* kpart = nullptr,
                  int64_t kpart_elems = 0);
+// Grouped convolution (one layer of the forwards of several grids): the
+// launch shape that plan_conv_group derives from the members (their g, x,
+// eta, y, kpart and skip set by the caller; it fills wg0, nwt and ks). Only
+// 3x3 layers and 1x1 up-convolutions without local weights are grouped
+// (plan_conv_group returns false otherwise). The member table must be in
+// device memory for launch_conv_group.
+struct ConvGroupLaunch {
+  int taps = 9, up = 0, eta = 0, tn = 32, wstat = 0, run = 1, gx = 0, cot = 0, nmem = 0, split = 0, ksum_gx = 0;
+};
+bool plan_conv_group(int taps, bool up, std::vector<ConvMember>& m, int64_t kpart_elems, ConvGroupLaunch& L);
+void launch_conv_group(const ConvGroupLaunch& L, const ConvMember* d_mem, const bf16_t* wp, int Kp,
+                       const float* bias, hipStream_t s);
+void launch_input_pack_group(const PackMember* d_mem, int n, int pitch, hipStream_t s);
+void launch_pool2_group(const PoolMember* d_mem, int n, int64_t max_out_pix, int C, int pin, int cin_off, int pout,
+                        hipStream_t s);
+void launch_deeponet_out_group(const OutMember* d_mem, int n, int64_t max_npix, int c0, int fold_pitch,
+                               const float* gamma, hipStream_t s);
 void launch_pack_weights(const float* w, int cout, int cin, int cin8, int taps, int Kp, bf16_t* out, hipStream_t s);
 // Input-gradient operator: rows = input channels (padded), K over cout_fwd.
 void launch_pack_weights_t(const float* w, int cout_fwd, int cin_fwd, int rows, int taps, int Kp, bf16_t* out,

@@ -120,6 +120,7 @@ SIGNATURES = {
     "ppe_net_save": (_i32, [_vp, ctypes.c_char_p]),
     "ppe_net_load": (_i32, [_vp, ctypes.c_char_p]),
     "ppe_net_forward": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
+    "ppe_net_forward_batch": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "ppe_net_train_step": (_i32, [_vp, _i32, _vp, _vp, _vp, _P(ppe_train_opts), _vp, _vp, _vp]),
     "ppe_profile_pcg": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_solve_opts), _i32, _vp, _vp]),
     "ppe_profile_copy": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),
@@ -414,6 +415,26 @@ def ppe_net_forward(net: Net, prob: Problem, r, y, stream=None):
     nb = _nb(r, prob)
     _check(lib().ppe_net_forward(net.handle, prob.handle, nb, _dev(r, torch.float32, "r"),
                                  _dev(y, torch.float32, "y"), _stream(stream)))
+
+
+def ppe_net_forward_batch(net: Net, probs, rs, ys, stream=None):
+    """The forward on one field of each of len(probs) grids of any sizes, one
+    grouped launch per layer. rs[i], ys[i]: device float32 [ny_i, nx_i]
+    (or [1, ny_i, nx_i])."""
+    import torch
+    n = len(probs)
+    if len(rs) != n or len(ys) != n:
+        raise ValueError("one input and one output per problem")
+    for p, r, y in zip(probs, rs, ys):
+        for t in (r, y):
+            if t.numel() != p.nx * p.ny:
+                raise ValueError("array size does not match its grid")
+    parr = (ctypes.c_void_p * n)(*[p.handle.value for p in probs])
+    rarr = (ctypes.c_void_p * n)(*[_dev(r, torch.float32, "r") for r in rs])
+    yarr = (ctypes.c_void_p * n)(*[_dev(y, torch.float32, "y") for y in ys])
+    _check(lib().ppe_net_forward_batch(net.handle, n, ctypes.cast(parr, ctypes.c_void_p),
+                                       ctypes.cast(rarr, ctypes.c_void_p), ctypes.cast(yarr, ctypes.c_void_p),
+                                       _stream(stream)))
 
 
 def ppe_solve_hybrid(prob: Problem, net, f, x, opts=None, stream=None):

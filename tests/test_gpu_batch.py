@@ -129,15 +129,22 @@ def _single_hybrid(ppe, p, net, f, **kw):
     return st, s[0], xd[0].cpu().numpy()
 
 
-@pytest.mark.parametrize("direction,tol,max_iter", [(2, 1e-6, 20000), (0, 0.0, 23), (0, 0.0, 40)],
-                         ids=["jacobi_to_tol", "net_23_iters", "net_40_iters"])
-def test_hybrid_mixed_batch_equals_single_solves(ppe, direction, tol, max_iter):
+# With the network direction the forwards of the batch run as one grouped
+# launch per layer; the solves decide at different rounds in the "to_tol"
+# cases (a loose tolerance: the random-init network's hybrid is a restarted
+# CG(3) and slow to reach a tight one), so the grouped replay unit is rebuilt
+# for fewer solves on the way and decided solves skip their share of the
+# grouped launches.
+@pytest.mark.parametrize("direction,tol,max_iter,graph", [(2, 1e-6, 20000, 1), (0, 0.0, 23, 1), (0, 0.0, 40, 1),
+                                                          (0, 1e-2, 20000, 1), (0, 1e-2, 20000, 0)],
+                         ids=["jacobi_to_tol", "net_23_iters", "net_40_iters", "net_to_tol", "net_to_tol_eager"])
+def test_hybrid_mixed_batch_equals_single_solves(ppe, direction, tol, max_iter, graph):
     sys_ = systems(HYB_SHAPES, seed=4)
     net = ppe.Net(ppe.ppe_net_config_default(), seed=3)
     probs = [ppe.ppe_problem_create(g) for g, _ in sys_]
     fs = [torch.from_numpy(f).cuda() for _, f in sys_]
     xs = [torch.zeros(f.shape, dtype=torch.float64, device="cuda") for _, f in sys_]
-    kw = dict(tol=tol, max_iter=max_iter, direction=direction)
+    kw = dict(tol=tol, max_iter=max_iter, direction=direction, use_graph=graph)
     st, stats = ppe.ppe_solve_batch(probs, fs, xs, ppe.ppe_solve_opts_default(**kw), net=net)
     assert st == (ppe.PPE_OK if tol > 0 else ppe.PPE_NOT_CONVERGED)
     for (g, f), x, s, p in zip(sys_, xs, stats, probs):
@@ -150,6 +157,55 @@ def test_hybrid_mixed_batch_equals_single_solves(ppe, direction, tol, max_iter):
             assert true_res(g, f, x.cpu().numpy()) <= tol * 1.001
         else:
             assert s["iters_total"] == max_iter and s["iters_dlsm"] > 0
+    if direction == 0 and tol > 0:  # the solves decided at different rounds
+        print("iterations", [s["iters_total"] for s in stats])
+        assert len({s["iters_total"] for s in stats}) > 1
+
+
+# The grouped forward: shapes whose coarse levels split their K loop (the
+# small grids) next to ones that do not, both local-weight forms and none.
+FWD_SHAPES = [(64, 64), (128, 72), (40, 96), (32, 32), (256, 200), (16, 24)]
+
+
+@pytest.mark.parametrize("use_eta", [2, 1, 0])
+def test_forward_batch_equals_single_forwards(ppe, use_eta):
+    net = ppe.Net(ppe.ppe_net_config_default(use_eta=use_eta), seed=5)
+    sys_ = systems(FWD_SHAPES, seed=8)
+    probs = [ppe.ppe_problem_create(g) for g, _ in sys_]
+    rs = [torch.from_numpy(f).cuda() for _, f in sys_]
+    ys = [torch.full(f.shape, float("nan"), dtype=torch.float32, device="cuda") for _, f in sys_]
+    ppe.ppe_net_forward_batch(net, probs, rs, ys)
+    for p, r, y in zip(probs, rs, ys):
+        y1 = torch.zeros((1,) + tuple(r.shape), dtype=torch.float32, device="cuda")
+        ppe.ppe_net_forward(net, p, r[None], y1)
+        np.testing.assert_array_equal(y.cpu().numpy(), y1[0].cpu().numpy())
+        assert torch.isfinite(y).all()
+    # order within the batch does not matter, and a single member is the plain forward
+    ys2 = [torch.zeros_like(y) for y in ys]
+    ppe.ppe_net_forward_batch(net, probs[::-1], rs[::-1], ys2[::-1])
+    for y, y2 in zip(ys, ys2):
+        assert torch.equal(y, y2)
+    y3 = torch.zeros_like(ys[4])
+    ppe.ppe_net_forward_batch(net, [probs[4]], [rs[4]], [y3])
+    assert torch.equal(y3, ys[4])
+
+
+def test_forward_batch_checks(ppe):
+    net = ppe.Net(ppe.ppe_net_config_default(), seed=5)
+    sys_ = systems(FWD_SHAPES[:2], seed=8)
+    probs = [ppe.ppe_problem_create(g) for g, _ in sys_]
+    rs = [torch.from_numpy(f).cuda() for _, f in sys_]
+    ys = [torch.zeros_like(r) for r in rs]
+    with pytest.raises(ppe.PPEError) as e:  # the same problem twice
+        ppe.ppe_net_forward_batch(net, [probs[0], probs[0]], [rs[0], rs[0]], [ys[0], ys[0]])
+    assert e.value.status == ppe.PPE_ERR_INVALID_ARG
+    g36 = inputs.make_grid(36, 36, 1.5)
+    with pytest.raises(ppe.PPEError) as e:  # 36 is not divisible by 8
+        ppe.ppe_net_forward_batch(net, [probs[0], ppe.ppe_problem_create(g36)],
+                                  [rs[0], torch.zeros((36, 36), device="cuda")],
+                                  [ys[0], torch.zeros((36, 36), device="cuda")])
+    assert e.value.status == ppe.PPE_ERR_SHAPE
+    ppe.ppe_net_forward_batch(net, [], [], [])
 
 
 def test_hybrid_batch_statuses_and_checks(ppe):
