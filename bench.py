@@ -32,7 +32,11 @@ the iterations one launch makes, over its average launch duration (HIP
 events attached to the launches); the kernel's own bytes per launch are
 given beside it. config["hbm_resident_batch"] repeats the solve for 32
 right-hand sides on the same grid, whose 1.1 GB of state cannot stay in the
-256 MB last-level cache. `cpu_baseline` times the FP64 oracle on a bounded
+256 MB last-level cache. config["mixed_batch"] solves one system on each
+of 48 grids of uneven sizes (128 to 1024 cells per axis): plain PCG in one
+work list, the hybrid in lock step with the network forwards of all grids
+grouped into one launch per layer, and that grouped forward timed against
+one forward per grid. `cpu_baseline` times the FP64 oracle on a bounded
 sample (a fixed number of PCG iterations on the same system, scaled to the
 iteration count of a full solve).
 """
@@ -54,6 +58,8 @@ BYTES_PCG2 = 24     # own bytes per cell and launch of two iterations: the same 
 BYTES_PHASE_A = 20  # own bytes per cell: reads r, p_old, x_c; writes p, x_c (FP32)
 BYTES_PHASE_B = 12  # own bytes per cell: reads p, r; writes r (FP32)
 HBM_BATCH = 32      # right-hand sides of the HBM-resident batch
+MIXED_N = 48        # grids of the mixed-size batch
+MIXED_ITERS = 60    # iterations of its hybrid solves
 
 
 def workload(n=1024, beta=1.75, seed=0):
@@ -301,6 +307,60 @@ def hbm_batch_run(ppe, torch, g, prob, args):
             "own_bytes_per_cell_launch": own, "GBps_own_bytes": own_gbs, "frac_own_bytes": own_gbs / HBM_PEAK_GBS}
 
 
+def mixed_batch_run(ppe, torch, args):
+    """MIXED_N grids of uneven sizes from 128 to 1024 cells per axis (tanh
+    grids with random stretching, GRF sources): the plain solves to the
+    tolerance in one work list, the hybrid solves in lock step for
+    MIXED_ITERS iterations (random-init network), and the network forward on
+    one field of every grid as one grouped launch per layer against one
+    forward launch sequence per grid."""
+    from paper_2604_01800_amd import inputs
+    rng = np.random.default_rng(51)
+    sizes = list(range(128, 1025, 64))
+    shapes = [(int(rng.choice(sizes)), int(rng.choice(sizes))) for _ in range(MIXED_N)]
+    grids = [inputs.random_stretched_grid(nx, ny, rng) for nx, ny in shapes]
+    probs = [ppe.ppe_problem_create(gk) for gk in grids]
+    fs = [torch.from_numpy(inputs.grf(gk, 500 + k).astype(np.float32)).cuda() for k, gk in enumerate(grids)]
+    xs = [torch.zeros(f.shape, dtype=torch.float64, device="cuda") for f in fs]
+    out = {"grids": MIXED_N, "cells": int(sum(nx * ny for nx, ny in shapes))}
+    o = ppe.ppe_solve_opts_default(tol=args.tol)
+    st, stats = ppe.ppe_solve_batch(probs, fs, xs, o)
+    out["plain_converged"] = st == ppe.PPE_OK
+    out["plain_ms"] = stats[0]["ms_total"]
+    out["plain_solves_per_s"] = MIXED_N * 1e3 / stats[0]["ms_total"]
+    net = ppe.Net(ppe.ppe_net_config_default(), seed=9)
+    ho = ppe.ppe_solve_opts_default(tol=args.tol, max_iter=MIXED_ITERS)
+    for rep in range(2):  # the first call also builds every grid's network constants
+        for x in xs:
+            x.zero_()
+        st, hs = ppe.ppe_solve_batch(probs, fs, xs, ho, net=net)
+    out["hybrid_iters"] = MIXED_ITERS
+    out["hybrid_forwards_per_solve"] = hs[0]["iters_dlsm"]
+    out["hybrid_ms"] = hs[0]["ms_total"]
+    out["hybrid_ms_split"] = {"cg": hs[0]["ms_pcg"], "net": hs[0]["ms_net"], "dlsm": hs[0]["ms_dlsm"]}
+    ys = [torch.empty_like(f) for f in fs]
+    ppe.ppe_net_forward_batch(net, probs, fs, ys)
+    reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ppe.ppe_net_forward_batch(net, probs, fs, ys)
+    torch.cuda.synchronize()
+    out["forward_grouped_ms"] = (time.perf_counter() - t0) * 1e3 / reps
+    for p, f, y in zip(probs, fs, ys):
+        ppe.ppe_net_forward(net, p, f[None], y[None])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for p, f, y in zip(probs, fs, ys):
+            ppe.ppe_net_forward(net, p, f[None], y[None])
+    torch.cuda.synchronize()
+    out["forward_per_grid_ms"] = (time.perf_counter() - t0) * 1e3 / reps
+    del probs, fs, xs, ys
+    torch.cuda.empty_cache()
+    return out
+
+
 def sequence_run(ppe, torch, g, prob, x, opts, form, rows, args):
     """Consecutive solves of a travelling source on one grid (the shape of the
     paper's 20 000-step PPE timings): plain PCG from x0 = 0 and warm-started,
@@ -356,6 +416,7 @@ def main():
     ap.add_argument("--train-steps", type=int, default=12000,
                     help="Adam steps of the network trained for config['hybrid_trained'] (0: skip that leg)")
     ap.add_argument("--no-hbm-batch", action="store_true", help="skip the HBM-resident batch leg")
+    ap.add_argument("--no-mixed-batch", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--mg-delta", type=float, default=0.1,
                     help="reliable-update threshold of the multigrid legs")
     ap.add_argument("--mg-hybrid-max-iter", type=int, default=500)
@@ -525,6 +586,8 @@ def main():
     out["config"].update(ic_run(ppe, torch, prob, f, x, args))
     if not args.no_hbm_batch:
         out["config"]["hbm_resident_batch"] = hbm_batch_run(ppe, torch, g, prob, args)
+    if not args.no_mixed_batch:
+        out["config"]["mixed_batch"] = mixed_batch_run(ppe, torch, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, f_np, iters, args.cpu_iters)
     print(json.dumps(out), flush=True)

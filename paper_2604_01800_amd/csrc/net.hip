@@ -2,6 +2,7 @@
 // per-grid network constants and the forward pass (Sec. 2.4).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -592,37 +593,30 @@ void net_group_free(NetGroup& G) {
   G = NetGroup{};
 }
 
-ppe_status net_group_build(int n, ppe_problem* const* probs, ppe_net* net, const float* const* r, float* const* y,
-                           const int32_t* const* skip, hipStream_t s, NetGroup& G) {
-  net_group_free(G);
-  if (n < 1) return set_error(PPE_ERR_INVALID_ARG, "empty group");
-  std::vector<std::vector<FwdOp>> ops(n);
-  for (int i = 0; i < n; ++i) {
-    ppe_status st = net_cache_ensure(probs[i], net, 1, s);
-    if (st != PPE_OK) return st;
-    forward_ops(probs[i], net, probs[i]->net_cache, r[i], y[i], ops[i]);
-    if (ops[i].size() != ops[0].size()) return set_error(PPE_ERR_UNSUPPORTED, "group members with different layers");
-  }
-  const size_t nops = ops[0].size();
-  std::vector<char> blob;
+// The tables of one part (members idx of the group) appended to blob.
+static ppe_status group_part(const std::vector<std::vector<FwdOp>>& ops, const std::vector<int>& idx,
+                             const int32_t* const* skip, std::vector<char>& blob, GroupPart& P) {
+  const int n = (int)idx.size();
+  const size_t nops = ops[idx[0]].size();
   auto append = [&](const void* src, size_t bytes) {
     const size_t o = (blob.size() + 255) / 256 * 256;
     blob.resize(o + bytes);
     std::memcpy(blob.data() + o, src, bytes);
     return (int64_t)o;
   };
-  G.n = n;
-  G.ops.resize(nops);
+  auto sk = [&](int i) { return skip ? skip[idx[i]] : nullptr; };
+  P.n = n;
+  P.ops.resize(nops);
   for (size_t k = 0; k < nops; ++k) {
-    const FwdOp& o0 = ops[0][k];
-    GroupOp& q = G.ops[k];
+    const FwdOp& o0 = ops[idx[0]][k];
+    GroupOp& q = P.ops[k];
     q.kind = o0.kind;
     switch (o0.kind) {
       case FwdOp::PACK: {
         std::vector<PackMember> m(n);
         for (int i = 0; i < n; ++i) {
-          const FwdOp& o = ops[i][k];
-          m[i] = PackMember{o.r, o.n, o.part, o.xin, skip ? skip[i] : nullptr};
+          const FwdOp& o = ops[idx[i]][k];
+          m[i] = PackMember{o.r, o.n, o.part, o.xin, sk(i)};
         }
         q.a = o0.pitch;
         q.off = append(m.data(), m.size() * sizeof(PackMember));
@@ -631,8 +625,8 @@ ppe_status net_group_build(int n, ppe_problem* const* probs, ppe_net* net, const
       case FwdOp::POOL: {
         std::vector<PoolMember> m(n);
         for (int i = 0; i < n; ++i) {
-          const FwdOp& o = ops[i][k];
-          m[i] = PoolMember{o.Ho, o.Wo, o.in, o.out, skip ? skip[i] : nullptr};
+          const FwdOp& o = ops[idx[i]][k];
+          m[i] = PoolMember{o.Ho, o.Wo, o.in, o.out, sk(i)};
           q.maxn = std::max<int64_t>(q.maxn, (int64_t)o.Ho * o.Wo);
         }
         q.a = o0.C;
@@ -645,14 +639,14 @@ ppe_status net_group_build(int n, ppe_problem* const* probs, ppe_net* net, const
       case FwdOp::CONV: {
         std::vector<ConvMember> m(n);
         for (int i = 0; i < n; ++i) {
-          const FwdOp& o = ops[i][k];
+          const FwdOp& o = ops[idx[i]][k];
           m[i] = ConvMember{};
           m[i].g = o.g;
           m[i].x = o.x;
           m[i].eta = o.eta;
           m[i].y = o.y;
           m[i].kpart = o.kpart;
-          m[i].skip = skip ? skip[i] : nullptr;
+          m[i].skip = sk(i);
         }
         if (!plan_conv_group(o0.taps, o0.up, m, o0.kpart_elems, q.conv))
           return set_error(PPE_ERR_UNSUPPORTED, "layer %zu has no grouped form", k);
@@ -665,8 +659,8 @@ ppe_status net_group_build(int n, ppe_problem* const* probs, ppe_net* net, const
       case FwdOp::OUT: {
         std::vector<OutMember> m(n);
         for (int i = 0; i < n; ++i) {
-          const FwdOp& o = ops[i][k];
-          m[i] = OutMember{o.n, o.d0, o.fold, o.yout, skip ? skip[i] : nullptr};
+          const FwdOp& o = ops[idx[i]][k];
+          m[i] = OutMember{o.n, o.d0, o.fold, o.yout, sk(i)};
           q.maxn = std::max<int64_t>(q.maxn, o.n);
         }
         q.a = o0.c0;
@@ -677,6 +671,44 @@ ppe_status net_group_build(int n, ppe_problem* const* probs, ppe_net* net, const
       }
     }
   }
+  return PPE_OK;
+}
+
+ppe_status net_group_build(int n, ppe_problem* const* probs, ppe_net* net, const float* const* r, float* const* y,
+                           const int32_t* const* skip, hipStream_t s, NetGroup& G) {
+  net_group_free(G);
+  if (n < 1) return set_error(PPE_ERR_INVALID_ARG, "empty group");
+  std::vector<std::vector<FwdOp>> ops(n);
+  for (int i = 0; i < n; ++i) {
+    ppe_status st = net_cache_ensure(probs[i], net, 1, s);
+    if (st != PPE_OK) return st;
+    forward_ops(probs[i], net, probs[i]->net_cache, r[i], y[i], ops[i]);
+    if (ops[i].size() != ops[0].size()) return set_error(PPE_ERR_UNSUPPORTED, "group members with different layers");
+  }
+  // parts: first fit over the grids by decreasing size
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto cells = [&](int i) { return (int64_t)probs[i]->nx * probs[i]->ny; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cells(a) > cells(b); });
+  std::vector<std::vector<int>> bins;
+  std::vector<int64_t> fill;
+  for (int i : order) {
+    size_t b = 0;
+    while (b < bins.size() && fill[b] + cells(i) > kGroupCells) ++b;
+    if (b == bins.size()) {
+      bins.emplace_back();
+      fill.push_back(0);
+    }
+    bins[b].push_back(i);
+    fill[b] += cells(i);
+  }
+  std::vector<char> blob;
+  G.n = n;
+  G.parts.resize(bins.size());
+  for (size_t b = 0; b < bins.size(); ++b) {
+    ppe_status st = group_part(ops, bins[b], skip, blob, G.parts[b]);
+    if (st != PPE_OK) return st;
+  }
   G.d_tab = (char*)dev_alloc(blob.size());
   if (!G.d_tab) return set_error(PPE_ERR_HIP, "allocation of the group tables failed");
   G.h_tab = std::move(blob);
@@ -685,15 +717,16 @@ ppe_status net_group_build(int n, ppe_problem* const* probs, ppe_net* net, const
 }
 
 ppe_status net_group_forward(const NetGroup& G, hipStream_t s) {
-  for (const GroupOp& q : G.ops) {
-    const void* t = G.d_tab + q.off;
-    switch (q.kind) {
-      case FwdOp::PACK: launch_input_pack_group((const PackMember*)t, G.n, q.a, s); break;
-      case FwdOp::POOL: launch_pool2_group((const PoolMember*)t, G.n, q.maxn, q.a, q.b, q.c, q.d, s); break;
-      case FwdOp::CONV: launch_conv_group(q.conv, (const ConvMember*)t, q.wp, q.Kp, q.bias, s); break;
-      case FwdOp::OUT: launch_deeponet_out_group((const OutMember*)t, G.n, q.maxn, q.a, q.b, q.gamma, s); break;
+  for (const GroupPart& P : G.parts)
+    for (const GroupOp& q : P.ops) {
+      const void* t = G.d_tab + q.off;
+      switch (q.kind) {
+        case FwdOp::PACK: launch_input_pack_group((const PackMember*)t, P.n, q.a, s); break;
+        case FwdOp::POOL: launch_pool2_group((const PoolMember*)t, P.n, q.maxn, q.a, q.b, q.c, q.d, s); break;
+        case FwdOp::CONV: launch_conv_group(q.conv, (const ConvMember*)t, q.wp, q.Kp, q.bias, s); break;
+        case FwdOp::OUT: launch_deeponet_out_group((const OutMember*)t, P.n, q.maxn, q.a, q.b, q.gamma, s); break;
+      }
     }
-  }
   HIPCHK(hipGetLastError());
   return PPE_OK;
 }

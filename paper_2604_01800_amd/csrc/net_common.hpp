@@ -74,7 +74,7 @@ struct ConvMember {
   int wg0;              // first workgroup of the member along x
   int nwt;              // workgroups per K share (runs of tiles)
   int ks;               // K shares: the split the member's own launch uses
-  int pad_;
+  int kwg0;             // first workgroup of the member in the K-split sum (none without a split)
 };
 struct PackMember {     // input scaling (sum of squares, then the packed input)
   const float* r;

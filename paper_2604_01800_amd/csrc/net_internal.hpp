@@ -83,10 +83,19 @@ struct GroupOp {
   const float* gamma = nullptr;
 };
 
-// The forwards of several grids (one field each) as one launch per layer.
-struct NetGroup {
+// The forwards of several grids (one field each) as one launch per layer
+// and part. The grids are packed into parts of at most kGroupCells cells (a
+// larger grid is a part of its own): a part's activations stay about as
+// large as one 1024^2 grid's, which the last-level cache holds from one
+// layer to the next; one launch over all grids would stream them from HBM.
+constexpr int64_t kGroupCells = int64_t(1) << 20;
+struct GroupPart {
   int n = 0;
   std::vector<GroupOp> ops;
+};
+struct NetGroup {
+  int n = 0;
+  std::vector<GroupPart> parts;
   char* d_tab = nullptr;
   std::vector<char> h_tab;  // host copy of the tables (source of the upload)
 };

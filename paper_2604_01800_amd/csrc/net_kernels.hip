@@ -489,26 +489,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // activation and the BF16 store of the unsplit epilogue (UP: to the 2 x 2
 // finer pixels). One thread per (pixel, 4 output channels); cp = channel pitch
 // of the partials.
-// GRP: blockIdx.y is the member of a grouped launch (members without a split
-// or whose solve has decided return).
+// GRP: a grouped launch; the workgroups of the members with a split follow
+// one another (member table `mem` of nb entries, ordered by kwg0), and those
+// of a member whose solve has decided return.
 template <bool UP, bool GRP>
 __global__ __launch_bounds__(256) void k_conv_ksum(ConvGeo g, int nb, int ksplit, int cp,
                                                    const float* __restrict__ kpart, const float* __restrict__ bias,
                                                    bf16_t* __restrict__ y, const ConvMember* __restrict__ mem) {
   int smp = blockIdx.y;
+  int64_t blk = blockIdx.x;
   if constexpr (GRP) {
-    const ConvMember& M = mem[blockIdx.y];
-    if (M.ks < 2 || (M.skip && *M.skip != 0)) return;
+    int lo = 0, hi = nb - 1;  // the last member whose first workgroup is <= blockIdx.x
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (mem[mid].kwg0 <= (int)blockIdx.x) lo = mid;
+      else hi = mid - 1;
+    }
+    const ConvMember& M = mem[lo];
+    if (M.ks < 2 || (M.skip && __builtin_amdgcn_readfirstlane(*M.skip) != 0)) return;
     g = M.g;
     nb = 1;
     ksplit = M.ks;
     kpart = M.kpart;
     y = M.y;
     smp = 0;
+    blk -= M.kwg0;
   }
   const int q4 = g.cout / 4;
   const int64_t hw = (int64_t)g.H * g.W;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = blk * 256 + threadIdx.x;
   if (i >= hw * q4) return;
   const int64_t p = i / q4;
   const int co = (int)(i - p * q4) * 4;
@@ -1026,16 +1035,14 @@ static void conv_group_plan_t(std::vector<ConvMember>& m, int64_t kpart_elems, C
   const ConvGeo& g0 = m[0].g;
   const int cot = (g0.cout + TN - 1) / TN;
   const int nch = (g0.cin8 + ConvShape<TN, TAPS>::CK - 1) / ConvShape<TN, TAPS>::CK;
-  int64_t wgs = 0, ksum_n = 0;
-  bool wstat = true, split = false;
+  int64_t wgs = 0, kwg = 0;
+  bool wstat = true;
   for (ConvMember& e : m) {
     e.ks = conv_ksplit<TN, TAPS>(e.g, 1, e.kpart != nullptr, kpart_elems);
     wgs += (int64_t)conv_tiles(e.g) * cot * e.ks;
     wstat = wstat && (nch + e.ks - 1) / e.ks == 1;
-    if (e.ks > 1) {
-      split = true;
-      ksum_n = std::max<int64_t>(ksum_n, (int64_t)e.g.H * e.g.W * (e.g.cout / 4));
-    }
+    e.kwg0 = (int)kwg;
+    if (e.ks > 1) kwg += ((int64_t)e.g.H * e.g.W * (e.g.cout / 4) + 255) / 256;
   }
   const int per_cu =
       wstat ? conv_per_cu<TN, TAPS, UP, ETA, true, true>() : conv_per_cu<TN, TAPS, UP, ETA, false, true>();
@@ -1053,8 +1060,8 @@ static void conv_group_plan_t(std::vector<ConvMember>& m, int64_t kpart_elems, C
   L.gx = (int)wg;
   L.cot = cot;
   L.nmem = (int)m.size();
-  L.split = split;
-  L.ksum_gx = (int)((ksum_n + 255) / 256);
+  L.split = kwg > 0;
+  L.ksum_gx = (int)kwg;
 }
 
 template <int TN, int TAPS, bool UP, int ETA>
@@ -1069,7 +1076,7 @@ static void conv_group_launch_t(const ConvGroupLaunch& L, const ConvMember* dm, 
     k_conv<TN, TAPS, UP, ETA, false, true><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr, L.run,
                                                                 nullptr, 1, dm, L.nmem);
   if (L.split)
-    k_conv_ksum<UP, true><<<dim3(L.ksum_gx, L.nmem), 256, 0, s>>>(g0, 1, 1, L.cot * TN, nullptr, bias, nullptr, dm);
+    k_conv_ksum<UP, true><<<dim3(L.ksum_gx, 1), 256, 0, s>>>(g0, L.nmem, 1, L.cot * TN, nullptr, bias, nullptr, dm);
 }
 
 // The instantiations a grouped forward uses: 3x3 layers with any local

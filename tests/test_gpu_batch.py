@@ -167,10 +167,15 @@ def test_hybrid_mixed_batch_equals_single_solves(ppe, direction, tol, max_iter, 
 FWD_SHAPES = [(64, 64), (128, 72), (40, 96), (32, 32), (256, 200), (16, 24)]
 
 
-@pytest.mark.parametrize("use_eta", [2, 1, 0])
-def test_forward_batch_equals_single_forwards(ppe, use_eta):
+# More than 2^20 cells in all: the grids are packed into several parts.
+FWD_SHAPES_LARGE = [(1024, 512), (64, 64), (512, 512), (640, 384), (128, 128), (40, 96)]
+
+
+@pytest.mark.parametrize("use_eta,shapes", [(2, FWD_SHAPES), (1, FWD_SHAPES), (0, FWD_SHAPES), (2, FWD_SHAPES_LARGE)],
+                         ids=["per_node", "per_channel", "no_eta", "per_node_parts"])
+def test_forward_batch_equals_single_forwards(ppe, use_eta, shapes):
     net = ppe.Net(ppe.ppe_net_config_default(use_eta=use_eta), seed=5)
-    sys_ = systems(FWD_SHAPES, seed=8)
+    sys_ = systems(shapes, seed=8)
     probs = [ppe.ppe_problem_create(g) for g, _ in sys_]
     rs = [torch.from_numpy(f).cuda() for _, f in sys_]
     ys = [torch.full(f.shape, float("nan"), dtype=torch.float32, device="cuda") for _, f in sys_]
@@ -185,9 +190,9 @@ def test_forward_batch_equals_single_forwards(ppe, use_eta):
     ppe.ppe_net_forward_batch(net, probs[::-1], rs[::-1], ys2[::-1])
     for y, y2 in zip(ys, ys2):
         assert torch.equal(y, y2)
-    y3 = torch.zeros_like(ys[4])
-    ppe.ppe_net_forward_batch(net, [probs[4]], [rs[4]], [y3])
-    assert torch.equal(y3, ys[4])
+    y3 = torch.zeros_like(ys[2])
+    ppe.ppe_net_forward_batch(net, [probs[2]], [rs[2]], [y3])
+    assert torch.equal(y3, ys[2])
 
 
 def test_forward_batch_checks(ppe):
