@@ -85,10 +85,11 @@ struct GroupOp {
 
 // The forwards of several grids (one field each) as one launch per layer
 // and part. The grids are packed into parts of at most kGroupCells cells (a
-// larger grid is a part of its own): a part's activations stay about as
-// large as one 1024^2 grid's, which the last-level cache holds from one
-// layer to the next; one launch over all grids would stream them from HBM.
-constexpr int64_t kGroupCells = int64_t(1) << 20;
+// larger grid is a part of its own). On 48 grids of 16 M cells in all, the
+// grouped forward took 17.4 ms with parts of 2^20 cells, 15.4 with 2^21,
+// 15.3 with 2^22 and 15.4 with 2^23: smaller parts add launches and their
+// tails, larger ones gain nothing more.
+constexpr int64_t kGroupCells = int64_t(1) << 22;
 struct GroupPart {
   int n = 0;
   std::vector<GroupOp> ops;

@@ -167,8 +167,8 @@ def test_hybrid_mixed_batch_equals_single_solves(ppe, direction, tol, max_iter, 
 FWD_SHAPES = [(64, 64), (128, 72), (40, 96), (32, 32), (256, 200), (16, 24)]
 
 
-# More than 2^20 cells in all: the grids are packed into several parts.
-FWD_SHAPES_LARGE = [(1024, 512), (64, 64), (512, 512), (640, 384), (128, 128), (40, 96)]
+# More than 2^22 cells in all: the grids are packed into two parts.
+FWD_SHAPES_LARGE = [(2048, 1536), (64, 64), (1024, 1040), (640, 384), (128, 128), (40, 96)]
 
 
 @pytest.mark.parametrize("use_eta,shapes", [(2, FWD_SHAPES), (1, FWD_SHAPES), (0, FWD_SHAPES), (2, FWD_SHAPES_LARGE)],
