@@ -397,7 +397,7 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
 
 static ConvGeo geo(const NetCache* c, int l, int cin8, int cout, int y_pitch, int y_off, int nb_eta_shared,
                    int x_pitch = 0) {
-  ConvGeo g;
+  ConvGeo g{};
   g.H = c->H[l];
   g.W = c->W[l];
   g.cin8 = cin8;
@@ -432,7 +432,7 @@ static ConvGeo with_static(const NetCache* c, ConvGeo g, int l, const bf16_t* A)
 // One launch of the forward on one grid: what the launch over nb samples of
 // the grid, or a grouped launch over grids, needs.
 struct FwdOp {
-  enum Kind { PACK, POOL, CONV, OUT } kind = PACK;
+  enum Kind { PACK, CONV, OUT } kind = PACK;
   // PACK: channel 0 of the level-0 input from r (pitch, bstride)
   const float* r = nullptr;
   int64_t n = 0;
@@ -440,11 +440,6 @@ struct FwdOp {
   bf16_t* xin = nullptr;
   int pitch = 0;
   int64_t bstride = 0;
-  // POOL: Ho x Wo pixels of C channels
-  int Ho = 0, Wo = 0, C = 0, pin = 0, cin_off = 0, pout = 0;
-  const bf16_t* in = nullptr;
-  bf16_t* out = nullptr;
-  int64_t in_bs = 0, out_bs = 0;
   // CONV
   int taps = 9;
   bool up = false;
@@ -467,7 +462,8 @@ struct FwdOp {
 };
 
 // The forward's launches for the grid of cache c, in order: input scaling,
-// per encoder level (pooling,) two Mesh-Convs, per decoder level the 1x1
+// per encoder level two Mesh-Convs (the second also writes the 2 x 2 average
+// of its output, E_l, as the next level's input), per decoder level the 1x1
 // up-convolution and two Mesh-Convs, then the DeepONet output.
 static void forward_ops(const ppe_problem* p, const ppe_net* n, const NetCache* c, const float* r, float* y,
                         std::vector<FwdOp>& ops) {
@@ -507,29 +503,19 @@ static void forward_ops(const ppe_problem* p, const ppe_net* n, const NetCache* 
   };
   for (int l = 0; l < L; ++l) {
     const int64_t hw = (int64_t)c->H[l] * c->W[l];
-    if (l > 0) {
-      // E_{l-1} lives in the decoder concat buffer of level l-1 at channel C_{l-1}
-      FwdOp o;
-      o.kind = FwdOp::POOL;
-      o.Ho = c->H[l];
-      o.Wo = c->W[l];
-      o.C = ch(l - 1);
-      o.in = A + c->o_cat[l - 1];
-      o.pin = c->p_cat[l - 1];
-      o.cin_off = ch(l - 1);
-      o.in_bs = 4 * hw * o.pin;
-      o.out = A + c->o_in[l];
-      o.pout = c->p_in[l];
-      o.out_bs = hw * c->p_in[l];
-      ops.push_back(o);
-    }
     const MConvL& ma = n->enc_a[l];
     const MConvL& mb = n->enc_b[l];
     conv(9, false, with_static(c, geo(c, l, ma.cin8, ma.cout, ch(l), 0, 1, c->p_in[l]), l, A), A + c->o_in[l],
          eta(c->eta_a[l]), n->d_pack + ma.opack, ma.kp, n->d_w + ma.ob, A + c->o_a[l]);
-    if (l < L - 1)
-      conv(9, false, geo(c, l, mb.cin8, mb.cout, c->p_cat[l], ch(l), 1), A + c->o_a[l], eta(c->eta_b[l]),
-           n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob, A + c->o_cat[l]);
+    if (l < L - 1) {
+      // E_l into the decoder concat buffer of level l at channel C_l, and pooled into level l + 1
+      ConvGeo gb = geo(c, l, mb.cin8, mb.cout, c->p_cat[l], ch(l), 1);
+      gb.pool_y = A + c->o_in[l + 1];
+      gb.pool_pitch = c->p_in[l + 1];
+      gb.pool_bstride = (int64_t)c->H[l + 1] * c->W[l + 1] * c->p_in[l + 1];
+      conv(9, false, gb, A + c->o_a[l], eta(c->eta_b[l]), n->d_pack + mb.opack, mb.kp, n->d_w + mb.ob,
+           A + c->o_cat[l]);
+    }
     else
       conv(9, false, geo(c, l, mb.cin8, mb.cout, ch(l), 0, 1), A + c->o_a[l], eta(c->eta_b[l]), n->d_pack + mb.opack,
            mb.kp, n->d_w + mb.ob, A + c->o_bot);
@@ -570,9 +556,6 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
   for (const FwdOp& o : ops) {
     switch (o.kind) {
       case FwdOp::PACK: launch_input_pack(o.r, o.n, nb, o.part, o.xin, o.pitch, o.bstride, s); break;
-      case FwdOp::POOL:
-        launch_pool2(o.Ho, o.Wo, o.C, o.in, o.pin, o.cin_off, o.in_bs, o.out, o.pout, o.out_bs, nb, s);
-        break;
       case FwdOp::CONV:
         launch_conv(o.taps, o.up, o.g, nb, o.x, o.eta, o.wp, o.Kp, o.bias, o.y, s, o.kpart, o.kpart_elems);
         break;
@@ -620,20 +603,6 @@ static ppe_status group_part(const std::vector<std::vector<FwdOp>>& ops, const s
         }
         q.a = o0.pitch;
         q.off = append(m.data(), m.size() * sizeof(PackMember));
-        break;
-      }
-      case FwdOp::POOL: {
-        std::vector<PoolMember> m(n);
-        for (int i = 0; i < n; ++i) {
-          const FwdOp& o = ops[idx[i]][k];
-          m[i] = PoolMember{o.Ho, o.Wo, o.in, o.out, sk(i)};
-          q.maxn = std::max<int64_t>(q.maxn, (int64_t)o.Ho * o.Wo);
-        }
-        q.a = o0.C;
-        q.b = o0.pin;
-        q.c = o0.cin_off;
-        q.d = o0.pout;
-        q.off = append(m.data(), m.size() * sizeof(PoolMember));
         break;
       }
       case FwdOp::CONV: {
@@ -722,7 +691,6 @@ ppe_status net_group_forward(const NetGroup& G, hipStream_t s) {
       const void* t = G.d_tab + q.off;
       switch (q.kind) {
         case FwdOp::PACK: launch_input_pack_group((const PackMember*)t, P.n, q.a, s); break;
-        case FwdOp::POOL: launch_pool2_group((const PoolMember*)t, P.n, q.maxn, q.a, q.b, q.c, q.d, s); break;
         case FwdOp::CONV: launch_conv_group(q.conv, (const ConvMember*)t, q.wp, q.Kp, q.bias, s); break;
         case FwdOp::OUT: launch_deeponet_out_group((const OutMember*)t, P.n, q.maxn, q.a, q.b, q.gamma, s); break;
       }

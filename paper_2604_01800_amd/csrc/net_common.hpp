@@ -58,6 +58,12 @@ struct ConvGeo {
   int64_t e_bstride; // elements between samples of eta (0 = shared by the batch)
   int act;          // epilogue activation: 0 none, 1 ReLU, 2 tanh
   int eta_node;     // 1: eta holds one weight per pixel ([H][W]), else one per input channel (pitch cin8)
+  // optional 2x2 average pooling of the output into the next level (H/2 x
+  // W/2 pixels, pitch pool_pitch, output channel co at channel co; H and W
+  // even; not with the upsampled output): null, or the pooled buffer
+  bf16_t* pool_y;
+  int pool_pitch;
+  int64_t pool_bstride;
 };
 
 // Grouped launches: one layer of the forwards of several grids (one sample
@@ -81,12 +87,6 @@ struct PackMember {     // input scaling (sum of squares, then the packed input)
   int64_t n;
   double* part;
   bf16_t* xin;
-  const int32_t* skip;
-};
-struct PoolMember {     // 2x2 pooling into a level
-  int Ho, Wo;
-  const bf16_t* in;
-  bf16_t* out;
   const int32_t* skip;
 };
 struct OutMember {      // DeepONet output

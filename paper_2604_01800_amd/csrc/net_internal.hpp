@@ -72,10 +72,10 @@ struct NetCache {
 // One layer of a grouped forward: its member table (at d_tab + off) and the
 // launch parameters the members share.
 struct GroupOp {
-  int kind = 0;            // input scaling, pooling, convolution, output (the forward's order)
+  int kind = 0;            // input scaling, convolution, output (the forward's order)
   int64_t off = 0;
-  int a = 0, b = 0, c = 0, d = 0;  // shared channel counts and pitches
-  int64_t maxn = 0;        // largest member's pixels (pooling, output)
+  int a = 0, b = 0;        // shared channel counts and pitches
+  int64_t maxn = 0;        // largest member's pixels (output)
   ConvGroupLaunch conv{};
   const bf16_t* wp = nullptr;
   int Kp = 0;

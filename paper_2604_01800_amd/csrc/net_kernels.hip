@@ -368,6 +368,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int HO = UP ? 2 * g.H : g.H, WO = UP ? 2 * g.W : g.W;
   const __amdgpu_buffer_rsrc_t yr =
       __builtin_amdgcn_make_buffer_rsrc(y, (short)0, (int)((int64_t)HO * WO * g.y_pitch * 2), 0x00020000);
+  // the 2 x 2 pooled output into the next level, when asked for
+  const bool pool = g.pool_y != nullptr;
+  const __amdgpu_buffer_rsrc_t pr = __builtin_amdgcn_make_buffer_rsrc(
+      pool ? g.pool_y + smp * g.pool_bstride : y, (short)0,
+      pool ? (int)((int64_t)(g.H / 2) * (g.W / 2) * g.pool_pitch * 2) : 0, 0x00020000);
   ConvLane<TN, TAPS> ln;
   if constexpr (kKeepLane<TN>) ln = conv_lane<TN, TAPS>(g);
   // input-channel chunks of this workgroup: all of them, or its share when
@@ -447,35 +452,64 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int mt = 0; mt < MT; ++mt) {
       const int col = mt * 16 + 4 * (lane >> 4);  // first of this lane's 4 channels within the workgroup's TN
       const int co = co0 + col;
-      if (co < g.cout) {
-        const f32x4_t b = *(const f32x4_t*)(s_b + col);
+      const bool cok = co < g.cout;
+      const f32x4_t b = *(const f32x4_t*)(s_b + col);
+      u32x2 pk[NT];  // the stored BF16 values (pooling reads them back)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
+      for (int nt = 0; nt < NT; ++nt) {
+        const int py = py0 + NT * wv + nt, px = px0 + (lane & 15);
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = acc[mt][nt][j] + b[j];
+        if (g.act == 1) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = __builtin_amdgcn_fmed3f(v[j], 0.f, __builtin_inff());
+        } else if (g.act == 2) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = tanh_nn(v[j]);
+        }
+        const u32x2 packed = {__builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){v[0], v[1]}, bf16x2_t)),
+                              __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){v[2], v[3]}, bf16x2_t))};
+        pk[nt] = packed;
+        if (!cok || py >= g.H || px >= g.W) continue;
+        if (!UP) {
+          const uint32_t o = (uint32_t)(((py * WO + px) * g.y_pitch + g.y_off + co) * 2);
+          __builtin_amdgcn_raw_buffer_store_b64(packed, yr, (int)o, 0, 0);
+        } else {
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) {
+              const uint32_t o = (uint32_t)((((2 * py + a) * WO + 2 * px + bb) * g.y_pitch + g.y_off + co) * 2);
+              __builtin_amdgcn_raw_buffer_store_b64(packed, yr, (int)o, 0, 0);
+            }
+        }
+      }
+      if (!UP && pool) {
+        // 2 x 2 average into the next level: rows nt, nt + 1 of this lane and
+        // the same rows of the next column's lane; the sum in the order and
+        // rounding of the pooling kernel, from the stored BF16 values
+#pragma unroll
+        for (int nt = 0; nt < NT; nt += 2) {
+          const uint32_t w[4][2] = {{pk[nt].x, pk[nt].y},
+                                    {(uint32_t)__shfl_xor((int)pk[nt].x, 1), (uint32_t)__shfl_xor((int)pk[nt].y, 1)},
+                                    {pk[nt + 1].x, pk[nt + 1].y},
+                                    {(uint32_t)__shfl_xor((int)pk[nt + 1].x, 1),
+                                     (uint32_t)__shfl_xor((int)pk[nt + 1].y, 1)}};
+          float sm[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              sm[2 * h] += bf2f((bf16_t)(w[q][h] & 0xffff));
+              sm[2 * h + 1] += bf2f((bf16_t)(w[q][h] >> 16));
+            }
           const int py = py0 + NT * wv + nt, px = px0 + (lane & 15);
-          if (py >= g.H || px >= g.W) continue;
-          float v[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) v[j] = acc[mt][nt][j] + b[j];
-          if (g.act == 1) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = __builtin_amdgcn_fmed3f(v[j], 0.f, __builtin_inff());
-          } else if (g.act == 2) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = tanh_nn(v[j]);
-          }
-          const u32x2 packed = {__builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){v[0], v[1]}, bf16x2_t)),
-                                __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){v[2], v[3]}, bf16x2_t))};
-          if (!UP) {
-            const uint32_t o = (uint32_t)(((py * WO + px) * g.y_pitch + g.y_off + co) * 2);
-            __builtin_amdgcn_raw_buffer_store_b64(packed, yr, (int)o, 0, 0);
-          } else {
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-              for (int bb = 0; bb < 2; ++bb) {
-                const uint32_t o = (uint32_t)((((2 * py + a) * WO + 2 * px + bb) * g.y_pitch + g.y_off + co) * 2);
-                __builtin_amdgcn_raw_buffer_store_b64(packed, yr, (int)o, 0, 0);
-              }
+          if (cok && (lane & 1) == 0 && py < g.H && px < g.W) {
+            const u32x2 pooled = {(uint32_t)f2bf(0.25f * sm[0]) | ((uint32_t)f2bf(0.25f * sm[1]) << 16),
+                                  (uint32_t)f2bf(0.25f * sm[2]) | ((uint32_t)f2bf(0.25f * sm[3]) << 16)};
+            const uint32_t o = (uint32_t)((((py >> 1) * (g.W >> 1) + (px >> 1)) * g.pool_pitch + co) * 2);
+            __builtin_amdgcn_raw_buffer_store_b64(pooled, pr, (int)o, 0, 0);
           }
         }
       }
@@ -515,12 +549,27 @@ __global__ __launch_bounds__(256) void k_conv_ksum(ConvGeo g, int nb, int ksplit
     smp = 0;
     blk -= M.kwg0;
   }
+  // one thread per 4 output channels of a pixel; with the pooled output the
+  // four pixels of a 2 x 2 block are the four lanes of a quad
+  const bool pool = !UP && g.pool_y != nullptr;
   const int q4 = g.cout / 4;
   const int64_t hw = (int64_t)g.H * g.W;
   const int64_t i = blk * 256 + threadIdx.x;
-  if (i >= hw * q4) return;
-  const int64_t p = i / q4;
-  const int co = (int)(i - p * q4) * 4;
+  if (i >= hw * q4) return;  // whole quads: hw * q4 is a multiple of 4 with pooling
+  int64_t p;
+  int co, sub = 0;
+  if (!pool) {
+    p = i / q4;
+    co = (int)(i - p * q4) * 4;
+  } else {
+    const int64_t t = i >> 2;  // (pooled pixel, channel quad)
+    sub = (int)(i & 3);        // (row, column) of the pixel in its block
+    const int64_t u = t / q4;
+    co = (int)(t - u * q4) * 4;
+    const int Wo = g.W / 2;
+    const int yo = (int)(u / Wo), xo = (int)(u - (int64_t)yo * Wo);
+    p = (int64_t)(2 * yo + (sub >> 1)) * g.W + 2 * xo + (sub & 1);
+  }
   const int64_t kstride = (int64_t)nb * hw * cp;
   const float* src = kpart + ((int64_t)smp * hw + p) * cp + co;
   f32x4_t a = *(const f32x4_t*)src;
@@ -552,6 +601,24 @@ __global__ __launch_bounds__(256) void k_conv_ksum(ConvGeo g, int nb, int ksplit
 #pragma unroll
       for (int b2 = 0; b2 < 2; ++b2)
         *(uint2*)(y + ((size_t)(2 * py + a2) * W2 + 2 * px + b2) * g.y_pitch + g.y_off + co) = packed;
+  }
+  if (pool) {
+    // the block's average in the pooling kernel's order (pixels 0..3 of the
+    // quad: row-major in the block), from the stored BF16 values
+    float sm[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t wx = (uint32_t)__shfl((int)packed.x, q, 4);
+      const uint32_t wy = (uint32_t)__shfl((int)packed.y, q, 4);
+      sm[0] += bf2f((bf16_t)(wx & 0xffff));
+      sm[1] += bf2f((bf16_t)(wx >> 16));
+      sm[2] += bf2f((bf16_t)(wy & 0xffff));
+      sm[3] += bf2f((bf16_t)(wy >> 16));
+    }
+    if (sub == 0)
+      *(uint2*)(g.pool_y + smp * g.pool_bstride + ((int64_t)(py >> 1) * (g.W >> 1) + (px >> 1)) * g.pool_pitch + co) =
+          make_uint2((uint32_t)f2bf(0.25f * sm[0]) | ((uint32_t)f2bf(0.25f * sm[1]) << 16),
+                     (uint32_t)f2bf(0.25f * sm[2]) | ((uint32_t)f2bf(0.25f * sm[3]) << 16));
   }
 }
 
@@ -863,19 +930,9 @@ __global__ __launch_bounds__(256) void k_input_pack(const float* __restrict__ r,
 
 // 2x2 average pooling of C channels (8 per thread) from a buffer of pitch
 // pin at channel offset cin_off into a buffer of pitch pout (channel 0 on).
-template <bool GRP>
 __global__ void k_pool2(int Ho, int Wo, int C, const bf16_t* __restrict__ in, int pin, int cin_off, int64_t in_bs,
-                        bf16_t* __restrict__ out, int pout, int64_t out_bs, const PoolMember* __restrict__ mem) {
-  int smp = blockIdx.y;
-  if constexpr (GRP) {
-    const PoolMember& M = mem[blockIdx.y];
-    if (M.skip && *M.skip != 0) return;
-    Ho = M.Ho;
-    Wo = M.Wo;
-    in = M.in;
-    out = M.out;
-    smp = 0;
-  }
+                        bf16_t* __restrict__ out, int pout, int64_t out_bs) {
+  const int smp = blockIdx.y;
   const int c8n = C / 8;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)Ho * Wo * c8n) return;
@@ -1218,20 +1275,12 @@ void launch_input_pack(const float* r, int64_t n, int nb, double* part, bf16_t* 
 void launch_pool2(int Ho, int Wo, int C, const bf16_t* in, int pin, int cin_off, int64_t in_bs, bf16_t* out, int pout,
                   int64_t out_bs, int nb, hipStream_t s) {
   const int64_t n = (int64_t)Ho * Wo * (C / 8);
-  k_pool2<false><<<dim3((unsigned)((n + 255) / 256), nb), 256, 0, s>>>(Ho, Wo, C, in, pin, cin_off, in_bs, out, pout,
-                                                                       out_bs, nullptr);
+  k_pool2<<<dim3((unsigned)((n + 255) / 256), nb), 256, 0, s>>>(Ho, Wo, C, in, pin, cin_off, in_bs, out, pout, out_bs);
 }
 
 void launch_input_pack_group(const PackMember* d_mem, int n, int pitch, hipStream_t s) {
   k_sumsq<true><<<dim3(kRedBlocks, n), 256, 0, s>>>(nullptr, 0, nullptr, d_mem);
   k_input_pack<true><<<dim3(kRedBlocks, n), 256, 0, s>>>(nullptr, 0, nullptr, kRedBlocks, nullptr, pitch, 0, d_mem);
-}
-
-void launch_pool2_group(const PoolMember* d_mem, int n, int64_t max_out_pix, int C, int pin, int cin_off, int pout,
-                        hipStream_t s) {
-  const int64_t m = max_out_pix * (C / 8);
-  k_pool2<true><<<dim3((unsigned)((m + 255) / 256), n), 256, 0, s>>>(0, 0, C, nullptr, pin, cin_off, 0, nullptr, pout,
-                                                                    0, d_mem);
 }
 
 void launch_deeponet_out_group(const OutMember* d_mem, int n, int64_t max_npix, int c0, int fold_pitch,

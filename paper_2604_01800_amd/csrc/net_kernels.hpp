@@ -35,8 +35,6 @@ bool plan_conv_group(int taps, bool up, std::vector<ConvMember>& m, int64_t kpar
 void launch_conv_group(const ConvGroupLaunch& L, const ConvMember* d_mem, const bf16_t* wp, int Kp,
                        const float* bias, hipStream_t s);
 void launch_input_pack_group(const PackMember* d_mem, int n, int pitch, hipStream_t s);
-void launch_pool2_group(const PoolMember* d_mem, int n, int64_t max_out_pix, int C, int pin, int cin_off, int pout,
-                        hipStream_t s);
 void launch_deeponet_out_group(const OutMember* d_mem, int n, int64_t max_npix, int c0, int fold_pitch,
                                const float* gamma, hipStream_t s);
 void launch_pack_weights(const float* w, int cout, int cin, int cin8, int taps, int Kp, bf16_t* out, hipStream_t s);

@@ -378,7 +378,7 @@ extern "C" ppe_status ppe_net_train_step(ppe_net* n, int32_t nb, ppe_problem* co
       }
     auto etap = [&](int64_t off) -> const bf16_t* { return cfg.use_eta ? E + off : nullptr; };
     auto geo = [&](int l, int cin8, int cout, int y_pitch, int y_off, int act) {
-      ConvGeo g;
+      ConvGeo g{};
       g.H = t->H[l];
       g.W = t->W[l];
       g.cin8 = cin8;
