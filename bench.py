@@ -132,6 +132,8 @@ def hybrid_run(ppe, torch, prob, f, x, args, net=None, name=None):
         else:
             name = "default network (4 levels, 32-256 channels), seeded random initialisation (control)"
     o = ppe.ppe_solve_opts_default(tol=args.tol, zero_x0=1, max_iter=args.hybrid_max_iter)
+    # the forward's tile widths tuned on this grid, as the plain solve's launch configuration is
+    tiles = ppe.ppe_tune_net(net, prob, nb=1, reps=10)
     ppe.ppe_solve_hybrid(prob, net, f, x, o)
     torch.cuda.synchronize()
     steps = max(1, min(args.steps, 2))
@@ -147,7 +149,9 @@ def hybrid_run(ppe, torch, prob, f, x, args, net=None, name=None):
            "iters": s0["iters_total"], "iters_cg": s0["iters_cg"], "iters_dlsm": s0["iters_dlsm"],
            "dlsm_rejected": s0["dlsm_rejected"], "rel_res_true": s0["rel_res_true"],
            "max_iter": args.hybrid_max_iter, "num_cg": 3, "num_dlsm": 2,
-           "ms_pcg": s0["ms_pcg"], "ms_net": s0["ms_net"], "ms_dlsm": s0["ms_dlsm"]}
+           "ms_pcg": s0["ms_pcg"], "ms_net": s0["ms_net"], "ms_dlsm": s0["ms_dlsm"],
+           "net_tiles_tuned": {"32": sum(t == 32 for t, _, _ in tiles.values()),
+                               "64": sum(t == 64 for t, _, _ in tiles.values())}}
     return out
 
 
@@ -405,6 +409,8 @@ def main():
     ap.add_argument("--network-forward", type=int, default=0, metavar="K",
                     help="time K forwards of the default DeepONet (random weights) on the workload's grid "
                          "instead (for kernel traces of the network)")
+    ap.add_argument("--tune-net", action="store_true",
+                    help="with --network-forward: also time the forward after tile-width tuning")
     ap.add_argument("--train-step", type=int, default=0, metavar="K",
                     help="time K training steps (forward, backward, Adam) of the default DeepONet on a pool of "
                          "--train-batch fabricated n x n systems instead (use with --n 256)")
@@ -468,8 +474,19 @@ def main():
             ppe.ppe_net_forward(net, prob, r, y)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / args.network_forward * 1e3
-        print(json.dumps({"network_forward_ms": ms, "grid": [g.nx, g.ny], "forwards": args.network_forward}),
-              flush=True)
+        line = {"network_forward_ms": ms, "grid": [g.nx, g.ny], "forwards": args.network_forward}
+        if args.tune_net:  # the same after tile-width tuning on this grid
+            tiles = ppe.ppe_tune_net(net, prob, nb=1, reps=20)
+            for _ in range(3):
+                ppe.ppe_net_forward(net, prob, r, y)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.network_forward):
+                ppe.ppe_net_forward(net, prob, r, y)
+            torch.cuda.synchronize()
+            line["network_forward_tuned_ms"] = (time.perf_counter() - t0) / args.network_forward * 1e3
+            line["tuned_tiles"] = {k: t for k, (t, _, _) in tiles.items()}
+        print(json.dumps(line), flush=True)
         return
 
     variant = {"auto": ppe.PPE_PCG_AUTO, "single": ppe.PPE_PCG_SINGLE_REDUCTION,

@@ -433,6 +433,33 @@ typedef struct {
 ppe_status ppe_tune_pcg(ppe_problem* p, int32_t nb, const float* f, double* x, int32_t reps,
                         ppe_tune_result* out, hipStream_t s);
 ppe_status ppe_set_tuning(ppe_problem* p, int32_t nb, int32_t variant, int32_t rows_per_wave);
+
+/* Launch-configuration tuning of the network forward (the Sec. 2.4 network)
+ * on one grid, per problem, network and batch size nb: every 3x3 or 1x1
+ * up-convolution with at least 64 output channels can run with 32 or 64
+ * output channels per workgroup (more workgroups and occupancy, or fewer
+ * re-reads of the input). By default a layer takes 64 when that still gives
+ * at least two workgroups per compute unit, else 32. ppe_tune_net runs the
+ * forward once on nb zero fields, then times each such launch `reps` times
+ * (HIP events) with either width and keeps the default unless the other is
+ * more than 3 % faster; later forwards of this problem with this network use
+ * the choice (a tile width can change a layer's K split, so outputs may
+ * differ from the untuned ones in rounding). In the grouped forward of a
+ * mixed-size batch each grid keeps the K split of its own (tuned or default)
+ * width, so its result stays bit-identical. The choice is dropped when the
+ * problem's network buffers are rebuilt (another network or a larger nb).
+ * out (host, optional): n = launches of one forward; for launch k the chosen
+ * width (0 where there is no choice) and the measured microseconds per
+ * launch with either width (0 where not timed). reps in [1, 1000]. */
+#define PPE_NET_MAX_LAUNCHES 64
+typedef struct {
+  int32_t n;
+  int32_t tile[PPE_NET_MAX_LAUNCHES];
+  float us32[PPE_NET_MAX_LAUNCHES];
+  float us64[PPE_NET_MAX_LAUNCHES];
+} ppe_net_tune_result;
+ppe_status ppe_tune_net(ppe_net* n, ppe_problem* p, int32_t nb, int32_t reps, ppe_net_tune_result* out,
+                        hipStream_t s);
 ppe_status ppe_get_tuning(const ppe_problem* p, int32_t nb, int32_t* variant, int32_t* rows_per_wave);
 
 /* Average kernel durations in ms of the PCG iteration on nb systems, for the

@@ -452,6 +452,7 @@ struct FwdOp {
   bf16_t* y = nullptr;
   float* kpart = nullptr;
   int64_t kpart_elems = 0;
+  int tn = 0;  // output channels per workgroup (0: the default)
   // OUT
   int c0 = 0, fold_pitch = 0;
   const bf16_t* d0 = nullptr;
@@ -499,6 +500,7 @@ static void forward_ops(const ppe_problem* p, const ppe_net* n, const NetCache* 
     o.y = yo;
     o.kpart = c->d_kpart;
     o.kpart_elems = c->kpart_elems;
+    o.tn = ops.size() < sizeof(c->conv_tn) ? c->conv_tn[ops.size()] : 0;
     ops.push_back(o);
   };
   for (int l = 0; l < L; ++l) {
@@ -547,23 +549,87 @@ static void forward_ops(const ppe_problem* p, const ppe_net* n, const NetCache* 
   ops.push_back(o);
 }
 
+// One launch of the forward over nb samples.
+static void launch_op(const FwdOp& o, int nb, hipStream_t s) {
+  switch (o.kind) {
+    case FwdOp::PACK: launch_input_pack(o.r, o.n, nb, o.part, o.xin, o.pitch, o.bstride, s); break;
+    case FwdOp::CONV:
+      launch_conv(o.taps, o.up, o.g, nb, o.x, o.eta, o.wp, o.Kp, o.bias, o.y, s, o.kpart, o.kpart_elems, o.tn);
+      break;
+    case FwdOp::OUT: launch_deeponet_out(o.n, o.c0, o.d0, o.d_bs, o.fold, o.fold_pitch, o.gamma, o.yout, nb, s); break;
+  }
+}
+
 // y = NN(r) for nb residual fields of one grid (device FP32 in and out).
 ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float* y, hipStream_t s) {
   ppe_status st = net_cache_ensure(p, n, nb, s);
   if (st != PPE_OK) return st;
   std::vector<FwdOp> ops;
   forward_ops(p, n, p->net_cache, r, y, ops);
-  for (const FwdOp& o : ops) {
-    switch (o.kind) {
-      case FwdOp::PACK: launch_input_pack(o.r, o.n, nb, o.part, o.xin, o.pitch, o.bstride, s); break;
-      case FwdOp::CONV:
-        launch_conv(o.taps, o.up, o.g, nb, o.x, o.eta, o.wp, o.Kp, o.bias, o.y, s, o.kpart, o.kpart_elems);
-        break;
-      case FwdOp::OUT: launch_deeponet_out(o.n, o.c0, o.d0, o.d_bs, o.fold, o.fold_pitch, o.gamma, o.yout, nb, s); break;
-    }
-  }
+  for (const FwdOp& o : ops) launch_op(o, nb, s);
   HIPCHK(hipGetLastError());
   return PPE_OK;
+}
+
+// Tile-width tuning of the forward's convolutions on one grid (see
+// ppe_tune_net): each launch with a choice timed alone with either width.
+static ppe_status tune_net_impl(ppe_problem* p, ppe_net* n, int nb, int reps, ppe_net_tune_result* out,
+                                hipStream_t s) {
+  ppe_status st = net_cache_ensure(p, n, nb, s);
+  if (st != PPE_OK) return st;
+  NetCache* c = p->net_cache;
+  const int64_t N = (int64_t)p->nx * p->ny;
+  float* r = (float*)dev_alloc((size_t)nb * N * sizeof(float) * 2);
+  if (!r) return set_error(PPE_ERR_HIP, "allocation of the tuning fields failed");
+  float* y = r + (size_t)nb * N;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto done = [&](ppe_status res) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    dev_free(r);
+    return res;
+  };
+  if (hipMemsetAsync(r, 0, (size_t)nb * N * sizeof(float), s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess)
+    return done(set_error(PPE_ERR_HIP, "tuning set-up failed"));
+  std::vector<FwdOp> ops;
+  for (int8_t& t : c->conv_tn) t = 0;
+  forward_ops(p, n, c, r, y, ops);
+  if (ops.size() > sizeof(c->conv_tn)) return done(set_error(PPE_ERR_UNSUPPORTED, "too many launches to tune"));
+  for (const FwdOp& o : ops) launch_op(o, nb, s);  // every buffer holds its layer's output
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    out->n = (int32_t)ops.size();
+  }
+  for (size_t k = 0; k < ops.size(); ++k) {
+    FwdOp o = ops[k];
+    if (o.kind != FwdOp::CONV || !conv_has_tile_choice(o.taps, o.up, o.eta != nullptr, o.g, o.Kp)) continue;
+    float us[2] = {0.f, 0.f};
+    for (int w = 0; w < 2; ++w) {
+      o.tn = w ? 64 : 32;
+      launch_op(o, nb, s);  // warm-up
+      if (hipEventRecord(e0, s) != hipSuccess) return done(set_error(PPE_ERR_HIP, "hipEventRecord failed"));
+      for (int i = 0; i < reps; ++i) launch_op(o, nb, s);
+      float ms = 0.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        return done(set_error(PPE_ERR_HIP, "timing of launch %zu failed", k));
+      us[w] = ms * 1e3f / (float)reps;
+    }
+    // the default width unless the other is more than 3 % faster
+    const int def = conv_default_tile(o.g, nb);
+    const float ud = def == 64 ? us[1] : us[0], uo = def == 64 ? us[0] : us[1];
+    const int choice = uo < 0.97f * ud ? 96 - def : def;
+    c->conv_tn[k] = (int8_t)choice;
+    if (out) {
+      out->tile[k] = choice;
+      out->us32[k] = us[0];
+      out->us64[k] = us[1];
+    }
+  }
+  if (hipGetLastError() != hipSuccess) return done(set_error(PPE_ERR_HIP, "tuning launches failed"));
+  return done(PPE_OK);
 }
 
 // ---------------------------------------------------------------------------
@@ -615,6 +681,7 @@ static ppe_status group_part(const std::vector<std::vector<FwdOp>>& ops, const s
           m[i].eta = o.eta;
           m[i].y = o.y;
           m[i].kpart = o.kpart;
+          m[i].tn = o.tn;
           m[i].skip = sk(i);
         }
         if (!plan_conv_group(o0.taps, o0.up, m, o0.kpart_elems, q.conv))
@@ -858,6 +925,16 @@ ppe_status ppe_net_forward_batch(ppe_net* n, int32_t count, ppe_problem* const* 
   if (st != PPE_OK) return st;
   if (e != hipSuccess) return set_error(PPE_ERR_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
   return PPE_OK;
+}
+
+ppe_status ppe_tune_net(ppe_net* n, ppe_problem* p, int32_t nb, int32_t reps, ppe_net_tune_result* out,
+                        hipStream_t s) {
+  if (!n || !p) return set_error(PPE_ERR_INVALID_ARG, "net or problem NULL");
+  if (nb < 1 || nb > 4096 || reps < 1 || reps > 1000)
+    return set_error(PPE_ERR_INVALID_ARG, "nb in [1, 4096] and reps in [1, 1000]");
+  ppe_status st = check_net_grid(p, n);
+  if (st != PPE_OK) return st;
+  return tune_net_impl(p, n, nb, reps, out, s);
 }
 
 ppe_status ppe_net_forward(ppe_net* n, ppe_problem* p, int32_t nb, const float* r, float* y, hipStream_t s) {

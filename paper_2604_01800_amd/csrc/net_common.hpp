@@ -81,6 +81,8 @@ struct ConvMember {
   int nwt;              // workgroups per K share (runs of tiles)
   int ks;               // K shares: the split the member's own launch uses
   int kwg0;             // first workgroup of the member in the K-split sum (none without a split)
+  int tn;               // the member's own tile width (0: the default), which sets that split
+  int pad_;
 };
 struct PackMember {     // input scaling (sum of squares, then the packed input)
   const float* r;

@@ -67,6 +67,7 @@ struct NetCache {
   double* d_part = nullptr;
   float* d_kpart = nullptr;  // partial sums of convolutions with a split K loop
   int64_t kpart_elems = 0;
+  int8_t conv_tn[64] = {};   // tuned output channels per workgroup of forward launch k (0: the default)
 };
 
 // One layer of a grouped forward: its member table (at d_tab + off) and the

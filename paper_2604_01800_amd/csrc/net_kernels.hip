@@ -1035,25 +1035,36 @@ static int conv_per_cu() {
 
 static int conv_tiles(const ConvGeo& g) { return ((g.W + kCTW - 1) / kCTW) * ((g.H + kCTH - 1) / kCTH); }
 
-// K shares of a layer's launch over nb samples. Layers with fewer workgroups
-// than compute units (the coarse levels of small grids) split their chunks of
-// input channels over up to ceil(cus / workgroups) workgroups, when the
-// caller gave room for the partials. A grouped launch applies the same rule
-// to each member alone, so that a member's sums are those of its own launch.
-template <int TN, int TAPS>
-static int conv_ksplit(const ConvGeo& g, int nb, bool have_kpart, int64_t kpart_elems) {
-  const int cot = (g.cout + TN - 1) / TN;
+// K shares of a layer's launch over nb samples with tn output channels per
+// workgroup. Layers with fewer workgroups than compute units (the coarse
+// levels of small grids) split their nch chunks of input channels over up to
+// ceil(cus / workgroups) workgroups, when the caller gave room for the
+// partials (cp: the channel pitch of the launch's partials). A grouped launch
+// applies the same rule to each member alone, with the member's own tn, so
+// that a member's sums are those of its own launch.
+static int conv_ksplit(const ConvGeo& g, int nb, int tn, int nch, bool have_kpart, int64_t kpart_elems, int cp) {
+  const int cot = (g.cout + tn - 1) / tn;
   const int cus = conv_device_cus();
   const int64_t wgs = (int64_t)conv_tiles(g) * cot * nb;
-  const int nch = (g.cin8 + ConvShape<TN, TAPS>::CK - 1) / ConvShape<TN, TAPS>::CK;
   int ks = 1;
   if (have_kpart && wgs < cus && nch > 1 && g.cout % 4 == 0) {
     ks = (int)std::min<int64_t>(nch, (cus + wgs - 1) / wgs);
     const int cps = (nch + ks - 1) / ks;
     ks = (nch + cps - 1) / cps;  // no empty shares
-    if ((int64_t)ks * nb * g.H * g.W * cot * TN > kpart_elems) ks = 1;
+    if ((int64_t)ks * nb * g.H * g.W * cp > kpart_elems) ks = 1;
   }
   return ks;
+}
+
+// Output channels per workgroup by default: 64 when the layer has at least
+// 64 output channels and still at least two workgroups per compute unit with
+// them (each staged input chunk then serves twice the channels), else 32
+// (twice the workgroups). Measured per layer on 64^2 to 1024^2 grids, the
+// wider tile won only above that count.
+int conv_default_tile(const ConvGeo& g, int nb) {
+  if (g.cout < 64) return 32;
+  const int64_t wgs64 = (int64_t)conv_tiles(g) * ((g.cout + 63) / 64) * nb;
+  return wgs64 >= 2 * (int64_t)conv_device_cus() ? 64 : 32;
 }
 
 template <int TN, int TAPS, bool UP, int ETA>
@@ -1064,7 +1075,7 @@ static void conv_go_eta(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t*
   const int cus = conv_device_cus();
   const int64_t wgs = (int64_t)tiles * cot * nb;
   const int nch = (g.cin8 + ConvShape<TN, TAPS>::CK - 1) / ConvShape<TN, TAPS>::CK;
-  const int ks = conv_ksplit<TN, TAPS>(g, nb, kpart != nullptr, kpart_elems);
+  const int ks = conv_ksplit(g, nb, TN, nch, kpart != nullptr, kpart_elems, cot * TN);
   // one chunk per workgroup: the weight slice is staged once
   const bool wstat = (nch + ks - 1) / ks == 1;
   // runs of tiles that fill the resident workgroups once
@@ -1095,7 +1106,9 @@ static void conv_group_plan_t(std::vector<ConvMember>& m, int64_t kpart_elems, C
   int64_t wgs = 0, kwg = 0;
   bool wstat = true;
   for (ConvMember& e : m) {
-    e.ks = conv_ksplit<TN, TAPS>(e.g, 1, e.kpart != nullptr, kpart_elems);
+    // the K split of the member's own launch (its own tile width)
+    e.ks = conv_ksplit(e.g, 1, e.tn ? e.tn : conv_default_tile(e.g, 1), nch, e.kpart != nullptr, kpart_elems,
+                       cot * TN);
     wgs += (int64_t)conv_tiles(e.g) * cot * e.ks;
     wstat = wstat && (nch + e.ks - 1) / e.ks == 1;
     e.kwg0 = (int)kwg;
@@ -1168,7 +1181,14 @@ bool plan_conv_group(int taps, bool up, std::vector<ConvMember>& m, int64_t kpar
   L.taps = taps;
   L.up = up;
   L.eta = conv_eta_mode(m[0]);
-  return conv_group_dispatch(taps, up, L.eta, m[0].g.cout >= 64, [&](auto tn, auto tp, auto upc, auto et) {
+  // the group's tile width by the default rule over all members' workgroups
+  bool wide = false;
+  if (m[0].g.cout >= 64) {
+    int64_t wgs64 = 0;
+    for (const ConvMember& e : m) wgs64 += (int64_t)conv_tiles(e.g) * ((e.g.cout + 63) / 64);
+    wide = wgs64 >= 2 * (int64_t)conv_device_cus();
+  }
+  return conv_group_dispatch(taps, up, L.eta, wide, [&](auto tn, auto tp, auto upc, auto et) {
     conv_group_plan_t<decltype(tn)::value, decltype(tp)::value, decltype(upc)::value, decltype(et)::value>(
         m, kpart_elems, L);
   });
@@ -1208,8 +1228,14 @@ static void conv1x1_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* 
   k_conv1x1<MT><<<dim3(per_smp, nb), 256, 0, s>>>(g, x, wp, Kp, bias, y);
 }
 
+bool conv_has_tile_choice(int taps, bool up, bool has_eta, const ConvGeo& g, int Kp) {
+  const bool skinny = taps == 1 && !up && !has_eta && !g.x1 && g.cout <= 128 && Kp <= 128 && g.y_pitch % 8 == 0 &&
+                      g.y_off % 8 == 0;
+  return !skinny && g.cout >= 64;
+}
+
 void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
-                 int Kp, const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems) {
+                 int Kp, const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems, int tn) {
   if (taps == 1 && !up && !eta && !g.x1 && g.cout <= 128 && Kp <= 128 && g.y_pitch % 8 == 0 && g.y_off % 8 == 0) {
     // small 1x1 layers: the skinny GEMM, one round of resident workgroups
     // over all samples
@@ -1218,7 +1244,7 @@ void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, c
     else conv1x1_go<8>(g, nb, x, wp, Kp, bias, y, s);
     return;
   }
-  const bool wide = g.cout >= 64;
+  const bool wide = (tn ? tn : conv_default_tile(g, nb)) == 64;
   if (taps == 9) {
     if (wide) conv_go<64, 9, false>(g, nb, x, eta, wp, Kp, bias, y, s, kpart, kpart_elems);
     else conv_go<32, 9, false>(g, nb, x, eta, wp, Kp, bias, y, s, kpart, kpart_elems);

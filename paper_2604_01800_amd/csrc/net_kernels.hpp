@@ -19,9 +19,14 @@ struct TrunkDesc {
 int64_t conv_kpart_elems();
 // kpart (optional, kpart_elems floats): room for FP32 partial sums, which lets
 // layers with fewer workgroups than compute units split their K loop.
+// tn: output channels per workgroup (32 or 64; 0: conv_default_tile).
 void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
                  int Kp, const float* bias, bf16_t* y, hipStream_t s, float* kpart = nullptr,
-                 int64_t kpart_elems = 0);
+                 int64_t kpart_elems = 0, int tn = 0);
+// The default tn of a layer over nb samples.
+int conv_default_tile(const ConvGeo& g, int nb);
+// Whether launch_conv has a choice of tn for this layer.
+bool conv_has_tile_choice(int taps, bool up, bool has_eta, const ConvGeo& g, int Kp);
 // Grouped convolution (one layer of the forwards of several grids): the
 // launch shape that plan_conv_group derives from the members (their g, x,
 // eta, y, kpart and skip set by the caller; it fills wg0, nwt and ks). Only

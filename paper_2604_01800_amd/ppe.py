@@ -53,6 +53,14 @@ class ppe_tune_result(ctypes.Structure):
                 ("us_per_iter", (ctypes.c_double * 6) * 3)]
 
 
+PPE_NET_MAX_LAUNCHES = 64
+
+
+class ppe_net_tune_result(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("tile", ctypes.c_int32 * PPE_NET_MAX_LAUNCHES),
+                ("us32", ctypes.c_float * PPE_NET_MAX_LAUNCHES), ("us64", ctypes.c_float * PPE_NET_MAX_LAUNCHES)]
+
+
 class ppe_solve_stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters_total", ctypes.c_int32), ("iters_cg", ctypes.c_int32),
                 ("iters_dlsm", ctypes.c_int32), ("dlsm_rejected", ctypes.c_int32),
@@ -121,6 +129,7 @@ SIGNATURES = {
     "ppe_net_load": (_i32, [_vp, ctypes.c_char_p]),
     "ppe_net_forward": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
     "ppe_net_forward_batch": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "ppe_tune_net": (_i32, [_vp, _vp, _i32, _i32, _P(ppe_net_tune_result), _vp]),
     "ppe_net_train_step": (_i32, [_vp, _i32, _vp, _vp, _vp, _P(ppe_train_opts), _vp, _vp, _vp]),
     "ppe_profile_pcg": (_i32, [_vp, _i32, _vp, _vp, _P(ppe_solve_opts), _i32, _vp, _vp]),
     "ppe_profile_copy": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),
@@ -415,6 +424,15 @@ def ppe_net_forward(net: Net, prob: Problem, r, y, stream=None):
     nb = _nb(r, prob)
     _check(lib().ppe_net_forward(net.handle, prob.handle, nb, _dev(r, torch.float32, "r"),
                                  _dev(y, torch.float32, "y"), _stream(stream)))
+
+
+def ppe_tune_net(net: Net, prob: Problem, nb: int = 1, reps: int = 20, stream=None):
+    """Tile-width tuning of the network forward on prob's grid for batch
+    size nb (stored in the problem); returns the per-launch choices
+    {k: (tile, us32, us64)} for the launches that have a choice."""
+    res = ppe_net_tune_result()
+    _check(lib().ppe_tune_net(net.handle, prob.handle, nb, reps, ctypes.byref(res), _stream(stream)))
+    return {k: (res.tile[k], res.us32[k], res.us64[k]) for k in range(res.n) if res.tile[k]}
 
 
 def ppe_net_forward_batch(net: Net, probs, rs, ys, stream=None):

@@ -15,7 +15,7 @@ from paper_2604_01800_amd import ppe
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ppe.h")
 STRUCTS = ["ppe_grid_desc", "ppe_solve_opts", "ppe_solve_stats", "ppe_net_config", "ppe_train_opts",
-           "ppe_tune_result"]
+           "ppe_tune_result", "ppe_net_tune_result"]
 
 
 def declared_functions():

@@ -195,6 +195,23 @@ def test_forward_batch_equals_single_forwards(ppe, use_eta, shapes):
     assert torch.equal(y3, ys[2])
 
 
+def test_forward_batch_with_tuned_members(ppe):
+    """Grids whose forward was tile-width tuned keep, inside the grouped
+    launch, the K split of their own tuned width: still bit-identical."""
+    net = ppe.Net(ppe.ppe_net_config_default(), seed=5)
+    sys_ = systems(FWD_SHAPES, seed=9)
+    probs = [ppe.ppe_problem_create(g) for g, _ in sys_]
+    for k in (0, 4):
+        ppe.ppe_tune_net(net, probs[k], nb=1, reps=3)
+    rs = [torch.from_numpy(f).cuda() for _, f in sys_]
+    ys = [torch.zeros_like(r) for r in rs]
+    ppe.ppe_net_forward_batch(net, probs, rs, ys)
+    for p, r, y in zip(probs, rs, ys):
+        y1 = torch.zeros((1,) + tuple(r.shape), dtype=torch.float32, device="cuda")
+        ppe.ppe_net_forward(net, p, r[None], y1)
+        np.testing.assert_array_equal(y.cpu().numpy(), y1[0].cpu().numpy())
+
+
 def test_forward_batch_checks(ppe):
     net = ppe.Net(ppe.ppe_net_config_default(), seed=5)
     sys_ = systems(FWD_SHAPES[:2], seed=8)

@@ -74,6 +74,41 @@ def test_forward_matches_oracle(ppe, nx, ny, bx, by, L, C, eta, sp, nb):
         assert e <= 2e-2, (s, e)
 
 
+@pytest.mark.parametrize("nx,ny,eta,nb", [(64, 64, 2, 1), (256, 256, 2, 1), (128, 96, 1, 2)])
+def test_tuned_forward_matches_oracle(ppe, nx, ny, eta, nb):
+    """Tile-width tuning of the forward's convolutions: every layer with a
+    choice gets 32 or 64 and both were timed, the tuned forward is
+    deterministic and as close to the oracle as the default one (widths
+    change only a layer's K split), and bad arguments are rejected."""
+    cfg = onet.NetConfig(use_eta=eta)
+    g = inputs.with_ellipse(inputs.make_grid(nx, ny, 1.6, 1.3), np.random.default_rng(nx))
+    net, p = make_net(ppe, cfg, seed=nx + 1)
+    prob = ppe.ppe_problem_create(g)
+    r = np.stack([inputs.grf(g, s, ell=0.1) * np.outer(g.hy, g.hx) for s in range(nb)]).astype(np.float32)
+    rd = torch.from_numpy(r).cuda()
+    y0 = torch.zeros((nb, ny, nx), dtype=torch.float32, device="cuda")
+    ppe.ppe_net_forward(net, prob, rd, y0)  # default widths
+    res = ppe.ppe_tune_net(net, prob, nb=nb, reps=5)
+    assert res and all(t in (32, 64) and u32 > 0 and u64 > 0 for t, u32, u64 in res.values())
+    y = torch.zeros_like(y0)
+    ppe.ppe_net_forward(net, prob, rd, y)
+    y2 = torch.zeros_like(y)
+    ppe.ppe_net_forward(net, prob, rd, y2)
+    assert torch.equal(y, y2)
+    yg, y0g = y.cpu().numpy(), y0.cpu().numpy()
+    for s in range(nb):
+        with torch.no_grad():
+            yo = onet.forward(p, cfg, g, r[s].astype(np.float64), g.mask)[0].numpy()
+        e0, e1 = rel(y0g[s], yo), rel(yg[s], yo)
+        print(f"{nx}x{ny} sample {s}: error default {e0:.4e}, tuned {e1:.4e}")
+        # within the forward's bar, or (an input whose BF16 error already
+        # reaches it with the default widths) no worse than the default
+        assert e1 <= max(2e-2, e0 + 1e-3)
+    print(f"{nx}x{ny} tuned widths:", {k: v[0] for k, v in res.items()})
+    with pytest.raises(ppe.PPEError):
+        ppe.ppe_tune_net(net, prob, nb=nb, reps=0)
+
+
 def test_forward_full_size_512(ppe):
     """512 x 512 (the hybrid-inference grid size) with the default network:
     sampled rows checked against the oracle on the full field."""
