@@ -325,6 +325,7 @@ ppe_status net_cache_ensure(ppe_problem* p, ppe_net* n, int nb, hipStream_t s) {
         c->o_cat[l] = act(l, c->p_cat[l]);
         c->o_c[l] = act(l, ch);
         c->o_d[l] = act(l, ch);
+        c->o_up[l] = act(l + 1, ch);  // the up-convolution's output, at level l + 1's resolution
       } else {
         c->o_bot = act(l, ch);
       }
@@ -525,14 +526,19 @@ static void forward_ops(const ppe_problem* p, const ppe_net* n, const NetCache* 
   for (int l = L - 2; l >= 0; --l) {
     const UpL& u = n->up[l];
     const bf16_t* src = (l == L - 2) ? A + c->o_bot : A + c->o_d[l + 1];
-    ConvGeo gu = geo(c, l + 1, u.cin, u.cout, c->p_cat[l], 0, 1);
-    gu.y_bstride = (int64_t)c->H[l] * c->W[l] * c->p_cat[l];
+    // the 1x1 up-convolution at the coarse level; the next convolution reads
+    // its output through the nearest upsampling as its first C_l channels
+    ConvGeo gu = geo(c, l + 1, u.cin, u.cout, ch(l), 0, 1);
     gu.act = 0;
-    conv(1, true, gu, src, nullptr, n->d_pack + u.opack, u.kp, n->d_w + u.ob, A + c->o_cat[l]);
+    conv(1, false, gu, src, nullptr, n->d_pack + u.opack, u.kp, n->d_w + u.ob, A + c->o_up[l]);
     const MConvL& mc = n->dec_c[l];
     const MConvL& md = n->dec_d[l];
-    conv(9, false, with_static(c, geo(c, l, mc.cin8, mc.cout, ch(l), 0, 1, c->p_cat[l]), l, A), A + c->o_cat[l],
-         eta(c->eta_c[l]), n->d_pack + mc.opack, mc.kp, n->d_w + mc.ob, A + c->o_c[l]);
+    ConvGeo gc = with_static(c, geo(c, l, mc.cin8, mc.cout, ch(l), 0, 1, c->p_cat[l]), l, A);
+    gc.xu = A + c->o_up[l];
+    gc.cu = ch(l);
+    gc.xu_pitch = ch(l);
+    gc.xu_bstride = (int64_t)c->H[l + 1] * c->W[l + 1] * ch(l);
+    conv(9, false, gc, A + c->o_cat[l], eta(c->eta_c[l]), n->d_pack + mc.opack, mc.kp, n->d_w + mc.ob, A + c->o_c[l]);
     conv(9, false, geo(c, l, md.cin8, md.cout, ch(l), 0, 1), A + c->o_c[l], eta(c->eta_d[l]), n->d_pack + md.opack,
          md.kp, n->d_w + md.ob, A + c->o_d[l]);
   }
@@ -684,7 +690,7 @@ static ppe_status group_part(const std::vector<std::vector<FwdOp>>& ops, const s
           m[i].tn = o.tn;
           m[i].skip = sk(i);
         }
-        if (!plan_conv_group(o0.taps, o0.up, m, o0.kpart_elems, q.conv))
+        if (!plan_conv_group(o0.taps, o0.up, o0.Kp, m, o0.kpart_elems, q.conv))
           return set_error(PPE_ERR_UNSUPPORTED, "layer %zu has no grouped form", k);
         q.wp = o0.wp;
         q.Kp = o0.Kp;

@@ -50,6 +50,13 @@ struct ConvGeo {
   int x1_pitch;      // channels per pixel of x1
   const bf16_t* x1;    // second input buffer (channels c1 .. cin8-1), or null when c1 = cin8
   int64_t x1_bstride;  // elements between samples of x1 (0 = shared by the batch)
+  // optional coarse source: input channels [0, cu) come from xu, a buffer at
+  // half the resolution (pixel (y, x) reads (y / 2, x / 2): the nearest
+  // upsampling of its values), pitch xu_pitch; cu a multiple of 32, cu <= c1
+  const bf16_t* xu;
+  int cu;
+  int xu_pitch;
+  int64_t xu_bstride;
   int cout;          // output channels
   int y_pitch;       // output buffer pitch (channels per pixel)
   int y_off;         // first output channel in that buffer

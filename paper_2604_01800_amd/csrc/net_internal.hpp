@@ -63,7 +63,7 @@ struct NetCache {
   // live in o_st, one copy shared by the batch, pitch 8)
   int p_in[kMaxLevels] = {}, p_cat[kMaxLevels] = {};
   int64_t o_in[kMaxLevels] = {}, o_a[kMaxLevels] = {}, o_cat[kMaxLevels] = {}, o_c[kMaxLevels] = {},
-          o_d[kMaxLevels] = {}, o_st[kMaxLevels] = {}, o_bot = 0;
+          o_d[kMaxLevels] = {}, o_st[kMaxLevels] = {}, o_up[kMaxLevels] = {}, o_bot = 0;
   double* d_part = nullptr;
   float* d_kpart = nullptr;  // partial sums of convolutions with a split K loop
   int64_t kpart_elems = 0;

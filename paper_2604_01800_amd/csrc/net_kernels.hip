@@ -164,19 +164,50 @@ __device__ __forceinline__ void conv_commit_w(const uint4* w, int ck8, bf16_t* s
 // Issues the loads of one item: thread t stages the 8-channel group t % G8 of
 // the halo pixels t / G8, t / G8 + PPR, ... and a share of the weight slice
 // (unless the slice is already in LDS). Inputs are read through buffer
-// resources over one sample: input channels below g.c1 from the input
-// buffer (xr), the others from the second source (x1r). On a tile whose halo
+// resources over one sample: input channels below g.cu from the coarse
+// source (xur, half the resolution), those below g.c1 from the input buffer
+// (xr), the others from the second source (x1r). On a tile whose halo
 // lies inside the image and a full chunk of the input buffer, every offset is
 // this thread's fixed one plus a scalar base; otherwise halo pixels outside
 // the image (and channel groups past the chunk or in the other source) get
 // an offset past the end, which reads as zero.
-template <int TN, int TAPS, int ETA>
+template <int TN, int TAPS, int ETA, bool XU>
 __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS, ETA>& st, const ConvLane<TN, TAPS>& ln,
                                            const ConvGeo& g, __amdgpu_buffer_rsrc_t xr, __amdgpu_buffer_rsrc_t x1r,
-                                           __amdgpu_buffer_rsrc_t er, __amdgpu_buffer_rsrc_t wr, int Kp, int co0,
-                                           int py0, int px0, int c0, int ck8, int kbase, bool fast, bool wload) {
+                                           __amdgpu_buffer_rsrc_t xur, __amdgpu_buffer_rsrc_t er,
+                                           __amdgpu_buffer_rsrc_t wr, int Kp, int co0, int py0, int px0, int c0,
+                                           int ck8, int kbase, bool fast, bool fastu, bool wload) {
   using S = ConvShape<TN, TAPS>;
-  if (fast) {
+  if (XU && fastu) {
+    // a full chunk of the coarse source on an interior tile: halo pixel
+    // (ly, lx) reads coarse pixel (py0 / 2 - 1 + (ly + 1) / 2, px0 / 2 - 1 +
+    // (lx + 1) / 2) (py0, px0 even), a per-thread offset plus a scalar base
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int c8 = tid % S::G8;
+    const int Wc = g.W >> 1;
+    const int ubase = ((py0 >> 1) - S::HALO) * Wc + ((px0 >> 1) - S::HALO);
+    const int xb = (ubase * g.xu_pitch + c0) * 2;
+    const int pbase = (py0 - S::HALO) * g.W + (px0 - S::HALO);
+#pragma unroll
+    for (int i = 0; i < S::NU; ++i) {
+      const int pix = tid / S::G8 + S::PPR * i;
+      const int ly = pix / S::LW, lx = pix - ly * S::LW;
+      const bool ok = pix < S::NPIX;
+      const uint32_t rel = (uint32_t)(((ly + S::HALO) >> 1) * Wc + ((lx + S::HALO) >> 1));
+      const uint32_t off = ok ? rel * (uint32_t)(g.xu_pitch * 2) + (uint32_t)c8 * 16u : 0x80000000u;
+      st.x[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xur, (int)off, xb, 0));
+      if constexpr (ETA == kEtaNode) {
+        const uint32_t eo = ok ? (uint32_t)(ly * g.W + lx) * 2u : 0x80000000u;
+        st.e1[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(er, (int)eo, pbase * 2, 0);
+      }
+      if constexpr (ETA == kEtaChannel) {  // the map is laid out with pitch cin8
+        const uint32_t eo = ok ? (uint32_t)(ly * g.W + lx) * (uint32_t)(g.cin8 * 2) + (uint32_t)(c0 + c8 * 8) * 2u
+                               : 0x80000000u;
+        st.e[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(er, (int)eo, pbase * g.cin8 * 2, 0));
+      }
+    }
+  } else if (fast) {
     const ConvLane<TN, TAPS> lf = kKeepLane<TN> ? ln : conv_lane<TN, TAPS>(g);
     const int pbase = (py0 - S::HALO) * g.W + (px0 - S::HALO);  // first halo pixel (>= 0 here)
     const int xb = (pbase * g.x_pitch + c0) * 2;
@@ -195,9 +226,9 @@ __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS, ETA>& st, const C
     const int c8 = tid % S::G8;
     const int cg = c0 + c8 * 8;  // this thread's first input channel
     const bool cg_ok = c8 < ck8;
-    const bool src1 = cg >= g.c1;
+    const bool srcu = XU && cg < g.cu, src1 = cg >= g.c1;
     // sources the chunk touches (uniform)
-    const bool any0 = c0 < g.c1, any1 = c0 + ck8 * 8 > g.c1;
+    const bool anyu = XU && c0 < g.cu, any0 = c0 < g.c1 && (!XU || c0 + ck8 * 8 > g.cu), any1 = c0 + ck8 * 8 > g.c1;
 #pragma unroll
     for (int i = 0; i < S::NU; ++i) {
       const int pix = tid / S::G8 + S::PPR * i;
@@ -206,9 +237,16 @@ __device__ __forceinline__ void conv_issue(ConvStage<TN, TAPS, ETA>& st, const C
       const bool in = cg_ok && pix < S::NPIX && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W;
       const uint32_t pi = (uint32_t)(gy * g.W + gx);
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (anyu) {
+        const uint32_t pu = (uint32_t)((gy >> 1) * (g.W >> 1) + (gx >> 1));
+        const uint32_t off = in && srcu ? pu * (uint32_t)(g.xu_pitch * 2) + (uint32_t)cg * 2u : 0x80000000u;
+        v = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xur, (int)off, 0, 0));
+      }
       if (any0) {
-        const uint32_t off = in && !src1 ? pi * (uint32_t)(g.x_pitch * 2) + (uint32_t)cg * 2u : 0x80000000u;
-        v = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)off, 0, 0));
+        const uint32_t off =
+            in && !src1 && !srcu ? pi * (uint32_t)(g.x_pitch * 2) + (uint32_t)cg * 2u : 0x80000000u;
+        const uint4 w = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)off, 0, 0));
+        v = make_uint4(v.x | w.x, v.y | w.y, v.z | w.z, v.w | w.w);
       }
       if (any1) {
         const uint32_t off =
@@ -303,7 +341,7 @@ __device__ __forceinline__ void conv_mfma(f32x4_t (&acc)[TN / 16][4], const bf16
 // entries ordered by their first workgroup along x); a workgroup finds its
 // member, returns at once when the member's solve has decided, and then does
 // exactly the work of the same tile run in the member's own launch.
-template <int TN, int TAPS, bool UP, int ETA, bool WSTAT, bool GRP>
+template <int TN, int TAPS, bool UP, int ETA, bool WSTAT, bool GRP, bool XU>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv(
     ConvGeo g, const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta, const bf16_t* __restrict__ wp, int Kp,
     const float* __restrict__ bias, bf16_t* __restrict__ y, int tiles_per_wg, float* __restrict__ kpart, int ksplit,
@@ -362,6 +400,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const __amdgpu_buffer_rsrc_t x1r = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<bf16_t*>(g.x1 ? g.x1 + smp * g.x1_bstride : x), (short)0,
       g.x1 ? (int)((int64_t)g.H * g.W * g.x1_pitch * 2) : 0, 0x00020000);
+  const __amdgpu_buffer_rsrc_t xur = XU ? __builtin_amdgcn_make_buffer_rsrc(
+                                               const_cast<bf16_t*>(g.xu + smp * g.xu_bstride), (short)0,
+                                               (int)((int64_t)(g.H / 2) * (g.W / 2) * g.xu_pitch * 2), 0x00020000)
+                                         : xr;
   const int eta_bytes = (int)((int64_t)g.H * g.W * (ETA == kEtaNode ? 1 : g.cin8) * 2);
   const __amdgpu_buffer_rsrc_t er = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<bf16_t*>(ETA != kEtaNone ? eta : x), (short)0, eta_bytes, 0x00020000);
@@ -404,10 +446,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int c0 = c * S::CK;
     const int ck8 = min(S::CK, g.cin8 - c0) / 8;
     const int py0 = (t / tiles_x) * kCTH, px0 = (t % tiles_x) * kCTW;
-    const bool fast = ck8 == S::G8 && c0 + S::CK <= g.c1 && (ETA != kEtaChannel || g.x_pitch == g.cin8) &&
-                      py0 >= S::HALO && px0 >= S::HALO && py0 + kCTH + S::HALO <= g.H && px0 + kCTW + S::HALO <= g.W;
-    conv_issue<TN, TAPS, ETA>(st, ln, g, xr, x1r, er, wr, Kp, co0, py0, px0, c0, ck8, c * S::SMAX * 32, fast,
-                              wload);
+    const bool interior =
+        py0 >= S::HALO && px0 >= S::HALO && py0 + kCTH + S::HALO <= g.H && px0 + kCTW + S::HALO <= g.W;
+    const bool fast = ck8 == S::G8 && (!XU || c0 >= g.cu) && c0 + S::CK <= g.c1 &&
+                      (ETA != kEtaChannel || g.x_pitch == g.cin8) && interior;
+    const bool fastu = XU && ck8 == S::G8 && c0 + S::CK <= g.cu && interior;
+    conv_issue<TN, TAPS, ETA, XU>(st, ln, g, xr, x1r, xur, er, wr, Kp, co0, py0, px0, c0, ck8, c * S::SMAX * 32, fast,
+                              fastu, wload);
   };
   for (int it = 0; it < items; ++it) {
     const int t = t0 + it / nch, c = c_lo + it - (it / nch) * nch;
@@ -629,19 +674,29 @@ __global__ __launch_bounds__(256) void k_conv_ksum(ConvGeo g, int nb, int ksplit
 // fragments (8 consecutive input channels of one pixel per lane) straight
 // from memory two tiles ahead, and computes all output channels of a tile.
 // Every input byte is read once. MT = output-channel tiles of 16 (cout <=
-// 16 MT); K-steps = Kp / 32 <= 4.
+// 16 MT); K-steps = Kp / 32 <= 4. GRP: a grouped launch, blockIdx.y the
+// member (its geometry and buffers from the member table).
 constexpr int kC1KS = 4;                  // K-steps at most (Kp <= 128)
 constexpr int kC1WP = kC1KS * 32 + 8;     // LDS pitch of a weight row (bf16)
-template <int MT>
+template <int MT, bool GRP>
 __global__ __launch_bounds__(256) void k_conv1x1(ConvGeo g, const bf16_t* __restrict__ x,
                                                  const bf16_t* __restrict__ wp, int Kp,
-                                                 const float* __restrict__ bias, bf16_t* __restrict__ y) {
+                                                 const float* __restrict__ bias, bf16_t* __restrict__ y,
+                                                 const ConvMember* __restrict__ mem) {
   __shared__ __attribute__((aligned(16))) bf16_t s_w[MT * 16 * kC1WP];
   constexpr int OP = MT * 16 + 8;  // LDS pitch (bf16) of a staged output pixel
   __shared__ __attribute__((aligned(16))) bf16_t s_o[4][16 * OP];  // per wavefront
   const int nks = Kp / 32;
   const int lane = threadIdx.x & 63;
-  const int smp = blockIdx.y;
+  int smp = blockIdx.y;
+  if constexpr (GRP) {
+    const ConvMember& M = mem[blockIdx.y];
+    if (M.skip && __builtin_amdgcn_readfirstlane(*M.skip) != 0) return;
+    g = M.g;
+    x = M.x;
+    y = M.y;
+    smp = 0;
+  }
   x += smp * g.x_bstride;
   y += smp * g.y_bstride;
   const int npix = g.H * g.W;
@@ -1020,17 +1075,24 @@ int64_t conv_kpart_elems() { return (int64_t)2 * conv_device_cus() * kCTH * kCTW
 
 // Resident workgroups per CU of a convolution kernel (registers and LDS),
 // queried once per instantiation.
-template <int TN, int TAPS, bool UP, int ETA, bool WSTAT, bool GRP>
+template <int TN, int TAPS, bool UP, int ETA, bool WSTAT, bool GRP, bool XU = false>
 static int conv_per_cu() {
   static int per_cu = 0;
   if (per_cu == 0) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv<TN, TAPS, UP, ETA, WSTAT, GRP>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv<TN, TAPS, UP, ETA, WSTAT, GRP, XU>, 256, 0) != hipSuccess ||
         n < 1)
       n = 1;
     per_cu = n;
   }
   return per_cu;
+}
+
+// Small 1x1 layers (at most 128 input and output channels, one input source,
+// no local weight, upsampling or pooling) run as the skinny GEMM.
+static bool conv_skinny(int taps, bool up, bool has_eta, const ConvGeo& g, int Kp) {
+  return taps == 1 && !up && !has_eta && !g.x1 && !g.xu && !g.pool_y && g.cout <= 128 && Kp <= 128 &&
+         g.y_pitch % 8 == 0 && g.y_off % 8 == 0;
 }
 
 static int conv_tiles(const ConvGeo& g) { return ((g.W + kCTW - 1) / kCTW) * ((g.H + kCTH - 1) / kCTH); }
@@ -1084,10 +1146,27 @@ static void conv_go_eta(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t*
   const int64_t slots = (int64_t)cus * per_cu;
   const int run = (int)std::max<int64_t>(1, (wgs + slots - 1) / slots);
   const dim3 grid((tiles + run - 1) / run, cot, nb * ks);
-  if (wstat)
-    k_conv<TN, TAPS, UP, ETA, true, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks, nullptr, 0);
-  else
-    k_conv<TN, TAPS, UP, ETA, false, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks, nullptr, 0);
+  // the coarse input source only in the kernels of layers that have one
+  bool launched = false;
+  if constexpr (TAPS == 9 && !UP) {
+    if (g.xu) {
+      if (wstat)
+        k_conv<TN, TAPS, UP, ETA, true, false, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks,
+                                                                          nullptr, 0);
+      else
+        k_conv<TN, TAPS, UP, ETA, false, false, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks,
+                                                                           nullptr, 0);
+      launched = true;
+    }
+  }
+  if (!launched) {
+    if (wstat)
+      k_conv<TN, TAPS, UP, ETA, true, false, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks,
+                                                                         nullptr, 0);
+    else
+      k_conv<TN, TAPS, UP, ETA, false, false, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks,
+                                                                          nullptr, 0);
+  }
   if (ks > 1) {
     const int64_t n = (int64_t)g.H * g.W * (g.cout / 4);
     k_conv_ksum<UP, false><<<dim3((unsigned)((n + 255) / 256), nb), 256, 0, s>>>(g, nb, ks, cot * TN, kpart, bias, y,
@@ -1116,6 +1195,7 @@ static void conv_group_plan_t(std::vector<ConvMember>& m, int64_t kpart_elems, C
   }
   const int per_cu =
       wstat ? conv_per_cu<TN, TAPS, UP, ETA, true, true>() : conv_per_cu<TN, TAPS, UP, ETA, false, true>();
+  L.xu = m[0].g.xu != nullptr;
   const int64_t slots = (int64_t)conv_device_cus() * per_cu;
   const int run = (int)std::max<int64_t>(1, (wgs + slots - 1) / slots);
   int64_t wg = 0;
@@ -1139,18 +1219,32 @@ static void conv_group_launch_t(const ConvGroupLaunch& L, const ConvMember* dm, 
                                 const float* bias, hipStream_t s) {
   const ConvGeo g0{};
   const dim3 grid(L.gx, L.cot, 1);
-  if (L.wstat)
-    k_conv<TN, TAPS, UP, ETA, true, true><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr, L.run,
-                                                               nullptr, 1, dm, L.nmem);
-  else
-    k_conv<TN, TAPS, UP, ETA, false, true><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr, L.run,
-                                                                nullptr, 1, dm, L.nmem);
+  bool launched = false;
+  if constexpr (TAPS == 9 && !UP) {
+    if (L.xu) {
+      if (L.wstat)
+        k_conv<TN, TAPS, UP, ETA, true, true, true><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr,
+                                                                         L.run, nullptr, 1, dm, L.nmem);
+      else
+        k_conv<TN, TAPS, UP, ETA, false, true, true><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr,
+                                                                          L.run, nullptr, 1, dm, L.nmem);
+      launched = true;
+    }
+  }
+  if (!launched) {
+    if (L.wstat)
+      k_conv<TN, TAPS, UP, ETA, true, true, false><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr,
+                                                                        L.run, nullptr, 1, dm, L.nmem);
+    else
+      k_conv<TN, TAPS, UP, ETA, false, true, false><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr,
+                                                                         L.run, nullptr, 1, dm, L.nmem);
+  }
   if (L.split)
     k_conv_ksum<UP, true><<<dim3(L.ksum_gx, 1), 256, 0, s>>>(g0, L.nmem, 1, L.cot * TN, nullptr, bias, nullptr, dm);
 }
 
 // The instantiations a grouped forward uses: 3x3 layers with any local
-// weight, and 1x1 up-convolutions without one.
+// weight, and 1x1 layers without one.
 template <class F>
 static bool conv_group_dispatch(int taps, bool up, int eta, bool wide, F&& f) {
   using std::integral_constant;
@@ -1164,10 +1258,15 @@ static bool conv_group_dispatch(int taps, bool up, int eta, bool wide, F&& f) {
     else by_eta(integral_constant<int, 32>{}, integral_constant<int, 9>{}, integral_constant<bool, false>{});
     return true;
   }
-  if (taps == 1 && up && eta == kEtaNone) {
+  if (taps == 1 && eta == kEtaNone) {
     const auto none = integral_constant<int, kEtaNone>{};
-    if (wide) f(integral_constant<int, 64>{}, integral_constant<int, 1>{}, integral_constant<bool, true>{}, none);
-    else f(integral_constant<int, 32>{}, integral_constant<int, 1>{}, integral_constant<bool, true>{}, none);
+    if (up) {
+      if (wide) f(integral_constant<int, 64>{}, integral_constant<int, 1>{}, integral_constant<bool, true>{}, none);
+      else f(integral_constant<int, 32>{}, integral_constant<int, 1>{}, integral_constant<bool, true>{}, none);
+    } else {
+      if (wide) f(integral_constant<int, 64>{}, integral_constant<int, 1>{}, integral_constant<bool, false>{}, none);
+      else f(integral_constant<int, 32>{}, integral_constant<int, 1>{}, integral_constant<bool, false>{}, none);
+    }
     return true;
   }
   return false;
@@ -1175,12 +1274,28 @@ static bool conv_group_dispatch(int taps, bool up, int eta, bool wide, F&& f) {
 
 static int conv_eta_mode(const ConvMember& e) { return !e.eta ? kEtaNone : e.g.eta_node ? kEtaNode : kEtaChannel; }
 
-bool plan_conv_group(int taps, bool up, std::vector<ConvMember>& m, int64_t kpart_elems, ConvGroupLaunch& L) {
+bool plan_conv_group(int taps, bool up, int Kp, std::vector<ConvMember>& m, int64_t kpart_elems,
+                     ConvGroupLaunch& L) {
   if (m.empty()) return false;
   L = ConvGroupLaunch{};
   L.taps = taps;
   L.up = up;
   L.eta = conv_eta_mode(m[0]);
+  if (conv_skinny(taps, up, m[0].eta != nullptr, m[0].g, Kp)) {
+    // the skinny GEMM of each member, blockIdx.y the member: its own launch's
+    // runs of workgroups, the largest over the members
+    L.skinny = m[0].g.cout <= 32 ? 2 : m[0].g.cout <= 64 ? 4 : 8;
+    L.nmem = (int)m.size();
+    int per_cu = 1;
+    const auto fn = L.skinny == 2 ? k_conv1x1<2, true> : L.skinny == 4 ? k_conv1x1<4, true> : k_conv1x1<8, true>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    const int64_t want = (int64_t)conv_device_cus() * per_cu;
+    for (const ConvMember& e : m) {
+      const int tiles = (e.g.H * e.g.W + 15) / 16;
+      L.gx = std::max(L.gx, (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, want / L.nmem)));
+    }
+    return true;
+  }
   // the group's tile width by the default rule over all members' workgroups
   bool wide = false;
   if (m[0].g.cout >= 64) {
@@ -1196,6 +1311,14 @@ bool plan_conv_group(int taps, bool up, std::vector<ConvMember>& m, int64_t kpar
 
 void launch_conv_group(const ConvGroupLaunch& L, const ConvMember* d_mem, const bf16_t* wp, int Kp,
                        const float* bias, hipStream_t s) {
+  if (L.skinny) {
+    const ConvGeo g0{};
+    const dim3 grid(L.gx, L.nmem);
+    if (L.skinny == 2) k_conv1x1<2, true><<<grid, 256, 0, s>>>(g0, nullptr, wp, Kp, bias, nullptr, d_mem);
+    else if (L.skinny == 4) k_conv1x1<4, true><<<grid, 256, 0, s>>>(g0, nullptr, wp, Kp, bias, nullptr, d_mem);
+    else k_conv1x1<8, true><<<grid, 256, 0, s>>>(g0, nullptr, wp, Kp, bias, nullptr, d_mem);
+    return;
+  }
   conv_group_dispatch(L.taps, L.up, L.eta, L.tn == 64, [&](auto tn, auto tp, auto upc, auto et) {
     conv_group_launch_t<decltype(tn)::value, decltype(tp)::value, decltype(upc)::value, decltype(et)::value>(
         L, d_mem, wp, Kp, bias, s);
@@ -1219,24 +1342,22 @@ static void conv1x1_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* 
   static int per_cu = 0;
   if (per_cu == 0) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv1x1<MT>, 256, 0) != hipSuccess || n < 1) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv1x1<MT, false>, 256, 0) != hipSuccess || n < 1) n = 1;
     per_cu = n;
   }
   const int tiles = (g.H * g.W + 15) / 16;
   const int64_t want = (int64_t)conv_device_cus() * per_cu;
   const int per_smp = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, want / nb));
-  k_conv1x1<MT><<<dim3(per_smp, nb), 256, 0, s>>>(g, x, wp, Kp, bias, y);
+  k_conv1x1<MT, false><<<dim3(per_smp, nb), 256, 0, s>>>(g, x, wp, Kp, bias, y, nullptr);
 }
 
 bool conv_has_tile_choice(int taps, bool up, bool has_eta, const ConvGeo& g, int Kp) {
-  const bool skinny = taps == 1 && !up && !has_eta && !g.x1 && g.cout <= 128 && Kp <= 128 && g.y_pitch % 8 == 0 &&
-                      g.y_off % 8 == 0;
-  return !skinny && g.cout >= 64;
+  return !conv_skinny(taps, up, has_eta, g, Kp) && g.cout >= 64;
 }
 
 void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp,
                  int Kp, const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems, int tn) {
-  if (taps == 1 && !up && !eta && !g.x1 && g.cout <= 128 && Kp <= 128 && g.y_pitch % 8 == 0 && g.y_off % 8 == 0) {
+  if (conv_skinny(taps, up, eta != nullptr, g, Kp)) {
     // small 1x1 layers: the skinny GEMM, one round of resident workgroups
     // over all samples
     if (g.cout <= 32) conv1x1_go<2>(g, nb, x, wp, Kp, bias, y, s);

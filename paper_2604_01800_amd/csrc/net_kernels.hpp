@@ -30,13 +30,16 @@ bool conv_has_tile_choice(int taps, bool up, bool has_eta, const ConvGeo& g, int
 // Grouped convolution (one layer of the forwards of several grids): the
 // launch shape that plan_conv_group derives from the members (their g, x,
 // eta, y, kpart and skip set by the caller; it fills wg0, nwt and ks). Only
-// 3x3 layers and 1x1 up-convolutions without local weights are grouped
+// 3x3 layers and 1x1 layers without local weights are grouped
 // (plan_conv_group returns false otherwise). The member table must be in
 // device memory for launch_conv_group.
 struct ConvGroupLaunch {
   int taps = 9, up = 0, eta = 0, tn = 32, wstat = 0, run = 1, gx = 0, cot = 0, nmem = 0, split = 0, ksum_gx = 0;
+  int skinny = 0;  // small 1x1 layers: the skinny GEMM with this many 16-channel tiles (2, 4, 8), else 0
+  int xu = 0;      // the members have a coarse input source
 };
-bool plan_conv_group(int taps, bool up, std::vector<ConvMember>& m, int64_t kpart_elems, ConvGroupLaunch& L);
+bool plan_conv_group(int taps, bool up, int Kp, std::vector<ConvMember>& m, int64_t kpart_elems,
+                     ConvGroupLaunch& L);
 void launch_conv_group(const ConvGroupLaunch& L, const ConvMember* d_mem, const bf16_t* wp, int Kp,
                        const float* bias, hipStream_t s);
 void launch_input_pack_group(const PackMember* d_mem, int n, int pitch, hipStream_t s);
