@@ -193,6 +193,7 @@ def main(argv=None):
                     help="the residual loss of Eq. 19, or the supervised or A-norm (line-search share) loss "
                          "against FP64 solutions of the pool")
     ap.add_argument("--eval-sizes", default="64,128,256")
+    ap.add_argument("--eval-count", type=int, default=6, help="held-out systems at the training size")
     ap.add_argument("--sweep", action="store_true",
                     help="also sweep Num_CG and Num_DLSM over 1..5 on held-out n x n systems (Appendix A)")
     args = ap.parse_args(argv)
@@ -226,7 +227,7 @@ def main(argv=None):
     if args.out:
         ppe.ppe_net_save(net, args.out)
     for n in (int(v) for v in args.eval_sizes.split(",") if v):
-        for row in evaluate(net, n, count=6 if n == args.n else 3):
+        for row in evaluate(net, n, count=args.eval_count if n == args.n else 3):
             print(json.dumps(row), flush=True)
     if args.sweep:
         for num_cg in range(1, 6):
