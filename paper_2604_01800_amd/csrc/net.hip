@@ -572,7 +572,22 @@ ppe_status net_forward(ppe_problem* p, ppe_net* n, int nb, const float* r, float
   if (st != PPE_OK) return st;
   std::vector<FwdOp> ops;
   forward_ops(p, n, p->net_cache, r, y, ops);
-  for (const FwdOp& o : ops) launch_op(o, nb, s);
+  // the last decoder convolution computes the DeepONet output in its
+  // epilogue where the layer allows it (same values as the two launches)
+  const size_t no = ops.size();
+  const bool fuse = no >= 2 && ops[no - 1].kind == FwdOp::OUT && ops[no - 2].kind == FwdOp::CONV &&
+                    ops[no - 2].taps == 9 && !ops[no - 2].up && ops[no - 2].y == ops[no - 1].d0;
+  for (size_t k = 0; k < (fuse ? no - 2 : no); ++k) launch_op(ops[k], nb, s);
+  if (fuse) {
+    const FwdOp& cv = ops[no - 2];
+    const FwdOp& ot = ops[no - 1];
+    const OutFold of{ot.fold, ot.gamma, ot.yout, ot.fold_pitch, ot.c0};
+    if (!launch_conv_out(cv.g, nb, cv.x, cv.eta, cv.wp, cv.Kp, cv.bias, cv.y, s, cv.kpart, cv.kpart_elems, cv.tn,
+                         of)) {
+      launch_op(cv, nb, s);
+      launch_op(ot, nb, s);
+    }
+  }
   HIPCHK(hipGetLastError());
   return PPE_OK;
 }

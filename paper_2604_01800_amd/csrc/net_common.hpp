@@ -98,6 +98,17 @@ struct PackMember {     // input scaling (sum of squares, then the packed input)
   bf16_t* xin;
   const int32_t* skip;
 };
+// DeepONet output fused into the epilogue of the last decoder convolution:
+// y = gamma * (D0 . fold[p][0:c0] + fold[p][c0]) per pixel p, fold rows of
+// `pitch` floats (a per-grid constant), y [samples][pixels] FP32; fold null:
+// no fused output.
+struct OutFold {
+  const float* fold;
+  const float* gamma;
+  float* y;
+  int pitch;
+  int c0;
+};
 struct OutMember {      // DeepONet output
   int64_t npix;
   const bf16_t* d0;

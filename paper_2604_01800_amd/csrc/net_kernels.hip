@@ -341,11 +341,22 @@ __device__ __forceinline__ void conv_mfma(f32x4_t (&acc)[TN / 16][4], const bf16
 // entries ordered by their first workgroup along x); a workgroup finds its
 // member, returns at once when the member's solve has decided, and then does
 // exactly the work of the same tile run in the member's own launch.
-template <int TN, int TAPS, bool UP, int ETA, bool WSTAT, bool GRP, bool XU>
+// One 4-channel group of the DeepONet output contraction: BF16 activations
+// d (two packed pairs) times fold weights w, a product and three FMAs in
+// channel order. Both output paths (the separate kernel and the fused
+// convolution epilogue) use it, so they round alike.
+__device__ __forceinline__ float out_group4(uint2 d, float4 w) {
+  float e = __fmul_rn(bf2f((bf16_t)(d.x & 0xffff)), w.x);
+  e = __fmaf_rn(bf2f((bf16_t)(d.x >> 16)), w.y, e);
+  e = __fmaf_rn(bf2f((bf16_t)(d.y & 0xffff)), w.z, e);
+  return __fmaf_rn(bf2f((bf16_t)(d.y >> 16)), w.w, e);
+}
+
+template <int TN, int TAPS, bool UP, int ETA, bool WSTAT, bool GRP, bool XU, bool OUTF = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv(
     ConvGeo g, const bf16_t* __restrict__ x, const bf16_t* __restrict__ eta, const bf16_t* __restrict__ wp, int Kp,
     const float* __restrict__ bias, bf16_t* __restrict__ y, int tiles_per_wg, float* __restrict__ kpart, int ksplit,
-    const ConvMember* __restrict__ mem, int nmem) {
+    const ConvMember* __restrict__ mem, int nmem, OutFold of) {
   using S = ConvShape<TN, TAPS>;
   constexpr int MT = TN / 16, NT = 4;
   __shared__ __attribute__((aligned(16))) bf16_t s_x[S::NPIX * S::CKP];
@@ -489,6 +500,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             *(f32x4_t*)(pp + ((int64_t)py * g.W + px) * cp + co) = acc[mt][nt];
           acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         }
+      }
+      continue;
+    }
+    if constexpr (OUTF) {
+      // DeepONet output instead of the stored activations (TN = 32 and
+      // c0 <= 32: the workgroup holds every channel of its pixels). The
+      // lane's channel group q = 4 mt + (lane >> 4) takes the place of lane q
+      // of k_deeponet_out: the same BF16-rounded values, the same group sum,
+      // and the same pairwise order across groups (q ^ 4 within the lane, then
+      // lanes ^ 32 and ^ 16), so the result is that kernel's bit for bit.
+      static_assert(TN == 32 && !UP && !GRP, "fused output: 32 output channels per workgroup, plain launch");
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int py = py0 + NT * wv + nt, px = px0 + (lane & 15);
+        const bool pok = py < g.H && px < g.W;
+        const int64_t pix = (int64_t)py * g.W + px;
+        float sq[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int col = mt * 16 + 4 * (lane >> 4);
+          const f32x4_t b = *(const f32x4_t*)(s_b + col);
+          float v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = acc[mt][nt][j] + b[j];
+          if (g.act == 1) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = __builtin_amdgcn_fmed3f(v[j], 0.f, __builtin_inff());
+          } else if (g.act == 2) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = tanh_nn(v[j]);
+          }
+          const uint2 pk = {__builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){v[0], v[1]}, bf16x2_t)),
+                            __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){v[2], v[3]}, bf16x2_t))};
+          sq[mt] = 0.f;
+          if (pok && col < of.c0) sq[mt] += out_group4(pk, *(const float4*)(of.fold + pix * of.pitch + col));
+          acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        }
+        float sv = sq[0] + sq[1];
+        sv += __shfl_xor(sv, 32);
+        sv += __shfl_xor(sv, 16);
+        if (pok && lane < 16)
+          of.y[(int64_t)smp * g.H * g.W + pix] = of.gamma[0] * (sv + of.fold[pix * of.pitch + of.c0]);
       }
       continue;
     }
@@ -1039,12 +1092,7 @@ __global__ void k_deeponet_out(int64_t npix, int c0, const bf16_t* __restrict__ 
   if (p < npix) {
     const bf16_t* d = d0 + smp * d_bs + p * c0;
     const float* f = fold + p * fold_pitch;
-    for (int c = 4 * l; c < c0; c += 32) {
-      const uint2 v = *(const uint2*)(d + c);
-      const float4 w = *(const float4*)(f + c);
-      s += bf2f((bf16_t)(v.x & 0xffff)) * w.x + bf2f((bf16_t)(v.x >> 16)) * w.y +
-           bf2f((bf16_t)(v.y & 0xffff)) * w.z + bf2f((bf16_t)(v.y >> 16)) * w.w;
-    }
+    for (int c = 4 * l; c < c0; c += 32) s += out_group4(*(const uint2*)(d + c), *(const float4*)(f + c));
   }
   s += __shfl_xor(s, 4, 8);
   s += __shfl_xor(s, 2, 8);
@@ -1075,12 +1123,13 @@ int64_t conv_kpart_elems() { return (int64_t)2 * conv_device_cus() * kCTH * kCTW
 
 // Resident workgroups per CU of a convolution kernel (registers and LDS),
 // queried once per instantiation.
-template <int TN, int TAPS, bool UP, int ETA, bool WSTAT, bool GRP, bool XU = false>
+template <int TN, int TAPS, bool UP, int ETA, bool WSTAT, bool GRP, bool XU = false, bool OUTF = false>
 static int conv_per_cu() {
   static int per_cu = 0;
   if (per_cu == 0) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv<TN, TAPS, UP, ETA, WSTAT, GRP, XU>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv<TN, TAPS, UP, ETA, WSTAT, GRP, XU, OUTF>, 256, 0) !=
+            hipSuccess ||
         n < 1)
       n = 1;
     per_cu = n;
@@ -1152,20 +1201,20 @@ static void conv_go_eta(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t*
     if (g.xu) {
       if (wstat)
         k_conv<TN, TAPS, UP, ETA, true, false, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks,
-                                                                          nullptr, 0);
+                                                                          nullptr, 0, OutFold{});
       else
         k_conv<TN, TAPS, UP, ETA, false, false, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks,
-                                                                           nullptr, 0);
+                                                                           nullptr, 0, OutFold{});
       launched = true;
     }
   }
   if (!launched) {
     if (wstat)
       k_conv<TN, TAPS, UP, ETA, true, false, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks,
-                                                                         nullptr, 0);
+                                                                         nullptr, 0, OutFold{});
     else
       k_conv<TN, TAPS, UP, ETA, false, false, false><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, kpart, ks,
-                                                                          nullptr, 0);
+                                                                          nullptr, 0, OutFold{});
   }
   if (ks > 1) {
     const int64_t n = (int64_t)g.H * g.W * (g.cout / 4);
@@ -1224,20 +1273,20 @@ static void conv_group_launch_t(const ConvGroupLaunch& L, const ConvMember* dm, 
     if (L.xu) {
       if (L.wstat)
         k_conv<TN, TAPS, UP, ETA, true, true, true><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr,
-                                                                         L.run, nullptr, 1, dm, L.nmem);
+                                                                         L.run, nullptr, 1, dm, L.nmem, OutFold{});
       else
         k_conv<TN, TAPS, UP, ETA, false, true, true><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr,
-                                                                          L.run, nullptr, 1, dm, L.nmem);
+                                                                          L.run, nullptr, 1, dm, L.nmem, OutFold{});
       launched = true;
     }
   }
   if (!launched) {
     if (L.wstat)
       k_conv<TN, TAPS, UP, ETA, true, true, false><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr,
-                                                                        L.run, nullptr, 1, dm, L.nmem);
+                                                                        L.run, nullptr, 1, dm, L.nmem, OutFold{});
     else
       k_conv<TN, TAPS, UP, ETA, false, true, false><<<grid, 256, 0, s>>>(g0, nullptr, nullptr, wp, Kp, bias, nullptr,
-                                                                         L.run, nullptr, 1, dm, L.nmem);
+                                                                         L.run, nullptr, 1, dm, L.nmem, OutFold{});
   }
   if (L.split)
     k_conv_ksum<UP, true><<<dim3(L.ksum_gx, 1), 256, 0, s>>>(g0, L.nmem, 1, L.cot * TN, nullptr, bias, nullptr, dm);
@@ -1349,6 +1398,43 @@ static void conv1x1_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* 
   const int64_t want = (int64_t)conv_device_cus() * per_cu;
   const int per_smp = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, want / nb));
   k_conv1x1<MT, false><<<dim3(per_smp, nb), 256, 0, s>>>(g, x, wp, Kp, bias, y, nullptr);
+}
+
+// The last decoder convolution with the DeepONet output in its epilogue
+// (one launch of 32 output channels per workgroup, no K split).
+template <int ETA>
+static void conv_out_go(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp, int Kp,
+                        const float* bias, bf16_t* y, int nch, const OutFold& of, hipStream_t s) {
+  const int tiles = conv_tiles(g);
+  const bool wstat = nch == 1;
+  const int per_cu = wstat ? conv_per_cu<32, 9, false, ETA, true, false, false, true>()
+                           : conv_per_cu<32, 9, false, ETA, false, false, false, true>();
+  const int64_t slots = (int64_t)conv_device_cus() * per_cu;
+  const int run = (int)std::max<int64_t>(1, ((int64_t)tiles * nb + slots - 1) / slots);
+  const dim3 grid((tiles + run - 1) / run, 1, nb);
+  if (wstat)
+    k_conv<32, 9, false, ETA, true, false, false, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, nullptr,
+                                                                              1, nullptr, 0, of);
+  else
+    k_conv<32, 9, false, ETA, false, false, false, true><<<grid, 256, 0, s>>>(g, x, eta, wp, Kp, bias, y, run, nullptr,
+                                                                               1, nullptr, 0, of);
+}
+
+bool launch_conv_out(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp, int Kp,
+                     const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems, int tn,
+                     const OutFold& of) {
+  if (g.xu || g.pool_y || g.cout != of.c0 || of.c0 > 32 || of.c0 % 4 || of.pitch % 4 || !of.fold || !of.y ||
+      (tn ? tn : conv_default_tile(g, nb)) != 32)
+    return false;
+  const int nch = (g.cin8 + ConvShape<32, 9>::CK - 1) / ConvShape<32, 9>::CK;
+  if (conv_ksplit(g, nb, 32, nch, kpart != nullptr, kpart_elems, 32) > 1) return false;
+  if (!eta)
+    conv_out_go<kEtaNone>(g, nb, x, eta, wp, Kp, bias, y, nch, of, s);
+  else if (g.eta_node)
+    conv_out_go<kEtaNode>(g, nb, x, eta, wp, Kp, bias, y, nch, of, s);
+  else
+    conv_out_go<kEtaChannel>(g, nb, x, eta, wp, Kp, bias, y, nch, of, s);
+  return true;
 }
 
 bool conv_has_tile_choice(int taps, bool up, bool has_eta, const ConvGeo& g, int Kp) {

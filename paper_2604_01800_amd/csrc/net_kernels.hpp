@@ -25,6 +25,14 @@ void launch_conv(int taps, bool up, const ConvGeo& g, int nb, const bf16_t* x, c
                  int64_t kpart_elems = 0, int tn = 0);
 // The default tn of a layer over nb samples.
 int conv_default_tile(const ConvGeo& g, int nb);
+// The 3x3 convolution of launch_conv (taps 9, no upsampling) followed by the
+// DeepONet output of `of` computed in its epilogue, its own output not
+// stored; bit-identical to launch_conv then launch_deeponet_out. Returns
+// false, launching nothing, where the layer does not allow it (more than 32
+// output channels or a tile width of 64, a K split, pooling, a coarse source).
+bool launch_conv_out(const ConvGeo& g, int nb, const bf16_t* x, const bf16_t* eta, const bf16_t* wp, int Kp,
+                     const float* bias, bf16_t* y, hipStream_t s, float* kpart, int64_t kpart_elems, int tn,
+                     const OutFold& of);
 // Whether launch_conv has a choice of tn for this layer.
 bool conv_has_tile_choice(int taps, bool up, bool has_eta, const ConvGeo& g, int Kp);
 // Grouped convolution (one layer of the forwards of several grids): the
