@@ -158,6 +158,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_01800_amd.build`")
+        # torch first: it brings its own HIP runtime (soname libamdhip64.so.7),
+        # and the library must bind to that one, the runtime of the device
+        # memory and streams it is handed. Loaded the other way round, the
+        # process would run torch on the system runtime, and the library's
+        # allocations fail after torch initialises the device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name, None)
